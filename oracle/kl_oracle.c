@@ -1,0 +1,511 @@
+/*
+ * kl_oracle.c -- CPU reference ("oracle") for the indexed Kleinian-attractor
+ * renderer (Rosa, arXiv:1709.08018).  TEST INFRASTRUCTURE ONLY: the test
+ * suite, the smoke check and the benchmark's CPU-baseline leg are its only
+ * users.  Plain C99, FP64 complex arithmetic, no blocking or reordering
+ * beyond what the definitions below state.  See kl_oracle.h for the
+ * conventions (letters, word order, index order, window).
+ *
+ * What is computed, and where it comes from:
+ *   - reduced words: strings over {a,b,A,B} with no adjacent inverse pair
+ *     (Section 1, crash words; Section 3, pruned tree and Table 1);
+ *   - their order: a depth-first walk of the pruned tree visiting children
+ *     in letter order; this equals the order of the survivors in the
+ *     paper's numeric scan of all 4^d digit strings (Section 4, digital and
+ *     indexed trees; Section 6, index search);
+ *   - word value: the word's maps applied right to left to the seed
+ *     (Section 1); the DFS evaluator carries the product of the maps from
+ *     the left, one 2x2 product per tree node, the literal evaluator walks
+ *     the point itself;
+ *   - render modes: "limit set" draws words of depth D only, "tiling"
+ *     draws every word of depth 1..D (Section 6);
+ *   - generators: the trace recipe (Indra's Pearls' "Grandma's recipe",
+ *     the paper's reference for generator construction), with the root of
+ *     the trace quadratic taken in the closed upper half plane;
+ *   - seed: attracting fixed point of the word's last letter.
+ */
+#include "kl_oracle.h"
+
+#include <complex.h>
+#include <math.h>
+#include <pthread.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef double complex cplx;
+typedef struct { cplx a, b, c, d; } mat2; /* [[a, b], [c, d]] */
+
+/* a <-> A, b <-> B */
+static const int INVERSE[4] = {2, 3, 0, 1};
+
+#define MAX_DEPTH 40
+
+/* ------------------------------------------------------------------ */
+/* counting                                                            */
+/* ------------------------------------------------------------------ */
+
+static uint64_t pow3(int n)
+{
+    uint64_t p = 1;
+    for (int i = 0; i < n; i++) p *= 3;
+    return p;
+}
+
+/* Reduced words of length d: 4 choices for the first letter, then 3 for
+ * each later letter (anything but the inverse of the previous one). */
+uint64_t oracle_num_words(int depth)
+{
+    if (depth < 1 || depth > MAX_DEPTH) return 0;
+    return 4 * pow3(depth - 1);
+}
+
+/* Node counts of the unpruned m-branched tree (Section 6): m^D nodes at
+ * depth D ("limit set"), or the sum over depths 1..D ("tiling"). */
+uint64_t oracle_num_tree_nodes(int m, int depth, int tiling)
+{
+    uint64_t total = 0, level = 1;
+    for (int d = 1; d <= depth; d++) {
+        level *= (uint64_t)m;
+        if (tiling || d == depth) total += level;
+    }
+    return total;
+}
+
+/* ------------------------------------------------------------------ */
+/* words                                                               */
+/* ------------------------------------------------------------------ */
+
+/* Random access by subtree sizes: below the root every node has 3
+ * children, so a child at depth j heads 3^(d-j) leaves.  At each level
+ * take the (rank / subtree)-th allowed child in letter order. */
+int oracle_unrank(uint64_t index, int depth, uint8_t *word)
+{
+    if (depth < 1 || depth > MAX_DEPTH || !word) return -1;
+    if (index >= oracle_num_words(depth)) return -1;
+    uint64_t rank = index;
+    int prev = -1;
+    for (int j = 1; j <= depth; j++) {
+        uint64_t subtree = pow3(depth - j);
+        uint64_t pick = rank / subtree;
+        rank = rank % subtree;
+        int seen = 0, chosen = -1;
+        for (int c = 0; c < 4; c++) {
+            if (prev >= 0 && c == INVERSE[prev]) continue;
+            if ((uint64_t)seen == pick) { chosen = c; break; }
+            seen++;
+        }
+        if (chosen < 0) return -1;
+        word[j - 1] = (uint8_t)chosen;
+        prev = chosen;
+    }
+    return 0;
+}
+
+typedef struct {
+    int depth;
+    uint64_t first, last; /* leaf index range [first, last) */
+    uint64_t next;        /* index of the next leaf the walk reaches */
+    uint8_t *out;
+    uint8_t word[MAX_DEPTH];
+} enum_ctx;
+
+static void enumerate_rec(enum_ctx *e, int j)
+{
+    if (j == e->depth) {
+        if (e->next >= e->first && e->next < e->last)
+            memcpy(e->out + (e->next - e->first) * (uint64_t)e->depth,
+                   e->word, (size_t)e->depth);
+        e->next++;
+        return;
+    }
+    for (int c = 0; c < 4; c++) {
+        if (j > 0 && c == INVERSE[e->word[j - 1]]) continue;
+        e->word[j] = (uint8_t)c;
+        enumerate_rec(e, j + 1);
+    }
+}
+
+/* Depth-first walk of the pruned tree with the explicit word on a stack;
+ * writes the words whose visiting rank lies in [first, first+count). */
+int oracle_enumerate(int depth, uint64_t first, uint64_t count, uint8_t *words)
+{
+    if (depth < 1 || depth > 20 || (!words && count)) return -1;
+    uint64_t n = oracle_num_words(depth);
+    if (first > n || count > n - first) return -1;
+    enum_ctx e;
+    memset(&e, 0, sizeof e);
+    e.depth = depth;
+    e.first = first;
+    e.last = first + count;
+    e.out = words;
+    enumerate_rec(&e, 0);
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Moebius maps                                                        */
+/* ------------------------------------------------------------------ */
+
+static mat2 mat_mul(mat2 x, mat2 y)
+{
+    mat2 r;
+    r.a = x.a * y.a + x.b * y.c;
+    r.b = x.a * y.b + x.b * y.d;
+    r.c = x.c * y.a + x.d * y.c;
+    r.d = x.c * y.b + x.d * y.d;
+    return r;
+}
+
+/* z -> (a z + b) / (c z + d)   (Section 3, linear fractional maps) */
+static cplx mobius(mat2 m, cplx z)
+{
+    return (m.a * z + m.b) / (m.c * z + m.d);
+}
+
+static mat2 mat_inverse(mat2 m)
+{
+    cplx det = m.a * m.d - m.b * m.c;
+    mat2 r = {m.d / det, -m.b / det, -m.c / det, m.a / det};
+    return r;
+}
+
+/* ------------------------------------------------------------------ */
+/* generators and seeds                                                */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+    cplx tab;
+    mat2 g[4];   /* a, b, A, B */
+    cplx fix[4]; /* attracting fixed point of each generator */
+} group;
+
+static int finite_c(cplx z) { return isfinite(creal(z)) && isfinite(cimag(z)); }
+
+/* Attracting fixed point of z -> (a z + b)/(c z + d): the roots of
+ * c z^2 + (d - a) z - b = 0; |g'(z)| = |det| / |c z + d|^2, so the
+ * attracting root is the one with the larger |c z + d|.  A tie (one
+ * parabolic root, or an elliptic pair) takes the "+" root. */
+static int attracting_fixed_point(mat2 m, cplx *out)
+{
+    if (m.c == 0) return -2;
+    cplx disc = (m.a - m.d) * (m.a - m.d) + 4.0 * m.b * m.c;
+    cplx root = csqrt(disc);
+    cplx zp = ((m.a - m.d) + root) / (2.0 * m.c);
+    cplx zm = ((m.a - m.d) - root) / (2.0 * m.c);
+    double kp = cabs(m.c * zp + m.d);
+    double km = cabs(m.c * zm + m.d);
+    *out = (km > kp) ? zm : zp;
+    return finite_c(*out) ? 0 : -2;
+}
+
+/* Trace recipe: given tr a = ta and tr b = tb, tab = tr ab is a root of
+ * tab^2 - ta tb tab + ta^2 + tb^2 = 0 (which makes tr abAB = -2), taken
+ * as (ta tb + s)/2 with s^2 the discriminant and s in the closed upper
+ * half plane; then
+ *   z0 = (tab - 2) tb / (tb tab - 2 ta + 2i tab)
+ *   a  = [[ta/2, (ta tab - 2 tb + 4i) / ((2 tab + 4) z0)],
+ *         [(ta tab - 2 tb - 4i) z0 / (2 tab - 4), ta/2]]
+ *   b  = [[(tb - 2i)/2, tb/2], [tb/2, (tb + 2i)/2]]
+ *   A  = a^-1, B = b^-1. */
+static int build_group(cplx ta, cplx tb, group *g)
+{
+    const cplx I2 = 2.0 * I, I4 = 4.0 * I;
+    cplx disc = (ta * tb) * (ta * tb) - 4.0 * (ta * ta + tb * tb);
+    cplx s = csqrt(disc);
+    if (cimag(s) < 0 || (cimag(s) == 0 && creal(s) < 0)) s = -s;
+    cplx tab = (ta * tb + s) / 2.0;
+    cplx den_z0 = tb * tab - 2.0 * ta + I2 * tab;
+    if (den_z0 == 0 || 2.0 * tab + 4.0 == 0 || 2.0 * tab - 4.0 == 0) return -2;
+    cplx z0 = (tab - 2.0) * tb / den_z0;
+    if (z0 == 0) return -2;
+    mat2 a, b;
+    a.a = ta / 2.0;
+    a.b = (ta * tab - 2.0 * tb + I4) / ((2.0 * tab + 4.0) * z0);
+    a.c = (ta * tab - 2.0 * tb - I4) * z0 / (2.0 * tab - 4.0);
+    a.d = ta / 2.0;
+    b.a = (tb - I2) / 2.0;
+    b.b = tb / 2.0;
+    b.c = tb / 2.0;
+    b.d = (tb + I2) / 2.0;
+    g->tab = tab;
+    g->g[0] = a;
+    g->g[1] = b;
+    g->g[2] = mat_inverse(a);
+    g->g[3] = mat_inverse(b);
+    for (int k = 0; k < 4; k++) {
+        mat2 m = g->g[k];
+        if (!finite_c(m.a) || !finite_c(m.b) || !finite_c(m.c) || !finite_c(m.d))
+            return -2;
+        if (attracting_fixed_point(m, &g->fix[k]) != 0) return -2;
+    }
+    return 0;
+}
+
+static void put_c(double *dst, cplx z)
+{
+    dst[0] = creal(z);
+    dst[1] = cimag(z);
+}
+
+static cplx get_c(const double *src) { return src[0] + src[1] * I; }
+
+int oracle_generators(double ta_re, double ta_im, double tb_re, double tb_im,
+                      double *tab_out, double *gens_out, double *fix_out)
+{
+    group g;
+    int rc = build_group(ta_re + ta_im * I, tb_re + tb_im * I, &g);
+    if (rc) return rc;
+    if (tab_out) put_c(tab_out, g.tab);
+    if (gens_out) {
+        for (int k = 0; k < 4; k++) {
+            put_c(gens_out + ((k * 2 + 0) * 2 + 0) * 2, g.g[k].a);
+            put_c(gens_out + ((k * 2 + 0) * 2 + 1) * 2, g.g[k].b);
+            put_c(gens_out + ((k * 2 + 1) * 2 + 0) * 2, g.g[k].c);
+            put_c(gens_out + ((k * 2 + 1) * 2 + 1) * 2, g.g[k].d);
+        }
+    }
+    if (fix_out)
+        for (int k = 0; k < 4; k++) put_c(fix_out + 2 * k, g.fix[k]);
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* word values                                                         */
+/* ------------------------------------------------------------------ */
+
+static cplx value_product(const group *g, const uint8_t *w, int d)
+{
+    /* M = G_{w1} G_{w2} ... G_{wd}, then M applied to the seed */
+    mat2 m = g->g[w[0]];
+    for (int j = 1; j < d; j++) m = mat_mul(m, g->g[w[j]]);
+    return mobius(m, g->fix[w[d - 1]]);
+}
+
+static cplx value_literal(const group *g, const uint8_t *w, int d)
+{
+    /* z0 = seed; z <- G_{wj}(z) for j = d, d-1, ..., 1 */
+    cplx z = g->fix[w[d - 1]];
+    for (int j = d - 1; j >= 0; j--) z = mobius(g->g[w[j]], z);
+    return z;
+}
+
+static int group_from_arrays(const double *gens, const double *fix, group *g)
+{
+    for (int k = 0; k < 4; k++) {
+        g->g[k].a = get_c(gens + ((k * 2 + 0) * 2 + 0) * 2);
+        g->g[k].b = get_c(gens + ((k * 2 + 0) * 2 + 1) * 2);
+        g->g[k].c = get_c(gens + ((k * 2 + 1) * 2 + 0) * 2);
+        g->g[k].d = get_c(gens + ((k * 2 + 1) * 2 + 1) * 2);
+        g->fix[k] = get_c(fix + 2 * k);
+    }
+    return 0;
+}
+
+int oracle_word_value(const uint8_t *word, int depth, const double *gens,
+                      const double *fix, int literal, double *z_out)
+{
+    if (!word || !gens || !fix || !z_out || depth < 1 || depth > MAX_DEPTH)
+        return -1;
+    for (int j = 0; j < depth; j++) {
+        if (word[j] > 3) return -1;
+        if (j > 0 && word[j] == INVERSE[word[j - 1]]) return -1;
+    }
+    group g;
+    group_from_arrays(gens, fix, &g);
+    put_c(z_out, literal ? value_literal(&g, word, depth)
+                         : value_product(&g, word, depth));
+    return 0;
+}
+
+int oracle_eval(double ta_re, double ta_im, double tb_re, double tb_im,
+                int depth, const uint64_t *idx, uint64_t n, int literal,
+                double *z_out)
+{
+    if (depth < 1 || depth > MAX_DEPTH || (n && (!idx || !z_out))) return -1;
+    group g;
+    int rc = build_group(ta_re + ta_im * I, tb_re + tb_im * I, &g);
+    if (rc) return rc;
+    uint8_t w[MAX_DEPTH];
+    for (uint64_t i = 0; i < n; i++) {
+        if (oracle_unrank(idx[i], depth, w) != 0) return -1;
+        put_c(z_out + 2 * i, literal ? value_literal(&g, w, depth)
+                                     : value_product(&g, w, depth));
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* rendering                                                           */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+    double x0, x1, y0, y1;
+    uint32_t width, height;
+    double edge_tol;
+} window;
+
+/* col = floor((x - x0) W / (x1 - x0)), row = floor((y - y0) H / (y1 - y0));
+ * kept iff both are in range; NaN and infinities are dropped. */
+static int bin_point(const window *w, cplx z, uint32_t *bin, int *near_edge)
+{
+    double x = creal(z), y = cimag(z);
+    *near_edge = 0;
+    if (!isfinite(x) || !isfinite(y)) return 0;
+    double fx = (x - w->x0) * (double)w->width / (w->x1 - w->x0);
+    double fy = (y - w->y0) * (double)w->height / (w->y1 - w->y0);
+    if (w->edge_tol > 0) {
+        double t = w->edge_tol;
+        int in_reach = fx > -t && fx < w->width + t && fy > -t && fy < w->height + t;
+        int close = fabs(fx - nearbyint(fx)) < t || fabs(fy - nearbyint(fy)) < t;
+        *near_edge = in_reach && close;
+    }
+    if (!(fx >= 0 && fx < (double)w->width && fy >= 0 && fy < (double)w->height))
+        return 0;
+    uint32_t col = (uint32_t)floor(fx), row = (uint32_t)floor(fy);
+    *bin = row * w->width + col;
+    return 1;
+}
+
+typedef struct {
+    const group *g;
+    const window *win;
+    int depth;
+    uint64_t first, last; /* leaf range [first, last) of this depth */
+    uint32_t *image;
+    uint64_t dropped, near_edge;
+    uint8_t word[MAX_DEPTH];
+} render_ctx;
+
+/* Node at depth j with word[0..j-1] and product m = G_{w1}...G_{wj};
+ * its subtree holds the leaves [base, base + 3^(d-j)) (4 * 3^(d-1) for
+ * the root).  Subtrees entirely outside [first, last) are not entered. */
+static void render_rec(render_ctx *r, int j, mat2 m, uint64_t base)
+{
+    int d = r->depth;
+    if (j == d) {
+        cplx z = mobius(m, r->g->fix[r->word[d - 1]]);
+        uint32_t bin;
+        int near;
+        if (bin_point(r->win, z, &bin, &near))
+            r->image[bin] += 1u;
+        else
+            r->dropped++;
+        r->near_edge += (uint64_t)near;
+        return;
+    }
+    uint64_t child_leaves = pow3(d - j - 1);
+    for (int c = 0; c < 4; c++) {
+        if (j > 0 && c == INVERSE[r->word[j - 1]]) continue;
+        uint64_t lo = base, hi = base + child_leaves;
+        base = hi;
+        if (hi <= r->first || lo >= r->last) continue;
+        r->word[j] = (uint8_t)c;
+        mat2 child = (j == 0) ? r->g->g[c] : mat_mul(m, r->g->g[c]);
+        render_rec(r, j + 1, child, lo);
+    }
+}
+
+/* Render the words with combined index in [first, first+count) of the
+ * index space "all words of depth min_depth, then all of min_depth+1, ...,
+ * then all of depth" into image (added to what it holds). */
+static void render_range(const group *g, const window *win, int min_depth,
+                         int depth, uint64_t first, uint64_t count,
+                         uint32_t *image, uint64_t *dropped, uint64_t *near_edge)
+{
+    uint64_t offset = 0, end = first + count;
+    for (int d = min_depth; d <= depth; d++) {
+        uint64_t n = oracle_num_words(d);
+        uint64_t lo = first > offset ? first - offset : 0;
+        uint64_t hi = end - offset < n ? end - offset : n;
+        if (end > offset && first < offset + n && lo < hi) {
+            render_ctx r;
+            memset(&r, 0, sizeof r);
+            r.g = g;
+            r.win = win;
+            r.depth = d;
+            r.first = lo;
+            r.last = hi;
+            r.image = image;
+            mat2 identity = {1, 0, 0, 1};
+            render_rec(&r, 0, identity, 0);
+            *dropped += r.dropped;
+            *near_edge += r.near_edge;
+        }
+        offset += n;
+    }
+}
+
+typedef struct {
+    const group *g;
+    const window *win;
+    int min_depth, depth;
+    uint64_t first, count;
+    uint32_t *image;
+    uint64_t dropped, near_edge;
+} thread_job;
+
+static void *thread_main(void *arg)
+{
+    thread_job *t = (thread_job *)arg;
+    render_range(t->g, t->win, t->min_depth, t->depth, t->first, t->count,
+                 t->image, &t->dropped, &t->near_edge);
+    return NULL;
+}
+
+int oracle_render(double ta_re, double ta_im, double tb_re, double tb_im,
+                  int depth, int min_depth,
+                  double x0, double x1, double y0, double y1,
+                  uint32_t width, uint32_t height,
+                  uint64_t first, uint64_t count, int nthreads,
+                  double edge_tol, uint32_t *image, uint64_t *dropped,
+                  uint64_t *near_edge)
+{
+    if (depth < 1 || depth > MAX_DEPTH || min_depth < 1 || min_depth > depth)
+        return -1;
+    if (!image || width == 0 || height == 0 || !(x1 > x0) || !(y1 > y0))
+        return -1;
+    uint64_t total = 0;
+    for (int d = min_depth; d <= depth; d++) total += oracle_num_words(d);
+    if (first > total || count > total - first) return -1;
+    if (nthreads < 1) nthreads = 1;
+    group g;
+    int rc = build_group(ta_re + ta_im * I, tb_re + tb_im * I, &g);
+    if (rc) return rc;
+    window win = {x0, x1, y0, y1, width, height, edge_tol};
+    uint64_t bins = (uint64_t)width * height;
+
+    /* contiguous sub-ranges, one private image per thread, summed after */
+    thread_job *jobs = (thread_job *)calloc((size_t)nthreads, sizeof(thread_job));
+    pthread_t *tids = (pthread_t *)calloc((size_t)nthreads, sizeof(pthread_t));
+    if (!jobs || !tids) { free(jobs); free(tids); return -1; }
+    uint64_t start = first;
+    for (int t = 0; t < nthreads; t++) {
+        uint64_t share = count / (uint64_t)nthreads + ((uint64_t)t < count % (uint64_t)nthreads);
+        jobs[t].g = &g;
+        jobs[t].win = &win;
+        jobs[t].min_depth = min_depth;
+        jobs[t].depth = depth;
+        jobs[t].first = start;
+        jobs[t].count = share;
+        start += share;
+        jobs[t].image = (t == 0) ? image : (uint32_t *)calloc(bins, sizeof(uint32_t));
+        if (!jobs[t].image) { nthreads = t; rc = -1; break; }
+    }
+    for (int t = 1; t < nthreads; t++) pthread_create(&tids[t], NULL, thread_main, &jobs[t]);
+    if (nthreads > 0) thread_main(&jobs[0]);
+    for (int t = 1; t < nthreads; t++) pthread_join(tids[t], NULL);
+    uint64_t drop = 0, near = 0;
+    for (int t = 0; t < nthreads; t++) {
+        drop += jobs[t].dropped;
+        near += jobs[t].near_edge;
+        if (t > 0) {
+            for (uint64_t i = 0; i < bins; i++) image[i] += jobs[t].image[i];
+            free(jobs[t].image);
+        }
+    }
+    free(jobs);
+    free(tids);
+    if (dropped) *dropped = drop;
+    if (near_edge) *near_edge = near;
+    return rc;
+}

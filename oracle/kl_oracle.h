@@ -1,0 +1,60 @@
+/*
+ * kl_oracle.h -- CPU reference ("oracle") for the indexed Kleinian-attractor
+ * renderer of Rosa, "A new indexed approach to render the attractors of
+ * Kleinian groups" (arXiv:1709.08018).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library is the slow, plain, obviously
+ * correct definition that the GPU path is checked against.  Only the test
+ * suite, the smoke check and the benchmark's CPU-baseline leg may load it.
+ * It shares no code, header, table or constant with the GPU library.
+ *
+ * Conventions (all FP64):
+ *   letters  0=a 1=b 2=A 3=B; A = a^-1, B = b^-1 (Section 3: the group is
+ *            free on a, b; the only crash pairs are aA, Aa, bB, Bb).
+ *   word     w[0..d-1], w[0] is the LEFTMOST letter, applied LAST
+ *            (Section 1: right-to-left reading, W = abA gives
+ *            z1 = A(z0), z2 = b(z1), z3 = a(z2); the last orbit point is
+ *            the word value).
+ *   index    rank of a reduced word of length d in lexicographic order of
+ *            (w[0], ..., w[d-1]) with the letter order above; equivalently
+ *            the rank among the survivors of the paper's scan of all m^d
+ *            digit strings in numeric order (Section 6, index search).
+ *   seed     attracting fixed point of the word's last (rightmost) letter.
+ *   complex  interleaved (re, im) doubles.
+ *   matrix   gens[((letter*2 + row)*2 + col)*2 + part], part 0=re 1=im.
+ *   window   [x0,x1) x [y0,y1), width x height bins, row 0 at y0,
+ *            bin index row*width + col; non-finite values are dropped.
+ *
+ * Return codes: 0 ok, -1 bad argument, -2 singular parameters.
+ */
+#ifndef KL_ORACLE_H
+#define KL_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+uint64_t oracle_num_words(int depth);
+uint64_t oracle_num_tree_nodes(int m, int depth, int tiling);
+int oracle_unrank(uint64_t index, int depth, uint8_t *word);
+int oracle_enumerate(int depth, uint64_t first, uint64_t count, uint8_t *words);
+int oracle_generators(double ta_re, double ta_im, double tb_re, double tb_im,
+                      double *tab_out, double *gens_out, double *fix_out);
+int oracle_word_value(const uint8_t *word, int depth, const double *gens,
+                      const double *fix, int literal, double *z_out);
+int oracle_eval(double ta_re, double ta_im, double tb_re, double tb_im,
+                int depth, const uint64_t *idx, uint64_t n, int literal,
+                double *z_out);
+int oracle_render(double ta_re, double ta_im, double tb_re, double tb_im,
+                  int depth, int min_depth,
+                  double x0, double x1, double y0, double y1,
+                  uint32_t width, uint32_t height,
+                  uint64_t first, uint64_t count, int nthreads,
+                  double edge_tol, uint32_t *image, uint64_t *dropped,
+                  uint64_t *near_edge);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

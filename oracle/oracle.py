@@ -1,0 +1,164 @@
+"""ctypes wrapper of the CPU reference library ``liboracle.so``.
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the
+benchmark's CPU-baseline leg are the only users of this module.  It imports
+nothing from the GPU package and the GPU package imports nothing from it.
+
+Every function here is argument marshalling around ``kl_oracle.c``; the
+arithmetic lives there (FP64, plain definitions; see its header comment for
+the passages of the paper each part follows).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle.so")
+# A test that plants mistakes in a copy of the reference points this at the
+# planted build; nothing else sets it.
+_OVERRIDE = os.environ.get("KL_ORACLE_LIB")
+SOURCES = [os.path.join(HERE, "kl_oracle.c")]
+
+
+def build(force: bool = True) -> str:
+    """Compile ``liboracle.so`` with gcc (plain -O2, no fast-math)."""
+    if force or not os.path.exists(LIB_PATH):
+        cmd = ["gcc", "-std=c99", "-O2", "-fPIC", "-shared", "-Wall",
+               "-Wno-unused-function", "-o", LIB_PATH + ".tmp"] + SOURCES + ["-lm", "-lpthread"]
+        subprocess.run(cmd, check=True)
+        os.replace(LIB_PATH + ".tmp", LIB_PATH)
+    return LIB_PATH
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if _OVERRIDE:
+            L = ctypes.CDLL(_OVERRIDE)
+        else:
+            if not os.path.exists(LIB_PATH):
+                build(force=False)
+            L = ctypes.CDLL(LIB_PATH)
+        u8p = ctypes.POINTER(ctypes.c_uint8)
+        u32p = ctypes.POINTER(ctypes.c_uint32)
+        u64p = ctypes.POINTER(ctypes.c_uint64)
+        dp = ctypes.POINTER(ctypes.c_double)
+        d = ctypes.c_double
+        L.oracle_num_words.argtypes = [ctypes.c_int]
+        L.oracle_num_words.restype = ctypes.c_uint64
+        L.oracle_num_tree_nodes.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int]
+        L.oracle_num_tree_nodes.restype = ctypes.c_uint64
+        L.oracle_unrank.argtypes = [ctypes.c_uint64, ctypes.c_int, u8p]
+        L.oracle_enumerate.argtypes = [ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64, u8p]
+        L.oracle_generators.argtypes = [d, d, d, d, dp, dp, dp]
+        L.oracle_word_value.argtypes = [u8p, ctypes.c_int, dp, dp, ctypes.c_int, dp]
+        L.oracle_eval.argtypes = [d, d, d, d, ctypes.c_int, u64p, ctypes.c_uint64,
+                                  ctypes.c_int, dp]
+        L.oracle_render.argtypes = [d, d, d, d, ctypes.c_int, ctypes.c_int,
+                                    d, d, d, d, ctypes.c_uint32, ctypes.c_uint32,
+                                    ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int, d,
+                                    u32p, u64p, u64p]
+        for f in (L.oracle_unrank, L.oracle_enumerate, L.oracle_generators,
+                  L.oracle_word_value, L.oracle_eval, L.oracle_render):
+            f.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _ptr(a, ctype):
+    return a.ctypes.data_as(ctypes.POINTER(ctype))
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+def _check(rc, what):
+    if rc != 0:
+        raise OracleError(f"{what} failed with code {rc}")
+
+
+def num_words(depth: int) -> int:
+    return int(lib().oracle_num_words(depth))
+
+
+def num_tree_nodes(m: int, depth: int, tiling: bool) -> int:
+    return int(lib().oracle_num_tree_nodes(m, depth, int(tiling)))
+
+
+def unrank(index: int, depth: int) -> np.ndarray:
+    w = np.zeros(depth, np.uint8)
+    _check(lib().oracle_unrank(index, depth, _ptr(w, ctypes.c_uint8)), "unrank")
+    return w
+
+
+def enumerate_words(depth: int, first: int = 0, count: int | None = None) -> np.ndarray:
+    n = num_words(depth)
+    if count is None:
+        count = n - first
+    out = np.zeros((count, depth), np.uint8)
+    _check(lib().oracle_enumerate(depth, first, count, _ptr(out, ctypes.c_uint8)),
+           "enumerate")
+    return out
+
+
+def generators(ta: complex, tb: complex):
+    """Returns (tab, gens[4,2,2] complex, fix[4] complex)."""
+    tab = np.zeros(2)
+    gens = np.zeros(32)
+    fix = np.zeros(8)
+    _check(lib().oracle_generators(ta.real, ta.imag, tb.real, tb.imag,
+                                   _ptr(tab, ctypes.c_double), _ptr(gens, ctypes.c_double),
+                                   _ptr(fix, ctypes.c_double)), "generators")
+    return (complex(tab[0], tab[1]), gens.view(np.complex128).reshape(4, 2, 2),
+            fix.view(np.complex128).copy())
+
+
+def word_value(word, gens, fix, literal: bool = False) -> complex:
+    w = np.ascontiguousarray(word, np.uint8)
+    g = np.ascontiguousarray(np.asarray(gens, np.complex128).reshape(-1)).view(np.float64)
+    f = np.ascontiguousarray(np.asarray(fix, np.complex128)).view(np.float64)
+    z = np.zeros(2)
+    _check(lib().oracle_word_value(_ptr(w, ctypes.c_uint8), len(w), _ptr(g, ctypes.c_double),
+                                   _ptr(f, ctypes.c_double), int(literal),
+                                   _ptr(z, ctypes.c_double)), "word_value")
+    return complex(z[0], z[1])
+
+
+def eval_values(ta: complex, tb: complex, depth: int, idx, literal: bool = False) -> np.ndarray:
+    idx = np.ascontiguousarray(idx, np.uint64)
+    z = np.zeros(2 * len(idx))
+    _check(lib().oracle_eval(ta.real, ta.imag, tb.real, tb.imag, depth,
+                             _ptr(idx, ctypes.c_uint64), len(idx), int(literal),
+                             _ptr(z, ctypes.c_double)), "eval")
+    return z.view(np.complex128)
+
+
+def render(ta: complex, tb: complex, depth: int, window, *, min_depth: int | None = None,
+           first: int = 0, count: int | None = None, nthreads: int = 1,
+           edge_tol: float = 0.0, image: np.ndarray | None = None):
+    """Render into a uint32 image.  window = (x0, x1, y0, y1, width, height).
+
+    Returns (image[height, width], dropped, near_edge)."""
+    x0, x1, y0, y1, W, H = window
+    if min_depth is None:
+        min_depth = depth
+    total = sum(num_words(d) for d in range(min_depth, depth + 1))
+    if count is None:
+        count = total - first
+    if image is None:
+        image = np.zeros((H, W), np.uint32)
+    dropped = ctypes.c_uint64(0)
+    near = ctypes.c_uint64(0)
+    _check(lib().oracle_render(ta.real, ta.imag, tb.real, tb.imag, depth, min_depth,
+                               x0, x1, y0, y1, W, H, first, count, nthreads, edge_tol,
+                               _ptr(image, ctypes.c_uint32), ctypes.byref(dropped),
+                               ctypes.byref(near)), "render")
+    return image, int(dropped.value), int(near.value)

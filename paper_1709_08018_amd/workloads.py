@@ -1,0 +1,99 @@
+"""Workload definitions and seeded parameter draws.
+
+This module holds only the parameters of the workloads (traces, depths,
+windows) and the seeded random draws of parameter sets.  It contains none
+of the method's arithmetic, so both the GPU path and the CPU reference can
+be fed from it.
+
+Workloads (traces are those of the trace recipe; windows are
+(x0, x1, y0, y1, width, height)):
+  fuchsian_tiling_d10   ta = tb = 3 (real, Fuchsian), tiling mode over
+                        depths 1..10, 512 x 512 over [-2, 2]^2
+  quasifuchsian_d18     ta = 1.91 + 0.05i, tb = 2, limit set at depth 18,
+                        2048 x 2048 over [-1.5, 1.5]^2
+  quasifuchsian_d22     same traces, depth 22, 4096 x 4096 over
+                        [-1.5, 1.5]^2, streamed by index range
+  batch256              256 parameter sets: Re ta, Re tb ~ U[1.8, 3.0],
+                        Im ta, Im tb ~ U[-0.3, 0.3], depth ~ U{12..18},
+                        512 x 512 over [-2, 2]^2 each
+  surrogate             parameter sets drawn as batch256 at depth 14,
+                        128 x 128 occupancy over [-2, 2]^2
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+C2_TA = complex(1.91, 0.05)
+C2_TB = complex(2.0, 0.0)
+C1_TA = complex(3.0, 0.0)
+C1_TB = complex(3.0, 0.0)
+
+
+@dataclass(frozen=True)
+class Window:
+    x0: float
+    x1: float
+    y0: float
+    y1: float
+    width: int
+    height: int
+
+    def as_tuple(self):
+        return (self.x0, self.x1, self.y0, self.y1, self.width, self.height)
+
+    @property
+    def pixel(self) -> float:
+        return (self.x1 - self.x0) / self.width
+
+
+@dataclass(frozen=True)
+class Workload:
+    name: str
+    ta: complex
+    tb: complex
+    depth: int
+    min_depth: int
+    window: Window
+
+
+FUCHSIAN_TILING_D10 = Workload("fuchsian_tiling_d10", C1_TA, C1_TB, 10, 1,
+                               Window(-2.0, 2.0, -2.0, 2.0, 512, 512))
+QUASIFUCHSIAN_D18 = Workload("quasifuchsian_d18", C2_TA, C2_TB, 18, 18,
+                             Window(-1.5, 1.5, -1.5, 1.5, 2048, 2048))
+QUASIFUCHSIAN_D22 = Workload("quasifuchsian_d22", C2_TA, C2_TB, 22, 22,
+                             Window(-1.5, 1.5, -1.5, 1.5, 4096, 4096))
+BATCH_WINDOW = Window(-2.0, 2.0, -2.0, 2.0, 512, 512)
+SURROGATE_WINDOW = Window(-2.0, 2.0, -2.0, 2.0, 128, 128)
+SURROGATE_DEPTH = 14
+
+
+def draw_param_sets(n: int, seed: int, depth_range=(12, 18)):
+    """n parameter sets (ta, tb, depth) from numpy's PCG64 with the given seed.
+
+    Re ta, Re tb ~ U[1.8, 3.0]; Im ta, Im tb ~ U[-0.3, 0.3];
+    depth ~ uniform integer in depth_range (inclusive)."""
+    rng = np.random.default_rng(seed)
+    re = rng.uniform(1.8, 3.0, size=(n, 2))
+    im = rng.uniform(-0.3, 0.3, size=(n, 2))
+    lo, hi = depth_range
+    depth = rng.integers(lo, hi + 1, size=n)
+    ta = re[:, 0] + 1j * im[:, 0]
+    tb = re[:, 1] + 1j * im[:, 1]
+    return ta.astype(np.complex128), tb.astype(np.complex128), depth.astype(np.int32)
+
+
+def batch256(seed: int = 0):
+    return draw_param_sets(256, seed, (12, 18))
+
+
+def surrogate_sets(n: int, seed: int):
+    ta, tb, _ = draw_param_sets(n, seed, (SURROGATE_DEPTH, SURROGATE_DEPTH))
+    return ta, tb
+
+
+def sample_indices(n_words: int, n: int, seed: int = 0) -> np.ndarray:
+    """n word indices drawn uniformly from [0, n_words) with PCG64(seed)."""
+    rng = np.random.default_rng(seed)
+    return np.sort(rng.integers(0, n_words, size=n, dtype=np.uint64))

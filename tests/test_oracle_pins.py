@@ -1,0 +1,267 @@
+"""Pins of the CPU reference against what the paper and the mathematics fix.
+
+None of these re-types the reference's own formulas: each checks it against
+an independent fact -- the paper's printed tables and worked examples, a
+brute-force scan written from the paper's description, closed-form counts,
+group invariants that the trace recipe must satisfy, eigenvectors computed by
+numpy, and the geometry of real-trace (Fuchsian) groups.
+"""
+import itertools
+import os
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1709_08018_amd import workloads as wl
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+LETTERS = "abAB"
+
+
+def _read_table(name):
+    rows = []
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                rows.append([int(x) for x in line.split()])
+    return np.array(rows)
+
+
+def _walk(table, symbols):
+    """Read the indexed word right to left from state 0 (Section 5)."""
+    states, state = [], 0
+    for s in reversed(symbols):
+        state = int(table[state][s])
+        states.append(state)
+        if state == 0:
+            return states, "crash"
+    return states, "regular"
+
+
+def test_table_walk_worked_examples():
+    tables = {"t11": _read_table("cayley_t11_indexed.txt"),
+              "klein4": _read_table("cayley_klein4_indexed.txt")}
+    with open(os.path.join(GOLDEN, "cayley_walks.txt")) as f:
+        cases = [l.split() for l in f if l.strip() and not l.startswith("#")]
+    assert len(cases) == 3
+    for table, word, states, verdict in cases:
+        got_states, got_verdict = _walk(tables[table], [int(c) for c in word])
+        assert got_states == [int(s) for s in states.split(",")]
+        assert got_verdict == verdict
+
+
+def _paper_scan(depth):
+    """Survivors of the paper's index search in its numeric order.
+
+    Every n in [0, 4^d) is written with d base-4 digits, most significant
+    digit leftmost; digit k is symbol k + 1 of the indexed table (I = 0 is
+    kept for the identity / crash state); words whose table walk reaches the
+    crash state are skipped (Sections 5 and 6)."""
+    table = _read_table("cayley_t11_indexed.txt")
+    out = []
+    for digits in itertools.product(range(4), repeat=depth):
+        if _walk(table, [d + 1 for d in digits])[1] == "regular":
+            out.append(digits)
+    return np.array(out, np.uint8)
+
+
+@pytest.mark.parametrize("depth", [1, 2, 3, 4, 5, 6, 7])
+def test_order_equals_paper_scan(depth):
+    scan = _paper_scan(depth)
+    assert len(scan) == O.num_words(depth) == 4 * 3 ** (depth - 1)
+    dfs = O.enumerate_words(depth)
+    np.testing.assert_array_equal(dfs, scan)
+    for i in range(len(scan)):
+        np.testing.assert_array_equal(O.unrank(i, depth), scan[i])
+
+
+def test_words_depth2_golden():
+    with open(os.path.join(GOLDEN, "words_depth2.txt")) as f:
+        want = [l for l in f if l.strip() and not l.startswith("#")][0].split()
+    got = ["".join(LETTERS[c] for c in w) for w in O.enumerate_words(2)]
+    assert got == want
+
+
+def test_counts_closed_form_and_paper():
+    for d in range(1, 41):
+        assert O.num_words(d) == 4 * 3 ** (d - 1)
+    assert O.num_words(0) == 0 and O.num_words(41) == 0
+    with open(os.path.join(GOLDEN, "paper_counts.txt")) as f:
+        m, depth, mode, approx = [l for l in f if l.strip() and not l.startswith("#")][0].split()
+    sigma = O.num_tree_nodes(int(m), int(depth), mode == "tiling")
+    assert sigma == sum(4 ** d for d in range(1, 15))
+    assert abs(sigma - int(approx)) / int(approx) < 0.03       # "about 350 millions"
+    assert O.num_tree_nodes(4, 14, False) == 4 ** 14
+
+
+@pytest.mark.parametrize("depth", [9, 18, 22, 40])
+def test_unrank_structure(depth):
+    n = O.num_words(depth)
+    assert list(O.unrank(0, depth)) == [0] * depth            # a...a
+    assert list(O.unrank(n - 1, depth)) == [3] * depth        # B...B
+    rng = np.random.default_rng(depth)
+    for i in rng.integers(0, n, size=200, dtype=np.uint64):
+        w = O.unrank(int(i), depth)
+        assert all(w[j + 1] != (w[j] ^ 2) for j in range(depth - 1))   # reduced
+        for k in (1, depth // 2, depth - 1):
+            np.testing.assert_array_equal(w[:k], O.unrank(int(i) // 3 ** (depth - k), k))
+    with pytest.raises(O.OracleError):
+        O.unrank(n, depth)
+
+
+def _mobius(m, z):
+    return (m[0, 0] * z + m[0, 1]) / (m[1, 0] * z + m[1, 1])
+
+
+def _param_sets():
+    ta, tb, _ = wl.draw_param_sets(16, seed=11)
+    return [(wl.C1_TA, wl.C1_TB), (wl.C2_TA, wl.C2_TB)] + list(zip(ta, tb))
+
+
+@pytest.mark.parametrize("ta,tb", _param_sets())
+def test_recipe_invariants(ta, tb):
+    tab, g, fix = O.generators(complex(ta), complex(tb))
+    a, b, A, B = g
+    I2 = np.eye(2)
+    for m in g:
+        assert abs(np.linalg.det(m) - 1) < 1e-12
+    np.testing.assert_allclose(a @ A, I2, atol=1e-12)
+    np.testing.assert_allclose(b @ B, I2, atol=1e-12)
+    assert abs(np.trace(a) - ta) < 1e-12
+    assert abs(np.trace(b) - tb) < 1e-12
+    assert abs(np.trace(a @ b) - tab) < 1e-11 * max(1, abs(tab))
+    assert abs(np.trace(a @ b @ A @ B) + 2) < 1e-10
+    assert abs(tab ** 2 - ta * tb * tab + ta ** 2 + tb ** 2) < 1e-10 * max(1, abs(tab) ** 2)
+    # root in the closed upper half plane of s = 2 tab - ta tb
+    s = 2 * tab - ta * tb
+    assert s.imag > -1e-12 and (abs(s.imag) > 1e-12 or s.real >= 0)
+
+
+def test_recipe_root_values():
+    assert O.generators(wl.C1_TA, wl.C1_TB)[0] == pytest.approx(6.0)
+    tab2 = O.generators(wl.C2_TA, wl.C2_TB)[0]
+    assert abs(tab2 - complex(1.91, 2.05)) < 1e-12
+    # the other root of the quadratic is ta tb - tab
+    other = wl.C2_TA * wl.C2_TB - tab2
+    assert abs(other ** 2 - wl.C2_TA * wl.C2_TB * other + wl.C2_TA ** 2 + wl.C2_TB ** 2) < 1e-12
+
+
+@pytest.mark.parametrize("ta,tb", _param_sets())
+def test_seeds_are_attracting_fixed_points(ta, tb):
+    _, g, fix = O.generators(complex(ta), complex(tb))
+    for m, z in zip(g, fix):
+        assert abs(_mobius(m, z) - z) < 1e-9 * max(1, abs(z))
+        # eigenvector (z, 1) of the larger-modulus eigenvalue is the attracting point
+        w, v = np.linalg.eig(m)
+        if abs(abs(w[0]) - abs(w[1])) > 1e-6:
+            k = int(np.argmax(np.abs(w)))
+            z_eig = v[0, k] / v[1, k]
+            assert abs(z_eig - z) < 1e-8 * max(1, abs(z))
+
+
+def test_c1_geometry():
+    _, g, fix = O.generators(wl.C1_TA, wl.C1_TB)
+    np.testing.assert_allclose(np.abs(fix), 1.0, atol=1e-14)
+    for d in range(1, 9):
+        z = O.eval_values(wl.C1_TA, wl.C1_TB, d, np.arange(O.num_words(d), dtype=np.uint64))
+        assert np.abs(np.abs(z) - 1).max() < 1e-9
+
+
+def test_depth1_values_are_seeds():
+    for ta, tb in [(wl.C1_TA, wl.C1_TB), (wl.C2_TA, wl.C2_TB)]:
+        _, _, fix = O.generators(ta, tb)
+        z = O.eval_values(ta, tb, 1, np.arange(4, dtype=np.uint64))
+        assert (np.abs(z - fix) / np.maximum(1, np.abs(fix))).max() < 1e-14
+
+
+def test_right_to_left_recursion():
+    """value(c w') = G_c(value(w')) when both words end in the same letter."""
+    _, g, fix = O.generators(wl.C2_TA, wl.C2_TB)
+    rng = np.random.default_rng(5)
+    for d in (2, 9, 17):
+        for i in rng.integers(0, O.num_words(d + 1), size=50, dtype=np.uint64):
+            w = O.unrank(int(i), d + 1)
+            z_long = O.word_value(w, g, fix)
+            z_short = O.word_value(w[1:], g, fix)
+            assert abs(_mobius(g[w[0]], z_short) - z_long) < 1e-11 * max(1, abs(z_long))
+
+
+@pytest.mark.parametrize("pair", ["ab", "aB", "bA", "BA"])
+def test_periodic_words_converge_to_product_fixed_point(pair):
+    """(xy)^k applied to any seed tends to the attracting eigenvector of x y."""
+    _, g, fix = O.generators(wl.C2_TA, wl.C2_TB)
+    x, y = (LETTERS.index(c) for c in pair)
+    m = g[x] @ g[y]
+    w, v = np.linalg.eig(m)
+    k = int(np.argmax(np.abs(w)))
+    target = v[0, k] / v[1, k]
+    word = np.array([x, y] * 14, np.uint8)
+    assert abs(O.word_value(word, g, fix) - target) < 1e-9
+    # the mirrored order (yx)^k tends elsewhere: this pins right-to-left reading
+    m2 = g[y] @ g[x]
+    w2, v2 = np.linalg.eig(m2)
+    k2 = int(np.argmax(np.abs(w2)))
+    assert abs(v2[0, k2] / v2[1, k2] - target) > 1e-3
+
+
+def test_literal_and_product_evaluators_agree():
+    for d in (12, 18, 22):
+        idx = wl.sample_indices(O.num_words(d), 2000, seed=d)
+        zp = O.eval_values(wl.C2_TA, wl.C2_TB, d, idx)
+        zl = O.eval_values(wl.C2_TA, wl.C2_TB, d, idx, literal=True)
+        assert (np.abs(zp - zl) / np.maximum(1, np.abs(zp))).max() < 1e-12
+
+
+WIN = (-1.5, 1.5, -1.5, 1.5, 96, 80)
+
+
+def _bin_numpy(z, win):
+    x0, x1, y0, y1, W, H = win
+    fx = (z.real - x0) * W / (x1 - x0)
+    fy = (z.imag - y0) * H / (y1 - y0)
+    ok = np.isfinite(fx) & np.isfinite(fy) & (fx >= 0) & (fx < W) & (fy >= 0) & (fy < H)
+    img = np.zeros(H * W, np.uint64)
+    np.add.at(img, (np.floor(fy[ok]).astype(np.int64) * W + np.floor(fx[ok]).astype(np.int64)), 1)
+    return img.reshape(H, W), int((~ok).sum())
+
+
+def test_render_invariants():
+    d = 9
+    n = O.num_words(d)
+    img, dropped, _ = O.render(wl.C2_TA, wl.C2_TB, d, WIN)
+    assert int(img.sum(dtype=np.uint64)) + dropped == n
+    # the DFS render equals the unrank-and-evaluate path binned independently
+    z = O.eval_values(wl.C2_TA, wl.C2_TB, d, np.arange(n, dtype=np.uint64))
+    ref, ref_drop = _bin_numpy(z, WIN)
+    np.testing.assert_array_equal(img, ref)
+    assert dropped == ref_drop
+    # range additivity and threads
+    cut = 12345
+    a, da, _ = O.render(wl.C2_TA, wl.C2_TB, d, WIN, first=0, count=cut)
+    b, db, _ = O.render(wl.C2_TA, wl.C2_TB, d, WIN, first=cut)
+    np.testing.assert_array_equal(a + b, img)
+    assert da + db == dropped
+    t4, d4, _ = O.render(wl.C2_TA, wl.C2_TB, d, WIN, nthreads=4)
+    np.testing.assert_array_equal(t4, img)
+    assert d4 == dropped
+
+
+def test_tiling_is_sum_of_limit_sets():
+    win = (-2.0, 2.0, -2.0, 2.0, 64, 64)
+    tiling, dt, _ = O.render(wl.C1_TA, wl.C1_TB, 6, win, min_depth=1)
+    acc = np.zeros((64, 64), np.uint32)
+    drop = 0
+    for d in range(1, 7):
+        img, dd, _ = O.render(wl.C1_TA, wl.C1_TB, d, win)
+        acc += img
+        drop += dd
+    np.testing.assert_array_equal(tiling, acc)
+    assert dt == drop
+    assert int(tiling.sum()) + dt == sum(O.num_words(d) for d in range(1, 7))
+
+
+def test_singular_parameters_rejected():
+    # ta = tb = 0 gives tab = 0, which zeroes the recipe's denominator tb tab - 2 ta + 2i tab
+    with pytest.raises(O.OracleError):
+        O.generators(complex(0.0, 0.0), complex(0.0, 0.0))
