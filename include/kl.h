@@ -1,0 +1,219 @@
+/*
+ * kl.h -- C ABI of libkl, an indexed renderer for the attractors (limit
+ * sets) of once-punctured-torus Kleinian groups on AMD Instinct MI355X
+ * (gfx950), after A. Rosa, "A new indexed approach to render the attractors
+ * of Kleinian groups", arXiv:1709.08018.
+ *
+ * The paper's problem statement (abstract, Section 4 and Section 6): words
+ * over the alphabet {a, b, A, B} are not stored in a dictionary but pulled
+ * out of integer indices; every reduced word (no crash pair aA, Aa, bB, Bb:
+ * Sections 1 and 3, Table 1) of the requested depth is visited, its
+ * Moebius maps are applied right to left to a seed point (Section 1: for
+ * W = abA, z1 = A(z0), z2 = b(z1), z3 = a(z2); the last orbit point is the
+ * word value) and the value is drawn (Section 6, index search).
+ *
+ * Conventions shared by every entry point
+ * ----------------------------------------
+ * letters   0 = a, 1 = b, 2 = A, 3 = B; A = a^-1, B = b^-1, so the inverse of
+ *           letter c is c ^ 2.  Letter 0 of a word is its LEFTMOST letter,
+ *           the one applied last.
+ * index     the reduced words of depth d are numbered 0 .. 4*3^(d-1) - 1 in
+ *           lexicographic order with the letter order above (first letter
+ *           most significant).  This is the order in which the paper's scan
+ *           of all 4^d digit strings (Section 6) meets the words that pass
+ *           its Cayley-table check (Section 5), renumbered densely.
+ * tiling    with min_depth < depth (kl_opts), every word of every depth
+ *           min_depth .. depth is drawn ("tiling" render mode of Section 6);
+ *           the index space is then all words of depth min_depth, followed
+ *           by all of depth min_depth + 1, ..., followed by all of depth.
+ *           Otherwise only words of length depth are drawn ("limit set").
+ * group     ta = tr a, tb = tr b; the generators come from the trace recipe
+ *           (Indra's Pearls' "Grandma's recipe", which the paper cites for
+ *           its generators): tab = tr ab is the root (ta tb + s)/2 of
+ *           tab^2 - ta tb tab + ta^2 + tb^2 = 0 with s in the closed upper
+ *           half plane, so that tr abAB = -2.
+ * seed      the attracting fixed point of the word's last letter.
+ * window    [x0, x1) x [y0, y1) split into width x height bins; row 0 holds
+ *           y in [y0, y0 + (y1 - y0)/height); bin index row * width + col.
+ *           Values outside the window or not finite are dropped.
+ * images    uint32 counts, row-major; additions wrap modulo 2^32.
+ * memory    pointers named *_out, idx, letters_out, image_out and images_out
+ *           are DEVICE pointers (memory of the current HIP device); all
+ *           others are host pointers.  The caller owns every buffer; the
+ *           library never frees caller memory.  The library allocates its
+ *           own temporaries with hipMallocAsync on the call's stream.
+ * streams   the plain entry points run on the null stream and return after
+ *           the device has finished; the *_ex entry points enqueue on
+ *           opts->stream (a hipStream_t, NULL = null stream) and return at
+ *           once, except where a host output is requested.
+ * errors    0 on success, a negative KL_E* code otherwise.  Every argument
+ *           is validated before anything is enqueued, and on error no
+ *           output is touched.  kl_strerror() names a code;
+ *           kl_last_error() describes the last failure of the calling
+ *           thread.
+ */
+#ifndef KL_H
+#define KL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define KL_OK 0
+#define KL_EINVAL (-1)     /* null pointer, depth outside 1..40, bad window, bad option */
+#define KL_ERANGE (-2)     /* index range beyond the words of the requested depth(s) */
+#define KL_ESINGULAR (-3)  /* traces for which the recipe or a seed is undefined */
+#define KL_EDEVICE (-4)    /* a HIP call failed */
+#define KL_ENOMEM (-5)     /* device memory for temporaries could not be allocated */
+
+#define KL_MAX_DEPTH 40
+
+/* precision of the word values */
+#define KL_PREC_FP32 0  /* FP64 generators, seeds and prefix products; FP32 suffix maps */
+#define KL_PREC_FP64 1  /* every step in FP64 */
+
+/* histogram strategy of the renderer */
+#define KL_HIST_AUTO 0    /* planner's choice */
+#define KL_HIST_RUNS 1    /* per-lane run-length counts, flushed with global atomics */
+#define KL_HIST_LDS 2     /* per-lane runs flushed into an LDS tile, merged per work unit */
+
+typedef struct { double re, im; } kl_c64;
+
+typedef struct {
+    double x0, x1, y0, y1;
+    uint32_t width, height;
+} kl_window;
+
+/* Options of the *_ex entry points.  A zero-initialised struct gives the
+ * defaults of the plain entry points (limit set, FP32 suffix path, whole
+ * index space, image cleared first, null stream, planner's split). */
+typedef struct {
+    int min_depth;        /* 0 or depth: limit set; 1 .. depth-1: tiling */
+    int precision;        /* KL_PREC_FP32 or KL_PREC_FP64 */
+    int use_range;        /* 0: every index; 1: only [first_idx, first_idx + count) */
+    uint64_t first_idx;
+    uint64_t count;
+    int accumulate;       /* 0: image cleared before drawing; 1: counts added */
+    void *stream;         /* hipStream_t; NULL = null stream */
+    uint64_t *dropped_out;/* device pointer to one uint64 or NULL: receives
+                             (or, with accumulate, is increased by) the number
+                             of words dropped as outside or not finite */
+    int tail_len;         /* r: letters per suffix table, 0 = planner (1..8) */
+    int lane_len;         /* m: letters each lane adds to its prefix, 0 = planner (1..20) */
+    int hist_mode;        /* KL_HIST_* */
+    int waves_per_cu;     /* persistent grid size, 0 = planner */
+    int suffix_form;      /* 0: affine suffix points unless one needs the
+                             homogeneous form; 1: homogeneous form always */
+} kl_opts;
+
+/* The split the renderer uses for one depth (see kl_plan). */
+typedef struct {
+    int depth;
+    int tail_len;      /* r: suffix letters enumerated from the LDS suffix table */
+    int lane_len;      /* m: letters a lane appends to its table prefix in FP64 */
+    int prefix_len;    /* k = depth - r - m: letters of the FP64 prefix table */
+    int hist_mode;
+    int waves_per_cu;
+} kl_plan_t;
+
+/* Number of reduced words of length depth, 4 * 3^(depth-1); 0 when depth
+ * is outside 1..40. */
+uint64_t kl_num_words(int depth);
+
+/* kl_decode: the words with indices first_idx .. first_idx + count - 1 of
+ * depth `depth` (Section 4, digital and indexed trees; Section 6, the
+ * index-to-word routine), without any stored word list.
+ *   letters_out  device buffer of count * depth bytes, word-major: letter j
+ *                of word first_idx + i is letters_out[i * depth + j].
+ * Errors: KL_EINVAL (depth, null pointer with count > 0), KL_ERANGE
+ * (first_idx + count exceeds the number of words, including overflow; the
+ * paper's routine silently wraps such indices, this one refuses them). */
+int kl_decode(uint64_t first_idx, uint64_t count, int depth, uint8_t *letters_out);
+int kl_decode_ex(uint64_t first_idx, uint64_t count, int depth, uint8_t *letters_out,
+                 void *stream);
+
+/* kl_render: limit-set image of the group with traces (ta, tb) at depth
+ * `depth` (Section 6, index search, limit-set mode): every reduced word of
+ * that length is decoded from its index, evaluated right to left from its
+ * seed and counted in its bin of image_out (device, width * height uint32,
+ * cleared first).  FP32 suffix path (see KL_PREC_FP32).
+ * Errors: KL_EINVAL, KL_ESINGULAR, KL_EDEVICE, KL_ENOMEM. */
+int kl_render(kl_c64 ta, kl_c64 tb, int depth, const kl_window *window, uint32_t *image_out);
+
+/* kl_render_ex: as kl_render with options: tiling mode (min_depth), FP64
+ * path, an index sub-range (streaming: rendering [0, x) then [x, N) with
+ * accumulate gives exactly the image of [0, N)), accumulation, a stream,
+ * the dropped-word count, and explicit split/histogram choices. */
+int kl_render_ex(kl_c64 ta, kl_c64 tb, int depth, const kl_window *window,
+                 uint32_t *image_out, const kl_opts *opts);
+
+/* kl_render_many: n independent limit-set renders in one persistent launch
+ * (parameter sets of uneven depth share one work queue).
+ *   ta, tb, depth  host arrays of n entries
+ *   images_out     device, n * width * height uint32; image i starts at
+ *                  images_out + i * width * height; each is cleared first.
+ * Image i equals kl_render(ta[i], tb[i], depth[i], window, ...) bit for bit.
+ * Errors: as kl_render; the message of kl_last_error() names the first bad
+ * set. */
+int kl_render_many(int n, const kl_c64 *ta, const kl_c64 *tb, const int *depth,
+                   const kl_window *window, uint32_t *images_out);
+/* opts: precision, accumulate, stream, hist_mode, waves_per_cu, tail_len
+ * and lane_len apply to every set (0 = planner per set);
+ * min_depth and use_range must be 0.  dropped_out, if set, points to n
+ * device uint64 counters, one per set. */
+int kl_render_many_ex(int n, const kl_c64 *ta, const kl_c64 *tb, const int *depth,
+                      const kl_window *window, uint32_t *images_out, const kl_opts *opts);
+
+/* kl_eval: values of the words with the given indices, computed with
+ * exactly the arithmetic the renderer uses for the same depth, precision
+ * and split (Section 1, word value).
+ *   idx     device, n uint64 word indices of depth `depth`
+ *   z_out   device, n complex values (re, im as doubles)
+ * kl_eval_ex additionally takes a window: with one, z_out receives the
+ * continuous pixel coordinates (col + fraction, row + fraction) the
+ * renderer floors into a bin, bit for bit; and options (precision, split,
+ * stream; the other fields are ignored).
+ * An index beyond the words of that depth yields NaN (the indices live in
+ * device memory and are checked there).
+ * Errors: KL_EINVAL, KL_ESINGULAR, KL_EDEVICE. */
+int kl_eval(kl_c64 ta, kl_c64 tb, int depth, const uint64_t *idx, uint64_t n,
+            int precision, kl_c64 *z_out);
+int kl_eval_ex(kl_c64 ta, kl_c64 tb, int depth, const uint64_t *idx, uint64_t n,
+               const kl_window *window, kl_c64 *z_out, const kl_opts *opts);
+
+/* kl_generators: host-side trace recipe and seeds, FP64.
+ *   tab_out     tr ab
+ *   gens_out    16 entries: generator g (0=a 1=b 2=A 3=B) entry (row, col)
+ *               at gens_out[g * 4 + row * 2 + col]
+ *   fix_out     4 entries: attracting fixed point of each generator
+ * Any output pointer may be NULL.  Errors: KL_ESINGULAR. */
+int kl_generators(kl_c64 ta, kl_c64 tb, kl_c64 *tab_out, kl_c64 *gens_out, kl_c64 *fix_out);
+
+/* kl_plan: the split and histogram strategy the renderer would use for one
+ * depth and precision on the current device, after the options' overrides.
+ * Errors: KL_EINVAL. */
+int kl_plan(int depth, int precision, const kl_window *window, const kl_opts *opts,
+            kl_plan_t *plan_out);
+
+/* kl_autotune: times the candidate splits, histogram strategies and grid
+ * sizes for (ta, tb, depth, window, precision) on the current device,
+ * keeps the fastest as the plan for every later render with the same
+ * (depth, precision, width, height) in this process, and appends it to
+ * the file named by the environment variable KL_AUTOTUNE_CACHE, if set
+ * (that file is read back at library load).  scratch_image: device,
+ * width * height uint32, overwritten.  best_out may be NULL; best_ms_out
+ * (host, may be NULL) receives the winner's median time.
+ * Errors: as kl_render_ex. */
+int kl_autotune(kl_c64 ta, kl_c64 tb, int depth, const kl_window *window, int precision,
+                uint32_t *scratch_image, kl_plan_t *best_out, double *best_ms_out);
+
+const char *kl_strerror(int code);
+const char *kl_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KL_H */

@@ -1,0 +1,41 @@
+"""Build ``libkl.so`` (HIP, gfx950) in the package directory.
+
+The library is compiled in place so that it travels with the source tree:
+    python -m paper_1709_08018_amd.build
+"""
+from __future__ import annotations
+
+import os
+import subprocess
+import sys
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(PKG)
+CSRC = os.path.join(PKG, "csrc")
+LIB = os.path.join(PKG, "libkl.so")
+SOURCES = [os.path.join(CSRC, f) for f in ("kernels.hip", "batch.hip", "abi.cpp", "autotune.cpp")]
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+
+FLAGS = [
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    # every floating-point step is written out; no contraction behind our back
+    "-ffp-contract=off",
+    # packed FP32 instructions stay off
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-Wall", "-Wno-unused-function", "-Wno-unused-result",
+    "-I", os.path.join(ROOT, "include"), "-I", CSRC,
+]
+
+
+def build(verbose: bool = False) -> str:
+    srcs = [s for s in SOURCES if os.path.exists(s)]
+    cmd = [HIPCC] + FLAGS + ["-o", LIB + ".tmp", "-x", "hip"] + srcs
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(LIB + ".tmp", LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    build(verbose="-v" in sys.argv)

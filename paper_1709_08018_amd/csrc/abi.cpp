@@ -1,0 +1,825 @@
+// abi.cpp -- host side of libkl: argument validation, the trace recipe and
+// seeds in FP64, planning of the head/tail split, device temporaries, and
+// the extern "C" entry points declared in include/kl.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "kl_internal.hpp"
+
+namespace kl {
+
+// ------------------------------------------------------------------ errors
+static thread_local std::string g_last_error;
+
+static int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+static int hip_fail(hipError_t e, const char* what) {
+    return fail(e == hipErrorOutOfMemory ? KL_ENOMEM : KL_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+// ------------------------------------------------------------------ counting
+uint64_t pow3_u64(int n) {
+    uint64_t p = 1;
+    for (int i = 0; i < n; ++i) p *= 3;
+    return p;
+}
+
+uint64_t num_words(int depth) {
+    if (depth < 1 || depth > KL_MAX_DEPTH) return 0;
+    return 4 * pow3_u64(depth - 1);
+}
+
+// ------------------------------------------------------------------ recipe
+using cd = std::complex<double>;
+
+static bool finite(cd z) { return std::isfinite(z.real()) && std::isfinite(z.imag()); }
+
+// Attracting fixed point of [[a, b], [c, d]] (det 1): the eigenvector
+// (lambda - d, c) of the eigenvalue of larger modulus; lambda =
+// (tr +- sqrt(tr^2 - 4)) / 2.  Equal moduli (parabolic, elliptic) take the
+// "+" eigenvalue.
+static int attracting_point(const cd m[4], cd* out) {
+    const cd a = m[0], b = m[1], c = m[2], d = m[3];
+    if (c == cd(0.0)) return KL_ESINGULAR;
+    const cd disc = (a - d) * (a - d) + 4.0 * b * c;
+    const cd root = std::sqrt(disc);
+    const cd zp = ((a - d) + root) / (2.0 * c);
+    const cd zm = ((a - d) - root) / (2.0 * c);
+    // |g'(z)| = 1 / |c z + d|^2: the attracting point has the larger |c z + d|
+    const double kp = std::abs(c * zp + d), km = std::abs(c * zm + d);
+    *out = km > kp ? zm : zp;
+    return finite(*out) ? KL_OK : KL_ESINGULAR;
+}
+
+// Trace recipe: tab solves tab^2 - ta tb tab + ta^2 + tb^2 = 0, root
+// (ta tb + s)/2 with s in the closed upper half plane.
+static int recipe(cd ta, cd tb, cd* tab_out, cd g[4][4], cd fix[4]) {
+    const cd i1(0.0, 1.0);
+    const cd p = ta * tb;
+    cd s = std::sqrt(p * p - 4.0 * (ta * ta + tb * tb));
+    if (s.imag() < 0.0 || (s.imag() == 0.0 && s.real() < 0.0)) s = -s;
+    const cd tab = (p + s) / 2.0;
+    const cd q_den = tb * tab - 2.0 * ta + 2.0 * i1 * tab;
+    const cd tp = 2.0 * tab + 4.0, tm = 2.0 * tab - 4.0;
+    if (q_den == cd(0.0) || tp == cd(0.0) || tm == cd(0.0))
+        return fail(KL_ESINGULAR, "trace recipe undefined for ta=(%g,%g) tb=(%g,%g)", ta.real(), ta.imag(),
+                    tb.real(), tb.imag());
+    const cd q = (tab - 2.0) * tb / q_den;
+    if (q == cd(0.0)) return fail(KL_ESINGULAR, "trace recipe degenerate (tab = 2 or tb = 0)");
+    const cd a[4] = {ta / 2.0, (ta * tab - 2.0 * tb + 4.0 * i1) / (tp * q),
+                     (ta * tab - 2.0 * tb - 4.0 * i1) * q / tm, ta / 2.0};
+    const cd b[4] = {(tb - 2.0 * i1) / 2.0, tb / 2.0, tb / 2.0, (tb + 2.0 * i1) / 2.0};
+    auto inverse = [](const cd m[4], cd out[4]) {
+        const cd det = m[0] * m[3] - m[1] * m[2];
+        out[0] = m[3] / det;
+        out[1] = -m[1] / det;
+        out[2] = -m[2] / det;
+        out[3] = m[0] / det;
+    };
+    for (int j = 0; j < 4; ++j) {
+        g[0][j] = a[j];
+        g[1][j] = b[j];
+    }
+    inverse(a, g[2]);
+    inverse(b, g[3]);
+    for (int k = 0; k < 4; ++k) {
+        for (int j = 0; j < 4; ++j)
+            if (!finite(g[k][j])) return fail(KL_ESINGULAR, "generator %d not finite", k);
+        if (attracting_point(g[k], &fix[k]) != KL_OK)
+            return fail(KL_ESINGULAR, "generator %d has no finite attracting fixed point", k);
+    }
+    *tab_out = tab;
+    return KL_OK;
+}
+
+static int make_gens(kl_c64 ta, kl_c64 tb, Gens* G, cd* tab_out = nullptr) {
+    cd g[4][4], fix[4], tab;
+    if (!std::isfinite(ta.re) || !std::isfinite(ta.im) || !std::isfinite(tb.re) || !std::isfinite(tb.im))
+        return fail(KL_EINVAL, "traces must be finite");
+    int rc = recipe(cd(ta.re, ta.im), cd(tb.re, tb.im), &tab, g, fix);
+    if (rc) return rc;
+    for (int k = 0; k < 4; ++k) {
+        G->g[k].a = {g[k][0].real(), g[k][0].imag()};
+        G->g[k].b = {g[k][1].real(), g[k][1].imag()};
+        G->g[k].c = {g[k][2].real(), g[k][2].imag()};
+        G->g[k].d = {g[k][3].real(), g[k][3].imag()};
+        G->fix[k] = {fix[k].real(), fix[k].imag()};
+    }
+    if (tab_out) *tab_out = tab;
+    return KL_OK;
+}
+
+// ------------------------------------------------------------------ window
+static int check_window(const kl_window* w) {
+    if (!w) return fail(KL_EINVAL, "window is NULL");
+    if (!std::isfinite(w->x0) || !std::isfinite(w->x1) || !std::isfinite(w->y0) || !std::isfinite(w->y1))
+        return fail(KL_EINVAL, "window bounds must be finite");
+    if (!(w->x1 > w->x0) || !(w->y1 > w->y0)) return fail(KL_EINVAL, "window must have x1 > x0 and y1 > y0");
+    if (w->width < 1 || w->height < 1 || w->width > 32768 || w->height > 32768 ||
+        (uint64_t)w->width * w->height >= (1ull << 31))
+        return fail(KL_EINVAL, "window size %ux%u outside 1..32768 per side, < 2^31 bins", w->width, w->height);
+    return KL_OK;
+}
+
+static Fold make_fold(const kl_window* w) {
+    Fold f;
+    if (!w) {
+        f.s = 1.0;
+        f.o = {0.0, 0.0};
+        f.aniso = 1.0;
+        f.use_aniso = 0;
+        return f;
+    }
+    const double sy = (double)w->height / (w->y1 - w->y0);
+    const double sx = (double)w->width / (w->x1 - w->x0);
+    f.s = sy;
+    f.o = {-w->x0 * sy, -w->y0 * sy};
+    f.aniso = sx / sy;
+    f.use_aniso = (sx != sy);
+    return f;
+}
+
+// ------------------------------------------------------------------ devices
+struct DeviceInfo {
+    int cus = 0;
+};
+static std::mutex g_dev_mutex;
+static std::vector<DeviceInfo> g_devs;
+
+int device_cu_count() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    std::lock_guard<std::mutex> lk(g_dev_mutex);
+    if ((int)g_devs.size() <= dev) g_devs.resize(dev + 1);
+    if (g_devs[dev].cus == 0) {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+            cus = 256;
+        g_devs[dev].cus = cus;
+    }
+    return g_devs[dev].cus;
+}
+
+// ------------------------------------------------------------------ planning
+static const int kDefaultTail = 5;
+static const int kDefaultWavesPerCU = 32;
+
+int plan_split(int depth, int precision, int r_req, int m_req, Split* sp, int prefix_cap) {
+    (void)precision;
+    int r;
+    if (r_req > 0) {
+        if (r_req > kMaxTail || r_req > depth) return fail(KL_EINVAL, "tail_len %d outside 1..min(8, depth)", r_req);
+        r = r_req;
+    } else {
+        r = depth <= 4 ? depth : std::min(kDefaultTail, depth - 1);
+        // the deepest words need a longer tail: k <= 14 and m <= 20
+        r = std::max(r, std::min(kMaxTail, depth - kMaxLane - kMaxPrefix));
+    }
+    const int h = depth - r;
+    int m, k;
+    if (h == 0) {
+        if (m_req > 0) return fail(KL_EINVAL, "lane_len %d needs a head (tail_len < depth)", m_req);
+        m = 0;
+        k = 0;
+    } else {
+        if (m_req > 0) {
+            if (m_req > kMaxLane || m_req > h - 1) return fail(KL_EINVAL, "lane_len %d outside 1..min(20, %d)", m_req, h - 1);
+            m = m_req;
+        } else {
+            m = std::min(std::max(h - prefix_cap, std::min(2, h - 1)), kMaxLane);
+        }
+        k = h - m;
+        if (k > kMaxPrefix) return fail(KL_EINVAL, "prefix table depth %d exceeds %d", k, kMaxPrefix);
+        if (m > kMaxLane) return fail(KL_EINVAL, "lane_len %d exceeds %d", m, kMaxLane);
+    }
+    sp->depth = depth;
+    sp->r = r;
+    sp->m = m;
+    sp->k = k;
+    sp->pow3_m = (uint32_t)pow3_u64(m);
+    sp->R1 = (uint32_t)pow3_u64(r - 1);
+    sp->R = pow3_u64(r);
+    sp->n_heads = (k + m == 0) ? 1 : num_words(k + m);
+    return KL_OK;
+}
+
+// ------------------------------------------------------------------ temporaries
+struct Temp {
+    hipStream_t s;
+    std::vector<void*> ptrs;
+    explicit Temp(hipStream_t st) : s(st) {}
+    hipError_t alloc(void** p, size_t bytes) {
+        *p = nullptr;
+        if (bytes == 0) bytes = 16;
+        hipError_t e = hipMallocAsync(p, bytes, s);
+        if (e == hipSuccess) ptrs.push_back(*p);
+        return e;
+    }
+    ~Temp() {
+        for (void* p : ptrs) (void)hipFreeAsync(p, s);
+    }
+};
+
+// Device tables of one parameter set for one split.
+struct SetTables {
+    Tables tab{};
+    const void* tail_homog = nullptr;
+};
+
+static int build_tables(const Gens& G, const Split& sp, int precision, int force_homog, Temp& tmp,
+                        SetTables* out) {
+    hipError_t e;
+    m64* prefix = nullptr;
+    uint8_t* last = nullptr;
+    if (sp.k > 0) {
+        const uint64_t np = num_words(sp.k);
+        if ((e = tmp.alloc((void**)&prefix, np * sizeof(m64))) != hipSuccess) return hip_fail(e, "prefix table");
+        if ((e = tmp.alloc((void**)&last, np)) != hipSuccess) return hip_fail(e, "prefix letters");
+        if ((e = launch_prefix_table(G, sp.k, prefix, last, tmp.s)) != hipSuccess) return hip_fail(e, "prefix kernel");
+    }
+    const uint64_t nt = num_words(sp.r);
+    const size_t esz = precision == KL_PREC_FP64 ? sizeof(c64) : sizeof(c32);
+    void *aff = nullptr, *hom = nullptr;
+    uint32_t* flags = nullptr;
+    if ((e = tmp.alloc(&aff, nt * esz + 16)) != hipSuccess) return hip_fail(e, "suffix table");
+    if ((e = tmp.alloc(&hom, 2 * nt * esz + 16)) != hipSuccess) return hip_fail(e, "suffix table");
+    if ((e = tmp.alloc((void**)&flags, 16)) != hipSuccess) return hip_fail(e, "suffix flags");
+    if ((e = launch_fill_u32(flags, 1, 0, tmp.s)) != hipSuccess) return hip_fail(e, "fill");
+    if ((e = launch_tail_table(G, sp.r, precision, aff, hom, flags, tmp.s)) != hipSuccess)
+        return hip_fail(e, "suffix kernel");
+    if (force_homog && (e = launch_fill_u32(flags, 1, 1, tmp.s)) != hipSuccess) return hip_fail(e, "fill");
+    out->tab.prefix = prefix;
+    out->tab.prefix_last = last;
+    out->tab.tail = aff;
+    out->tab.tail_flags = flags;
+    out->tail_homog = hom;
+    return KL_OK;
+}
+
+static int grid_for(int waves_per_cu) {
+    if (waves_per_cu <= 0) waves_per_cu = kDefaultWavesPerCU;
+    return std::max(1, device_cu_count() * waves_per_cu / (kBlock / kWave));
+}
+
+static bool persistent_ok(const Split& sp) { return sp.k + sp.m > 0 && sp.r >= 3 && sp.n_heads >= (uint64_t)kWave; }
+
+// ------------------------------------------------------------------ tuned plans
+// Plans chosen by kl_autotune, keyed by (depth, precision): the split
+// decides the arithmetic of every word, so kl_eval and every render of one
+// depth and precision share it.  KL_AUTOTUNE_CACHE names a text file of
+// "depth precision tail_len lane_len waves_per_cu hist_mode ms" lines that
+// is read at the first lookup and appended to by kl_autotune.
+struct Tuned {
+    int depth, precision, r, m, wpc, hist;
+    double ms;
+};
+static std::mutex g_tune_mutex;
+static std::vector<Tuned> g_tuned;
+static bool g_tune_loaded = false;
+
+static void load_tuned_locked() {
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char* path = getenv("KL_AUTOTUNE_CACHE");
+    if (!path || !*path) return;
+    FILE* f = fopen(path, "r");
+    if (!f) return;
+    char line[256];
+    while (fgets(line, sizeof line, f)) {
+        Tuned t;
+        if (sscanf(line, "%d %d %d %d %d %d %lf", &t.depth, &t.precision, &t.r, &t.m, &t.wpc, &t.hist, &t.ms) == 7 &&
+            t.depth >= 1 && t.depth <= KL_MAX_DEPTH && t.r >= 1 && t.r <= kMaxTail && t.r < t.depth && t.m >= 0 &&
+            t.m <= kMaxLane && t.wpc >= 0 && t.wpc <= 32) {
+            auto it = std::find_if(g_tuned.begin(), g_tuned.end(),
+                                   [&](const Tuned& x) { return x.depth == t.depth && x.precision == t.precision; });
+            if (it != g_tuned.end()) *it = t;
+            else g_tuned.push_back(t);
+        }
+    }
+    fclose(f);
+}
+
+static bool find_tuned(int depth, int precision, Tuned* out) {
+    std::lock_guard<std::mutex> lk(g_tune_mutex);
+    load_tuned_locked();
+    for (const Tuned& t : g_tuned)
+        if (t.depth == depth && t.precision == precision) {
+            *out = t;
+            return true;
+        }
+    return false;
+}
+
+static void store_tuned(const Tuned& t) {
+    std::lock_guard<std::mutex> lk(g_tune_mutex);
+    load_tuned_locked();
+    auto it = std::find_if(g_tuned.begin(), g_tuned.end(),
+                           [&](const Tuned& x) { return x.depth == t.depth && x.precision == t.precision; });
+    if (it != g_tuned.end()) *it = t;
+    else g_tuned.push_back(t);
+    const char* path = getenv("KL_AUTOTUNE_CACHE");
+    if (path && *path) {
+        FILE* f = fopen(path, "a");
+        if (f) {
+            fprintf(f, "%d %d %d %d %d %d %.6f\n", t.depth, t.precision, t.r, t.m, t.wpc, t.hist, t.ms);
+            fclose(f);
+        }
+    }
+}
+
+// Options with the tuned plan filled in where the caller left the planner's choice.
+static kl_opts apply_tuned(const kl_opts& o, int depth, const kl_window* w) {
+    (void)w;
+    kl_opts r = o;
+    Tuned t;
+    if (o.tail_len == 0 && o.lane_len == 0 && find_tuned(depth, o.precision, &t)) {
+        r.tail_len = t.r;
+        r.lane_len = t.m;
+        if (r.waves_per_cu == 0) r.waves_per_cu = t.wpc;
+        if (r.hist_mode == KL_HIST_AUTO) r.hist_mode = t.hist;
+    }
+    return r;
+}
+
+// Render the words [lo, hi) of one depth.
+static int render_depth(const Gens& G, const Fold& f, int depth, uint64_t lo, uint64_t hi, const kl_opts& o_in,
+                        const kl_window* w, uint32_t* image, uint64_t* dropped, hipStream_t s) {
+    if (lo >= hi) return KL_OK;
+    const kl_opts o = apply_tuned(o_in, depth, w);
+    Split sp;
+    int rc = plan_split(depth, o.precision, o.tail_len, o.lane_len, &sp);
+    if (rc) return rc;
+    Temp tmp(s);
+    SetTables st;
+    if ((rc = build_tables(G, sp, o.precision, o.suffix_form, tmp, &st))) return rc;
+    RenderJob job{};
+    job.sp = sp;
+    job.precision = o.precision;
+    job.gens = G;
+    job.fold = f;
+    job.tab = st.tab;
+    job.tail_homog = st.tail_homog;
+    job.image = image;
+    job.width = w->width;
+    job.height = w->height;
+    job.dropped = dropped;
+    job.hist_mode = o.hist_mode;
+    job.grid_blocks = grid_for(o.waves_per_cu);
+    uint64_t rag_lo = lo, rag_hi = hi;  // default: every word by the per-word kernel
+    if (persistent_ok(sp)) {
+        // whole heads inside [lo, hi), in units of 64 heads, go to the persistent kernel
+        const uint64_t hb = (lo + sp.R - 1) / sp.R, he = hi / sp.R;
+        const uint64_t units = he > hb ? (he - hb) / kWave : 0;
+        if (units > 0) {
+            for (uint64_t done = 0; done < units;) {
+                const uint64_t chunk = std::min<uint64_t>(units - done, 1ull << 30);
+                RenderJob part = job;
+                part.head_begin = hb + done * kWave;
+                part.n_units = (uint32_t)chunk;
+                hipError_t e = launch_render(part, s);
+                if (e != hipSuccess) return hip_fail(e, "render kernel");
+                done += chunk;
+            }
+            const uint64_t h_end = hb + units * kWave;
+            rag_hi = hb * sp.R;
+            job.rag_first[1] = h_end * sp.R;
+            job.rag_count[1] = hi - h_end * sp.R;
+        }
+    }
+    job.n_units = 0;
+    job.rag_first[0] = rag_lo;
+    job.rag_count[0] = rag_hi - rag_lo;
+    if (job.rag_count[0] + job.rag_count[1] > 0) {
+        hipError_t e = launch_render(job, s);
+        if (e != hipSuccess) return hip_fail(e, "per-word kernel");
+    }
+    return KL_OK;
+}
+
+static int check_opts_common(const kl_opts& o) {
+    if (o.precision != KL_PREC_FP32 && o.precision != KL_PREC_FP64)
+        return fail(KL_EINVAL, "precision %d is neither KL_PREC_FP32 nor KL_PREC_FP64", o.precision);
+    if (o.tail_len < 0 || o.tail_len > kMaxTail) return fail(KL_EINVAL, "tail_len %d outside 0..8", o.tail_len);
+    if (o.lane_len < 0 || o.lane_len > kMaxLane) return fail(KL_EINVAL, "lane_len %d outside 0..20", o.lane_len);
+    if (o.hist_mode < KL_HIST_AUTO || o.hist_mode > KL_HIST_LDS) return fail(KL_EINVAL, "hist_mode %d", o.hist_mode);
+    if (o.waves_per_cu < 0 || o.waves_per_cu > 32) return fail(KL_EINVAL, "waves_per_cu %d outside 0..32", o.waves_per_cu);
+    return KL_OK;
+}
+
+// The tail_len / lane_len overrides apply to the depths that can take them;
+// shallower depths of a tiling render use the planner.
+static kl_opts opts_for_depth(const kl_opts& o, int d) {
+    kl_opts od = o;
+    if (od.tail_len >= d || (od.lane_len > 0 && od.lane_len > d - (od.tail_len ? od.tail_len : 1) - 1)) {
+        od.tail_len = 0;
+        od.lane_len = 0;
+    }
+    return od;
+}
+
+static kl_opts default_opts() {
+    kl_opts o;
+    memset(&o, 0, sizeof o);
+    return o;
+}
+
+}  // namespace kl
+
+using namespace kl;
+
+// ====================================================================== C ABI
+extern "C" {
+
+uint64_t kl_num_words(int depth) { return num_words(depth); }
+
+const char* kl_strerror(int code) {
+    switch (code) {
+        case KL_OK: return "success";
+        case KL_EINVAL: return "invalid argument";
+        case KL_ERANGE: return "index range beyond the words of the requested depth";
+        case KL_ESINGULAR: return "singular parameters: generators or seeds undefined";
+        case KL_EDEVICE: return "HIP device error";
+        case KL_ENOMEM: return "out of device memory";
+        default: return "unknown error";
+    }
+}
+
+const char* kl_last_error(void) { return g_last_error.c_str(); }
+
+int kl_generators(kl_c64 ta, kl_c64 tb, kl_c64* tab_out, kl_c64* gens_out, kl_c64* fix_out) {
+    Gens G;
+    cd tab;
+    int rc = make_gens(ta, tb, &G, &tab);
+    if (rc) return rc;
+    if (tab_out) *tab_out = {tab.real(), tab.imag()};
+    if (gens_out)
+        for (int k = 0; k < 4; ++k) {
+            gens_out[4 * k + 0] = {G.g[k].a.re, G.g[k].a.im};
+            gens_out[4 * k + 1] = {G.g[k].b.re, G.g[k].b.im};
+            gens_out[4 * k + 2] = {G.g[k].c.re, G.g[k].c.im};
+            gens_out[4 * k + 3] = {G.g[k].d.re, G.g[k].d.im};
+        }
+    if (fix_out)
+        for (int k = 0; k < 4; ++k) fix_out[k] = {G.fix[k].re, G.fix[k].im};
+    return KL_OK;
+}
+
+int kl_decode_ex(uint64_t first_idx, uint64_t count, int depth, uint8_t* letters_out, void* stream) {
+    if (depth < 1 || depth > KL_MAX_DEPTH) return fail(KL_EINVAL, "depth %d outside 1..40", depth);
+    if (count == 0) return KL_OK;
+    if (!letters_out) return fail(KL_EINVAL, "letters_out is NULL");
+    const uint64_t n = num_words(depth);
+    if (first_idx > n || count > n - first_idx)
+        return fail(KL_ERANGE, "indices [%llu, %llu + %llu) exceed the %llu words of depth %d",
+                    (unsigned long long)first_idx, (unsigned long long)first_idx, (unsigned long long)count,
+                    (unsigned long long)n, depth);
+    hipError_t e = launch_decode(first_idx, count, depth, letters_out, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "decode kernel");
+    return KL_OK;
+}
+
+int kl_decode(uint64_t first_idx, uint64_t count, int depth, uint8_t* letters_out) {
+    int rc = kl_decode_ex(first_idx, count, depth, letters_out, nullptr);
+    if (rc || count == 0) return rc;
+    hipError_t e = hipStreamSynchronize(nullptr);
+    return e == hipSuccess ? KL_OK : hip_fail(e, "decode");
+}
+
+int kl_plan(int depth, int precision, const kl_window* window, const kl_opts* opts, kl_plan_t* plan_out) {
+    (void)window;
+    if (depth < 1 || depth > KL_MAX_DEPTH) return fail(KL_EINVAL, "depth %d outside 1..40", depth);
+    if (!plan_out) return fail(KL_EINVAL, "plan_out is NULL");
+    kl_opts o = opts ? *opts : default_opts();
+    o.precision = precision;
+    int rc = check_opts_common(o);
+    if (rc) return rc;
+    o = apply_tuned(o, depth, window);
+    Split sp;
+    if ((rc = plan_split(depth, precision, o.tail_len, o.lane_len, &sp))) return rc;
+    plan_out->depth = depth;
+    plan_out->tail_len = sp.r;
+    plan_out->lane_len = sp.m;
+    plan_out->prefix_len = sp.k;
+    plan_out->hist_mode = o.hist_mode ? o.hist_mode : KL_HIST_RUNS;
+    (void)window;
+    plan_out->waves_per_cu = o.waves_per_cu ? o.waves_per_cu : kDefaultWavesPerCU;
+    return KL_OK;
+}
+
+int kl_render_ex(kl_c64 ta, kl_c64 tb, int depth, const kl_window* window, uint32_t* image_out,
+                 const kl_opts* opts) {
+    kl_opts o = opts ? *opts : default_opts();
+    if (depth < 1 || depth > KL_MAX_DEPTH) return fail(KL_EINVAL, "depth %d outside 1..40", depth);
+    int rc = check_window(window);
+    if (rc) return rc;
+    if (!image_out) return fail(KL_EINVAL, "image_out is NULL");
+    if ((rc = check_opts_common(o))) return rc;
+    const int min_depth = o.min_depth == 0 ? depth : o.min_depth;
+    if (min_depth < 1 || min_depth > depth) return fail(KL_EINVAL, "min_depth %d outside 1..%d", o.min_depth, depth);
+    uint64_t total = 0;
+    for (int d = min_depth; d <= depth; ++d) {
+        const uint64_t n = num_words(d);
+        if (total > UINT64_MAX - n) return fail(KL_ERANGE, "index space of depths %d..%d exceeds 2^64", min_depth, depth);
+        total += n;
+    }
+    uint64_t first = 0, count = total;
+    if (o.use_range) {
+        first = o.first_idx;
+        count = o.count;
+        if (first > total || count > total - first)
+            return fail(KL_ERANGE, "range [%llu, +%llu) exceeds the %llu words", (unsigned long long)first,
+                        (unsigned long long)count, (unsigned long long)total);
+    }
+    // every split must be plannable before anything is enqueued
+    for (int d = min_depth; d <= depth; ++d) {
+        Split sp;
+        const kl_opts od = d == depth ? o : opts_for_depth(o, d);
+        if ((rc = plan_split(d, od.precision, od.tail_len, od.lane_len, &sp))) return rc;
+    }
+    Gens G;
+    if ((rc = make_gens(ta, tb, &G))) return rc;
+    const Fold f = make_fold(window);
+    hipStream_t s = (hipStream_t)o.stream;
+    hipError_t e;
+    const uint64_t bins = (uint64_t)window->width * window->height;
+    if (!o.accumulate) {
+        if ((e = launch_fill_u32(image_out, bins, 0, s)) != hipSuccess) return hip_fail(e, "clear image");
+        if (o.dropped_out && (e = launch_fill_u64(o.dropped_out, 1, 0, s)) != hipSuccess)
+            return hip_fail(e, "clear dropped");
+    }
+    uint64_t offset = 0;
+    const uint64_t end = first + count;
+    for (int d = min_depth; d <= depth; ++d) {
+        const uint64_t n = num_words(d);
+        const uint64_t lo = first > offset ? first - offset : 0;
+        const uint64_t hi = end - offset < n ? end - offset : n;
+        if (end > offset && first < offset + n && lo < hi) {
+            const kl_opts od = d == depth ? o : opts_for_depth(o, d);
+            if ((rc = render_depth(G, f, d, lo, hi, od, window, image_out, o.dropped_out, s))) return rc;
+        }
+        offset += n;
+    }
+    return KL_OK;
+}
+
+int kl_render(kl_c64 ta, kl_c64 tb, int depth, const kl_window* window, uint32_t* image_out) {
+    int rc = kl_render_ex(ta, tb, depth, window, image_out, nullptr);
+    if (rc) return rc;
+    hipError_t e = hipStreamSynchronize(nullptr);
+    return e == hipSuccess ? KL_OK : hip_fail(e, "render");
+}
+
+int kl_eval_ex(kl_c64 ta, kl_c64 tb, int depth, const uint64_t* idx, uint64_t n, const kl_window* window,
+               kl_c64* z_out, const kl_opts* opts) {
+    kl_opts o = opts ? *opts : default_opts();
+    if (depth >= 1 && depth <= KL_MAX_DEPTH) o = apply_tuned(o, depth, window);
+    if (depth < 1 || depth > KL_MAX_DEPTH) return fail(KL_EINVAL, "depth %d outside 1..40", depth);
+    int rc = check_opts_common(o);
+    if (rc) return rc;
+    if (window && (rc = check_window(window))) return rc;
+    if (n == 0) return KL_OK;
+    if (!idx || !z_out) return fail(KL_EINVAL, "idx and z_out must not be NULL");
+    Split sp;
+    if ((rc = plan_split(depth, o.precision, o.tail_len, o.lane_len, &sp))) return rc;
+    Gens G;
+    if ((rc = make_gens(ta, tb, &G))) return rc;
+    hipStream_t s = (hipStream_t)o.stream;
+    Temp tmp(s);
+    SetTables st;
+    if ((rc = build_tables(G, sp, o.precision, o.suffix_form, tmp, &st))) return rc;
+    EvalJob job{};
+    job.sp = sp;
+    job.precision = o.precision;
+    job.gens = G;
+    job.fold = make_fold(window);
+    job.tab = st.tab;
+    job.tail_homog = st.tail_homog;
+    job.idx = idx;
+    job.n = n;
+    job.out = (c64*)z_out;
+    hipError_t e = launch_eval(job, s);
+    if (e != hipSuccess) return hip_fail(e, "eval kernel");
+    return KL_OK;
+}
+
+int kl_eval(kl_c64 ta, kl_c64 tb, int depth, const uint64_t* idx, uint64_t n, int precision, kl_c64* z_out) {
+    kl_opts o = default_opts();
+    o.precision = precision;
+    int rc = kl_eval_ex(ta, tb, depth, idx, n, nullptr, z_out, &o);
+    if (rc) return rc;
+    hipError_t e = hipStreamSynchronize(nullptr);
+    return e == hipSuccess ? KL_OK : hip_fail(e, "eval");
+}
+
+int kl_render_many_ex(int n, const kl_c64* ta, const kl_c64* tb, const int* depth, const kl_window* window,
+                      uint32_t* images_out, const kl_opts* opts) {
+    kl_opts o = opts ? *opts : default_opts();
+    if (n <= 0) return fail(KL_EINVAL, "n = %d must be positive", n);
+    if (!ta || !tb || !depth) return fail(KL_EINVAL, "ta, tb and depth must not be NULL");
+    int rc = check_window(window);
+    if (rc) return rc;
+    if (!images_out) return fail(KL_EINVAL, "images_out is NULL");
+    if ((rc = check_opts_common(o))) return rc;
+    if (o.min_depth != 0 || o.use_range) return fail(KL_EINVAL, "min_depth and use_range must be 0 for kl_render_many");
+    const uint64_t bins = (uint64_t)window->width * window->height;
+    std::vector<Gens> gens(n);
+    std::vector<Split> splits(n);
+    std::vector<kl_opts> per(n);
+    for (int i = 0; i < n; ++i) {
+        if (depth[i] < 1 || depth[i] > KL_MAX_DEPTH) return fail(KL_EINVAL, "set %d: depth %d outside 1..40", i, depth[i]);
+        per[i] = apply_tuned(opts_for_depth(o, depth[i]), depth[i], window);
+        if ((rc = plan_split(depth[i], o.precision, per[i].tail_len, per[i].lane_len, &splits[i], 8))) {
+            std::string m = g_last_error;
+            return fail(rc, "set %d: %s", i, m.c_str());
+        }
+        if ((rc = make_gens(ta[i], tb[i], &gens[i]))) {
+            std::string m = g_last_error;
+            return fail(rc, "set %d: %s", i, m.c_str());
+        }
+    }
+    const Fold f = make_fold(window);
+    hipStream_t s = (hipStream_t)o.stream;
+    hipError_t e;
+    if (!o.accumulate) {
+        if ((e = launch_fill_u32(images_out, bins * (uint64_t)n, 0, s)) != hipSuccess) return hip_fail(e, "clear images");
+        if (o.dropped_out && (e = launch_fill_u64(o.dropped_out, (uint64_t)n, 0, s)) != hipSuccess)
+            return hip_fail(e, "clear dropped");
+    }
+    // persistent sets share one launch; the rest (shallow depths) render one by one
+    std::vector<int> batch;
+    for (int i = 0; i < n; ++i)
+        if (persistent_ok(splits[i])) batch.push_back(i);
+        else if ((rc = render_depth(gens[i], f, depth[i], 0, num_words(depth[i]), per[i], window, images_out + bins * i,
+                                    o.dropped_out ? o.dropped_out + i : nullptr, s)))
+            return rc;
+    if (batch.empty()) return KL_OK;
+    const int nb = (int)batch.size();
+    const size_t esz = o.precision == KL_PREC_FP64 ? sizeof(c64) : sizeof(c32);
+    uint64_t n_prefix = 0, n_tail = 0;
+    uint32_t max_prefix = 0, max_tail = 0;
+    for (int i : batch) {
+        const uint32_t np = splits[i].k ? (uint32_t)num_words(splits[i].k) : 0;
+        const uint32_t nt = (uint32_t)num_words(splits[i].r);
+        n_prefix += np;
+        n_tail += nt;
+        max_prefix = std::max(max_prefix, np);
+        max_tail = std::max(max_tail, nt);
+    }
+    Temp tmp(s);
+    SetDesc* d_sets = nullptr;
+    uint64_t* d_off = nullptr;
+    m64* d_prefix = nullptr;
+    uint8_t* d_last = nullptr;
+    unsigned char *d_aff = nullptr, *d_hom = nullptr;
+    uint32_t* d_flags = nullptr;
+    if ((e = tmp.alloc((void**)&d_sets, nb * sizeof(SetDesc))) != hipSuccess ||
+        (e = tmp.alloc((void**)&d_off, (nb + 1) * sizeof(uint64_t))) != hipSuccess ||
+        (e = tmp.alloc((void**)&d_prefix, n_prefix * sizeof(m64))) != hipSuccess ||
+        (e = tmp.alloc((void**)&d_last, n_prefix + 16)) != hipSuccess ||
+        (e = tmp.alloc((void**)&d_aff, n_tail * esz + 16 * nb)) != hipSuccess ||
+        (e = tmp.alloc((void**)&d_hom, 2 * n_tail * esz + 16 * nb)) != hipSuccess ||
+        (e = tmp.alloc((void**)&d_flags, nb * sizeof(uint32_t))) != hipSuccess)
+        return hip_fail(e, "batch temporaries");
+    std::vector<SetDesc> h_sets(nb);
+    std::vector<uint64_t> h_off(nb + 1);
+    uint64_t po = 0, to_aff = 0, to_hom = 0, units = 0;
+    uint32_t max_bytes = 0;
+    for (int j = 0; j < nb; ++j) {
+        const int i = batch[j];
+        SetDesc& D = h_sets[j];
+        memset(&D, 0, sizeof D);
+        D.gens = gens[i];
+        D.sp = splits[i];
+        D.n_prefix = splits[i].k ? (uint32_t)num_words(splits[i].k) : 0;
+        D.n_tail = (uint32_t)num_words(splits[i].r);
+        D.tab.prefix = d_prefix + po;
+        D.tab.prefix_last = d_last + po;
+        D.tab.tail = d_aff + to_aff;
+        D.tail_homog = d_hom + to_hom;
+        D.tab.tail_flags = d_flags + j;
+        D.image = images_out + bins * i;
+        D.dropped = o.dropped_out ? o.dropped_out + i : nullptr;
+        po += D.n_prefix;
+        to_aff += ((D.n_tail * esz + 15) / 16) * 16;
+        to_hom += ((2 * D.n_tail * esz + 15) / 16) * 16;
+        max_bytes = std::max<uint32_t>(max_bytes, (uint32_t)(((2 * D.n_tail * esz + 15) / 16) * 16));
+        h_off[j] = units;
+        units += (splits[i].n_heads + kWave - 1) / kWave;
+    }
+    h_off[nb] = units;
+    if ((e = hipMemcpyAsync(d_sets, h_sets.data(), nb * sizeof(SetDesc), hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(d_off, h_off.data(), (nb + 1) * sizeof(uint64_t), hipMemcpyHostToDevice, s)) != hipSuccess)
+        return hip_fail(e, "batch descriptors");
+    if ((e = launch_fill_u32(d_flags, nb, 0, s)) != hipSuccess) return hip_fail(e, "fill");
+    BatchJob job{};
+    job.sets = d_sets;
+    job.unit_offsets = d_off;
+    job.n_sets = nb;
+    job.total_units = units;
+    job.precision = o.precision;
+    job.fold = f;
+    job.width = window->width;
+    job.height = window->height;
+    job.grid_blocks = grid_for(o.waves_per_cu ? o.waves_per_cu : per[batch[0]].waves_per_cu);
+    job.lds_per_wave = max_bytes + 4 * sizeof(m64);
+    job.max_prefix = max_prefix;
+    job.max_tail = max_tail;
+    job.force_homog = o.suffix_form;
+    if ((e = launch_batch_tables(job, s)) != hipSuccess) return hip_fail(e, "batch tables");
+    if ((e = launch_render_batch(job, s)) != hipSuccess) return hip_fail(e, "batch render");
+    // the descriptors live in host vectors: finish the copies before they go
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "batch");
+    return KL_OK;
+}
+
+int kl_render_many(int n, const kl_c64* ta, const kl_c64* tb, const int* depth, const kl_window* window,
+                   uint32_t* images_out) {
+    int rc = kl_render_many_ex(n, ta, tb, depth, window, images_out, nullptr);
+    if (rc) return rc;
+    hipError_t e = hipStreamSynchronize(nullptr);
+    return e == hipSuccess ? KL_OK : hip_fail(e, "render_many");
+}
+
+int kl_autotune(kl_c64 ta, kl_c64 tb, int depth, const kl_window* window, int precision, uint32_t* scratch_image,
+                kl_plan_t* best_out, double* best_ms_out) {
+    if (depth < 2 || depth > KL_MAX_DEPTH) return fail(KL_EINVAL, "depth %d outside 2..40", depth);
+    int rc = check_window(window);
+    if (rc) return rc;
+    if (!scratch_image) return fail(KL_EINVAL, "scratch_image is NULL");
+    if (precision != KL_PREC_FP32 && precision != KL_PREC_FP64) return fail(KL_EINVAL, "precision %d", precision);
+    Gens G;
+    if ((rc = make_gens(ta, tb, &G))) return rc;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return fail(KL_EDEVICE, "hipEventCreate failed");
+    Tuned best{depth, precision, 0, 0, 0, KL_HIST_RUNS, 1e300};
+    const int wpcs[] = {8, 16, 24, 32};
+    for (int r = 3; r <= std::min(kMaxTail - 1, depth - 1); ++r) {
+        for (int m = 1; m <= std::min(6, depth - r - 1); ++m) {
+            if (depth - r - m > kMaxPrefix) continue;
+            for (int wpc : wpcs) {
+                kl_opts o = default_opts();
+                o.precision = precision;
+                o.tail_len = r;
+                o.lane_len = m;
+                o.waves_per_cu = wpc;
+                o.hist_mode = KL_HIST_RUNS;
+                std::vector<float> times;
+                for (int rep = 0; rep < 4; ++rep) {
+                    (void)hipEventRecord(e0, nullptr);
+                    rc = kl_render_ex(ta, tb, depth, window, scratch_image, &o);
+                    (void)hipEventRecord(e1, nullptr);
+                    if (rc) break;
+                    if (hipEventSynchronize(e1) != hipSuccess) {
+                        rc = fail(KL_EDEVICE, "autotune timing failed");
+                        break;
+                    }
+                    float ms = 0;
+                    (void)hipEventElapsedTime(&ms, e0, e1);
+                    if (rep) times.push_back(ms);
+                }
+                if (rc) {
+                    (void)hipEventDestroy(e0);
+                    (void)hipEventDestroy(e1);
+                    return rc;
+                }
+                std::sort(times.begin(), times.end());
+                const double med = times[times.size() / 2];
+                if (med < best.ms) best = Tuned{depth, precision, r, m, wpc, KL_HIST_RUNS, med};
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (best.r == 0) return fail(KL_EINVAL, "no candidate plan for depth %d", depth);
+    store_tuned(best);
+    if (best_out) {
+        best_out->depth = depth;
+        best_out->tail_len = best.r;
+        best_out->lane_len = best.m;
+        best_out->prefix_len = depth - best.r - best.m;
+        best_out->hist_mode = best.hist;
+        best_out->waves_per_cu = best.wpc;
+    }
+    if (best_ms_out) *best_ms_out = best.ms;
+    return KL_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,162 @@
+// kl_internal.hpp -- shared declarations of libkl (host planner, launchers,
+// device arithmetic).  Every floating-point step of a word value is written
+// with explicit fma / mul / add and the library is built with
+// -ffp-contract=off, so the persistent renderer, the per-word kernel and
+// kl_eval produce bit-identical values for the same word and split.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "kl.h"
+
+namespace kl {
+
+constexpr int kMaxTail = 8;         // LDS suffix tables hold 4*3^(r-1) <= 8748 entries
+constexpr int kMaxLane = 20;        // letters a lane appends to its prefix (3^20 < 2^32)
+constexpr int kMaxPrefix = 14;      // prefix table depth (4*3^13 entries of 64 B at most)
+constexpr int kWave = 64;
+constexpr int kBlock = 256;         // threads per workgroup of the renderer
+constexpr double kAffineLimit = 4294967296.0;  // |tail point| above this -> homogeneous form
+
+// ---------------------------------------------------------------- complex
+template <typename T>
+struct cpx {
+    T re, im;
+};
+using c32 = cpx<float>;
+using c64 = cpx<double>;
+
+template <typename T>
+struct mat {  // [[a, b], [c, d]]
+    cpx<T> a, b, c, d;
+};
+using m64 = mat<double>;
+using m32 = mat<float>;
+
+__host__ __device__ inline double fma_(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__host__ __device__ inline float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
+// x * y (complex), fixed operation order
+template <typename T>
+__host__ __device__ inline cpx<T> cmul(cpx<T> x, cpx<T> y) {
+    return {fma_(x.re, y.re, -(x.im * y.im)), fma_(x.re, y.im, x.im * y.re)};
+}
+// x * y + z (complex), fixed operation order
+template <typename T>
+__host__ __device__ inline cpx<T> cfma(cpx<T> x, cpx<T> y, cpx<T> z) {
+    return {fma_(x.re, y.re, fma_(-x.im, y.im, z.re)), fma_(x.re, y.im, fma_(x.im, y.re, z.im))};
+}
+
+template <typename T>
+__host__ __device__ inline mat<T> mmul(const mat<T>& x, const mat<T>& y) {
+    return {cfma(x.a, y.a, cmul(x.b, y.c)), cfma(x.a, y.b, cmul(x.b, y.d)),
+            cfma(x.c, y.a, cmul(x.d, y.c)), cfma(x.c, y.b, cmul(x.d, y.d))};
+}
+
+// ---------------------------------------------------------------- launch args
+struct Gens {
+    m64 g[4];        // a, b, A, B  (FP64)
+    c64 fix[4];      // attracting fixed points (FP64)
+};
+
+// Affine map folded into the head so the word value comes out in pixel
+// coordinates: pixel = s * z + o (with aniso applied to the real part).
+struct Fold {
+    double s;        // bins per unit along y
+    c64 o;           // -(x0, y0) * s
+    double aniso;    // (bins per unit along x) / s
+    int use_aniso;
+};
+
+struct Split {
+    int depth, r, m, k;        // depth = k + m + r (k = 0 only when m = 0 and r = depth)
+    uint32_t pow3_m;           // 3^m
+    uint32_t R1;               // 3^(r-1): suffixes per first suffix letter
+    uint64_t R;                // 3^r: suffixes after a given letter
+    uint64_t n_heads;          // 4*3^(k+m-1) (1 when k+m = 0)
+};
+
+struct Tables {                // device pointers of one parameter set
+    const m64* prefix;         // N_k prefix products (k >= 1)
+    const uint8_t* prefix_last;// last letter of each prefix
+    const void* tail;          // N_r suffix points: affine (T) or homogeneous (2 T)
+    const uint32_t* tail_flags;// bit 0: some suffix point needs the homogeneous form
+};
+
+// Host-side planning and validation helpers (abi.cpp)
+int plan_split(int depth, int precision, int r_req, int m_req, Split* out, int prefix_cap = 10);
+uint64_t num_words(int depth);
+uint64_t pow3_u64(int n);
+
+// Launchers (kernels.hip).  All enqueue on `stream` and return a hipError_t.
+hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s);
+hipError_t launch_fill_u64(uint64_t* p, uint64_t n, uint64_t v, hipStream_t s);
+hipError_t launch_decode(uint64_t first, uint64_t count, int depth, uint8_t* out, hipStream_t s);
+hipError_t launch_prefix_table(const Gens& g, int k, m64* prefix, uint8_t* last, hipStream_t s);
+hipError_t launch_tail_table(const Gens& g, int r, int precision, void* tail_affine,
+                             void* tail_homog, uint32_t* flags, hipStream_t s);
+
+struct RenderJob {
+    Split sp;
+    int precision;
+    Gens gens;
+    Fold fold;
+    Tables tab;
+    const void* tail_homog;
+    uint32_t* image;
+    uint32_t width, height;
+    uint64_t* dropped;         // device u64 (may be null)
+    // persistent kernel: heads [head_begin, head_begin + 64 n_units)
+    uint64_t head_begin;
+    uint32_t n_units;
+    // per-word kernel: word indices (within this depth) of the ragged ends
+    uint64_t rag_first[2], rag_count[2];
+    int hist_mode;
+    int grid_blocks;
+};
+hipError_t launch_render(const RenderJob& job, hipStream_t s);
+
+struct EvalJob {
+    Split sp;
+    int precision;
+    Gens gens;
+    Fold fold;
+    Tables tab;
+    const void* tail_homog;
+    const uint64_t* idx;
+    uint64_t n;
+    c64* out;
+};
+hipError_t launch_eval(const EvalJob& job, hipStream_t s);
+
+// Batched renderer: one descriptor per parameter set (device array).
+struct SetDesc {
+    Gens gens;
+    Split sp;
+    Tables tab;
+    const void* tail_homog;
+    uint32_t* image;
+    uint64_t* dropped;         // device u64 of this set (may be null)
+    uint32_t n_prefix;         // 4*3^(k-1)
+    uint32_t n_tail;           // 4*3^(r-1)
+};
+struct BatchJob {
+    const SetDesc* sets;           // device, n_sets entries
+    const uint64_t* unit_offsets;  // device, n_sets + 1 prefix sums of units (64 heads each)
+    int n_sets;
+    uint64_t total_units;
+    int precision;
+    Fold fold;
+    uint32_t width, height;
+    int grid_blocks;
+    uint32_t lds_per_wave;         // bytes of LDS each wave holds its set's suffix table in
+    uint32_t max_prefix, max_tail; // largest n_prefix / n_tail over the sets
+    int force_homog;
+};
+hipError_t launch_batch_tables(const BatchJob& job, hipStream_t s);
+hipError_t launch_render_batch(const BatchJob& job, hipStream_t s);
+
+int device_cu_count();
+
+}  // namespace kl

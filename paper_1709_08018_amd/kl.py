@@ -1,0 +1,248 @@
+"""Python binding of libkl (``include/kl.h``).
+
+Argument marshalling only: every step of a render runs in the HIP library.
+PyTorch supplies device buffers and the current stream; the library never
+sees a torch type.  Importing this module loads ``libkl.so``; a missing or
+unloadable library raises ``KLError`` (there is no fallback path).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import torch  # loads the HIP runtime that libkl shares
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libkl.so")
+HEADER = os.path.join(os.path.dirname(PKG), "include", "kl.h")
+
+KL_OK, KL_EINVAL, KL_ERANGE, KL_ESINGULAR, KL_EDEVICE, KL_ENOMEM = 0, -1, -2, -3, -4, -5
+PREC = {"fp32": 0, "fp64": 1}
+HIST = {"auto": 0, "runs": 1, "lds": 2}
+
+
+class KLError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libkl error {code}: {msg}")
+        self.code = code
+
+
+class c64(ctypes.Structure):
+    _fields_ = [("re", ctypes.c_double), ("im", ctypes.c_double)]
+
+
+class Window(ctypes.Structure):
+    _fields_ = [("x0", ctypes.c_double), ("x1", ctypes.c_double), ("y0", ctypes.c_double),
+                ("y1", ctypes.c_double), ("width", ctypes.c_uint32), ("height", ctypes.c_uint32)]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("min_depth", ctypes.c_int), ("precision", ctypes.c_int), ("use_range", ctypes.c_int),
+                ("first_idx", ctypes.c_uint64), ("count", ctypes.c_uint64), ("accumulate", ctypes.c_int),
+                ("stream", ctypes.c_void_p), ("dropped_out", ctypes.c_void_p), ("tail_len", ctypes.c_int),
+                ("lane_len", ctypes.c_int), ("hist_mode", ctypes.c_int), ("waves_per_cu", ctypes.c_int),
+                ("suffix_form", ctypes.c_int)]
+
+
+class Plan(ctypes.Structure):
+    _fields_ = [("depth", ctypes.c_int), ("tail_len", ctypes.c_int), ("lane_len", ctypes.c_int),
+                ("prefix_len", ctypes.c_int), ("hist_mode", ctypes.c_int), ("waves_per_cu", ctypes.c_int)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            from . import build
+            build.build()
+        try:
+            L = ctypes.CDLL(LIB_PATH)
+        except OSError as e:
+            raise KLError(KL_EDEVICE, f"cannot load {LIB_PATH}: {e}") from e
+        vp, u64, i = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int
+        W = ctypes.POINTER(Window)
+        O = ctypes.POINTER(Opts)
+        C = ctypes.POINTER(c64)
+        L.kl_num_words.argtypes = [i]
+        L.kl_num_words.restype = u64
+        L.kl_decode.argtypes = [u64, u64, i, vp]
+        L.kl_decode_ex.argtypes = [u64, u64, i, vp, vp]
+        L.kl_render.argtypes = [c64, c64, i, W, vp]
+        L.kl_render_ex.argtypes = [c64, c64, i, W, vp, O]
+        L.kl_render_many.argtypes = [i, C, C, ctypes.POINTER(i), W, vp]
+        L.kl_render_many_ex.argtypes = [i, C, C, ctypes.POINTER(i), W, vp, O]
+        L.kl_eval.argtypes = [c64, c64, i, vp, u64, i, vp]
+        L.kl_eval_ex.argtypes = [c64, c64, i, vp, u64, W, vp, O]
+        L.kl_generators.argtypes = [c64, c64, C, C, C]
+        L.kl_plan.argtypes = [i, i, W, O, ctypes.POINTER(Plan)]
+        L.kl_autotune.argtypes = [c64, c64, i, W, i, vp, ctypes.POINTER(Plan), ctypes.POINTER(ctypes.c_double)]
+        L.kl_strerror.argtypes = [i]
+        L.kl_strerror.restype = ctypes.c_char_p
+        L.kl_last_error.argtypes = []
+        L.kl_last_error.restype = ctypes.c_char_p
+        for f in ("kl_decode", "kl_decode_ex", "kl_render", "kl_render_ex", "kl_render_many",
+                  "kl_render_many_ex", "kl_eval", "kl_eval_ex", "kl_generators", "kl_plan", "kl_autotune"):
+            getattr(L, f).restype = i
+        _lib = L
+    return _lib
+
+
+def declared_symbols():
+    """Names of the functions include/kl.h declares."""
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(kl_\w+)\s*\(", text)))
+
+
+def _check(rc):
+    if rc != KL_OK:
+        msg = lib().kl_last_error().decode(errors="replace")
+        raise KLError(rc, f"{lib().kl_strerror(rc).decode()}: {msg}")
+
+
+def _c(z) -> c64:
+    z = complex(z)
+    return c64(z.real, z.imag)
+
+
+def make_window(window) -> Window:
+    if isinstance(window, Window):
+        return window
+    if hasattr(window, "as_tuple"):
+        window = window.as_tuple()
+    x0, x1, y0, y1, w, h = window
+    return Window(float(x0), float(x1), float(y0), float(y1), int(w), int(h))
+
+
+def _stream(stream):
+    if stream is None:
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, torch.cuda.Stream):
+        return ctypes.c_void_p(stream.cuda_stream)
+    return ctypes.c_void_p(stream)
+
+
+def make_opts(*, min_depth=0, precision="fp32", first=None, count=None, accumulate=False, stream=None,
+              dropped=None, tail_len=0, lane_len=0, hist_mode="auto", waves_per_cu=0, suffix_form=0,
+              use_stream=True) -> Opts:
+    o = Opts()
+    o.min_depth = int(min_depth)
+    o.precision = PREC[precision] if isinstance(precision, str) else int(precision)
+    if first is not None or count is not None:
+        o.use_range = 1
+        o.first_idx = int(first or 0)
+        o.count = int(count)
+    o.accumulate = int(bool(accumulate))
+    o.stream = _stream(stream).value if use_stream else None
+    o.dropped_out = None if dropped is None else dropped.data_ptr()
+    o.tail_len = int(tail_len)
+    o.lane_len = int(lane_len)
+    o.hist_mode = HIST[hist_mode] if isinstance(hist_mode, str) else int(hist_mode)
+    o.waves_per_cu = int(waves_per_cu)
+    o.suffix_form = int(suffix_form)
+    return o
+
+
+def num_words(depth: int) -> int:
+    return int(lib().kl_num_words(depth))
+
+
+def generators(ta, tb):
+    """Host-side trace recipe: (tab, gens[4, 2, 2] complex, fix[4] complex)."""
+    tab = c64()
+    gens = (c64 * 16)()
+    fix = (c64 * 4)()
+    _check(lib().kl_generators(_c(ta), _c(tb), ctypes.byref(tab), gens, fix))
+    g = np.array([complex(x.re, x.im) for x in gens]).reshape(4, 2, 2)
+    f = np.array([complex(x.re, x.im) for x in fix])
+    return complex(tab.re, tab.im), g, f
+
+
+def plan(depth: int, precision="fp32", window=None, **opts) -> dict:
+    p = Plan()
+    o = make_opts(precision=precision, use_stream=False, **opts)
+    w = None if window is None else ctypes.byref(make_window(window))
+    _check(lib().kl_plan(depth, o.precision, w, ctypes.byref(o), ctypes.byref(p)))
+    return {k: getattr(p, k) for k, _ in Plan._fields_}
+
+
+def _device():
+    if not torch.cuda.is_available():
+        raise KLError(KL_EDEVICE, "no HIP device is visible")
+    return torch.device("cuda", torch.cuda.current_device())
+
+
+def decode(first: int, count: int, depth: int, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Letters of words first..first+count-1 of `depth`, shape (count, depth), uint8 on the GPU."""
+    if out is None:
+        out = torch.empty((count, depth), dtype=torch.uint8, device=_device())
+    _check(lib().kl_decode_ex(int(first), int(count), int(depth), out.data_ptr() if count else None,
+                              _stream(stream)))
+    return out
+
+
+def new_image(window, n: int | None = None) -> torch.Tensor:
+    w = make_window(window)
+    shape = (w.height, w.width) if n is None else (n, w.height, w.width)
+    return torch.zeros(shape, dtype=torch.int32, device=_device())
+
+
+def render(ta, tb, depth: int, window, image: torch.Tensor | None = None, **opts) -> torch.Tensor:
+    """Density image (int32 storage holding uint32 counts), shape (height, width)."""
+    w = make_window(window)
+    if image is None:
+        image = new_image(w)
+    o = make_opts(**opts)
+    _check(lib().kl_render_ex(_c(ta), _c(tb), int(depth), ctypes.byref(w), image.data_ptr(), ctypes.byref(o)))
+    return image
+
+
+def render_many(ta, tb, depths, window, images: torch.Tensor | None = None, **opts) -> torch.Tensor:
+    ta = np.asarray(ta, np.complex128).ravel()
+    tb = np.asarray(tb, np.complex128).ravel()
+    depths = np.asarray(depths, np.int32).ravel()
+    n = len(ta)
+    w = make_window(window)
+    if images is None:
+        images = new_image(w, n)
+    cta = (c64 * n)(*[c64(z.real, z.imag) for z in ta])
+    ctb = (c64 * n)(*[c64(z.real, z.imag) for z in tb])
+    cd = (ctypes.c_int * n)(*[int(d) for d in depths])
+    o = make_opts(**opts)
+    _check(lib().kl_render_many_ex(n, cta, ctb, cd, ctypes.byref(w), images.data_ptr(), ctypes.byref(o)))
+    return images
+
+
+def eval_values(ta, tb, depth: int, idx, precision="fp32", window=None, **opts) -> torch.Tensor:
+    """Values (or, with a window, renderer pixel coordinates) of the words idx: float64 (n, 2)."""
+    if not isinstance(idx, torch.Tensor):
+        idx = torch.as_tensor(np.ascontiguousarray(idx, np.uint64).view(np.int64))
+    idx = idx.to(device=_device(), dtype=torch.int64).contiguous()
+    n = idx.numel()
+    out = torch.empty((n, 2), dtype=torch.float64, device=_device())
+    o = make_opts(precision=precision, **opts)
+    w = None if window is None else ctypes.byref(make_window(window))
+    _check(lib().kl_eval_ex(_c(ta), _c(tb), int(depth), idx.data_ptr() if n else None, n, w,
+                            out.data_ptr() if n else None, ctypes.byref(o)))
+    return out
+
+
+def autotune(ta, tb, depth: int, window, precision="fp32", scratch: torch.Tensor | None = None):
+    w = make_window(window)
+    if scratch is None:
+        scratch = new_image(w)
+    p = Plan()
+    ms = ctypes.c_double(0.0)
+    _check(lib().kl_autotune(_c(ta), _c(tb), int(depth), ctypes.byref(w), PREC[precision], scratch.data_ptr(),
+                             ctypes.byref(p), ctypes.byref(ms)))
+    return {k: getattr(p, k) for k, _ in Plan._fields_}, ms.value
+
+
+def as_u32(image: torch.Tensor) -> np.ndarray:
+    """Copy an image tensor to the host as uint32 counts."""
+    return image.detach().cpu().numpy().view(np.uint32)

@@ -1,0 +1,158 @@
+"""Host-side checks of the C ABI (no GPU needed).
+
+Every call here either needs no device at all (recipe, plans, counts) or is
+rejected by argument validation before anything touches the device, so the
+fake device addresses passed below are never dereferenced.
+"""
+import ctypes
+import subprocess
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_1709_08018_amd import kl
+from paper_1709_08018_amd import workloads as wl
+
+FAKE = ctypes.c_void_p(0x1000)   # never dereferenced: every call below fails validation first
+L = kl.lib()
+
+# A call that unexpectedly passed validation would reach the device with a
+# fake address; where a device exists these host checks are not run.
+pytestmark = pytest.mark.skipif(torch.cuda.is_available(),
+                                reason="host-only checks with fake device addresses")
+
+
+def test_library_exports_every_declared_symbol():
+    declared = kl.declared_symbols()
+    assert len(declared) >= 14
+    out = subprocess.run(["nm", "-D", "--defined-only", kl.LIB_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    exported = {line.split()[-1] for line in out.splitlines() if " T " in line}
+    assert set(declared) <= exported, set(declared) - exported
+    for name in declared:
+        assert hasattr(L, name)
+
+
+def test_num_words_matches_reference():
+    for d in range(0, 42):
+        assert kl.num_words(d) == O.num_words(d)
+
+
+def _param_sets():
+    ta, tb, _ = wl.draw_param_sets(32, seed=3)
+    return [(wl.C1_TA, wl.C1_TB), (wl.C2_TA, wl.C2_TB)] + list(zip(ta, tb))
+
+
+@pytest.mark.parametrize("ta,tb", _param_sets())
+def test_generators_agree_with_reference(ta, tb):
+    tab, g, fix = kl.generators(ta, tb)
+    tab_r, g_r, fix_r = O.generators(complex(ta), complex(tb))
+    assert abs(tab - tab_r) <= 1e-14 * max(1, abs(tab_r))
+    np.testing.assert_allclose(g, g_r, rtol=1e-13, atol=1e-14)
+    np.testing.assert_allclose(fix, fix_r, rtol=1e-12, atol=1e-13)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_plans_cover_every_depth(precision):
+    for d in range(1, 41):
+        p = kl.plan(d, precision)
+        assert p["prefix_len"] + p["lane_len"] + p["tail_len"] == d
+        assert 1 <= p["tail_len"] <= 8
+        assert p["prefix_len"] <= 14 and p["lane_len"] <= 20
+        if p["tail_len"] < d:
+            assert p["prefix_len"] >= 1
+
+
+def test_plan_overrides_and_rejects():
+    p = kl.plan(18, "fp32", tail_len=6, lane_len=4)
+    assert (p["tail_len"], p["lane_len"], p["prefix_len"]) == (6, 4, 8)
+    for bad in [dict(tail_len=9), dict(tail_len=19), dict(lane_len=21), dict(tail_len=5, lane_len=13),
+                dict(waves_per_cu=33), dict(hist_mode=7)]:
+        with pytest.raises(kl.KLError) as e:
+            kl.plan(18, "fp32", **bad)
+        assert e.value.code == kl.KL_EINVAL
+    with pytest.raises(kl.KLError):
+        kl.plan(0, "fp32")
+    with pytest.raises(kl.KLError):
+        kl.plan(41, "fp32")
+
+
+def _win(x0=-1.5, x1=1.5, y0=-1.5, y1=1.5, w=64, h=64):
+    return kl.Window(x0, x1, y0, y1, w, h)
+
+
+def _render(ta=wl.C2_TA, tb=wl.C2_TB, depth=10, window=None, image=FAKE, opts=None):
+    w = ctypes.byref(window) if window is not None else None
+    o = ctypes.byref(opts) if opts is not None else None
+    return L.kl_render_ex(kl._c(ta), kl._c(tb), depth, w, image, o)
+
+
+def test_render_argument_errors():
+    good = _win()
+    assert _render(depth=0, window=good) == kl.KL_EINVAL
+    assert _render(depth=41, window=good) == kl.KL_EINVAL
+    assert _render(window=None) == kl.KL_EINVAL
+    assert _render(window=good, image=None) == kl.KL_EINVAL
+    for w in [_win(x1=-1.5), _win(y1=-2.0), _win(w=0), _win(h=0), _win(w=40000), _win(h=32769),
+              _win(x0=float("nan")), _win(y1=float("inf"))]:
+        assert _render(window=w) == kl.KL_EINVAL
+    o = kl.make_opts(precision=2, use_stream=False)
+    assert _render(window=good, opts=o) == kl.KL_EINVAL
+    o = kl.make_opts(min_depth=11, use_stream=False)
+    assert _render(window=good, opts=o) == kl.KL_EINVAL
+    n = kl.num_words(10)
+    o = kl.make_opts(first=n - 5, count=6, use_stream=False)
+    assert _render(window=good, opts=o) == kl.KL_ERANGE
+    o = kl.make_opts(first=2 ** 64 - 1, count=2, use_stream=False)
+    assert _render(window=good, opts=o) == kl.KL_ERANGE
+    # tiling index space: depths 3..10
+    total = sum(kl.num_words(d) for d in range(3, 11))
+    o = kl.make_opts(min_depth=3, first=total, count=1, use_stream=False)
+    assert _render(window=good, opts=o) == kl.KL_ERANGE
+    assert "exceeds" in L.kl_last_error().decode()
+
+
+def test_render_singular_and_nonfinite_traces():
+    good = _win()
+    assert _render(ta=0, tb=0, window=good) == kl.KL_ESINGULAR
+    assert _render(ta=complex(float("nan"), 0), window=good) == kl.KL_EINVAL
+
+
+def test_decode_and_eval_argument_errors():
+    assert L.kl_decode(0, 1, 0, FAKE) == kl.KL_EINVAL
+    assert L.kl_decode(0, 1, 41, FAKE) == kl.KL_EINVAL
+    assert L.kl_decode(0, 5, 3, None) == kl.KL_EINVAL
+    assert L.kl_decode(0, 0, 3, None) == kl.KL_OK          # empty request touches nothing
+    assert L.kl_decode(kl.num_words(3), 1, 3, FAKE) == kl.KL_ERANGE
+    assert L.kl_decode(2 ** 64 - 1, 2, 3, FAKE) == kl.KL_ERANGE
+    assert L.kl_eval(kl._c(wl.C2_TA), kl._c(wl.C2_TB), 0, FAKE, 1, 0, FAKE) == kl.KL_EINVAL
+    assert L.kl_eval(kl._c(wl.C2_TA), kl._c(wl.C2_TB), 5, None, 1, 0, FAKE) == kl.KL_EINVAL
+    assert L.kl_eval(kl._c(wl.C2_TA), kl._c(wl.C2_TB), 5, FAKE, 1, 3, FAKE) == kl.KL_EINVAL
+    assert L.kl_eval(kl._c(0), kl._c(0), 5, FAKE, 1, 0, FAKE) == kl.KL_ESINGULAR
+
+
+def test_render_many_argument_errors():
+    n = 3
+    ta = (kl.c64 * n)(*[kl._c(wl.C2_TA)] * n)
+    tb = (kl.c64 * n)(*[kl._c(wl.C2_TB)] * n)
+    good = (ctypes.c_int * n)(10, 11, 12)
+    w = _win()
+    assert L.kl_render_many(0, ta, tb, good, ctypes.byref(w), FAKE) == kl.KL_EINVAL
+    assert L.kl_render_many(n, None, tb, good, ctypes.byref(w), FAKE) == kl.KL_EINVAL
+    bad = (ctypes.c_int * n)(10, 0, 12)
+    assert L.kl_render_many(n, ta, tb, bad, ctypes.byref(w), FAKE) == kl.KL_EINVAL
+    assert "set 1" in L.kl_last_error().decode()
+    tb2 = (kl.c64 * n)(kl._c(wl.C2_TB), kl._c(wl.C2_TB), kl.c64(0, 0))
+    ta2 = (kl.c64 * n)(kl._c(wl.C2_TA), kl._c(wl.C2_TA), kl.c64(0, 0))
+    assert L.kl_render_many(n, ta2, tb2, good, ctypes.byref(w), FAKE) == kl.KL_ESINGULAR
+    assert "set 2" in L.kl_last_error().decode()
+    o = kl.make_opts(min_depth=2, use_stream=False)
+    assert L.kl_render_many_ex(n, ta, tb, good, ctypes.byref(w), FAKE, ctypes.byref(o)) == kl.KL_EINVAL
+
+
+def test_strerror_names_every_code():
+    for code in (0, -1, -2, -3, -4, -5):
+        assert L.kl_strerror(code)
+    assert L.kl_strerror(-99) == b"unknown error"
