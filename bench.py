@@ -1,0 +1,188 @@
+#!/usr/bin/env python3
+"""Benchmark of the indexed Kleinian-attractor renderer on one MI355X.
+
+Workload (one step): the limit set of the quasi-Fuchsian group with traces
+ta = 1.91 + 0.05i, tb = 2 at depth 18 -- all 4*3^17 = 516,560,652 reduced
+words, decoded from their indices, evaluated right to left from their seeds
+(FP64 prefixes, FP32 suffix maps) and binned into a 2048 x 2048 uint32 image
+over [-1.5, 1.5]^2.  A step is one kl_render_ex call: image clear, prefix
+and suffix tables, persistent renderer, per-word ragged end.
+
+Prints one JSON line: whole-job words/s (Gwords/s), the renderer kernel's
+FP32 roofline position (its average duration measured with HIP events on
+its own stream), and the CPU reference timed on this host's cores.
+
+    python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Gwords/s and VALU roofline fraction at depth 18; surrogate vs plain scan time @IoU≥0.95"
+# algorithmic FP32 work per word of the renderer: head map applied to the
+# suffix point (2 complex multiply-adds, 16 flops), |den|^2 (3), reciprocal
+# (1), numerator times conjugate denominator (6), scaling to pixels (2)
+FLOPS_PER_WORD = 28
+FP32_PEAK_TFLOPS = 157.3  # MI355X FP32 vector peak (counts packed FMA)
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "render_kernel_quasifuchsian_d18_pmc.txt")
+KERNEL_SRC = os.path.join(ROOT, "paper_1709_08018_amd", "csrc", "kernels.hip")
+
+
+def _hip():
+    lib = ctypes.CDLL("libamdhip64.so.7")  # the runtime torch already loaded
+    lib.hipEventCreate.argtypes = [ctypes.POINTER(ctypes.c_void_p)]
+    lib.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p, ctypes.c_void_p]
+    lib.hipEventDestroy.argtypes = [ctypes.c_void_p]
+    return lib
+
+
+def _traffic_from_profile():
+    """HBM bytes per launch from the committed counter summary, if it was
+    taken on the current kernel source; else None."""
+    if not os.path.exists(PMC_SUMMARY):
+        return None
+    src_hash = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+    vals = {}
+    for line in open(PMC_SUMMARY):
+        if ":" in line:
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernels.hip sha256[:16]") != src_hash:
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(wl_obj, seconds_hint: float):
+    from oracle import oracle as ref
+
+    threads = min(len(os.sched_getaffinity(0)), 16)
+    n = ref.num_words(wl_obj.depth)
+    t0 = time.perf_counter()
+    img, dropped, _ = ref.render(wl_obj.ta, wl_obj.tb, wl_obj.depth, wl_obj.window.as_tuple(), nthreads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": n / dt / 1e9, "unit": "Gwords/s", "cores": threads, "kind": "oracle",
+            "sample": f"the full workload ({n} words, depth {wl_obj.depth}), FP64 depth-first walk, "
+                      f"{threads} threads over contiguous index ranges, {dt:.2f} s"}, img, dropped
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="after the steps, copy 256 MiB device to device twice (a kernel of known HBM "
+                         "traffic that scales counter-based byte counts)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the renderer shards by "
+              f"index range with one image reduction, which this build does not run.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1709_08018_amd import kl
+    from paper_1709_08018_amd import workloads as wl
+
+    torch.cuda.set_device(0)
+    W = wl.QUASIFUCHSIAN_D18
+    n_words = kl.num_words(W.depth)
+    plan = kl.plan(W.depth, "fp32")
+    image = kl.new_image(W.window)
+    dropped = torch.zeros(1, dtype=torch.int64, device="cuda")
+    hip = _hip()
+    events = []
+    for _ in range(2 * args.steps):
+        e = ctypes.c_void_p()
+        if hip.hipEventCreate(ctypes.byref(e)) != 0:
+            raise RuntimeError("hipEventCreate failed")
+        events.append(e.value)
+
+    def step(i=None):
+        ev = None if i is None else (events[2 * i], events[2 * i + 1])
+        kl.render(W.ta, W.tb, W.depth, W.window, image=image, dropped=dropped, kernel_events=ev)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(i)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = wall * 1e3 / args.steps
+    kernel_ms = []
+    for i in range(args.steps):
+        ms = ctypes.c_float()
+        hip.hipEventElapsedTime(ctypes.byref(ms), events[2 * i], events[2 * i + 1])
+        kernel_ms.append(ms.value)
+    for e in events:
+        hip.hipEventDestroy(e)
+    kernel_avg = float(np.mean(kernel_ms))
+
+    if args.calib_copy:
+        src = torch.empty(64 * 2 ** 20, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(2):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+
+    h = kl.as_u32(image).astype(np.int64)
+    total = int(h.sum()) + int(dropped.item())
+    assert total == n_words, f"image + dropped = {total} != {n_words}"
+
+    # words handled by the persistent kernel: whole units of 64 heads
+    R = 3 ** plan["tail_len"]
+    heads = n_words // R
+    kernel_words = (heads // 64) * 64 * R
+    achieved = FLOPS_PER_WORD * kernel_words / (kernel_avg * 1e-3) / 1e12
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / FP32_PEAK_TFLOPS, 4), "traffic": _traffic_from_profile(),
+                "kernel": "render_kernel<float>", "kernel_ms": round(kernel_avg, 4),
+                "flops_per_word": FLOPS_PER_WORD, "words_per_launch": kernel_words}
+
+    out = {
+        "metric": METRIC,
+        "value": round(n_words / (ms_per_step * 1e-3) / 1e9, 3),
+        "unit": "Gwords/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "strong",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": W.name, "depth": W.depth, "words": n_words,
+                   "ta": [W.ta.real, W.ta.imag], "tb": [W.tb.real, W.tb.imag],
+                   "image": f"{W.window.width}x{W.window.height} u32 over [-1.5,1.5]^2",
+                   "arithmetic": "FP64 generators, seeds and prefix products; FP32 suffix maps",
+                   "split": {k: plan[k] for k in ("prefix_len", "lane_len", "tail_len", "waves_per_cu")},
+                   "dropped": int(dropped.item())},
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        cb, ref_img, ref_drop = cpu_baseline(W, 15.0)
+        out["cpu_baseline"] = cb
+        diff = int(np.abs(h - ref_img.astype(np.int64)).sum())
+        out["config"]["l1_vs_reference_image"] = diff
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -107,6 +107,10 @@ typedef struct {
     int waves_per_cu;     /* persistent grid size, 0 = planner */
     int suffix_form;      /* 0: affine suffix points unless one needs the
                              homogeneous form; 1: homogeneous form always */
+    void *kernel_events[2];/* instrumentation: two hipEvent_t created by the
+                             caller, or NULL; recorded on the stream right
+                             before and right after the persistent renderer's
+                             launches (of the deepest depth rendered) */
 } kl_opts;
 
 /* The split the renderer uses for one depth (see kl_plan). */

@@ -388,6 +388,7 @@ static int render_depth(const Gens& G, const Fold& f, int depth, uint64_t lo, ui
         const uint64_t hb = (lo + sp.R - 1) / sp.R, he = hi / sp.R;
         const uint64_t units = he > hb ? (he - hb) / kWave : 0;
         if (units > 0) {
+            if (o.kernel_events[0]) (void)hipEventRecord((hipEvent_t)o.kernel_events[0], s);
             for (uint64_t done = 0; done < units;) {
                 const uint64_t chunk = std::min<uint64_t>(units - done, 1ull << 30);
                 RenderJob part = job;
@@ -397,6 +398,7 @@ static int render_depth(const Gens& G, const Fold& f, int depth, uint64_t lo, ui
                 if (e != hipSuccess) return hip_fail(e, "render kernel");
                 done += chunk;
             }
+            if (o.kernel_events[1]) (void)hipEventRecord((hipEvent_t)o.kernel_events[1], s);
             const uint64_t h_end = hb + units * kWave;
             rag_hi = hb * sp.R;
             job.rag_first[1] = h_end * sp.R;

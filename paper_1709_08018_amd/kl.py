@@ -43,7 +43,7 @@ class Opts(ctypes.Structure):
                 ("first_idx", ctypes.c_uint64), ("count", ctypes.c_uint64), ("accumulate", ctypes.c_int),
                 ("stream", ctypes.c_void_p), ("dropped_out", ctypes.c_void_p), ("tail_len", ctypes.c_int),
                 ("lane_len", ctypes.c_int), ("hist_mode", ctypes.c_int), ("waves_per_cu", ctypes.c_int),
-                ("suffix_form", ctypes.c_int)]
+                ("suffix_form", ctypes.c_int), ("kernel_events", ctypes.c_void_p * 2)]
 
 
 class Plan(ctypes.Structure):
@@ -129,7 +129,7 @@ def _stream(stream):
 
 def make_opts(*, min_depth=0, precision="fp32", first=None, count=None, accumulate=False, stream=None,
               dropped=None, tail_len=0, lane_len=0, hist_mode="auto", waves_per_cu=0, suffix_form=0,
-              use_stream=True) -> Opts:
+              kernel_events=None, use_stream=True) -> Opts:
     o = Opts()
     o.min_depth = int(min_depth)
     o.precision = PREC[precision] if isinstance(precision, str) else int(precision)
@@ -145,6 +145,9 @@ def make_opts(*, min_depth=0, precision="fp32", first=None, count=None, accumula
     o.hist_mode = HIST[hist_mode] if isinstance(hist_mode, str) else int(hist_mode)
     o.waves_per_cu = int(waves_per_cu)
     o.suffix_form = int(suffix_form)
+    if kernel_events is not None:
+        o.kernel_events[0] = kernel_events[0]
+        o.kernel_events[1] = kernel_events[1]
     return o
 
 
