@@ -145,10 +145,10 @@ def main():
     total = int(h.sum()) + int(dropped.item())
     assert total == n_words, f"image + dropped = {total} != {n_words}"
 
-    # words handled by the persistent kernel: whole units of 64 heads
+    # words handled by the persistent kernel: every whole head (all of them
+    # for a full render, whose word count is a multiple of 3^tail_len)
     R = 3 ** plan["tail_len"]
-    heads = n_words // R
-    kernel_words = (heads // 64) * 64 * R
+    kernel_words = (n_words // R) * R
     achieved = FLOPS_PER_WORD * kernel_words / (kernel_avg * 1e-3) / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / FP32_PEAK_TFLOPS, 4), "traffic": _traffic_from_profile(),

@@ -237,39 +237,49 @@ struct Temp {
     }
 };
 
-// Device tables of one parameter set for one split.
+// Device tables of one parameter set for one split, in one temporary
+// allocation, built by the fused set-up kernel (which also clears the image
+// and the dropped counter when asked to).
 struct SetTables {
     Tables tab{};
     const void* tail_homog = nullptr;
 };
 
-static int build_tables(const Gens& G, const Split& sp, int precision, int force_homog, Temp& tmp,
-                        SetTables* out) {
-    hipError_t e;
-    m64* prefix = nullptr;
-    uint8_t* last = nullptr;
-    if (sp.k > 0) {
-        const uint64_t np = num_words(sp.k);
-        if ((e = tmp.alloc((void**)&prefix, np * sizeof(m64))) != hipSuccess) return hip_fail(e, "prefix table");
-        if ((e = tmp.alloc((void**)&last, np)) != hipSuccess) return hip_fail(e, "prefix letters");
-        if ((e = launch_prefix_table(G, sp.k, prefix, last, tmp.s)) != hipSuccess) return hip_fail(e, "prefix kernel");
-    }
+static size_t round16(size_t x) { return (x + 15) & ~size_t(15); }
+
+static int build_tables(const Gens& G, const Split& sp, int precision, int force_homog, Temp& tmp, SetTables* out,
+                        uint32_t* clear_image = nullptr, uint64_t bins = 0, uint64_t* clear_dropped = nullptr) {
+    const uint64_t np = sp.k ? num_words(sp.k) : 0;
     const uint64_t nt = num_words(sp.r);
     const size_t esz = precision == KL_PREC_FP64 ? sizeof(c64) : sizeof(c32);
-    void *aff = nullptr, *hom = nullptr;
-    uint32_t* flags = nullptr;
-    if ((e = tmp.alloc(&aff, nt * esz + 16)) != hipSuccess) return hip_fail(e, "suffix table");
-    if ((e = tmp.alloc(&hom, 2 * nt * esz + 16)) != hipSuccess) return hip_fail(e, "suffix table");
-    if ((e = tmp.alloc((void**)&flags, 16)) != hipSuccess) return hip_fail(e, "suffix flags");
-    if ((e = launch_fill_u32(flags, 1, 0, tmp.s)) != hipSuccess) return hip_fail(e, "fill");
-    if ((e = launch_tail_table(G, sp.r, precision, aff, hom, flags, tmp.s)) != hipSuccess)
-        return hip_fail(e, "suffix kernel");
-    if (force_homog && (e = launch_fill_u32(flags, 1, 1, tmp.s)) != hipSuccess) return hip_fail(e, "fill");
-    out->tab.prefix = prefix;
-    out->tab.prefix_last = last;
-    out->tab.tail = aff;
-    out->tab.tail_flags = flags;
-    out->tail_homog = hom;
+    const size_t off_last = round16(np * sizeof(m64));
+    const size_t off_aff = off_last + round16(np);
+    const size_t off_hom = off_aff + round16(nt * esz + 16);
+    const size_t off_flags = off_hom + round16(2 * nt * esz + 16);
+    const size_t total = off_flags + 16;
+    unsigned char* base = nullptr;
+    hipError_t e = tmp.alloc((void**)&base, total);
+    if (e != hipSuccess) return hip_fail(e, "tables");
+    SetupJob j{};
+    j.gens = G;
+    j.precision = precision;
+    j.k = sp.k;
+    j.r = sp.r;
+    j.force_homog = force_homog;
+    j.prefix = np ? (m64*)base : nullptr;
+    j.last = np ? base + off_last : nullptr;
+    j.aff = base + off_aff;
+    j.hom = base + off_hom;
+    j.flags = (uint32_t*)(base + off_flags);
+    j.image = clear_image;
+    j.bins = bins;
+    j.dropped = clear_dropped;
+    if ((e = launch_setup(j, tmp.s)) != hipSuccess) return hip_fail(e, "set-up kernel");
+    out->tab.prefix = j.prefix;
+    out->tab.prefix_last = j.last;
+    out->tab.tail = j.aff;
+    out->tab.tail_flags = j.flags;
+    out->tail_homog = j.hom;
     return KL_OK;
 }
 
@@ -358,17 +368,22 @@ static kl_opts apply_tuned(const kl_opts& o, int depth, const kl_window* w) {
     return r;
 }
 
-// Render the words [lo, hi) of one depth.
+// Render the words [lo, hi) of one depth; with `clear`, the set-up kernel
+// also clears the image and the dropped counter first.
 static int render_depth(const Gens& G, const Fold& f, int depth, uint64_t lo, uint64_t hi, const kl_opts& o_in,
-                        const kl_window* w, uint32_t* image, uint64_t* dropped, hipStream_t s) {
-    if (lo >= hi) return KL_OK;
+                        const kl_window* w, uint32_t* image, uint64_t* dropped, hipStream_t s, bool clear) {
+    if (lo >= hi && !clear) return KL_OK;
     const kl_opts o = apply_tuned(o_in, depth, w);
     Split sp;
     int rc = plan_split(depth, o.precision, o.tail_len, o.lane_len, &sp);
     if (rc) return rc;
     Temp tmp(s);
     SetTables st;
-    if ((rc = build_tables(G, sp, o.precision, o.suffix_form, tmp, &st))) return rc;
+    const uint64_t bins = (uint64_t)w->width * w->height;
+    if ((rc = build_tables(G, sp, o.precision, o.suffix_form, tmp, &st, clear ? image : nullptr, bins,
+                           clear ? dropped : nullptr)))
+        return rc;
+    if (lo >= hi) return KL_OK;
     RenderJob job{};
     job.sp = sp;
     job.precision = o.precision;
@@ -384,25 +399,25 @@ static int render_depth(const Gens& G, const Fold& f, int depth, uint64_t lo, ui
     job.grid_blocks = grid_for(o.waves_per_cu);
     uint64_t rag_lo = lo, rag_hi = hi;  // default: every word by the per-word kernel
     if (persistent_ok(sp)) {
-        // whole heads inside [lo, hi), in units of 64 heads, go to the persistent kernel
+        // whole heads inside [lo, hi) go to the persistent kernel
         const uint64_t hb = (lo + sp.R - 1) / sp.R, he = hi / sp.R;
-        const uint64_t units = he > hb ? (he - hb) / kWave : 0;
-        if (units > 0) {
+        if (he > hb) {
             if (o.kernel_events[0]) (void)hipEventRecord((hipEvent_t)o.kernel_events[0], s);
-            for (uint64_t done = 0; done < units;) {
-                const uint64_t chunk = std::min<uint64_t>(units - done, 1ull << 30);
+            const uint64_t max_heads = (uint64_t)kWave << 30;
+            for (uint64_t h0 = hb; h0 < he;) {
+                const uint64_t nh = std::min(he - h0, max_heads);
                 RenderJob part = job;
-                part.head_begin = hb + done * kWave;
-                part.n_units = (uint32_t)chunk;
+                part.head_begin = h0;
+                part.n_heads = nh;
+                part.n_units = (uint32_t)((nh + kWave - 1) / kWave);
                 hipError_t e = launch_render(part, s);
                 if (e != hipSuccess) return hip_fail(e, "render kernel");
-                done += chunk;
+                h0 += nh;
             }
             if (o.kernel_events[1]) (void)hipEventRecord((hipEvent_t)o.kernel_events[1], s);
-            const uint64_t h_end = hb + units * kWave;
             rag_hi = hb * sp.R;
-            job.rag_first[1] = h_end * sp.R;
-            job.rag_count[1] = hi - h_end * sp.R;
+            job.rag_first[1] = he * sp.R;
+            job.rag_count[1] = hi - he * sp.R;
         }
     }
     job.n_units = 0;
@@ -559,22 +574,20 @@ int kl_render_ex(kl_c64 ta, kl_c64 tb, int depth, const kl_window* window, uint3
     if ((rc = make_gens(ta, tb, &G))) return rc;
     const Fold f = make_fold(window);
     hipStream_t s = (hipStream_t)o.stream;
-    hipError_t e;
-    const uint64_t bins = (uint64_t)window->width * window->height;
-    if (!o.accumulate) {
-        if ((e = launch_fill_u32(image_out, bins, 0, s)) != hipSuccess) return hip_fail(e, "clear image");
-        if (o.dropped_out && (e = launch_fill_u64(o.dropped_out, 1, 0, s)) != hipSuccess)
-            return hip_fail(e, "clear dropped");
-    }
+    bool clear = !o.accumulate;
     uint64_t offset = 0;
     const uint64_t end = first + count;
     for (int d = min_depth; d <= depth; ++d) {
         const uint64_t n = num_words(d);
         const uint64_t lo = first > offset ? first - offset : 0;
         const uint64_t hi = end - offset < n ? end - offset : n;
-        if (end > offset && first < offset + n && lo < hi) {
+        if ((end > offset && first < offset + n && lo < hi) || (clear && d == depth)) {
             const kl_opts od = d == depth ? o : opts_for_depth(o, d);
-            if ((rc = render_depth(G, f, d, lo, hi, od, window, image_out, o.dropped_out, s))) return rc;
+            const bool any = end > offset && first < offset + n && lo < hi;
+            if ((rc = render_depth(G, f, d, any ? lo : 0, any ? hi : 0, od, window, image_out, o.dropped_out, s,
+                                   clear)))
+                return rc;
+            clear = false;
         }
         offset += n;
     }
@@ -669,7 +682,7 @@ int kl_render_many_ex(int n, const kl_c64* ta, const kl_c64* tb, const int* dept
     for (int i = 0; i < n; ++i)
         if (persistent_ok(splits[i])) batch.push_back(i);
         else if ((rc = render_depth(gens[i], f, depth[i], 0, num_words(depth[i]), per[i], window, images_out + bins * i,
-                                    o.dropped_out ? o.dropped_out + i : nullptr, s)))
+                                    o.dropped_out ? o.dropped_out + i : nullptr, s, false)))
             return rc;
     if (batch.empty()) return KL_OK;
     const int nb = (int)batch.size();

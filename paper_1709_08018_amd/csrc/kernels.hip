@@ -210,7 +210,7 @@ __device__ inline void scale_pow2(cpx<T>& u, cpx<T>& v) {
 // and its affine form y = u / v.
 template <typename T>
 __device__ inline void tail_entry(const Gens& g, int r, uint32_t t, cpx<T>* __restrict__ affine,
-                                  cpx<T>* __restrict__ homog, uint32_t* __restrict__ flags) {
+                                  cpx<T>* __restrict__ homog, uint32_t* __restrict__ flags, bool atomic = true) {
     const uint64_t w = decode_packed(t, r);
     const int last = (int)((w >> (2 * (r - 1))) & 3);
     cpx<T> u = {(T)g.fix[last].re, (T)g.fix[last].im};
@@ -232,7 +232,8 @@ __device__ inline void tail_entry(const Gens& g, int r, uint32_t t, cpx<T>* __re
     const bool ok = n2 > T(0) && isfinite(y.re) && isfinite(y.im) && fabs(y.re) <= T(kAffineLimit) &&
                     fabs(y.im) <= T(kAffineLimit);
     if (!ok) {
-        atomicOr(flags, 1u);
+        if (atomic) atomicOr(flags, 1u);
+        else *flags = 1u;
         y = {T(0), T(0)};
     }
     affine[t] = y;
@@ -257,6 +258,57 @@ hipError_t launch_tail_table(const Gens& g, int r, int precision, void* tail_aff
         hipLaunchKernelGGL(tail_table_kernel<float>, dim3((n + 255) / 256), dim3(256), 0, s, g, r, n,
                            (c32*)tail_affine, (c32*)tail_homog, flags);
     return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ fused set-up
+// One launch that clears the image and the dropped counter, builds the
+// FP64 prefix table (blocks 1..) and the suffix table (block 0, which also
+// decides the suffix form without a separate clear of the flag).
+struct SetupArgs {
+    Gens g;
+    int k, r;
+    uint32_t n_prefix, n_tail;
+    m64* prefix;
+    uint8_t* last;
+    void* aff;
+    void* hom;
+    uint32_t* flags;
+    int force_homog;
+    uint32_t* image;      // null: leave the image alone
+    uint64_t bins;
+    uint64_t* dropped;    // null: leave the counter alone
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void setup_kernel(const SetupArgs a) {
+    if (a.image) {
+        const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+        const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+        if (((uintptr_t)a.image & 15) == 0) {
+            const uint64_t n4 = a.bins / 4;
+            uint4* p4 = (uint4*)a.image;
+            for (uint64_t i = tid; i < n4; i += stride) p4[i] = make_uint4(0, 0, 0, 0);
+            for (uint64_t i = n4 * 4 + tid; i < a.bins; i += stride) a.image[i] = 0;
+        } else {
+            for (uint64_t i = tid; i < a.bins; i += stride) a.image[i] = 0;
+        }
+    }
+    if (blockIdx.x == 0) {
+        uint32_t bad = 0;
+        for (uint32_t t = threadIdx.x; t < a.n_tail; t += blockDim.x) {
+            uint32_t f = 0;
+            tail_entry<T>(a.g, a.r, t, (cpx<T>*)a.aff, (cpx<T>*)a.hom, &f, false);
+            bad |= f;
+        }
+        bad = __syncthreads_or(bad);
+        if (threadIdx.x == 0) {
+            a.flags[0] = (bad || a.force_homog) ? 1u : 0u;
+            if (a.dropped) a.dropped[0] = 0;
+        }
+    } else {
+        const uint32_t p = (blockIdx.x - 1) * 256 + threadIdx.x;
+        if (p < a.n_prefix) prefix_entry(a.g, a.k, p, a.prefix, a.last);
+    }
 }
 
 // ------------------------------------------------------------------ shared arithmetic
@@ -401,7 +453,8 @@ struct RenderArgs {
     uint32_t* image;
     uint32_t W, H;
     uint64_t* dropped;
-    uint64_t head_begin;   // first head; the heads [head_begin, head_begin + 64 n_units) are rendered
+    uint64_t head_begin;   // the heads [head_begin, head_begin + n_heads) are rendered,
+    uint64_t n_heads;      // in n_units = ceil(n_heads / 64) units of 64
     uint32_t n_units;
 };
 
@@ -469,9 +522,24 @@ __device__ __forceinline__ void render_units(const RenderArgs& a, const unsigned
     const T aniso = (T)a.fold.aniso;
     uint32_t t_words = 0;
     for (uint32_t unit = gwave; unit < a.n_units; unit += waves) {
-        const uint64_t hidx = a.head_begin + (uint64_t)unit * kWave + lane;
-        const Head<T> h = compute_head<T>(hidx, a.sp, a.tab.prefix, a.tab.prefix_last, G, a.fold);
-        walk_tails<T, AFFINE, ANISO>(h, tail_lds, a.sp.R1, aniso, a.W, a.H, a.image, s, t_words);
+        const uint64_t local = (uint64_t)unit * kWave + lane;
+        if ((uint64_t)(unit + 1) * kWave <= a.n_heads) {
+            const Head<T> h = compute_head<T>(a.head_begin + local, a.sp, a.tab.prefix, a.tab.prefix_last, G, a.fold);
+            walk_tails<T, AFFINE, ANISO>(h, tail_lds, a.sp.R1, aniso, a.W, a.H, a.image, s, t_words);
+        } else {
+            // last, partial unit: idle lanes walk a valid head without binning
+            // and their count is discarded
+            const bool live = local < a.n_heads;
+            const uint64_t hidx = a.head_begin + (live ? local : a.n_heads - 1);
+            close_run(s, t_words, a.image);
+            s.cur = kOutside;
+            s.start = t_words;
+            const Head<T> h = compute_head<T>(hidx, a.sp, a.tab.prefix, a.tab.prefix_last, G, a.fold);
+            walk_tails<T, AFFINE, ANISO, true>(h, tail_lds, a.sp.R1, aniso, a.W, a.H, a.image, s, t_words, live);
+            if (live) close_run(s, t_words, a.image);
+            s.cur = kOutside;
+            s.start = t_words;
+        }
     }
     close_run(s, t_words, a.image);
 }
@@ -612,6 +680,7 @@ static hipError_t launch_render_t(const RenderJob& job, hipStream_t s) {
         a.H = job.height;
         a.dropped = job.dropped;
         a.head_begin = job.head_begin;
+        a.n_heads = job.n_heads;
         a.n_units = job.n_units;
         const size_t n_tail = 4 * (size_t)job.sp.R1;
         const size_t lds = ((n_tail * 2 * sizeof(cpx<T>) + 15) & ~size_t(15)) + 4 * sizeof(m64);
@@ -866,6 +935,35 @@ hipError_t launch_render_batch(const BatchJob& job, hipStream_t s) {
         if (an) hipLaunchKernelGGL((render_batch_kernel<float, true>), dim3(grid), dim3(kBlock), lds, s, a);
         else hipLaunchKernelGGL((render_batch_kernel<float, false>), dim3(grid), dim3(kBlock), lds, s, a);
     }
+    return hipGetLastError();
+}
+
+}  // namespace kl
+
+namespace kl {
+
+hipError_t launch_setup(const SetupJob& j, hipStream_t s) {
+    SetupArgs a;
+    a.g = j.gens;
+    a.k = j.k;
+    a.r = j.r;
+    a.n_prefix = j.k ? (uint32_t)num_words(j.k) : 0;
+    a.n_tail = (uint32_t)num_words(j.r);
+    a.prefix = j.prefix;
+    a.last = j.last;
+    a.aff = j.aff;
+    a.hom = j.hom;
+    a.flags = j.flags;
+    a.force_homog = j.force_homog;
+    a.image = j.image;
+    a.bins = j.bins;
+    a.dropped = j.dropped;
+    uint64_t blocks = 1 + (a.n_prefix + 255) / 256;
+    if (a.image) blocks = std::max<uint64_t>(blocks, std::min<uint64_t>(2048, (a.bins / 4 + 255) / 256));
+    if (j.precision == KL_PREC_FP64)
+        hipLaunchKernelGGL(setup_kernel<double>, dim3((unsigned)blocks), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL(setup_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

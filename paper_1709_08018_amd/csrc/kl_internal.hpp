@@ -97,6 +97,22 @@ hipError_t launch_prefix_table(const Gens& g, int k, m64* prefix, uint8_t* last,
 hipError_t launch_tail_table(const Gens& g, int r, int precision, void* tail_affine,
                              void* tail_homog, uint32_t* flags, hipStream_t s);
 
+// Fused set-up of one render or evaluation: image / dropped clear, FP64
+// prefix table, suffix table and its form flag.
+struct SetupJob {
+    Gens gens;
+    int precision, k, r, force_homog;
+    m64* prefix;
+    uint8_t* last;
+    void* aff;
+    void* hom;
+    uint32_t* flags;
+    uint32_t* image;       // null: not cleared
+    uint64_t bins;
+    uint64_t* dropped;     // null: not cleared
+};
+hipError_t launch_setup(const SetupJob& j, hipStream_t s);
+
 struct RenderJob {
     Split sp;
     int precision;
@@ -107,8 +123,9 @@ struct RenderJob {
     uint32_t* image;
     uint32_t width, height;
     uint64_t* dropped;         // device u64 (may be null)
-    // persistent kernel: heads [head_begin, head_begin + 64 n_units)
+    // persistent kernel: heads [head_begin, head_begin + n_heads), n_units = ceil(n_heads / 64)
     uint64_t head_begin;
+    uint64_t n_heads;
     uint32_t n_units;
     // per-word kernel: word indices (within this depth) of the ragged ends
     uint64_t rag_first[2], rag_count[2];
