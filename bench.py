@@ -45,9 +45,9 @@ def _hip():
     return lib
 
 
-def _traffic_from_profile():
+def _traffic_from_profile(plan):
     """HBM bytes per launch from the committed counter summary, if it was
-    taken on the current kernel source; else None."""
+    taken on the current kernel source and split; else None."""
     if not os.path.exists(PMC_SUMMARY):
         return None
     src_hash = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
@@ -57,6 +57,9 @@ def _traffic_from_profile():
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
     if vals.get("kernels.hip sha256[:16]") != src_hash:
+        return None
+    split = f"prefix {plan['prefix_len']}, lane {plan['lane_len']}, tail {plan['tail_len']}"
+    if split not in vals.get("split", ""):
         return None
     try:
         return float(vals["hbm_bytes_per_launch"])
@@ -77,11 +80,134 @@ def cpu_baseline(wl_obj, seconds_hint: float):
                       f"{threads} threads over contiguous index ranges, {dt:.2f} s"}, img, dropped
 
 
+def _time(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / steps
+
+
+def leg_d22(args):
+    """Depth 22 streamed by index range: FP32 suffix path vs full FP64, and the
+    FP32 path's pixel error against the CPU reference on 10^6 sampled words."""
+    import numpy as np
+    import torch
+
+    from oracle import oracle as ref
+    from paper_1709_08018_amd import kl
+    from paper_1709_08018_amd import workloads as wl
+
+    W = wl.QUASIFUCHSIAN_D22
+    n = kl.num_words(W.depth)
+    chunks = 8
+    cuts = [n * i // chunks for i in range(chunks + 1)]
+    image = kl.new_image(W.window)
+    dropped = torch.zeros(1, dtype=torch.int64, device="cuda")
+    res = {}
+    for prec in ("fp32", "fp64"):
+        def run():
+            for a, b in zip(cuts[:-1], cuts[1:]):
+                kl.render(W.ta, W.tb, W.depth, W.window, image=image, precision=prec, first=a, count=b - a,
+                          accumulate=a > 0, dropped=dropped)
+        ms = _time(run, max(1, args.steps // 4), 1)
+        h = kl.as_u32(image).astype(np.int64)
+        assert int(h.sum()) + int(dropped.item()) == n
+        res[prec] = {"ms": round(ms, 3), "gwords_per_s": round(n / ms / 1e6, 2), "max_bin": int(h.max())}
+    idx = wl.sample_indices(n, 1_000_000, seed=0)
+    p = kl.eval_values(W.ta, W.tb, W.depth, idx, precision="fp32", window=W.window).cpu().numpy()
+    z = ref.eval_values(W.ta, W.tb, W.depth, idx)
+    x0, x1, y0, y1, Wd, Hd = W.window.as_tuple()
+    fx, fy = (z.real - x0) * Wd / (x1 - x0), (z.imag - y0) * Hd / (y1 - y0)
+    near = (fx > -1) & (fx < Wd + 1) & (fy > -1) & (fy < Hd + 1)
+    err = np.hypot(p[near, 0] - fx[near], p[near, 1] - fy[near])
+    return {"workload": W.name, "words": n, "chunks": chunks, **res,
+            "fp32_pixel_error": {"max": float(err.max()), "p99": float(np.quantile(err, 0.99)),
+                                 "mean": float(err.mean()), "words": int(near.sum()), "sample": 1_000_000}}
+
+
+def leg_batch(args):
+    """256 parameter sets of depths 12..18: one batched persistent launch vs
+    256 single renders enqueued back to back on one stream."""
+    import numpy as np
+    import torch
+
+    from paper_1709_08018_amd import kl
+    from paper_1709_08018_amd import workloads as wl
+
+    ta, tb, depth = wl.batch256(seed=0)
+    win = wl.BATCH_WINDOW
+    words = sum(kl.num_words(int(d)) for d in depth)
+    imgs = kl.new_image(win, len(ta))
+
+    def batched():
+        kl.render_many(ta, tb, depth, win, images=imgs)
+
+    def separate():
+        for i in range(len(ta)):
+            kl.render(ta[i], tb[i], int(depth[i]), win, image=imgs[i])
+
+    ms_b = _time(batched, max(2, args.steps // 4), 1)
+    ref = imgs.clone()
+    ms_s = _time(separate, max(2, args.steps // 4), 1)
+    same = bool(torch.equal(ref, imgs))
+    return {"workload": "batch256", "sets": len(ta), "words": words, "batched_ms": round(ms_b, 3),
+            "separate_ms": round(ms_s, 3), "speedup": round(ms_s / ms_b, 3),
+            "batched_gwords_per_s": round(words / ms_b / 1e6, 2), "images_identical": same}
+
+
+def leg_tiling(args):
+    """Real traces ta = tb = 3, tiling mode over depths 1..10 (FP64 and FP32)."""
+    from paper_1709_08018_amd import kl
+    from paper_1709_08018_amd import workloads as wl
+
+    W = wl.FUCHSIAN_TILING_D10
+    words = sum(kl.num_words(d) for d in range(1, W.depth + 1))
+    image = kl.new_image(W.window)
+    out = {"workload": W.name, "words": words}
+    for prec in ("fp32", "fp64"):
+        ms = _time(lambda: kl.render(W.ta, W.tb, W.depth, W.window, image=image, min_depth=1, precision=prec),
+                   args.steps, args.warmup)
+        out[prec] = {"ms": round(ms, 4), "gwords_per_s": round(words / ms / 1e6, 3)}
+    return out
+
+
+def leg_hist(args):
+    """Depth-18 renderer kernel time per histogram strategy and split."""
+    import numpy as np
+    import torch
+
+    from paper_1709_08018_amd import kl
+    from paper_1709_08018_amd import workloads as wl
+
+    W = wl.QUASIFUCHSIAN_D18
+    image = kl.new_image(W.window)
+    rows = []
+    ref = None
+    for r in (4, 5, 6):
+        for m in (2, 3, 4):
+            for wpc in (16, 32):
+                for hist in ("runs", "lds"):
+                    opts = dict(tail_len=r, lane_len=m, waves_per_cu=wpc, hist_mode=hist)
+                    ms = _time(lambda: kl.render(W.ta, W.tb, W.depth, W.window, image=image, **opts), 5, 1)
+                    if ref is None:
+                        ref = image.clone()
+                    rows.append({**opts, "step_ms": round(ms, 4)})
+    rows.sort(key=lambda x: x["step_ms"])
+    return {"workload": W.name, "candidates": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="quasifuchsian_d18",
+                    choices=["quasifuchsian_d18", "quasifuchsian_d22", "batch256", "fuchsian_tiling_d10", "hist"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="after the steps, copy 256 MiB device to device twice (a kernel of known HBM "
@@ -99,6 +225,11 @@ def main():
     from paper_1709_08018_amd import workloads as wl
 
     torch.cuda.set_device(0)
+    legs = {"quasifuchsian_d22": leg_d22, "batch256": leg_batch, "fuchsian_tiling_d10": leg_tiling,
+            "hist": leg_hist}
+    if args.workload in legs:
+        print(json.dumps(legs[args.workload](args)), flush=True)
+        return
     W = wl.QUASIFUCHSIAN_D18
     n_words = kl.num_words(W.depth)
     plan = kl.plan(W.depth, "fp32")
@@ -151,7 +282,7 @@ def main():
     kernel_words = (n_words // R) * R
     achieved = FLOPS_PER_WORD * kernel_words / (kernel_avg * 1e-3) / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / FP32_PEAK_TFLOPS, 4), "traffic": _traffic_from_profile(),
+                "frac": round(achieved / FP32_PEAK_TFLOPS, 4), "traffic": _traffic_from_profile(plan),
                 "kernel": "render_kernel<float>", "kernel_ms": round(kernel_avg, 4),
                 "flops_per_word": FLOPS_PER_WORD, "words_per_launch": kernel_words}
 

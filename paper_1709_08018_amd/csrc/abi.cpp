@@ -178,7 +178,7 @@ int device_cu_count() {
 }
 
 // ------------------------------------------------------------------ planning
-static const int kDefaultTail = 5;
+static const int kDefaultTail = 6;
 static const int kDefaultWavesPerCU = 32;
 
 int plan_split(int depth, int precision, int r_req, int m_req, Split* sp, int prefix_cap) {
@@ -789,13 +789,13 @@ int kl_autotune(kl_c64 ta, kl_c64 tb, int depth, const kl_window* window, int pr
     for (int r = 3; r <= std::min(kMaxTail - 1, depth - 1); ++r) {
         for (int m = 1; m <= std::min(6, depth - r - 1); ++m) {
             if (depth - r - m > kMaxPrefix) continue;
-            for (int wpc : wpcs) {
+            for (int wpc : wpcs) for (int hist : {KL_HIST_RUNS, KL_HIST_LDS}) {
                 kl_opts o = default_opts();
                 o.precision = precision;
                 o.tail_len = r;
                 o.lane_len = m;
                 o.waves_per_cu = wpc;
-                o.hist_mode = KL_HIST_RUNS;
+                o.hist_mode = hist;
                 std::vector<float> times;
                 for (int rep = 0; rep < 4; ++rep) {
                     (void)hipEventRecord(e0, nullptr);
@@ -817,7 +817,7 @@ int kl_autotune(kl_c64 ta, kl_c64 tb, int depth, const kl_window* window, int pr
                 }
                 std::sort(times.begin(), times.end());
                 const double med = times[times.size() / 2];
-                if (med < best.ms) best = Tuned{depth, precision, r, m, wpc, KL_HIST_RUNS, med};
+                if (med < best.ms) best = Tuned{depth, precision, r, m, wpc, hist, med};
             }
         }
     }

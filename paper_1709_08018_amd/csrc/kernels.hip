@@ -465,10 +465,57 @@ struct Runs {
     uint64_t drop;
 };
 
-__device__ __forceinline__ void close_run(Runs& s, uint32_t t_words, uint32_t* image) {
+// Where a closed run's count goes.  GlobalSink: one global atomic add per
+// run.  TileSink: runs whose bin falls in the wave's 32 x 32 LDS tile are
+// added there with an LDS atomic; the tile is merged into the image with
+// one global add per non-zero bin whenever the wave moves its tile.
+struct GlobalSink {
+    uint32_t* image;
+    __device__ __forceinline__ void add(uint32_t key, uint32_t cnt) const { atomicAdd(image + key, cnt); }
+};
+
+constexpr int kTile = 32;
+
+struct TileSink {
+    uint32_t* image;
+    uint32_t* tile;   // LDS, kTile * kTile bins of this wave
+    uint32_t W, H;
+    int col0, row0;   // image position of tile bin (0, 0)
+    __device__ __forceinline__ void add(uint32_t key, uint32_t cnt) const {
+        const uint32_t row = key / W, col = key - row * W;
+        const uint32_t tc = col - (uint32_t)col0, tr = row - (uint32_t)row0;
+        if (tc < (uint32_t)kTile && tr < (uint32_t)kTile) atomicAdd(tile + tr * kTile + tc, cnt);
+        else atomicAdd(image + key, cnt);
+    }
+    // merge the tile into the image and clear it (whole wave, uniform)
+    __device__ __forceinline__ void merge(int lane) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (int i = lane; i < kTile * kTile; i += kWave) {
+            const uint32_t v = tile[i];
+            if (v) {
+                const uint32_t row = (uint32_t)row0 + (uint32_t)(i / kTile);
+                const uint32_t col = (uint32_t)col0 + (uint32_t)(i % kTile);
+                atomicAdd(image + row * W + col, v);
+                tile[i] = 0;
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+};
+
+template <typename Sink>
+__device__ __forceinline__ void close_run(Runs& s, uint32_t t_words, const Sink& sink) {
     const uint32_t cnt = t_words - s.start;
     if (s.cur == kOutside) s.drop += cnt;
-    else if (cnt) atomicAdd(image + s.cur, cnt);
+    else if (cnt) sink.add(s.cur, cnt);
+}
+
+__device__ __forceinline__ void close_run(Runs& s, uint32_t t_words, uint32_t* image) {
+    close_run(s, t_words, GlobalSink{image});
 }
 
 // All tails of one head: the 3 blocks of suffixes whose first letter may
@@ -476,10 +523,10 @@ __device__ __forceinline__ void close_run(Runs& s, uint32_t t_words, uint32_t* i
 // points loaded from LDS ahead of their use.
 // With MASKED, lanes whose `live` is false walk along without binning
 // (their bin stays kOutside; the caller discards their count).
-template <typename T, bool AFFINE, bool ANISO, bool MASKED = false>
-__device__ __forceinline__ void walk_tails(const Head<T>& h, const unsigned char* tail_lds, uint32_t R1,
-                                           T aniso, uint32_t W, uint32_t H, uint32_t* image, Runs& s,
-                                           uint32_t& t_words, bool live = true) {
+template <typename T, bool AFFINE, bool ANISO, bool MASKED = false, typename Sink = GlobalSink>
+__device__ __forceinline__ void walk_tails_s(const Head<T>& h, const unsigned char* tail_lds, uint32_t R1,
+                                             T aniso, uint32_t W, uint32_t H, const Sink& sink, Runs& s,
+                                             uint32_t& t_words, bool live = true) {
     const int ie = inv_letter(h.e);
     for (int j = 0; j < 3; ++j) {
         const uint32_t y1 = (uint32_t)(j + (j >= ie));
@@ -503,7 +550,7 @@ __device__ __forceinline__ void walk_tails(const Head<T>& h, const unsigned char
                 uint32_t key = bin_key(px, py, W, H);
                 if (MASKED && !live) key = kOutside;
                 if (key != s.cur) {
-                    close_run(s, t_words, image);
+                    close_run(s, t_words, sink);
                     s.cur = key;
                     s.start = t_words;
                 }
@@ -513,35 +560,77 @@ __device__ __forceinline__ void walk_tails(const Head<T>& h, const unsigned char
     }
 }
 
+template <typename T, bool AFFINE, bool ANISO, bool MASKED = false>
+__device__ __forceinline__ void walk_tails(const Head<T>& h, const unsigned char* tail_lds, uint32_t R1,
+                                           T aniso, uint32_t W, uint32_t H, uint32_t* image, Runs& s,
+                                           uint32_t& t_words, bool live = true) {
+    walk_tails_s<T, AFFINE, ANISO, MASKED>(h, tail_lds, R1, aniso, W, H, GlobalSink{image}, s, t_words, live);
+}
+
+// Bin of the head's first allowed word in some lane, wave-uniform; kOutside
+// if no lane's first word is in the window.
 template <typename T, bool AFFINE, bool ANISO>
+__device__ __forceinline__ uint32_t first_key(const Head<T>& h, const unsigned char* tail_lds, uint32_t R1, T aniso,
+                                              uint32_t W, uint32_t H) {
+    const uint32_t y1 = (uint32_t)(0 + (0 >= inv_letter(h.e)));
+    T px, py;
+    if constexpr (AFFINE) eval_point<T, ANISO>(h, ((const cpx<T>*)tail_lds)[y1 * R1], aniso, px, py);
+    else eval_point_h<T, ANISO>(h, ((const cpx<T>*)tail_lds)[2 * y1 * R1], ((const cpx<T>*)tail_lds)[2 * y1 * R1 + 1],
+                                aniso, px, py);
+    const uint32_t key = bin_key(px, py, W, H);
+    const uint64_t m = __ballot(key != kOutside);
+    if (!m) return kOutside;
+    return __shfl(key, __ffsll((unsigned long long)m) - 1, kWave);
+}
+
+template <typename T, bool AFFINE, bool ANISO, bool LDSHIST>
 __device__ __forceinline__ void render_units(const RenderArgs& a, const unsigned char* tail_lds, const m64* G,
-                                             Runs& s) {
+                                             uint32_t* tile, Runs& s) {
     const int lane = threadIdx.x & (kWave - 1);
     const uint32_t waves = gridDim.x * (kBlock / kWave);
     const uint32_t gwave = blockIdx.x * (kBlock / kWave) + (threadIdx.x / kWave);
     const T aniso = (T)a.fold.aniso;
     uint32_t t_words = 0;
+    TileSink ts{a.image, tile, a.W, a.H, -(1 << 30), -(1 << 30)};
     for (uint32_t unit = gwave; unit < a.n_units; unit += waves) {
         const uint64_t local = (uint64_t)unit * kWave + lane;
-        if ((uint64_t)(unit + 1) * kWave <= a.n_heads) {
-            const Head<T> h = compute_head<T>(a.head_begin + local, a.sp, a.tab.prefix, a.tab.prefix_last, G, a.fold);
-            walk_tails<T, AFFINE, ANISO>(h, tail_lds, a.sp.R1, aniso, a.W, a.H, a.image, s, t_words);
+        const bool full = (uint64_t)(unit + 1) * kWave <= a.n_heads;
+        const bool live = local < a.n_heads;
+        const uint64_t hidx = a.head_begin + (live ? local : a.n_heads - 1);
+        const Head<T> h = compute_head<T>(hidx, a.sp, a.tab.prefix, a.tab.prefix_last, G, a.fold);
+        if constexpr (LDSHIST) {
+            // move the tile to where this unit's words start
+            const uint32_t k0 = first_key<T, AFFINE, ANISO>(h, tail_lds, a.sp.R1, aniso, a.W, a.H);
+            ts.merge(lane);
+            if (k0 != kOutside) {
+                const uint32_t row = k0 / a.W;
+                ts.row0 = (int)row - kTile / 2;
+                ts.col0 = (int)(k0 - row * a.W) - kTile / 2;
+            } else {
+                ts.row0 = ts.col0 = -(1 << 30);
+            }
+        }
+        if (full) {
+            if constexpr (LDSHIST) walk_tails_s<T, AFFINE, ANISO, false>(h, tail_lds, a.sp.R1, aniso, a.W, a.H, ts, s, t_words);
+            else walk_tails<T, AFFINE, ANISO>(h, tail_lds, a.sp.R1, aniso, a.W, a.H, a.image, s, t_words);
         } else {
             // last, partial unit: idle lanes walk a valid head without binning
             // and their count is discarded
-            const bool live = local < a.n_heads;
-            const uint64_t hidx = a.head_begin + (live ? local : a.n_heads - 1);
             close_run(s, t_words, a.image);
             s.cur = kOutside;
             s.start = t_words;
-            const Head<T> h = compute_head<T>(hidx, a.sp, a.tab.prefix, a.tab.prefix_last, G, a.fold);
             walk_tails<T, AFFINE, ANISO, true>(h, tail_lds, a.sp.R1, aniso, a.W, a.H, a.image, s, t_words, live);
             if (live) close_run(s, t_words, a.image);
             s.cur = kOutside;
             s.start = t_words;
         }
     }
-    close_run(s, t_words, a.image);
+    if constexpr (LDSHIST) {
+        close_run(s, t_words, ts);
+        ts.merge(lane);
+    } else {
+        close_run(s, t_words, a.image);
+    }
 }
 
 // One wave per unit of 64 consecutive heads, units dealt round robin over
@@ -549,25 +638,31 @@ __device__ __forceinline__ void render_units(const RenderArgs& a, const unsigned
 // the bin, and a run-length counter: a lane adds to the image only when its
 // bin changes (consecutive tails of one head lie close together), and keeps
 // its dropped words in a register until the end.
-template <typename T, bool ANISO>
+// LDS: suffix table (sized for the homogeneous form), generators, and with
+// LDSHIST one 32 x 32 tile of uint32 bins per wave.
+template <typename T, bool ANISO, bool LDSHIST>
 __global__ __launch_bounds__(kBlock) void render_kernel(const RenderArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     const uint32_t n_tail = 4 * a.sp.R1;
     const bool affine = *a.tab.tail_flags == 0;
     const size_t entry = affine ? sizeof(cpx<T>) : 2 * sizeof(cpx<T>);
     const size_t tbytes = (n_tail * entry + 15) & ~size_t(15);
+    const size_t tmax = (n_tail * 2 * sizeof(cpx<T>) + 15) & ~size_t(15);
     m64* G = (m64*)(smem + tbytes);
+    uint32_t* tile = (uint32_t*)(smem + tmax + 4 * sizeof(m64)) + (threadIdx.x / kWave) * (kTile * kTile);
     {
         const uint4* src = (const uint4*)(affine ? a.tab.tail : a.tail_homog);
         uint4* dst = (uint4*)smem;
         const uint32_t n16 = (uint32_t)(tbytes / 16);
         for (uint32_t i = threadIdx.x; i < n16; i += blockDim.x) dst[i] = src[i];
         if (threadIdx.x < 4) G[threadIdx.x] = a.gens.g[threadIdx.x];
+        if (LDSHIST)
+            for (int i = threadIdx.x & (kWave - 1); i < kTile * kTile; i += kWave) tile[i] = 0;
     }
     __syncthreads();
     Runs s = {kOutside, 0, 0};
-    if (affine) render_units<T, true, ANISO>(a, smem, G, s);
-    else render_units<T, false, ANISO>(a, smem, G, s);
+    if (affine) render_units<T, true, ANISO, LDSHIST>(a, smem, G, tile, s);
+    else render_units<T, false, ANISO, LDSHIST>(a, smem, G, tile, s);
     if (a.dropped) {
         uint64_t drop = s.drop;
         for (int off = kWave / 2; off > 0; off >>= 1) drop += __shfl_down(drop, off, kWave);
@@ -683,17 +778,21 @@ static hipError_t launch_render_t(const RenderJob& job, hipStream_t s) {
         a.n_heads = job.n_heads;
         a.n_units = job.n_units;
         const size_t n_tail = 4 * (size_t)job.sp.R1;
-        const size_t lds = ((n_tail * 2 * sizeof(cpx<T>) + 15) & ~size_t(15)) + 4 * sizeof(m64);
+        const bool ldsh = job.hist_mode == KL_HIST_LDS;
+        const size_t lds = ((n_tail * 2 * sizeof(cpx<T>) + 15) & ~size_t(15)) + 4 * sizeof(m64) +
+                           (ldsh ? (kBlock / kWave) * kTile * kTile * sizeof(uint32_t) : 0);
+        const void* fn = ldsh ? reinterpret_cast<const void*>(&render_kernel<T, ANISO, true>)
+                              : reinterpret_cast<const void*>(&render_kernel<T, ANISO, false>);
         if (lds > 65536) {
-            hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&render_kernel<T, ANISO>),
-                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
             if (e != hipSuccess) return e;
         }
         uint32_t grid = (uint32_t)job.grid_blocks;
         const uint32_t need = (job.n_units + (kBlock / kWave) - 1) / (kBlock / kWave);
         if (grid > need) grid = need;
         if (grid < 1) grid = 1;
-        hipLaunchKernelGGL((render_kernel<T, ANISO>), dim3(grid), dim3(kBlock), lds, s, a);
+        if (ldsh) hipLaunchKernelGGL((render_kernel<T, ANISO, true>), dim3(grid), dim3(kBlock), lds, s, a);
+        else hipLaunchKernelGGL((render_kernel<T, ANISO, false>), dim3(grid), dim3(kBlock), lds, s, a);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

@@ -187,6 +187,16 @@ def test_tiling_ranges_cross_depths():
     assert torch.equal(acc, full)
 
 
+@pytest.mark.parametrize("depth", [14, 18])
+def test_lds_tile_histogram_equals_direct_runs(depth):
+    a = kl.render(*C2, depth, WIN_C2, hist_mode="runs")
+    b = kl.render(*C2, depth, WIN_C2, hist_mode="lds")
+    assert torch.equal(a, b)
+    c = kl.render(*C1, 10, WIN_C1, min_depth=1, hist_mode="lds")
+    d = kl.render(*C1, 10, WIN_C1, min_depth=1, hist_mode="runs")
+    assert torch.equal(c, d)
+
+
 def test_run_to_run_bit_equality():
     a = kl.render(*C2, 16, WIN_C2)
     b = kl.render(*C2, 16, WIN_C2)
