@@ -13,7 +13,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libkl.so")
-SOURCES = [os.path.join(CSRC, f) for f in ("kernels.hip", "batch.hip", "abi.cpp", "autotune.cpp")]
+SOURCES = [os.path.join(CSRC, f) for f in ("kernels.hip", "surrogate.hip", "abi.cpp")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

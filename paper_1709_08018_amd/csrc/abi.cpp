@@ -20,7 +20,7 @@ namespace kl {
 // ------------------------------------------------------------------ errors
 static thread_local std::string g_last_error;
 
-static int fail(int code, const char* fmt, ...) {
+int set_error(int code, const char* fmt, ...) {
     char buf[512];
     va_list ap;
     va_start(ap, fmt);
@@ -29,6 +29,7 @@ static int fail(int code, const char* fmt, ...) {
     g_last_error = buf;
     return code;
 }
+#define fail set_error
 
 static int hip_fail(hipError_t e, const char* what) {
     return fail(e == hipErrorOutOfMemory ? KL_ENOMEM : KL_EDEVICE, "%s: %s", what, hipGetErrorString(e));

@@ -85,6 +85,7 @@ struct Tables {                // device pointers of one parameter set
 };
 
 // Host-side planning and validation helpers (abi.cpp)
+int set_error(int code, const char* fmt, ...);  // records kl_last_error(), returns code
 int plan_split(int depth, int precision, int r_req, int m_req, Split* out, int prefix_cap = 10);
 uint64_t num_words(int depth);
 uint64_t pow3_u64(int n);

@@ -17,6 +17,7 @@ import torch  # loads the HIP runtime that libkl shares
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libkl.so")
 HEADER = os.path.join(os.path.dirname(PKG), "include", "kl.h")
+HEADERS = [HEADER, os.path.join(os.path.dirname(PKG), "include", "kl_surrogate.h")]
 
 KL_OK, KL_EINVAL, KL_ERANGE, KL_ESINGULAR, KL_EDEVICE, KL_ENOMEM = 0, -1, -2, -3, -4, -5
 PREC = {"fp32": 0, "fp64": 1}
@@ -88,15 +89,34 @@ def lib():
         for f in ("kl_decode", "kl_decode_ex", "kl_render", "kl_render_ex", "kl_render_many",
                   "kl_render_many_ex", "kl_eval", "kl_eval_ex", "kl_generators", "kl_plan", "kl_autotune"):
             getattr(L, f).restype = i
+        sz, i64, f32 = ctypes.c_size_t, ctypes.c_int64, ctypes.c_float
+        L.kl_sur_num_params.argtypes = []
+        L.kl_sur_num_params.restype = sz
+        L.kl_sur_workspace_bytes.argtypes = [i]
+        L.kl_sur_workspace_bytes.restype = sz
+        L.kl_sur_forward.argtypes = [vp, vp, vp, i, vp, vp, sz, vp]
+        L.kl_sur_loss_grad.argtypes = [vp, vp, vp, vp, i, vp, vp, vp, sz, vp]
+        L.kl_sur_adam.argtypes = [vp, vp, vp, vp, i, f32, vp]
+        L.kl_sur_train_step.argtypes = [vp, vp, vp, vp, i, f32, vp, vp, vp, i, vp, vp, sz, vp]
+        L.kl_occupancy.argtypes = [vp, u64, vp, vp]
+        L.kl_sur_predict_occupancy.argtypes = [vp, u64, vp, vp]
+        L.kl_sur_uncertainty.argtypes = [vp, i, vp, vp]
+        L.kl_iou.argtypes = [vp, vp, vp, i, vp, vp]
+        L.kl_gemm_bf16.argtypes = [i, i, i, vp, i64, i64, vp, i64, i64, vp, i64, vp, i, i, vp]
+        for f in ("kl_sur_forward", "kl_sur_loss_grad", "kl_sur_adam", "kl_sur_train_step", "kl_occupancy",
+                  "kl_sur_uncertainty", "kl_iou", "kl_gemm_bf16", "kl_sur_predict_occupancy"):
+            getattr(L, f).restype = i
         _lib = L
     return _lib
 
 
 def declared_symbols():
-    """Names of the functions include/kl.h declares."""
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(kl_\w+)\s*\(", text)))
+    """Names of the functions include/kl.h and include/kl_surrogate.h declare."""
+    names = set()
+    for h in HEADERS:
+        text = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names |= set(re.findall(r"\b(kl_\w+)\s*\(", text))
+    return sorted(names)
 
 
 def _check(rc):
@@ -249,3 +269,90 @@ def autotune(ta, tb, depth: int, window, precision="fp32", scratch: torch.Tensor
 def as_u32(image: torch.Tensor) -> np.ndarray:
     """Copy an image tensor to the host as uint32 counts."""
     return image.detach().cpu().numpy().view(np.uint32)
+
+
+# ---------------------------------------------------------------- surrogate
+def _p(t):
+    return None if t is None else t.data_ptr()
+
+
+def sur_num_params() -> int:
+    return int(lib().kl_sur_num_params())
+
+
+def sur_workspace(batch: int) -> torch.Tensor:
+    n = int(lib().kl_sur_workspace_bytes(batch))
+    return torch.empty(n, dtype=torch.uint8, device=_device())
+
+
+def as_c64(z) -> torch.Tensor:
+    """Complex values as a device (n, 2) float64 tensor (kl_c64 layout)."""
+    z = np.asarray(z, np.complex128).ravel()
+    return torch.as_tensor(np.stack([z.real, z.imag], 1)).to(_device())
+
+
+def sur_forward(params, ta, tb, workspace=None, out=None, stream=None):
+    ta_d, tb_d = (ta if isinstance(ta, torch.Tensor) else as_c64(ta)), (tb if isinstance(tb, torch.Tensor) else as_c64(tb))
+    B = ta_d.shape[0]
+    ws = workspace if workspace is not None else sur_workspace(B)
+    if out is None:
+        out = torch.empty((B, 128, 128), dtype=torch.float32, device=_device())
+    _check(lib().kl_sur_forward(_p(params), _p(ta_d), _p(tb_d), B, _p(out), _p(ws), ws.numel(), _stream(stream)))
+    return out
+
+
+def sur_loss_grad(params, ta, tb, targets, workspace=None, grad=None, stream=None):
+    ta_d, tb_d = (ta if isinstance(ta, torch.Tensor) else as_c64(ta)), (tb if isinstance(tb, torch.Tensor) else as_c64(tb))
+    B = ta_d.shape[0]
+    ws = workspace if workspace is not None else sur_workspace(B)
+    if grad is None:
+        grad = torch.empty_like(params)
+    loss = torch.empty(1, dtype=torch.float32, device=_device())
+    _check(lib().kl_sur_loss_grad(_p(params), _p(ta_d), _p(tb_d), _p(targets), B, _p(grad), _p(loss), _p(ws),
+                                  ws.numel(), _stream(stream)))
+    return loss, grad
+
+
+def sur_adam(params, grad, m, v, step, lr, stream=None):
+    _check(lib().kl_sur_adam(_p(params), _p(grad), _p(m), _p(v), int(step), float(lr), _stream(stream)))
+
+
+def sur_train_step(params, m, v, grad, step, lr, ta_d, tb_d, targets, workspace, loss, stream=None):
+    B = ta_d.shape[0]
+    _check(lib().kl_sur_train_step(_p(params), _p(m), _p(v), _p(grad), int(step), float(lr), _p(ta_d), _p(tb_d),
+                                   _p(targets), B, _p(loss), _p(workspace), workspace.numel(), _stream(stream)))
+
+
+def occupancy(counts: torch.Tensor, out=None, stream=None) -> torch.Tensor:
+    if out is None:
+        out = torch.empty(counts.shape, dtype=torch.uint8, device=counts.device)
+    _check(lib().kl_occupancy(_p(counts), counts.numel(), _p(out), _stream(stream)))
+    return out
+
+
+def sur_predict_occupancy(logits: torch.Tensor, out=None, stream=None) -> torch.Tensor:
+    if out is None:
+        out = torch.empty(logits.shape, dtype=torch.uint8, device=logits.device)
+    _check(lib().kl_sur_predict_occupancy(_p(logits), logits.numel(), _p(out), _stream(stream)))
+    return out
+
+
+def sur_uncertainty(logits: torch.Tensor, stream=None) -> torch.Tensor:
+    out = torch.empty(logits.shape[0], dtype=torch.float32, device=logits.device)
+    _check(lib().kl_sur_uncertainty(_p(logits), logits.shape[0], _p(out), _stream(stream)))
+    return out
+
+
+def iou(target_occ: torch.Tensor, logits: torch.Tensor | None = None, pred_occ: torch.Tensor | None = None,
+        stream=None) -> torch.Tensor:
+    B = target_occ.shape[0]
+    out = torch.empty(B, dtype=torch.float32, device=target_occ.device)
+    _check(lib().kl_iou(_p(logits), _p(pred_occ), _p(target_occ), B, _p(out), _stream(stream)))
+    return out
+
+
+def gemm_bf16(M, N, K, A, lda_m, lda_k, B, ldb_k, ldb_n, C, ldc, bias=None, relu=False, accumulate=False,
+              stream=None):
+    _check(lib().kl_gemm_bf16(M, N, K, _p(A), lda_m, lda_k, _p(B), ldb_k, ldb_n, _p(C), ldc, _p(bias), int(relu),
+                              int(accumulate), _stream(stream)))
+    return C
