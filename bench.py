@@ -177,7 +177,7 @@ def leg_tiling(args):
 
 
 def leg_hist(args):
-    """Depth-18 renderer kernel time per histogram strategy and split."""
+    """Depth-18 step time per engine, histogram strategy and split."""
     import numpy as np
     import torch
 
@@ -187,15 +187,12 @@ def leg_hist(args):
     W = wl.QUASIFUCHSIAN_D18
     image = kl.new_image(W.window)
     rows = []
-    ref = None
-    for r in (4, 5, 6):
+    for r in (5, 6, 7):
         for m in (2, 3, 4):
             for wpc in (16, 32):
-                for hist in ("runs", "lds"):
-                    opts = dict(tail_len=r, lane_len=m, waves_per_cu=wpc, hist_mode=hist)
+                for engine, hist in (("valu", "runs"), ("valu", "lds"), ("matrix", "runs")):
+                    opts = dict(tail_len=r, lane_len=m, waves_per_cu=wpc, hist_mode=hist, engine=engine)
                     ms = _time(lambda: kl.render(W.ta, W.tb, W.depth, W.window, image=image, **opts), 5, 1)
-                    if ref is None:
-                        ref = image.clone()
                     rows.append({**opts, "step_ms": round(ms, 4)})
     rows.sort(key=lambda x: x["step_ms"])
     return {"workload": W.name, "candidates": rows}
@@ -283,7 +280,8 @@ def main():
     achieved = FLOPS_PER_WORD * kernel_words / (kernel_avg * 1e-3) / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / FP32_PEAK_TFLOPS, 4), "traffic": _traffic_from_profile(plan),
-                "kernel": "render_kernel<float>", "kernel_ms": round(kernel_avg, 4),
+                "kernel": "render_kernel_mfma<float>" if plan["engine"] == 2 else "render_kernel<float>",
+                "kernel_ms": round(kernel_avg, 4),
                 "flops_per_word": FLOPS_PER_WORD, "words_per_launch": kernel_words}
 
     out = {
@@ -303,7 +301,7 @@ def main():
                    "ta": [W.ta.real, W.ta.imag], "tb": [W.tb.real, W.tb.imag],
                    "image": f"{W.window.width}x{W.window.height} u32 over [-1.5,1.5]^2",
                    "arithmetic": "FP64 generators, seeds and prefix products; FP32 suffix maps",
-                   "split": {k: plan[k] for k in ("prefix_len", "lane_len", "tail_len", "waves_per_cu")},
+                   "split": {k: plan[k] for k in ("prefix_len", "lane_len", "tail_len", "waves_per_cu", "engine")},
                    "dropped": int(dropped.item())},
         "roofline": roofline,
     }

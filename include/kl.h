@@ -75,6 +75,11 @@ extern "C" {
 #define KL_PREC_FP32 0  /* FP64 generators, seeds and prefix products; FP32 suffix maps */
 #define KL_PREC_FP64 1  /* every step in FP64 */
 
+/* where the FP32 renderer applies each head's map to its suffix points */
+#define KL_ENGINE_AUTO 0    /* planner's choice */
+#define KL_ENGINE_VALU 1    /* vector ALU FMAs */
+#define KL_ENGINE_MATRIX 2  /* matrix cores (v_mfma_f32_4x4x1f32); same results bit for bit */
+
 /* histogram strategy of the renderer */
 #define KL_HIST_AUTO 0    /* planner's choice */
 #define KL_HIST_RUNS 1    /* per-lane run-length counts, flushed with global atomics */
@@ -107,6 +112,7 @@ typedef struct {
     int waves_per_cu;     /* persistent grid size, 0 = planner */
     int suffix_form;      /* 0: affine suffix points unless one needs the
                              homogeneous form; 1: homogeneous form always */
+    int engine;           /* KL_ENGINE_* (the FP64 path always uses the VALU) */
     void *kernel_events[2];/* instrumentation: two hipEvent_t created by the
                              caller, or NULL; recorded on the stream right
                              before and right after the persistent renderer's
@@ -121,6 +127,7 @@ typedef struct {
     int prefix_len;    /* k = depth - r - m: letters of the FP64 prefix table */
     int hist_mode;
     int waves_per_cu;
+    int engine;
 } kl_plan_t;
 
 /* Number of reduced words of length depth, 4 * 3^(depth-1); 0 when depth

@@ -391,10 +391,17 @@ __device__ __forceinline__ double recip(double x) { return 1.0 / x; }
 
 // Value of one word: the head map applied to the suffix point y (affine
 // form), in pixel coordinates when the head carries the window fold.
+// x * y + z with the y.re products accumulated first, the order in which
+// the matrix cores (v_mfma_f32_4x4x1f32, an exact FMA per K step) form it.
+template <typename T>
+__device__ __forceinline__ cpx<T> cfma_kre(cpx<T> x, cpx<T> y, cpx<T> z) {
+    return {fma_(-x.im, y.im, fma_(x.re, y.re, z.re)), fma_(x.re, y.im, fma_(x.im, y.re, z.im))};
+}
+
+// The part of a word's value after its homogeneous numerator and
+// denominator: complex division folded into pixel units.
 template <typename T, bool ANISO>
-__device__ __forceinline__ void eval_point(const Head<T>& h, cpx<T> y, T aniso, T& px, T& py) {
-    const cpx<T> num = cfma(h.A, y, h.B);
-    const cpx<T> den = cfma(h.C, y, h.D);
+__device__ __forceinline__ void finish_point(cpx<T> num, cpx<T> den, T aniso, T& px, T& py) {
     const T n2 = fma_(den.re, den.re, den.im * den.im);
     const T rc = recip(n2);
     const T re = fma_(num.re, den.re, num.im * den.im);
@@ -402,6 +409,11 @@ __device__ __forceinline__ void eval_point(const Head<T>& h, cpx<T> y, T aniso, 
     px = re * rc;
     py = im * rc;
     if (ANISO) px = px * aniso;
+}
+
+template <typename T, bool ANISO>
+__device__ __forceinline__ void eval_point(const Head<T>& h, cpx<T> y, T aniso, T& px, T& py) {
+    finish_point<T, ANISO>(cfma_kre(h.A, y, h.B), cfma_kre(h.C, y, h.D), aniso, px, py);
 }
 
 // Same with the suffix point in homogeneous form (p : q).
@@ -456,6 +468,7 @@ struct RenderArgs {
     uint64_t head_begin;   // the heads [head_begin, head_begin + n_heads) are rendered,
     uint64_t n_heads;      // in n_units = ceil(n_heads / 64) units of 64
     uint32_t n_units;
+    uint32_t n_units16;    // ceil(n_heads / 16): units of the matrix-core renderer
 };
 
 // Run-length binning state of one lane: the open run's bin and the word
@@ -671,6 +684,123 @@ __global__ __launch_bounds__(kBlock) void render_kernel(const RenderArgs a) {
     }
 }
 
+// ------------------------------------------------------------------ matrix-core renderer
+// The map of a head applied to a suffix point is, over a block of 4 heads'
+// rows and 4 suffix points, a 4 x 4 product with K = 2 (the point's real and
+// imaginary part) plus the constant terms: v_mfma_f32_4x4x1f32 runs 16 such
+// blocks per wave instruction, two instructions per 64 words.  Lane l holds
+// row (l & 3) of head (l >> 2)'s coefficients, suffix column (l & 3), and
+// receives (num.re, num.im, den.re, den.im) of word (head l >> 2, suffix
+// l & 3).  The accumulation is an exact FMA per K step (y.re first), the
+// order eval_point() uses, so this renderer and every other kernel agree
+// bit for bit.
+typedef float mf32x4 __attribute__((ext_vector_type(4)));
+
+template <bool ANISO, bool MASKED>
+__device__ __forceinline__ void mfma_bin(const mf32x4 d, float aniso, uint32_t W, uint32_t H, uint32_t* image,
+                                         Runs& s, uint32_t& t_words, bool live, bool valid) {
+    float px, py;
+    finish_point<float, ANISO>({d[0], d[1]}, {d[2], d[3]}, aniso, px, py);
+    uint32_t key = bin_key(px, py, W, H);
+    if (MASKED && !live) key = kOutside;
+    if (!valid) key = s.cur;
+    if (key != s.cur) {
+        close_run(s, t_words, image);
+        s.cur = key;
+        s.start = t_words;
+    }
+    if (!valid) s.start += 1;   // the repeated suffix is not a word
+    ++t_words;
+}
+
+template <bool ANISO, bool MASKED>
+__device__ __forceinline__ void walk_tails_mfma(const Head<float>& h, const cpx<float>* tail, uint32_t R1,
+                                                float aniso, uint32_t W, uint32_t H, uint32_t* image, Runs& s,
+                                                uint32_t& t_words, bool live, int col) {
+    const float a0 = col == 0 ? h.A.re : col == 1 ? h.A.im : col == 2 ? h.C.re : h.C.im;
+    const float a1 = col == 0 ? -h.A.im : col == 1 ? h.A.re : col == 2 ? -h.C.im : h.C.re;
+    const mf32x4 c0 = {h.B.re, h.B.im, h.D.re, h.D.im};
+    const int ie = inv_letter(h.e);
+    const uint32_t full = R1 & ~3u, rem = R1 & 3u;
+    for (int j = 0; j < 3; ++j) {
+        const uint32_t y1 = (uint32_t)(j + (j >= ie));
+        const cpx<float>* row = tail + y1 * R1;
+#pragma unroll 4
+        for (uint32_t t0 = 0; t0 < full; t0 += 4) {
+            const cpx<float> y = row[t0 + col];
+            mf32x4 d = __builtin_amdgcn_mfma_f32_4x4x1f32(a0, y.re, c0, 0, 0, 0);
+            d = __builtin_amdgcn_mfma_f32_4x4x1f32(a1, y.im, d, 0, 0, 0);
+            mfma_bin<ANISO, MASKED>(d, aniso, W, H, image, s, t_words, live, true);
+        }
+        if (rem) {
+            // the block's last step: columns >= rem repeat its last suffix and do not count
+            const bool valid = (uint32_t)col < rem;
+            const cpx<float> y = row[full + (valid ? (uint32_t)col : rem - 1)];
+            mf32x4 d = __builtin_amdgcn_mfma_f32_4x4x1f32(a0, y.re, c0, 0, 0, 0);
+            d = __builtin_amdgcn_mfma_f32_4x4x1f32(a1, y.im, d, 0, 0, 0);
+            mfma_bin<ANISO, MASKED>(d, aniso, W, H, image, s, t_words, live, valid);
+        }
+    }
+}
+
+template <bool ANISO>
+__device__ __forceinline__ void render_units_mfma(const RenderArgs& a, const cpx<float>* tail, const m64* G, Runs& s) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int blk = lane >> 2, col = lane & 3;
+    const uint32_t waves = gridDim.x * (kBlock / kWave);
+    const uint32_t gwave = blockIdx.x * (kBlock / kWave) + (threadIdx.x / kWave);
+    const float aniso = (float)a.fold.aniso;
+    uint32_t t_words = 0;
+    for (uint32_t unit = gwave; unit < a.n_units16; unit += waves) {
+        const uint64_t local = (uint64_t)unit * 16 + blk;
+        const bool full = (uint64_t)(unit + 1) * 16 <= a.n_heads;
+        const bool live = local < a.n_heads;
+        const uint64_t hidx = a.head_begin + (live ? local : a.n_heads - 1);
+        const Head<float> h = compute_head<float>(hidx, a.sp, a.tab.prefix, a.tab.prefix_last, G, a.fold);
+        if (full) {
+            walk_tails_mfma<ANISO, false>(h, tail, a.sp.R1, aniso, a.W, a.H, a.image, s, t_words, true, col);
+        } else {
+            close_run(s, t_words, a.image);
+            s.cur = kOutside;
+            s.start = t_words;
+            walk_tails_mfma<ANISO, true>(h, tail, a.sp.R1, aniso, a.W, a.H, a.image, s, t_words, live, col);
+            if (live) close_run(s, t_words, a.image);
+            s.cur = kOutside;
+            s.start = t_words;
+        }
+    }
+    close_run(s, t_words, a.image);
+}
+
+// FP32 renderer on the matrix cores (affine suffix points); a homogeneous
+// suffix table falls back to the VALU walk in the same launch.
+template <bool ANISO>
+__global__ __launch_bounds__(kBlock) void render_kernel_mfma(const RenderArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const uint32_t n_tail = 4 * a.sp.R1;
+    const bool affine = *a.tab.tail_flags == 0;
+    const size_t entry = affine ? sizeof(c32) : 2 * sizeof(c32);
+    const size_t tbytes = (n_tail * entry + 15) & ~size_t(15);
+    m64* G = (m64*)(smem + tbytes);
+    {
+        const uint4* src = (const uint4*)(affine ? a.tab.tail : a.tail_homog);
+        uint4* dst = (uint4*)smem;
+        const uint32_t n16 = (uint32_t)(tbytes / 16);
+        for (uint32_t i = threadIdx.x; i < n16; i += blockDim.x) dst[i] = src[i];
+        if (threadIdx.x < 4) G[threadIdx.x] = a.gens.g[threadIdx.x];
+    }
+    __syncthreads();
+    Runs s = {kOutside, 0, 0};
+    if (affine) render_units_mfma<ANISO>(a, (const cpx<float>*)smem, G, s);
+    else render_units<float, false, ANISO, false>(a, smem, G, nullptr, s);
+    if (a.dropped) {
+        uint64_t drop = s.drop;
+        for (int off = kWave / 2; off > 0; off >>= 1) drop += __shfl_down(drop, off, kWave);
+        if ((threadIdx.x & (kWave - 1)) == 0 && drop)
+            atomicAdd((unsigned long long*)a.dropped, (unsigned long long)drop);
+    }
+}
+
 // ------------------------------------------------------------------ per-word kernel
 struct PerWordArgs {
     Split sp;
@@ -777,6 +907,7 @@ static hipError_t launch_render_t(const RenderJob& job, hipStream_t s) {
         a.head_begin = job.head_begin;
         a.n_heads = job.n_heads;
         a.n_units = job.n_units;
+        a.n_units16 = (uint32_t)((job.n_heads + 15) / 16);
         const size_t n_tail = 4 * (size_t)job.sp.R1;
         const bool ldsh = job.hist_mode == KL_HIST_LDS;
         const size_t lds = ((n_tail * 2 * sizeof(cpx<T>) + 15) & ~size_t(15)) + 4 * sizeof(m64) +
@@ -791,8 +922,23 @@ static hipError_t launch_render_t(const RenderJob& job, hipStream_t s) {
         const uint32_t need = (job.n_units + (kBlock / kWave) - 1) / (kBlock / kWave);
         if (grid > need) grid = need;
         if (grid < 1) grid = 1;
-        if (ldsh) hipLaunchKernelGGL((render_kernel<T, ANISO, true>), dim3(grid), dim3(kBlock), lds, s, a);
-        else hipLaunchKernelGGL((render_kernel<T, ANISO, false>), dim3(grid), dim3(kBlock), lds, s, a);
+        const bool mfma = std::is_same<T, float>::value && job.engine == KL_ENGINE_MATRIX;
+        if (mfma) {
+            const uint32_t need16 = (a.n_units16 + (kBlock / kWave) - 1) / (kBlock / kWave);
+            uint32_t g16 = std::min<uint32_t>((uint32_t)job.grid_blocks, need16);
+            if (g16 < 1) g16 = 1;
+            const size_t lds16 = ((n_tail * 2 * sizeof(c32) + 15) & ~size_t(15)) + 4 * sizeof(m64);
+            if (lds16 > 65536) {
+                hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&render_kernel_mfma<ANISO>),
+                                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds16);
+                if (e != hipSuccess) return e;
+            }
+            hipLaunchKernelGGL((render_kernel_mfma<ANISO>), dim3(g16), dim3(kBlock), lds16, s, a);
+        } else if (ldsh) {
+            hipLaunchKernelGGL((render_kernel<T, ANISO, true>), dim3(grid), dim3(kBlock), lds, s, a);
+        } else {
+            hipLaunchKernelGGL((render_kernel<T, ANISO, false>), dim3(grid), dim3(kBlock), lds, s, a);
+        }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

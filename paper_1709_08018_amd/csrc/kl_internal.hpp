@@ -131,6 +131,7 @@ struct RenderJob {
     // per-word kernel: word indices (within this depth) of the ragged ends
     uint64_t rag_first[2], rag_count[2];
     int hist_mode;
+    int engine;                // KL_ENGINE_VALU or KL_ENGINE_MATRIX (FP32 only)
     int grid_blocks;
 };
 hipError_t launch_render(const RenderJob& job, hipStream_t s);

@@ -181,6 +181,16 @@ def run(train_n=18000, calib_n=2000, test_n=2000, steps=3000, batch=128, lr=2e-3
     occ_scan, accepted, scan_s = scan(params, ta_te, tb_te, tau, depth)
     scan_iou = kl.iou(occ_true, pred_occ=occ_scan).cpu().numpy()
     ev, iou_sur, _ = evaluate(params, ta_te, tb_te, occ_true, tau)
+    # what the gate buys at other quality bars: calibrated on the calibration sets,
+    # applied to the held-out sets, timed as a full scan
+    tradeoff = []
+    for target in (0.5, 0.6, 0.7, 0.8, 0.9, IOU_TARGET):
+        tau_t = gate_threshold(unc_cal, iou_cal, target)
+        occ_t, acc_t, sec_t = scan(params, ta_te, tb_te, tau_t, depth)
+        iou_t = kl.iou(occ_true, pred_occ=occ_t).cpu().numpy()
+        tradeoff.append({"iou_target": target, "accepted": int(acc_t.sum()), "seconds": round(sec_t, 4),
+                         "speedup": round(plain_s / sec_t, 3), "min_iou": float(iou_t.min()),
+                         "sets_below_target": int((iou_t < target).sum())})
     # baselines without the trained network: untrained weights, and the mean training image
     untrained = evaluate(init_params(seed + 1), ta_te, tb_te, occ_true, tau)[0]
     mean_img = (occ_all[:train_n].float().mean(0) >= 0.5).to(torch.uint8)
@@ -198,6 +208,9 @@ def run(train_n=18000, calib_n=2000, test_n=2000, steps=3000, batch=128, lr=2e-3
                  "sets_below_target": int((scan_iou < IOU_TARGET).sum())},
         "baselines": {"untrained_mean_iou": untrained["mean_iou_surrogate"],
                       "mean_image_mean_iou": float(iou_mean.mean())},
+        "held_out_iou_quantiles": {q: float(np.quantile(iou_sur, float(q))) for q in ("0.1", "0.5", "0.9", "0.99")}
+        | {"max": float(iou_sur.max())},
+        "tradeoff": tradeoff,
     }, params
 
 

@@ -197,6 +197,29 @@ def test_lds_tile_histogram_equals_direct_runs(depth):
     assert torch.equal(c, d)
 
 
+@pytest.mark.parametrize("case", ["d14", "d18", "aniso", "tiling", "ranges"])
+def test_matrix_core_renderer_equals_valu_renderer(case):
+    """The matrix-core renderer forms every word with the same FMA sequence."""
+    kw = {}
+    if case == "d14":
+        args = (*C2, 14, WIN_C2)
+    elif case == "d18":
+        args = (*C2, 18, WIN_C2)
+    elif case == "aniso":
+        args = (*C2, 15, (-2.0, 2.0, -1.5, 1.5, 700, 300))
+    elif case == "tiling":
+        args = (*C1, 10, WIN_C1)
+        kw = dict(min_depth=1)
+    else:
+        args = (*C2, 16, WIN_C2)
+        n = kl.num_words(16)
+        kw = dict(first=12345, count=n // 3)
+    for r in (5, 6):
+        a = kl.render(*args, engine="valu", tail_len=r, **kw)
+        b = kl.render(*args, engine="matrix", tail_len=r, **kw)
+        assert torch.equal(a, b), (case, r)
+
+
 def test_run_to_run_bit_equality():
     a = kl.render(*C2, 16, WIN_C2)
     b = kl.render(*C2, 16, WIN_C2)
