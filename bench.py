@@ -12,7 +12,7 @@ Prints one JSON line: whole-job words/s (Gwords/s), the renderer kernel's
 FP32 roofline position (its average duration measured with HIP events on
 its own stream), and the CPU reference timed on this host's cores.
 
-    python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--no-cpu-baseline]
+    python bench.py [--gpus 1] [--steps 200] [--warmup 400] [--no-cpu-baseline]
 """
 from __future__ import annotations
 
@@ -28,11 +28,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "Gwords/s and VALU roofline fraction at depth 18; surrogate vs plain scan time @IoU≥0.95"
-# algorithmic FP32 work per word of the renderer: head map applied to the
-# suffix point (2 complex multiply-adds, 16 flops), |den|^2 (3), reciprocal
-# (1), numerator times conjugate denominator (6), scaling to pixels (2)
-FLOPS_PER_WORD = 28
+# algorithmic FP32 work per word of the renderer, the head's map in pole
+# form P + Q / (y + S) applied to the suffix point y: u = y + S (2 flops),
+# |u|^2 (3), reciprocal (1), per pixel coordinate one product and two FMAs (10)
+FLOPS_PER_WORD = 16
 FP32_PEAK_TFLOPS = 157.3  # MI355X FP32 vector peak (counts packed FMA)
+EVENT_EVERY = 10
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "render_kernel_quasifuchsian_d18_pmc.txt")
 KERNEL_SRC = os.path.join(ROOT, "paper_1709_08018_amd", "csrc", "kernels.hip")
 
@@ -177,7 +178,7 @@ def leg_tiling(args):
 
 
 def leg_hist(args):
-    """Depth-18 step time per engine, histogram strategy and split."""
+    """Depth-18 step time per histogram strategy and split."""
     import numpy as np
     import torch
 
@@ -190,8 +191,8 @@ def leg_hist(args):
     for r in (5, 6, 7):
         for m in (2, 3, 4):
             for wpc in (16, 32):
-                for engine, hist in (("valu", "runs"), ("valu", "lds"), ("matrix", "runs")):
-                    opts = dict(tail_len=r, lane_len=m, waves_per_cu=wpc, hist_mode=hist, engine=engine)
+                for hist in ("runs", "lds"):
+                    opts = dict(tail_len=r, lane_len=m, waves_per_cu=wpc, hist_mode=hist)
                     ms = _time(lambda: kl.render(W.ta, W.tb, W.depth, W.window, image=image, **opts), 5, 1)
                     rows.append({**opts, "step_ms": round(ms, 4)})
     rows.sort(key=lambda x: x["step_ms"])
@@ -201,8 +202,9 @@ def leg_hist(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=400,
+                    help="untimed steps first (the GPU clock ramps up over the first ~100 ms of work)")
     ap.add_argument("--workload", default="quasifuchsian_d18",
                     choices=["quasifuchsian_d18", "quasifuchsian_d22", "batch256", "fuchsian_tiling_d10", "hist"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -233,16 +235,20 @@ def main():
     image = kl.new_image(W.window)
     dropped = torch.zeros(1, dtype=torch.int64, device="cuda")
     hip = _hip()
+    # the renderer's kernel time is sampled on every EVENT_EVERY-th timed step
+    # (an event pair costs a few microseconds of queue time per step)
+    sampled = list(range(0, args.steps, EVENT_EVERY))
     events = []
-    for _ in range(2 * args.steps):
+    for _ in range(2 * len(sampled)):
         e = ctypes.c_void_p()
         if hip.hipEventCreate(ctypes.byref(e)) != 0:
             raise RuntimeError("hipEventCreate failed")
         events.append(e.value)
 
     def step(i=None):
-        ev = None if i is None else (events[2 * i], events[2 * i + 1])
-        kl.render(W.ta, W.tb, W.depth, W.window, image=image, dropped=dropped, kernel_events=ev)
+        j = None if i is None or i % EVENT_EVERY else i // EVENT_EVERY
+        ev = None if j is None else (events[2 * j], events[2 * j + 1])
+        kl.render(W.ta, W.tb, W.depth, W.window, image=image, kernel_events=ev)
 
     for _ in range(args.warmup):
         step()
@@ -254,9 +260,9 @@ def main():
     wall = time.perf_counter() - t0
     ms_per_step = wall * 1e3 / args.steps
     kernel_ms = []
-    for i in range(args.steps):
+    for j in range(len(sampled)):
         ms = ctypes.c_float()
-        hip.hipEventElapsedTime(ctypes.byref(ms), events[2 * i], events[2 * i + 1])
+        hip.hipEventElapsedTime(ctypes.byref(ms), events[2 * j], events[2 * j + 1])
         kernel_ms.append(ms.value)
     for e in events:
         hip.hipEventDestroy(e)
@@ -269,7 +275,12 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
 
+    # the timed steps do not count dropped words (kl_render does not); one
+    # more render with the counter checks that every word was counted once
+    h_timed = kl.as_u32(image).astype(np.int64)
+    kl.render(W.ta, W.tb, W.depth, W.window, image=image, dropped=dropped)
     h = kl.as_u32(image).astype(np.int64)
+    assert np.array_equal(h, h_timed), "image differs with the dropped counter on"
     total = int(h.sum()) + int(dropped.item())
     assert total == n_words, f"image + dropped = {total} != {n_words}"
 
@@ -280,7 +291,7 @@ def main():
     achieved = FLOPS_PER_WORD * kernel_words / (kernel_avg * 1e-3) / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / FP32_PEAK_TFLOPS, 4), "traffic": _traffic_from_profile(plan),
-                "kernel": "render_kernel_mfma<float>" if plan["engine"] == 2 else "render_kernel<float>",
+                "kernel": "render_kernel<float, %s, false>" % ("true" if plan["hist_mode"] == 2 else "false"),
                 "kernel_ms": round(kernel_avg, 4),
                 "flops_per_word": FLOPS_PER_WORD, "words_per_launch": kernel_words}
 
@@ -301,7 +312,7 @@ def main():
                    "ta": [W.ta.real, W.ta.imag], "tb": [W.tb.real, W.tb.imag],
                    "image": f"{W.window.width}x{W.window.height} u32 over [-1.5,1.5]^2",
                    "arithmetic": "FP64 generators, seeds and prefix products; FP32 suffix maps",
-                   "split": {k: plan[k] for k in ("prefix_len", "lane_len", "tail_len", "waves_per_cu", "engine")},
+                   "split": {k: plan[k] for k in ("prefix_len", "lane_len", "tail_len", "waves_per_cu")},
                    "dropped": int(dropped.item())},
         "roofline": roofline,
     }

@@ -75,11 +75,6 @@ extern "C" {
 #define KL_PREC_FP32 0  /* FP64 generators, seeds and prefix products; FP32 suffix maps */
 #define KL_PREC_FP64 1  /* every step in FP64 */
 
-/* where the FP32 renderer applies each head's map to its suffix points */
-#define KL_ENGINE_AUTO 0    /* planner's choice */
-#define KL_ENGINE_VALU 1    /* vector ALU FMAs */
-#define KL_ENGINE_MATRIX 2  /* matrix cores (v_mfma_f32_4x4x1f32); same results bit for bit */
-
 /* histogram strategy of the renderer */
 #define KL_HIST_AUTO 0    /* planner's choice */
 #define KL_HIST_RUNS 1    /* per-lane run-length counts, flushed with global atomics */
@@ -112,7 +107,13 @@ typedef struct {
     int waves_per_cu;     /* persistent grid size, 0 = planner */
     int suffix_form;      /* 0: affine suffix points unless one needs the
                              homogeneous form; 1: homogeneous form always */
-    int engine;           /* KL_ENGINE_* (the FP64 path always uses the VALU) */
+    int head_form;        /* how each head's map is applied to its suffix
+                             points: 0: as P + Q / (y + S) (c != 0, det 1)
+                             wherever that form fits the working precision,
+                             else as the ratio (A y + B) / (C y + D);
+                             1: the ratio for every head; 2: the ratio for
+                             heads of odd index (waves then mix both forms).
+                             1 and 2 exist to test the ratio path. */
     void *kernel_events[2];/* instrumentation: two hipEvent_t created by the
                              caller, or NULL; recorded on the stream right
                              before and right after the persistent renderer's
@@ -127,7 +128,6 @@ typedef struct {
     int prefix_len;    /* k = depth - r - m: letters of the FP64 prefix table */
     int hist_mode;
     int waves_per_cu;
-    int engine;
 } kl_plan_t;
 
 /* Number of reduced words of length depth, 4 * 3^(depth-1); 0 when depth
@@ -211,10 +211,11 @@ int kl_plan(int depth, int precision, const kl_window *window, const kl_opts *op
 
 /* kl_autotune: times the candidate splits, histogram strategies and grid
  * sizes for (ta, tb, depth, window, precision) on the current device,
- * keeps the fastest as the plan for every later render with the same
- * (depth, precision, width, height) in this process, and appends it to
- * the file named by the environment variable KL_AUTOTUNE_CACHE, if set
- * (that file is read back at library load).  scratch_image: device,
+ * keeps the fastest as the plan for every later render and evaluation
+ * with the same (depth, precision) in this process that leaves tail_len
+ * and lane_len to the planner, and appends it to the file named by the
+ * environment variable KL_AUTOTUNE_CACHE, if set (that file is read at
+ * the first plan lookup of the process).  scratch_image: device,
  * width * height uint32, overwritten.  best_out may be NULL; best_ms_out
  * (host, may be NULL) receives the winner's median time.
  * Errors: as kl_render_ex. */

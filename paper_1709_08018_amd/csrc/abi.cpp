@@ -139,13 +139,13 @@ static int check_window(const kl_window* w) {
     return KL_OK;
 }
 
-static Fold make_fold(const kl_window* w) {
+static Fold make_fold(const kl_window* w, int head_form) {
     Fold f;
+    f.head_form = head_form;
     if (!w) {
         f.s = 1.0;
         f.o = {0.0, 0.0};
         f.aniso = 1.0;
-        f.use_aniso = 0;
         return f;
     }
     const double sy = (double)w->height / (w->y1 - w->y0);
@@ -153,7 +153,6 @@ static Fold make_fold(const kl_window* w) {
     f.s = sy;
     f.o = {-w->x0 * sy, -w->y0 * sy};
     f.aniso = sx / sy;
-    f.use_aniso = (sx != sy);
     return f;
 }
 
@@ -257,7 +256,8 @@ static int build_tables(const Gens& G, const Split& sp, int precision, int force
     const size_t off_aff = off_last + round16(np);
     const size_t off_hom = off_aff + round16(nt * esz + 16);
     const size_t off_flags = off_hom + round16(2 * nt * esz + 16);
-    const size_t total = off_flags + 16;
+    const uint32_t n_flags = (uint32_t)((nt + 255) / 256);  // one per set-up block of suffix points
+    const size_t total = off_flags + round16(n_flags * sizeof(uint32_t));
     unsigned char* base = nullptr;
     hipError_t e = tmp.alloc((void**)&base, total);
     if (e != hipSuccess) return hip_fail(e, "tables");
@@ -280,17 +280,9 @@ static int build_tables(const Gens& G, const Split& sp, int precision, int force
     out->tab.prefix_last = j.last;
     out->tab.tail = j.aff;
     out->tab.tail_flags = j.flags;
+    out->tab.n_flags = n_flags;
     out->tail_homog = j.hom;
     return KL_OK;
-}
-
-// FP32 renders default to the matrix cores; FP64 always uses the VALU.
-// The matrix-core walk runs only when asked for (or picked by kl_autotune):
-// on the depth-18 workload it measures slower than the vector walk.
-static int resolve_engine(const kl_opts& o) {
-    if (o.precision == KL_PREC_FP64) return KL_ENGINE_VALU;
-    if (o.hist_mode == KL_HIST_LDS) return KL_ENGINE_VALU;
-    return o.engine == KL_ENGINE_MATRIX ? KL_ENGINE_MATRIX : KL_ENGINE_VALU;
 }
 
 static int grid_for(int waves_per_cu) {
@@ -304,10 +296,10 @@ static bool persistent_ok(const Split& sp) { return sp.k + sp.m > 0 && sp.r >= 3
 // Plans chosen by kl_autotune, keyed by (depth, precision): the split
 // decides the arithmetic of every word, so kl_eval and every render of one
 // depth and precision share it.  KL_AUTOTUNE_CACHE names a text file of
-// "depth precision tail_len lane_len waves_per_cu hist_mode engine ms" lines that
+// "depth precision tail_len lane_len waves_per_cu hist_mode ms" lines that
 // is read at the first lookup and appended to by kl_autotune.
 struct Tuned {
-    int depth, precision, r, m, wpc, hist, engine;
+    int depth, precision, r, m, wpc, hist;
     double ms;
 };
 static std::mutex g_tune_mutex;
@@ -324,9 +316,8 @@ static void load_tuned_locked() {
     char line[256];
     while (fgets(line, sizeof line, f)) {
         Tuned t;
-        if (sscanf(line, "%d %d %d %d %d %d %d %lf", &t.depth, &t.precision, &t.r, &t.m, &t.wpc, &t.hist, &t.engine,
-                   &t.ms) == 8 &&
-            t.engine >= KL_ENGINE_AUTO && t.engine <= KL_ENGINE_MATRIX && t.hist >= KL_HIST_AUTO && t.hist <= KL_HIST_LDS &&
+        if (sscanf(line, "%d %d %d %d %d %d %lf", &t.depth, &t.precision, &t.r, &t.m, &t.wpc, &t.hist, &t.ms) == 7 &&
+            t.hist >= KL_HIST_AUTO && t.hist <= KL_HIST_LDS &&
             t.depth >= 1 && t.depth <= KL_MAX_DEPTH && t.r >= 1 && t.r <= kMaxTail && t.r < t.depth && t.m >= 0 &&
             t.m <= kMaxLane && t.wpc >= 0 && t.wpc <= 32) {
             auto it = std::find_if(g_tuned.begin(), g_tuned.end(),
@@ -360,7 +351,7 @@ static void store_tuned(const Tuned& t) {
     if (path && *path) {
         FILE* f = fopen(path, "a");
         if (f) {
-            fprintf(f, "%d %d %d %d %d %d %d %.6f\n", t.depth, t.precision, t.r, t.m, t.wpc, t.hist, t.engine, t.ms);
+            fprintf(f, "%d %d %d %d %d %d %.6f\n", t.depth, t.precision, t.r, t.m, t.wpc, t.hist, t.ms);
             fclose(f);
         }
     }
@@ -376,7 +367,6 @@ static kl_opts apply_tuned(const kl_opts& o, int depth, const kl_window* w) {
         r.lane_len = t.m;
         if (r.waves_per_cu == 0) r.waves_per_cu = t.wpc;
         if (r.hist_mode == KL_HIST_AUTO) r.hist_mode = t.hist;
-        if (r.engine == KL_ENGINE_AUTO) r.engine = t.engine;
     }
     return r;
 }
@@ -409,7 +399,6 @@ static int render_depth(const Gens& G, const Fold& f, int depth, uint64_t lo, ui
     job.height = w->height;
     job.dropped = dropped;
     job.hist_mode = o.hist_mode;
-    job.engine = resolve_engine(o);
     job.grid_blocks = grid_for(o.waves_per_cu);
     uint64_t rag_lo = lo, rag_hi = hi;  // default: every word by the per-word kernel
     if (persistent_ok(sp)) {
@@ -451,7 +440,7 @@ static int check_opts_common(const kl_opts& o) {
     if (o.lane_len < 0 || o.lane_len > kMaxLane) return fail(KL_EINVAL, "lane_len %d outside 0..20", o.lane_len);
     if (o.hist_mode < KL_HIST_AUTO || o.hist_mode > KL_HIST_LDS) return fail(KL_EINVAL, "hist_mode %d", o.hist_mode);
     if (o.waves_per_cu < 0 || o.waves_per_cu > 32) return fail(KL_EINVAL, "waves_per_cu %d outside 0..32", o.waves_per_cu);
-    if (o.engine < KL_ENGINE_AUTO || o.engine > KL_ENGINE_MATRIX) return fail(KL_EINVAL, "engine %d", o.engine);
+    if (o.head_form < 0 || o.head_form > 2) return fail(KL_EINVAL, "head_form %d outside 0..2", o.head_form);
     return KL_OK;
 }
 
@@ -552,7 +541,6 @@ int kl_plan(int depth, int precision, const kl_window* window, const kl_opts* op
     plan_out->hist_mode = o.hist_mode ? o.hist_mode : KL_HIST_RUNS;
     (void)window;
     plan_out->waves_per_cu = o.waves_per_cu ? o.waves_per_cu : kDefaultWavesPerCU;
-    plan_out->engine = resolve_engine(o);
     return KL_OK;
 }
 
@@ -588,7 +576,7 @@ int kl_render_ex(kl_c64 ta, kl_c64 tb, int depth, const kl_window* window, uint3
     }
     Gens G;
     if ((rc = make_gens(ta, tb, &G))) return rc;
-    const Fold f = make_fold(window);
+    const Fold f = make_fold(window, o.head_form);
     hipStream_t s = (hipStream_t)o.stream;
     bool clear = !o.accumulate;
     uint64_t offset = 0;
@@ -639,7 +627,7 @@ int kl_eval_ex(kl_c64 ta, kl_c64 tb, int depth, const uint64_t* idx, uint64_t n,
     job.sp = sp;
     job.precision = o.precision;
     job.gens = G;
-    job.fold = make_fold(window);
+    job.fold = make_fold(window, o.head_form);
     job.tab = st.tab;
     job.tail_homog = st.tail_homog;
     job.idx = idx;
@@ -685,7 +673,7 @@ int kl_render_many_ex(int n, const kl_c64* ta, const kl_c64* tb, const int* dept
             return fail(rc, "set %d: %s", i, m.c_str());
         }
     }
-    const Fold f = make_fold(window);
+    const Fold f = make_fold(window, o.head_form);
     hipStream_t s = (hipStream_t)o.stream;
     hipError_t e;
     if (!o.accumulate) {
@@ -745,6 +733,7 @@ int kl_render_many_ex(int n, const kl_c64* ta, const kl_c64* tb, const int* dept
         D.tab.tail = d_aff + to_aff;
         D.tail_homog = d_hom + to_hom;
         D.tab.tail_flags = d_flags + j;
+        D.tab.n_flags = 1;
         D.image = images_out + bins * i;
         D.dropped = o.dropped_out ? o.dropped_out + i : nullptr;
         po += D.n_prefix;
@@ -773,6 +762,7 @@ int kl_render_many_ex(int n, const kl_c64* ta, const kl_c64* tb, const int* dept
     job.max_prefix = max_prefix;
     job.max_tail = max_tail;
     job.force_homog = o.suffix_form;
+    job.count_dropped = o.dropped_out != nullptr;
     if ((e = launch_batch_tables(job, s)) != hipSuccess) return hip_fail(e, "batch tables");
     if ((e = launch_render_batch(job, s)) != hipSuccess) return hip_fail(e, "batch render");
     // the descriptors live in host vectors: finish the copies before they go
@@ -800,23 +790,18 @@ int kl_autotune(kl_c64 ta, kl_c64 tb, int depth, const kl_window* window, int pr
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return fail(KL_EDEVICE, "hipEventCreate failed");
-    Tuned best{depth, precision, 0, 0, 0, KL_HIST_RUNS, KL_ENGINE_VALU, 1e300};
+    Tuned best{depth, precision, 0, 0, 0, KL_HIST_RUNS, 1e300};
     const int wpcs[] = {8, 16, 24, 32};
     for (int r = 3; r <= std::min(kMaxTail - 1, depth - 1); ++r) {
         for (int m = 1; m <= std::min(6, depth - r - 1); ++m) {
             if (depth - r - m > kMaxPrefix) continue;
-            for (int wpc : wpcs) for (int variant = 0; variant < 3; ++variant) {
-                // VALU with register runs, VALU with the LDS tile, matrix cores (FP32)
-                const int hist = variant == 1 ? KL_HIST_LDS : KL_HIST_RUNS;
-                const int engine = variant == 2 ? KL_ENGINE_MATRIX : KL_ENGINE_VALU;
-                if (engine == KL_ENGINE_MATRIX && precision == KL_PREC_FP64) continue;
+            for (int wpc : wpcs) for (int hist : {KL_HIST_RUNS, KL_HIST_LDS}) {
                 kl_opts o = default_opts();
                 o.precision = precision;
                 o.tail_len = r;
                 o.lane_len = m;
                 o.waves_per_cu = wpc;
                 o.hist_mode = hist;
-                o.engine = engine;
                 std::vector<float> times;
                 for (int rep = 0; rep < 4; ++rep) {
                     (void)hipEventRecord(e0, nullptr);
@@ -838,7 +823,7 @@ int kl_autotune(kl_c64 ta, kl_c64 tb, int depth, const kl_window* window, int pr
                 }
                 std::sort(times.begin(), times.end());
                 const double med = times[times.size() / 2];
-                if (med < best.ms) best = Tuned{depth, precision, r, m, wpc, hist, engine, med};
+                if (med < best.ms) best = Tuned{depth, precision, r, m, wpc, hist, med};
             }
         }
     }
@@ -853,7 +838,6 @@ int kl_autotune(kl_c64 ta, kl_c64 tb, int depth, const kl_window* window, int pr
         best_out->prefix_len = depth - best.r - best.m;
         best_out->hist_mode = best.hist;
         best_out->waves_per_cu = best.wpc;
-        best_out->engine = best.engine;
     }
     if (best_ms_out) *best_ms_out = best.ms;
     return KL_OK;

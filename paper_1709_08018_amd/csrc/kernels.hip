@@ -11,16 +11,17 @@
 // and rejects crash words).  A depth-d word is head . tail, head = k + m
 // letters, tail = r letters:
 //   * the first k letters pick an FP64 prefix product from a table built
-//     once per render (prefix_table_kernel);
+//     once per render (setup_kernel);
 //   * each lane of the renderer owns one head: it appends its m letters in
 //     FP64, folds the window map into the product, scales it by a power of
 //     two and rounds it once to the working precision;
 //   * the r tail letters run through a table of suffix points
 //     G_{y1}(...G_{y(r-1)}(fix(yr))) built right to left in the working
-//     precision (tail_table_kernel), held in LDS; the lane walks the 3^r
+//     precision (setup_kernel), held in LDS; the lane walks the 3^r
 //     tails allowed after its head's last letter in index order.
-// The value of head . tail is then one Moebius map of one point, computed
-// by eval_point() below, which every kernel shares.
+// The value of head . tail is then one Moebius map of one point, in the
+// pole form of the head (compute_head, word_value below), which every
+// kernel shares.
 #include <algorithm>
 #include <type_traits>
 
@@ -178,19 +179,6 @@ __device__ inline void prefix_entry(const Gens& g, int k, uint32_t p, m64* __res
     last[p] = (uint8_t)c;
 }
 
-__global__ __launch_bounds__(256) void prefix_table_kernel(Gens g, int k, uint32_t n,
-                                                           m64* __restrict__ table,
-                                                           uint8_t* __restrict__ last) {
-    const uint32_t p = blockIdx.x * 256 + threadIdx.x;
-    if (p < n) prefix_entry(g, k, p, table, last);
-}
-
-hipError_t launch_prefix_table(const Gens& g, int k, m64* prefix, uint8_t* last, hipStream_t s) {
-    const uint32_t n = (uint32_t)num_words(k);
-    hipLaunchKernelGGL(prefix_table_kernel, dim3((n + 255) / 256), dim3(256), 0, s, g, k, n, prefix, last);
-    return hipGetLastError();
-}
-
 // ------------------------------------------------------------------ tail table
 template <typename T>
 __device__ inline void scale_pow2(cpx<T>& u, cpx<T>& v) {
@@ -239,40 +227,21 @@ __device__ inline void tail_entry(const Gens& g, int r, uint32_t t, cpx<T>* __re
     affine[t] = y;
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void tail_table_kernel(Gens g, int r, uint32_t n,
-                                                         cpx<T>* __restrict__ affine,
-                                                         cpx<T>* __restrict__ homog,
-                                                         uint32_t* __restrict__ flags) {
-    const uint32_t t = blockIdx.x * 256 + threadIdx.x;
-    if (t < n) tail_entry<T>(g, r, t, affine, homog, flags);
-}
-
-hipError_t launch_tail_table(const Gens& g, int r, int precision, void* tail_affine, void* tail_homog,
-                             uint32_t* flags, hipStream_t s) {
-    const uint32_t n = (uint32_t)num_words(r);
-    if (precision == KL_PREC_FP64)
-        hipLaunchKernelGGL(tail_table_kernel<double>, dim3((n + 255) / 256), dim3(256), 0, s, g, r, n,
-                           (c64*)tail_affine, (c64*)tail_homog, flags);
-    else
-        hipLaunchKernelGGL(tail_table_kernel<float>, dim3((n + 255) / 256), dim3(256), 0, s, g, r, n,
-                           (c32*)tail_affine, (c32*)tail_homog, flags);
-    return hipGetLastError();
-}
-
 // ------------------------------------------------------------------ fused set-up
-// One launch that clears the image and the dropped counter, builds the
-// FP64 prefix table (blocks 1..) and the suffix table (block 0, which also
-// decides the suffix form without a separate clear of the flag).
+// One launch that clears the image and the dropped counter and builds the
+// suffix table (blocks 0 .. nb_tail-1, one point per thread) and the FP64
+// prefix table (the next blocks).  Each suffix block writes one word of the
+// form flags: nonzero when one of its points needs the homogeneous form (or
+// that form is forced), so no flag has to be cleared beforehand.
 struct SetupArgs {
     Gens g;
     int k, r;
-    uint32_t n_prefix, n_tail;
+    uint32_t n_prefix, n_tail, nb_tail;
     m64* prefix;
     uint8_t* last;
     void* aff;
     void* hom;
-    uint32_t* flags;
+    uint32_t* flags;      // nb_tail words
     int force_homog;
     uint32_t* image;      // null: leave the image alone
     uint64_t bins;
@@ -293,37 +262,71 @@ __global__ __launch_bounds__(256) void setup_kernel(const SetupArgs a) {
             for (uint64_t i = tid; i < a.bins; i += stride) a.image[i] = 0;
         }
     }
-    if (blockIdx.x == 0) {
+    if (blockIdx.x < a.nb_tail) {
+        const uint32_t t = blockIdx.x * 256 + threadIdx.x;
         uint32_t bad = 0;
-        for (uint32_t t = threadIdx.x; t < a.n_tail; t += blockDim.x) {
-            uint32_t f = 0;
-            tail_entry<T>(a.g, a.r, t, (cpx<T>*)a.aff, (cpx<T>*)a.hom, &f, false);
-            bad |= f;
-        }
+        if (t < a.n_tail) tail_entry<T>(a.g, a.r, t, (cpx<T>*)a.aff, (cpx<T>*)a.hom, &bad, false);
         bad = __syncthreads_or(bad);
         if (threadIdx.x == 0) {
-            a.flags[0] = (bad || a.force_homog) ? 1u : 0u;
-            if (a.dropped) a.dropped[0] = 0;
+            a.flags[blockIdx.x] = (bad || a.force_homog) ? 1u : 0u;
+            if (blockIdx.x == 0 && a.dropped) a.dropped[0] = 0;
         }
     } else {
-        const uint32_t p = (blockIdx.x - 1) * 256 + threadIdx.x;
+        const uint32_t p = (blockIdx.x - a.nb_tail) * 256 + threadIdx.x;
         if (p < a.n_prefix) prefix_entry(a.g, a.k, p, a.prefix, a.last);
     }
 }
 
+// Whether the suffix table is used in its affine form: no flag word is set.
+// Uniform over the block; every thread of the block must call it.
+__device__ inline bool tail_affine_block(const Tables& t) {
+    uint32_t bad = 0;
+    for (uint32_t i = threadIdx.x; i < t.n_flags; i += blockDim.x) bad |= t.tail_flags[i];
+    return !__syncthreads_or(bad);
+}
+
+// Same, uniform over the wave; every lane of the wave must call it.
+__device__ inline bool tail_affine_wave(const Tables& t) {
+    uint32_t bad = 0;
+    for (uint32_t i = threadIdx.x & (kWave - 1); i < t.n_flags; i += kWave) bad |= t.tail_flags[i];
+    return __ballot(bad != 0) == 0;
+}
+
 // ------------------------------------------------------------------ shared arithmetic
+// Map of one head, rounded once to T, in two forms.
+//
+// Pole form, for a head matrix [[a, b], [c, d]] of determinant 1 with c != 0:
+//   h(y) = P + Q / (y + S),   P = a / c,  Q = -1 / c^2,  S = d / c,
+// with the window fold F(z) = s z + o applied (P <- F(P), Q <- s Q) and the
+// x anisotropy folded into the coefficients of the real part, so that with
+// u = y + S
+//   px = Px + (ax u.re + bx u.im) / |u|^2,   py = Py + (ay u.re + by u.im) / |u|^2.
+// That is eleven operations per word: two adds, |u|^2, one reciprocal and
+// per coordinate a product and two FMAs.  Its rounding error is of the
+// order of eps (|P| + |h(y) - P|), like that of the ratio below.
+//
+// General form, for heads whose c is 0 or whose pole form leaves T's range:
+// the folded matrix (A, B) = s (a, b) + o (c, d), (C, D) = (c, d), scaled by
+// a power of two and evaluated as (A y + B) / (C y + D).
 template <typename T>
 struct Head {
-    cpx<T> A, B, C, D;  // window-folded head map, scaled by a power of two
+    cpx<T> S;
+    T Px, Py, ax, bx, ay, by;
+    cpx<T> A, B, C, D;
+    T aniso;
+    bool pole;          // the pole form is valid
     int e;              // last letter of the head, -1 for the empty head
 };
 
 template <typename T>
 __device__ __forceinline__ T conv(double x) { return (T)x; }
 
+// |x| <= lim (false for NaN)
+template <typename T>
+__device__ __forceinline__ bool bounded(T x, double lim) { return x <= (T)lim && x >= -(T)lim; }
+
 // Head map of head index hidx: prefix-table product of its first k letters
-// times its m lane letters (FP64, left to right), window folded
-// (A, B) <- s (A, B) + o (C, D), scaled by a power of two, rounded to T.
+// times its m lane letters (FP64, left to right), in both forms.
 template <typename T>
 __device__ inline Head<T> compute_head(uint64_t hidx, const Split& sp, const m64* __restrict__ prefix,
                                        const uint8_t* __restrict__ plast, const m64* G, const Fold& f) {
@@ -363,6 +366,29 @@ __device__ inline Head<T> compute_head(uint64_t hidx, const Split& sp, const m64
             e = c;
         }
     }
+    Head<T> h;
+    h.e = e;
+    h.aniso = conv<T>(f.aniso);
+    {
+        const double cn = fma_(M.c.re, M.c.re, M.c.im * M.c.im);
+        const c64 ic = {M.c.re / cn, -M.c.im / cn};
+        const c64 pm = cmul(M.a, ic), sm = cmul(M.d, ic), q = cmul(ic, ic);
+        const double Pre = fma_(f.s, pm.re, f.o.re), Pim = fma_(f.s, pm.im, f.o.im);
+        const double Qre = -(f.s * q.re), Qim = -(f.s * q.im);
+        h.S = {conv<T>(sm.re), conv<T>(sm.im)};
+        h.Px = conv<T>(f.aniso * Pre);
+        h.Py = conv<T>(Pim);
+        h.ax = conv<T>(f.aniso * Qre);
+        h.bx = conv<T>(f.aniso * Qim);
+        h.ay = conv<T>(Qim);
+        h.by = conv<T>(-Qre);
+        // bounds keep |u|^2 and the products of one word finite for affine
+        // suffix points (|y| <= 2^32)
+        h.pole = cn > 0.0 && cn <= 0x1p1000 && bounded(h.S.re, 0x1p40) && bounded(h.S.im, 0x1p40) &&
+                 bounded(h.ax, 0x1p80) && bounded(h.bx, 0x1p80) && bounded(h.ay, 0x1p80) &&
+                 bounded(h.by, 0x1p80) && bounded(h.Px, 0x1p100) && bounded(h.Py, 0x1p100);
+        if (f.head_form == 1 || (f.head_form == 2 && (hidx & 1))) h.pole = false;
+    }
     const c64 sa = {f.s * M.a.re, f.s * M.a.im};
     const c64 sb = {f.s * M.b.re, f.s * M.b.im};
     c64 A = cfma(f.o, M.c, sa);
@@ -377,57 +403,75 @@ __device__ inline Head<T> compute_head(uint64_t hidx, const Split& sp, const m64
         A.re *= sc; A.im *= sc; B.re *= sc; B.im *= sc;
         C.re *= sc; C.im *= sc; D.re *= sc; D.im *= sc;
     }
-    Head<T> h;
     h.A = {conv<T>(A.re), conv<T>(A.im)};
     h.B = {conv<T>(B.re), conv<T>(B.im)};
     h.C = {conv<T>(C.re), conv<T>(C.im)};
     h.D = {conv<T>(D.re), conv<T>(D.im)};
-    h.e = e;
     return h;
 }
 
 __device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double recip(double x) { return 1.0 / x; }
 
-// Value of one word: the head map applied to the suffix point y (affine
-// form), in pixel coordinates when the head carries the window fold.
-// x * y + z with the y.re products accumulated first, the order in which
-// the matrix cores (v_mfma_f32_4x4x1f32, an exact FMA per K step) form it.
+// Pole form at an affine suffix point y.
 template <typename T>
-__device__ __forceinline__ cpx<T> cfma_kre(cpx<T> x, cpx<T> y, cpx<T> z) {
-    return {fma_(-x.im, y.im, fma_(x.re, y.re, z.re)), fma_(x.re, y.im, fma_(x.im, y.re, z.im))};
+__device__ __forceinline__ void eval_pole(const Head<T>& h, cpx<T> y, T& px, T& py) {
+    const T ur = y.re + h.S.re, ui = y.im + h.S.im;
+    const T rc = recip(fma_(ur, ur, ui * ui));
+    px = fma_(fma_(h.ax, ur, h.bx * ui), rc, h.Px);
+    py = fma_(fma_(h.ay, ur, h.by * ui), rc, h.Py);
 }
 
-// The part of a word's value after its homogeneous numerator and
-// denominator: complex division folded into pixel units.
-template <typename T, bool ANISO>
+// Pole form at a homogeneous suffix point (p : q): with u = p + S q and
+// v = q conj(u), Q q / u = Q v / |u|^2.  (p : 0) is infinity, whose image is P.
+template <typename T>
+__device__ __forceinline__ void eval_pole_h(const Head<T>& h, cpx<T> p, cpx<T> q, T& px, T& py) {
+    const cpx<T> u = cfma(h.S, q, p);
+    const T vr = fma_(q.re, u.re, q.im * u.im);
+    const T vi = fma_(q.im, u.re, -(q.re * u.im));
+    const T rc = recip(fma_(u.re, u.re, u.im * u.im));
+    px = fma_(fma_(h.ax, vr, -(h.bx * vi)), rc, h.Px);
+    py = fma_(fma_(h.ay, vr, -(h.by * vi)), rc, h.Py);
+}
+
+// General form: num / den in pixel units.
+template <typename T>
 __device__ __forceinline__ void finish_point(cpx<T> num, cpx<T> den, T aniso, T& px, T& py) {
     const T n2 = fma_(den.re, den.re, den.im * den.im);
     const T rc = recip(n2);
     const T re = fma_(num.re, den.re, num.im * den.im);
     const T im = fma_(num.im, den.re, -(num.re * den.im));
-    px = re * rc;
+    px = (re * rc) * aniso;
     py = im * rc;
-    if (ANISO) px = px * aniso;
 }
 
-template <typename T, bool ANISO>
-__device__ __forceinline__ void eval_point(const Head<T>& h, cpx<T> y, T aniso, T& px, T& py) {
-    finish_point<T, ANISO>(cfma_kre(h.A, y, h.B), cfma_kre(h.C, y, h.D), aniso, px, py);
+template <typename T>
+__device__ __forceinline__ void eval_general(const Head<T>& h, cpx<T> y, T& px, T& py) {
+    finish_point(cfma(h.A, y, h.B), cfma(h.C, y, h.D), h.aniso, px, py);
 }
 
-// Same with the suffix point in homogeneous form (p : q).
-template <typename T, bool ANISO>
-__device__ __forceinline__ void eval_point_h(const Head<T>& h, cpx<T> p, cpx<T> q, T aniso, T& px, T& py) {
-    const cpx<T> num = cfma(h.A, p, cmul(h.B, q));
-    const cpx<T> den = cfma(h.C, p, cmul(h.D, q));
-    const T n2 = fma_(den.re, den.re, den.im * den.im);
-    const T rc = recip(n2);
-    const T re = fma_(num.re, den.re, num.im * den.im);
-    const T im = fma_(num.im, den.re, -(num.re * den.im));
-    px = re * rc;
-    py = im * rc;
-    if (ANISO) px = px * aniso;
+template <typename T>
+__device__ __forceinline__ void eval_general_h(const Head<T>& h, cpx<T> p, cpx<T> q, T& px, T& py) {
+    finish_point(cfma(h.A, p, cmul(h.B, q)), cfma(h.C, p, cmul(h.D, q)), h.aniso, px, py);
+}
+
+// Value of head . tail in pixel units, the suffix point being y (AFFINE) or
+// (y : q).  A lane uses its head's pole form when valid, else the general
+// form.  DUAL: some lane of the wave holds a head without a pole form, so
+// every lane evaluates both and keeps its own head's; without DUAL every
+// head of the wave has one.  All kernels evaluate words through these
+// functions, so they agree bit for bit on every word under the same split.
+template <typename T, bool AFFINE, bool DUAL>
+__device__ __forceinline__ void word_value(const Head<T>& h, cpx<T> y, cpx<T> q, T& px, T& py) {
+    if constexpr (AFFINE) eval_pole(h, y, px, py);
+    else eval_pole_h(h, y, q, px, py);
+    if constexpr (DUAL) {
+        T gx, gy;
+        if constexpr (AFFINE) eval_general(h, y, gx, gy);
+        else eval_general_h(h, y, q, gx, gy);
+        px = h.pole ? px : gx;
+        py = h.pole ? py : gy;
+    }
 }
 
 // Bin of pixel coordinates, or kOutside when outside [0,W) x [0,H) or NaN.
@@ -468,11 +512,12 @@ struct RenderArgs {
     uint64_t head_begin;   // the heads [head_begin, head_begin + n_heads) are rendered,
     uint64_t n_heads;      // in n_units = ceil(n_heads / 64) units of 64
     uint32_t n_units;
-    uint32_t n_units16;    // ceil(n_heads / 16): units of the matrix-core renderer
 };
 
 // Run-length binning state of one lane: the open run's bin and the word
-// count at which it began.  The word counter itself is wave-uniform.
+// count at which it began.  The word counter itself is wave-uniform.  With
+// DROP the lane also counts the words of its runs outside the image.
+template <bool DROP>
 struct Runs {
     uint32_t cur, start;
     uint64_t drop;
@@ -520,14 +565,17 @@ struct TileSink {
     }
 };
 
-template <typename Sink>
-__device__ __forceinline__ void close_run(Runs& s, uint32_t t_words, const Sink& sink) {
+// A run is closed at a later word count than it was opened at, so a run
+// inside the image always has a count of at least 1.
+template <bool DROP, typename Sink>
+__device__ __forceinline__ void close_run(Runs<DROP>& s, uint32_t t_words, const Sink& sink) {
     const uint32_t cnt = t_words - s.start;
-    if (s.cur == kOutside) s.drop += cnt;
-    else if (cnt) sink.add(s.cur, cnt);
+    if (s.cur != kOutside) sink.add(s.cur, cnt);
+    else if (DROP) s.drop += cnt;
 }
 
-__device__ __forceinline__ void close_run(Runs& s, uint32_t t_words, uint32_t* image) {
+template <bool DROP>
+__device__ __forceinline__ void close_run(Runs<DROP>& s, uint32_t t_words, uint32_t* image) {
     close_run(s, t_words, GlobalSink{image});
 }
 
@@ -536,9 +584,9 @@ __device__ __forceinline__ void close_run(Runs& s, uint32_t t_words, uint32_t* i
 // points loaded from LDS ahead of their use.
 // With MASKED, lanes whose `live` is false walk along without binning
 // (their bin stays kOutside; the caller discards their count).
-template <typename T, bool AFFINE, bool ANISO, bool MASKED = false, typename Sink = GlobalSink>
+template <typename T, bool AFFINE, bool DUAL, bool MASKED = false, typename Sink = GlobalSink, bool DROP = false>
 __device__ __forceinline__ void walk_tails_s(const Head<T>& h, const unsigned char* tail_lds, uint32_t R1,
-                                             T aniso, uint32_t W, uint32_t H, const Sink& sink, Runs& s,
+                                             uint32_t W, uint32_t H, const Sink& sink, Runs<DROP>& s,
                                              uint32_t& t_words, bool live = true) {
     const int ie = inv_letter(h.e);
     for (int j = 0; j < 3; ++j) {
@@ -550,59 +598,66 @@ __device__ __forceinline__ void walk_tails_s(const Head<T>& h, const unsigned ch
             for (uint32_t u = 0; u < 9; ++u) {
                 if constexpr (AFFINE) {
                     ya[u] = ((const cpx<T>*)tail_lds)[e0 + u];
+                    yb[u] = {T(1), T(0)};
                 } else {
                     ya[u] = ((const cpx<T>*)tail_lds)[2 * (e0 + u)];
                     yb[u] = ((const cpx<T>*)tail_lds)[2 * (e0 + u) + 1];
                 }
             }
+            // the word counter is wave-uniform: keep it in a scalar register
+            const uint32_t tw = __builtin_amdgcn_readfirstlane(t_words);
 #pragma unroll
             for (uint32_t u = 0; u < 9; ++u) {
                 T px, py;
-                if constexpr (AFFINE) eval_point<T, ANISO>(h, ya[u], aniso, px, py);
-                else eval_point_h<T, ANISO>(h, ya[u], yb[u], aniso, px, py);
+                word_value<T, AFFINE, DUAL>(h, ya[u], yb[u], px, py);
                 uint32_t key = bin_key(px, py, W, H);
                 if (MASKED && !live) key = kOutside;
                 if (key != s.cur) {
-                    close_run(s, t_words, sink);
+                    close_run(s, tw + u, sink);
                     s.cur = key;
-                    s.start = t_words;
+                    s.start = tw + u;
                 }
-                ++t_words;
             }
+            t_words = tw + 9;
         }
     }
 }
 
-template <typename T, bool AFFINE, bool ANISO, bool MASKED = false>
+template <typename T, bool AFFINE, bool DUAL, bool MASKED = false, bool DROP = false>
 __device__ __forceinline__ void walk_tails(const Head<T>& h, const unsigned char* tail_lds, uint32_t R1,
-                                           T aniso, uint32_t W, uint32_t H, uint32_t* image, Runs& s,
+                                           uint32_t W, uint32_t H, uint32_t* image, Runs<DROP>& s,
                                            uint32_t& t_words, bool live = true) {
-    walk_tails_s<T, AFFINE, ANISO, MASKED>(h, tail_lds, R1, aniso, W, H, GlobalSink{image}, s, t_words, live);
+    walk_tails_s<T, AFFINE, DUAL, MASKED>(h, tail_lds, R1, W, H, GlobalSink{image}, s, t_words, live);
 }
+
+// Whether some lane of the wave holds a head without a pole form (uniform).
+template <typename T>
+__device__ __forceinline__ bool wave_needs_dual(const Head<T>& h) { return __ballot(!h.pole) != 0; }
 
 // Bin of the head's first allowed word in some lane, wave-uniform; kOutside
 // if no lane's first word is in the window.
-template <typename T, bool AFFINE, bool ANISO>
-__device__ __forceinline__ uint32_t first_key(const Head<T>& h, const unsigned char* tail_lds, uint32_t R1, T aniso,
+template <typename T, bool AFFINE>
+__device__ __forceinline__ uint32_t first_key(const Head<T>& h, const unsigned char* tail_lds, uint32_t R1,
                                               uint32_t W, uint32_t H) {
     const uint32_t y1 = (uint32_t)(0 + (0 >= inv_letter(h.e)));
     T px, py;
-    if constexpr (AFFINE) eval_point<T, ANISO>(h, ((const cpx<T>*)tail_lds)[y1 * R1], aniso, px, py);
-    else eval_point_h<T, ANISO>(h, ((const cpx<T>*)tail_lds)[2 * y1 * R1], ((const cpx<T>*)tail_lds)[2 * y1 * R1 + 1],
-                                aniso, px, py);
+    if constexpr (AFFINE)
+        word_value<T, true, true>(h, ((const cpx<T>*)tail_lds)[y1 * R1], cpx<T>{T(1), T(0)}, px, py);
+    else
+        word_value<T, false, true>(h, ((const cpx<T>*)tail_lds)[2 * y1 * R1],
+                                   ((const cpx<T>*)tail_lds)[2 * y1 * R1 + 1], px, py);
     const uint32_t key = bin_key(px, py, W, H);
     const uint64_t m = __ballot(key != kOutside);
     if (!m) return kOutside;
     return __shfl(key, __ffsll((unsigned long long)m) - 1, kWave);
 }
 
-template <typename T, bool AFFINE, bool ANISO, bool LDSHIST>
+template <typename T, bool AFFINE, bool LDSHIST, bool DROP>
 __device__ __forceinline__ void render_units(const RenderArgs& a, const unsigned char* tail_lds, const m64* G,
-                                             uint32_t* tile, Runs& s) {
+                                             uint32_t* tile, Runs<DROP>& s) {
     const int lane = threadIdx.x & (kWave - 1);
     const uint32_t waves = gridDim.x * (kBlock / kWave);
     const uint32_t gwave = blockIdx.x * (kBlock / kWave) + (threadIdx.x / kWave);
-    const T aniso = (T)a.fold.aniso;
     uint32_t t_words = 0;
     TileSink ts{a.image, tile, a.W, a.H, -(1 << 30), -(1 << 30)};
     for (uint32_t unit = gwave; unit < a.n_units; unit += waves) {
@@ -611,9 +666,10 @@ __device__ __forceinline__ void render_units(const RenderArgs& a, const unsigned
         const bool live = local < a.n_heads;
         const uint64_t hidx = a.head_begin + (live ? local : a.n_heads - 1);
         const Head<T> h = compute_head<T>(hidx, a.sp, a.tab.prefix, a.tab.prefix_last, G, a.fold);
+        const bool dual = wave_needs_dual(h);
         if constexpr (LDSHIST) {
             // move the tile to where this unit's words start
-            const uint32_t k0 = first_key<T, AFFINE, ANISO>(h, tail_lds, a.sp.R1, aniso, a.W, a.H);
+            const uint32_t k0 = first_key<T, AFFINE>(h, tail_lds, a.sp.R1, a.W, a.H);
             ts.merge(lane);
             if (k0 != kOutside) {
                 const uint32_t row = k0 / a.W;
@@ -624,15 +680,20 @@ __device__ __forceinline__ void render_units(const RenderArgs& a, const unsigned
             }
         }
         if (full) {
-            if constexpr (LDSHIST) walk_tails_s<T, AFFINE, ANISO, false>(h, tail_lds, a.sp.R1, aniso, a.W, a.H, ts, s, t_words);
-            else walk_tails<T, AFFINE, ANISO>(h, tail_lds, a.sp.R1, aniso, a.W, a.H, a.image, s, t_words);
+            if constexpr (LDSHIST) {
+                if (dual) walk_tails_s<T, AFFINE, true>(h, tail_lds, a.sp.R1, a.W, a.H, ts, s, t_words);
+                else walk_tails_s<T, AFFINE, false>(h, tail_lds, a.sp.R1, a.W, a.H, ts, s, t_words);
+            } else {
+                if (dual) walk_tails<T, AFFINE, true>(h, tail_lds, a.sp.R1, a.W, a.H, a.image, s, t_words);
+                else walk_tails<T, AFFINE, false>(h, tail_lds, a.sp.R1, a.W, a.H, a.image, s, t_words);
+            }
         } else {
             // last, partial unit: idle lanes walk a valid head without binning
             // and their count is discarded
             close_run(s, t_words, a.image);
             s.cur = kOutside;
             s.start = t_words;
-            walk_tails<T, AFFINE, ANISO, true>(h, tail_lds, a.sp.R1, aniso, a.W, a.H, a.image, s, t_words, live);
+            walk_tails<T, AFFINE, true, true>(h, tail_lds, a.sp.R1, a.W, a.H, a.image, s, t_words, live);
             if (live) close_run(s, t_words, a.image);
             s.cur = kOutside;
             s.start = t_words;
@@ -653,11 +714,11 @@ __device__ __forceinline__ void render_units(const RenderArgs& a, const unsigned
 // its dropped words in a register until the end.
 // LDS: suffix table (sized for the homogeneous form), generators, and with
 // LDSHIST one 32 x 32 tile of uint32 bins per wave.
-template <typename T, bool ANISO, bool LDSHIST>
+template <typename T, bool LDSHIST, bool DROP>
 __global__ __launch_bounds__(kBlock) void render_kernel(const RenderArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     const uint32_t n_tail = 4 * a.sp.R1;
-    const bool affine = *a.tab.tail_flags == 0;
+    const bool affine = tail_affine_block(a.tab);
     const size_t entry = affine ? sizeof(cpx<T>) : 2 * sizeof(cpx<T>);
     const size_t tbytes = (n_tail * entry + 15) & ~size_t(15);
     const size_t tmax = (n_tail * 2 * sizeof(cpx<T>) + 15) & ~size_t(15);
@@ -673,127 +734,10 @@ __global__ __launch_bounds__(kBlock) void render_kernel(const RenderArgs a) {
             for (int i = threadIdx.x & (kWave - 1); i < kTile * kTile; i += kWave) tile[i] = 0;
     }
     __syncthreads();
-    Runs s = {kOutside, 0, 0};
-    if (affine) render_units<T, true, ANISO, LDSHIST>(a, smem, G, tile, s);
-    else render_units<T, false, ANISO, LDSHIST>(a, smem, G, tile, s);
-    if (a.dropped) {
-        uint64_t drop = s.drop;
-        for (int off = kWave / 2; off > 0; off >>= 1) drop += __shfl_down(drop, off, kWave);
-        if ((threadIdx.x & (kWave - 1)) == 0 && drop)
-            atomicAdd((unsigned long long*)a.dropped, (unsigned long long)drop);
-    }
-}
-
-// ------------------------------------------------------------------ matrix-core renderer
-// The map of a head applied to a suffix point is, over a block of 4 heads'
-// rows and 4 suffix points, a 4 x 4 product with K = 2 (the point's real and
-// imaginary part) plus the constant terms: v_mfma_f32_4x4x1f32 runs 16 such
-// blocks per wave instruction, two instructions per 64 words.  Lane l holds
-// row (l & 3) of head (l >> 2)'s coefficients, suffix column (l & 3), and
-// receives (num.re, num.im, den.re, den.im) of word (head l >> 2, suffix
-// l & 3).  The accumulation is an exact FMA per K step (y.re first), the
-// order eval_point() uses, so this renderer and every other kernel agree
-// bit for bit.
-typedef float mf32x4 __attribute__((ext_vector_type(4)));
-
-template <bool ANISO, bool MASKED>
-__device__ __forceinline__ void mfma_bin(const mf32x4 d, float aniso, uint32_t W, uint32_t H, uint32_t* image,
-                                         Runs& s, uint32_t& t_words, bool live, bool valid) {
-    float px, py;
-    finish_point<float, ANISO>({d[0], d[1]}, {d[2], d[3]}, aniso, px, py);
-    uint32_t key = bin_key(px, py, W, H);
-    if (MASKED && !live) key = kOutside;
-    if (!valid) key = s.cur;
-    if (key != s.cur) {
-        close_run(s, t_words, image);
-        s.cur = key;
-        s.start = t_words;
-    }
-    if (!valid) s.start += 1;   // the repeated suffix is not a word
-    ++t_words;
-}
-
-template <bool ANISO, bool MASKED>
-__device__ __forceinline__ void walk_tails_mfma(const Head<float>& h, const cpx<float>* tail, uint32_t R1,
-                                                float aniso, uint32_t W, uint32_t H, uint32_t* image, Runs& s,
-                                                uint32_t& t_words, bool live, int col) {
-    const float a0 = col == 0 ? h.A.re : col == 1 ? h.A.im : col == 2 ? h.C.re : h.C.im;
-    const float a1 = col == 0 ? -h.A.im : col == 1 ? h.A.re : col == 2 ? -h.C.im : h.C.re;
-    const mf32x4 c0 = {h.B.re, h.B.im, h.D.re, h.D.im};
-    const int ie = inv_letter(h.e);
-    const uint32_t full = R1 & ~3u, rem = R1 & 3u;
-    for (int j = 0; j < 3; ++j) {
-        const uint32_t y1 = (uint32_t)(j + (j >= ie));
-        const cpx<float>* row = tail + y1 * R1;
-#pragma unroll 4
-        for (uint32_t t0 = 0; t0 < full; t0 += 4) {
-            const cpx<float> y = row[t0 + col];
-            mf32x4 d = __builtin_amdgcn_mfma_f32_4x4x1f32(a0, y.re, c0, 0, 0, 0);
-            d = __builtin_amdgcn_mfma_f32_4x4x1f32(a1, y.im, d, 0, 0, 0);
-            mfma_bin<ANISO, MASKED>(d, aniso, W, H, image, s, t_words, live, true);
-        }
-        if (rem) {
-            // the block's last step: columns >= rem repeat its last suffix and do not count
-            const bool valid = (uint32_t)col < rem;
-            const cpx<float> y = row[full + (valid ? (uint32_t)col : rem - 1)];
-            mf32x4 d = __builtin_amdgcn_mfma_f32_4x4x1f32(a0, y.re, c0, 0, 0, 0);
-            d = __builtin_amdgcn_mfma_f32_4x4x1f32(a1, y.im, d, 0, 0, 0);
-            mfma_bin<ANISO, MASKED>(d, aniso, W, H, image, s, t_words, live, valid);
-        }
-    }
-}
-
-template <bool ANISO>
-__device__ __forceinline__ void render_units_mfma(const RenderArgs& a, const cpx<float>* tail, const m64* G, Runs& s) {
-    const int lane = threadIdx.x & (kWave - 1);
-    const int blk = lane >> 2, col = lane & 3;
-    const uint32_t waves = gridDim.x * (kBlock / kWave);
-    const uint32_t gwave = blockIdx.x * (kBlock / kWave) + (threadIdx.x / kWave);
-    const float aniso = (float)a.fold.aniso;
-    uint32_t t_words = 0;
-    for (uint32_t unit = gwave; unit < a.n_units16; unit += waves) {
-        const uint64_t local = (uint64_t)unit * 16 + blk;
-        const bool full = (uint64_t)(unit + 1) * 16 <= a.n_heads;
-        const bool live = local < a.n_heads;
-        const uint64_t hidx = a.head_begin + (live ? local : a.n_heads - 1);
-        const Head<float> h = compute_head<float>(hidx, a.sp, a.tab.prefix, a.tab.prefix_last, G, a.fold);
-        if (full) {
-            walk_tails_mfma<ANISO, false>(h, tail, a.sp.R1, aniso, a.W, a.H, a.image, s, t_words, true, col);
-        } else {
-            close_run(s, t_words, a.image);
-            s.cur = kOutside;
-            s.start = t_words;
-            walk_tails_mfma<ANISO, true>(h, tail, a.sp.R1, aniso, a.W, a.H, a.image, s, t_words, live, col);
-            if (live) close_run(s, t_words, a.image);
-            s.cur = kOutside;
-            s.start = t_words;
-        }
-    }
-    close_run(s, t_words, a.image);
-}
-
-// FP32 renderer on the matrix cores (affine suffix points); a homogeneous
-// suffix table falls back to the VALU walk in the same launch.
-template <bool ANISO>
-__global__ __launch_bounds__(kBlock) void render_kernel_mfma(const RenderArgs a) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    const uint32_t n_tail = 4 * a.sp.R1;
-    const bool affine = *a.tab.tail_flags == 0;
-    const size_t entry = affine ? sizeof(c32) : 2 * sizeof(c32);
-    const size_t tbytes = (n_tail * entry + 15) & ~size_t(15);
-    m64* G = (m64*)(smem + tbytes);
-    {
-        const uint4* src = (const uint4*)(affine ? a.tab.tail : a.tail_homog);
-        uint4* dst = (uint4*)smem;
-        const uint32_t n16 = (uint32_t)(tbytes / 16);
-        for (uint32_t i = threadIdx.x; i < n16; i += blockDim.x) dst[i] = src[i];
-        if (threadIdx.x < 4) G[threadIdx.x] = a.gens.g[threadIdx.x];
-    }
-    __syncthreads();
-    Runs s = {kOutside, 0, 0};
-    if (affine) render_units_mfma<ANISO>(a, (const cpx<float>*)smem, G, s);
-    else render_units<float, false, ANISO, false>(a, smem, G, nullptr, s);
-    if (a.dropped) {
+    Runs<DROP> s = {kOutside, 0, 0};
+    if (affine) render_units<T, true, LDSHIST>(a, smem, G, tile, s);
+    else render_units<T, false, LDSHIST>(a, smem, G, tile, s);
+    if (DROP) {
         uint64_t drop = s.drop;
         for (int off = kWave / 2; off > 0; off >>= 1) drop += __shfl_down(drop, off, kWave);
         if ((threadIdx.x & (kWave - 1)) == 0 && drop)
@@ -821,8 +765,8 @@ struct PerWordArgs {
 };
 
 // Value of word i of depth sp.depth, with the renderer's arithmetic.
-template <typename T, bool ANISO>
-__device__ inline void word_point(uint64_t i, const PerWordArgs& a, const m64* G, T& px, T& py) {
+template <typename T>
+__device__ inline void word_point(uint64_t i, const PerWordArgs& a, const m64* G, bool affine, T& px, T& py) {
     const Split& sp = a.sp;
     Head<T> h;
     uint64_t entry;
@@ -838,27 +782,28 @@ __device__ inline void word_point(uint64_t i, const PerWordArgs& a, const m64* G
         const int y1 = (int)j + ((int)j >= inv_letter(h.e));
         entry = (uint64_t)y1 * sp.R1 + tt;
     }
-    const T aniso = (T)a.fold.aniso;
-    if (*a.tab.tail_flags == 0) {
+    if (affine) {
         const cpx<T> y = ((const cpx<T>*)a.tab.tail)[entry];
-        eval_point<T, ANISO>(h, y, aniso, px, py);
+        if (h.pole) eval_pole(h, y, px, py);
+        else eval_general(h, y, px, py);
     } else {
         const cpx<T>* hm = (const cpx<T>*)a.tail_homog;
-        eval_point_h<T, ANISO>(h, hm[2 * entry], hm[2 * entry + 1], aniso, px, py);
+        if (h.pole) eval_pole_h(h, hm[2 * entry], hm[2 * entry + 1], px, py);
+        else eval_general_h(h, hm[2 * entry], hm[2 * entry + 1], px, py);
     }
 }
 
-template <typename T, bool ANISO>
+template <typename T>
 __global__ __launch_bounds__(256) void perword_render_kernel(const PerWordArgs a) {
     __shared__ m64 G[4];
     if (threadIdx.x < 4) G[threadIdx.x] = a.gens.g[threadIdx.x];
-    __syncthreads();
+    const bool affine = tail_affine_block(a.tab);  // also orders the G stores before their use
     const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     uint64_t drop = 0;
     if (tid < a.count0 + a.count1) {
         const uint64_t i = tid < a.count0 ? a.first0 + tid : a.first1 + (tid - a.count0);
         T px, py;
-        word_point<T, ANISO>(i, a, G, px, py);
+        word_point<T>(i, a, G, affine, px, py);
         const uint32_t key = bin_key(px, py, a.W, a.H);
         if (key == kOutside) drop = 1;
         else atomicAdd(a.image + key, 1u);
@@ -870,11 +815,11 @@ __global__ __launch_bounds__(256) void perword_render_kernel(const PerWordArgs a
     }
 }
 
-template <typename T, bool ANISO>
+template <typename T>
 __global__ __launch_bounds__(256) void eval_kernel(const PerWordArgs a) {
     __shared__ m64 G[4];
     if (threadIdx.x < 4) G[threadIdx.x] = a.gens.g[threadIdx.x];
-    __syncthreads();
+    const bool affine = tail_affine_block(a.tab);  // also orders the G stores before their use
     const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (tid >= a.n) return;
     const uint64_t i = a.idx[tid];
@@ -883,7 +828,7 @@ __global__ __launch_bounds__(256) void eval_kernel(const PerWordArgs a) {
         return;
     }
     T px, py;
-    word_point<T, ANISO>(i, a, G, px, py);
+    word_point<T>(i, a, G, affine, px, py);
     a.out[tid] = {(double)px, (double)py};
 }
 
@@ -891,7 +836,7 @@ __global__ __launch_bounds__(256) void eval_kernel(const PerWordArgs a) {
 
 namespace kl {
 
-template <typename T, bool ANISO>
+template <typename T>
 static hipError_t launch_render_t(const RenderJob& job, hipStream_t s) {
     if (job.n_units > 0) {
         RenderArgs a;
@@ -907,13 +852,14 @@ static hipError_t launch_render_t(const RenderJob& job, hipStream_t s) {
         a.head_begin = job.head_begin;
         a.n_heads = job.n_heads;
         a.n_units = job.n_units;
-        a.n_units16 = (uint32_t)((job.n_heads + 15) / 16);
         const size_t n_tail = 4 * (size_t)job.sp.R1;
         const bool ldsh = job.hist_mode == KL_HIST_LDS;
         const size_t lds = ((n_tail * 2 * sizeof(cpx<T>) + 15) & ~size_t(15)) + 4 * sizeof(m64) +
                            (ldsh ? (kBlock / kWave) * kTile * kTile * sizeof(uint32_t) : 0);
-        const void* fn = ldsh ? reinterpret_cast<const void*>(&render_kernel<T, ANISO, true>)
-                              : reinterpret_cast<const void*>(&render_kernel<T, ANISO, false>);
+        const bool drop = job.dropped != nullptr;
+        void (*kern)(RenderArgs) = ldsh ? (drop ? render_kernel<T, true, true> : render_kernel<T, true, false>)
+                                        : (drop ? render_kernel<T, false, true> : render_kernel<T, false, false>);
+        const void* fn = reinterpret_cast<const void*>(kern);
         if (lds > 65536) {
             hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
             if (e != hipSuccess) return e;
@@ -922,23 +868,7 @@ static hipError_t launch_render_t(const RenderJob& job, hipStream_t s) {
         const uint32_t need = (job.n_units + (kBlock / kWave) - 1) / (kBlock / kWave);
         if (grid > need) grid = need;
         if (grid < 1) grid = 1;
-        const bool mfma = std::is_same<T, float>::value && job.engine == KL_ENGINE_MATRIX;
-        if (mfma) {
-            const uint32_t need16 = (a.n_units16 + (kBlock / kWave) - 1) / (kBlock / kWave);
-            uint32_t g16 = std::min<uint32_t>((uint32_t)job.grid_blocks, need16);
-            if (g16 < 1) g16 = 1;
-            const size_t lds16 = ((n_tail * 2 * sizeof(c32) + 15) & ~size_t(15)) + 4 * sizeof(m64);
-            if (lds16 > 65536) {
-                hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&render_kernel_mfma<ANISO>),
-                                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds16);
-                if (e != hipSuccess) return e;
-            }
-            hipLaunchKernelGGL((render_kernel_mfma<ANISO>), dim3(g16), dim3(kBlock), lds16, s, a);
-        } else if (ldsh) {
-            hipLaunchKernelGGL((render_kernel<T, ANISO, true>), dim3(grid), dim3(kBlock), lds, s, a);
-        } else {
-            hipLaunchKernelGGL((render_kernel<T, ANISO, false>), dim3(grid), dim3(kBlock), lds, s, a);
-        }
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), lds, s, a);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -961,7 +891,7 @@ static hipError_t launch_render_t(const RenderJob& job, hipStream_t s) {
         p.dropped = job.dropped;
         const uint64_t blocks = (rag + 255) / 256;
         if (blocks > 0x7FFFFFFFull) return hipErrorInvalidValue;
-        hipLaunchKernelGGL((perword_render_kernel<T, ANISO>), dim3((unsigned)blocks), dim3(256), 0, s, p);
+        hipLaunchKernelGGL((perword_render_kernel<T>), dim3((unsigned)blocks), dim3(256), 0, s, p);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -969,13 +899,10 @@ static hipError_t launch_render_t(const RenderJob& job, hipStream_t s) {
 }
 
 hipError_t launch_render(const RenderJob& job, hipStream_t s) {
-    const bool an = job.fold.use_aniso != 0;
-    if (job.precision == KL_PREC_FP64)
-        return an ? launch_render_t<double, true>(job, s) : launch_render_t<double, false>(job, s);
-    return an ? launch_render_t<float, true>(job, s) : launch_render_t<float, false>(job, s);
+    return job.precision == KL_PREC_FP64 ? launch_render_t<double>(job, s) : launch_render_t<float>(job, s);
 }
 
-template <typename T, bool ANISO>
+template <typename T>
 static hipError_t launch_eval_t(const EvalJob& job, hipStream_t s) {
     PerWordArgs p = {};
     p.sp = job.sp;
@@ -989,16 +916,13 @@ static hipError_t launch_eval_t(const EvalJob& job, hipStream_t s) {
     p.n = job.n;
     const uint64_t blocks = (job.n + 255) / 256;
     if (blocks > 0x7FFFFFFFull) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((eval_kernel<T, ANISO>), dim3((unsigned)blocks), dim3(256), 0, s, p);
+    hipLaunchKernelGGL((eval_kernel<T>), dim3((unsigned)blocks), dim3(256), 0, s, p);
     return hipGetLastError();
 }
 
 hipError_t launch_eval(const EvalJob& job, hipStream_t s) {
     if (job.n == 0) return hipSuccess;
-    const bool an = job.fold.use_aniso != 0;
-    if (job.precision == KL_PREC_FP64)
-        return an ? launch_eval_t<double, true>(job, s) : launch_eval_t<double, false>(job, s);
-    return an ? launch_eval_t<float, true>(job, s) : launch_eval_t<float, false>(job, s);
+    return job.precision == KL_PREC_FP64 ? launch_eval_t<double>(job, s) : launch_eval_t<float>(job, s);
 }
 
 }  // namespace kl
@@ -1068,7 +992,7 @@ __device__ __forceinline__ void flush_drop(uint64_t& drop, uint64_t* dst) {
 // the set it is working on in its own LDS slice and reloads them when its
 // next unit belongs to another set.  The last unit of a set may be partial:
 // its idle lanes walk a valid head without binning.
-template <typename T, bool ANISO>
+template <typename T, bool DROP>
 __global__ __launch_bounds__(kBlock) void render_batch_kernel(const BatchArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int wid = threadIdx.x / kWave;
@@ -1077,7 +1001,6 @@ __global__ __launch_bounds__(kBlock) void render_batch_kernel(const BatchArgs a)
     m64* G = (m64*)(slice + a.lds_per_wave - 4 * sizeof(m64));
     const uint32_t waves = gridDim.x * (kBlock / kWave);
     const uint32_t gwave = blockIdx.x * (kBlock / kWave) + wid;
-    const T aniso = (T)a.fold.aniso;
 
     int cur = -1;
     bool affine = true;
@@ -1087,7 +1010,7 @@ __global__ __launch_bounds__(kBlock) void render_batch_kernel(const BatchArgs a)
     uint32_t* image = nullptr;
     uint64_t* dropped = nullptr;
     uint64_t base = 0;
-    Runs s = {kOutside, 0, 0};
+    Runs<DROP> s = {kOutside, 0, 0};
     uint32_t t_words = 0;
 
     for (uint64_t unit = gwave; unit < a.total_units; unit += waves) {
@@ -1101,7 +1024,7 @@ __global__ __launch_bounds__(kBlock) void render_batch_kernel(const BatchArgs a)
         if (lo != cur) {
             if (cur >= 0) {
                 close_run(s, t_words, image);
-                flush_drop(s.drop, dropped);
+                if (DROP) flush_drop(s.drop, dropped);
             }
             s.cur = kOutside;
             s.start = t_words;
@@ -1113,7 +1036,7 @@ __global__ __launch_bounds__(kBlock) void render_batch_kernel(const BatchArgs a)
             image = S.image;
             dropped = S.dropped;
             base = a.unit_offsets[cur];
-            affine = *S.tab.tail_flags == 0;
+            affine = tail_affine_wave(S.tab);
             const size_t bytes = (size_t)S.n_tail * (affine ? 1 : 2) * sizeof(cpx<T>);
             const uint4* src = (const uint4*)(affine ? S.tab.tail : S.tail_homog);
             wave_lds_sync();
@@ -1126,8 +1049,13 @@ __global__ __launch_bounds__(kBlock) void render_batch_kernel(const BatchArgs a)
         const bool partial = (local + 1) * kWave > sp.n_heads;
         if (!partial) {
             const Head<T> h = compute_head<T>(hidx, sp, prefix, plast, G, a.fold);
-            if (affine) walk_tails<T, true, ANISO>(h, slice, sp.R1, aniso, a.W, a.H, image, s, t_words);
-            else walk_tails<T, false, ANISO>(h, slice, sp.R1, aniso, a.W, a.H, image, s, t_words);
+            if (wave_needs_dual(h)) {
+                if (affine) walk_tails<T, true, true>(h, slice, sp.R1, a.W, a.H, image, s, t_words);
+                else walk_tails<T, false, true>(h, slice, sp.R1, a.W, a.H, image, s, t_words);
+            } else {
+                if (affine) walk_tails<T, true, false>(h, slice, sp.R1, a.W, a.H, image, s, t_words);
+                else walk_tails<T, false, false>(h, slice, sp.R1, a.W, a.H, image, s, t_words);
+            }
         } else {
             const bool live = hidx < sp.n_heads;
             if (!live) hidx = sp.n_heads - 1;
@@ -1135,8 +1063,8 @@ __global__ __launch_bounds__(kBlock) void render_batch_kernel(const BatchArgs a)
             s.cur = kOutside;
             s.start = t_words;
             const Head<T> h = compute_head<T>(hidx, sp, prefix, plast, G, a.fold);
-            if (affine) walk_tails<T, true, ANISO, true>(h, slice, sp.R1, aniso, a.W, a.H, image, s, t_words, live);
-            else walk_tails<T, false, ANISO, true>(h, slice, sp.R1, aniso, a.W, a.H, image, s, t_words, live);
+            if (affine) walk_tails<T, true, true, true>(h, slice, sp.R1, a.W, a.H, image, s, t_words, live);
+            else walk_tails<T, false, true, true>(h, slice, sp.R1, a.W, a.H, image, s, t_words, live);
             if (live) close_run(s, t_words, image);
             s.cur = kOutside;
             s.start = t_words;
@@ -1144,7 +1072,7 @@ __global__ __launch_bounds__(kBlock) void render_batch_kernel(const BatchArgs a)
     }
     if (cur >= 0) {
         close_run(s, t_words, image);
-        flush_drop(s.drop, dropped);
+        if (DROP) flush_drop(s.drop, dropped);
     }
 }
 
@@ -1163,23 +1091,16 @@ hipError_t launch_render_batch(const BatchJob& job, hipStream_t s) {
     uint64_t need = (job.total_units + (kBlock / kWave) - 1) / (kBlock / kWave);
     uint32_t grid = (uint32_t)std::min<uint64_t>(need, (uint64_t)job.grid_blocks);
     if (grid < 1) grid = 1;
-    const bool an = job.fold.use_aniso != 0;
+    const bool drop = job.count_dropped != 0;
+    void (*kern)(BatchArgs) = job.precision == KL_PREC_FP64
+                                  ? (drop ? render_batch_kernel<double, true> : render_batch_kernel<double, false>)
+                                  : (drop ? render_batch_kernel<float, true> : render_batch_kernel<float, false>);
     if (lds > 65536) {
-        const void* fn = job.precision == KL_PREC_FP64
-                             ? (an ? reinterpret_cast<const void*>(&render_batch_kernel<double, true>)
-                                   : reinterpret_cast<const void*>(&render_batch_kernel<double, false>))
-                             : (an ? reinterpret_cast<const void*>(&render_batch_kernel<float, true>)
-                                   : reinterpret_cast<const void*>(&render_batch_kernel<float, false>));
-        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    if (job.precision == KL_PREC_FP64) {
-        if (an) hipLaunchKernelGGL((render_batch_kernel<double, true>), dim3(grid), dim3(kBlock), lds, s, a);
-        else hipLaunchKernelGGL((render_batch_kernel<double, false>), dim3(grid), dim3(kBlock), lds, s, a);
-    } else {
-        if (an) hipLaunchKernelGGL((render_batch_kernel<float, true>), dim3(grid), dim3(kBlock), lds, s, a);
-        else hipLaunchKernelGGL((render_batch_kernel<float, false>), dim3(grid), dim3(kBlock), lds, s, a);
-    }
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), lds, s, a);
     return hipGetLastError();
 }
 
@@ -1203,7 +1124,8 @@ hipError_t launch_setup(const SetupJob& j, hipStream_t s) {
     a.image = j.image;
     a.bins = j.bins;
     a.dropped = j.dropped;
-    uint64_t blocks = 1 + (a.n_prefix + 255) / 256;
+    a.nb_tail = (a.n_tail + 255) / 256;
+    uint64_t blocks = a.nb_tail + (a.n_prefix + 255) / 256;
     if (a.image) blocks = std::max<uint64_t>(blocks, std::min<uint64_t>(2048, (a.bins / 4 + 255) / 256));
     if (j.precision == KL_PREC_FP64)
         hipLaunchKernelGGL(setup_kernel<double>, dim3((unsigned)blocks), dim3(256), 0, s, a);

@@ -65,8 +65,8 @@ struct Gens {
 struct Fold {
     double s;        // bins per unit along y
     c64 o;           // -(x0, y0) * s
-    double aniso;    // (bins per unit along x) / s
-    int use_aniso;
+    double aniso;    // (bins per unit along x) / s; 1 for square bins
+    int head_form;   // kl_opts.head_form
 };
 
 struct Split {
@@ -81,12 +81,13 @@ struct Tables {                // device pointers of one parameter set
     const m64* prefix;         // N_k prefix products (k >= 1)
     const uint8_t* prefix_last;// last letter of each prefix
     const void* tail;          // N_r suffix points: affine (T) or homogeneous (2 T)
-    const uint32_t* tail_flags;// bit 0: some suffix point needs the homogeneous form
+    const uint32_t* tail_flags;// n_flags words; the suffix table is used in its
+    uint32_t n_flags;          // homogeneous form when any of them is nonzero
 };
 
 // Host-side planning and validation helpers (abi.cpp)
 int set_error(int code, const char* fmt, ...);  // records kl_last_error(), returns code
-int plan_split(int depth, int precision, int r_req, int m_req, Split* out, int prefix_cap = 10);
+int plan_split(int depth, int precision, int r_req, int m_req, Split* out, int prefix_cap = 9);
 uint64_t num_words(int depth);
 uint64_t pow3_u64(int n);
 
@@ -94,12 +95,9 @@ uint64_t pow3_u64(int n);
 hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s);
 hipError_t launch_fill_u64(uint64_t* p, uint64_t n, uint64_t v, hipStream_t s);
 hipError_t launch_decode(uint64_t first, uint64_t count, int depth, uint8_t* out, hipStream_t s);
-hipError_t launch_prefix_table(const Gens& g, int k, m64* prefix, uint8_t* last, hipStream_t s);
-hipError_t launch_tail_table(const Gens& g, int r, int precision, void* tail_affine,
-                             void* tail_homog, uint32_t* flags, hipStream_t s);
 
 // Fused set-up of one render or evaluation: image / dropped clear, FP64
-// prefix table, suffix table and its form flag.
+// prefix table, suffix table and its form flags (one word per 256 points).
 struct SetupJob {
     Gens gens;
     int precision, k, r, force_homog;
@@ -131,7 +129,6 @@ struct RenderJob {
     // per-word kernel: word indices (within this depth) of the ragged ends
     uint64_t rag_first[2], rag_count[2];
     int hist_mode;
-    int engine;                // KL_ENGINE_VALU or KL_ENGINE_MATRIX (FP32 only)
     int grid_blocks;
 };
 hipError_t launch_render(const RenderJob& job, hipStream_t s);
@@ -172,6 +169,7 @@ struct BatchJob {
     uint32_t lds_per_wave;         // bytes of LDS each wave holds its set's suffix table in
     uint32_t max_prefix, max_tail; // largest n_prefix / n_tail over the sets
     int force_homog;
+    int count_dropped;             // the sets' dropped counters are set
 };
 hipError_t launch_batch_tables(const BatchJob& job, hipStream_t s);
 hipError_t launch_render_batch(const BatchJob& job, hipStream_t s);

@@ -22,7 +22,6 @@ HEADERS = [HEADER, os.path.join(os.path.dirname(PKG), "include", "kl_surrogate.h
 KL_OK, KL_EINVAL, KL_ERANGE, KL_ESINGULAR, KL_EDEVICE, KL_ENOMEM = 0, -1, -2, -3, -4, -5
 PREC = {"fp32": 0, "fp64": 1}
 HIST = {"auto": 0, "runs": 1, "lds": 2}
-ENGINE = {"auto": 0, "valu": 1, "matrix": 2}
 
 
 class KLError(RuntimeError):
@@ -45,13 +44,13 @@ class Opts(ctypes.Structure):
                 ("first_idx", ctypes.c_uint64), ("count", ctypes.c_uint64), ("accumulate", ctypes.c_int),
                 ("stream", ctypes.c_void_p), ("dropped_out", ctypes.c_void_p), ("tail_len", ctypes.c_int),
                 ("lane_len", ctypes.c_int), ("hist_mode", ctypes.c_int), ("waves_per_cu", ctypes.c_int),
-                ("suffix_form", ctypes.c_int), ("engine", ctypes.c_int), ("kernel_events", ctypes.c_void_p * 2)]
+                ("suffix_form", ctypes.c_int), ("head_form", ctypes.c_int),
+                ("kernel_events", ctypes.c_void_p * 2)]
 
 
 class Plan(ctypes.Structure):
     _fields_ = [("depth", ctypes.c_int), ("tail_len", ctypes.c_int), ("lane_len", ctypes.c_int),
-                ("prefix_len", ctypes.c_int), ("hist_mode", ctypes.c_int), ("waves_per_cu", ctypes.c_int),
-                ("engine", ctypes.c_int)]
+                ("prefix_len", ctypes.c_int), ("hist_mode", ctypes.c_int), ("waves_per_cu", ctypes.c_int)]
 
 
 _lib = None
@@ -151,7 +150,7 @@ def _stream(stream):
 
 def make_opts(*, min_depth=0, precision="fp32", first=None, count=None, accumulate=False, stream=None,
               dropped=None, tail_len=0, lane_len=0, hist_mode="auto", waves_per_cu=0, suffix_form=0,
-              engine="auto", kernel_events=None, use_stream=True) -> Opts:
+              head_form=0, kernel_events=None, use_stream=True) -> Opts:
     o = Opts()
     o.min_depth = int(min_depth)
     o.precision = PREC[precision] if isinstance(precision, str) else int(precision)
@@ -167,7 +166,7 @@ def make_opts(*, min_depth=0, precision="fp32", first=None, count=None, accumula
     o.hist_mode = HIST[hist_mode] if isinstance(hist_mode, str) else int(hist_mode)
     o.waves_per_cu = int(waves_per_cu)
     o.suffix_form = int(suffix_form)
-    o.engine = ENGINE[engine] if isinstance(engine, str) else int(engine)
+    o.head_form = int(head_form)
     if kernel_events is not None:
         o.kernel_events[0] = kernel_events[0]
         o.kernel_events[1] = kernel_events[1]

@@ -69,7 +69,7 @@ def test_plan_overrides_and_rejects():
     p = kl.plan(18, "fp32", tail_len=6, lane_len=4)
     assert (p["tail_len"], p["lane_len"], p["prefix_len"]) == (6, 4, 8)
     for bad in [dict(tail_len=9), dict(tail_len=19), dict(lane_len=21), dict(tail_len=5, lane_len=13),
-                dict(waves_per_cu=33), dict(hist_mode=7)]:
+                dict(waves_per_cu=33), dict(hist_mode=7), dict(head_form=3), dict(head_form=-1)]:
         with pytest.raises(kl.KLError) as e:
             kl.plan(18, "fp32", **bad)
         assert e.value.code == kl.KL_EINVAL

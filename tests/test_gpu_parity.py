@@ -197,27 +197,45 @@ def test_lds_tile_histogram_equals_direct_runs(depth):
     assert torch.equal(c, d)
 
 
-@pytest.mark.parametrize("case", ["d14", "d18", "aniso", "tiling", "ranges"])
-def test_matrix_core_renderer_equals_valu_renderer(case):
-    """The matrix-core renderer forms every word with the same FMA sequence."""
-    kw = {}
-    if case == "d14":
-        args = (*C2, 14, WIN_C2)
-    elif case == "d18":
-        args = (*C2, 18, WIN_C2)
-    elif case == "aniso":
-        args = (*C2, 15, (-2.0, 2.0, -1.5, 1.5, 700, 300))
-    elif case == "tiling":
-        args = (*C1, 10, WIN_C1)
-        kw = dict(min_depth=1)
-    else:
-        args = (*C2, 16, WIN_C2)
-        n = kl.num_words(16)
-        kw = dict(first=12345, count=n // 3)
-    for r in (5, 6):
-        a = kl.render(*args, engine="valu", tail_len=r, **kw)
-        b = kl.render(*args, engine="matrix", tail_len=r, **kw)
-        assert torch.equal(a, b), (case, r)
+# ---------------------------------------------------------------- head forms
+@pytest.mark.parametrize("head_form", [1, 2])
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_ratio_form_heads_render_their_own_bins(head_form, precision):
+    """Heads applied as the ratio (A y + B) / (C y + D) -- every head, or
+    every odd one so that waves mix both forms -- draw exactly the bins
+    kl_eval gives their words under the same head form, with either
+    histogram strategy and in the batched renderer."""
+    depth, win = 13, (-1.7, 1.3, -1.4, 1.6, 640, 480)
+    n = kl.num_words(depth)
+    dropped = torch.zeros(1, dtype=torch.int64, device="cuda")
+    img = kl.render(*C2, depth, win, precision=precision, dropped=dropped, head_form=head_form)
+    p = kl.eval_values(*C2, depth, np.arange(n, dtype=np.uint64), precision=precision, window=win,
+                       head_form=head_form).cpu().numpy()
+    ref, drop = _bins_from_pixels(p[:, 0], p[:, 1], win)
+    np.testing.assert_array_equal(kl.as_u32(img).astype(np.int64), ref)
+    assert int(dropped.item()) == drop
+    lds = kl.render(*C2, depth, win, precision=precision, head_form=head_form, hist_mode="lds")
+    assert torch.equal(lds, img)
+    many = kl.render_many([C2[0]] * 2, [C2[1]] * 2, [depth, depth], win, precision=precision,
+                          head_form=head_form)
+    assert torch.equal(many[0], img) and torch.equal(many[1], img)
+
+
+@pytest.mark.parametrize("head_form", [0, 1, 2])
+def test_head_forms_meet_the_fp32_bar(head_form):
+    """Pole form and ratio form both stay within 0.25 pixel of the FP64
+    reference per word, and their images within the near-edge bound."""
+    depth, win = 18, WIN_C2
+    idx = wl.sample_indices(kl.num_words(depth), 100000, seed=3)
+    p = kl.eval_values(*C2, depth, idx, precision="fp32", window=win, head_form=head_form).cpu().numpy()
+    fx, fy = _ref_pixels(O.eval_values(*C2, depth, idx), win)
+    err = np.hypot(p[:, 0] - fx, p[:, 1] - fy)
+    inside = (fx > -1) & (fx < win[4] + 1) & (fy > -1) & (fy < win[5] + 1)
+    print(f"head_form {head_form}: FP32 pixel error max {err[inside].max():.3e} mean {err[inside].mean():.3e}")
+    assert err[inside].max() <= 0.25
+    img = kl.as_u32(kl.render(*C2, 12, win, precision="fp32", head_form=head_form)).astype(np.int64)
+    ref, _, near = O.render(*C2, 12, win, edge_tol=0.25, nthreads=8)
+    assert int(np.abs(img - ref.astype(np.int64)).sum()) <= 2 * near
 
 
 def test_run_to_run_bit_equality():
