@@ -177,6 +177,19 @@ def leg_tiling(args):
     return out
 
 
+def leg_surrogate(args):
+    """Learned occupancy surrogate at depth 14, 128^2 over [-2,2]^2: 20,000
+    training sets (PCG64 seed 1; the last 2,000 calibrate the gate) and 2,000
+    held-out sets (seed 2).  Times the held-out scan -- surrogate forward,
+    gate, fallback renders of the rejected sets -- against the plain
+    renderer, at the IoU target 0.95 and at lower targets."""
+    from paper_1709_08018_amd import surrogate as S
+
+    res, _ = S.run(train_n=18000, calib_n=2000, test_n=2000, steps=12000, batch=128, lr=2e-3, log_every=1000)
+    res["metric"] = "surrogate vs plain scan time @IoU>=0.95"
+    return res
+
+
 def leg_hist(args):
     """Depth-18 step time per histogram strategy and split."""
     import numpy as np
@@ -206,7 +219,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=400,
                     help="untimed steps first (the GPU clock ramps up over the first ~100 ms of work)")
     ap.add_argument("--workload", default="quasifuchsian_d18",
-                    choices=["quasifuchsian_d18", "quasifuchsian_d22", "batch256", "fuchsian_tiling_d10", "hist"])
+                    choices=["quasifuchsian_d18", "quasifuchsian_d22", "batch256", "fuchsian_tiling_d10", "surrogate",
+                             "hist"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="after the steps, copy 256 MiB device to device twice (a kernel of known HBM "
@@ -225,7 +239,7 @@ def main():
 
     torch.cuda.set_device(0)
     legs = {"quasifuchsian_d22": leg_d22, "batch256": leg_batch, "fuchsian_tiling_d10": leg_tiling,
-            "hist": leg_hist}
+            "surrogate": leg_surrogate, "hist": leg_hist}
     if args.workload in legs:
         print(json.dumps(legs[args.workload](args)), flush=True)
         return

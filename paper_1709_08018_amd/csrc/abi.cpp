@@ -741,7 +741,7 @@ int kl_render_many_ex(int n, const kl_c64* ta, const kl_c64* tb, const int* dept
         to_hom += ((2 * D.n_tail * esz + 15) / 16) * 16;
         max_bytes = std::max<uint32_t>(max_bytes, (uint32_t)(((2 * D.n_tail * esz + 15) / 16) * 16));
         h_off[j] = units;
-        units += (splits[i].n_heads + kWave - 1) / kWave;
+        units += (splits[i].n_heads + kBlock - 1) / kBlock;  // block units: one head per thread
     }
     h_off[nb] = units;
     if ((e = hipMemcpyAsync(d_sets, h_sets.data(), nb * sizeof(SetDesc), hipMemcpyHostToDevice, s)) != hipSuccess ||
@@ -758,7 +758,7 @@ int kl_render_many_ex(int n, const kl_c64* ta, const kl_c64* tb, const int* dept
     job.width = window->width;
     job.height = window->height;
     job.grid_blocks = grid_for(o.waves_per_cu ? o.waves_per_cu : per[batch[0]].waves_per_cu);
-    job.lds_per_wave = max_bytes + 4 * sizeof(m64);
+    job.table_bytes = max_bytes;
     job.max_prefix = max_prefix;
     job.max_tail = max_tail;
     job.force_homog = o.suffix_form;

@@ -966,19 +966,13 @@ hipError_t launch_batch_tables(const BatchJob& job, hipStream_t s) {
 
 struct BatchArgs {
     const SetDesc* sets;
-    const uint64_t* unit_offsets;
+    const uint64_t* unit_offsets;  // n_sets + 1 prefix sums of block units
     int n_sets;
     uint64_t total_units;
     Fold fold;
     uint32_t W, H;
-    uint32_t lds_per_wave;
+    uint32_t table_bytes;          // LDS bytes of the largest suffix table (homogeneous form)
 };
-
-__device__ __forceinline__ void wave_lds_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 __device__ __forceinline__ void flush_drop(uint64_t& drop, uint64_t* dst) {
     uint64_t d = drop;
@@ -987,20 +981,19 @@ __device__ __forceinline__ void flush_drop(uint64_t& drop, uint64_t* dst) {
     drop = 0;
 }
 
-// Units of 64 heads from every set form one queue dealt round robin over
-// the persistent waves; each wave keeps the suffix table and generators of
-// the set it is working on in its own LDS slice and reloads them when its
-// next unit belongs to another set.  The last unit of a set may be partial:
-// its idle lanes walk a valid head without binning.
+// Block units of kBlock heads (64 per wave) from every set form one queue
+// dealt round robin over the persistent blocks.  A block keeps the suffix
+// table and generators of the set it is working on in LDS, shared by its
+// waves, and reloads them between two barriers when its next unit belongs
+// to another set.  The last unit of a set may be partial: waves past the
+// set's last head skip it, and the idle lanes of a partly filled wave walk a
+// valid head without binning.
 template <typename T, bool DROP>
 __global__ __launch_bounds__(kBlock) void render_batch_kernel(const BatchArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
-    const int wid = threadIdx.x / kWave;
+    m64* G = (m64*)(smem + a.table_bytes);
+    const uint64_t wid = threadIdx.x / kWave;
     const int lane = threadIdx.x & (kWave - 1);
-    unsigned char* slice = smem + (size_t)wid * a.lds_per_wave;
-    m64* G = (m64*)(slice + a.lds_per_wave - 4 * sizeof(m64));
-    const uint32_t waves = gridDim.x * (kBlock / kWave);
-    const uint32_t gwave = blockIdx.x * (kBlock / kWave) + wid;
 
     int cur = -1;
     bool affine = true;
@@ -1013,8 +1006,8 @@ __global__ __launch_bounds__(kBlock) void render_batch_kernel(const BatchArgs a)
     Runs<DROP> s = {kOutside, 0, 0};
     uint32_t t_words = 0;
 
-    for (uint64_t unit = gwave; unit < a.total_units; unit += waves) {
-        // set of this unit: the last set whose first unit is <= unit
+    for (uint64_t unit = blockIdx.x; unit < a.total_units; unit += gridDim.x) {
+        // set of this unit: the last set whose first unit is <= unit (uniform over the block)
         int lo = 0, hi = a.n_sets - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
@@ -1036,25 +1029,26 @@ __global__ __launch_bounds__(kBlock) void render_batch_kernel(const BatchArgs a)
             image = S.image;
             dropped = S.dropped;
             base = a.unit_offsets[cur];
-            affine = tail_affine_wave(S.tab);
+            __syncthreads();  // every wave is done with the previous set's table
+            affine = tail_affine_block(S.tab);
             const size_t bytes = (size_t)S.n_tail * (affine ? 1 : 2) * sizeof(cpx<T>);
             const uint4* src = (const uint4*)(affine ? S.tab.tail : S.tail_homog);
-            wave_lds_sync();
-            for (uint32_t i = lane; i < (uint32_t)((bytes + 15) / 16); i += kWave) ((uint4*)slice)[i] = src[i];
-            if (lane < 4) G[lane] = S.gens.g[lane];
-            wave_lds_sync();
+            for (uint32_t i = threadIdx.x; i < (uint32_t)((bytes + 15) / 16); i += kBlock) ((uint4*)smem)[i] = src[i];
+            if (threadIdx.x < 4) G[threadIdx.x] = S.gens.g[threadIdx.x];
+            __syncthreads();
         }
-        const uint64_t local = unit - base;
-        uint64_t hidx = local * kWave + lane;
-        const bool partial = (local + 1) * kWave > sp.n_heads;
+        const uint64_t wunit = (unit - base) * (kBlock / kWave) + wid;  // this wave's 64 heads of the set
+        if (wunit * kWave >= sp.n_heads) continue;
+        uint64_t hidx = wunit * kWave + lane;
+        const bool partial = (wunit + 1) * kWave > sp.n_heads;
         if (!partial) {
             const Head<T> h = compute_head<T>(hidx, sp, prefix, plast, G, a.fold);
             if (wave_needs_dual(h)) {
-                if (affine) walk_tails<T, true, true>(h, slice, sp.R1, a.W, a.H, image, s, t_words);
-                else walk_tails<T, false, true>(h, slice, sp.R1, a.W, a.H, image, s, t_words);
+                if (affine) walk_tails<T, true, true>(h, smem, sp.R1, a.W, a.H, image, s, t_words);
+                else walk_tails<T, false, true>(h, smem, sp.R1, a.W, a.H, image, s, t_words);
             } else {
-                if (affine) walk_tails<T, true, false>(h, slice, sp.R1, a.W, a.H, image, s, t_words);
-                else walk_tails<T, false, false>(h, slice, sp.R1, a.W, a.H, image, s, t_words);
+                if (affine) walk_tails<T, true, false>(h, smem, sp.R1, a.W, a.H, image, s, t_words);
+                else walk_tails<T, false, false>(h, smem, sp.R1, a.W, a.H, image, s, t_words);
             }
         } else {
             const bool live = hidx < sp.n_heads;
@@ -1063,8 +1057,8 @@ __global__ __launch_bounds__(kBlock) void render_batch_kernel(const BatchArgs a)
             s.cur = kOutside;
             s.start = t_words;
             const Head<T> h = compute_head<T>(hidx, sp, prefix, plast, G, a.fold);
-            if (affine) walk_tails<T, true, true, true>(h, slice, sp.R1, a.W, a.H, image, s, t_words, live);
-            else walk_tails<T, false, true, true>(h, slice, sp.R1, a.W, a.H, image, s, t_words, live);
+            if (affine) walk_tails<T, true, true, true>(h, smem, sp.R1, a.W, a.H, image, s, t_words, live);
+            else walk_tails<T, false, true, true>(h, smem, sp.R1, a.W, a.H, image, s, t_words, live);
             if (live) close_run(s, t_words, image);
             s.cur = kOutside;
             s.start = t_words;
@@ -1086,10 +1080,9 @@ hipError_t launch_render_batch(const BatchJob& job, hipStream_t s) {
     a.fold = job.fold;
     a.W = job.width;
     a.H = job.height;
-    a.lds_per_wave = job.lds_per_wave;
-    const size_t lds = (size_t)job.lds_per_wave * (kBlock / kWave);
-    uint64_t need = (job.total_units + (kBlock / kWave) - 1) / (kBlock / kWave);
-    uint32_t grid = (uint32_t)std::min<uint64_t>(need, (uint64_t)job.grid_blocks);
+    a.table_bytes = job.table_bytes;
+    const size_t lds = (size_t)job.table_bytes + 4 * sizeof(m64);
+    uint32_t grid = (uint32_t)std::min<uint64_t>(job.total_units, (uint64_t)job.grid_blocks);
     if (grid < 1) grid = 1;
     const bool drop = job.count_dropped != 0;
     void (*kern)(BatchArgs) = job.precision == KL_PREC_FP64

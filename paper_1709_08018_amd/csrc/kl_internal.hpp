@@ -159,14 +159,14 @@ struct SetDesc {
 };
 struct BatchJob {
     const SetDesc* sets;           // device, n_sets entries
-    const uint64_t* unit_offsets;  // device, n_sets + 1 prefix sums of units (64 heads each)
+    const uint64_t* unit_offsets;  // device, n_sets + 1 prefix sums of block units (kBlock heads each)
     int n_sets;
     uint64_t total_units;
     int precision;
     Fold fold;
     uint32_t width, height;
     int grid_blocks;
-    uint32_t lds_per_wave;         // bytes of LDS each wave holds its set's suffix table in
+    uint32_t table_bytes;          // LDS bytes of the largest suffix table (homogeneous form)
     uint32_t max_prefix, max_tail; // largest n_prefix / n_tail over the sets
     int force_homog;
     int count_dropped;             // the sets' dropped counters are set

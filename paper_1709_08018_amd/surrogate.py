@@ -13,6 +13,7 @@ from __future__ import annotations
 import argparse
 import json
 import math
+import sys
 import time
 
 import numpy as np
@@ -99,7 +100,7 @@ def train(ta, tb, occ: torch.Tensor, steps: int, batch: int = 128, lr: float = 2
                           occ[s0:s0 + batch], ws, loss)
         if log_every and (step % log_every == 0 or step == steps):
             hist.append((step, float(loss.item())))
-            print(f"[surrogate] step {step}/{steps} loss {hist[-1][1]:.5f}", flush=True)
+            print(f"[surrogate] step {step}/{steps} loss {hist[-1][1]:.5f}", file=sys.stderr, flush=True)
     return params, hist
 
 
@@ -162,7 +163,7 @@ def run(train_n=18000, calib_n=2000, test_n=2000, steps=3000, batch=128, lr=2e-3
     occ_all = render_occupancy(ta_all, tb_all, depth)
     torch.cuda.synchronize()
     data_s = time.perf_counter() - t
-    print(f"[surrogate] rendered {train_n + calib_n} training sets in {data_s:.1f} s", flush=True)
+    print(f"[surrogate] rendered {train_n + calib_n} training sets in {data_s:.1f} s", file=sys.stderr, flush=True)
     t = time.perf_counter()
     params, hist = train(ta_all[:train_n], tb_all[:train_n], occ_all[:train_n], steps, batch, lr, seed,
                          log_every=log_every)
