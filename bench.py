@@ -190,6 +190,23 @@ def leg_surrogate(args):
     return res
 
 
+def leg_calib(args):
+    """Instruction-throughput calibration of the VALU roofline (libkl_calib.so):
+    SIMD cycles per wave64 instruction of each class the renderer's word loop
+    issues, at the device's reported clock."""
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_1709_08018_amd", "libkl_calib.so"))
+    ms = (ctypes.c_double * 9)()
+    cyc = (ctypes.c_double * 9)()
+    ghz = ctypes.c_double()
+    if lib.kl_calib_valu(ms, cyc, ctypes.byref(ghz)) != 0:
+        raise RuntimeError("kl_calib_valu failed")
+    names = ["v_fma_f32", "v_mul_f32", "v_add_f32", "v_add_u32", "v_rcp_f32", "v_mad_u32_u24",
+             "v_cvt_flr_i32_f32+v_add_f32", "v_cmp_gt_u32+v_cndmask_b32", "v_fma_f64"]
+    return {"workload": "calib", "clock_ghz": ghz.value,
+            "cycles_per_wave64_group": {n: round(c, 3) for n, c in zip(names, cyc)},
+            "ms": {n: round(m, 4) for n, m in zip(names, ms)}}
+
+
 def leg_hist(args):
     """Depth-18 step time per histogram strategy and split."""
     import numpy as np
@@ -220,7 +237,7 @@ def main():
                     help="untimed steps first (the GPU clock ramps up over the first ~100 ms of work)")
     ap.add_argument("--workload", default="quasifuchsian_d18",
                     choices=["quasifuchsian_d18", "quasifuchsian_d22", "batch256", "fuchsian_tiling_d10", "surrogate",
-                             "hist"])
+                             "hist", "calib"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="after the steps, copy 256 MiB device to device twice (a kernel of known HBM "
@@ -239,7 +256,7 @@ def main():
 
     torch.cuda.set_device(0)
     legs = {"quasifuchsian_d22": leg_d22, "batch256": leg_batch, "fuchsian_tiling_d10": leg_tiling,
-            "surrogate": leg_surrogate, "hist": leg_hist}
+            "surrogate": leg_surrogate, "hist": leg_hist, "calib": leg_calib}
     if args.workload in legs:
         print(json.dumps(legs[args.workload](args)), flush=True)
         return

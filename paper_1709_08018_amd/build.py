@@ -1,6 +1,7 @@
-"""Build ``libkl.so`` (HIP, gfx950) in the package directory.
+"""Build ``libkl.so`` (HIP, gfx950) and the instruction-rate calibration
+library ``libkl_calib.so`` in the package directory.
 
-The library is compiled in place so that it travels with the source tree:
+The libraries are compiled in place so that they travel with the source tree:
     python -m paper_1709_08018_amd.build
 """
 from __future__ import annotations
@@ -14,6 +15,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libkl.so")
 SOURCES = [os.path.join(CSRC, f) for f in ("kernels.hip", "surrogate.hip", "abi.cpp")]
+CALIB_LIB = os.path.join(PKG, "libkl_calib.so")
+CALIB_SOURCES = [os.path.join(CSRC, "calib.hip")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
@@ -27,13 +30,17 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
-    srcs = [s for s in SOURCES if os.path.exists(s)]
-    cmd = [HIPCC] + FLAGS + ["-o", LIB + ".tmp", "-x", "hip"] + srcs
+def _link(lib: str, sources: list[str], verbose: bool) -> None:
+    cmd = [HIPCC] + FLAGS + ["-o", lib + ".tmp", "-x", "hip"] + sources
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(LIB + ".tmp", LIB)
+    os.replace(lib + ".tmp", lib)
+
+
+def build(verbose: bool = False) -> str:
+    _link(LIB, SOURCES, verbose)
+    _link(CALIB_LIB, CALIB_SOURCES, verbose)
     return LIB
 
 

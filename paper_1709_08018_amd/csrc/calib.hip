@@ -1,0 +1,117 @@
+// calib.hip -- libkl_calib.so: instruction-throughput microbenchmarks that
+// calibrate the renderer's VALU roofline on gfx950.  Not part of the
+// renderer's ABI; bench.py --workload calib calls it.
+//
+// Each kernel runs 8 independent dependency chains of one instruction class
+// per lane for a fixed trip count on 32 waves per CU, and stores one value
+// per thread at the end.  From the event-timed duration and the device
+// clock follows the cost of one wave64 instruction group per SIMD, in cycles:
+//   cycles = ms * clock * (CUs * 4 SIMDs) / (waves * groups per wave).
+// The integer and compare classes are written as single ALU instructions so
+// that the compiler cannot fold their chains.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace {
+
+constexpr int kIters = 4096;
+constexpr int kChains = 8;
+constexpr int kClasses = 9;
+
+template <int OP>
+__global__ __launch_bounds__(256) void rate_kernel(float* out, float s, float t, unsigned su) {
+    float a[kChains];
+    unsigned u[kChains];
+    double d[kChains];
+    for (int i = 0; i < kChains; ++i) {
+        a[i] = threadIdx.x * 1e-3f + i;
+        u[i] = threadIdx.x + i;
+        d[i] = threadIdx.x * 1e-3 + i;
+    }
+    for (int it = 0; it < kIters; ++it) {
+#pragma unroll
+        for (int i = 0; i < kChains; ++i) {
+            if constexpr (OP == 0) a[i] = __builtin_fmaf(a[i], s, t);
+            if constexpr (OP == 1) a[i] = a[i] * s;
+            if constexpr (OP == 2) a[i] = a[i] + s;
+            if constexpr (OP == 3) asm volatile("v_add_u32 %0, %0, %1" : "+v"(u[i]) : "s"(su));
+            if constexpr (OP == 4) a[i] = __builtin_amdgcn_rcpf(a[i]);
+            if constexpr (OP == 5) asm volatile("v_mad_u32_u24 %0, %0, %1, 7" : "+v"(u[i]) : "s"(su));
+            if constexpr (OP == 6) {
+                int r;
+                asm volatile("v_cvt_flr_i32_f32 %0, %1" : "=v"(r) : "v"(a[i]));
+                a[i] = __int_as_float(r) + s;
+            }
+            if constexpr (OP == 7)
+                asm volatile("v_cmp_gt_u32 vcc, %1, %0\n\tv_cndmask_b32 %0, %1, %0, vcc" : "+v"(u[i]) : "v"(su) : "vcc");
+            if constexpr (OP == 8) d[i] = __builtin_fma(d[i], (double)s, (double)t);
+        }
+    }
+    float acc = 0;
+    for (int i = 0; i < kChains; ++i) acc += a[i] + (float)u[i] + (float)d[i];
+    out[blockIdx.x * 256 + threadIdx.x] = acc;
+}
+
+template <int OP>
+hipError_t time_class(float* out, int blocks, hipEvent_t e0, hipEvent_t e1, float* ms) {
+    for (int w = 0; w < 3; ++w) hipLaunchKernelGGL(rate_kernel<OP>, dim3(blocks), dim3(256), 0, 0, out, 1.0001f, 0.5f, 123u);
+    hipError_t e = hipEventRecord(e0, nullptr);
+    for (int w = 0; w < 5; ++w) hipLaunchKernelGGL(rate_kernel<OP>, dim3(blocks), dim3(256), 0, 0, out, 1.0001f, 0.5f, 123u);
+    if (e == hipSuccess) e = hipEventRecord(e1, nullptr);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    if (e == hipSuccess) e = hipEventElapsedTime(ms, e0, e1);
+    *ms /= 5;
+    return e == hipSuccess ? hipGetLastError() : e;
+}
+
+}  // namespace
+
+extern "C" {
+
+// Instruction classes, in the order of the outputs:
+//   0 v_fma_f32, 1 v_mul_f32, 2 v_add_f32, 3 v_add_u32, 4 v_rcp_f32,
+//   5 v_mad_u32_u24, 6 v_cvt_flr_i32_f32 + v_add_f32 (a group of two),
+//   7 v_cmp_gt_u32 + v_cndmask_b32 (a group of two), 8 v_fma_f64.
+// ms_out[9]: kernel milliseconds; cycles_out[9]: SIMD cycles per wave64
+// group at clock_ghz_out (the device's reported maximum clock).  Host
+// pointers.  Returns 0, or -4 on a HIP error.
+int kl_calib_valu(double* ms_out, double* cycles_out, double* clock_ghz_out) {
+    int dev = 0, cus = 0, khz = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipDeviceGetAttribute(&khz, hipDeviceAttributeClockRate, dev) != hipSuccess)
+        return -4;
+    const int blocks = cus * 8;  // 32 waves per CU
+    float* out = nullptr;
+    if (hipMalloc(&out, (size_t)blocks * 256 * sizeof(float)) != hipSuccess) return -4;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        (void)hipFree(out);
+        return -4;
+    }
+    float ms[kClasses] = {};
+    hipError_t e = time_class<0>(out, blocks, e0, e1, &ms[0]);
+    if (e == hipSuccess) e = time_class<1>(out, blocks, e0, e1, &ms[1]);
+    if (e == hipSuccess) e = time_class<2>(out, blocks, e0, e1, &ms[2]);
+    if (e == hipSuccess) e = time_class<3>(out, blocks, e0, e1, &ms[3]);
+    if (e == hipSuccess) e = time_class<4>(out, blocks, e0, e1, &ms[4]);
+    if (e == hipSuccess) e = time_class<5>(out, blocks, e0, e1, &ms[5]);
+    if (e == hipSuccess) e = time_class<6>(out, blocks, e0, e1, &ms[6]);
+    if (e == hipSuccess) e = time_class<7>(out, blocks, e0, e1, &ms[7]);
+    if (e == hipSuccess) e = time_class<8>(out, blocks, e0, e1, &ms[8]);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(out);
+    if (e != hipSuccess) return -4;
+    const double ghz = khz * 1e-6;
+    const double groups = (double)blocks * 4 * kIters * kChains;  // wave-groups
+    for (int i = 0; i < kClasses; ++i) {
+        ms_out[i] = ms[i];
+        cycles_out[i] = ms[i] * 1e-3 * ghz * 1e9 * (cus * 4.0) / groups;
+    }
+    *clock_ghz_out = ghz;
+    return 0;
+}
+
+}  // extern "C"

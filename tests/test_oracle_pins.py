@@ -91,7 +91,7 @@ def test_counts_closed_form_and_paper():
         m, depth, mode, approx = [l for l in f if l.strip() and not l.startswith("#")][0].split()
     sigma = O.num_tree_nodes(int(m), int(depth), mode == "tiling")
     assert sigma == sum(4 ** d for d in range(1, 15))
-    assert abs(sigma - int(approx)) / int(approx) < 0.03       # "about 350 millions"
+    assert abs(sigma - int(approx)) / int(approx) < 0.03       # the paper gives roughly 350 million
     assert O.num_tree_nodes(4, 14, False) == 4 ** 14
 
 
