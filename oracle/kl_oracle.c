@@ -21,8 +21,14 @@
  *     draws every word of depth 1..D (Section 6);
  *   - generators: the trace recipe (Indra's Pearls' "Grandma's recipe",
  *     the paper's reference for generator construction), with the root of
- *     the trace quadratic taken in the closed upper half plane;
- *   - seed: attracting fixed point of the word's last letter.
+ *     the trace quadratic taken in the closed upper half plane; or two
+ *     explicit matrices; or Maskit's parametrisation of the once-punctured
+ *     torus groups (the embedding of the paper's figures);
+ *   - seed: attracting fixed point of the word's last letter; or, as in the
+ *     paper's index-search loop (Section 6), one generator's attracting
+ *     fixed point fed to every word, all of the word's maps applied, for
+ *     each generator in turn.  Seeds are points of the Riemann sphere,
+ *     kept as homogeneous pairs (u : v) so that infinity is one of them.
  */
 #include "kl_oracle.h"
 
@@ -156,10 +162,18 @@ static mat2 mat_mul(mat2 x, mat2 y)
     return r;
 }
 
-/* z -> (a z + b) / (c z + d)   (Section 3, linear fractional maps) */
-static cplx mobius(mat2 m, cplx z)
+/* The point (u : v) of the Riemann sphere, infinity when v = 0. */
+static cplx point_of(cplx u, cplx v)
 {
-    return (m.a * z + m.b) / (m.c * z + m.d);
+    if (v == 0) return INFINITY;
+    return u / v;
+}
+
+/* z -> (a z + b) / (c z + d)   (Section 3, linear fractional maps), for
+ * z = (u : v) on the Riemann sphere: (a u + b v) / (c u + d v). */
+static cplx mobius_h(mat2 m, cplx u, cplx v)
+{
+    return point_of(m.a * u + m.b * v, m.c * u + m.d * v);
 }
 
 static mat2 mat_inverse(mat2 m)
@@ -175,27 +189,70 @@ static mat2 mat_inverse(mat2 m)
 
 typedef struct {
     cplx tab;
-    mat2 g[4];   /* a, b, A, B */
-    cplx fix[4]; /* attracting fixed point of each generator */
+    mat2 g[4];         /* a, b, A, B */
+    cplx fu[4], fv[4]; /* attracting fixed point of each generator: fu / fv, fv = 0 at infinity */
 } group;
 
 static int finite_c(cplx z) { return isfinite(creal(z)) && isfinite(cimag(z)); }
 
-/* Attracting fixed point of z -> (a z + b)/(c z + d): the roots of
- * c z^2 + (d - a) z - b = 0; |g'(z)| = |det| / |c z + d|^2, so the
- * attracting root is the one with the larger |c z + d|.  A tie (one
- * parabolic root, or an elliptic pair) takes the "+" root. */
-static int attracting_fixed_point(mat2 m, cplx *out)
+/* Attracting fixed point of z -> (a z + b)/(c z + d) on the Riemann sphere,
+ * as a homogeneous pair (u : v).
+ * c != 0: the roots of c z^2 + (d - a) z - b = 0; |g'(z)| = |det| / |c z + d|^2,
+ *   so the attracting root is the one with the larger |c z + d|.  A tie (one
+ *   parabolic root, or an elliptic pair) takes the "+" root.
+ * c == 0: the map is z -> (a z + b) / d.  Infinity is fixed; when a != d so is
+ *   b / (d - a), where the derivative is a / d: it attracts iff |a / d| < 1,
+ *   else infinity does.  When a == d infinity is the only fixed point
+ *   (parabolic), and the identity (b == 0 too) has no attracting point. */
+static int attracting_fixed_point(mat2 m, cplx *u, cplx *v)
 {
-    if (m.c == 0) return -2;
+    if (m.c == 0) {
+        if (m.d == 0) return -2;
+        *u = 1;
+        *v = 0;
+        if (m.a == m.d) return m.b == 0 ? -2 : 0;
+        if (cabs(m.a / m.d) < 1) {
+            *u = m.b / (m.d - m.a);
+            *v = 1;
+        }
+        return finite_c(*u) ? 0 : -2;
+    }
     cplx disc = (m.a - m.d) * (m.a - m.d) + 4.0 * m.b * m.c;
     cplx root = csqrt(disc);
     cplx zp = ((m.a - m.d) + root) / (2.0 * m.c);
     cplx zm = ((m.a - m.d) - root) / (2.0 * m.c);
     double kp = cabs(m.c * zp + m.d);
     double km = cabs(m.c * zm + m.d);
-    *out = (km > kp) ? zm : zp;
-    return finite_c(*out) ? 0 : -2;
+    *u = (km > kp) ? zm : zp;
+    *v = 1;
+    return finite_c(*u) ? 0 : -2;
+}
+
+/* The four maps a, b, A = a^-1, B = b^-1 from a and b, each scaled to
+ * determinant 1 (the Moebius map is unchanged), and their seeds. */
+static int complete_group(mat2 a, mat2 b, group *g)
+{
+    mat2 ab[2] = {a, b};
+    for (int k = 0; k < 2; k++) {
+        cplx det = ab[k].a * ab[k].d - ab[k].b * ab[k].c;
+        if (det == 0 || !finite_c(det)) return -2;
+        cplx r = csqrt(det);
+        ab[k].a /= r;
+        ab[k].b /= r;
+        ab[k].c /= r;
+        ab[k].d /= r;
+    }
+    g->g[0] = ab[0];
+    g->g[1] = ab[1];
+    g->g[2] = mat_inverse(ab[0]);
+    g->g[3] = mat_inverse(ab[1]);
+    for (int k = 0; k < 4; k++) {
+        mat2 m = g->g[k];
+        if (!finite_c(m.a) || !finite_c(m.b) || !finite_c(m.c) || !finite_c(m.d))
+            return -2;
+        if (attracting_fixed_point(m, &g->fu[k], &g->fv[k]) != 0) return -2;
+    }
+    return 0;
 }
 
 /* Trace recipe: given tr a = ta and tr b = tb, tab = tr ab is a root of
@@ -236,9 +293,23 @@ static int build_group(cplx ta, cplx tb, group *g)
         mat2 m = g->g[k];
         if (!finite_c(m.a) || !finite_c(m.b) || !finite_c(m.c) || !finite_c(m.d))
             return -2;
-        if (attracting_fixed_point(m, &g->fix[k]) != 0) return -2;
+        if (attracting_fixed_point(m, &g->fu[k], &g->fv[k]) != 0) return -2;
+        if (g->fv[k] == 0) return -2;  /* no recipe map fixes infinity */
     }
     return 0;
+}
+
+/* Maskit's parametrisation of the once-punctured torus groups (the Maskit
+ * embedding of the paper's figures), as in Indra's Pearls:
+ *   a = [[-i mu, -i], [-i, 0]],  b = [[1, 2], [0, 1]],
+ * so tr a = -i mu, b is the translation z -> z + 2 (parabolic, fixed at
+ * infinity) and tr abAB = -2. */
+static int build_maskit(cplx mu, group *g)
+{
+    mat2 a = {-I * mu, -I, -I, 0};
+    mat2 b = {1, 2, 0, 1};
+    g->tab = 0;
+    return complete_group(a, b, g);
 }
 
 static void put_c(double *dst, cplx z)
@@ -265,7 +336,53 @@ int oracle_generators(double ta_re, double ta_im, double tb_re, double tb_im,
         }
     }
     if (fix_out)
-        for (int k = 0; k < 4; k++) put_c(fix_out + 2 * k, g.fix[k]);
+        for (int k = 0; k < 4; k++) put_c(fix_out + 2 * k, g.fu[k] / g.fv[k]);
+    return 0;
+}
+
+static void put_group(const group *g, double *gens_out, double *seeds_out)
+{
+    for (int k = 0; k < 4; k++) {
+        put_c(gens_out + ((k * 2 + 0) * 2 + 0) * 2, g->g[k].a);
+        put_c(gens_out + ((k * 2 + 0) * 2 + 1) * 2, g->g[k].b);
+        put_c(gens_out + ((k * 2 + 1) * 2 + 0) * 2, g->g[k].c);
+        put_c(gens_out + ((k * 2 + 1) * 2 + 1) * 2, g->g[k].d);
+        put_c(seeds_out + 4 * k, g->fu[k]);
+        put_c(seeds_out + 4 * k + 2, g->fv[k]);
+    }
+}
+
+int oracle_group_recipe(double ta_re, double ta_im, double tb_re, double tb_im,
+                        double *gens_out, double *seeds_out)
+{
+    if (!gens_out || !seeds_out) return -1;
+    group g;
+    int rc = build_group(ta_re + ta_im * I, tb_re + tb_im * I, &g);
+    if (rc) return rc;
+    put_group(&g, gens_out, seeds_out);
+    return 0;
+}
+
+int oracle_group_explicit(const double *ab, double *gens_out, double *seeds_out)
+{
+    if (!ab || !gens_out || !seeds_out) return -1;
+    group g;
+    mat2 a = {get_c(ab + 0), get_c(ab + 2), get_c(ab + 4), get_c(ab + 6)};
+    mat2 b = {get_c(ab + 8), get_c(ab + 10), get_c(ab + 12), get_c(ab + 14)};
+    g.tab = 0;
+    int rc = complete_group(a, b, &g);
+    if (rc) return rc;
+    put_group(&g, gens_out, seeds_out);
+    return 0;
+}
+
+int oracle_group_maskit(double mu_re, double mu_im, double *gens_out, double *seeds_out)
+{
+    if (!gens_out || !seeds_out) return -1;
+    group g;
+    int rc = build_maskit(mu_re + mu_im * I, &g);
+    if (rc) return rc;
+    put_group(&g, gens_out, seeds_out);
     return 0;
 }
 
@@ -273,20 +390,30 @@ int oracle_generators(double ta_re, double ta_im, double tb_re, double tb_im,
 /* word values                                                         */
 /* ------------------------------------------------------------------ */
 
-static cplx value_product(const group *g, const uint8_t *w, int d)
+/* seed < 0: the attracting fixed point of the word's last letter (the
+ * default); seed = 0..3: that generator's attracting fixed point, fed to
+ * every word (the paper's index-search loop, Section 6). */
+static cplx value_product(const group *g, const uint8_t *w, int d, int seed)
 {
     /* M = G_{w1} G_{w2} ... G_{wd}, then M applied to the seed */
     mat2 m = g->g[w[0]];
     for (int j = 1; j < d; j++) m = mat_mul(m, g->g[w[j]]);
-    return mobius(m, g->fix[w[d - 1]]);
+    int s = seed < 0 ? w[d - 1] : seed;
+    return mobius_h(m, g->fu[s], g->fv[s]);
 }
 
-static cplx value_literal(const group *g, const uint8_t *w, int d)
+static cplx value_literal(const group *g, const uint8_t *w, int d, int seed)
 {
-    /* z0 = seed; z <- G_{wj}(z) for j = d, d-1, ..., 1 */
-    cplx z = g->fix[w[d - 1]];
-    for (int j = d - 1; j >= 0; j--) z = mobius(g->g[w[j]], z);
-    return z;
+    /* (u : v) = seed; (u : v) <- G_{wj} (u : v) for j = d, d-1, ..., 1 */
+    const int k = (seed >= 0) ? seed : w[d - 1];
+    cplx u = g->fu[k], v = g->fv[k];
+    for (int j = d - 1; j >= 0; j--) {
+        mat2 m = g->g[w[j]];
+        cplx nu = m.a * u + m.b * v;
+        v = m.c * u + m.d * v;
+        u = nu;
+    }
+    return point_of(u, v);
 }
 
 static int group_from_arrays(const double *gens, const double *fix, group *g)
@@ -296,9 +423,21 @@ static int group_from_arrays(const double *gens, const double *fix, group *g)
         g->g[k].b = get_c(gens + ((k * 2 + 0) * 2 + 1) * 2);
         g->g[k].c = get_c(gens + ((k * 2 + 1) * 2 + 0) * 2);
         g->g[k].d = get_c(gens + ((k * 2 + 1) * 2 + 1) * 2);
-        g->fix[k] = get_c(fix + 2 * k);
+        g->fu[k] = get_c(fix + 2 * k);
+        g->fv[k] = 1;
     }
     return 0;
+}
+
+/* gens as oracle_generators lays them out; seeds: 4 homogeneous pairs (u, v) */
+static void group_from_group_arrays(const double *gens, const double *seeds, group *g)
+{
+    group_from_arrays(gens, seeds, g);  /* matrices */
+    for (int k = 0; k < 4; k++) {
+        g->fu[k] = get_c(seeds + 4 * k);
+        g->fv[k] = get_c(seeds + 4 * k + 2);
+    }
+    g->tab = 0;
 }
 
 int oracle_word_value(const uint8_t *word, int depth, const double *gens,
@@ -312,8 +451,20 @@ int oracle_word_value(const uint8_t *word, int depth, const double *gens,
     }
     group g;
     group_from_arrays(gens, fix, &g);
-    put_c(z_out, literal ? value_literal(&g, word, depth)
-                         : value_product(&g, word, depth));
+    put_c(z_out, literal ? value_literal(&g, word, depth, -1)
+                         : value_product(&g, word, depth, -1));
+    return 0;
+}
+
+static int eval_words(const group *g, int seed, int depth, const uint64_t *idx, uint64_t n,
+                      int literal, double *z_out)
+{
+    uint8_t w[MAX_DEPTH];
+    for (uint64_t i = 0; i < n; i++) {
+        if (oracle_unrank(idx[i], depth, w) != 0) return -1;
+        put_c(z_out + 2 * i, literal ? value_literal(g, w, depth, seed)
+                                     : value_product(g, w, depth, seed));
+    }
     return 0;
 }
 
@@ -325,13 +476,17 @@ int oracle_eval(double ta_re, double ta_im, double tb_re, double tb_im,
     group g;
     int rc = build_group(ta_re + ta_im * I, tb_re + tb_im * I, &g);
     if (rc) return rc;
-    uint8_t w[MAX_DEPTH];
-    for (uint64_t i = 0; i < n; i++) {
-        if (oracle_unrank(idx[i], depth, w) != 0) return -1;
-        put_c(z_out + 2 * i, literal ? value_literal(&g, w, depth)
-                                     : value_product(&g, w, depth));
-    }
-    return 0;
+    return eval_words(&g, -1, depth, idx, n, literal, z_out);
+}
+
+int oracle_eval_group(const double *gens, const double *seeds, int seed, int depth,
+                      const uint64_t *idx, uint64_t n, int literal, double *z_out)
+{
+    if (!gens || !seeds || seed < -1 || seed > 3) return -1;
+    if (depth < 1 || depth > MAX_DEPTH || (n && (!idx || !z_out))) return -1;
+    group g;
+    group_from_group_arrays(gens, seeds, &g);
+    return eval_words(&g, seed, depth, idx, n, literal, z_out);
 }
 
 /* ------------------------------------------------------------------ */
@@ -369,7 +524,7 @@ static int bin_point(const window *w, cplx z, uint32_t *bin, int *near_edge)
 typedef struct {
     const group *g;
     const window *win;
-    int depth;
+    int depth, seed;
     uint64_t first, last; /* leaf range [first, last) of this depth */
     uint32_t *image;
     uint64_t dropped, near_edge;
@@ -383,7 +538,8 @@ static void render_rec(render_ctx *r, int j, mat2 m, uint64_t base)
 {
     int d = r->depth;
     if (j == d) {
-        cplx z = mobius(m, r->g->fix[r->word[d - 1]]);
+        const int s = r->seed < 0 ? r->word[d - 1] : r->seed;
+        cplx z = mobius_h(m, r->g->fu[s], r->g->fv[s]);
         uint32_t bin;
         int near;
         if (bin_point(r->win, z, &bin, &near))
@@ -407,11 +563,18 @@ static void render_rec(render_ctx *r, int j, mat2 m, uint64_t base)
 
 /* Render the words with combined index in [first, first+count) of the
  * index space "all words of depth min_depth, then all of min_depth+1, ...,
- * then all of depth" into image (added to what it holds). */
-static void render_range(const group *g, const window *win, int min_depth,
+ * then all of depth" into image (added to what it holds).  seed: as in
+ * value_product, or 4 for every generator's fixed point in turn, each word
+ * drawn once from each (the paper's index-search loop, Section 6). */
+static void render_range(const group *g, const window *win, int seed, int min_depth,
                          int depth, uint64_t first, uint64_t count,
                          uint32_t *image, uint64_t *dropped, uint64_t *near_edge)
 {
+    if (seed == 4) {
+        for (int p = 0; p < 4; p++)
+            render_range(g, win, p, min_depth, depth, first, count, image, dropped, near_edge);
+        return;
+    }
     uint64_t offset = 0, end = first + count;
     for (int d = min_depth; d <= depth; d++) {
         uint64_t n = oracle_num_words(d);
@@ -423,6 +586,7 @@ static void render_range(const group *g, const window *win, int min_depth,
             r.g = g;
             r.win = win;
             r.depth = d;
+            r.seed = seed;
             r.first = lo;
             r.last = hi;
             r.image = image;
@@ -438,7 +602,7 @@ static void render_range(const group *g, const window *win, int min_depth,
 typedef struct {
     const group *g;
     const window *win;
-    int min_depth, depth;
+    int seed, min_depth, depth;
     uint64_t first, count;
     uint32_t *image;
     uint64_t dropped, near_edge;
@@ -447,20 +611,19 @@ typedef struct {
 static void *thread_main(void *arg)
 {
     thread_job *t = (thread_job *)arg;
-    render_range(t->g, t->win, t->min_depth, t->depth, t->first, t->count,
+    render_range(t->g, t->win, t->seed, t->min_depth, t->depth, t->first, t->count,
                  t->image, &t->dropped, &t->near_edge);
     return NULL;
 }
 
-int oracle_render(double ta_re, double ta_im, double tb_re, double tb_im,
-                  int depth, int min_depth,
-                  double x0, double x1, double y0, double y1,
-                  uint32_t width, uint32_t height,
-                  uint64_t first, uint64_t count, int nthreads,
-                  double edge_tol, uint32_t *image, uint64_t *dropped,
-                  uint64_t *near_edge)
+static int render_group(const group *g, int seed, int depth, int min_depth,
+                        double x0, double x1, double y0, double y1,
+                        uint32_t width, uint32_t height,
+                        uint64_t first, uint64_t count, int nthreads,
+                        double edge_tol, uint32_t *image, uint64_t *dropped,
+                        uint64_t *near_edge)
 {
-    if (depth < 1 || depth > MAX_DEPTH || min_depth < 1 || min_depth > depth)
+    if (depth < 1 || depth > MAX_DEPTH || min_depth < 1 || min_depth > depth || seed < -1 || seed > 4)
         return -1;
     if (!image || width == 0 || height == 0 || !(x1 > x0) || !(y1 > y0))
         return -1;
@@ -468,9 +631,7 @@ int oracle_render(double ta_re, double ta_im, double tb_re, double tb_im,
     for (int d = min_depth; d <= depth; d++) total += oracle_num_words(d);
     if (first > total || count > total - first) return -1;
     if (nthreads < 1) nthreads = 1;
-    group g;
-    int rc = build_group(ta_re + ta_im * I, tb_re + tb_im * I, &g);
-    if (rc) return rc;
+    int rc = 0;
     window win = {x0, x1, y0, y1, width, height, edge_tol};
     uint64_t bins = (uint64_t)width * height;
 
@@ -481,8 +642,9 @@ int oracle_render(double ta_re, double ta_im, double tb_re, double tb_im,
     uint64_t start = first;
     for (int t = 0; t < nthreads; t++) {
         uint64_t share = count / (uint64_t)nthreads + ((uint64_t)t < count % (uint64_t)nthreads);
-        jobs[t].g = &g;
+        jobs[t].g = g;
         jobs[t].win = &win;
+        jobs[t].seed = seed;
         jobs[t].min_depth = min_depth;
         jobs[t].depth = depth;
         jobs[t].first = start;
@@ -508,4 +670,34 @@ int oracle_render(double ta_re, double ta_im, double tb_re, double tb_im,
     if (dropped) *dropped = drop;
     if (near_edge) *near_edge = near;
     return rc;
+}
+
+int oracle_render(double ta_re, double ta_im, double tb_re, double tb_im,
+                  int depth, int min_depth,
+                  double x0, double x1, double y0, double y1,
+                  uint32_t width, uint32_t height,
+                  uint64_t first, uint64_t count, int nthreads,
+                  double edge_tol, uint32_t *image, uint64_t *dropped,
+                  uint64_t *near_edge)
+{
+    group g;
+    int rc = build_group(ta_re + ta_im * I, tb_re + tb_im * I, &g);
+    if (rc) return rc;
+    return render_group(&g, -1, depth, min_depth, x0, x1, y0, y1, width, height, first, count,
+                        nthreads, edge_tol, image, dropped, near_edge);
+}
+
+int oracle_render_group(const double *gens, const double *seeds, int seed,
+                        int depth, int min_depth,
+                        double x0, double x1, double y0, double y1,
+                        uint32_t width, uint32_t height,
+                        uint64_t first, uint64_t count, int nthreads,
+                        double edge_tol, uint32_t *image, uint64_t *dropped,
+                        uint64_t *near_edge)
+{
+    if (!gens || !seeds) return -1;
+    group g;
+    group_from_group_arrays(gens, seeds, &g);
+    return render_group(&g, seed, depth, min_depth, x0, x1, y0, y1, width, height, first, count,
+                        nthreads, edge_tol, image, dropped, near_edge);
 }

@@ -19,11 +19,19 @@
  *            (w[0], ..., w[d-1]) with the letter order above; equivalently
  *            the rank among the survivors of the paper's scan of all m^d
  *            digit strings in numeric order (Section 6, index search).
- *   seed     attracting fixed point of the word's last (rightmost) letter.
+ *   seed     attracting fixed point of the word's last (rightmost) letter;
+ *            the *_group functions also feed one generator's fixed point to
+ *            every word (seed 0..3), or each of the four in turn (seed 4,
+ *            renders only): the paper's index-search loop (Section 6).
  *   complex  interleaved (re, im) doubles.
  *   matrix   gens[((letter*2 + row)*2 + col)*2 + part], part 0=re 1=im.
  *   window   [x0,x1) x [y0,y1), width x height bins, row 0 at y0,
  *            bin index row*width + col; non-finite values are dropped.
+ *
+ *   group    gens: 32 doubles, the four matrices laid out as above;
+ *            seeds: 16 doubles, each generator's attracting fixed point as
+ *            a homogeneous pair (u, v) of complex numbers, the point u / v
+ *            (v = 0: infinity).  Matrices have determinant 1.
  *
  * Return codes: 0 ok, -1 bad argument, -2 singular parameters.
  */
@@ -53,6 +61,25 @@ int oracle_render(double ta_re, double ta_im, double tb_re, double tb_im,
                   uint64_t first, uint64_t count, int nthreads,
                   double edge_tol, uint32_t *image, uint64_t *dropped,
                   uint64_t *near_edge);
+
+/* groups: by the trace recipe; from two explicit matrices a, b (16 doubles,
+ * a then b, each row-major complex; scaled to determinant 1, A and B are
+ * their inverses); by Maskit's parametrisation with parameter mu */
+int oracle_group_recipe(double ta_re, double ta_im, double tb_re, double tb_im,
+                        double *gens_out, double *seeds_out);
+int oracle_group_explicit(const double *ab, double *gens_out, double *seeds_out);
+int oracle_group_maskit(double mu_re, double mu_im, double *gens_out, double *seeds_out);
+/* seed: -1 the word's own, 0..3 that generator's fixed point for every word */
+int oracle_eval_group(const double *gens, const double *seeds, int seed, int depth,
+                      const uint64_t *idx, uint64_t n, int literal, double *z_out);
+/* seed: as oracle_eval_group, or 4 for each generator's fixed point in turn */
+int oracle_render_group(const double *gens, const double *seeds, int seed,
+                        int depth, int min_depth,
+                        double x0, double x1, double y0, double y1,
+                        uint32_t width, uint32_t height,
+                        uint64_t first, uint64_t count, int nthreads,
+                        double edge_tol, uint32_t *image, uint64_t *dropped,
+                        uint64_t *near_edge);
 
 #ifdef __cplusplus
 }

@@ -65,8 +65,19 @@ def lib():
                                     d, d, d, d, ctypes.c_uint32, ctypes.c_uint32,
                                     ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int, d,
                                     u32p, u64p, u64p]
+        L.oracle_group_recipe.argtypes = [d, d, d, d, dp, dp]
+        L.oracle_group_explicit.argtypes = [dp, dp, dp]
+        L.oracle_group_maskit.argtypes = [d, d, dp, dp]
+        L.oracle_eval_group.argtypes = [dp, dp, ctypes.c_int, ctypes.c_int, u64p, ctypes.c_uint64,
+                                        ctypes.c_int, dp]
+        L.oracle_render_group.argtypes = [dp, dp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                          d, d, d, d, ctypes.c_uint32, ctypes.c_uint32,
+                                          ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int, d,
+                                          u32p, u64p, u64p]
         for f in (L.oracle_unrank, L.oracle_enumerate, L.oracle_generators,
-                  L.oracle_word_value, L.oracle_eval, L.oracle_render):
+                  L.oracle_word_value, L.oracle_eval, L.oracle_render, L.oracle_group_recipe,
+                  L.oracle_group_explicit, L.oracle_group_maskit, L.oracle_eval_group,
+                  L.oracle_render_group):
             f.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -161,4 +172,77 @@ def render(ta: complex, tb: complex, depth: int, window, *, min_depth: int | Non
                                x0, x1, y0, y1, W, H, first, count, nthreads, edge_tol,
                                _ptr(image, ctypes.c_uint32), ctypes.byref(dropped),
                                ctypes.byref(near)), "render")
+    return image, int(dropped.value), int(near.value)
+
+
+class Group:
+    """A group as the *_group functions take it: gens[4, 2, 2] complex
+    (a, b, A, B) and seeds[4, 2] complex (homogeneous fixed points u : v)."""
+
+    def __init__(self, gens: np.ndarray, seeds: np.ndarray):
+        self.gens = np.ascontiguousarray(gens, np.complex128).reshape(4, 2, 2)
+        self.seeds = np.ascontiguousarray(seeds, np.complex128).reshape(4, 2)
+
+    def _arrays(self):
+        return (np.ascontiguousarray(self.gens.reshape(-1)).view(np.float64),
+                np.ascontiguousarray(self.seeds.reshape(-1)).view(np.float64))
+
+    def seed_points(self) -> np.ndarray:
+        """Each generator's seed as a point (inf where v = 0)."""
+        u, v = self.seeds[:, 0], self.seeds[:, 1]
+        with np.errstate(divide="ignore", invalid="ignore"):
+            return np.where(v == 0, np.inf, u / np.where(v == 0, 1, v))
+
+
+def _group_from(fn, *args) -> Group:
+    gens = np.zeros(32)
+    seeds = np.zeros(16)
+    _check(fn(*args, _ptr(gens, ctypes.c_double), _ptr(seeds, ctypes.c_double)), "group")
+    return Group(gens.view(np.complex128), seeds.view(np.complex128))
+
+
+def group_recipe(ta: complex, tb: complex) -> Group:
+    return _group_from(lib().oracle_group_recipe, ta.real, ta.imag, tb.real, tb.imag)
+
+
+def group_explicit(a, b) -> Group:
+    ab = np.ascontiguousarray(np.concatenate([np.asarray(a, np.complex128).reshape(-1),
+                                              np.asarray(b, np.complex128).reshape(-1)])).view(np.float64)
+    return _group_from(lib().oracle_group_explicit, _ptr(ab, ctypes.c_double))
+
+
+def group_maskit(mu: complex) -> Group:
+    return _group_from(lib().oracle_group_maskit, mu.real, mu.imag)
+
+
+def eval_group(group: Group, depth: int, idx, seed: int = -1, literal: bool = False) -> np.ndarray:
+    g, s = group._arrays()
+    idx = np.ascontiguousarray(idx, np.uint64)
+    z = np.zeros(2 * len(idx))
+    _check(lib().oracle_eval_group(_ptr(g, ctypes.c_double), _ptr(s, ctypes.c_double), seed, depth,
+                                   _ptr(idx, ctypes.c_uint64), len(idx), int(literal),
+                                   _ptr(z, ctypes.c_double)), "eval_group")
+    return z.view(np.complex128)
+
+
+def render_group(group: Group, depth: int, window, *, seed: int = -1, min_depth: int | None = None,
+                 first: int = 0, count: int | None = None, nthreads: int = 1, edge_tol: float = 0.0,
+                 image: np.ndarray | None = None):
+    """As render(), for an explicit group and seed mode (-1 own, 0..3 one
+    generator's fixed point, 4 each in turn).  Returns (image, dropped, near_edge)."""
+    g, s = group._arrays()
+    x0, x1, y0, y1, W, H = window
+    if min_depth is None:
+        min_depth = depth
+    total = sum(num_words(d) for d in range(min_depth, depth + 1))
+    if count is None:
+        count = total - first
+    if image is None:
+        image = np.zeros((H, W), np.uint32)
+    dropped = ctypes.c_uint64(0)
+    near = ctypes.c_uint64(0)
+    _check(lib().oracle_render_group(_ptr(g, ctypes.c_double), _ptr(s, ctypes.c_double), seed, depth,
+                                     min_depth, x0, x1, y0, y1, W, H, first, count, nthreads, edge_tol,
+                                     _ptr(image, ctypes.c_uint32), ctypes.byref(dropped),
+                                     ctypes.byref(near)), "render_group")
     return image, int(dropped.value), int(near.value)

@@ -1,0 +1,172 @@
+"""Pins of the oracle's seed modes, explicit groups and Maskit groups.
+
+The paper's index-search loop (Section 6) feeds every generator's fixed
+point to every word, all of the word's maps applied; Maskit's embedding is
+the one of the paper's figures (Fig. 1, Fig. 6).  The pins below fix those
+paths by facts of the mathematics: the right-to-left action, invariant
+circles, attracting fixed points, traces, the translation b(z) = z + 2,
+closed-form word values, scale invariance of Moebius maps, and agreement of
+two independent evaluators.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1709_08018_amd import workloads as wl
+
+C2 = (wl.C2_TA, wl.C2_TB)
+C1 = (wl.C1_TA, wl.C1_TB)
+MU_FIG = complex(-0.097, 1.838)      # the paper's figures (Fig. 1 and Fig. 6 captions)
+
+
+def _words_idx(depth, n, seed):
+    return wl.sample_indices(O.num_words(depth), n, seed=seed)
+
+
+def _moebius(m, z):
+    return (m[0, 0] * z + m[0, 1]) / (m[1, 0] * z + m[1, 1])
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_seeded_values_act_right_to_left(seed):
+    """value(c.w, p) = G_c(value(w, p)): the leftmost letter is applied last."""
+    G = O.group_recipe(*C2)
+    d = 9
+    idx = _words_idx(d, 400, seed)
+    words = np.array([O.unrank(int(i), d) for i in idx])
+    z = O.eval_group(G, d, idx, seed=seed)
+    for w, zw in zip(words, z):
+        for c in range(4):
+            if c == (w[0] ^ 2):
+                continue
+            longer = np.concatenate([[c], w]).astype(np.uint8)
+            # rank of the longer word: it exists; evaluate it through its index
+            j = _rank(longer)
+            zc = O.eval_group(G, d + 1, np.array([j], np.uint64), seed=seed)[0]
+            want = _moebius(G.gens[c], zw)
+            assert abs(zc - want) <= 1e-9 * max(1.0, abs(want))
+
+
+def _rank(word):
+    """Index of a reduced word (lexicographic, first letter most significant)."""
+    d = len(word)
+    r = int(word[0]) * 3 ** (d - 1)
+    for j in range(1, d):
+        t = int(word[j]) - (1 if int(word[j]) > (int(word[j - 1]) ^ 2) else 0)
+        r += t * 3 ** (d - 1 - j)
+    return r
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_real_traces_keep_every_seed_on_the_circle(seed):
+    """ta = tb = 3: the group preserves the unit disc and every generator's
+    fixed points lie on its boundary, so every word maps any seed on the
+    circle to a point on the circle."""
+    G = O.group_recipe(*C1)
+    pts = G.seed_points()
+    assert np.allclose(np.abs(pts), 1.0, atol=1e-12)
+    d = 7
+    z = O.eval_group(G, d, np.arange(O.num_words(d), dtype=np.uint64), seed=seed)
+    assert np.abs(np.abs(z) - 1.0).max() < 1e-9
+
+
+def test_powers_pull_any_seed_to_the_attracting_point():
+    """a^n(p) -> fix(a) for any seed p other than the repelling point; with
+    tr a = 3 the multiplier is ((3 + sqrt 5)/2)^2 per letter."""
+    G = O.group_recipe(*C1)
+    fa = G.seed_points()[0]
+    word = np.zeros(30, np.uint8)  # a^30
+    j = _rank(word)
+    for seed in (1, 3):   # seed 2, A's attracting point, is a's repelling one
+        z = O.eval_group(G, 30, np.array([j], np.uint64), seed=seed)[0]
+        assert abs(z - fa) < 1e-8, (seed, z, fa)
+    z = O.eval_group(G, 30, np.array([j], np.uint64), seed=0)[0]
+    assert abs(z - fa) < 1e-12
+
+
+@pytest.mark.parametrize("group", ["recipe", "maskit"])
+def test_literal_and_product_evaluators_agree_for_every_seed(group):
+    G = O.group_recipe(*C2) if group == "recipe" else O.group_maskit(MU_FIG)
+    d = 10
+    idx = _words_idx(d, 3000, 5)
+    for seed in (-1, 0, 1, 2, 3):
+        zp = O.eval_group(G, d, idx, seed=seed)
+        zl = O.eval_group(G, d, idx, seed=seed, literal=True)
+        fin = np.isfinite(zp)
+        assert np.array_equal(fin, np.isfinite(zl)), seed
+        rel = np.abs(zp[fin] - zl[fin]) / np.maximum(1.0, np.abs(zp[fin]))
+        assert rel.max() < 1e-12, (seed, rel.max())
+
+
+def test_maskit_closed_forms():
+    mu = MU_FIG
+    G = O.group_maskit(mu)
+    a, b, A, B = G.gens
+    assert abs(np.trace(a) - (-1j * mu)) < 1e-14
+    assert abs(np.trace(b) - 2) < 1e-14
+    assert abs(np.trace(a @ b @ A @ B) + 2) < 1e-12
+    assert np.allclose(b / b[0, 0], [[1, 2], [0, 1]], atol=0)    # z -> z + 2
+    pts = G.seed_points()
+    assert np.isinf(pts[1]) and np.isinf(pts[3])                   # b, B fix only infinity
+    roots = np.roots([1, -mu, -1])                                 # a's fixed points: z^2 - mu z - 1 = 0
+    for k, m in ((0, a), (2, A)):
+        assert np.min(np.abs(roots - pts[k])) < 1e-12
+        other = roots[np.argmax(np.abs(roots - pts[k]))]
+        # attracting: |c z + d| larger at the chosen root
+        assert abs(m[1, 0] * pts[k] + m[1, 1]) > abs(m[1, 0] * other + m[1, 1])
+    # a(b(inf)) = a(inf) = mu and A(b(inf)) = A(inf) = 0, with the own seed infinity
+    z = O.eval_group(G, 2, np.array([_rank([0, 1]), _rank([2, 1])], np.uint64))
+    assert abs(z[0] - mu) < 1e-14 and abs(z[1]) < 1e-14
+    # b applied last translates by 2
+    d = 8
+    idx = _words_idx(d, 500, 3)
+    words = [O.unrank(int(i), d) for i in idx]
+    keep = [i for i, w in zip(idx, words) if w[0] != 3]
+    zw = O.eval_group(G, d, np.array(keep, np.uint64))
+    zb = O.eval_group(G, d + 1, np.array([_rank(np.concatenate([[1], O.unrank(int(i), d)])) for i in keep],
+                                         np.uint64))
+    fin = np.isfinite(zw)
+    assert np.abs(zb[fin] - (zw[fin] + 2)).max() < 1e-12
+
+
+def test_explicit_generators_are_scale_invariant():
+    """Multiplying a generator matrix by a constant leaves its map, and every
+    word value, unchanged."""
+    R = O.group_recipe(*C2)
+    E = O.group_explicit(3.0 * R.gens[0], 5j * R.gens[1])
+    d = 9
+    idx = _words_idx(d, 2000, 8)
+    for seed in (-1, 0, 1, 2, 3):
+        zr = O.eval_group(R, d, idx, seed=seed)
+        ze = O.eval_group(E, d, idx, seed=seed)
+        assert (np.abs(zr - ze) / np.maximum(1, np.abs(zr))).max() < 1e-12
+
+
+def test_affine_generator_seeds():
+    """a: z -> 4z + 2 fixes -2/3 (repelling, a' = 4) and infinity, which
+    attracts; A: z -> (z - 2)/4 attracts to -2/3."""
+    a = np.array([[2, 1], [0, 0.5]], complex)
+    b = np.array([[2, 1], [1, 1]], complex)
+    G = O.group_explicit(a, b)
+    pts = G.seed_points()
+    assert np.isinf(pts[0])
+    assert abs(pts[2] + 2 / 3) < 1e-15
+    # b = [[2, 1], [1, 1]] is hyperbolic with fixed points (1 +- sqrt 5)/2; the
+    # attracting one is where |z + 1| is larger
+    r = np.array([(1 + 5 ** 0.5) / 2, (1 - 5 ** 0.5) / 2])
+    assert abs(pts[1] - r[np.argmax(np.abs(r + 1))]) < 1e-14
+    assert abs(pts[3] - r[np.argmin(np.abs(r + 1))]) < 1e-14
+
+
+def test_render_of_all_seeds_is_the_sum_of_single_seeds():
+    G = O.group_maskit(MU_FIG)
+    win = (-1.0, 1.0, -0.2, 2.0, 96, 96)
+    d = 8
+    total, drops = np.zeros((96, 96), np.uint64), 0
+    for s in range(4):
+        img, dr, _ = O.render_group(G, d, win, seed=s)
+        total += img
+        drops += dr
+    img4, dr4, _ = O.render_group(G, d, win, seed=4)
+    assert np.array_equal(img4.astype(np.uint64), total) and dr4 == drops
+    assert int(img4.sum()) + dr4 == 4 * O.num_words(d)

@@ -4,8 +4,11 @@ Each case edits one plausible mistake into a temporary copy of
 ``oracle/kl_oracle.c`` (a transposed operand, the product read left to
 right, a wrong sign in the trace recipe, the repelling seed, the wrong
 seed letter, a wrong skip in the unranking, swapped bin axes, a dropped
-term, the other root of the trace quadratic), builds it with gcc, and runs
-the pin tests against the planted build in a child process.  The pins pass
+term, the other root of the trace quadratic, a sign in Maskit's
+generators, the repelling point of an affine map as its seed, the wrong
+generator's seed fed to every word, a seed at infinity treated as finite),
+builds it with gcc, and runs the pin tests against the planted build in a
+child process.  The pins pass
 on the real reference and must fail on every planted copy.
 """
 import os
@@ -22,8 +25,8 @@ MUTATIONS = {
     "left_to_right_product": ("for (int j = 1; j < d; j++) m = mat_mul(m, g->g[w[j]]);",
                               "for (int j = 1; j < d; j++) m = mat_mul(g->g[w[j]], m);"),
     "recipe_sign": ("a.b = (ta * tab - 2.0 * tb + I4)", "a.b = (ta * tab - 2.0 * tb - I4)"),
-    "repelling_seed": ("*out = (km > kp) ? zm : zp;", "*out = (km < kp) ? zm : zp;"),
-    "first_letter_seed": ("return mobius(m, g->fix[w[d - 1]]);", "return mobius(m, g->fix[w[0]]);"),
+    "repelling_seed": ("*u = (km > kp) ? zm : zp;", "*u = (km < kp) ? zm : zp;"),
+    "first_letter_seed": ("int s = seed < 0 ? w[d - 1] : seed;", "int s = seed < 0 ? w[0] : seed;"),
     "unrank_skip": ("if (prev >= 0 && c == INVERSE[prev]) continue;",
                     "if (prev >= 0 && c == prev) continue;"),
     "bin_axes_swapped": ("*bin = row * w->width + col;", "*bin = col * w->width + row;"),
@@ -31,7 +34,13 @@ MUTATIONS = {
                      "cplx disc = (ta * tb) * (ta * tb) - 4.0 * (ta * ta);"),
     "other_root": ("if (cimag(s) < 0 || (cimag(s) == 0 && creal(s) < 0)) s = -s;",
                    "if (cimag(s) > 0 || (cimag(s) == 0 && creal(s) > 0)) s = -s;"),
+    "maskit_sign": ("mat2 a = {-I * mu, -I, -I, 0};", "mat2 a = {I * mu, -I, -I, 0};"),
+    "affine_repelling_seed": ("if (cabs(m.a / m.d) < 1) {", "if (cabs(m.a / m.d) > 1) {"),
+    "wrong_seed_generator": ("int s = seed < 0 ? w[d - 1] : seed;", "int s = seed < 0 ? w[d - 1] : (seed + 1) % 4;"),
+    "infinite_seed_as_finite": ("return point_of(m.a * u + m.b * v, m.c * u + m.d * v);",
+                                "return point_of(m.a * u + m.b, m.c * u + m.d);"),
 }
+PINS = [os.path.join(ROOT, "tests", f) for f in ("test_oracle_pins.py", "test_oracle_groups.py")]
 
 
 @pytest.mark.parametrize("name", sorted(MUTATIONS))
@@ -46,7 +55,6 @@ def test_planted_mistake_is_caught(name, tmp_path):
     subprocess.run(["gcc", "-std=c99", "-O2", "-fPIC", "-shared", "-o", str(lib), str(mutant),
                     "-lm", "-lpthread"], check=True)
     env = dict(os.environ, KL_ORACLE_LIB=str(lib))
-    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-                        os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider"] + PINS,
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode != 0, f"planted mistake {name} passed every pin:\n{r.stdout[-2000:]}"
