@@ -177,6 +177,42 @@ def leg_tiling(args):
     return out
 
 
+def leg_maskit(args):
+    """The configuration of the paper's index-search figure: Maskit's group
+    at mu = -0.097 + 1.838i, tiling mode over depths 1..14, every word drawn
+    from each generator's fixed point in turn (9,565,936 words, 4 points
+    each), 1024^2 over one period of the translation b.  FP32 and FP64 step
+    times, and the FP64 image against the CPU reference's."""
+    import numpy as np
+
+    from oracle import oracle as ref
+    from paper_1709_08018_amd import kl
+    from paper_1709_08018_amd import workloads as wl
+
+    W = wl.MASKIT_D14
+    ab = kl.maskit_generators(W.ta)
+    words = sum(kl.num_words(d) for d in range(W.min_depth, W.depth + 1))
+    image = kl.new_image(W.window)
+    out = {"workload": W.name, "mu": [W.ta.real, W.ta.imag], "words": words, "points": 4 * words}
+    for prec in ("fp32", "fp64"):
+        ms = _time(lambda: kl.render_group(ab, W.depth, W.window, image=image, min_depth=W.min_depth, seed="all",
+                                           precision=prec), max(2, args.steps // 4), 3)
+        out[prec] = {"ms": round(ms, 4), "gpoints_per_s": round(4 * words / ms / 1e6, 3)}
+    kl.render_group(ab, W.depth, W.window, image=image, min_depth=W.min_depth, seed="all", precision="fp64")
+    img = kl.as_u32(image).astype(np.int64)
+    threads = min(len(os.sched_getaffinity(0)), 16)
+    t0 = time.perf_counter()
+    ref_img, ref_drop, near = ref.render_group(ref.group_maskit(W.ta), W.depth, W.window.as_tuple(), seed=4,
+                                               min_depth=W.min_depth, edge_tol=1e-7, nthreads=threads)
+    dt = time.perf_counter() - t0
+    out["fp64_l1_vs_reference"] = int(np.abs(img - ref_img.astype(np.int64)).sum())
+    out["reference_near_edge_words"] = int(near)
+    out["points_in_window"] = int(img.sum())
+    out["cpu_reference"] = {"seconds": round(dt, 3), "gpoints_per_s": round(4 * words / dt / 1e9, 4),
+                            "threads": threads}
+    return out
+
+
 def leg_surrogate(args):
     """Learned occupancy surrogate at depth 14, 128^2 over [-2,2]^2: 20,000
     training sets (PCG64 seed 1; the last 2,000 calibrate the gate) and 2,000
@@ -236,8 +272,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=400,
                     help="untimed steps first (the GPU clock ramps up over the first ~100 ms of work)")
     ap.add_argument("--workload", default="quasifuchsian_d18",
-                    choices=["quasifuchsian_d18", "quasifuchsian_d22", "batch256", "fuchsian_tiling_d10", "surrogate",
-                             "hist", "calib"])
+                    choices=["quasifuchsian_d18", "quasifuchsian_d22", "batch256", "fuchsian_tiling_d10",
+                             "maskit_tiling_d14", "surrogate", "hist", "calib"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="after the steps, copy 256 MiB device to device twice (a kernel of known HBM "
@@ -256,7 +292,7 @@ def main():
 
     torch.cuda.set_device(0)
     legs = {"quasifuchsian_d22": leg_d22, "batch256": leg_batch, "fuchsian_tiling_d10": leg_tiling,
-            "surrogate": leg_surrogate, "hist": leg_hist, "calib": leg_calib}
+            "maskit_tiling_d14": leg_maskit, "surrogate": leg_surrogate, "hist": leg_hist, "calib": leg_calib}
     if args.workload in legs:
         print(json.dumps(legs[args.workload](args)), flush=True)
         return

@@ -75,6 +75,16 @@ extern "C" {
 #define KL_PREC_FP32 0  /* FP64 generators, seeds and prefix products; FP32 suffix maps */
 #define KL_PREC_FP64 1  /* every step in FP64 */
 
+/* where each word's orbit starts (Section 6, index search: the paper feeds
+ * every generator's fixed point to every word, each word's maps applied to
+ * it in turn) */
+#define KL_SEED_OWN 0     /* the attracting fixed point of the word's last letter */
+#define KL_SEED_ALL 1     /* each of the four below in turn: four values per word (renders only) */
+#define KL_SEED_A 2       /* the attracting fixed point of a, fed to every word; */
+#define KL_SEED_B 3       /*   of b; */
+#define KL_SEED_INV_A 4   /*   of A; */
+#define KL_SEED_INV_B 5   /*   of B */
+
 /* histogram strategy of the renderer */
 #define KL_HIST_AUTO 0    /* planner's choice */
 #define KL_HIST_RUNS 1    /* per-lane run-length counts, flushed with global atomics */
@@ -107,6 +117,8 @@ typedef struct {
     int waves_per_cu;     /* persistent grid size, 0 = planner */
     int suffix_form;      /* 0: affine suffix points unless one needs the
                              homogeneous form; 1: homogeneous form always */
+    int seed_mode;        /* KL_SEED_*; with KL_SEED_ALL the image and the
+                             dropped count hold four points per word */
     int head_form;        /* how each head's map is applied to its suffix
                              points: 0: as P + Q / (y + S) (c != 0, det 1)
                              wherever that form fits the working precision,
@@ -186,7 +198,8 @@ int kl_render_many_ex(int n, const kl_c64 *ta, const kl_c64 *tb, const int *dept
  * kl_eval_ex additionally takes a window: with one, z_out receives the
  * continuous pixel coordinates (col + fraction, row + fraction) the
  * renderer floors into a bin, bit for bit; and options (precision, split,
- * stream; the other fields are ignored).
+ * stream, suffix form, head form, seed mode -- one seed per word, so
+ * KL_SEED_ALL is KL_EINVAL; the other fields are ignored).
  * An index beyond the words of that depth yields NaN (the indices live in
  * device memory and are checked there).
  * Errors: KL_EINVAL, KL_ESINGULAR, KL_EDEVICE. */
@@ -202,6 +215,38 @@ int kl_eval_ex(kl_c64 ta, kl_c64 tb, int depth, const uint64_t *idx, uint64_t n,
  *   fix_out     4 entries: attracting fixed point of each generator
  * Any output pointer may be NULL.  Errors: KL_ESINGULAR. */
 int kl_generators(kl_c64 ta, kl_c64 tb, kl_c64 *tab_out, kl_c64 *gens_out, kl_c64 *fix_out);
+
+/* Groups given by two generators instead of traces (Section 3: the maps
+ * are linear fractional, z -> (a z + b)/(c z + d)).
+ *   ab   host, 8 entries: a = [[ab[0], ab[1]], [ab[2], ab[3]]], then b
+ *        likewise in ab[4..7].  Each is scaled to determinant 1, which
+ *        leaves its map unchanged; A and B are the inverses.
+ * A generator's seed is its attracting fixed point on the Riemann sphere,
+ * which may be infinity (a map with c = 0, as for a translation).  Words
+ * whose value is infinity are dropped like any non-finite value.
+ *
+ * kl_group_seeds: the four normalised maps (gens_out, 16 entries, laid out
+ * as in kl_generators) and their seeds as homogeneous pairs (seeds_out, 8
+ * entries: seed k = seeds_out[2k] / seeds_out[2k+1], infinity when the
+ * second is 0).  Host pointers, either may be NULL.
+ * Errors: KL_EINVAL (NULL ab, non-finite entries), KL_ESINGULAR (a zero
+ * determinant, a map without an attracting fixed point: the identity). */
+int kl_group_seeds(const kl_c64 *ab, kl_c64 *gens_out, kl_c64 *seeds_out);
+
+/* kl_maskit_generators: Maskit's parametrisation of the once-punctured
+ * torus groups, the embedding of the paper's figures (Fig. 1, Fig. 6 use
+ * mu = -0.097 + 1.838i): a = [[-i mu, -i], [-i, 0]], b = [[1, 2], [0, 1]]
+ * into ab_out (host, 8 entries, as kl_group_seeds takes them).
+ * Errors: KL_EINVAL (NULL ab_out, non-finite mu). */
+int kl_maskit_generators(kl_c64 mu, kl_c64 *ab_out);
+
+/* kl_render_group_ex / kl_eval_group_ex: kl_render_ex / kl_eval_ex for a
+ * group given by its two generators; every option applies the same way.
+ * Errors: as kl_render_ex / kl_eval_ex, and as kl_group_seeds. */
+int kl_render_group_ex(const kl_c64 *ab, int depth, const kl_window *window, uint32_t *image_out,
+                       const kl_opts *opts);
+int kl_eval_group_ex(const kl_c64 *ab, int depth, const uint64_t *idx, uint64_t n,
+                     const kl_window *window, kl_c64 *z_out, const kl_opts *opts);
 
 /* kl_plan: the split and histogram strategy the renderer would use for one
  * depth and precision on the current device, after the options' overrides.

@@ -52,21 +52,58 @@ using cd = std::complex<double>;
 
 static bool finite(cd z) { return std::isfinite(z.real()) && std::isfinite(z.imag()); }
 
-// Attracting fixed point of [[a, b], [c, d]] (det 1): the eigenvector
-// (lambda - d, c) of the eigenvalue of larger modulus; lambda =
-// (tr +- sqrt(tr^2 - 4)) / 2.  Equal moduli (parabolic, elliptic) take the
-// "+" eigenvalue.
-static int attracting_point(const cd m[4], cd* out) {
+// Attracting fixed point of [[a, b], [c, d]] (det 1) on the Riemann sphere.
+// c != 0: of the two roots z of c z^2 + (d - a) z - b = 0, the one where
+// |c z + d| is larger, since |g'(z)| = 1 / |c z + d|^2; equal moduli
+// (parabolic, elliptic) take the "+" root.  c == 0: z -> (a z + b) / d
+// fixes infinity, and b / (d - a) when a != d, where g' = a / d; that point
+// attracts iff |a / d| < 1, else infinity does; with a == d infinity is the
+// only fixed point, and the identity has no attracting one.
+static int attracting_point(const cd m[4], cd* out, bool* at_inf) {
     const cd a = m[0], b = m[1], c = m[2], d = m[3];
-    if (c == cd(0.0)) return KL_ESINGULAR;
+    *at_inf = false;
+    *out = cd(0.0);
+    if (c == cd(0.0)) {
+        if (d == cd(0.0)) return KL_ESINGULAR;
+        if (a == d) {
+            if (b == cd(0.0)) return KL_ESINGULAR;
+            *at_inf = true;
+            return KL_OK;
+        }
+        if (std::abs(a / d) < 1.0) {
+            *out = b / (d - a);
+            return finite(*out) ? KL_OK : KL_ESINGULAR;
+        }
+        *at_inf = true;
+        return KL_OK;
+    }
     const cd disc = (a - d) * (a - d) + 4.0 * b * c;
     const cd root = std::sqrt(disc);
     const cd zp = ((a - d) + root) / (2.0 * c);
     const cd zm = ((a - d) - root) / (2.0 * c);
-    // |g'(z)| = 1 / |c z + d|^2: the attracting point has the larger |c z + d|
     const double kp = std::abs(c * zp + d), km = std::abs(c * zm + d);
     *out = km > kp ? zm : zp;
     return finite(*out) ? KL_OK : KL_ESINGULAR;
+}
+
+static void inverse2(const cd m[4], cd out[4]) {
+    const cd det = m[0] * m[3] - m[1] * m[2];
+    out[0] = m[3] / det;
+    out[1] = -m[1] / det;
+    out[2] = -m[2] / det;
+    out[3] = m[0] / det;
+}
+
+static void store_gens(const cd g[4][4], const cd fix[4], const bool inf[4], Gens* G) {
+    G->inf_mask = 0;
+    for (int k = 0; k < 4; ++k) {
+        G->g[k].a = {g[k][0].real(), g[k][0].imag()};
+        G->g[k].b = {g[k][1].real(), g[k][1].imag()};
+        G->g[k].c = {g[k][2].real(), g[k][2].imag()};
+        G->g[k].d = {g[k][3].real(), g[k][3].imag()};
+        G->fix[k] = {fix[k].real(), fix[k].imag()};
+        if (inf[k]) G->inf_mask |= 1u << k;
+    }
 }
 
 // Trace recipe: tab solves tab^2 - ta tb tab + ta^2 + tb^2 = 0, root
@@ -87,23 +124,17 @@ static int recipe(cd ta, cd tb, cd* tab_out, cd g[4][4], cd fix[4]) {
     const cd a[4] = {ta / 2.0, (ta * tab - 2.0 * tb + 4.0 * i1) / (tp * q),
                      (ta * tab - 2.0 * tb - 4.0 * i1) * q / tm, ta / 2.0};
     const cd b[4] = {(tb - 2.0 * i1) / 2.0, tb / 2.0, tb / 2.0, (tb + 2.0 * i1) / 2.0};
-    auto inverse = [](const cd m[4], cd out[4]) {
-        const cd det = m[0] * m[3] - m[1] * m[2];
-        out[0] = m[3] / det;
-        out[1] = -m[1] / det;
-        out[2] = -m[2] / det;
-        out[3] = m[0] / det;
-    };
     for (int j = 0; j < 4; ++j) {
         g[0][j] = a[j];
         g[1][j] = b[j];
     }
-    inverse(a, g[2]);
-    inverse(b, g[3]);
+    inverse2(a, g[2]);
+    inverse2(b, g[3]);
     for (int k = 0; k < 4; ++k) {
         for (int j = 0; j < 4; ++j)
             if (!finite(g[k][j])) return fail(KL_ESINGULAR, "generator %d not finite", k);
-        if (attracting_point(g[k], &fix[k]) != KL_OK)
+        bool at_inf;
+        if (attracting_point(g[k], &fix[k], &at_inf) != KL_OK || at_inf)
             return fail(KL_ESINGULAR, "generator %d has no finite attracting fixed point", k);
     }
     *tab_out = tab;
@@ -116,14 +147,37 @@ static int make_gens(kl_c64 ta, kl_c64 tb, Gens* G, cd* tab_out = nullptr) {
         return fail(KL_EINVAL, "traces must be finite");
     int rc = recipe(cd(ta.re, ta.im), cd(tb.re, tb.im), &tab, g, fix);
     if (rc) return rc;
-    for (int k = 0; k < 4; ++k) {
-        G->g[k].a = {g[k][0].real(), g[k][0].imag()};
-        G->g[k].b = {g[k][1].real(), g[k][1].imag()};
-        G->g[k].c = {g[k][2].real(), g[k][2].imag()};
-        G->g[k].d = {g[k][3].real(), g[k][3].imag()};
-        G->fix[k] = {fix[k].real(), fix[k].imag()};
-    }
+    const bool inf[4] = {false, false, false, false};
+    store_gens(g, fix, inf, G);
     if (tab_out) *tab_out = tab;
+    return KL_OK;
+}
+
+// Group of two explicit generators a = ab[0..3], b = ab[4..7] (row major),
+// each scaled by 1/sqrt(det) to determinant 1, with A, B their inverses.
+static int make_gens_ab(const kl_c64* ab, Gens* G) {
+    if (!ab) return fail(KL_EINVAL, "generator array is NULL");
+    cd g[4][4], fix[4];
+    bool inf[4];
+    for (int k = 0; k < 2; ++k) {
+        for (int j = 0; j < 4; ++j) {
+            g[k][j] = cd(ab[4 * k + j].re, ab[4 * k + j].im);
+            if (!finite(g[k][j])) return fail(KL_EINVAL, "generator entries must be finite");
+        }
+        const cd det = g[k][0] * g[k][3] - g[k][1] * g[k][2];
+        if (det == cd(0.0)) return fail(KL_ESINGULAR, "generator %c has determinant 0", k ? 'b' : 'a');
+        const cd r = std::sqrt(det);
+        for (int j = 0; j < 4; ++j) g[k][j] /= r;
+    }
+    inverse2(g[0], g[2]);
+    inverse2(g[1], g[3]);
+    for (int k = 0; k < 4; ++k) {
+        for (int j = 0; j < 4; ++j)
+            if (!finite(g[k][j])) return fail(KL_ESINGULAR, "generator %d not finite", k);
+        if (attracting_point(g[k], &fix[k], &inf[k]) != KL_OK)
+            return fail(KL_ESINGULAR, "generator %d has no attracting fixed point", k);
+    }
+    store_gens(g, fix, inf, G);
     return KL_OK;
 }
 
@@ -247,8 +301,9 @@ struct SetTables {
 
 static size_t round16(size_t x) { return (x + 15) & ~size_t(15); }
 
-static int build_tables(const Gens& G, const Split& sp, int precision, int force_homog, Temp& tmp, SetTables* out,
-                        uint32_t* clear_image = nullptr, uint64_t bins = 0, uint64_t* clear_dropped = nullptr) {
+static int build_tables(const Gens& G, const Split& sp, int precision, int force_homog, int seed, Temp& tmp,
+                        SetTables* out, uint32_t* clear_image = nullptr, uint64_t bins = 0,
+                        uint64_t* clear_dropped = nullptr) {
     const uint64_t np = sp.k ? num_words(sp.k) : 0;
     const uint64_t nt = num_words(sp.r);
     const size_t esz = precision == KL_PREC_FP64 ? sizeof(c64) : sizeof(c32);
@@ -267,6 +322,7 @@ static int build_tables(const Gens& G, const Split& sp, int precision, int force
     j.k = sp.k;
     j.r = sp.r;
     j.force_homog = force_homog;
+    j.seed = seed;
     j.prefix = np ? (m64*)base : nullptr;
     j.last = np ? base + off_last : nullptr;
     j.aff = base + off_aff;
@@ -357,6 +413,9 @@ static void store_tuned(const Tuned& t) {
     }
 }
 
+// Seed of every word for the suffix tables: -1 (each word's own) or a generator.
+static int seed_index(const kl_opts& o) { return o.seed_mode >= KL_SEED_A ? o.seed_mode - KL_SEED_A : -1; }
+
 // Options with the tuned plan filled in where the caller left the planner's choice.
 static kl_opts apply_tuned(const kl_opts& o, int depth, const kl_window* w) {
     (void)w;
@@ -383,7 +442,7 @@ static int render_depth(const Gens& G, const Fold& f, int depth, uint64_t lo, ui
     Temp tmp(s);
     SetTables st;
     const uint64_t bins = (uint64_t)w->width * w->height;
-    if ((rc = build_tables(G, sp, o.precision, o.suffix_form, tmp, &st, clear ? image : nullptr, bins,
+    if ((rc = build_tables(G, sp, o.precision, o.suffix_form, seed_index(o), tmp, &st, clear ? image : nullptr, bins,
                            clear ? dropped : nullptr)))
         return rc;
     if (lo >= hi) return KL_OK;
@@ -441,6 +500,8 @@ static int check_opts_common(const kl_opts& o) {
     if (o.hist_mode < KL_HIST_AUTO || o.hist_mode > KL_HIST_LDS) return fail(KL_EINVAL, "hist_mode %d", o.hist_mode);
     if (o.waves_per_cu < 0 || o.waves_per_cu > 32) return fail(KL_EINVAL, "waves_per_cu %d outside 0..32", o.waves_per_cu);
     if (o.head_form < 0 || o.head_form > 2) return fail(KL_EINVAL, "head_form %d outside 0..2", o.head_form);
+    if (o.seed_mode < KL_SEED_OWN || o.seed_mode > KL_SEED_INV_B)
+        return fail(KL_EINVAL, "seed_mode %d outside 0..5", o.seed_mode);
     return KL_OK;
 }
 
@@ -544,9 +605,19 @@ int kl_plan(int depth, int precision, const kl_window* window, const kl_opts* op
     return KL_OK;
 }
 
-int kl_render_ex(kl_c64 ta, kl_c64 tb, int depth, const kl_window* window, uint32_t* image_out,
-                 const kl_opts* opts) {
-    kl_opts o = opts ? *opts : default_opts();
+}  // extern "C"
+
+namespace kl {
+
+// Index space of a render: words [first, first + count) of depths min_depth..depth.
+struct RenderSpan {
+    int min_depth;
+    uint64_t first, count;
+};
+
+// Every check of a render that needs no group; nothing is enqueued.
+static int check_render(int depth, const kl_window* window, const uint32_t* image_out, const kl_opts& o,
+                        RenderSpan* span) {
     if (depth < 1 || depth > KL_MAX_DEPTH) return fail(KL_EINVAL, "depth %d outside 1..40", depth);
     int rc = check_window(window);
     if (rc) return rc;
@@ -574,14 +645,31 @@ int kl_render_ex(kl_c64 ta, kl_c64 tb, int depth, const kl_window* window, uint3
         const kl_opts od = d == depth ? o : opts_for_depth(o, d);
         if ((rc = plan_split(d, od.precision, od.tail_len, od.lane_len, &sp))) return rc;
     }
-    Gens G;
-    if ((rc = make_gens(ta, tb, &G))) return rc;
+    *span = {min_depth, first, count};
+    return KL_OK;
+}
+
+// The render itself, once every argument has been checked.  KL_SEED_ALL is
+// four renders of the same words, one per generator's fixed point (the
+// paper's index-search loop), accumulated.
+static int render_run(const Gens& G, int depth, const kl_window* window, uint32_t* image_out, const kl_opts& o,
+                      const RenderSpan& span) {
+    int rc;
+    if (o.seed_mode == KL_SEED_ALL) {
+        for (int q = 0; q < 4; ++q) {
+            kl_opts oq = o;
+            oq.seed_mode = KL_SEED_A + q;
+            oq.accumulate = o.accumulate || q > 0;
+            if ((rc = render_run(G, depth, window, image_out, oq, span))) return rc;
+        }
+        return KL_OK;
+    }
     const Fold f = make_fold(window, o.head_form);
     hipStream_t s = (hipStream_t)o.stream;
     bool clear = !o.accumulate;
     uint64_t offset = 0;
-    const uint64_t end = first + count;
-    for (int d = min_depth; d <= depth; ++d) {
+    const uint64_t first = span.first, end = span.first + span.count;
+    for (int d = span.min_depth; d <= depth; ++d) {
         const uint64_t n = num_words(d);
         const uint64_t lo = first > offset ? first - offset : 0;
         const uint64_t hi = end - offset < n ? end - offset : n;
@@ -598,31 +686,26 @@ int kl_render_ex(kl_c64 ta, kl_c64 tb, int depth, const kl_window* window, uint3
     return KL_OK;
 }
 
-int kl_render(kl_c64 ta, kl_c64 tb, int depth, const kl_window* window, uint32_t* image_out) {
-    int rc = kl_render_ex(ta, tb, depth, window, image_out, nullptr);
-    if (rc) return rc;
-    hipError_t e = hipStreamSynchronize(nullptr);
-    return e == hipSuccess ? KL_OK : hip_fail(e, "render");
-}
-
-int kl_eval_ex(kl_c64 ta, kl_c64 tb, int depth, const uint64_t* idx, uint64_t n, const kl_window* window,
-               kl_c64* z_out, const kl_opts* opts) {
-    kl_opts o = opts ? *opts : default_opts();
-    if (depth >= 1 && depth <= KL_MAX_DEPTH) o = apply_tuned(o, depth, window);
+// Every check of an evaluation that needs no group.
+static int check_eval(int depth, const uint64_t* idx, uint64_t n, const kl_window* window, const kl_c64* z_out,
+                      const kl_opts& o, Split* sp) {
     if (depth < 1 || depth > KL_MAX_DEPTH) return fail(KL_EINVAL, "depth %d outside 1..40", depth);
     int rc = check_opts_common(o);
     if (rc) return rc;
+    if (o.seed_mode == KL_SEED_ALL) return fail(KL_EINVAL, "KL_SEED_ALL gives four values per word; evaluate one seed at a time");
     if (window && (rc = check_window(window))) return rc;
+    if (n && (!idx || !z_out)) return fail(KL_EINVAL, "idx and z_out must not be NULL");
+    return plan_split(depth, o.precision, o.tail_len, o.lane_len, sp);
+}
+
+static int eval_run(const Gens& G, const Split& sp, const uint64_t* idx, uint64_t n, const kl_window* window,
+                    kl_c64* z_out, const kl_opts& o) {
     if (n == 0) return KL_OK;
-    if (!idx || !z_out) return fail(KL_EINVAL, "idx and z_out must not be NULL");
-    Split sp;
-    if ((rc = plan_split(depth, o.precision, o.tail_len, o.lane_len, &sp))) return rc;
-    Gens G;
-    if ((rc = make_gens(ta, tb, &G))) return rc;
     hipStream_t s = (hipStream_t)o.stream;
     Temp tmp(s);
     SetTables st;
-    if ((rc = build_tables(G, sp, o.precision, o.suffix_form, tmp, &st))) return rc;
+    int rc;
+    if ((rc = build_tables(G, sp, o.precision, o.suffix_form, seed_index(o), tmp, &st))) return rc;
     EvalJob job{};
     job.sp = sp;
     job.precision = o.precision;
@@ -635,6 +718,98 @@ int kl_eval_ex(kl_c64 ta, kl_c64 tb, int depth, const uint64_t* idx, uint64_t n,
     job.out = (c64*)z_out;
     hipError_t e = launch_eval(job, s);
     if (e != hipSuccess) return hip_fail(e, "eval kernel");
+    return KL_OK;
+}
+
+}  // namespace kl
+
+extern "C" {
+
+int kl_render_ex(kl_c64 ta, kl_c64 tb, int depth, const kl_window* window, uint32_t* image_out,
+                 const kl_opts* opts) {
+    const kl_opts o = opts ? *opts : default_opts();
+    RenderSpan span;
+    int rc = check_render(depth, window, image_out, o, &span);
+    if (rc) return rc;
+    Gens G;
+    if ((rc = make_gens(ta, tb, &G))) return rc;
+    return render_run(G, depth, window, image_out, o, span);
+}
+
+int kl_render_group_ex(const kl_c64* ab, int depth, const kl_window* window, uint32_t* image_out,
+                       const kl_opts* opts) {
+    const kl_opts o = opts ? *opts : default_opts();
+    RenderSpan span;
+    int rc = check_render(depth, window, image_out, o, &span);
+    if (rc) return rc;
+    Gens G;
+    if ((rc = make_gens_ab(ab, &G))) return rc;
+    return render_run(G, depth, window, image_out, o, span);
+}
+
+int kl_render(kl_c64 ta, kl_c64 tb, int depth, const kl_window* window, uint32_t* image_out) {
+    int rc = kl_render_ex(ta, tb, depth, window, image_out, nullptr);
+    if (rc) return rc;
+    hipError_t e = hipStreamSynchronize(nullptr);
+    return e == hipSuccess ? KL_OK : hip_fail(e, "render");
+}
+
+int kl_eval_ex(kl_c64 ta, kl_c64 tb, int depth, const uint64_t* idx, uint64_t n, const kl_window* window,
+               kl_c64* z_out, const kl_opts* opts) {
+    kl_opts o = opts ? *opts : default_opts();
+    if (depth >= 1 && depth <= KL_MAX_DEPTH) o = apply_tuned(o, depth, window);
+    Split sp;
+    int rc = check_eval(depth, idx, n, window, z_out, o, &sp);
+    if (rc || n == 0) return rc;
+    Gens G;
+    if ((rc = make_gens(ta, tb, &G))) return rc;
+    return eval_run(G, sp, idx, n, window, z_out, o);
+}
+
+int kl_eval_group_ex(const kl_c64* ab, int depth, const uint64_t* idx, uint64_t n, const kl_window* window,
+                     kl_c64* z_out, const kl_opts* opts) {
+    kl_opts o = opts ? *opts : default_opts();
+    if (depth >= 1 && depth <= KL_MAX_DEPTH) o = apply_tuned(o, depth, window);
+    Split sp;
+    int rc = check_eval(depth, idx, n, window, z_out, o, &sp);
+    if (rc) return rc;
+    Gens G;
+    if ((rc = make_gens_ab(ab, &G))) return rc;
+    return eval_run(G, sp, idx, n, window, z_out, o);
+}
+
+int kl_group_seeds(const kl_c64* ab, kl_c64* gens_out, kl_c64* seeds_out) {
+    Gens G;
+    int rc = make_gens_ab(ab, &G);
+    if (rc) return rc;
+    for (int k = 0; k < 4; ++k) {
+        if (gens_out) {
+            gens_out[4 * k + 0] = {G.g[k].a.re, G.g[k].a.im};
+            gens_out[4 * k + 1] = {G.g[k].b.re, G.g[k].b.im};
+            gens_out[4 * k + 2] = {G.g[k].c.re, G.g[k].c.im};
+            gens_out[4 * k + 3] = {G.g[k].d.re, G.g[k].d.im};
+        }
+        if (seeds_out) {
+            const bool inf = (G.inf_mask >> k) & 1u;
+            seeds_out[2 * k] = inf ? kl_c64{1.0, 0.0} : kl_c64{G.fix[k].re, G.fix[k].im};
+            seeds_out[2 * k + 1] = inf ? kl_c64{0.0, 0.0} : kl_c64{1.0, 0.0};
+        }
+    }
+    return KL_OK;
+}
+
+// Maskit's parametrisation: a = [[-i mu, -i], [-i, 0]], b = [[1, 2], [0, 1]].
+int kl_maskit_generators(kl_c64 mu, kl_c64* ab_out) {
+    if (!ab_out) return fail(KL_EINVAL, "ab_out is NULL");
+    if (!std::isfinite(mu.re) || !std::isfinite(mu.im)) return fail(KL_EINVAL, "mu must be finite");
+    ab_out[0] = {mu.im, -mu.re};  // -i mu
+    ab_out[1] = {0.0, -1.0};
+    ab_out[2] = {0.0, -1.0};
+    ab_out[3] = {0.0, 0.0};
+    ab_out[4] = {1.0, 0.0};
+    ab_out[5] = {2.0, 0.0};
+    ab_out[6] = {0.0, 0.0};
+    ab_out[7] = {1.0, 0.0};
     return KL_OK;
 }
 
@@ -657,6 +832,16 @@ int kl_render_many_ex(int n, const kl_c64* ta, const kl_c64* tb, const int* dept
     if (!images_out) return fail(KL_EINVAL, "images_out is NULL");
     if ((rc = check_opts_common(o))) return rc;
     if (o.min_depth != 0 || o.use_range) return fail(KL_EINVAL, "min_depth and use_range must be 0 for kl_render_many");
+    if (o.seed_mode == KL_SEED_ALL) {
+        // the paper's loop over the generators' fixed points: four batches, accumulated
+        for (int q = 0; q < 4; ++q) {
+            kl_opts oq = o;
+            oq.seed_mode = KL_SEED_A + q;
+            oq.accumulate = o.accumulate || q > 0;
+            if ((rc = kl_render_many_ex(n, ta, tb, depth, window, images_out, &oq))) return rc;
+        }
+        return KL_OK;
+    }
     const uint64_t bins = (uint64_t)window->width * window->height;
     std::vector<Gens> gens(n);
     std::vector<Split> splits(n);
@@ -762,6 +947,7 @@ int kl_render_many_ex(int n, const kl_c64* ta, const kl_c64* tb, const int* dept
     job.max_prefix = max_prefix;
     job.max_tail = max_tail;
     job.force_homog = o.suffix_form;
+    job.seed = seed_index(o);
     job.count_dropped = o.dropped_out != nullptr;
     if ((e = launch_batch_tables(job, s)) != hipSuccess) return hip_fail(e, "batch tables");
     if ((e = launch_render_batch(job, s)) != hipSuccess) return hip_fail(e, "batch render");

@@ -192,18 +192,25 @@ __device__ inline void scale_pow2(cpx<T>& u, cpx<T>& v) {
 }
 
 // Suffix point of tail t (length r, r <= 8): the homogeneous pair (u, v)
-// of G_{y1}(...G_{y(r-1)}(fix(yr))) walked right to left in precision T
-// from the rounded seed with the rounded generators (G_{yr} fixes its own
-// seed and is not applied), rescaled by powers of two after every step;
-// and its affine form y = u / v.
+// of G_{y1}(...G_{yr}(z0)) walked right to left in precision T from the
+// rounded seed with the rounded generators, rescaled by powers of two after
+// every step; and its affine form y = u / v.  seed < 0: z0 is the attracting
+// fixed point of the tail's last letter yr, which G_{yr} fixes, so that map
+// is not applied; seed = 0..3: z0 is that generator's attracting fixed
+// point and every map is applied.  A seed at infinity starts as (1, 0).
 template <typename T>
-__device__ inline void tail_entry(const Gens& g, int r, uint32_t t, cpx<T>* __restrict__ affine,
+__device__ inline void tail_entry(const Gens& g, int r, uint32_t t, int seed, cpx<T>* __restrict__ affine,
                                   cpx<T>* __restrict__ homog, uint32_t* __restrict__ flags, bool atomic = true) {
     const uint64_t w = decode_packed(t, r);
     const int last = (int)((w >> (2 * (r - 1))) & 3);
-    cpx<T> u = {(T)g.fix[last].re, (T)g.fix[last].im};
+    const int s = seed < 0 ? last : seed;
+    cpx<T> u = {(T)g.fix[s].re, (T)g.fix[s].im};
     cpx<T> v = {T(1), T(0)};
-    for (int j = r - 2; j >= 0; --j) {
+    if ((g.inf_mask >> s) & 1u) {
+        u = {T(1), T(0)};
+        v = {T(0), T(0)};
+    }
+    for (int j = seed < 0 ? r - 2 : r - 1; j >= 0; --j) {
         const m64& G = g.g[(w >> (2 * j)) & 3];
         const cpx<T> a = {(T)G.a.re, (T)G.a.im}, b = {(T)G.b.re, (T)G.b.im};
         const cpx<T> c = {(T)G.c.re, (T)G.c.im}, d = {(T)G.d.re, (T)G.d.im};
@@ -235,7 +242,7 @@ __device__ inline void tail_entry(const Gens& g, int r, uint32_t t, cpx<T>* __re
 // that form is forced), so no flag has to be cleared beforehand.
 struct SetupArgs {
     Gens g;
-    int k, r;
+    int k, r, seed;
     uint32_t n_prefix, n_tail, nb_tail;
     m64* prefix;
     uint8_t* last;
@@ -265,7 +272,7 @@ __global__ __launch_bounds__(256) void setup_kernel(const SetupArgs a) {
     if (blockIdx.x < a.nb_tail) {
         const uint32_t t = blockIdx.x * 256 + threadIdx.x;
         uint32_t bad = 0;
-        if (t < a.n_tail) tail_entry<T>(a.g, a.r, t, (cpx<T>*)a.aff, (cpx<T>*)a.hom, &bad, false);
+        if (t < a.n_tail) tail_entry<T>(a.g, a.r, t, a.seed, (cpx<T>*)a.aff, (cpx<T>*)a.hom, &bad, false);
         bad = __syncthreads_or(bad);
         if (threadIdx.x == 0) {
             a.flags[blockIdx.x] = (bad || a.force_homog) ? 1u : 0u;
@@ -939,13 +946,14 @@ __global__ __launch_bounds__(256) void prefix_table_batch_kernel(const SetDesc* 
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void tail_table_batch_kernel(const SetDesc* __restrict__ sets, int force_homog) {
+__global__ __launch_bounds__(256) void tail_table_batch_kernel(const SetDesc* __restrict__ sets, int force_homog,
+                                                               int seed) {
     const SetDesc& S = sets[blockIdx.y];
     const uint32_t t = blockIdx.x * 256 + threadIdx.x;
     if (t >= S.n_tail) return;
     const Gens g = S.gens;
     uint32_t* flags = (uint32_t*)S.tab.tail_flags;
-    tail_entry<T>(g, S.sp.r, t, (cpx<T>*)S.tab.tail, (cpx<T>*)S.tail_homog, flags);
+    tail_entry<T>(g, S.sp.r, t, seed, (cpx<T>*)S.tab.tail, (cpx<T>*)S.tail_homog, flags);
     if (force_homog && t == 0) atomicOr(flags, 1u);
 }
 
@@ -958,9 +966,11 @@ hipError_t launch_batch_tables(const BatchJob& job, hipStream_t s) {
     }
     dim3 grid((job.max_tail + 255) / 256, job.n_sets);
     if (job.precision == KL_PREC_FP64)
-        hipLaunchKernelGGL(tail_table_batch_kernel<double>, grid, dim3(256), 0, s, job.sets, job.force_homog);
+        hipLaunchKernelGGL(tail_table_batch_kernel<double>, grid, dim3(256), 0, s, job.sets, job.force_homog,
+                           job.seed);
     else
-        hipLaunchKernelGGL(tail_table_batch_kernel<float>, grid, dim3(256), 0, s, job.sets, job.force_homog);
+        hipLaunchKernelGGL(tail_table_batch_kernel<float>, grid, dim3(256), 0, s, job.sets, job.force_homog,
+                           job.seed);
     return hipGetLastError();
 }
 
@@ -1106,6 +1116,7 @@ hipError_t launch_setup(const SetupJob& j, hipStream_t s) {
     a.g = j.gens;
     a.k = j.k;
     a.r = j.r;
+    a.seed = j.seed;
     a.n_prefix = j.k ? (uint32_t)num_words(j.k) : 0;
     a.n_tail = (uint32_t)num_words(j.r);
     a.prefix = j.prefix;

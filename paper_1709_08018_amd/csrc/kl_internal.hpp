@@ -56,8 +56,9 @@ __host__ __device__ inline mat<T> mmul(const mat<T>& x, const mat<T>& y) {
 
 // ---------------------------------------------------------------- launch args
 struct Gens {
-    m64 g[4];        // a, b, A, B  (FP64)
-    c64 fix[4];      // attracting fixed points (FP64)
+    m64 g[4];           // a, b, A, B  (FP64, determinant 1)
+    c64 fix[4];         // attracting fixed points (FP64); 0 where at infinity
+    uint32_t inf_mask;  // bit k: generator k's attracting fixed point is infinity
 };
 
 // Affine map folded into the head so the word value comes out in pixel
@@ -101,6 +102,7 @@ hipError_t launch_decode(uint64_t first, uint64_t count, int depth, uint8_t* out
 struct SetupJob {
     Gens gens;
     int precision, k, r, force_homog;
+    int seed;              // -1: each suffix from its last letter's fixed point; 0..3: that generator's
     m64* prefix;
     uint8_t* last;
     void* aff;
@@ -169,6 +171,7 @@ struct BatchJob {
     uint32_t table_bytes;          // LDS bytes of the largest suffix table (homogeneous form)
     uint32_t max_prefix, max_tail; // largest n_prefix / n_tail over the sets
     int force_homog;
+    int seed;                      // as SetupJob::seed
     int count_dropped;             // the sets' dropped counters are set
 };
 hipError_t launch_batch_tables(const BatchJob& job, hipStream_t s);

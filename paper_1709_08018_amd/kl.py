@@ -22,6 +22,7 @@ HEADERS = [HEADER, os.path.join(os.path.dirname(PKG), "include", "kl_surrogate.h
 KL_OK, KL_EINVAL, KL_ERANGE, KL_ESINGULAR, KL_EDEVICE, KL_ENOMEM = 0, -1, -2, -3, -4, -5
 PREC = {"fp32": 0, "fp64": 1}
 HIST = {"auto": 0, "runs": 1, "lds": 2}
+SEED = {"own": 0, "all": 1, "a": 2, "b": 3, "A": 4, "B": 5}
 
 
 class KLError(RuntimeError):
@@ -44,7 +45,7 @@ class Opts(ctypes.Structure):
                 ("first_idx", ctypes.c_uint64), ("count", ctypes.c_uint64), ("accumulate", ctypes.c_int),
                 ("stream", ctypes.c_void_p), ("dropped_out", ctypes.c_void_p), ("tail_len", ctypes.c_int),
                 ("lane_len", ctypes.c_int), ("hist_mode", ctypes.c_int), ("waves_per_cu", ctypes.c_int),
-                ("suffix_form", ctypes.c_int), ("head_form", ctypes.c_int),
+                ("suffix_form", ctypes.c_int), ("seed_mode", ctypes.c_int), ("head_form", ctypes.c_int),
                 ("kernel_events", ctypes.c_void_p * 2)]
 
 
@@ -81,6 +82,10 @@ def lib():
         L.kl_eval.argtypes = [c64, c64, i, vp, u64, i, vp]
         L.kl_eval_ex.argtypes = [c64, c64, i, vp, u64, W, vp, O]
         L.kl_generators.argtypes = [c64, c64, C, C, C]
+        L.kl_group_seeds.argtypes = [C, C, C]
+        L.kl_maskit_generators.argtypes = [c64, C]
+        L.kl_render_group_ex.argtypes = [C, i, W, vp, O]
+        L.kl_eval_group_ex.argtypes = [C, i, vp, u64, W, vp, O]
         L.kl_plan.argtypes = [i, i, W, O, ctypes.POINTER(Plan)]
         L.kl_autotune.argtypes = [c64, c64, i, W, i, vp, ctypes.POINTER(Plan), ctypes.POINTER(ctypes.c_double)]
         L.kl_strerror.argtypes = [i]
@@ -88,7 +93,8 @@ def lib():
         L.kl_last_error.argtypes = []
         L.kl_last_error.restype = ctypes.c_char_p
         for f in ("kl_decode", "kl_decode_ex", "kl_render", "kl_render_ex", "kl_render_many",
-                  "kl_render_many_ex", "kl_eval", "kl_eval_ex", "kl_generators", "kl_plan", "kl_autotune"):
+                  "kl_render_many_ex", "kl_eval", "kl_eval_ex", "kl_generators", "kl_plan", "kl_autotune",
+                  "kl_group_seeds", "kl_maskit_generators", "kl_render_group_ex", "kl_eval_group_ex"):
             getattr(L, f).restype = i
         sz, i64, f32 = ctypes.c_size_t, ctypes.c_int64, ctypes.c_float
         L.kl_sur_num_params.argtypes = []
@@ -150,7 +156,7 @@ def _stream(stream):
 
 def make_opts(*, min_depth=0, precision="fp32", first=None, count=None, accumulate=False, stream=None,
               dropped=None, tail_len=0, lane_len=0, hist_mode="auto", waves_per_cu=0, suffix_form=0,
-              head_form=0, kernel_events=None, use_stream=True) -> Opts:
+              head_form=0, seed="own", kernel_events=None, use_stream=True) -> Opts:
     o = Opts()
     o.min_depth = int(min_depth)
     o.precision = PREC[precision] if isinstance(precision, str) else int(precision)
@@ -167,6 +173,7 @@ def make_opts(*, min_depth=0, precision="fp32", first=None, count=None, accumula
     o.waves_per_cu = int(waves_per_cu)
     o.suffix_form = int(suffix_form)
     o.head_form = int(head_form)
+    o.seed_mode = SEED[seed] if isinstance(seed, str) else int(seed)
     if kernel_events is not None:
         o.kernel_events[0] = kernel_events[0]
         o.kernel_events[1] = kernel_events[1]
@@ -358,3 +365,51 @@ def gemm_bf16(M, N, K, A, lda_m, lda_k, B, ldb_k, ldb_n, C, ldc, bias=None, relu
     _check(lib().kl_gemm_bf16(M, N, K, _p(A), lda_m, lda_k, _p(B), ldb_k, ldb_n, _p(C), ldc, _p(bias), int(relu),
                               int(accumulate), _stream(stream)))
     return C
+
+
+# ---------------------------------------------------------------- explicit groups
+def _ab(ab):
+    """Two generators (a, b) as 2x2 complex arrays -> the 8-entry c64 array the library takes."""
+    ab = np.asarray(ab, np.complex128).reshape(8)
+    return (c64 * 8)(*[c64(z.real, z.imag) for z in ab])
+
+
+def maskit_generators(mu) -> np.ndarray:
+    """Maskit's a, b for parameter mu: (2, 2, 2) complex."""
+    out = (c64 * 8)()
+    _check(lib().kl_maskit_generators(_c(mu), out))
+    return np.array([complex(z.re, z.im) for z in out]).reshape(2, 2, 2)
+
+
+def group_seeds(ab):
+    """(gens[4, 2, 2], seeds[4, 2]) of a group given by a, b: the normalised maps and
+    each generator's attracting fixed point as a homogeneous pair (u, v)."""
+    g = (c64 * 16)()
+    sd = (c64 * 8)()
+    _check(lib().kl_group_seeds(_ab(ab), g, sd))
+    return (np.array([complex(z.re, z.im) for z in g]).reshape(4, 2, 2),
+            np.array([complex(z.re, z.im) for z in sd]).reshape(4, 2))
+
+
+def render_group(ab, depth: int, window, image: torch.Tensor | None = None, **opts) -> torch.Tensor:
+    """kl_render_ex for a group given by its generators a, b."""
+    w = make_window(window)
+    if image is None:
+        image = new_image(w)
+    o = make_opts(**opts)
+    _check(lib().kl_render_group_ex(_ab(ab), int(depth), ctypes.byref(w), image.data_ptr(), ctypes.byref(o)))
+    return image
+
+
+def eval_group(ab, depth: int, idx, precision="fp32", window=None, **opts) -> torch.Tensor:
+    """kl_eval_ex for a group given by its generators a, b."""
+    if not isinstance(idx, torch.Tensor):
+        idx = torch.as_tensor(np.ascontiguousarray(idx, np.uint64).view(np.int64))
+    idx = idx.to(device=_device(), dtype=torch.int64).contiguous()
+    n = idx.numel()
+    out = torch.empty((n, 2), dtype=torch.float64, device=_device())
+    o = make_opts(precision=precision, **opts)
+    w = None if window is None else ctypes.byref(make_window(window))
+    _check(lib().kl_eval_group_ex(_ab(ab), int(depth), idx.data_ptr() if n else None, n, w,
+                                  out.data_ptr() if n else None, ctypes.byref(o)))
+    return out

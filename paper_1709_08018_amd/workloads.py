@@ -18,6 +18,12 @@ Workloads (traces are those of the trace recipe; windows are
                         512 x 512 over [-2, 2]^2 each
   surrogate             parameter sets drawn as batch256 at depth 14,
                         128 x 128 occupancy over [-2, 2]^2
+  maskit_tiling_d14     Maskit's group at mu = -0.097 + 1.838i (the
+                        parameter of the paper's figures), tiling mode over
+                        depths 1..14, every generator's fixed point fed to
+                        every word (the paper's index-search loop);
+                        1024 x 1024 over one period of the translation b,
+                        [-1.05, 1.05] x [-0.1, 2.0]
 """
 from __future__ import annotations
 
@@ -67,6 +73,10 @@ QUASIFUCHSIAN_D22 = Workload("quasifuchsian_d22", C2_TA, C2_TB, 22, 22,
 BATCH_WINDOW = Window(-2.0, 2.0, -2.0, 2.0, 512, 512)
 SURROGATE_WINDOW = Window(-2.0, 2.0, -2.0, 2.0, 128, 128)
 SURROGATE_DEPTH = 14
+MASKIT_MU = complex(-0.097, 1.838)
+# ta holds Maskit's parameter mu for this workload; tb is unused
+MASKIT_D14 = Workload("maskit_tiling_d14", MASKIT_MU, complex(0.0, 0.0), 14, 1,
+                      Window(-1.05, 1.05, -0.1, 2.0, 1024, 1024))
 
 
 def draw_param_sets(n: int, seed: int, depth_range=(12, 18)):

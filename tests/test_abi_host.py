@@ -156,3 +156,84 @@ def test_strerror_names_every_code():
     for code in (0, -1, -2, -3, -4, -5):
         assert L.kl_strerror(code)
     assert L.kl_strerror(-99) == b"unknown error"
+
+
+# ---------------------------------------------------------------- explicit groups and seeds
+MU_FIG = complex(-0.097, 1.838)
+
+
+def _same_map(m, r):
+    """2x2 matrices m, r define the same Moebius map: m = c r for some c != 0."""
+    k = np.argmax(np.abs(r))
+    c = m.flat[k] / r.flat[k]
+    return np.allclose(m, c * r, rtol=1e-13, atol=1e-14)
+
+
+@pytest.mark.parametrize("mu", [MU_FIG, 2j, complex(0.3, 1.95)])
+def test_maskit_group_agrees_with_reference(mu):
+    ab = kl.maskit_generators(mu)
+    G = O.group_maskit(mu)
+    assert _same_map(ab[0], G.gens[0]) and _same_map(ab[1], G.gens[1])
+    gens, seeds = kl.group_seeds(ab)
+    for k in range(4):
+        assert _same_map(gens[k], G.gens[k])
+        np.testing.assert_allclose(np.linalg.det(gens[k]), 1.0, atol=1e-13)
+    pts = G.seed_points()
+    for k in range(4):
+        u, v = seeds[k]
+        if np.isinf(pts[k]):
+            assert v == 0 and u != 0
+        else:
+            assert abs(u / v - pts[k]) <= 1e-12 * max(1, abs(pts[k]))
+
+
+@pytest.mark.parametrize("ta,tb", _param_sets()[:8])
+def test_explicit_group_of_recipe_generators_agrees_with_reference(ta, tb):
+    _, g, _ = kl.generators(ta, tb)
+    gens, seeds = kl.group_seeds(np.stack([g[0], g[1]]))
+    R = O.group_recipe(complex(ta), complex(tb))
+    pts = R.seed_points()
+    for k in range(4):
+        assert _same_map(gens[k], R.gens[k])
+        assert abs(seeds[k, 0] / seeds[k, 1] - pts[k]) <= 1e-11 * max(1, abs(pts[k]))
+
+
+def test_affine_generator_seeds_agree_with_reference():
+    a = np.array([[2, 1], [0, 0.5]], complex)
+    b = np.array([[2, 1], [1, 1]], complex)
+    _, seeds = kl.group_seeds(np.stack([a, b]))
+    pts = O.group_explicit(a, b).seed_points()
+    assert seeds[0, 1] == 0 and np.isinf(pts[0])
+    for k in (1, 2, 3):
+        assert abs(seeds[k, 0] / seeds[k, 1] - pts[k]) < 1e-14
+
+
+def test_group_argument_errors():
+    w = _win()
+    ab = kl._ab(kl.maskit_generators(MU_FIG))
+    assert L.kl_group_seeds(None, None, None) == kl.KL_EINVAL
+    assert L.kl_maskit_generators(kl._c(complex(float("nan"), 0)), (kl.c64 * 8)()) == kl.KL_EINVAL
+    assert L.kl_maskit_generators(kl._c(MU_FIG), None) == kl.KL_EINVAL
+    singular = kl._ab(np.array([[[1, 2], [2, 4]], [[1, 2], [0, 1]]], complex))
+    assert L.kl_group_seeds(singular, None, None) == kl.KL_ESINGULAR
+    identity = kl._ab(np.array([[[1, 0], [0, 1]], [[1, 2], [0, 1]]], complex))
+    assert L.kl_group_seeds(identity, None, None) == kl.KL_ESINGULAR
+    nonfinite = kl._ab(np.array([[[np.nan, 0], [0, 1]], [[1, 2], [0, 1]]], complex))
+    assert L.kl_group_seeds(nonfinite, None, None) == kl.KL_EINVAL
+    o = kl.make_opts(use_stream=False)
+    assert L.kl_render_group_ex(ab, 0, ctypes.byref(w), FAKE, ctypes.byref(o)) == kl.KL_EINVAL
+    assert L.kl_render_group_ex(ab, 10, ctypes.byref(w), None, ctypes.byref(o)) == kl.KL_EINVAL
+    assert L.kl_render_group_ex(singular, 10, ctypes.byref(w), FAKE, ctypes.byref(o)) == kl.KL_ESINGULAR
+    assert L.kl_eval_group_ex(ab, 41, FAKE, 1, None, FAKE, ctypes.byref(o)) == kl.KL_EINVAL
+    assert L.kl_eval_group_ex(None, 10, FAKE, 1, None, FAKE, ctypes.byref(o)) == kl.KL_EINVAL
+
+
+def test_seed_mode_errors():
+    w = _win()
+    for bad in (-1, 6):
+        o = kl.make_opts(seed=bad, use_stream=False)
+        assert _render(window=w, opts=o) == kl.KL_EINVAL
+    o = kl.make_opts(seed="all", use_stream=False)
+    assert L.kl_eval_ex(kl._c(wl.C2_TA), kl._c(wl.C2_TB), 10, FAKE, 1, None, FAKE,
+                        ctypes.byref(o)) == kl.KL_EINVAL
+    assert "four values" in L.kl_last_error().decode()

@@ -1,0 +1,187 @@
+"""GPU path vs the CPU reference for the seed modes and for groups given by
+their generators (Maskit's embedding of the paper's figures), through the
+C ABI.
+
+Maskit's group has a translation among its generators: seeds at infinity,
+heads whose map fixes infinity (the ratio fallback of the pole form) and
+suffix points at infinity (the homogeneous suffix table) all occur, so these
+cases run the renderer's rarely used paths on a real workload.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_1709_08018_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+if torch.cuda.is_available():
+    from paper_1709_08018_amd import kl
+
+C2 = (wl.C2_TA, wl.C2_TB)
+C1 = (wl.C1_TA, wl.C1_TB)
+WIN_C2 = wl.QUASIFUCHSIAN_D18.window.as_tuple()
+WIN_MASKIT = wl.MASKIT_D14.window.as_tuple()
+MU = wl.MASKIT_MU
+SEEDS = ["a", "b", "A", "B"]
+
+
+def _z(t):
+    a = t.cpu().numpy()
+    return a[:, 0] + 1j * a[:, 1]
+
+
+def _ref_pixels(z, win):
+    x0, x1, y0, y1, W, H = win
+    return (z.real - x0) * W / (x1 - x0), (z.imag - y0) * H / (y1 - y0)
+
+
+def _bins_from_pixels(px, py, win):
+    W, H = win[4], win[5]
+    ok = np.isfinite(px) & np.isfinite(py) & (px >= 0) & (px < W) & (py >= 0) & (py < H)
+    img = np.zeros(W * H, np.int64)
+    np.add.at(img, np.floor(py[ok]).astype(np.int64) * W + np.floor(px[ok]).astype(np.int64), 1)
+    return img.reshape(H, W), int((~ok).sum())
+
+
+def _rel_err(z, zr):
+    fin = np.isfinite(zr)
+    assert np.isfinite(z[fin]).all()
+    return (np.abs(z[fin] - zr[fin]) / np.maximum(1, np.abs(zr[fin]))).max()
+
+
+# ---------------------------------------------------------------- seed modes
+@pytest.mark.parametrize("seed", SEEDS)
+def test_seeded_fp64_values(seed):
+    G = O.group_recipe(*C2)
+    p = SEEDS.index(seed)
+    idx = np.arange(kl.num_words(10), dtype=np.uint64)
+    assert _rel_err(_z(kl.eval_values(*C2, 10, idx, precision="fp64", seed=seed)),
+                    O.eval_group(G, 10, idx, seed=p)) < 1e-10
+    idx = wl.sample_indices(kl.num_words(18), 20000, seed=p)
+    assert _rel_err(_z(kl.eval_values(*C2, 18, idx, precision="fp64", seed=seed)),
+                    O.eval_group(G, 18, idx, seed=p)) < 1e-10
+
+
+@pytest.mark.parametrize("seed", SEEDS)
+def test_seeded_fp32_pixel_error(seed):
+    G = O.group_recipe(*C2)
+    idx = wl.sample_indices(kl.num_words(18), 100000, seed=7)
+    p = kl.eval_values(*C2, 18, idx, precision="fp32", window=WIN_C2, seed=seed).cpu().numpy()
+    fx, fy = _ref_pixels(O.eval_group(G, 18, idx, seed=SEEDS.index(seed)), WIN_C2)
+    err = np.hypot(p[:, 0] - fx, p[:, 1] - fy)
+    near = (fx > -1) & (fx < WIN_C2[4] + 1) & (fy > -1) & (fy < WIN_C2[5] + 1)
+    assert err[near].max() <= 0.25
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_seeded_image_is_histogram_of_own_bins(precision):
+    depth, win = 12, WIN_C2
+    n = kl.num_words(depth)
+    dropped = torch.zeros(1, dtype=torch.int64, device="cuda")
+    img = kl.as_u32(kl.render(*C2, depth, win, precision=precision, seed="b", dropped=dropped)).astype(np.int64)
+    p = kl.eval_values(*C2, depth, np.arange(n, dtype=np.uint64), precision=precision, window=win,
+                       seed="b").cpu().numpy()
+    ref, drop = _bins_from_pixels(p[:, 0], p[:, 1], win)
+    np.testing.assert_array_equal(img, ref)
+    assert int(dropped.item()) == drop
+
+
+@pytest.mark.parametrize("case", ["c1_tiling", "c2_d11"])
+def test_all_seeds_fp64_image_matches_reference(case):
+    """The paper's index-search loop: every word drawn once from each
+    generator's fixed point."""
+    if case == "c1_tiling":
+        (ta, tb), depth, win, mind = C1, 8, wl.FUCHSIAN_TILING_D10.window.as_tuple(), 1
+    else:
+        (ta, tb), depth, win, mind = C2, 11, WIN_C2, 11
+    dropped = torch.zeros(1, dtype=torch.int64, device="cuda")
+    img = kl.as_u32(kl.render(ta, tb, depth, win, precision="fp64", min_depth=mind, seed="all",
+                              dropped=dropped)).astype(np.int64)
+    G = O.group_recipe(complex(ta), complex(tb))
+    ref, drop, near = O.render_group(G, depth, win, seed=4, min_depth=mind, edge_tol=1e-7, nthreads=8)
+    assert int(np.abs(img - ref.astype(np.int64)).sum()) <= 2 * near
+    words = sum(kl.num_words(d) for d in range(mind, depth + 1))
+    assert int(img.sum()) + int(dropped.item()) == 4 * words
+
+
+@pytest.mark.parametrize("seed", ["B", "all"])
+def test_render_many_with_seeds_equals_single_renders(seed):
+    ta, tb, _ = wl.draw_param_sets(5, seed=31)
+    depths = np.array([12, 13, 12, 14, 9])
+    win = (-2.0, 2.0, -2.0, 2.0, 256, 256)
+    many = kl.render_many(ta, tb, depths, win, seed=seed)
+    for i in range(5):
+        one = kl.render(complex(ta[i]), complex(tb[i]), int(depths[i]), win, seed=seed)
+        assert torch.equal(many[i], one), i
+
+
+# ---------------------------------------------------------------- explicit groups
+def test_explicit_recipe_generators_give_the_recipe_values():
+    _, g, _ = kl.generators(*C2)
+    ab = np.stack([g[0], g[1]])
+    idx = wl.sample_indices(kl.num_words(16), 20000, seed=2)
+    for seed in ("own", "a", "B"):
+        za = _z(kl.eval_group(ab, 16, idx, precision="fp64", seed=seed))
+        zb = _z(kl.eval_values(*C2, 16, idx, precision="fp64", seed=seed))
+        assert (np.abs(za - zb) / np.maximum(1, np.abs(zb))).max() < 1e-10
+
+
+@pytest.mark.parametrize("seed", ["own", "b", "A"])
+def test_maskit_fp64_values(seed):
+    ab = kl.maskit_generators(MU)
+    G = O.group_maskit(MU)
+    s = -1 if seed == "own" else SEEDS.index(seed)
+    idx = np.arange(kl.num_words(9), dtype=np.uint64)
+    z = _z(kl.eval_group(ab, 9, idx, precision="fp64", seed=seed))
+    zr = O.eval_group(G, 9, idx, seed=s)
+    assert _rel_err(z, zr) < 1e-10
+    idx = wl.sample_indices(kl.num_words(14), 20000, seed=4)
+    assert _rel_err(_z(kl.eval_group(ab, 14, idx, precision="fp64", seed=seed)), O.eval_group(G, 14, idx, seed=s)) < 1e-10
+
+
+@pytest.mark.parametrize("seed", ["own", "b"])
+def test_maskit_fp32_pixel_error(seed):
+    ab = kl.maskit_generators(MU)
+    G = O.group_maskit(MU)
+    idx = wl.sample_indices(kl.num_words(14), 100000, seed=9)
+    p = kl.eval_group(ab, 14, idx, precision="fp32", window=WIN_MASKIT, seed=seed).cpu().numpy()
+    fx, fy = _ref_pixels(O.eval_group(G, 14, idx, seed=-1 if seed == "own" else SEEDS.index(seed)), WIN_MASKIT)
+    near = np.isfinite(fx) & np.isfinite(fy) & (fx > -1) & (fx < WIN_MASKIT[4] + 1) & (fy > -1) & (fy < WIN_MASKIT[5] + 1)
+    err = np.hypot(p[near, 0] - fx[near], p[near, 1] - fy[near])
+    assert near.sum() > 1000 and err.max() <= 0.25, err.max()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_maskit_tiling_image_is_histogram_of_own_bins(precision):
+    ab = kl.maskit_generators(MU)
+    depth, win = 10, WIN_MASKIT
+    dropped = torch.zeros(1, dtype=torch.int64, device="cuda")
+    img = kl.as_u32(kl.render_group(ab, depth, win, precision=precision, min_depth=1, seed="b",
+                                    dropped=dropped)).astype(np.int64)
+    ref = np.zeros_like(img)
+    drop = 0
+    for d in range(1, depth + 1):
+        p = kl.eval_group(ab, d, np.arange(kl.num_words(d), dtype=np.uint64), precision=precision, window=win,
+                          seed="b").cpu().numpy()
+        r, dr = _bins_from_pixels(p[:, 0], p[:, 1], win)
+        ref += r
+        drop += dr
+    np.testing.assert_array_equal(img, ref)
+    assert int(dropped.item()) == drop
+
+
+def test_maskit_all_seeds_fp64_image_matches_reference():
+    """The configuration of the paper's index-search figure at a smaller
+    depth: Maskit's group, tiling mode, every generator's fixed point."""
+    ab = kl.maskit_generators(MU)
+    depth, win = 9, WIN_MASKIT
+    dropped = torch.zeros(1, dtype=torch.int64, device="cuda")
+    img = kl.as_u32(kl.render_group(ab, depth, win, precision="fp64", min_depth=1, seed="all",
+                                    dropped=dropped)).astype(np.int64)
+    ref, drop, near = O.render_group(O.group_maskit(MU), depth, win, seed=4, min_depth=1, edge_tol=1e-7,
+                                     nthreads=8)
+    assert int(np.abs(img - ref.astype(np.int64)).sum()) <= 2 * near
+    assert int(img.sum()) + int(dropped.item()) == 4 * sum(kl.num_words(d) for d in range(1, depth + 1))
+    assert int(dropped.item()) == drop or abs(int(dropped.item()) - drop) <= near
