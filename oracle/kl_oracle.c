@@ -701,3 +701,282 @@ int oracle_render_group(const double *gens, const double *seeds, int seed,
     return render_group(&g, seed, depth, min_depth, x0, x1, y0, y1, width, height, first, count,
                         nthreads, edge_tol, image, dropped, near_edge);
 }
+
+/* ------------------------------------------------------------------ */
+/* indexed Cayley tables (Section 5)                                   */
+/* ------------------------------------------------------------------ */
+/*
+ * A table has states 0..S-1 and symbols 1..m; next = table[s * (m + 1) + x]
+ * (column 0, the identity symbol, is not read).  State 0 is where a walk
+ * starts and, reached again, the crash state.  A word x_1 ... x_d is read
+ * right to left (x_d first, Section 5's table walk); it is regular when no
+ * step of that walk lands in state 0.  Regular words are numbered in
+ * lexicographic order of (x_1, ..., x_d), x_1 most significant, which is the
+ * order in which the paper's scan of all m^d digit strings (Section 6)
+ * meets them.
+ *
+ * Counting: C[L][s] is the number of regular words of length L whose walk
+ * ends in state s (C[0][0] = 1: the empty walk stays in the start state).
+ * A prefix p of a word is read after the rest of the word, starting in the
+ * state the rest ended in; good_p is the set of states from which p can be
+ * read without a crash, with good_(p x)(s) = [T(s, x) != 0] and
+ * good_p(T(s, x)).  The words that begin with p number
+ * sum over s in good_p of C[d - |p|][s].
+ */
+
+#define MAX_STATES 16
+#define MAX_SYMBOLS 8
+
+typedef struct {
+    int S, m;
+    const uint8_t *t;
+    uint64_t C[MAX_DEPTH + 1][MAX_STATES];
+    int depth;
+} cayley;
+
+static int cayley_next(const cayley *c, int s, int x) { return c->t[s * (c->m + 1) + x]; }
+
+static int cayley_init(const uint8_t *table, int S, int m, int depth, cayley *c)
+{
+    if (!table || S < 2 || S > MAX_STATES || m < 1 || m > MAX_SYMBOLS || depth < 1 || depth > MAX_DEPTH)
+        return -1;
+    for (int i = 0; i < S * (m + 1); i++)
+        if (table[i] >= S) return -1;
+    c->S = S;
+    c->m = m;
+    c->t = table;
+    c->depth = depth;
+    memset(c->C, 0, sizeof c->C);
+    c->C[0][0] = 1;
+    for (int L = 1; L <= depth; L++) {
+        for (int s = 0; s < S; s++) {
+            if (!c->C[L - 1][s]) continue;
+            for (int x = 1; x <= m; x++) {
+                int t = cayley_next(c, s, x);
+                if (t == 0) continue;
+                if (c->C[L][t] > UINT64_MAX / 2 - c->C[L - 1][s]) return -1;  /* too many words */
+                c->C[L][t] += c->C[L - 1][s];
+            }
+        }
+    }
+    return 0;
+}
+
+/* words beginning with a prefix whose good set is `good`, with L symbols to go */
+static uint64_t cayley_count(const cayley *c, int L, uint32_t good)
+{
+    uint64_t n = 0;
+    for (int s = 0; s < c->S; s++)
+        if ((good >> s) & 1u) n += c->C[L][s];
+    return n;
+}
+
+static uint32_t cayley_extend(const cayley *c, uint32_t good, int x)
+{
+    uint32_t g = 0;
+    for (int s = 0; s < c->S; s++) {
+        int t = cayley_next(c, s, x);
+        if (t != 0 && ((good >> t) & 1u)) g |= 1u << s;
+    }
+    return g;
+}
+
+uint64_t oracle_cayley_num_words(const uint8_t *table, int n_states, int n_symbols, int depth)
+{
+    cayley c;
+    if (cayley_init(table, n_states, n_symbols, depth, &c)) return 0;
+    return cayley_count(&c, depth, (1u << n_states) - 1);
+}
+
+int oracle_cayley_unrank(const uint8_t *table, int n_states, int n_symbols, uint64_t index, int depth,
+                         uint8_t *symbols)
+{
+    cayley c;
+    if (!symbols || cayley_init(table, n_states, n_symbols, depth, &c)) return -1;
+    uint32_t good = (1u << n_states) - 1;
+    if (index >= cayley_count(&c, depth, good)) return -1;
+    for (int j = 0; j < depth; j++) {
+        int L = depth - j - 1;
+        int x;
+        for (x = 1; x <= n_symbols; x++) {
+            uint32_t g = cayley_extend(&c, good, x);
+            uint64_t n = cayley_count(&c, L, g);
+            if (index < n) {
+                good = g;
+                break;
+            }
+            index -= n;
+        }
+        symbols[j] = (uint8_t)x;
+    }
+    return 0;
+}
+
+/* the paper's scan: every m^d digit string in numeric order (digit x - 1
+ * for symbol x, most significant leftmost), kept when its right-to-left
+ * table walk never reaches state 0; writes the first `cap` survivors */
+int oracle_cayley_scan(const uint8_t *table, int n_states, int n_symbols, int depth, uint8_t *out,
+                       uint64_t cap, uint64_t *n_out)
+{
+    if (!table || !n_out || depth < 1 || depth > 12 || n_symbols < 1 || n_symbols > MAX_SYMBOLS) return -1;
+    uint64_t total = 1, kept = 0;
+    for (int j = 0; j < depth; j++) total *= (uint64_t)n_symbols;
+    uint8_t w[16];
+    for (uint64_t n = 0; n < total; n++) {
+        uint64_t q = n;
+        for (int j = depth - 1; j >= 0; j--) {
+            w[j] = (uint8_t)(q % (uint64_t)n_symbols + 1);
+            q /= (uint64_t)n_symbols;
+        }
+        int s = 0, ok = 1;
+        for (int j = depth - 1; j >= 0 && ok; j--) {
+            s = table[s * (n_symbols + 1) + w[j]];
+            ok = s != 0;
+        }
+        if (!ok) continue;
+        if (out && kept < cap) memcpy(out + kept * depth, w, (size_t)depth);
+        kept++;
+    }
+    *n_out = kept;
+    return 0;
+}
+
+/* maps: m matrices of 8 doubles (a, b, c, d complex); each symbol's seed is
+ * its map's attracting fixed point (homogeneous) */
+static int cayley_maps(const double *maps, int m, mat2 *g, cplx *fu, cplx *fv)
+{
+    for (int k = 0; k < m; k++) {
+        mat2 a = {get_c(maps + 8 * k), get_c(maps + 8 * k + 2), get_c(maps + 8 * k + 4), get_c(maps + 8 * k + 6)};
+        if (!finite_c(a.a) || !finite_c(a.b) || !finite_c(a.c) || !finite_c(a.d)) return -1;
+        cplx det = a.a * a.d - a.b * a.c;
+        if (det == 0) return -2;
+        cplx r = csqrt(det);
+        a.a /= r;
+        a.b /= r;
+        a.c /= r;
+        a.d /= r;
+        g[k] = a;
+        if (attracting_fixed_point(a, &fu[k], &fv[k]) != 0) return -2;
+    }
+    return 0;
+}
+
+/* value of symbols x_1..x_d: maps applied right to left to the seed (the
+ * last symbol's fixed point, or symbol seed + 1's) */
+static cplx cayley_value(const mat2 *g, const cplx *fu, const cplx *fv, const uint8_t *w, int d, int seed,
+                         int literal)
+{
+    int s = seed < 0 ? w[d - 1] - 1 : seed;
+    if (literal) {
+        cplx u = fu[s], v = fv[s];
+        for (int j = d - 1; j >= 0; j--) {
+            mat2 a = g[w[j] - 1];
+            cplx nu = a.a * u + a.b * v;
+            v = a.c * u + a.d * v;
+            u = nu;
+        }
+        return point_of(u, v);
+    }
+    mat2 p = g[w[0] - 1];
+    for (int j = 1; j < d; j++) p = mat_mul(p, g[w[j] - 1]);
+    return mobius_h(p, fu[s], fv[s]);
+}
+
+int oracle_cayley_eval(const uint8_t *table, int n_states, int n_symbols, const double *maps, int seed,
+                       int depth, const uint64_t *idx, uint64_t n, int literal, double *z_out)
+{
+    if (!maps || seed < -1 || seed >= n_symbols || (n && (!idx || !z_out))) return -1;
+    mat2 g[MAX_SYMBOLS];
+    cplx fu[MAX_SYMBOLS], fv[MAX_SYMBOLS];
+    int rc = cayley_maps(maps, n_symbols, g, fu, fv);
+    if (rc) return rc;
+    uint8_t w[MAX_DEPTH];
+    for (uint64_t i = 0; i < n; i++) {
+        if (oracle_cayley_unrank(table, n_states, n_symbols, idx[i], depth, w)) return -1;
+        put_c(z_out + 2 * i, cayley_value(g, fu, fv, w, depth, seed, literal));
+    }
+    return 0;
+}
+
+typedef struct {
+    const cayley *c;
+    const mat2 *g;
+    const cplx *fu, *fv;
+    const window *win;
+    int seed;
+    uint64_t first, last;
+    uint32_t *image;
+    uint64_t dropped, near_edge;
+    uint8_t word[MAX_DEPTH];
+} cayley_ctx;
+
+/* depth-first walk over the regular words of one depth in index order;
+ * the node at depth j has prefix word[0..j-1], product m and good set
+ * `good`; its words are [base, base + count) */
+static void cayley_rec(cayley_ctx *r, int j, mat2 m, uint32_t good, uint64_t base)
+{
+    const cayley *c = r->c;
+    int d = c->depth;
+    if (j == d) {
+        int s = r->seed < 0 ? r->word[d - 1] - 1 : r->seed;
+        cplx z = mobius_h(m, r->fu[s], r->fv[s]);
+        uint32_t bin;
+        int near;
+        if (bin_point(r->win, z, &bin, &near))
+            r->image[bin] += 1u;
+        else
+            r->dropped++;
+        r->near_edge += (uint64_t)near;
+        return;
+    }
+    for (int x = 1; x <= c->m; x++) {
+        uint32_t g = cayley_extend(c, good, x);
+        uint64_t n = cayley_count(c, d - j - 1, g);
+        uint64_t lo = base, hi = base + n;
+        base = hi;
+        if (n == 0 || hi <= r->first || lo >= r->last) continue;
+        r->word[j] = (uint8_t)x;
+        mat2 child = (j == 0) ? r->g[x - 1] : mat_mul(m, r->g[x - 1]);
+        cayley_rec(r, j + 1, child, g, lo);
+    }
+}
+
+/* seed: -1 own, 0..m-1 that symbol's fixed point, m: each symbol's in turn */
+int oracle_cayley_render(const uint8_t *table, int n_states, int n_symbols, const double *maps, int seed,
+                         int depth, int min_depth, double x0, double x1, double y0, double y1,
+                         uint32_t width, uint32_t height, double edge_tol, uint32_t *image,
+                         uint64_t *dropped, uint64_t *near_edge)
+{
+    if (!maps || !image || seed < -1 || seed > n_symbols || min_depth < 1 || min_depth > depth) return -1;
+    if (width == 0 || height == 0 || !(x1 > x0) || !(y1 > y0)) return -1;
+    mat2 g[MAX_SYMBOLS];
+    cplx fu[MAX_SYMBOLS], fv[MAX_SYMBOLS];
+    int rc = cayley_maps(maps, n_symbols, g, fu, fv);
+    if (rc) return rc;
+    window win = {x0, x1, y0, y1, width, height, edge_tol};
+    uint64_t drop = 0, near = 0;
+    for (int s0 = (seed == n_symbols ? 0 : seed); s0 <= (seed == n_symbols ? n_symbols - 1 : seed); s0++) {
+        for (int d = min_depth; d <= depth; d++) {
+            cayley c;
+            if (cayley_init(table, n_states, n_symbols, d, &c)) return -1;
+            cayley_ctx r;
+            memset(&r, 0, sizeof r);
+            r.c = &c;
+            r.g = g;
+            r.fu = fu;
+            r.fv = fv;
+            r.win = &win;
+            r.seed = s0;
+            r.first = 0;
+            r.last = UINT64_MAX;
+            r.image = image;
+            mat2 identity = {1, 0, 0, 1};
+            cayley_rec(&r, 0, identity, (1u << n_states) - 1, 0);
+            drop += r.dropped;
+            near += r.near_edge;
+        }
+    }
+    if (dropped) *dropped = drop;
+    if (near_edge) *near_edge = near;
+    return 0;
+}

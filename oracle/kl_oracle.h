@@ -81,6 +81,27 @@ int oracle_render_group(const double *gens, const double *seeds, int seed,
                         double edge_tol, uint32_t *image, uint64_t *dropped,
                         uint64_t *near_edge);
 
+/* Indexed Cayley tables (Section 5): table[s * (n_symbols + 1) + x] is the
+ * state after reading symbol x (1..n_symbols) in state s (0..n_states-1);
+ * state 0 is the start and, reached again, the crash state.  Words
+ * x_1..x_d are read right to left and are regular when no step lands in
+ * state 0; they are numbered in lexicographic order, x_1 most significant.
+ * maps: n_symbols matrices of 8 doubles (a, b, c, d complex); each symbol's
+ * seed is its map's attracting fixed point; seed -1 takes the last
+ * symbol's, 0..n_symbols-1 that symbol's for every word, and (renders
+ * only) n_symbols each symbol's in turn. */
+uint64_t oracle_cayley_num_words(const uint8_t *table, int n_states, int n_symbols, int depth);
+int oracle_cayley_unrank(const uint8_t *table, int n_states, int n_symbols, uint64_t index, int depth,
+                         uint8_t *symbols);
+int oracle_cayley_scan(const uint8_t *table, int n_states, int n_symbols, int depth, uint8_t *out,
+                       uint64_t cap, uint64_t *n_out);
+int oracle_cayley_eval(const uint8_t *table, int n_states, int n_symbols, const double *maps, int seed,
+                       int depth, const uint64_t *idx, uint64_t n, int literal, double *z_out);
+int oracle_cayley_render(const uint8_t *table, int n_states, int n_symbols, const double *maps, int seed,
+                         int depth, int min_depth, double x0, double x1, double y0, double y1,
+                         uint32_t width, uint32_t height, double edge_tol, uint32_t *image,
+                         uint64_t *dropped, uint64_t *near_edge);
+
 #ifdef __cplusplus
 }
 #endif

@@ -74,6 +74,17 @@ def lib():
                                           d, d, d, d, ctypes.c_uint32, ctypes.c_uint32,
                                           ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int, d,
                                           u32p, u64p, u64p]
+        L.oracle_cayley_num_words.argtypes = [u8p, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+        L.oracle_cayley_num_words.restype = ctypes.c_uint64
+        L.oracle_cayley_unrank.argtypes = [u8p, ctypes.c_int, ctypes.c_int, ctypes.c_uint64, ctypes.c_int, u8p]
+        L.oracle_cayley_scan.argtypes = [u8p, ctypes.c_int, ctypes.c_int, ctypes.c_int, u8p, ctypes.c_uint64, u64p]
+        L.oracle_cayley_eval.argtypes = [u8p, ctypes.c_int, ctypes.c_int, dp, ctypes.c_int, ctypes.c_int, u64p,
+                                         ctypes.c_uint64, ctypes.c_int, dp]
+        L.oracle_cayley_render.argtypes = [u8p, ctypes.c_int, ctypes.c_int, dp, ctypes.c_int, ctypes.c_int,
+                                           ctypes.c_int, d, d, d, d, ctypes.c_uint32, ctypes.c_uint32, d,
+                                           u32p, u64p, u64p]
+        for f in (L.oracle_cayley_unrank, L.oracle_cayley_scan, L.oracle_cayley_eval, L.oracle_cayley_render):
+            f.restype = ctypes.c_int
         for f in (L.oracle_unrank, L.oracle_enumerate, L.oracle_generators,
                   L.oracle_word_value, L.oracle_eval, L.oracle_render, L.oracle_group_recipe,
                   L.oracle_group_explicit, L.oracle_group_maskit, L.oracle_eval_group,
@@ -245,4 +256,66 @@ def render_group(group: Group, depth: int, window, *, seed: int = -1, min_depth:
                                      min_depth, x0, x1, y0, y1, W, H, first, count, nthreads, edge_tol,
                                      _ptr(image, ctypes.c_uint32), ctypes.byref(dropped),
                                      ctypes.byref(near)), "render_group")
+    return image, int(dropped.value), int(near.value)
+
+
+class Cayley:
+    """An indexed Cayley table: table[n_states, n_symbols + 1] of next states
+    (column 0 unused), and one 2x2 complex map per symbol."""
+
+    def __init__(self, table, maps):
+        self.table = np.ascontiguousarray(table, np.uint8)
+        self.n_states, cols = self.table.shape
+        self.n_symbols = cols - 1
+        self.maps = np.ascontiguousarray(np.asarray(maps, np.complex128).reshape(self.n_symbols, 2, 2))
+
+    def _args(self):
+        return _ptr(self.table, ctypes.c_uint8), self.n_states, self.n_symbols
+
+    def _maps(self):
+        return np.ascontiguousarray(self.maps.reshape(-1)).view(np.float64)
+
+
+def cayley_num_words(c: Cayley, depth: int) -> int:
+    return int(lib().oracle_cayley_num_words(*c._args(), depth))
+
+
+def cayley_unrank(c: Cayley, index: int, depth: int) -> np.ndarray:
+    w = np.zeros(depth, np.uint8)
+    _check(lib().oracle_cayley_unrank(*c._args(), index, depth, _ptr(w, ctypes.c_uint8)), "cayley_unrank")
+    return w
+
+
+def cayley_scan(c: Cayley, depth: int) -> np.ndarray:
+    """The paper's scan of all m^d digit strings: the survivors, in order."""
+    n = ctypes.c_uint64(0)
+    _check(lib().oracle_cayley_scan(*c._args(), depth, None, 0, ctypes.byref(n)), "cayley_scan")
+    out = np.zeros((n.value, depth), np.uint8)
+    _check(lib().oracle_cayley_scan(*c._args(), depth, _ptr(out, ctypes.c_uint8), n.value, ctypes.byref(n)),
+           "cayley_scan")
+    return out
+
+
+def cayley_eval(c: Cayley, depth: int, idx, seed: int = -1, literal: bool = False) -> np.ndarray:
+    m = c._maps()
+    idx = np.ascontiguousarray(idx, np.uint64)
+    z = np.zeros(2 * len(idx))
+    _check(lib().oracle_cayley_eval(*c._args(), _ptr(m, ctypes.c_double), seed, depth,
+                                    _ptr(idx, ctypes.c_uint64), len(idx), int(literal),
+                                    _ptr(z, ctypes.c_double)), "cayley_eval")
+    return z.view(np.complex128)
+
+
+def cayley_render(c: Cayley, depth: int, window, *, seed: int = -1, min_depth: int | None = None,
+                  edge_tol: float = 0.0):
+    """Returns (image[H, W], dropped, near_edge)."""
+    m = c._maps()
+    x0, x1, y0, y1, W, H = window
+    image = np.zeros((H, W), np.uint32)
+    dropped = ctypes.c_uint64(0)
+    near = ctypes.c_uint64(0)
+    _check(lib().oracle_cayley_render(*c._args(), _ptr(m, ctypes.c_double), seed, depth,
+                                      depth if min_depth is None else min_depth, x0, x1, y0, y1, W, H, edge_tol,
+                                      _ptr(image, ctypes.c_uint32), ctypes.byref(dropped),
+                                      ctypes.byref(near)), "cayley_render")
     return image, int(dropped.value), int(near.value)

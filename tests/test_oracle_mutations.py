@@ -6,7 +6,9 @@ right, a wrong sign in the trace recipe, the repelling seed, the wrong
 seed letter, a wrong skip in the unranking, swapped bin axes, a dropped
 term, the other root of the trace quadratic, a sign in Maskit's
 generators, the repelling point of an affine map as its seed, the wrong
-generator's seed fed to every word, a seed at infinity treated as finite),
+generator's seed fed to every word, a seed at infinity treated as finite,
+a transposed good-set update, the wrong start state of the empty walk and
+a scan that reads words left to right in the Cayley-table path),
 builds it with gcc, and runs the pin tests against the planted build in a
 child process.  The pins pass
 on the real reference and must fail on every planted copy.
@@ -39,8 +41,14 @@ MUTATIONS = {
     "wrong_seed_generator": ("int s = seed < 0 ? w[d - 1] : seed;", "int s = seed < 0 ? w[d - 1] : (seed + 1) % 4;"),
     "infinite_seed_as_finite": ("return point_of(m.a * u + m.b * v, m.c * u + m.d * v);",
                                 "return point_of(m.a * u + m.b, m.c * u + m.d);"),
+    "cayley_good_set_transposed": ("if (t != 0 && ((good >> t) & 1u)) g |= 1u << s;",
+                                   "if (t != 0 && ((good >> s) & 1u)) g |= 1u << t;"),
+    "cayley_empty_walk_state": ("c->C[0][0] = 1;", "c->C[0][1] = 1;"),
+    "cayley_scan_left_to_right": ("for (int j = depth - 1; j >= 0 && ok; j--) {",
+                                  "for (int j = 0; j < depth && ok; j++) {"),
 }
-PINS = [os.path.join(ROOT, "tests", f) for f in ("test_oracle_pins.py", "test_oracle_groups.py")]
+PINS = [os.path.join(ROOT, "tests", f) for f in ("test_oracle_pins.py", "test_oracle_groups.py",
+                                                  "test_oracle_cayley.py")]
 
 
 @pytest.mark.parametrize("name", sorted(MUTATIONS))
