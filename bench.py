@@ -213,6 +213,58 @@ def leg_maskit(args):
     return out
 
 
+def leg_cayley(args):
+    """Words of indexed Cayley tables (Section 5) on the general table path:
+    (1) the once-punctured torus table (Table 2) with the depth-16
+    quasi-Fuchsian maps, 57,395,628 words, against the specialised renderer
+    on the same words; (2) the modular group PSL(2, Z) = <a, b | a^2 = b^3 = 1>
+    in tiling mode over depths 1..40 from every symbol's fixed point.  Both
+    images are checked against the CPU reference."""
+    import numpy as np
+
+    from oracle import oracle as ref
+    from paper_1709_08018_amd import kl
+    from paper_1709_08018_amd import workloads as wl
+
+    out = {"workload": "cayley"}
+    threads = min(len(os.sched_getaffinity(0)), 16)
+    t11 = np.array([[0, 1, 2, 3, 4], [1, 1, 2, 0, 4], [2, 1, 2, 3, 0], [3, 0, 2, 3, 4], [4, 1, 0, 3, 4]], np.uint8)
+    maps = ref.group_recipe(wl.C2_TA, wl.C2_TB).gens
+    win = wl.QUASIFUCHSIAN_D18.window.as_tuple()
+    t = kl.Cayley(t11, maps)
+    d = 16
+    n = kl.cayley_num_words(t, d)
+    image = kl.new_image(win)
+    ms = _time(lambda: kl.cayley_render(t, d, win, image=image), max(2, args.steps // 10), 2)
+    ms_spec = _time(lambda: kl.render(wl.C2_TA, wl.C2_TB, d, win, image=kl.new_image(win), precision="fp64"),
+                    max(2, args.steps // 10), 2)
+    kl.cayley_render(t, d, win, image=image)
+    img = kl.as_u32(image).astype(np.int64)
+    t0 = time.perf_counter()
+    rimg, _, near = ref.render(wl.C2_TA, wl.C2_TB, d, win, edge_tol=1e-7, nthreads=threads)
+    dt = time.perf_counter() - t0
+    out["t11_d16"] = {"words": n, "ms": round(ms, 4), "gwords_per_s": round(n / ms / 1e6, 3),
+                      "specialised_fp64_ms": round(ms_spec, 4),
+                      "l1_vs_reference": int(np.abs(img - rimg.astype(np.int64)).sum()), "near_edge": int(near),
+                      "cpu_reference_s": round(dt, 3), "cpu_threads": threads}
+    mod = np.array([[0, 1, 2, 3], [1, 0, 2, 3], [2, 1, 0, 0], [3, 1, 0, 0]], np.uint8)
+    mod_maps = np.array([[[0, -1], [1, 0]], [[0, -1], [1, 1]], [[1, 1], [-1, 0]]], complex)
+    tm = kl.Cayley(mod, mod_maps)
+    wm = (-2.0, 2.0, 0.0, 1.25, 2048, 640)
+    words = sum(kl.cayley_num_words(tm, dd) for dd in range(1, 41))
+    image = kl.new_image(wm)
+    ms = _time(lambda: kl.cayley_render(tm, 40, wm, image=image, min_depth=1, seed="all"), max(2, args.steps // 10), 2)
+    img = kl.as_u32(image).astype(np.int64)
+    t0 = time.perf_counter()
+    rimg, _, near = ref.cayley_render(ref.Cayley(mod, mod_maps), 40, wm, seed=3, min_depth=1, edge_tol=1e-7)
+    dt = time.perf_counter() - t0
+    out["modular_tiling_d40"] = {"words": words, "points": 3 * words, "ms": round(ms, 4),
+                                 "gpoints_per_s": round(3 * words / ms / 1e6, 3),
+                                 "l1_vs_reference": int(np.abs(img - rimg.astype(np.int64)).sum()),
+                                 "near_edge": int(near), "cpu_reference_s": round(dt, 3), "cpu_threads": 1}
+    return out
+
+
 def leg_surrogate(args):
     """Learned occupancy surrogate at depth 14, 128^2 over [-2,2]^2: 20,000
     training sets (PCG64 seed 1; the last 2,000 calibrate the gate) and 2,000
@@ -273,7 +325,7 @@ def main():
                     help="untimed steps first (the GPU clock ramps up over the first ~100 ms of work)")
     ap.add_argument("--workload", default="quasifuchsian_d18",
                     choices=["quasifuchsian_d18", "quasifuchsian_d22", "batch256", "fuchsian_tiling_d10",
-                             "maskit_tiling_d14", "surrogate", "hist", "calib"])
+                             "maskit_tiling_d14", "cayley", "surrogate", "hist", "calib"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="after the steps, copy 256 MiB device to device twice (a kernel of known HBM "
@@ -292,7 +344,8 @@ def main():
 
     torch.cuda.set_device(0)
     legs = {"quasifuchsian_d22": leg_d22, "batch256": leg_batch, "fuchsian_tiling_d10": leg_tiling,
-            "maskit_tiling_d14": leg_maskit, "surrogate": leg_surrogate, "hist": leg_hist, "calib": leg_calib}
+            "maskit_tiling_d14": leg_maskit, "cayley": leg_cayley, "surrogate": leg_surrogate, "hist": leg_hist,
+            "calib": leg_calib}
     if args.workload in legs:
         print(json.dumps(legs[args.workload](args)), flush=True)
         return

@@ -248,6 +248,58 @@ int kl_render_group_ex(const kl_c64 *ab, int depth, const kl_window *window, uin
 int kl_eval_group_ex(const kl_c64 *ab, int depth, const uint64_t *idx, uint64_t n,
                      const kl_window *window, kl_c64 *z_out, const kl_opts *opts);
 
+/* Indexed Cayley tables (Section 5, Tables 2 and 3): words over any finite
+ * presentation the table encodes, drawn with one Moebius map per symbol.
+ *   n_states   2..16; state 0 is where a walk starts and, reached again,
+ *              the crash state
+ *   n_symbols  1..8; symbols are 1..n_symbols (0 is the identity column)
+ *   table      host, n_states * (n_symbols + 1) bytes: table[s * (n_symbols
+ *              + 1) + x] is the state after reading symbol x in state s
+ *   maps       host, 4 * n_symbols entries: symbol x's map [[m0, m1], [m2,
+ *              m3]] at maps[4 (x - 1)]; scaled to determinant 1; NULL is
+ *              allowed for kl_cayley_num_words and kl_cayley_decode_ex
+ * A word x_1..x_d is read right to left from state 0 (Section 5's table
+ * walk) and is regular when no step lands in state 0; the regular words of
+ * each length are numbered in lexicographic order, x_1 most significant --
+ * the order in which the paper's scan of all digit strings (Section 6)
+ * meets them.  With the once-punctured torus table (Table 2) and letter x
+ * = symbol x + 1, these are exactly the words and indices of kl_decode.
+ * A word's value applies its maps right to left to its seed: the
+ * attracting fixed point of its last symbol (KL_SEED_OWN), of symbol q + 1
+ * for every word (KL_SEED_A + q, q < n_symbols), or each symbol's in turn
+ * (KL_SEED_ALL, renders).  This path computes in FP64 throughout. */
+typedef struct {
+    int n_states;
+    int n_symbols;
+    const uint8_t *table;
+    const kl_c64 *maps;
+} kl_cayley;
+
+/* Number of regular words of length depth; 0 for an invalid table or depth,
+ * or when a count of words by length and end state reaches 2^63, or the
+ * total 2^64. */
+uint64_t kl_cayley_num_words(const kl_cayley *t, int depth);
+
+/* symbols_out: device, count * depth bytes, word-major (symbol j of word
+ * first_idx + i at symbols_out[i * depth + j]).  Asynchronous on stream.
+ * Errors: KL_EINVAL (table, depth, NULL output with count > 0), KL_ERANGE. */
+int kl_cayley_decode_ex(const kl_cayley *t, uint64_t first_idx, uint64_t count, int depth,
+                        uint8_t *symbols_out, void *stream);
+
+/* As kl_eval_ex: word values, or with a window continuous pixel
+ * coordinates, bit for bit those kl_cayley_render_ex bins.  opts: stream
+ * and seed_mode (not KL_SEED_ALL).  An index beyond the words gives NaN.
+ * Errors: KL_EINVAL, KL_ESINGULAR (a map of determinant 0 or without an
+ * attracting fixed point). */
+int kl_cayley_eval_ex(const kl_cayley *t, int depth, const uint64_t *idx, uint64_t n,
+                      const kl_window *window, kl_c64 *z_out, const kl_opts *opts);
+
+/* As kl_render_ex for the table's words: limit set or tiling (min_depth),
+ * an index range of the combined index space, accumulate, stream,
+ * dropped_out and seed_mode apply; the other options are ignored. */
+int kl_cayley_render_ex(const kl_cayley *t, int depth, const kl_window *window, uint32_t *image_out,
+                        const kl_opts *opts);
+
 /* kl_plan: the split and histogram strategy the renderer would use for one
  * depth and precision on the current device, after the options' overrides.
  * Errors: KL_EINVAL. */

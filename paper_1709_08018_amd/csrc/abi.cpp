@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <complex>
 #include <cstdarg>
@@ -820,6 +821,212 @@ int kl_eval(kl_c64 ta, kl_c64 tb, int depth, const uint64_t* idx, uint64_t n, in
     if (rc) return rc;
     hipError_t e = hipStreamSynchronize(nullptr);
     return e == hipSuccess ? KL_OK : hip_fail(e, "eval");
+}
+
+}  // extern "C"
+
+namespace kl {
+
+// A table with its maps and seeds, checked, and the start of each depth in
+// the combined index space of depths min_depth..max_depth.  need_maps:
+// evaluation and rendering (decoding reads the table only).
+static int make_cayley(const kl_cayley* t, int min_depth, int max_depth, bool need_maps, CayleyJob* j) {
+    if (!t || !t->table) return fail(KL_EINVAL, "Cayley table is NULL");
+    const int S = t->n_states, m = t->n_symbols;
+    if (S < 2 || S > kCayleyMaxStates) return fail(KL_EINVAL, "n_states %d outside 2..16", S);
+    if (m < 1 || m > kCayleyMaxSymbols) return fail(KL_EINVAL, "n_symbols %d outside 1..8", m);
+    if (min_depth < 1 || max_depth > KL_MAX_DEPTH || min_depth > max_depth)
+        return fail(KL_EINVAL, "depths %d..%d outside 1..40", min_depth, max_depth);
+    memset(j, 0, sizeof *j);
+    j->S = S;
+    j->m = m;
+    j->min_depth = min_depth;
+    j->max_depth = max_depth;
+    for (int i = 0; i < S * (m + 1); ++i) {
+        if (t->table[i] >= S) return fail(KL_EINVAL, "table entry %d = %d is not a state", i, t->table[i]);
+        j->table[i] = t->table[i];
+    }
+    // counts of regular words by length and end state, as the kernel forms them
+    std::vector<std::array<uint64_t, kCayleyMaxStates>> C(max_depth + 1);
+    for (auto& row : C) row.fill(0);
+    C[0][0] = 1;
+    // every count below 2^63, every sum of counts within 64 bits
+    const uint64_t cap = (1ull << 63) - 1;
+    for (int L = 1; L <= max_depth; ++L)
+        for (int s = 0; s < S; ++s)
+            for (int x = 1; x <= m; ++x) {
+                const int nx = t->table[s * (m + 1) + x];
+                if (nx == 0) continue;
+                if (C[L][nx] > cap - C[L - 1][s]) return fail(KL_EINVAL, "the words of length %d exceed 2^63", L);
+                C[L][nx] += C[L - 1][s];
+            }
+    uint64_t start = 0;
+    for (int d = min_depth; d <= max_depth; ++d) {
+        j->depth_start[d - min_depth] = start;
+        uint64_t n = 0;
+        for (int s = 1; s < S; ++s) {
+            if (n > UINT64_MAX - C[d][s]) return fail(KL_EINVAL, "the words of depth %d exceed 2^64", d);
+            n += C[d][s];
+        }
+        if (start > UINT64_MAX - n) return fail(KL_EINVAL, "the words of depths %d..%d exceed 2^64", min_depth, max_depth);
+        start += n;
+    }
+    j->depth_start[max_depth - min_depth + 1] = start;
+    // the good sets reachable from the set of all states, and their transitions
+    auto extend = [&](uint32_t good, int x) {
+        uint32_t g = 0;
+        for (int s = 0; s < S; ++s) {
+            const int nx = t->table[s * (m + 1) + x];
+            if (nx != 0 && ((good >> nx) & 1u)) g |= 1u << s;
+        }
+        return g;
+    };
+    j->sets[0] = (uint16_t)((1u << S) - 1u);
+    j->n_sets = 1;
+    for (int g = 0; g < j->n_sets; ++g)
+        for (int x = 1; x <= m; ++x) {
+            const uint32_t nxt = extend(j->sets[g], x);
+            int h = 0;
+            while (h < j->n_sets && j->sets[h] != nxt) ++h;
+            if (h == j->n_sets) {
+                if (h == kCayleyMaxSets)
+                    return fail(KL_EINVAL, "the table's prefixes need more than %d good-state sets", kCayleyMaxSets);
+                j->sets[h] = (uint16_t)nxt;
+                ++j->n_sets;
+            }
+            j->next_set[g * m + x - 1] = (uint8_t)h;
+        }
+    if (!need_maps) return KL_OK;
+    if (!t->maps) return fail(KL_EINVAL, "Cayley maps are NULL");
+    for (int x = 0; x < m; ++x) {
+        cd g[4];
+        for (int e = 0; e < 4; ++e) {
+            g[e] = cd(t->maps[4 * x + e].re, t->maps[4 * x + e].im);
+            if (!finite(g[e])) return fail(KL_EINVAL, "map of symbol %d is not finite", x + 1);
+        }
+        const cd det = g[0] * g[3] - g[1] * g[2];
+        if (det == cd(0.0)) return fail(KL_ESINGULAR, "map of symbol %d has determinant 0", x + 1);
+        const cd r = std::sqrt(det);
+        for (auto& e : g) e /= r;
+        cd fix;
+        bool inf;
+        if (attracting_point(g, &fix, &inf) != KL_OK)
+            return fail(KL_ESINGULAR, "map of symbol %d has no attracting fixed point", x + 1);
+        j->maps[x].a = {g[0].real(), g[0].imag()};
+        j->maps[x].b = {g[1].real(), g[1].imag()};
+        j->maps[x].c = {g[2].real(), g[2].imag()};
+        j->maps[x].d = {g[3].real(), g[3].imag()};
+        j->fix[x] = {fix.real(), fix.imag()};
+        if (inf) j->inf_mask |= 1u << x;
+    }
+    return KL_OK;
+}
+
+static int cayley_seed(const kl_opts& o, int m, int* seed) {
+    if (o.seed_mode == KL_SEED_OWN) *seed = -1;
+    else if (o.seed_mode >= KL_SEED_A && o.seed_mode <= KL_SEED_INV_B && o.seed_mode - KL_SEED_A < m)
+        *seed = o.seed_mode - KL_SEED_A;
+    else return fail(KL_EINVAL, "seed_mode %d does not name one of the %d symbols", o.seed_mode, m);
+    return KL_OK;
+}
+
+}  // namespace kl
+
+extern "C" {
+
+uint64_t kl_cayley_num_words(const kl_cayley* t, int depth) {
+    CayleyJob j;
+    if (depth < 1 || depth > KL_MAX_DEPTH || make_cayley(t, depth, depth, false, &j) != KL_OK) return 0;
+    return j.depth_start[1];
+}
+
+int kl_cayley_decode_ex(const kl_cayley* t, uint64_t first_idx, uint64_t count, int depth, uint8_t* symbols_out,
+                        void* stream) {
+    CayleyJob j;
+    int rc = make_cayley(t, depth, depth, false, &j);
+    if (rc) return rc;
+    const uint64_t n = j.depth_start[1];
+    if (first_idx > n || count > n - first_idx)
+        return fail(KL_ERANGE, "indices [%llu, +%llu) exceed the %llu words", (unsigned long long)first_idx,
+                    (unsigned long long)count, (unsigned long long)n);
+    if (count == 0) return KL_OK;
+    if (!symbols_out) return fail(KL_EINVAL, "symbols_out is NULL");
+    j.first = first_idx;
+    j.count = count;
+    j.symbols_out = symbols_out;
+    j.grid_blocks = device_cu_count() * 8;
+    hipError_t e = launch_cayley(j, kCayleyDecode, (hipStream_t)stream);
+    return e == hipSuccess ? KL_OK : hip_fail(e, "Cayley decode kernel");
+}
+
+int kl_cayley_eval_ex(const kl_cayley* t, int depth, const uint64_t* idx, uint64_t n, const kl_window* window,
+                      kl_c64* z_out, const kl_opts* opts) {
+    const kl_opts o = opts ? *opts : default_opts();
+    CayleyJob j;
+    int rc = make_cayley(t, depth, depth, true, &j);
+    if (rc) return rc;
+    if ((rc = check_opts_common(o)) || (rc = cayley_seed(o, j.m, &j.seed))) return rc;
+    if (window && (rc = check_window(window))) return rc;
+    if (n == 0) return KL_OK;
+    if (!idx || !z_out) return fail(KL_EINVAL, "idx and z_out must not be NULL");
+    j.fold = make_fold(window, 0);
+    j.count = n;
+    j.idx = idx;
+    j.z_out = (c64*)z_out;
+    j.grid_blocks = device_cu_count() * 8;
+    hipError_t e = launch_cayley(j, kCayleyEval, (hipStream_t)o.stream);
+    return e == hipSuccess ? KL_OK : hip_fail(e, "Cayley eval kernel");
+}
+
+int kl_cayley_render_ex(const kl_cayley* t, int depth, const kl_window* window, uint32_t* image_out,
+                        const kl_opts* opts) {
+    const kl_opts o = opts ? *opts : default_opts();
+    int rc = check_window(window);
+    if (rc) return rc;
+    if (!image_out) return fail(KL_EINVAL, "image_out is NULL");
+    if ((rc = check_opts_common(o))) return rc;
+    if (depth < 1 || depth > KL_MAX_DEPTH) return fail(KL_EINVAL, "depth %d outside 1..40", depth);
+    const int min_depth = o.min_depth == 0 ? depth : o.min_depth;
+    CayleyJob j;
+    if ((rc = make_cayley(t, min_depth, depth, true, &j))) return rc;
+    const uint64_t total = j.depth_start[depth - min_depth + 1];
+    uint64_t first = 0, count = total;
+    if (o.use_range) {
+        first = o.first_idx;
+        count = o.count;
+        if (first > total || count > total - first)
+            return fail(KL_ERANGE, "range [%llu, +%llu) exceeds the %llu words", (unsigned long long)first,
+                        (unsigned long long)count, (unsigned long long)total);
+    }
+    std::vector<int> seeds;
+    if (o.seed_mode == KL_SEED_ALL) {
+        for (int x = 0; x < j.m; ++x) seeds.push_back(x);
+    } else {
+        int sd;
+        if ((rc = cayley_seed(o, j.m, &sd))) return rc;
+        seeds.push_back(sd);
+    }
+    hipStream_t s = (hipStream_t)o.stream;
+    hipError_t e;
+    if (!o.accumulate) {
+        if ((e = launch_fill_u32(image_out, (uint64_t)window->width * window->height, 0, s)) != hipSuccess)
+            return hip_fail(e, "clear image");
+        if (o.dropped_out && (e = launch_fill_u64(o.dropped_out, 1, 0, s)) != hipSuccess)
+            return hip_fail(e, "clear dropped");
+    }
+    j.fold = make_fold(window, 0);
+    j.first = first;
+    j.count = count;
+    j.image = image_out;
+    j.W = window->width;
+    j.H = window->height;
+    j.dropped = o.dropped_out;
+    j.grid_blocks = device_cu_count() * 8;
+    for (int sd : seeds) {
+        j.seed = sd;
+        if ((e = launch_cayley(j, kCayleyRender, s)) != hipSuccess) return hip_fail(e, "Cayley render kernel");
+    }
+    return KL_OK;
 }
 
 int kl_render_many_ex(int n, const kl_c64* ta, const kl_c64* tb, const int* depth, const kl_window* window,

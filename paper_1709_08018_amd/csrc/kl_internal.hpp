@@ -177,6 +177,37 @@ struct BatchJob {
 hipError_t launch_batch_tables(const BatchJob& job, hipStream_t s);
 hipError_t launch_render_batch(const BatchJob& job, hipStream_t s);
 
+// Words of an indexed Cayley table (Section 5), one per thread.  Every field
+// is passed by value: the table, the maps and the seeds are small.
+constexpr int kCayleyMaxStates = 16;
+constexpr int kCayleyMaxSymbols = 8;
+constexpr int kCayleyMaxSets = 64;      // good-state sets reachable from the set of all states
+enum { kCayleyDecode = 0, kCayleyEval = 1, kCayleyRender = 2 };
+struct CayleyJob {
+    uint8_t table[kCayleyMaxStates * (kCayleyMaxSymbols + 1)];
+    // good sets: set 0 holds every state; next_set[g * m + x - 1] is the set
+    // after choosing symbol x with set g
+    uint16_t sets[kCayleyMaxSets];
+    uint8_t next_set[kCayleyMaxSets * kCayleyMaxSymbols];
+    int n_sets;
+    m64 maps[kCayleyMaxSymbols];        // determinant 1
+    c64 fix[kCayleyMaxSymbols];         // attracting fixed points; 0 where at infinity
+    uint32_t inf_mask;                  // bit x - 1: symbol x's fixed point is infinity
+    int S, m, min_depth, max_depth;
+    int seed;                           // -1: each word's last symbol's fixed point; else symbol seed + 1's
+    uint64_t first, count;              // decode / render: words [first, first + count) of the combined
+    uint64_t depth_start[KL_MAX_DEPTH + 2];  // index space; depth_start[d - min_depth] = its first word
+    Fold fold;
+    uint32_t* image;
+    uint32_t W, H;
+    uint64_t* dropped;                  // render: device u64 or null
+    uint8_t* symbols_out;               // decode: count * max_depth bytes
+    const uint64_t* idx;                // eval: count indices of words of max_depth
+    c64* z_out;                         // eval
+    int grid_blocks;
+};
+hipError_t launch_cayley(const CayleyJob& j, int mode, hipStream_t s);
+
 int device_cu_count();
 
 }  // namespace kl

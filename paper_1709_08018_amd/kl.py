@@ -49,6 +49,11 @@ class Opts(ctypes.Structure):
                 ("kernel_events", ctypes.c_void_p * 2)]
 
 
+class CayleyT(ctypes.Structure):
+    _fields_ = [("n_states", ctypes.c_int), ("n_symbols", ctypes.c_int),
+                ("table", ctypes.POINTER(ctypes.c_uint8)), ("maps", ctypes.POINTER(c64))]
+
+
 class Plan(ctypes.Structure):
     _fields_ = [("depth", ctypes.c_int), ("tail_len", ctypes.c_int), ("lane_len", ctypes.c_int),
                 ("prefix_len", ctypes.c_int), ("hist_mode", ctypes.c_int), ("waves_per_cu", ctypes.c_int)]
@@ -82,6 +87,14 @@ def lib():
         L.kl_eval.argtypes = [c64, c64, i, vp, u64, i, vp]
         L.kl_eval_ex.argtypes = [c64, c64, i, vp, u64, W, vp, O]
         L.kl_generators.argtypes = [c64, c64, C, C, C]
+        CT = ctypes.POINTER(CayleyT)
+        L.kl_cayley_num_words.argtypes = [CT, i]
+        L.kl_cayley_num_words.restype = u64
+        L.kl_cayley_decode_ex.argtypes = [CT, u64, u64, i, vp, vp]
+        L.kl_cayley_eval_ex.argtypes = [CT, i, vp, u64, W, vp, O]
+        L.kl_cayley_render_ex.argtypes = [CT, i, W, vp, O]
+        for f in ("kl_cayley_decode_ex", "kl_cayley_eval_ex", "kl_cayley_render_ex"):
+            getattr(L, f).restype = i
         L.kl_group_seeds.argtypes = [C, C, C]
         L.kl_maskit_generators.argtypes = [c64, C]
         L.kl_render_group_ex.argtypes = [C, i, W, vp, O]
@@ -413,3 +426,56 @@ def eval_group(ab, depth: int, idx, precision="fp32", window=None, **opts) -> to
     _check(lib().kl_eval_group_ex(_ab(ab), int(depth), idx.data_ptr() if n else None, n, w,
                                   out.data_ptr() if n else None, ctypes.byref(o)))
     return out
+
+
+# ---------------------------------------------------------------- indexed Cayley tables
+class Cayley:
+    """An indexed Cayley table (uint8 [n_states, n_symbols + 1], column 0
+    unused) and, for values and renders, one 2x2 complex map per symbol."""
+
+    def __init__(self, table, maps=None):
+        self._table = np.ascontiguousarray(table, np.uint8)
+        n_states, cols = self._table.shape
+        self._maps = None
+        mp = None
+        if maps is not None:
+            mv = np.asarray(maps, np.complex128).reshape(-1)
+            self._maps = (c64 * len(mv))(*[c64(z.real, z.imag) for z in mv])
+            mp = ctypes.cast(self._maps, ctypes.POINTER(c64))
+        self.struct = CayleyT(n_states, cols - 1, self._table.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), mp)
+
+    def ref(self):
+        return ctypes.byref(self.struct)
+
+
+def cayley_num_words(t: Cayley, depth: int) -> int:
+    return int(lib().kl_cayley_num_words(t.ref(), depth))
+
+
+def cayley_decode(t: Cayley, first: int, count: int, depth: int, stream=None) -> torch.Tensor:
+    out = torch.empty((count, depth), dtype=torch.uint8, device=_device())
+    _check(lib().kl_cayley_decode_ex(t.ref(), first, count, depth, out.data_ptr() if count else None,
+                                     _stream(stream)))
+    return out
+
+
+def cayley_eval(t: Cayley, depth: int, idx, window=None, **opts) -> torch.Tensor:
+    if not isinstance(idx, torch.Tensor):
+        idx = torch.as_tensor(np.ascontiguousarray(idx, np.uint64).view(np.int64))
+    idx = idx.to(device=_device(), dtype=torch.int64).contiguous()
+    n = idx.numel()
+    out = torch.empty((n, 2), dtype=torch.float64, device=_device())
+    o = make_opts(**opts)
+    w = None if window is None else ctypes.byref(make_window(window))
+    _check(lib().kl_cayley_eval_ex(t.ref(), int(depth), idx.data_ptr() if n else None, n, w,
+                                   out.data_ptr() if n else None, ctypes.byref(o)))
+    return out
+
+
+def cayley_render(t: Cayley, depth: int, window, image: torch.Tensor | None = None, **opts) -> torch.Tensor:
+    w = make_window(window)
+    if image is None:
+        image = new_image(w)
+    o = make_opts(**opts)
+    _check(lib().kl_cayley_render_ex(t.ref(), int(depth), ctypes.byref(w), image.data_ptr(), ctypes.byref(o)))
+    return image

@@ -237,3 +237,53 @@ def test_seed_mode_errors():
     assert L.kl_eval_ex(kl._c(wl.C2_TA), kl._c(wl.C2_TB), 10, FAKE, 1, None, FAKE,
                         ctypes.byref(o)) == kl.KL_EINVAL
     assert "four values" in L.kl_last_error().decode()
+
+
+# ---------------------------------------------------------------- indexed Cayley tables
+def _golden_table(name):
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", name)
+    rows = [line.split() for line in open(path) if line.strip() and not line.startswith("#")]
+    return np.array(rows, dtype=np.uint8)
+
+
+MODULAR = np.array([[0, 1, 2, 3], [1, 0, 2, 3], [2, 1, 0, 0], [3, 1, 0, 0]], np.uint8)
+
+
+@pytest.mark.parametrize("name", ["t11", "klein4", "modular"])
+def test_cayley_counts_agree_with_reference(name):
+    table = {"t11": _golden_table("cayley_t11_indexed.txt"), "klein4": _golden_table("cayley_klein4_indexed.txt"),
+             "modular": MODULAR}[name]
+    t = kl.Cayley(table)
+    ref = O.Cayley(table, np.array([[[1, 0], [0, 1]]] * (table.shape[1] - 1), complex))
+    for d in range(1, 41):
+        assert kl.cayley_num_words(t, d) == O.cayley_num_words(ref, d)
+
+
+def test_cayley_argument_errors():
+    w = _win()
+    o = kl.make_opts(use_stream=False)
+    good = kl.Cayley(MODULAR, np.array([[[0, -1], [1, 0]], [[0, -1], [1, 1]], [[1, 1], [-1, 0]]], complex))
+    assert L.kl_cayley_render_ex(good.ref(), 0, ctypes.byref(w), FAKE, ctypes.byref(o)) == kl.KL_EINVAL
+    assert L.kl_cayley_render_ex(good.ref(), 5, ctypes.byref(w), None, ctypes.byref(o)) == kl.KL_EINVAL
+    assert L.kl_cayley_render_ex(None, 5, ctypes.byref(w), FAKE, ctypes.byref(o)) == kl.KL_EINVAL
+    no_maps = kl.Cayley(MODULAR)
+    assert L.kl_cayley_render_ex(no_maps.ref(), 5, ctypes.byref(w), FAKE, ctypes.byref(o)) == kl.KL_EINVAL
+    bad_entry = MODULAR.copy()
+    bad_entry[2, 1] = 9
+    assert kl.cayley_num_words(kl.Cayley(bad_entry), 5) == 0
+    assert L.kl_cayley_decode_ex(kl.Cayley(bad_entry).ref(), 0, 1, 5, FAKE, None) == kl.KL_EINVAL
+    singular = kl.Cayley(MODULAR, np.array([[[1, 2], [2, 4]], [[0, -1], [1, 1]], [[1, 1], [-1, 0]]], complex))
+    assert L.kl_cayley_render_ex(singular.ref(), 5, ctypes.byref(w), FAKE, ctypes.byref(o)) == kl.KL_ESINGULAR
+    o4 = kl.make_opts(seed="B", use_stream=False)   # symbol 4: the table has 3
+    assert L.kl_cayley_render_ex(good.ref(), 5, ctypes.byref(w), FAKE, ctypes.byref(o4)) == kl.KL_EINVAL
+    n = kl.cayley_num_words(good, 6)
+    assert L.kl_cayley_decode_ex(good.ref(), n - 1, 2, 6, FAKE, None) == kl.KL_ERANGE
+    assert L.kl_cayley_decode_ex(good.ref(), 0, 0, 6, None, None) == kl.KL_OK
+    # eight symbols that never crash: 8^21 = 2^63 words of length 21 ending in state 1
+    free8 = np.ones((2, 9), np.uint8)
+    free8[:, 0] = 0
+    assert kl.cayley_num_words(kl.Cayley(free8), 20) == 8 ** 20
+    assert kl.cayley_num_words(kl.Cayley(free8), 21) == 0
+    huge = kl.Cayley(free8, np.array([[[2, 0], [0, 0.5]]] * 8, complex))
+    assert L.kl_cayley_render_ex(huge.ref(), 21, ctypes.byref(w), FAKE, ctypes.byref(o)) == kl.KL_EINVAL

@@ -1,0 +1,147 @@
+"""GPU path vs the CPU reference for words of indexed Cayley tables
+(Section 5), through the C ABI: decoding bit-exact, FP64 values within
+1e-10 relative, images equal to the histogram of the kernel's own pixel
+coordinates and to the reference image up to words within 1e-7 px of an
+edge.
+"""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_1709_08018_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+if torch.cuda.is_available():
+    from paper_1709_08018_amd import kl
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _golden_table(name):
+    rows = [line.split() for line in open(os.path.join(GOLDEN, name)) if line.strip() and not line.startswith("#")]
+    return np.array(rows, dtype=np.uint8)
+
+
+T11 = _golden_table("cayley_t11_indexed.txt")
+KLEIN4 = _golden_table("cayley_klein4_indexed.txt")
+MODULAR = np.array([[0, 1, 2, 3], [1, 0, 2, 3], [2, 1, 0, 0], [3, 1, 0, 0]], np.uint8)
+MOD_MAPS = np.array([[[0, -1], [1, 0]], [[0, -1], [1, 1]], [[1, 1], [-1, 0]]], complex)
+ONEWAY = np.array([[0, 1, 2], [0, 1, 2], [0, 0, 2]], np.uint8)
+# the Klein four-group as Moebius maps: a(z) = -z, b(z) = 1/z, ab(z) = -1/z
+K4_MAPS = np.array([[[1j, 0], [0, -1j]], [[0, 1j], [1j, 0]], [[0, -1], [1, 0]]], complex)
+WIN_MOD = (-2.0, 2.0, 0.0, 1.25, 1024, 320)
+
+
+def _recipe_maps():
+    return O.group_recipe(wl.C2_TA, wl.C2_TB).gens
+
+
+def _pair(table, maps):
+    return kl.Cayley(table, maps), O.Cayley(table, maps)
+
+
+def _bins(px, py, win):
+    W, H = win[4], win[5]
+    ok = np.isfinite(px) & np.isfinite(py) & (px >= 0) & (px < W) & (py >= 0) & (py < H)
+    img = np.zeros(W * H, np.int64)
+    np.add.at(img, np.floor(py[ok]).astype(np.int64) * W + np.floor(px[ok]).astype(np.int64), 1)
+    return img.reshape(H, W), int((~ok).sum())
+
+
+@pytest.mark.parametrize("name,table,dmax", [("t11", T11, 9), ("klein4", KLEIN4, 12), ("modular", MODULAR, 16),
+                                             ("oneway", ONEWAY, 14)])
+def test_decode_all_words(name, table, dmax):
+    t, ref = kl.Cayley(table), O.Cayley(table, np.array([[[1, 0], [0, 1]]] * (table.shape[1] - 1), complex))
+    for d in (1, 2, dmax // 2, dmax):
+        n = kl.cayley_num_words(t, d)
+        got = kl.cayley_decode(t, 0, n, d).cpu().numpy()
+        want = np.array([O.cayley_unrank(ref, i, d) for i in range(n)]).reshape(n, d)
+        np.testing.assert_array_equal(got, want)
+
+
+def test_free_group_table_decodes_like_kl_decode():
+    t = kl.Cayley(T11)
+    for d in (5, 18, 40):
+        n = kl.num_words(d)
+        first = n // 3
+        count = min(5000, n - first)
+        got = kl.cayley_decode(t, first, count, d).cpu().numpy().astype(np.int64)
+        want = kl.decode(first, count, d).cpu().numpy().astype(np.int64)
+        np.testing.assert_array_equal(got - 1, want)
+
+
+@pytest.mark.parametrize("case", ["t11", "modular", "klein4"])
+def test_fp64_values(case):
+    if case == "t11":
+        t, ref = _pair(T11, _recipe_maps())
+        d = 12
+    elif case == "modular":
+        t, ref = _pair(MODULAR, MOD_MAPS)
+        d = 24
+    else:
+        t, ref = _pair(KLEIN4, K4_MAPS)
+        d = 10
+    n = kl.cayley_num_words(t, d)
+    idx = wl.sample_indices(n, min(n, 20000), seed=3)
+    seeds = [("own", -1), ("a", 0), ("b", 1)]
+    for name, s in seeds:
+        z = kl.cayley_eval(t, d, idx, seed=name).cpu().numpy()
+        z = z[:, 0] + 1j * z[:, 1]
+        zr = O.cayley_eval(ref, d, idx, seed=s)
+        fin = np.isfinite(zr)
+        assert np.isfinite(z[fin]).all()
+        assert (np.abs(z[fin] - zr[fin]) / np.maximum(1, np.abs(zr[fin]))).max() < 1e-10, name
+    # an index beyond the words gives NaN
+    z = kl.cayley_eval(t, d, np.array([n - 1, n], np.uint64)).cpu().numpy()
+    assert np.isfinite(z[0]).all() and np.isnan(z[1]).all()
+
+
+@pytest.mark.parametrize("seed", ["own", "b"])
+def test_image_is_histogram_of_own_bins(seed):
+    t, _ = _pair(MODULAR, MOD_MAPS)
+    win, depth, mind = WIN_MOD, 22, 1
+    dropped = torch.zeros(1, dtype=torch.int64, device="cuda")
+    img = kl.as_u32(kl.cayley_render(t, depth, win, min_depth=mind, seed=seed, dropped=dropped)).astype(np.int64)
+    ref = np.zeros_like(img)
+    drop = 0
+    for d in range(mind, depth + 1):
+        n = kl.cayley_num_words(t, d)
+        p = kl.cayley_eval(t, d, np.arange(n, dtype=np.uint64), window=win, seed=seed).cpu().numpy()
+        r, dr = _bins(p[:, 0], p[:, 1], win)
+        ref += r
+        drop += dr
+    np.testing.assert_array_equal(img, ref)
+    assert int(dropped.item()) == drop
+
+
+@pytest.mark.parametrize("case", ["modular_all_seeds", "t11_limit_set"])
+def test_image_matches_reference(case):
+    if case == "modular_all_seeds":
+        t, ref = _pair(MODULAR, MOD_MAPS)
+        depth, mind, win, seed, s = 20, 1, WIN_MOD, "all", 3
+    else:
+        t, ref = _pair(T11, _recipe_maps())
+        depth, mind, win, seed, s = 11, 11, wl.QUASIFUCHSIAN_D18.window.as_tuple(), "own", -1
+    dropped = torch.zeros(1, dtype=torch.int64, device="cuda")
+    img = kl.as_u32(kl.cayley_render(t, depth, win, min_depth=mind, seed=seed, dropped=dropped)).astype(np.int64)
+    rimg, rdrop, near = O.cayley_render(ref, depth, win, seed=s, min_depth=mind, edge_tol=1e-7)
+    assert int(np.abs(img - rimg.astype(np.int64)).sum()) <= 2 * near
+    words = sum(kl.cayley_num_words(t, d) for d in range(mind, depth + 1))
+    copies = 3 if seed == "all" else 1
+    assert int(img.sum()) + int(dropped.item()) == copies * words
+
+
+def test_range_additivity():
+    t, _ = _pair(MODULAR, MOD_MAPS)
+    depth, mind, win = 26, 1, WIN_MOD
+    total = sum(kl.cayley_num_words(t, d) for d in range(mind, depth + 1))
+    full = kl.cayley_render(t, depth, win, min_depth=mind)
+    acc = kl.new_image(win)
+    cuts = sorted({0, 1, 777, total // 3, total - 5, total})
+    for a, b in zip(cuts[:-1], cuts[1:]):
+        kl.cayley_render(t, depth, win, image=acc, min_depth=mind, first=a, count=b - a, accumulate=True)
+    assert torch.equal(acc, full)
