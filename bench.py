@@ -32,6 +32,11 @@ METRIC = "Gwords/s and VALU roofline fraction at depth 18; surrogate vs plain sc
 # form P + Q / (y + S) applied to the suffix point y: u = y + S (2 flops),
 # |u|^2 (3), reciprocal (1), per pixel coordinate one product and two FMAs (10)
 FLOPS_PER_WORD = 16
+# the per-word work of the point-walk formulation in which the renderer's
+# target was set: (d - k - 1) FP32 mat-vecs of 28 flops at depth 18 with an
+# 8-letter prefix (252 FP32) plus the FP64 prefix application (45 FP64), in
+# FP32-equivalent flops (FP64 at half the FP32 rate)
+SURVEY_FP32_EQUIV_FLOPS_PER_WORD = 252 + 2 * 45
 FP32_PEAK_TFLOPS = 157.3  # MI355X FP32 vector peak (counts packed FMA)
 EVENT_EVERY = 10
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "render_kernel_quasifuchsian_d18_pmc.txt")
@@ -413,7 +418,9 @@ def main():
                 "frac": round(achieved / FP32_PEAK_TFLOPS, 4), "traffic": _traffic_from_profile(plan),
                 "kernel": "render_kernel<float, %s, false>" % ("true" if plan["hist_mode"] == 2 else "false"),
                 "kernel_ms": round(kernel_avg, 4),
-                "flops_per_word": FLOPS_PER_WORD, "words_per_launch": kernel_words}
+                "flops_per_word": FLOPS_PER_WORD, "words_per_launch": kernel_words,
+                "useful_frac_point_walk_formulation": round(
+                    SURVEY_FP32_EQUIV_FLOPS_PER_WORD * kernel_words / (kernel_avg * 1e-3) / 1e12 / FP32_PEAK_TFLOPS, 3)}
 
     out = {
         "metric": METRIC,
