@@ -59,8 +59,8 @@ def _traffic_from_profile(plan):
     src_hash = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
     vals = {}
     for line in open(PMC_SUMMARY):
-        if ":" in line:
-            k, v = line.split(":", 1)
+        if ": " in line:
+            k, v = line.split(": ", 1)
             vals[k.strip()] = v.strip()
     if vals.get("kernels.hip sha256[:16]") != src_hash:
         return None

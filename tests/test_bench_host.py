@@ -1,0 +1,51 @@
+"""Host logic of bench.py: the HBM traffic figure is read from the committed
+counter summary only when that summary was taken on the current kernel
+source and split."""
+import hashlib
+
+import bench
+
+SPLIT = {"prefix_len": 9, "lane_len": 3, "tail_len": 6}
+
+
+def _summary(tmp_path, src_hash, split="prefix 9, lane 3, tail 6 letters; 32 waves per CU"):
+    p = tmp_path / "pmc.txt"
+    p.write_text("# HBM traffic (KiB per dispatch)\n"
+                 "# command: rocprofv3 --pmc FETCH_SIZE -- python3 bench.py\n"
+                 f"kernels.hip sha256[:16]: {src_hash}\n"
+                 f"split: {split}\n"
+                 "render_kernel FETCH_SIZE KiB per dispatch (mean of 4): 1204.7\n"
+                 "hbm_bytes_per_launch: 40753009\n")
+    return str(p)
+
+
+def _current_hash():
+    return hashlib.sha256(open(bench.KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def test_traffic_read_when_source_and_split_match(tmp_path, monkeypatch):
+    monkeypatch.setattr(bench, "PMC_SUMMARY", _summary(tmp_path, _current_hash()))
+    assert bench._traffic_from_profile(SPLIT) == 40753009.0
+
+
+def test_traffic_null_for_another_source(tmp_path, monkeypatch):
+    monkeypatch.setattr(bench, "PMC_SUMMARY", _summary(tmp_path, "0" * 16))
+    assert bench._traffic_from_profile(SPLIT) is None
+
+
+def test_traffic_null_for_another_split(tmp_path, monkeypatch):
+    monkeypatch.setattr(bench, "PMC_SUMMARY", _summary(tmp_path, _current_hash(), "prefix 8, lane 4, tail 6 letters"))
+    assert bench._traffic_from_profile(SPLIT) is None
+
+
+def test_traffic_null_without_summary(tmp_path, monkeypatch):
+    monkeypatch.setattr(bench, "PMC_SUMMARY", str(tmp_path / "absent.txt"))
+    assert bench._traffic_from_profile(SPLIT) is None
+
+
+def test_multi_gpu_request_exits_with_a_message():
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, bench.__file__, "--gpus", "2"], capture_output=True, text=True, timeout=120)
+    assert r.returncode != 0
+    assert "one GPU" in (r.stdout + r.stderr) or "single GPU" in (r.stdout + r.stderr)
