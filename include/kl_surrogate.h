@@ -20,10 +20,13 @@
  * sigmoid(z) against the occupancy.  Optimiser: Adam (beta1 0.9, beta2
  * 0.999, eps 1e-8) on FP32 master weights.
  *
- * Arithmetic: every matrix product (the linear layers, the transposed
- * convolutions in their column form, and all their gradients) runs on the
- * BF16 matrix cores: operands rounded to bfloat16 (nearest even), products
- * accumulated in FP32.  Everything else is FP32.
+ * Arithmetic: the operands of every matrix product are rounded to bfloat16
+ * (nearest even) and its products accumulated in FP32; everything else is
+ * FP32.  kl_sur_forward runs the whole network of one set in one workgroup,
+ * activations in LDS: the first linear layer (four inputs) on the vector
+ * ALUs, every other product on the BF16 matrix cores.  Training runs every
+ * product (the transposed convolutions in their column form, and all the
+ * gradients) on the matrix cores.
  *
  * Parameters: one flat FP32 device vector of kl_sur_num_params() values in
  * the order W1 b1 W2 b2 K1 c1 K2 c2 K3 c3 K4 c4, each row-major as shaped

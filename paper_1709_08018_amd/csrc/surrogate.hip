@@ -56,6 +56,9 @@ __device__ __forceinline__ unsigned short to_bf16(float x) {
     return (unsigned short)(u >> 16);
 }
 
+// the value of x rounded to bfloat16, as FP32
+__device__ __forceinline__ float bf16_value(float x) { return __uint_as_float((uint32_t)to_bf16(x) << 16); }
+
 struct GemmArgs {
     int M, N, K;
     const float* A;
@@ -388,12 +391,306 @@ __global__ void iou_kernel(const float* __restrict__ z, const uint8_t* __restric
     if (threadIdx.x == 0) out[blockIdx.x] = ru[0] == 0 ? 1.f : (float)ri[0] / (float)ru[0];
 }
 
+// ------------------------------------------------------------------ fused forward (inference)
+// The whole network for one set in one workgroup, every activation held in
+// LDS as bfloat16 -- the rounding the training path applies when it reads
+// them as GEMM operands:
+//   * u -> h1 (4 -> 256): four products per output on the vector ALUs;
+//   * h1 -> h2 (256 -> 256): W2^T h1 on the matrix cores, h1 the only
+//     non-zero column of the right operand;
+//   * convT k4 s4 p0 (16 -> 64 channels, 4^2 -> 16^2): no two taps of one
+//     input pixel overlap, so it is one product x0 (16 pixels x 16) K1
+//     (16 x 1024) scattered to the output pixels;
+//   * convT k4 s2 p1: output pixel (2m + py, 2n + px) gathers the input
+//     pixels (m + dy, n + dx) over two row taps and two column taps fixed by
+//     the phase (py, px) (tap_dy, tap_k below), so each of the four phases is
+//     a 2 x 2 convolution: Cout x (4 taps * Cin) weights times (4 taps *
+//     Cin) x (16 pixels) read straight from the padded input in LDS, one tap
+//     and 32 channels per product step.  Taken this way round, a lane ends up
+//     holding four consecutive channels of one output pixel;
+//   * the last layer (16 -> 1 channel) in column form: col = y3 K4 (16 taps
+//     per pixel).  A lane's four channels of y3 are exactly its operand of
+//     that product, so y3 never leaves the registers; the columns of four
+//     y3 rows at a time go to a ring of nine zero-padded LDS rows (tap-major,
+//     so that the lanes of a wave read consecutive words), and each logit
+//     sums its four column entries.
+// Products: v_mfma_f32_16x16x32_bf16 (16x16x16 where K is 16), FP32 accumulation.
+typedef unsigned short bf16_t;
+typedef short bf16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int kFwdThreads = 512;                      // 8 waves
+constexpr int kY1S = 64 + 8, kY2S = 32 + 8;           // bf16 per pixel: 16-byte rows, padded against bank conflicts
+constexpr int kY1Bytes = 18 * 18 * kY1S * 2;          // 16^2 grid with a zero border
+constexpr int kY2Bytes = 34 * 34 * kY2S * 2;          // 32^2 grid with a zero border
+constexpr int kRing = 9;                              // column rows m0-1 .. m0+7 never share a slot
+constexpr int kRingW = 66;                            // x = -1 .. 64, the ends zero
+constexpr int kRingBytes = kRing * kRingW * 16 * 4;
+constexpr int kFwdLds = kY2Bytes + kY1Bytes + 256 * 2 + 256 * 2 + 16;
+static_assert(kRingBytes <= kY1Bytes, "the column ring reuses the y1 space");
+
+// packed bfloat16 weights: a lane's k values adjacent
+constexpr size_t kK1p = 1024 * 16;          // [n = o*16 + ky*4 + kx][c]
+constexpr size_t kK2p = 4 * 8 * 32 * 32;    // [phase][k step][o][32 k]; k step = tap * 2 + channel half
+constexpr size_t kK3p = 4 * 4 * 16 * 32;    // [phase][tap][o][32 c]
+constexpr size_t kK4p = 16 * 16;            // [tap = ky*4 + kx][c]
+constexpr size_t kW2p = 16 * 8 * 16 * 32;   // [o / 16][k step][o % 16][32 k]
+constexpr size_t kPackedElems = kK1p + kK2p + kK3p + kK4p + kW2p;
+
+// Stride-2, pad-1 transposed convolution: for output phase p (0 even, 1
+// odd) and tap a (0, 1), the input offset and kernel index.
+__device__ __forceinline__ int tap_dy(int p, int a) { return p ? (a ? 0 : 1) : (a ? -1 : 0); }
+__device__ __forceinline__ int tap_k(int p, int a) { return p ? (a ? 2 : 0) : (a ? 3 : 1); }
+
+struct PackArgs {
+    const float *W2, *K1, *K2, *K3, *K4;
+    bf16_t* out;
+};
+
+__global__ void pack_weights_kernel(const PackArgs a) {
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < kPackedElems; e += (size_t)gridDim.x * blockDim.x) {
+        float v;
+        size_t i = e;
+        if (i < kK1p) {
+            const int n = (int)(i / 16), c = (int)(i % 16);
+            v = a.K1[(c * 64 + n / 16) * 16 + n % 16];
+        } else if ((i -= kK1p) < kK2p) {
+            const int kk = (int)(i % 32), o = (int)((i / 32) % 32), ks = (int)((i / 1024) % 8), ph = (int)(i / 8192);
+            const int tap = ks >> 1, c = (ks & 1) * 32 + kk;
+            const int ky = tap_k(ph >> 1, tap >> 1), kx = tap_k(ph & 1, tap & 1);
+            v = a.K2[((c * 32 + o) * 4 + ky) * 4 + kx];
+        } else if ((i -= kK2p) < kK3p) {
+            const int c = (int)(i % 32), o = (int)((i / 32) % 16), tap = (int)((i / 512) % 4), ph = (int)(i / 2048);
+            const int ky = tap_k(ph >> 1, tap >> 1), kx = tap_k(ph & 1, tap & 1);
+            v = a.K3[((c * 16 + o) * 4 + ky) * 4 + kx];
+        } else if ((i -= kK3p) < kK4p) {
+            const int tap = (int)(i / 16), c = (int)(i % 16);
+            v = a.K4[c * 16 + tap];
+        } else {
+            i -= kK4p;
+            const int kk = (int)(i % 32), oo = (int)((i / 32) % 16), ks = (int)((i / 512) % 8), mt = (int)(i / 4096);
+            v = a.W2[(ks * 32 + kk) * 256 + mt * 16 + oo];
+        }
+        a.out[e] = to_bf16(v);
+    }
+}
+
+struct FwdArgs {
+    const kl_c64 *ta, *tb;
+    const float *W1, *b1, *b2;                     // FP32 parameters
+    const bf16_t *w2, *k1, *k2, *k3, *k4;          // packed weights
+    const float *c1, *c2, *c3, *c4;                // biases
+    float* logits;                                 // B x 128 x 128
+    int B;
+};
+
+__device__ __forceinline__ bf16x4 frag4(const bf16_t* p) { return *(const bf16x4*)p; }
+__device__ __forceinline__ bf16x8 frag8(const bf16_t* p) { return *(const bf16x8*)p; }
+__device__ __forceinline__ f32x4 mma16(bf16x4 a, bf16x4 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f32x4 mma32(bf16x8 a, bf16x8 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ bf16x4 relu_bf16(f32x4 d, const float* bias) {
+    bf16x4 r;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) r[v] = (short)to_bf16(fmaxf(d[v] + bias[v], 0.f));
+    return r;
+}
+
+// One workgroup per set, sets dealt round robin over the grid.
+__global__ __launch_bounds__(kFwdThreads) void forward_kernel(const FwdArgs a) {
+    __shared__ __align__(16) unsigned char dsm[kFwdLds];
+    bf16_t* y2p = (bf16_t*)dsm;                                // [34][34][kY2S]
+    bf16_t* y1p = (bf16_t*)(dsm + kY2Bytes);                   // [18][18][kY1S]
+    bf16_t* h1s = (bf16_t*)(dsm + kY2Bytes + kY1Bytes);        // [256]
+    bf16_t* x0s = h1s + 256;                                   // [16 pixels][16 channels]
+    float* us = (float*)(x0s + 256);                           // [4]
+    float* ring = (float*)(dsm + kY2Bytes);                    // [kRing][16 taps][kRingW], once y1 is consumed
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lr = lane & 15, lq = lane >> 4;
+    const f32x4 zero4 = {0.f, 0.f, 0.f, 0.f};
+
+    // weights that stay in registers
+    const int ph2 = wave >> 1;                 // convT 2: phase, output rows 8 (wave & 1) .. + 8
+    bf16x8 w2[2][8];
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int ks = 0; ks < 8; ++ks) w2[t][ks] = frag8(a.k2 + ((ph2 * 8 + ks) * 32 + 16 * t + lr) * 32 + 8 * lq);
+    // convT 3 tiles of this wave: row r3 of each group of four, column phase px3, halves 0 and 1;
+    // the row phase is r3 & 1 because groups start at multiples of four
+    const int r3 = wave >> 1, px3 = wave & 1, ph3 = (r3 & 1) * 2 + px3;
+    bf16x8 w3[4];
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) w3[ks] = frag8(a.k3 + ((ph3 * 4 + ks) * 16 + lr) * 32 + 8 * lq);
+    const bf16x4 w4 = frag4(a.k4 + lr * 16 + 4 * lq);
+    float b2c[2][4], b3c[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        b2c[0][v] = a.c2[4 * lq + v];
+        b2c[1][v] = a.c2[16 + 4 * lq + v];
+        b3c[v] = a.c3[4 * lq + v];
+    }
+    const float b4 = a.c4[0];
+
+    for (int i = tid; i < kY2Bytes / 4; i += kFwdThreads) ((uint32_t*)y2p)[i] = 0u;   // border stays zero
+
+    for (int b = blockIdx.x; b < a.B; b += gridDim.x) {
+        for (int i = tid; i < kY1Bytes / 4; i += kFwdThreads) ((uint32_t*)y1p)[i] = 0u;
+        if (tid == 0) {
+            us[0] = (float)((a.ta[b].re - 2.4) / 0.6);
+            us[1] = (float)(a.ta[b].im / 0.3);
+            us[2] = (float)((a.tb[b].re - 2.4) / 0.6);
+            us[3] = (float)(a.tb[b].im / 0.3);
+        }
+        __syncthreads();
+        // h1 = relu(u W1 + b1), operands rounded to bfloat16
+        if (tid < 256) {
+            float acc = 0.f;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) acc = fmaf(bf16_value(us[k]), bf16_value(a.W1[k * 256 + tid]), acc);
+            h1s[tid] = to_bf16(fmaxf(acc + a.b1[tid], 0.f));
+        }
+        __syncthreads();
+        // h2 = relu(h1 W2 + b2): rows o of W2^T, 16 per tile, two tiles per wave; column 0 = h1
+        {
+            f32x4 d[2] = {zero4, zero4};
+#pragma unroll
+            for (int ks = 0; ks < 8; ++ks) {
+                bf16x8 hb = {0, 0, 0, 0, 0, 0, 0, 0};
+                if (lr == 0) hb = frag8(h1s + ks * 32 + 8 * lq);
+#pragma unroll
+                for (int u = 0; u < 2; ++u)
+                    d[u] = mma32(frag8(a.w2 + (((2 * wave + u) * 8 + ks) * 16 + lr) * 32 + 8 * lq), hb, d[u]);
+            }
+            if (lr == 0) {
+#pragma unroll
+                for (int u = 0; u < 2; ++u)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int o = 16 * (2 * wave + u) + 4 * lq + v;   // feature c*16 + q -> x0 pixel q, channel c
+                        x0s[(o % 16) * 16 + o / 16] = to_bf16(fmaxf(d[u][v] + a.b2[o], 0.f));
+                    }
+            }
+        }
+        __syncthreads();
+
+        // convT 1: N tile t = output channel t (16 taps); rows = the 16 input pixels
+        {
+            const bf16x4 ax = frag4(x0s + lr * 16 + 4 * lq);
+            const int ky = lr >> 2, kx = lr & 3;
+            for (int t = wave; t < 64; t += kFwdThreads / 64) {
+                const f32x4 d = mma16(ax, frag4(a.k1 + (16 * t + lr) * 16 + 4 * lq), zero4);
+                const float bias = a.c1[t];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int p = 4 * lq + v, i = p >> 2, j = p & 3;
+                    y1p[((4 * i + ky + 1) * 18 + 4 * j + kx + 1) * kY1S + t] = to_bf16(fmaxf(d[v] + bias, 0.f));
+                }
+            }
+        }
+        __syncthreads();
+
+        // convT 2, phase ph2: tile = output row 2m + py, columns 2n + px for n = lane's lr
+        {
+            const int py = ph2 >> 1, px = ph2 & 1;
+            for (int mi = 0; mi < 8; ++mi) {
+                const int m = 8 * (wave & 1) + mi;
+                bf16x8 ay[8];
+#pragma unroll
+                for (int ks = 0; ks < 8; ++ks) {
+                    const int tap = ks >> 1;
+                    const int iy = m + tap_dy(py, tap >> 1) + 1, ix = lr + tap_dy(px, tap & 1) + 1;
+                    ay[ks] = frag8(y1p + (iy * 18 + ix) * kY1S + (ks & 1) * 32 + 8 * lq);
+                }
+                f32x4 d0 = zero4, d1 = zero4;
+#pragma unroll
+                for (int ks = 0; ks < 8; ++ks) {
+                    d0 = mma32(w2[0][ks], ay[ks], d0);
+                    d1 = mma32(w2[1][ks], ay[ks], d1);
+                }
+                // keep that order: the 8 LDS reads, then the 16 products
+                __builtin_amdgcn_sched_group_barrier(0x100, 8, 0);
+                __builtin_amdgcn_sched_group_barrier(0x008, 16, 0);
+                bf16_t* dst = y2p + ((2 * m + py + 1) * 34 + 2 * lr + px + 1) * kY2S + 4 * lq;
+                *(bf16x4*)dst = relu_bf16(d0, b2c[0]);
+                *(bf16x4*)(dst + 16) = relu_bf16(d1, b2c[1]);
+            }
+        }
+        __syncthreads();
+        // the ring: row -1 (slot 0) zero, the end pixels of every row zero
+        for (int i = tid; i < kRingW * 16; i += kFwdThreads) ring[i] = 0.f;
+        for (int i = tid; i < (kRing - 1) * 16 * 2; i += kFwdThreads) {
+            const int slot = 1 + i / 32, tap = (i / 2) % 16, end = i & 1;
+            ring[(slot * 16 + tap) * kRingW + (end ? kRingW - 1 : 0)] = 0.f;
+        }
+
+        // groups of four y3 rows m0 .. m0 + 3 (slot of row m: (m + 1) mod kRing);
+        // the 17th group only closes the last logit row
+        for (int g = 0; g <= 16; ++g) {
+            const int m0 = 4 * g;
+            if (g < 16) {
+                const int Y = m0 + r3, m = Y >> 1, py = Y & 1;
+                bf16x8 ay[2][4];
+#pragma unroll
+                for (int ks = 0; ks < 4; ++ks) {
+                    const int iy = m + tap_dy(py, ks >> 1) + 1;
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const int ix = 16 * h + lr + tap_dy(px3, ks & 1) + 1;
+                        ay[h][ks] = frag8(y2p + (iy * 34 + ix) * kY2S + 8 * lq);
+                    }
+                }
+                f32x4 d[2] = {zero4, zero4};
+#pragma unroll
+                for (int ks = 0; ks < 4; ++ks)
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) d[h] = mma32(w3[ks], ay[h][ks], d[h]);
+                __builtin_amdgcn_sched_group_barrier(0x100, 8, 0);
+                __builtin_amdgcn_sched_group_barrier(0x008, 8, 0);
+                float* row = ring + ((Y + 1) % kRing) * 16 * kRingW;
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const f32x4 c = mma16(w4, relu_bf16(d[h], b3c), zero4);   // taps 4 lq + v of pixel x
+                    const int x = 2 * (16 * h + lr) + px3;
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) row[(4 * lq + v) * kRingW + x + 1] = c[v];
+                }
+            } else {
+                for (int i = tid; i < kRingW * 16; i += kFwdThreads) ring[(65 % kRing) * kRingW * 16 + i] = 0.f;  // row 64
+            }
+            __syncthreads();
+            // logit row Z = 2 m0 - 1 + tid / 64 (those in range), columns 2u and 2u + 1 for u = tid % 64:
+            // X = 2u takes pixels u (kx 1) and u - 1 (kx 3), X = 2u + 1 pixels u + 1 (kx 0) and u (kx 2)
+            {
+                const int Z = 2 * m0 - 1 + (tid >> 6), u = tid & 63;
+                if (Z >= 0 && Z < 128) {
+                    float e0 = 0.f, e1 = 0.f;
+#pragma unroll
+                    for (int ra = 0; ra < 2; ++ra) {
+                        // taps (ky, 0..3) of y3 row (Z >> 1) + dy; ring x = pixel + 1
+                        const float* t = ring + ((((Z >> 1) + tap_dy(Z & 1, ra) + 1) % kRing) * 16 +
+                                                 4 * tap_k(Z & 1, ra)) * kRingW + u;
+                        e0 += t[kRingW + 1] + t[3 * kRingW];
+                        e1 += t[2] + t[2 * kRingW + 1];
+                    }
+                    float2 out = {e0 + b4, e1 + b4};
+                    *(float2*)(a.logits + ((int64_t)b * 128 + Z) * 128 + 2 * u) = out;
+                }
+            }
+        }
+        __syncthreads();   // the next set's y1 clear overwrites the ring
+    }
+}
+
 static unsigned grid_for(int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>(8192, (n + 255) / 256)); }
 
 // ------------------------------------------------------------------ workspace
 struct WS {
     float *u, *h1, *h2, *x0, *col1, *y1, *col2, *y2, *col3, *y3, *col4, *logits, *dlogits, *dy3, *dy2, *dy1, *dx0,
         *dh2, *dh1, *partial, *loss;
+    bf16_t* packed;   // decoder weights of the fused inference path
     size_t bytes;
 };
 
@@ -429,6 +726,7 @@ static WS carve(void* base, int B) {
     w.dh1 = take(b * 256);
     w.partial = take(1024 * 256);
     w.loss = take(64);
+    w.packed = (bf16_t*)take((kPackedElems + 1) / 2);
     w.bytes = o;
     return w;
 }
@@ -460,6 +758,24 @@ static hipError_t forward(const float* P, const kl_c64* ta, const kl_c64* tb, in
     CHECK_HIP(gemm(B * 4096, 16, 16, w.y3, 16, 1, P + L.K4, 16, 1, w.col4, 16, nullptr, 0, 0, s));
     hipLaunchKernelGGL(col2im_kernel, dim3(grid_for((int64_t)B * kImg * kImg)), dim3(256), 0, s, w.col4, P + L.c4,
                        logits, B, kC4, 0);
+    return hipGetLastError();
+}
+
+// Inference forward: the weights packed once per call, then the whole network
+// per set in one kernel.
+static hipError_t forward_fused(const float* P, const kl_c64* ta, const kl_c64* tb, int B, float* logits,
+                                const WS& w, hipStream_t s) {
+    const Layout L = layout();
+    const PackArgs pa{P + L.W2, P + L.K1, P + L.K2, P + L.K3, P + L.K4, w.packed};
+    hipLaunchKernelGGL(pack_weights_kernel, dim3(grid_for((int64_t)kPackedElems)), dim3(256), 0, s, pa);
+    const bf16_t* k1 = w.packed;
+    const bf16_t* k2 = k1 + kK1p;
+    const bf16_t* k3 = k2 + kK2p;
+    const bf16_t* k4 = k3 + kK3p;
+    const bf16_t* w2 = k4 + kK4p;
+    const FwdArgs f{ta, tb, P + L.W1, P + L.b1, P + L.b2, w2, k1, k2, k3, k4, P + L.c1, P + L.c2, P + L.c3, P + L.c4,
+                    logits, B};
+    hipLaunchKernelGGL(forward_kernel, dim3(std::min(B, 1024)), dim3(kFwdThreads), 0, s, f);
     return hipGetLastError();
 }
 
@@ -540,7 +856,7 @@ int kl_sur_forward(const float* params, const kl_c64* ta, const kl_c64* tb, int 
         return sur_fail(KL_EINVAL, "bad surrogate forward arguments");
     if (workspace_bytes < kl_sur_workspace_bytes(batch)) return sur_fail(KL_EINVAL, "workspace too small");
     const WS w = carve(workspace, batch);
-    hipError_t e = forward(params, ta, tb, batch, logits_out, w, (hipStream_t)stream);
+    hipError_t e = forward_fused(params, ta, tb, batch, logits_out, w, (hipStream_t)stream);
     return e == hipSuccess ? KL_OK : sur_fail(KL_EDEVICE, hipGetErrorString(e));
 }
 

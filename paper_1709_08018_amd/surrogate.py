@@ -155,6 +155,27 @@ def evaluate(params, ta, tb, occ_true, tau):
             "accepted_below_target": int((iou_sur[acc] < IOU_TARGET).sum())}, iou_sur, unc
 
 
+def sensitivity(ta, tb, occ, eps_list=(1e-3, 3e-3, 1e-2, 3e-2), n=500, seed=5, depth=DEPTH):
+    """How far the occupancy moves with the traces: IoU between each set's
+    plain render (occ) and the plain render at traces moved a distance eps in
+    a random direction of (Re ta, Im ta, Re tb, Im tb).  A predictor that
+    reaches the IoU target must resolve the traces to about the eps at which
+    this IoU falls below it."""
+    rng = np.random.default_rng(seed)
+    n = min(n, len(ta))
+    out = []
+    for eps in eps_list:
+        d = rng.normal(size=(n, 4))
+        d /= np.linalg.norm(d, axis=1, keepdims=True)
+        ta2 = np.asarray(ta[:n]) + eps * (d[:, 0] + 1j * d[:, 1])
+        tb2 = np.asarray(tb[:n]) + eps * (d[:, 2] + 1j * d[:, 3])
+        iou = kl.iou(occ[:n], pred_occ=render_occupancy(ta2, tb2, depth)).cpu().numpy()
+        out.append({"eps": eps, "sets": n, "mean_iou": round(float(iou.mean()), 4),
+                    "median_iou": round(float(np.median(iou)), 4),
+                    "frac_at_target": round(float((iou >= IOU_TARGET).mean()), 4)})
+    return out
+
+
 def run(train_n=18000, calib_n=2000, test_n=2000, steps=3000, batch=128, lr=2e-3, depth=DEPTH, seed=0,
         log_every=250):
     t = time.perf_counter()
@@ -193,6 +214,7 @@ def run(train_n=18000, calib_n=2000, test_n=2000, steps=3000, batch=128, lr=2e-3
                          "speedup": round(plain_s / sec_t, 3), "min_iou": float(iou_t.min()),
                          "sets_below_target": int((iou_t < target).sum())})
     # baselines without the trained network: untrained weights, and the mean training image
+    sens = sensitivity(ta_te, tb_te, occ_true, depth=depth)
     untrained = evaluate(init_params(seed + 1), ta_te, tb_te, occ_true, tau)[0]
     mean_img = (occ_all[:train_n].float().mean(0) >= 0.5).to(torch.uint8)
     iou_mean = kl.iou(occ_true, pred_occ=mean_img.expand(test_n, 128, 128).contiguous()).cpu().numpy()
@@ -212,6 +234,7 @@ def run(train_n=18000, calib_n=2000, test_n=2000, steps=3000, batch=128, lr=2e-3
         "held_out_iou_quantiles": {q: float(np.quantile(iou_sur, float(q))) for q in ("0.1", "0.5", "0.9", "0.99")}
         | {"max": float(iou_sur.max())},
         "tradeoff": tradeoff,
+        "parameter_sensitivity": sens,
     }, params
 
 

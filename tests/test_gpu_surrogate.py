@@ -76,6 +76,32 @@ def test_forward_matches_reference():
     assert np.abs(z - ref).max() <= 2e-2 * rms + 1e-4, (np.abs(z - ref).max(), rms)
 
 
+def test_fused_forward_is_batch_independent():
+    """Inference runs one set per workgroup: a set's logits do not depend on
+    the batch around it, from a batch of one to the largest batch."""
+    flat = _dev(_params(5))
+    ta, tb = _sets(512, 13)
+    full = kl.sur_forward(flat, ta, tb)
+    assert torch.isfinite(full).all()
+    for i in (0, 1, 255, 256, 511):
+        one = kl.sur_forward(flat, ta[i:i + 1], tb[i:i + 1])
+        assert torch.equal(one[0], full[i]), i
+    part = kl.sur_forward(flat, ta[100:137], tb[100:137])
+    assert torch.equal(part, full[100:137])
+
+
+def test_fused_forward_agrees_with_the_training_forward():
+    """Inference (fused decoder) and training (column form) round the same
+    operands to bfloat16; only the order of FP32 sums differs."""
+    flat = _params(6)
+    ta, tb = _sets(24, 14)
+    rng = np.random.default_rng(8)
+    targets = (rng.random((24, 128, 128)) < 0.05).astype(np.uint8)
+    loss, _ = kl.sur_loss_grad(_dev(flat), ta, tb, _dev(targets, torch.uint8))
+    z = kl.sur_forward(_dev(flat), ta, tb).cpu().numpy().astype(np.float64)
+    assert abs(N.bce_loss(z, targets)[0] - loss.item()) <= 1e-4 * abs(loss.item())
+
+
 def test_loss_and_gradients_match_reference():
     flat = _params(1)
     ta, tb = _sets(12, 12)
