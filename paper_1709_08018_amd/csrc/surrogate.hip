@@ -281,13 +281,20 @@ __global__ void colsum_stage1(const float* __restrict__ x, int64_t M, int C, int
         partial[(int64_t)blockIdx.x * C + threadIdx.x] = sum;
     }
 }
+// one workgroup per column: strided partial sums, then a fixed tree
 __global__ void colsum_stage2(const float* __restrict__ partial, int blocks, int C, float* __restrict__ out,
                               int accumulate) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= C) return;
+    __shared__ float red[256];
+    const int c = blockIdx.x;
     float sum = 0.f;
-    for (int b = 0; b < blocks; ++b) sum += partial[(int64_t)b * C + c];
-    out[c] = accumulate ? out[c] + sum : sum;
+    for (int b = threadIdx.x; b < blocks; b += 256) sum += partial[(int64_t)b * C + c];
+    red[threadIdx.x] = sum;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[c] = accumulate ? out[c] + red[0] : red[0];
 }
 
 static hipError_t colsum(const float* x, int64_t M, int C, float* out, float* partial, hipStream_t s) {
@@ -295,7 +302,7 @@ static hipError_t colsum(const float* x, int64_t M, int C, float* out, float* pa
     if (blocks < 1) blocks = 1;
     const int64_t rpb = (M + blocks - 1) / blocks;
     hipLaunchKernelGGL(colsum_stage1, dim3(blocks), dim3(256), 0, s, x, M, C, rpb, partial);
-    hipLaunchKernelGGL(colsum_stage2, dim3((C + 255) / 256), dim3(256), 0, s, partial, blocks, C, out, 0);
+    hipLaunchKernelGGL(colsum_stage2, dim3(C), dim3(256), 0, s, partial, blocks, C, out, 0);
     return hipGetLastError();
 }
 
@@ -319,10 +326,16 @@ __global__ void bce_kernel(const float* __restrict__ z, const uint8_t* __restric
     if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
 __global__ void loss_final_kernel(const float* partial, int blocks, int64_t n, float* loss) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    __shared__ float red[256];
     float s = 0.f;
-    for (int b = 0; b < blocks; ++b) s += partial[b];
-    *loss = s / (float)n;
+    for (int b = threadIdx.x; b < blocks; b += 256) s += partial[b];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *loss = red[0] / (float)n;
 }
 
 __global__ void adam_kernel(float* p, const float* g, float* m, float* v, int64_t n, float lr, float bc1, float bc2) {
@@ -802,7 +815,7 @@ static hipError_t loss_grad(const float* P, const kl_c64* ta, const kl_c64* tb, 
     const int64_t npx = (int64_t)B * kImg * kImg;
     const int bce_blocks = (int)std::min<int64_t>(1024, (npx + 255) / 256);
     hipLaunchKernelGGL(bce_kernel, dim3(bce_blocks), dim3(256), 0, s, w.logits, targets, npx, w.dlogits, w.partial);
-    hipLaunchKernelGGL(loss_final_kernel, dim3(1), dim3(64), 0, s, w.partial, bce_blocks, npx, loss);
+    hipLaunchKernelGGL(loss_final_kernel, dim3(1), dim3(256), 0, s, w.partial, bce_blocks, npx, loss);
     // C4 (no activation): d_out = dlogits
     CHECK_HIP(conv_backward(w.dlogits, w.y3, P + L.K4, 16, kC4, B, w.col4, G + L.K4, G + L.c4, w.dy3, w, s));
     hipLaunchKernelGGL(relu_mask_kernel, dim3(grid_for((int64_t)B * 4096 * 16)), dim3(256), 0, s, w.dy3, w.y3,

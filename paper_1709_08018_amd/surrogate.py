@@ -61,7 +61,7 @@ def render_occupancy(ta, tb, depth: int = DEPTH, chunk: int = 1024) -> torch.Ten
     return out
 
 
-def predict(params: torch.Tensor, ta, tb, batch: int = 256) -> torch.Tensor:
+def predict(params: torch.Tensor, ta, tb, batch: int = 512) -> torch.Tensor:
     n = len(ta)
     out = torch.empty((n, 128, 128), dtype=torch.float32, device="cuda")
     ws = kl.sur_workspace(min(batch, n))
@@ -116,7 +116,7 @@ def gate_threshold(uncertainty: np.ndarray, iou: np.ndarray, target: float = IOU
     return tau
 
 
-def scan(params: torch.Tensor, ta, tb, tau: float, depth: int = DEPTH, batch: int = 256):
+def scan(params: torch.Tensor, ta, tb, tau: float, depth: int = DEPTH, batch: int = 512):
     """Occupancy images of all sets: the surrogate's where the gate accepts it,
     the plain renderer's elsewhere.  Returns (occ, accepted, seconds)."""
     torch.cuda.synchronize()
@@ -176,6 +176,53 @@ def sensitivity(ta, tb, occ, eps_list=(1e-3, 3e-3, 1e-2, 3e-2), n=500, seed=5, d
     return out
 
 
+def _median_of(fn, reps):
+    """Run fn() reps times; its last return value is seconds.  Returns the last
+    result and the median time."""
+    times, out = [], None
+    for _ in range(reps):
+        out = fn()
+        times.append(out[-1])
+    return out, float(np.median(times))
+
+
+FWD_FLOP_PER_SET = 2 * 18_154_496   # two flops per multiply-add of one forward pass (the shapes above)
+
+
+def kernel_rates(params, ta, tb, batch=512, reps=20):
+    """Event-timed forward pass on `batch` sets and training step on 128."""
+    ws = kl.sur_workspace(batch)
+    ta_d, tb_d = kl.as_c64(ta[:batch]), kl.as_c64(tb[:batch])
+    out = torch.empty((batch, 128, 128), dtype=torch.float32, device="cuda")
+    for _ in range(3):
+        kl.sur_forward(params, ta_d, tb_d, workspace=ws, out=out)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        kl.sur_forward(params, ta_d, tb_d, workspace=ws, out=out)
+    e1.record()
+    torch.cuda.synchronize()
+    fwd_ms = e0.elapsed_time(e1) / reps
+    b = 128
+    p = params.clone()
+    m, v, g = torch.zeros_like(p), torch.zeros_like(p), torch.zeros_like(p)
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    occ = torch.zeros((b, 128, 128), dtype=torch.uint8, device="cuda")
+    ws = kl.sur_workspace(b)
+    for st in range(1, 4):
+        kl.sur_train_step(p, m, v, g, st, 1e-5, ta_d[:b], tb_d[:b], occ, ws, loss)
+    e0.record()
+    for st in range(4, 4 + reps):
+        kl.sur_train_step(p, m, v, g, st, 1e-5, ta_d[:b], tb_d[:b], occ, ws, loss)
+    e1.record()
+    torch.cuda.synchronize()
+    step_ms = e0.elapsed_time(e1) / reps
+    return {"forward_sets": batch, "forward_ms": round(fwd_ms, 4),
+            "forward_tflops": round(batch * FWD_FLOP_PER_SET / fwd_ms / 1e9, 1),
+            "train_step_sets": b, "train_step_ms": round(step_ms, 4),
+            "train_step_tflops": round(3 * b * FWD_FLOP_PER_SET / step_ms / 1e9, 1)}
+
+
 def run(train_n=18000, calib_n=2000, test_n=2000, steps=3000, batch=128, lr=2e-3, depth=DEPTH, seed=0,
         log_every=250):
     t = time.perf_counter()
@@ -198,9 +245,9 @@ def run(train_n=18000, calib_n=2000, test_n=2000, steps=3000, batch=128, lr=2e-3
     tau = gate_threshold(unc_cal, iou_cal)
     # held-out: plain scan (the judge) and gated surrogate scan
     plain_scan(ta_te[:64], tb_te[:64], depth)  # warm-up
-    occ_true, plain_s = plain_scan(ta_te, tb_te, depth)
+    (occ_true, _), plain_s = _median_of(lambda: plain_scan(ta_te, tb_te, depth), 5)
     scan(params, ta_te[:64], tb_te[:64], tau, depth)  # warm-up
-    occ_scan, accepted, scan_s = scan(params, ta_te, tb_te, tau, depth)
+    (occ_scan, accepted, _), scan_s = _median_of(lambda: scan(params, ta_te, tb_te, tau, depth), 5)
     scan_iou = kl.iou(occ_true, pred_occ=occ_scan).cpu().numpy()
     ev, iou_sur, _ = evaluate(params, ta_te, tb_te, occ_true, tau)
     # what the gate buys at other quality bars: calibrated on the calibration sets,
@@ -208,13 +255,14 @@ def run(train_n=18000, calib_n=2000, test_n=2000, steps=3000, batch=128, lr=2e-3
     tradeoff = []
     for target in (0.5, 0.6, 0.7, 0.8, 0.9, IOU_TARGET):
         tau_t = gate_threshold(unc_cal, iou_cal, target)
-        occ_t, acc_t, sec_t = scan(params, ta_te, tb_te, tau_t, depth)
+        (occ_t, acc_t, _), sec_t = _median_of(lambda: scan(params, ta_te, tb_te, tau_t, depth), 5)
         iou_t = kl.iou(occ_true, pred_occ=occ_t).cpu().numpy()
         tradeoff.append({"iou_target": target, "accepted": int(acc_t.sum()), "seconds": round(sec_t, 4),
                          "speedup": round(plain_s / sec_t, 3), "min_iou": float(iou_t.min()),
                          "sets_below_target": int((iou_t < target).sum())})
     # baselines without the trained network: untrained weights, and the mean training image
     sens = sensitivity(ta_te, tb_te, occ_true, depth=depth)
+    rates = kernel_rates(params, ta_te, tb_te)
     untrained = evaluate(init_params(seed + 1), ta_te, tb_te, occ_true, tau)[0]
     mean_img = (occ_all[:train_n].float().mean(0) >= 0.5).to(torch.uint8)
     iou_mean = kl.iou(occ_true, pred_occ=mean_img.expand(test_n, 128, 128).contiguous()).cpu().numpy()
@@ -235,6 +283,8 @@ def run(train_n=18000, calib_n=2000, test_n=2000, steps=3000, batch=128, lr=2e-3
         | {"max": float(iou_sur.max())},
         "tradeoff": tradeoff,
         "parameter_sensitivity": sens,
+        "kernel_rates": rates,
+        "timing": "plain and gated scans: median of 5 runs each",
     }, params
 
 
