@@ -872,6 +872,17 @@ static int make_cayley(const kl_cayley* t, int min_depth, int max_depth, bool ne
         start += n;
     }
     j->depth_start[max_depth - min_depth + 1] = start;
+    // tail length of the head/tail evaluation: the longest r <= 12 (and <= the
+    // largest depth) whose regular words fit the tail table
+    for (int r = std::min(kCayleyMaxTail, max_depth); r >= 1; --r) {
+        uint64_t n = 0;
+        for (int s = 1; s < S; ++s) n += C[r][s];
+        if (n <= (uint64_t)kCayleyMaxTails) {
+            j->r = r;
+            j->n_tails = (int)n;
+            break;
+        }
+    }
     // the good sets reachable from the set of all states, and their transitions
     auto extend = [&](uint32_t good, int x) {
         uint32_t g = 0;
@@ -1021,7 +1032,7 @@ int kl_cayley_render_ex(const kl_cayley* t, int depth, const kl_window* window, 
     j.W = window->width;
     j.H = window->height;
     j.dropped = o.dropped_out;
-    j.grid_blocks = device_cu_count() * 8;
+    j.grid_blocks = device_cu_count() * 2;   // the tail table fits two workgroups per CU
     for (int sd : seeds) {
         j.seed = sd;
         if ((e = launch_cayley(j, kCayleyRender, s)) != hipSuccess) return hip_fail(e, "Cayley render kernel");

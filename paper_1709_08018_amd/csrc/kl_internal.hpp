@@ -182,6 +182,8 @@ hipError_t launch_render_batch(const BatchJob& job, hipStream_t s);
 constexpr int kCayleyMaxStates = 16;
 constexpr int kCayleyMaxSymbols = 8;
 constexpr int kCayleyMaxSets = 64;      // good-state sets reachable from the set of all states
+constexpr int kCayleyMaxTails = 1024;   // entries of the tail table
+constexpr int kCayleyMaxTail = 12;      // its longest tails
 enum { kCayleyDecode = 0, kCayleyEval = 1, kCayleyRender = 2 };
 struct CayleyJob {
     uint8_t table[kCayleyMaxStates * (kCayleyMaxSymbols + 1)];
@@ -205,6 +207,10 @@ struct CayleyJob {
     const uint64_t* idx;                // eval: count indices of words of max_depth
     c64* z_out;                         // eval
     int grid_blocks;
+    // head/tail evaluation of words of depth >= r (r = 0: none): a table of the
+    // n_tails regular words of length r, their end states and their points
+    int r, n_tails;
+    int run;                            // render: consecutive words per thread
 };
 hipError_t launch_cayley(const CayleyJob& j, int mode, hipStream_t s);
 
