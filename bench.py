@@ -40,6 +40,9 @@ SURVEY_FP32_EQUIV_FLOPS_PER_WORD = 252 + 2 * 45
 FP32_PEAK_TFLOPS = 157.3  # MI355X FP32 vector peak (counts packed FMA)
 EVENT_EVERY = 10
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "render_kernel_quasifuchsian_d18_pmc.txt")
+VALU_SUMMARY = os.path.join(ROOT, "profiles", "render_kernel_quasifuchsian_d18_valu.txt")
+# VALU issue slots: 256 CUs x 4 SIMDs, one wave64 instruction per 4 cycles each, at 2.4 GHz
+SIMDS, CLOCK_HZ, CYCLES_PER_VALU = 1024, 2.4e9, 4
 KERNEL_SRC = os.path.join(ROOT, "paper_1709_08018_amd", "csrc", "kernels.hip")
 
 
@@ -51,14 +54,14 @@ def _hip():
     return lib
 
 
-def _traffic_from_profile(plan):
-    """HBM bytes per launch from the committed counter summary, if it was
-    taken on the current kernel source and split; else None."""
-    if not os.path.exists(PMC_SUMMARY):
+def _profile_value(path, key, plan):
+    """A figure from a committed counter summary, if the summary was taken on
+    the current kernel source and split; else None."""
+    if not os.path.exists(path):
         return None
     src_hash = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
     vals = {}
-    for line in open(PMC_SUMMARY):
+    for line in open(path):
         if ": " in line:
             k, v = line.split(": ", 1)
             vals[k.strip()] = v.strip()
@@ -68,9 +71,19 @@ def _traffic_from_profile(plan):
     if split not in vals.get("split", ""):
         return None
     try:
-        return float(vals["hbm_bytes_per_launch"])
+        return float(vals[key])
     except (KeyError, ValueError):
         return None
+
+
+def _traffic_from_profile(plan):
+    """HBM bytes per launch (FETCH_SIZE and WRITE_SIZE, copy-calibrated)."""
+    return _profile_value(PMC_SUMMARY, "hbm_bytes_per_launch", plan)
+
+
+def _valu_per_wave_word(plan):
+    """VALU instructions per 64 words (SQ_INSTS_VALU over the words)."""
+    return _profile_value(VALU_SUMMARY, "VALU instructions per wave-word (64 words)", plan)
 
 
 def cpu_baseline(wl_obj, seconds_hint: float):
@@ -421,6 +434,12 @@ def main():
                 "flops_per_word": FLOPS_PER_WORD, "words_per_launch": kernel_words,
                 "useful_frac_point_walk_formulation": round(
                     SURVEY_FP32_EQUIV_FLOPS_PER_WORD * kernel_words / (kernel_avg * 1e-3) / 1e12 / FP32_PEAK_TFLOPS, 3)}
+    # VALU issue: the kernel's VALU instructions (counters) against the issue slots
+    # of its measured duration at the nominal 4 cycles per wave64 instruction
+    vpw = _valu_per_wave_word(plan)
+    roofline["valu_instr_per_wave_word"] = vpw
+    roofline["valu_issue_frac_nominal"] = None if vpw is None else round(
+        vpw * (kernel_words / 64) * CYCLES_PER_VALU / (kernel_avg * 1e-3 * CLOCK_HZ * SIMDS), 3)
 
     out = {
         "metric": METRIC,

@@ -49,3 +49,15 @@ def test_multi_gpu_request_exits_with_a_message():
     r = subprocess.run([sys.executable, bench.__file__, "--gpus", "2"], capture_output=True, text=True, timeout=120)
     assert r.returncode != 0
     assert "one GPU" in (r.stdout + r.stderr) or "single GPU" in (r.stdout + r.stderr)
+
+
+def test_valu_figure_read_with_the_same_checks(tmp_path, monkeypatch):
+    p = tmp_path / "valu.txt"
+    p.write_text(f"kernels.hip sha256[:16]: {_current_hash()}\n"
+                 "split: prefix 9, lane 3, tail 6 letters; 32 waves per CU\n"
+                 "VALU instructions per wave-word (64 words): 20.49\n")
+    monkeypatch.setattr(bench, "VALU_SUMMARY", str(p))
+    assert bench._valu_per_wave_word(SPLIT) == 20.49
+    p.write_text("kernels.hip sha256[:16]: 0000000000000000\nsplit: prefix 9, lane 3, tail 6 letters\n"
+                 "VALU instructions per wave-word (64 words): 20.49\n")
+    assert bench._valu_per_wave_word(SPLIT) is None
