@@ -650,12 +650,200 @@ static int check_render(int depth, const kl_window* window, const uint32_t* imag
     return KL_OK;
 }
 
+// One set of a batched render: its generators, split, seed and outputs.
+struct SetSpec {
+    Gens gens;
+    Split sp;
+    int seed;
+    uint32_t* image;
+    uint64_t* dropped;
+};
+
+// Many sets in a few launches: one table launch builds every set's prefix
+// and suffix tables, one persistent launch renders the sets the persistent
+// kernel takes (whole heads), one per-word launch renders the rest.  Sets
+// may share an image and a dropped counter.  Every word is evaluated with
+// its set's split and tables, bit for bit as a single render of that set.
+// The descriptors are uploaded from host memory; the call waits for those
+// copies (not for the renders) before it returns.
+static int render_sets(const std::vector<SetSpec>& specs, const kl_window* w, const kl_opts& o, int wpc,
+                       hipStream_t s) {
+    const int nb = (int)specs.size();
+    if (nb == 0) return KL_OK;
+    const size_t esz = o.precision == KL_PREC_FP64 ? sizeof(c64) : sizeof(c32);
+    uint64_t n_prefix = 0, n_tail = 0;
+    uint32_t max_prefix = 0, max_tail = 0;
+    for (const SetSpec& q : specs) {
+        const uint32_t np = q.sp.k ? (uint32_t)num_words(q.sp.k) : 0;
+        const uint32_t nt = (uint32_t)num_words(q.sp.r);
+        n_prefix += np;
+        n_tail += nt;
+        max_prefix = std::max(max_prefix, np);
+        max_tail = std::max(max_tail, nt);
+    }
+    // every temporary in one allocation: the descriptors (uploaded together)
+    // then the tables
+    std::vector<SetDesc> h_sets(nb), h_psets;
+    std::vector<uint64_t> h_off(1, 0), h_woff(1, 0);
+    std::vector<int> h_ids;
+    for (int j = 0; j < nb; ++j) {
+        if (persistent_ok(specs[j].sp)) {
+            h_off.push_back(h_off.back() + (specs[j].sp.n_heads + kBlock - 1) / kBlock);  // block units: one head per thread
+        } else {
+            h_ids.push_back(j);
+            h_woff.push_back(h_woff.back() + num_words(specs[j].sp.depth));
+        }
+    }
+    const int np_sets = (int)h_off.size() - 1, nw_sets = (int)h_ids.size();
+    size_t off = 0;
+    auto place = [&](size_t bytes) {
+        const size_t at = off;
+        off += round16(bytes);
+        return at;
+    };
+    const size_t o_sets = place(nb * sizeof(SetDesc)), o_psets = place(np_sets * sizeof(SetDesc));
+    const size_t o_off = place(h_off.size() * sizeof(uint64_t)), o_woff = place(h_woff.size() * sizeof(uint64_t));
+    const size_t o_ids = place(nw_sets * sizeof(int)), o_flags = place(nb * sizeof(uint32_t));
+    const size_t upload = off;
+    const size_t o_prefix = place(n_prefix * sizeof(m64)), o_last = place(n_prefix + 16);
+    const size_t o_aff = place(n_tail * esz + 16 * nb), o_hom = place(2 * n_tail * esz + 16 * nb);
+    Temp tmp(s);
+    unsigned char* base = nullptr;
+    hipError_t e;
+    if ((e = tmp.alloc((void**)&base, off)) != hipSuccess) return hip_fail(e, "batch temporaries");
+    SetDesc* d_sets = (SetDesc*)(base + o_sets);
+    SetDesc* d_psets = (SetDesc*)(base + o_psets);
+    uint64_t* d_off = (uint64_t*)(base + o_off);
+    uint64_t* d_woff = (uint64_t*)(base + o_woff);
+    int* d_ids = (int*)(base + o_ids);
+    uint32_t* d_flags = (uint32_t*)(base + o_flags);
+    m64* d_prefix = (m64*)(base + o_prefix);
+    uint8_t* d_last = base + o_last;
+    unsigned char* d_aff = base + o_aff;
+    unsigned char* d_hom = base + o_hom;
+    uint64_t po = 0, to_aff = 0, to_hom = 0;
+    uint32_t max_bytes = 0;
+    for (int j = 0; j < nb; ++j) {
+        const SetSpec& q = specs[j];
+        SetDesc& D = h_sets[j];
+        memset(&D, 0, sizeof D);
+        D.gens = q.gens;
+        D.sp = q.sp;
+        D.seed = q.seed;
+        D.n_prefix = q.sp.k ? (uint32_t)num_words(q.sp.k) : 0;
+        D.n_tail = (uint32_t)num_words(q.sp.r);
+        D.tab.prefix = d_prefix + po;
+        D.tab.prefix_last = d_last + po;
+        D.tab.tail = d_aff + to_aff;
+        D.tail_homog = d_hom + to_hom;
+        D.tab.tail_flags = d_flags + j;
+        D.tab.n_flags = 1;
+        D.image = q.image;
+        D.dropped = q.dropped;
+        po += D.n_prefix;
+        to_aff += ((D.n_tail * esz + 15) / 16) * 16;
+        to_hom += ((2 * D.n_tail * esz + 15) / 16) * 16;
+        if (persistent_ok(q.sp)) {
+            max_bytes = std::max<uint32_t>(max_bytes, (uint32_t)(((2 * D.n_tail * esz + 15) / 16) * 16));
+            h_psets.push_back(D);
+        }
+    }
+    std::vector<unsigned char> blob(upload, 0);   // the form flags start at zero
+    memcpy(blob.data() + o_sets, h_sets.data(), nb * sizeof(SetDesc));
+    if (np_sets) memcpy(blob.data() + o_psets, h_psets.data(), np_sets * sizeof(SetDesc));
+    memcpy(blob.data() + o_off, h_off.data(), h_off.size() * sizeof(uint64_t));
+    memcpy(blob.data() + o_woff, h_woff.data(), h_woff.size() * sizeof(uint64_t));
+    if (nw_sets) memcpy(blob.data() + o_ids, h_ids.data(), nw_sets * sizeof(int));
+    if ((e = hipMemcpyAsync(base, blob.data(), upload, hipMemcpyHostToDevice, s)) != hipSuccess)
+        return hip_fail(e, "batch descriptors");
+    hipEvent_t copied;
+    if ((e = hipEventCreateWithFlags(&copied, hipEventDisableTiming)) != hipSuccess) return hip_fail(e, "event");
+    e = hipEventRecord(copied, s);
+    int rc = KL_OK;
+    BatchJob job{};
+    job.sets = d_sets;
+    job.n_sets = nb;
+    job.precision = o.precision;
+    job.fold = make_fold(w, o.head_form);
+    job.width = w->width;
+    job.height = w->height;
+    job.grid_blocks = grid_for(wpc);
+    job.max_prefix = max_prefix;
+    job.max_tail = max_tail;
+    job.force_homog = o.suffix_form;
+    job.count_dropped = o.dropped_out != nullptr;
+    if (e == hipSuccess) e = launch_batch_tables(job, s);
+    if (e == hipSuccess && np_sets) {
+        BatchJob pj = job;
+        pj.sets = d_psets;
+        pj.n_sets = np_sets;
+        pj.unit_offsets = d_off;
+        pj.total_units = h_off.back();
+        pj.table_bytes = max_bytes;
+        e = launch_render_batch(pj, s);
+    }
+    if (e == hipSuccess && nw_sets) {
+        PerWordBatchJob wj{};
+        wj.sets = d_sets;
+        wj.word_offsets = d_woff;
+        wj.set_ids = d_ids;
+        wj.n = nw_sets;
+        wj.total = h_woff.back();
+        wj.precision = o.precision;
+        wj.fold = job.fold;
+        wj.width = w->width;
+        wj.height = w->height;
+        e = launch_perword_batch(wj, s);
+    }
+    if (e != hipSuccess) rc = hip_fail(e, "batch render");
+    // the descriptors live in host vectors: wait for their copies before they go
+    const hipError_t e2 = hipEventSynchronize(copied);
+    (void)hipEventDestroy(copied);
+    if (rc == KL_OK && e2 != hipSuccess) rc = hip_fail(e2, "batch descriptors");
+    return rc;
+}
+
+// A tiling render of its whole index space: every depth of every seed is one
+// set of a batched render into the one image, each set planned as a single
+// render of its depth would be, so the image is the same.
+static int render_tiling(const Gens& G, int depth, const kl_window* w, uint32_t* image, const kl_opts& o,
+                         int min_depth) {
+    hipStream_t s = (hipStream_t)o.stream;
+    std::vector<int> seeds;
+    if (o.seed_mode == KL_SEED_ALL) seeds = {0, 1, 2, 3};
+    else seeds = {seed_index(o)};
+    std::vector<SetSpec> specs;
+    int wpc = o.waves_per_cu;
+    for (int sd : seeds)
+        for (int d = min_depth; d <= depth; ++d) {
+            const kl_opts od = apply_tuned(d == depth ? o : opts_for_depth(o, d), d, w);
+            Split sp;
+            int rc = plan_split(d, od.precision, od.tail_len, od.lane_len, &sp);
+            if (rc) return rc;
+            if (!wpc && d == depth) wpc = od.waves_per_cu;
+            specs.push_back({G, sp, sd, image, o.dropped_out});
+        }
+    if (!o.accumulate) {
+        hipError_t e;
+        if ((e = launch_fill_u32(image, (uint64_t)w->width * w->height, 0, s)) != hipSuccess)
+            return hip_fail(e, "clear image");
+        if (o.dropped_out && (e = launch_fill_u64(o.dropped_out, 1, 0, s)) != hipSuccess)
+            return hip_fail(e, "clear dropped");
+    }
+    return render_sets(specs, w, o, wpc, s);
+}
+
 // The render itself, once every argument has been checked.  KL_SEED_ALL is
 // four renders of the same words, one per generator's fixed point (the
 // paper's index-search loop), accumulated.
 static int render_run(const Gens& G, int depth, const kl_window* window, uint32_t* image_out, const kl_opts& o,
                       const RenderSpan& span) {
     int rc;
+    if (span.min_depth < depth && !o.kernel_events[0] && !o.kernel_events[1]) {
+        uint64_t total = 0;
+        for (int d = span.min_depth; d <= depth; ++d) total += num_words(d);
+        if (span.first == 0 && span.count == total) return render_tiling(G, depth, window, image_out, o, span.min_depth);
+    }
     if (o.seed_mode == KL_SEED_ALL) {
         for (int q = 0; q < 4; ++q) {
             kl_opts oq = o;
@@ -1076,7 +1264,6 @@ int kl_render_many_ex(int n, const kl_c64* ta, const kl_c64* tb, const int* dept
             return fail(rc, "set %d: %s", i, m.c_str());
         }
     }
-    const Fold f = make_fold(window, o.head_form);
     hipStream_t s = (hipStream_t)o.stream;
     hipError_t e;
     if (!o.accumulate) {
@@ -1084,94 +1271,13 @@ int kl_render_many_ex(int n, const kl_c64* ta, const kl_c64* tb, const int* dept
         if (o.dropped_out && (e = launch_fill_u64(o.dropped_out, (uint64_t)n, 0, s)) != hipSuccess)
             return hip_fail(e, "clear dropped");
     }
-    // persistent sets share one launch; the rest (shallow depths) render one by one
-    std::vector<int> batch;
-    for (int i = 0; i < n; ++i)
-        if (persistent_ok(splits[i])) batch.push_back(i);
-        else if ((rc = render_depth(gens[i], f, depth[i], 0, num_words(depth[i]), per[i], window, images_out + bins * i,
-                                    o.dropped_out ? o.dropped_out + i : nullptr, s, false)))
-            return rc;
-    if (batch.empty()) return KL_OK;
-    const int nb = (int)batch.size();
-    const size_t esz = o.precision == KL_PREC_FP64 ? sizeof(c64) : sizeof(c32);
-    uint64_t n_prefix = 0, n_tail = 0;
-    uint32_t max_prefix = 0, max_tail = 0;
-    for (int i : batch) {
-        const uint32_t np = splits[i].k ? (uint32_t)num_words(splits[i].k) : 0;
-        const uint32_t nt = (uint32_t)num_words(splits[i].r);
-        n_prefix += np;
-        n_tail += nt;
-        max_prefix = std::max(max_prefix, np);
-        max_tail = std::max(max_tail, nt);
+    std::vector<SetSpec> specs(n);
+    int wpc = o.waves_per_cu;
+    for (int i = 0; i < n; ++i) {
+        specs[i] = {gens[i], splits[i], seed_index(o), images_out + bins * i, o.dropped_out ? o.dropped_out + i : nullptr};
+        if (!wpc && persistent_ok(splits[i])) wpc = per[i].waves_per_cu;
     }
-    Temp tmp(s);
-    SetDesc* d_sets = nullptr;
-    uint64_t* d_off = nullptr;
-    m64* d_prefix = nullptr;
-    uint8_t* d_last = nullptr;
-    unsigned char *d_aff = nullptr, *d_hom = nullptr;
-    uint32_t* d_flags = nullptr;
-    if ((e = tmp.alloc((void**)&d_sets, nb * sizeof(SetDesc))) != hipSuccess ||
-        (e = tmp.alloc((void**)&d_off, (nb + 1) * sizeof(uint64_t))) != hipSuccess ||
-        (e = tmp.alloc((void**)&d_prefix, n_prefix * sizeof(m64))) != hipSuccess ||
-        (e = tmp.alloc((void**)&d_last, n_prefix + 16)) != hipSuccess ||
-        (e = tmp.alloc((void**)&d_aff, n_tail * esz + 16 * nb)) != hipSuccess ||
-        (e = tmp.alloc((void**)&d_hom, 2 * n_tail * esz + 16 * nb)) != hipSuccess ||
-        (e = tmp.alloc((void**)&d_flags, nb * sizeof(uint32_t))) != hipSuccess)
-        return hip_fail(e, "batch temporaries");
-    std::vector<SetDesc> h_sets(nb);
-    std::vector<uint64_t> h_off(nb + 1);
-    uint64_t po = 0, to_aff = 0, to_hom = 0, units = 0;
-    uint32_t max_bytes = 0;
-    for (int j = 0; j < nb; ++j) {
-        const int i = batch[j];
-        SetDesc& D = h_sets[j];
-        memset(&D, 0, sizeof D);
-        D.gens = gens[i];
-        D.sp = splits[i];
-        D.n_prefix = splits[i].k ? (uint32_t)num_words(splits[i].k) : 0;
-        D.n_tail = (uint32_t)num_words(splits[i].r);
-        D.tab.prefix = d_prefix + po;
-        D.tab.prefix_last = d_last + po;
-        D.tab.tail = d_aff + to_aff;
-        D.tail_homog = d_hom + to_hom;
-        D.tab.tail_flags = d_flags + j;
-        D.tab.n_flags = 1;
-        D.image = images_out + bins * i;
-        D.dropped = o.dropped_out ? o.dropped_out + i : nullptr;
-        po += D.n_prefix;
-        to_aff += ((D.n_tail * esz + 15) / 16) * 16;
-        to_hom += ((2 * D.n_tail * esz + 15) / 16) * 16;
-        max_bytes = std::max<uint32_t>(max_bytes, (uint32_t)(((2 * D.n_tail * esz + 15) / 16) * 16));
-        h_off[j] = units;
-        units += (splits[i].n_heads + kBlock - 1) / kBlock;  // block units: one head per thread
-    }
-    h_off[nb] = units;
-    if ((e = hipMemcpyAsync(d_sets, h_sets.data(), nb * sizeof(SetDesc), hipMemcpyHostToDevice, s)) != hipSuccess ||
-        (e = hipMemcpyAsync(d_off, h_off.data(), (nb + 1) * sizeof(uint64_t), hipMemcpyHostToDevice, s)) != hipSuccess)
-        return hip_fail(e, "batch descriptors");
-    if ((e = launch_fill_u32(d_flags, nb, 0, s)) != hipSuccess) return hip_fail(e, "fill");
-    BatchJob job{};
-    job.sets = d_sets;
-    job.unit_offsets = d_off;
-    job.n_sets = nb;
-    job.total_units = units;
-    job.precision = o.precision;
-    job.fold = f;
-    job.width = window->width;
-    job.height = window->height;
-    job.grid_blocks = grid_for(o.waves_per_cu ? o.waves_per_cu : per[batch[0]].waves_per_cu);
-    job.table_bytes = max_bytes;
-    job.max_prefix = max_prefix;
-    job.max_tail = max_tail;
-    job.force_homog = o.suffix_form;
-    job.seed = seed_index(o);
-    job.count_dropped = o.dropped_out != nullptr;
-    if ((e = launch_batch_tables(job, s)) != hipSuccess) return hip_fail(e, "batch tables");
-    if ((e = launch_render_batch(job, s)) != hipSuccess) return hip_fail(e, "batch render");
-    // the descriptors live in host vectors: finish the copies before they go
-    if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "batch");
-    return KL_OK;
+    return render_sets(specs, window, o, wpc, s);
 }
 
 int kl_render_many(int n, const kl_c64* ta, const kl_c64* tb, const int* depth, const kl_window* window,

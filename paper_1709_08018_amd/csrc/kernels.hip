@@ -783,31 +783,36 @@ struct PerWordArgs {
 
 // Value of word i of depth sp.depth, with the renderer's arithmetic.
 template <typename T>
-__device__ inline void word_point(uint64_t i, const PerWordArgs& a, const m64* G, bool affine, T& px, T& py) {
-    const Split& sp = a.sp;
+__device__ inline void word_point(uint64_t i, const Split& sp, const Tables& tab, const void* tail_homog,
+                                  const Fold& fold, const m64* G, bool affine, T& px, T& py) {
     Head<T> h;
     uint64_t entry;
     if (sp.k + sp.m == 0) {
-        h = compute_head<T>(0, sp, nullptr, nullptr, G, a.fold);
+        h = compute_head<T>(0, sp, nullptr, nullptr, G, fold);
         entry = i;
     } else {
         const uint64_t hidx = i / sp.R;
         const uint32_t t = (uint32_t)(i - hidx * sp.R);
-        h = compute_head<T>(hidx, sp, a.tab.prefix, a.tab.prefix_last, G, a.fold);
+        h = compute_head<T>(hidx, sp, tab.prefix, tab.prefix_last, G, fold);
         const uint32_t j = t / sp.R1;
         const uint32_t tt = t - j * sp.R1;
         const int y1 = (int)j + ((int)j >= inv_letter(h.e));
         entry = (uint64_t)y1 * sp.R1 + tt;
     }
     if (affine) {
-        const cpx<T> y = ((const cpx<T>*)a.tab.tail)[entry];
+        const cpx<T> y = ((const cpx<T>*)tab.tail)[entry];
         if (h.pole) eval_pole(h, y, px, py);
         else eval_general(h, y, px, py);
     } else {
-        const cpx<T>* hm = (const cpx<T>*)a.tail_homog;
+        const cpx<T>* hm = (const cpx<T>*)tail_homog;
         if (h.pole) eval_pole_h(h, hm[2 * entry], hm[2 * entry + 1], px, py);
         else eval_general_h(h, hm[2 * entry], hm[2 * entry + 1], px, py);
     }
+}
+
+template <typename T>
+__device__ inline void word_point(uint64_t i, const PerWordArgs& a, const m64* G, bool affine, T& px, T& py) {
+    word_point<T>(i, a.sp, a.tab, a.tail_homog, a.fold, G, affine, px, py);
 }
 
 template <typename T>
@@ -830,6 +835,51 @@ __global__ __launch_bounds__(256) void perword_render_kernel(const PerWordArgs a
         if ((threadIdx.x & (kWave - 1)) == 0 && drop)
             atomicAdd((unsigned long long*)a.dropped, (unsigned long long)drop);
     }
+}
+
+// Words of several sets (their tables built by the batch table kernels, one
+// form flag word per set), one per thread.  Dropped words are summed over
+// the wave when its lanes share one counter, else counted lane by lane.
+template <typename T>
+__global__ __launch_bounds__(256) void perword_batch_kernel(const PerWordBatchJob a) {
+    const int lane = (int)(threadIdx.x & (kWave - 1));
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < a.total; w += stride) {
+        int lo = 0, hi = a.n - 1;   // the last q with word_offsets[q] <= w
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (a.word_offsets[mid] <= w) lo = mid;
+            else hi = mid - 1;
+        }
+        const SetDesc& S = a.sets[a.set_ids[lo]];
+        const bool affine = S.tab.tail_flags[0] == 0u;
+        T px, py;
+        word_point<T>(w - a.word_offsets[lo], S.sp, S.tab, S.tail_homog, a.fold, S.gens.g, affine, px, py);
+        const uint32_t key = bin_key(px, py, a.width, a.height);
+        if (key != kOutside) atomicAdd(S.image + key, 1u);
+        uint64_t* dst = S.dropped;
+        const uint64_t bits = (uint64_t)dst;
+        const uint32_t b0 = __builtin_amdgcn_readfirstlane((uint32_t)bits);
+        const uint32_t b1 = __builtin_amdgcn_readfirstlane((uint32_t)(bits >> 32));
+        const bool same = (uint32_t)bits == b0 && (uint32_t)(bits >> 32) == b1;
+        if (__ballot(!same) == 0) {
+            const uint64_t n = (uint64_t)__popcll(__ballot(key == kOutside));
+            const int first = __ffsll((long long)__ballot(1)) - 1;
+            if (lane == first && dst && n) atomicAdd((unsigned long long*)dst, (unsigned long long)n);
+        } else if (key == kOutside && dst) {
+            atomicAdd((unsigned long long*)dst, 1ull);
+        }
+    }
+}
+
+hipError_t launch_perword_batch(const PerWordBatchJob& job, hipStream_t s) {
+    if (job.total == 0) return hipSuccess;
+    const uint64_t blocks = std::min<uint64_t>((job.total + 255) / 256, 8192);
+    if (job.precision == KL_PREC_FP64)
+        hipLaunchKernelGGL(perword_batch_kernel<double>, dim3((unsigned)blocks), dim3(256), 0, s, job);
+    else
+        hipLaunchKernelGGL(perword_batch_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, s, job);
+    return hipGetLastError();
 }
 
 template <typename T>
@@ -956,14 +1006,13 @@ __global__ __launch_bounds__(256) void prefix_table_batch_kernel(const SetDesc* 
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void tail_table_batch_kernel(const SetDesc* __restrict__ sets, int force_homog,
-                                                               int seed) {
+__global__ __launch_bounds__(256) void tail_table_batch_kernel(const SetDesc* __restrict__ sets, int force_homog) {
     const SetDesc& S = sets[blockIdx.y];
     const uint32_t t = blockIdx.x * 256 + threadIdx.x;
     if (t >= S.n_tail) return;
     const Gens g = S.gens;
     uint32_t* flags = (uint32_t*)S.tab.tail_flags;
-    tail_entry<T>(g, S.sp.r, t, seed, (cpx<T>*)S.tab.tail, (cpx<T>*)S.tail_homog, flags);
+    tail_entry<T>(g, S.sp.r, t, S.seed, (cpx<T>*)S.tab.tail, (cpx<T>*)S.tail_homog, flags);
     if (force_homog && t == 0) atomicOr(flags, 1u);
 }
 
@@ -976,11 +1025,9 @@ hipError_t launch_batch_tables(const BatchJob& job, hipStream_t s) {
     }
     dim3 grid((job.max_tail + 255) / 256, job.n_sets);
     if (job.precision == KL_PREC_FP64)
-        hipLaunchKernelGGL(tail_table_batch_kernel<double>, grid, dim3(256), 0, s, job.sets, job.force_homog,
-                           job.seed);
+        hipLaunchKernelGGL(tail_table_batch_kernel<double>, grid, dim3(256), 0, s, job.sets, job.force_homog);
     else
-        hipLaunchKernelGGL(tail_table_batch_kernel<float>, grid, dim3(256), 0, s, job.sets, job.force_homog,
-                           job.seed);
+        hipLaunchKernelGGL(tail_table_batch_kernel<float>, grid, dim3(256), 0, s, job.sets, job.force_homog);
     return hipGetLastError();
 }
 

@@ -158,6 +158,7 @@ struct SetDesc {
     uint64_t* dropped;         // device u64 of this set (may be null)
     uint32_t n_prefix;         // 4*3^(k-1)
     uint32_t n_tail;           // 4*3^(r-1)
+    int seed;                  // as SetupJob::seed
 };
 struct BatchJob {
     const SetDesc* sets;           // device, n_sets entries
@@ -171,11 +172,24 @@ struct BatchJob {
     uint32_t table_bytes;          // LDS bytes of the largest suffix table (homogeneous form)
     uint32_t max_prefix, max_tail; // largest n_prefix / n_tail over the sets
     int force_homog;
-    int seed;                      // as SetupJob::seed
     int count_dropped;             // the sets' dropped counters are set
 };
 hipError_t launch_batch_tables(const BatchJob& job, hipStream_t s);
 hipError_t launch_render_batch(const BatchJob& job, hipStream_t s);
+
+// Every word of the sets too shallow for the persistent kernel, one per
+// thread: word w of the launch is word w - word_offsets[q] of set set_ids[q].
+struct PerWordBatchJob {
+    const SetDesc* sets;           // device (the batch's descriptors)
+    const uint64_t* word_offsets;  // device, n + 1 prefix sums of the sets' words
+    const int* set_ids;            // device, n indices into sets
+    int n;
+    uint64_t total;
+    int precision;
+    Fold fold;
+    uint32_t width, height;
+};
+hipError_t launch_perword_batch(const PerWordBatchJob& job, hipStream_t s);
 
 // Words of an indexed Cayley table (Section 5), one per thread.  Every field
 // is passed by value: the table, the maps and the seeds are small.

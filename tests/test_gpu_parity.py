@@ -330,3 +330,27 @@ def test_autotune_keeps_eval_and_render_consistent():
     p = kl.eval_values(*C2, depth, np.arange(n, dtype=np.uint64), window=win).cpu().numpy()
     ref, _ = _bins_from_pixels(p[:, 0], p[:, 1], win)
     np.testing.assert_array_equal(img, ref)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("seed", ["own", "all"])
+def test_tiling_render_equals_sum_of_single_depths(precision, seed):
+    """A tiling render of its whole index space runs as one batched render
+    (every depth and seed a set of it); it equals the single-depth renders
+    of each depth and seed added up, counts and dropped words alike."""
+    depth, mind, win = 12, 1, WIN_C2
+    dropped = torch.zeros(1, dtype=torch.int64, device="cuda")
+    img = kl.render(wl.C2_TA, wl.C2_TB, depth, win, precision=precision, min_depth=mind, seed=seed, dropped=dropped)
+    acc = kl.new_image(win)
+    dacc = torch.zeros(1, dtype=torch.int64, device="cuda")
+    first = True
+    for s in (["a", "b", "A", "B"] if seed == "all" else [seed]):
+        for d in range(mind, depth + 1):
+            kl.render(wl.C2_TA, wl.C2_TB, d, win, image=acc, precision=precision, seed=s, accumulate=not first,
+                      dropped=dacc)
+            first = False
+    assert torch.equal(img, acc)
+    assert int(dropped.item()) == int(dacc.item())
+    copies = 4 if seed == "all" else 1
+    assert int(kl.as_u32(img).astype(np.int64).sum()) + int(dropped.item()) == copies * sum(
+        kl.num_words(d) for d in range(mind, depth + 1))
