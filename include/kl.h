@@ -45,7 +45,10 @@
  * streams   the plain entry points run on the null stream and return after
  *           the device has finished; the *_ex entry points enqueue on
  *           opts->stream (a hipStream_t, NULL = null stream) and return at
- *           once, except where a host output is requested.
+ *           once, except where a host output is requested.  Batched renders
+ *           (kl_render_many_ex, and a tiling render of its whole index
+ *           space) upload their set descriptors from host memory and return
+ *           once that upload has finished, before the renders have.
  * errors    0 on success, a negative KL_E* code otherwise.  Every argument
  *           is validated before anything is enqueued, and on error no
  *           output is touched.  kl_strerror() names a code;
