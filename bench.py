@@ -99,6 +99,85 @@ def cpu_baseline(wl_obj, seconds_hint: float):
                       f"{threads} threads over contiguous index ranges, {dt:.2f} s"}, img, dropped
 
 
+# The oracle, timed beside the GPU legs: each returns a leg's "cpu_baseline"
+# object, with the leg's GPU image (or sampled values) compared against it.
+def _oracle():
+    from oracle import oracle as ref
+    return ref
+
+
+def cpu_baseline_d22(W, idx, p):
+    """The FP32 path's pixel error on the sampled words against the oracle's
+    FP64 values, and the oracle's rate on that sample."""
+    import numpy as np
+    ref = _oracle()
+    t0 = time.perf_counter()
+    z = ref.eval_values(W.ta, W.tb, W.depth, idx)
+    dt = time.perf_counter() - t0
+    x0, x1, y0, y1, Wd, Hd = W.window.as_tuple()
+    fx, fy = (z.real - x0) * Wd / (x1 - x0), (z.imag - y0) * Hd / (y1 - y0)
+    near = (fx > -1) & (fx < Wd + 1) & (fy > -1) & (fy < Hd + 1)
+    err = np.hypot(p[near, 0] - fx[near], p[near, 1] - fy[near])
+    return {"kind": "oracle", "value": round(len(idx) / dt / 1e9, 5), "unit": "Gwords/s", "cores": 1,
+            "sample": f"{len(idx)} sampled words, values by random access",
+            "fp32_pixel_error": {"max": float(err.max()), "p99": float(np.quantile(err, 0.99)),
+                                 "mean": float(err.mean()), "words": int(near.sum())}}
+
+
+def cpu_baseline_maskit(W, words, img):
+    """The oracle's render of the same tiling (all four seeds), timed, and the
+    GPU's FP64 image against it."""
+    import numpy as np
+    ref = _oracle()
+    threads = min(len(os.sched_getaffinity(0)), 16)
+    t0 = time.perf_counter()
+    ref_img, _, near = ref.render_group(ref.group_maskit(W.ta), W.depth, W.window.as_tuple(), seed=4,
+                                        min_depth=W.min_depth, edge_tol=1e-7, nthreads=threads)
+    dt = time.perf_counter() - t0
+    return {"kind": "oracle", "value": round(4 * words / dt / 1e9, 4), "unit": "Gpoints/s", "cores": threads,
+            "sample": "the full workload", "seconds": round(dt, 3),
+            "fp64_l1_vs_oracle": int(np.abs(img - ref_img.astype(np.int64)).sum()),
+            "oracle_near_edge_words": int(near)}
+
+
+def cpu_baseline_cayley_t11(ta, tb, depth, win, words, img):
+    """The oracle's render of the reduced words (the words of Table 2), timed,
+    and the table path's image against it."""
+    import numpy as np
+    ref = _oracle()
+    threads = min(len(os.sched_getaffinity(0)), 16)
+    t0 = time.perf_counter()
+    rimg, _, near = ref.render(ta, tb, depth, win, edge_tol=1e-7, nthreads=threads)
+    dt = time.perf_counter() - t0
+    return {"kind": "oracle", "value": round(words / dt / 1e9, 4), "unit": "Gwords/s", "cores": threads,
+            "sample": "the full workload", "seconds": round(dt, 3),
+            "l1_vs_oracle": int(np.abs(img - rimg.astype(np.int64)).sum()), "oracle_near_edge_words": int(near)}
+
+
+def cpu_baseline_cayley_modular(table, maps, win, words, img):
+    """The oracle's table render of the same tiling (every symbol's fixed
+    point), timed, and the GPU image against it."""
+    import numpy as np
+    ref = _oracle()
+    t0 = time.perf_counter()
+    rimg, _, near = ref.cayley_render(ref.Cayley(table, maps), 40, win, seed=3, min_depth=1, edge_tol=1e-7)
+    dt = time.perf_counter() - t0
+    return {"kind": "oracle", "value": round(3 * words / dt / 1e9, 4), "unit": "Gpoints/s", "cores": 1,
+            "sample": "the full workload", "seconds": round(dt, 3),
+            "l1_vs_oracle": int(np.abs(img - rimg.astype(np.int64)).sum()), "oracle_near_edge_words": int(near)}
+
+
+def cpu_baseline_decode(first, depth, rows, got):
+    """The oracle's unranking of the sampled rows, timed, against the kernel's."""
+    import numpy as np
+    ref = _oracle()
+    t0 = time.perf_counter()
+    want = np.array([ref.unrank(first + r, depth) for r in rows])
+    dt = time.perf_counter() - t0
+    return {"kind": "oracle", "value": round(len(rows) / dt / 1e9, 9), "unit": "Gwords/s", "cores": 1,
+            "sample": f"{len(rows)} words by random access", "rows_equal": bool(np.array_equal(want, got))}
+
+
 def _time(fn, steps, warmup):
     import torch
     for _ in range(warmup):
@@ -117,7 +196,6 @@ def leg_d22(args):
     import numpy as np
     import torch
 
-    from oracle import oracle as ref
     from paper_1709_08018_amd import kl
     from paper_1709_08018_amd import workloads as wl
 
@@ -139,14 +217,50 @@ def leg_d22(args):
         res[prec] = {"ms": round(ms, 3), "gwords_per_s": round(n / ms / 1e6, 2), "max_bin": int(h.max())}
     idx = wl.sample_indices(n, 1_000_000, seed=0)
     p = kl.eval_values(W.ta, W.tb, W.depth, idx, precision="fp32", window=W.window).cpu().numpy()
-    z = ref.eval_values(W.ta, W.tb, W.depth, idx)
-    x0, x1, y0, y1, Wd, Hd = W.window.as_tuple()
-    fx, fy = (z.real - x0) * Wd / (x1 - x0), (z.imag - y0) * Hd / (y1 - y0)
-    near = (fx > -1) & (fx < Wd + 1) & (fy > -1) & (fy < Hd + 1)
-    err = np.hypot(p[near, 0] - fx[near], p[near, 1] - fy[near])
     return {"workload": W.name, "words": n, "chunks": chunks, **res,
-            "fp32_pixel_error": {"max": float(err.max()), "p99": float(np.quantile(err, 0.99)),
-                                 "mean": float(err.mean()), "words": int(near.sum()), "sample": 1_000_000}}
+            "cpu_baseline": cpu_baseline_d22(W, idx, p)}
+
+
+def leg_decode(args):
+    """kl_decode at depth 18: 2^27 consecutive words from a third of the way
+    into the index space, written as a (count x 18) byte array.  The kernel
+    is bound by its HBM writes: 18 bytes per word."""
+    import torch
+
+    from paper_1709_08018_amd import kl
+
+    d, count = 18, 1 << 27
+    first = kl.num_words(d) // 3
+    out = torch.empty((count, d), dtype=torch.uint8, device="cuda")
+    for _ in range(3):
+        kl.decode(first, count, d, out=out)
+    reps = max(5, args.steps // 10)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        kl.decode(first, count, d, out=out)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    gbs = count * d / ms / 1e6
+    # the same bytes written by torch's fill kernel (8-byte elements): what plain writes reach
+    e0.record()
+    wide = out.view(-1)[: (count * d) // 8 * 8].view(torch.int64)
+    for _ in range(reps):
+        wide.fill_(7)
+    e1.record()
+    torch.cuda.synchronize()
+    fill_gbs = count * d / (e0.elapsed_time(e1) / reps) / 1e6
+    for _ in range(2):
+        kl.decode(first, count, d, out=out)
+    rows = [0, 1, count // 2, count - 1]
+    got = out[rows].cpu().numpy()
+    return {"workload": "decode_d18", "words": count, "first": first, "ms": round(ms, 4),
+            "gwords_per_s": round(count / ms / 1e6, 2),
+            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": 8000.0, "unit": "GB/s",
+                         "frac": round(gbs / 8000.0, 3), "bytes_per_word": d,
+                         "fill_kernel_gbs": round(fill_gbs, 1)},
+            "cpu_baseline": cpu_baseline_decode(first, d, rows, got)}
 
 
 def leg_batch(args):
@@ -226,7 +340,6 @@ def leg_maskit(args):
     times, and the FP64 image against the CPU reference's."""
     import numpy as np
 
-    from oracle import oracle as ref
     from paper_1709_08018_amd import kl
     from paper_1709_08018_amd import workloads as wl
 
@@ -241,16 +354,8 @@ def leg_maskit(args):
         out[prec] = {"ms": round(ms, 4), "gpoints_per_s": round(4 * words / ms / 1e6, 3)}
     kl.render_group(ab, W.depth, W.window, image=image, min_depth=W.min_depth, seed="all", precision="fp64")
     img = kl.as_u32(image).astype(np.int64)
-    threads = min(len(os.sched_getaffinity(0)), 16)
-    t0 = time.perf_counter()
-    ref_img, ref_drop, near = ref.render_group(ref.group_maskit(W.ta), W.depth, W.window.as_tuple(), seed=4,
-                                               min_depth=W.min_depth, edge_tol=1e-7, nthreads=threads)
-    dt = time.perf_counter() - t0
-    out["fp64_l1_vs_reference"] = int(np.abs(img - ref_img.astype(np.int64)).sum())
-    out["reference_near_edge_words"] = int(near)
     out["points_in_window"] = int(img.sum())
-    out["cpu_reference"] = {"seconds": round(dt, 3), "gpoints_per_s": round(4 * words / dt / 1e9, 4),
-                            "threads": threads}
+    out["cpu_baseline"] = cpu_baseline_maskit(W, words, img)
     return out
 
 
@@ -263,14 +368,12 @@ def leg_cayley(args):
     images are checked against the CPU reference."""
     import numpy as np
 
-    from oracle import oracle as ref
     from paper_1709_08018_amd import kl
     from paper_1709_08018_amd import workloads as wl
 
     out = {"workload": "cayley"}
-    threads = min(len(os.sched_getaffinity(0)), 16)
     t11 = np.array([[0, 1, 2, 3, 4], [1, 1, 2, 0, 4], [2, 1, 2, 3, 0], [3, 0, 2, 3, 4], [4, 1, 0, 3, 4]], np.uint8)
-    maps = ref.group_recipe(wl.C2_TA, wl.C2_TB).gens
+    maps = kl.generators(wl.C2_TA, wl.C2_TB)[1]   # a, b, A, B from the library's recipe
     win = wl.QUASIFUCHSIAN_D18.window.as_tuple()
     t = kl.Cayley(t11, maps)
     d = 16
@@ -281,13 +384,9 @@ def leg_cayley(args):
                     max(2, args.steps // 10), 2)
     kl.cayley_render(t, d, win, image=image)
     img = kl.as_u32(image).astype(np.int64)
-    t0 = time.perf_counter()
-    rimg, _, near = ref.render(wl.C2_TA, wl.C2_TB, d, win, edge_tol=1e-7, nthreads=threads)
-    dt = time.perf_counter() - t0
     out["t11_d16"] = {"words": n, "ms": round(ms, 4), "gwords_per_s": round(n / ms / 1e6, 3),
                       "specialised_fp64_ms": round(ms_spec, 4),
-                      "l1_vs_reference": int(np.abs(img - rimg.astype(np.int64)).sum()), "near_edge": int(near),
-                      "cpu_reference_s": round(dt, 3), "cpu_threads": threads}
+                      "cpu_baseline": cpu_baseline_cayley_t11(wl.C2_TA, wl.C2_TB, d, win, n, img)}
     mod = np.array([[0, 1, 2, 3], [1, 0, 2, 3], [2, 1, 0, 0], [3, 1, 0, 0]], np.uint8)
     mod_maps = np.array([[[0, -1], [1, 0]], [[0, -1], [1, 1]], [[1, 1], [-1, 0]]], complex)
     tm = kl.Cayley(mod, mod_maps)
@@ -296,13 +395,9 @@ def leg_cayley(args):
     image = kl.new_image(wm)
     ms = _time(lambda: kl.cayley_render(tm, 40, wm, image=image, min_depth=1, seed="all"), max(2, args.steps // 10), 2)
     img = kl.as_u32(image).astype(np.int64)
-    t0 = time.perf_counter()
-    rimg, _, near = ref.cayley_render(ref.Cayley(mod, mod_maps), 40, wm, seed=3, min_depth=1, edge_tol=1e-7)
-    dt = time.perf_counter() - t0
     out["modular_tiling_d40"] = {"words": words, "points": 3 * words, "ms": round(ms, 4),
                                  "gpoints_per_s": round(3 * words / ms / 1e6, 3),
-                                 "l1_vs_reference": int(np.abs(img - rimg.astype(np.int64)).sum()),
-                                 "near_edge": int(near), "cpu_reference_s": round(dt, 3), "cpu_threads": 1}
+                                 "cpu_baseline": cpu_baseline_cayley_modular(mod, mod_maps, wm, words, img)}
     return out
 
 
@@ -365,7 +460,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=400,
                     help="untimed steps first (the GPU clock ramps up over the first ~100 ms of work)")
     ap.add_argument("--workload", default="quasifuchsian_d18",
-                    choices=["quasifuchsian_d18", "quasifuchsian_d22", "batch256", "fuchsian_tiling_d10",
+                    choices=["quasifuchsian_d18", "quasifuchsian_d22", "decode", "batch256", "fuchsian_tiling_d10",
                              "maskit_tiling_d14", "cayley", "surrogate", "hist", "calib"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
@@ -384,7 +479,7 @@ def main():
     from paper_1709_08018_amd import workloads as wl
 
     torch.cuda.set_device(0)
-    legs = {"quasifuchsian_d22": leg_d22, "batch256": leg_batch, "fuchsian_tiling_d10": leg_tiling,
+    legs = {"quasifuchsian_d22": leg_d22, "decode": leg_decode, "batch256": leg_batch, "fuchsian_tiling_d10": leg_tiling,
             "maskit_tiling_d14": leg_maskit, "cayley": leg_cayley, "surrogate": leg_surrogate, "hist": leg_hist,
             "calib": leg_calib}
     if args.workload in legs:

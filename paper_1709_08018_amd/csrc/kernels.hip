@@ -93,74 +93,121 @@ __device__ inline uint64_t decode_packed(uint64_t index, int n) {
 }
 
 // ------------------------------------------------------------------ decode
-// One thread per word; letters staged in LDS and written out as one
-// contiguous, coalesced byte range per workgroup.
+// A word of depth d is its first letter index / 3^(d-1) followed by the
+// d - 1 base-3 digits of the rest, most significant first; letter j is the
+// t_j-th letter that is not the inverse of letter j - 1.  The digits go six
+// at a time through a table, built once per workgroup in LDS, that maps
+// (previous letter, six digits) to the next six letters, 2 bits each.  A
+// shorter last group is padded with zero digits at its end, whose letters
+// are not kept.  Words are staged in LDS 256 at a time and written as one
+// contiguous byte range per tile: 16-byte stores where the destination is
+// aligned, byte stores otherwise.
+constexpr uint32_t kDigitGroup = 729;   // 3^6
+
+__device__ __forceinline__ void put_letters(uint64_t& lo, uint64_t& hi, int pos, uint64_t bits) {
+    const int sh = 2 * pos;   // pos <= 39, bits < 2^12
+    if (sh < 64) {
+        lo |= bits << sh;
+        if (sh > 52) hi |= bits >> (64 - sh);
+    } else {
+        hi |= bits << (sh - 64);
+    }
+}
+
+__device__ __forceinline__ uint8_t letter_at(uint64_t lo, uint64_t hi, int j) {
+    return (uint8_t)((j < 32 ? lo >> (2 * j) : hi >> (2 * j - 64)) & 3u);
+}
+
 __global__ __launch_bounds__(256) void decode_kernel(uint64_t first, uint64_t count, int depth,
                                                      uint8_t* __restrict__ out) {
-    __shared__ uint8_t stage[256 * KL_MAX_DEPTH];
-    const uint64_t block_first = (uint64_t)blockIdx.x * 256;
+    __shared__ uint16_t next6[4 * kDigitGroup];
+    __shared__ __align__(16) uint8_t stage[256 * KL_MAX_DEPTH];
     const int tid = threadIdx.x;
-    const uint64_t rem = count - block_first;
-    const int nw = rem < 256 ? (int)rem : 256;
-    if (tid < nw) {
-        const uint64_t index = first + block_first + tid;
-        // digits from the least significant end into LDS, then letters
-        uint8_t* w = stage + tid * depth;
-        uint64_t x = index;
-        int j = depth - 1;
-        for (; j >= 1 && (x >> 32); --j) {
-            uint64_t q = div3_u64(x);
-            w[j] = (uint8_t)(x - 3 * q);
-            x = q;
+    for (uint32_t e = tid; e < 4 * kDigitGroup; e += 256) {
+        int prev = (int)(e / kDigitGroup);
+        uint32_t v = e - (uint32_t)prev * kDigitGroup;
+        int dg[6];
+        for (int j = 5; j >= 0; --j) {
+            const uint32_t q = v / 3;
+            dg[j] = (int)(v - 3 * q);
+            v = q;
         }
-        uint32_t x32 = (uint32_t)x;
-        for (; j >= 1; --j) {
-            uint32_t q = div3_u32(x32);
-            w[j] = (uint8_t)(x32 - 3 * q);
-            x32 = q;
-        }
-        int prev = (int)x32;
-        w[0] = (uint8_t)prev;
-        for (int i = 1; i < depth; ++i) {
-            int t = w[i];
-            int c = t + (t >= inv_letter(prev));
-            w[i] = (uint8_t)c;
+        uint32_t bits = 0;
+        for (int j = 0; j < 6; ++j) {
+            const int c = dg[j] + (dg[j] >= inv_letter(prev));
+            bits |= (uint32_t)c << (2 * j);
             prev = c;
         }
+        next6[e] = (uint16_t)bits;
     }
     __syncthreads();
-    const uint64_t nbytes = (uint64_t)nw * depth;
-    uint8_t* dst = out + block_first * depth;
-    // 4-byte stores where the destination is aligned, bytes at the edges
-    const uintptr_t addr = (uintptr_t)dst;
-    const uint32_t lead = (uint32_t)((4 - (addr & 3)) & 3);
-    const uint32_t head = lead < nbytes ? lead : (uint32_t)nbytes;
-    if ((uint32_t)tid < head) dst[tid] = stage[tid];
-    const uint64_t body = (nbytes - head) / 4;
-    uint32_t* dst32 = (uint32_t*)(dst + head);
-    for (uint64_t i = tid; i < body; i += 256) {
-        const uint8_t* s = stage + head + 4 * i;
-        dst32[i] = (uint32_t)s[0] | ((uint32_t)s[1] << 8) | ((uint32_t)s[2] << 16) | ((uint32_t)s[3] << 24);
+    const int n = depth - 1, groups = n / 6, p = n - 6 * groups;   // p digits in a last, shorter group
+    uint32_t pow_p = 1;
+    for (int j = 0; j < p; ++j) pow_p *= 3;
+    const uint32_t pad = kDigitGroup / pow_p;   // 3^(6 - p)
+    const uint64_t tiles = (count + 255) / 256;
+    for (uint64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+        const uint64_t tfirst = tile * 256;
+        const uint64_t rem = count - tfirst;
+        const int nw = rem < 256 ? (int)rem : 256;
+        if (tid < nw) {
+            uint64_t r = first + tfirst + tid;
+            uint32_t last = 0;
+            if (p) {
+                uint64_t q = r;
+                for (int j = 0; j < p; ++j) q = div3_u64(q);
+                last = (uint32_t)(r - q * pow_p);
+                r = q;
+            }
+            uint32_t g[6];   // groups of six digits, least significant first
+#pragma unroll
+            for (int k = 0; k < 6; ++k) {
+                g[k] = 0;
+                if (k < groups) {
+                    const uint64_t q = r / kDigitGroup;
+                    g[k] = (uint32_t)(r - q * kDigitGroup);
+                    r = q;
+                }
+            }
+            int prev = (int)(r & 3u);   // the first letter
+            uint64_t lo = (uint64_t)prev, hi = 0;
+            int pos = 1;
+#pragma unroll
+            for (int k = 5; k >= 0; --k) {
+                if (k < groups) {
+                    const uint32_t bits = next6[prev * kDigitGroup + g[k]];
+                    put_letters(lo, hi, pos, bits);
+                    prev = (int)(bits >> 10);
+                    pos += 6;
+                }
+            }
+            if (p) {
+                const uint32_t bits = next6[prev * kDigitGroup + last * pad] & ((1u << (2 * p)) - 1u);
+                put_letters(lo, hi, pos, bits);
+            }
+            uint8_t* w = stage + tid * depth;
+            for (int j = 0; j < depth; ++j) w[j] = letter_at(lo, hi, j);
+        }
+        __syncthreads();
+        const uint32_t nbytes = (uint32_t)nw * (uint32_t)depth;
+        uint8_t* dst = out + tfirst * (uint64_t)depth;
+        if (((uintptr_t)dst & 15u) == 0) {
+            const uint32_t n16 = nbytes / 16;
+            for (uint32_t i = tid; i < n16; i += 256) ((uint4*)dst)[i] = ((const uint4*)stage)[i];
+            for (uint32_t i = n16 * 16 + tid; i < nbytes; i += 256) dst[i] = stage[i];
+        } else {
+            for (uint32_t i = tid; i < nbytes; i += 256) dst[i] = stage[i];
+        }
+        __syncthreads();
     }
-    const uint64_t tail_start = head + body * 4;
-    if ((uint64_t)tid < nbytes - tail_start) dst[tail_start + tid] = stage[tail_start + tid];
 }
 
 hipError_t launch_decode(uint64_t first, uint64_t count, int depth, uint8_t* out, hipStream_t s) {
-    uint64_t blocks = (count + 255) / 256;
-    // grid.x is limited to 2^31 - 1 blocks; kl_decode splits larger requests
-    while (blocks) {
-        uint64_t nb = blocks > 0x7FFFFFFFull ? 0x7FFFFFFFull : blocks;
-        uint64_t words = nb * 256 < count ? nb * 256 : count;
-        hipLaunchKernelGGL(decode_kernel, dim3((unsigned)nb), dim3(256), 0, s, first, words, depth, out);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-        first += words;
-        out += words * depth;
-        count -= words;
-        blocks -= nb;
-    }
-    return hipSuccess;
+    if (count == 0) return hipSuccess;
+    const uint64_t tiles = (count + 255) / 256;
+    const uint64_t blocks = std::min<uint64_t>(tiles, (uint64_t)device_cu_count() * 8);
+    hipLaunchKernelGGL(decode_kernel, dim3((unsigned)blocks), dim3(256), 0, s, first, count, depth, out);
+    return hipGetLastError();
 }
 
 // ------------------------------------------------------------------ prefix table
