@@ -35,7 +35,10 @@
  * seed      the attracting fixed point of the word's last letter.
  * window    [x0, x1) x [y0, y1) split into width x height bins; row 0 holds
  *           y in [y0, y0 + (y1 - y0)/height); bin index row * width + col.
- *           Values outside the window or not finite are dropped.
+ *           Values outside the window or not finite are dropped.  The
+ *           bin is taken from the word's pixel coordinates (kl_eval_ex
+ *           with the window): column floor(px) for px in [+0, width),
+ *           row likewise; a coordinate of -0.0 counts as outside.
  * images    uint32 counts, row-major; additions wrap modulo 2^32.
  * memory    pointers named *_out, idx, letters_out, image_out and images_out
  *           are DEVICE pointers (memory of the current HIP device); all

@@ -538,11 +538,16 @@ __device__ __forceinline__ void word_value(const Head<T>& h, cpx<T> y, cpx<T> q,
     }
 }
 
-// Bin of pixel coordinates, or kOutside when outside [0,W) x [0,H) or NaN.
+// Bin of pixel coordinates: row floor(py), column floor(px) when px lies in
+// [+0, W) and py in [+0, H), else kOutside.  The range is taken in the
+// order of the floats' bit patterns: read as unsigned integers, the
+// patterns of +0 up to +infinity increase with the value, and a set sign
+// bit (-0 included) or a NaN's pattern lies above that of any finite W.  So
+// one unsigned compare per coordinate rejects a negative value, -0, a value
+// at or beyond the edge, an infinity and a NaN; -0 counts as outside.
 constexpr uint32_t kOutside = 0xFFFFFFFFu;
 
-// floor(x) as int32, saturating (v_cvt_flr_i32_f32; NaN gives 0, which the
-// caller rejects separately)
+// floor(x) as int32, saturating (v_cvt_flr_i32_f32)
 __device__ __forceinline__ int floor_i32(float x) {
     int r;
     asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(r) : "v"(x));
@@ -552,12 +557,14 @@ __device__ __forceinline__ int floor_i32(float x) {
 __device__ __forceinline__ uint32_t bin_key(float px, float py, uint32_t W, uint32_t H) {
     const uint32_t col = (uint32_t)floor_i32(px);
     const uint32_t row = (uint32_t)floor_i32(py);
-    const bool ok = !__builtin_isunordered(px, py) & (col < W) & (row < H);
+    const bool ok = (__float_as_uint(px) < __float_as_uint((float)W)) &
+                    (__float_as_uint(py) < __float_as_uint((float)H));
     return ok ? __umul24(row, W) + col : kOutside;
 }
 
 __device__ __forceinline__ uint32_t bin_key(double px, double py, uint32_t W, uint32_t H) {
-    const bool ok = (px >= 0.0) & (px < (double)W) & (py >= 0.0) & (py < (double)H);
+    const bool ok = ((uint64_t)__double_as_longlong(px) < (uint64_t)__double_as_longlong((double)W)) &
+                    ((uint64_t)__double_as_longlong(py) < (uint64_t)__double_as_longlong((double)H));
     const uint32_t col = ok ? (uint32_t)px : 0u;
     const uint32_t row = ok ? (uint32_t)py : 0u;
     return ok ? __umul24(row, W) + col : kOutside;

@@ -36,7 +36,7 @@ def _ref_pixels(z, win):
 
 def _bins_from_pixels(px, py, win):
     W, H = win[4], win[5]
-    ok = ~np.isnan(px) & ~np.isnan(py) & (px >= 0) & (px < W) & (py >= 0) & (py < H)
+    ok = ~np.isnan(px) & ~np.isnan(py) & ~np.signbit(px) & (px < W) & ~np.signbit(py) & (py < H)
     img = np.zeros(W * H, np.int64)
     np.add.at(img, np.floor(py[ok]).astype(np.int64) * W + np.floor(px[ok]).astype(np.int64), 1)
     return img.reshape(H, W), int((~ok).sum())
@@ -270,6 +270,24 @@ def test_window_edge_cases():
 
 
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_non_finite_and_far_coordinates_are_dropped(precision):
+    """A window so narrow that its scale to pixels leaves FP32's range: the
+    FP32 coordinates are infinite or NaN, the FP64 ones finite and far
+    outside.  Both renders drop exactly the words the histogram of their own
+    coordinates drops."""
+    depth, win = 12, (0.0, 1e-37, 0.0, 1e-37, 64, 64)
+    n = kl.num_words(depth)
+    dropped = torch.zeros(1, dtype=torch.int64, device="cuda")
+    img = kl.as_u32(kl.render(*C2, depth, win, precision=precision, dropped=dropped)).astype(np.int64)
+    p = kl.eval_values(*C2, depth, np.arange(n, dtype=np.uint64), precision=precision, window=win).cpu().numpy()
+    if precision == "fp32":
+        assert (~np.isfinite(p)).any()
+    ref, drop = _bins_from_pixels(p[:, 0], p[:, 1], win)
+    np.testing.assert_array_equal(img, ref)
+    assert int(dropped.item()) == drop
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
 def test_homogeneous_suffix_form(precision):
     depth, win = 12, WIN_C2
     n = kl.num_words(depth)
@@ -314,7 +332,7 @@ def test_full_quasifuchsian_d18_invariants_and_samples():
     idx = wl.sample_indices(n, 50000, seed=2)
     p = kl.eval_values(*C2, depth, idx, window=win).cpu().numpy()
     fx, fy = _ref_pixels(O.eval_values(*C2, depth, idx), win)
-    ok = (p[:, 0] >= 0) & (p[:, 0] < win[4]) & (p[:, 1] >= 0) & (p[:, 1] < win[5])
+    ok = ~np.signbit(p[:, 0]) & (p[:, 0] < win[4]) & ~np.signbit(p[:, 1]) & (p[:, 1] < win[5])
     rows, cols = np.floor(p[ok, 1]).astype(int), np.floor(p[ok, 0]).astype(int)
     assert (h[rows, cols] > 0).all()
     assert np.hypot(p[ok, 0] - fx[ok], p[ok, 1] - fy[ok]).max() <= 0.25
