@@ -221,6 +221,74 @@ def leg_d22(args):
             "cpu_baseline": cpu_baseline_d22(W, idx, p)}
 
 
+def _kernel_ms(render, reps):
+    """Mean persistent-kernel time in ms of render(kernel_events=...) over
+    reps calls, from a HIP event pair recorded around its launches."""
+    import ctypes
+
+    hip = _hip()
+    ev = []
+    for _ in range(2):
+        e = ctypes.c_void_p()
+        if hip.hipEventCreate(ctypes.byref(e)) != 0:
+            raise RuntimeError("hipEventCreate failed")
+        ev.append(e.value)
+    total = 0.0
+    for _ in range(reps):
+        render(kernel_events=(ev[0], ev[1]))
+        hip.hipEventSynchronize(ctypes.c_void_p(ev[1]))
+        ms = ctypes.c_float()
+        hip.hipEventElapsedTime(ctypes.byref(ms), ev[0], ev[1])
+        total += ms.value
+    for e in ev:
+        hip.hipEventDestroy(e)
+    return total / reps
+
+
+def leg_bounded(args):
+    """Block bounds (kl_opts.block_bounds) on the depth-18 workload: each
+    head bounds where each group of 27 suffixes lands, and only groups whose
+    bound spans more than one bin are evaluated word by word.  Step time and
+    persistent-kernel time against the per-word renderer on the same words,
+    the two images and dropped counts compared bin for bin; and depth 22
+    streamed in 8 index ranges, both ways."""
+    import numpy as np
+    import torch
+
+    from paper_1709_08018_amd import kl
+    from paper_1709_08018_amd import workloads as wl
+
+    out = {"workload": "block_bounds"}
+    for W, chunks in ((wl.QUASIFUCHSIAN_D18, 1), (wl.QUASIFUCHSIAN_D22, 8)):
+        n = kl.num_words(W.depth)
+        cuts = [n * i // chunks for i in range(chunks + 1)]
+        res = {"words": n, "chunks": chunks}
+        imgs = {}
+        for bounded in (False, True):
+            image = kl.new_image(W.window)
+            dropped = torch.zeros(1, dtype=torch.int64, device="cuda")
+
+            def run(dropped=None, **kw):
+                for a, b in zip(cuts[:-1], cuts[1:]):
+                    rng = {} if chunks == 1 else {"first": a, "count": b - a}
+                    kl.render(W.ta, W.tb, W.depth, W.window, image=image, accumulate=a > 0, dropped=dropped,
+                              block_bounds=bounded, **rng, **kw)
+            steps = max(2, args.steps // (4 * chunks))
+            ms = _time(run, steps, max(2, steps // 4))
+            key = "bounded" if bounded else "per_word"
+            res[key] = {"ms": round(ms, 4), "gwords_per_s": round(n / ms / 1e6, 1)}
+            if chunks == 1:
+                res[key]["kernel_ms"] = round(_kernel_ms(lambda **kw: run(**kw), steps), 4)
+            run(dropped=dropped)
+            imgs[bounded] = (kl.as_u32(image).astype(np.int64), int(dropped.item()))
+        res["images_equal"] = bool(np.array_equal(imgs[False][0], imgs[True][0]))
+        res["dropped_equal"] = imgs[False][1] == imgs[True][1]
+        res["speedup"] = round(res["per_word"]["ms"] / res["bounded"]["ms"], 2)
+        assert res["images_equal"] and res["dropped_equal"], "block bounds changed the image"
+        out[W.name] = res
+    return out
+
+
 def leg_decode(args):
     """kl_decode at depth 18: 2^27 consecutive words from a third of the way
     into the index space, written as a (count x 18) byte array.  The kernel
@@ -460,7 +528,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=400,
                     help="untimed steps first (the GPU clock ramps up over the first ~100 ms of work)")
     ap.add_argument("--workload", default="quasifuchsian_d18",
-                    choices=["quasifuchsian_d18", "quasifuchsian_d22", "decode", "batch256", "fuchsian_tiling_d10",
+                    choices=["quasifuchsian_d18", "quasifuchsian_d22", "decode", "bounded", "batch256", "fuchsian_tiling_d10",
                              "maskit_tiling_d14", "cayley", "surrogate", "hist", "calib"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
@@ -479,7 +547,7 @@ def main():
     from paper_1709_08018_amd import workloads as wl
 
     torch.cuda.set_device(0)
-    legs = {"quasifuchsian_d22": leg_d22, "decode": leg_decode, "batch256": leg_batch, "fuchsian_tiling_d10": leg_tiling,
+    legs = {"quasifuchsian_d22": leg_d22, "decode": leg_decode, "bounded": leg_bounded, "batch256": leg_batch, "fuchsian_tiling_d10": leg_tiling,
             "maskit_tiling_d14": leg_maskit, "cayley": leg_cayley, "surrogate": leg_surrogate, "hist": leg_hist,
             "calib": leg_calib}
     if args.workload in legs:

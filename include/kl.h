@@ -136,6 +136,21 @@ typedef struct {
                              caller, or NULL; recorded on the stream right
                              before and right after the persistent renderer's
                              launches (of the deepest depth rendered) */
+    int block_bounds;     /* 0: the renderer evaluates every word.  1: the
+                             persistent renderer first bounds, for each head
+                             and each group of 27 suffixes sharing their
+                             leading letters, the bins those words can reach
+                             (the head is a linear fractional map, Section
+                             3, so it sends the group's bounding disk to a
+                             disk; a margin covers the FP32 arithmetic).  A
+                             group whose bound lies outside the window is
+                             counted as dropped, one inside a single bin is
+                             added to it, and only the others are evaluated
+                             word by word.  Images and dropped counts are
+                             bit for bit those of 0.  Applies to FP32
+                             renders of one depth (limit set, index ranges)
+                             with tail_len >= 4 and KL_HIST_RUNS or AUTO;
+                             ignored elsewhere. */
 } kl_opts;
 
 /* The split the renderer uses for one depth (see kl_plan). */

@@ -460,6 +460,7 @@ static int render_depth(const Gens& G, const Fold& f, int depth, uint64_t lo, ui
     job.dropped = dropped;
     job.hist_mode = o.hist_mode;
     job.grid_blocks = grid_for(o.waves_per_cu);
+    job.bounded = o.block_bounds && o.precision == KL_PREC_FP32 && sp.r >= 4 && o.hist_mode != KL_HIST_LDS;
     uint64_t rag_lo = lo, rag_hi = hi;  // default: every word by the per-word kernel
     if (persistent_ok(sp)) {
         // whole heads inside [lo, hi) go to the persistent kernel
@@ -503,6 +504,8 @@ static int check_opts_common(const kl_opts& o) {
     if (o.head_form < 0 || o.head_form > 2) return fail(KL_EINVAL, "head_form %d outside 0..2", o.head_form);
     if (o.seed_mode < KL_SEED_OWN || o.seed_mode > KL_SEED_INV_B)
         return fail(KL_EINVAL, "seed_mode %d outside 0..5", o.seed_mode);
+    if (o.block_bounds != 0 && o.block_bounds != 1)
+        return fail(KL_EINVAL, "block_bounds %d is neither 0 nor 1", o.block_bounds);
     return KL_OK;
 }
 

@@ -723,9 +723,244 @@ __device__ __forceinline__ uint32_t first_key(const Head<T>& h, const unsigned c
     return __shfl(key, __ffsll((unsigned long long)m) - 1, kWave);
 }
 
-template <typename T, bool AFFINE, bool LDSHIST, bool DROP>
+// ------------------------------------------------------------------ block bounds
+// Suffix nodes: the suffixes that share their first r - 3 letters, 27 of
+// them, consecutive in the suffix table (node q holds entries 27q .. 27q +
+// 26).  A head with last letter e walks the 3^(r-3) nodes under its three
+// allowed first letters.
+constexpr uint32_t kNodeWords = 27;
+constexpr uint32_t kSpan = 0xFFFFFFFEu;   // run key of a node whose words wait in the span queue
+constexpr uint32_t kQueue = 128;          // span queue entries per wave
+
+struct NodeDisk {
+    float cr, ci, rho, pad;
+};
+
+// Bounding disk of node q's suffix points: the centre c is the midpoint of
+// their bounding box rounded to FP32; the radius is their largest distance
+// from c, computed in FP64 and enlarged by 2^-40, plus 2^-22 (|c.re| +
+// |c.im|), which covers the FP32 rounding of c + S in node_class; it is
+// rounded up to FP32.
+__device__ inline void node_disk(const cpx<float>* tail, uint32_t q, NodeDisk* out) {
+    const cpx<float>* p = tail + q * kNodeWords;
+    float x0 = p[0].re, x1 = p[0].re, y0 = p[0].im, y1 = p[0].im;
+    for (uint32_t t = 1; t < kNodeWords; ++t) {
+        x0 = fminf(x0, p[t].re);
+        x1 = fmaxf(x1, p[t].re);
+        y0 = fminf(y0, p[t].im);
+        y1 = fmaxf(y1, p[t].im);
+    }
+    const float cr = (float)(0.5 * ((double)x0 + (double)x1));
+    const float ci = (float)(0.5 * ((double)y0 + (double)y1));
+    double r2 = 0.0;
+    for (uint32_t t = 0; t < kNodeWords; ++t) {
+        const double dx = (double)p[t].re - (double)cr, dy = (double)p[t].im - (double)ci;
+        r2 = fmax(r2, dx * dx + dy * dy);
+    }
+    const double rho = sqrt(r2) * (1.0 + 0x1p-40) + 0x1p-22 * (fabs((double)cr) + fabs((double)ci)) + 0x1p-100;
+    out[q] = {cr, ci, __double2float_ru(rho), 0.0f};
+}
+
+// Constants of node_class for one head, formed once per unit.
+struct HeadBound {
+    float gx, gy;       // |ax| + |bx|, |ay| + |by|
+    float gx14, gy14;   // 2^-14 times those
+    float mPx, mPy;     // 2^-18 |Px| + 2^-100, likewise Py
+    float sS;           // covers the FP32 rounding of c + S: 2^-22 (1 + 2^-20) (|S.re| + |S.im|)
+    bool ok;            // the products of one word stay finite (a NaN fails this too)
+};
+
+__device__ __forceinline__ HeadBound head_bound(const Head<float>& h) {
+    HeadBound b;
+    b.gx = fabsf(h.ax) + fabsf(h.bx);
+    b.gy = fabsf(h.ay) + fabsf(h.by);
+    b.gx14 = b.gx * 0x1p-14f;
+    b.gy14 = b.gy * 0x1p-14f;
+    b.mPx = fmaf(fabsf(h.Px), 0x1p-18f, 0x1p-100f);
+    b.mPy = fmaf(fabsf(h.Py), 0x1p-18f, 0x1p-100f);
+    b.sS = (fabsf(h.S.re) + fabsf(h.S.im)) * (0x1p-22f * (1.0f + 0x1p-20f));
+    b.ok = fmaxf(b.gx, b.gy) <= 0x1p60f && fabsf(h.Px) <= 0x1p100f && fabsf(h.Py) <= 0x1p100f;
+    return b;
+}
+
+// Where a pole-form head sends the 27 words of a node, as the FP32
+// arithmetic of eval_pole computes them: kOutside when every word's bin is
+// outside the window, that bin when every word falls in one bin, kSpan
+// when neither can be shown.
+//
+// For y in the disk D(c, rho) and w = c + S with |w| > rho, u = y + S lies
+// in D(w, rho), so 1/u lies in the disk of centre conj(w) / den and radius
+// rho / den, den = |w|^2 - rho^2, and the exact pole form px = Px + Re((ax
+// + i bx) / u) lies within (|ax| + |bx|) rho / den of cx = Px + (ax w.re +
+// bx w.im) / den; likewise py with ay, by.
+//
+// Margins.  (1) The FP32 evaluation at the same inputs (two sums, |u|^2
+// from a product and an FMA, a reciprocal within one ulp, the numerator
+// from a product and an FMA, the closing FMA) differs from the exact value
+// by at most about eps (|Px| + 10 |ax + i bx| / |u|), eps = 2^-24, with
+// |u| >= |w| - rho.  (2) This function computes in FP32 too: w's rounding
+// is inside rho (node_disk, sS); with |w| - rho >= |w| / 64 (a guard) the
+// computed |w| - rho is within about 200 eps of its value, and cx - Px, the
+// radius and the reciprocal within about 420 eps of theirs, all relative
+// to (|ax| + |bx|) / (|w| - rho).  The margin 2^-18 |Px| + 2^-14 (|ax| +
+// |bx|) / (|w| - rho) holds both with room.  Guards keep every product of
+// the FP32 evaluation finite and normal, else kSpan; NaN fails them.
+__device__ __forceinline__ uint32_t node_class(const Head<float>& h, const HeadBound& b, const NodeDisk& d,
+                                               float Wf, float Hf, uint32_t W) {
+    const float wr = d.cr + h.S.re, wi = d.ci + h.S.im;
+    const float rp = fmaf(d.rho, 1.0f + 0x1p-20f, b.sS);
+    const float aw = __builtin_amdgcn_sqrtf(fmaf(wr, wr, wi * wi));
+    const float umin = aw - rp, umax = aw + rp;
+    const float inv = __builtin_amdgcn_rcpf(umin * umax);
+    const float kr = wr * inv, ki = wi * inv, kap = rp * inv, iu = umax * inv;
+    const float cx = fmaf(h.ax, kr, fmaf(h.bx, ki, h.Px));
+    const float cy = fmaf(h.ay, kr, fmaf(h.by, ki, h.Py));
+    const float hx = fmaf(b.gx, kap, fmaf(b.gx14, iu, b.mPx));
+    const float hy = fmaf(b.gy, kap, fmaf(b.gy14, iu, b.mPy));
+    const float lx = cx - hx, ux = cx + hx, ly = cy - hy, uy = cy + hy;
+    const bool ok = b.ok & (umin >= fmaxf(aw * 0x1p-6f, 0x1p-30f)) & (umax <= 0x1p40f);
+    const bool out = (ux < 0.0f) | (lx >= Wf) | (uy < 0.0f) | (ly >= Hf);
+    const int c0 = floor_i32(lx), c1 = floor_i32(ux), r0 = floor_i32(ly), r1 = floor_i32(uy);
+    const bool one = (lx > 0.0f) & (ux < Wf) & (ly > 0.0f) & (uy < Hf) & (c0 == c1) & (r0 == r1);
+    const uint32_t key = one ? __umul24((uint32_t)r0, W) + (uint32_t)c0 : kSpan;
+    return !ok ? kSpan : out ? kOutside : key;
+}
+
+// Close a run of the bounded walk: bins add their count, kOutside runs are
+// dropped words, kSpan runs were queued and add nothing here.
+template <bool DROP>
+__device__ __forceinline__ void close_bounded(Runs<DROP>& s, uint32_t t_words, uint32_t* image) {
+    const uint32_t cnt = t_words - s.start;
+    if (s.cur < kSpan) atomicAdd(image + s.cur, cnt);
+    else if (DROP && s.cur == kOutside) s.drop += cnt;
+}
+
+// Lanes q < c evaluate the 27 words of span-queue entry q (the head of lane
+// entry >> 8, its node entry & 255) word by word, with eval_pole and
+// bin_key as every other kernel, and run-length counts of their own.
+template <bool DROP>
+__device__ inline void drain_span_queue(const Head<float>& h, int lane, const uint16_t* queue, uint32_t c,
+                                        const unsigned char* tail_lds, uint32_t per, uint32_t W, uint32_t H,
+                                        uint32_t* image, Runs<DROP>& s) {
+    const uint32_t entry = (uint32_t)lane < c ? queue[lane] : 0u;
+    const int src = (int)(entry >> 8);
+    Head<float> g;
+    g.S.re = __shfl(h.S.re, src, kWave);
+    g.S.im = __shfl(h.S.im, src, kWave);
+    g.ax = __shfl(h.ax, src, kWave);
+    g.bx = __shfl(h.bx, src, kWave);
+    g.ay = __shfl(h.ay, src, kWave);
+    g.by = __shfl(h.by, src, kWave);
+    g.Px = __shfl(h.Px, src, kWave);
+    g.Py = __shfl(h.Py, src, kWave);
+    const int e = __shfl(h.e, src, kWave);
+    if ((uint32_t)lane < c) {
+        const uint32_t n = entry & 255u;
+        const uint32_t j = n / per, sub = n - j * per;
+        const uint32_t y1 = j + (j >= (uint32_t)inv_letter(e));
+        const uint32_t base = (y1 * per + sub) * kNodeWords;
+        uint32_t cur = kOutside, cnt = 0;
+        for (uint32_t t0 = 0; t0 < kNodeWords; t0 += 9) {
+            cpx<float> ya[9];
+#pragma unroll
+            for (uint32_t u = 0; u < 9; ++u) ya[u] = ((const cpx<float>*)tail_lds)[base + t0 + u];
+#pragma unroll
+            for (uint32_t u = 0; u < 9; ++u) {
+                float px, py;
+                eval_pole(g, ya[u], px, py);
+                const uint32_t key = bin_key(px, py, W, H);
+                if (key != cur) {
+                    if (cur != kOutside) atomicAdd(image + cur, cnt);
+                    else if (DROP) s.drop += cnt;
+                    cur = key;
+                    cnt = 0;
+                }
+                ++cnt;
+            }
+        }
+        if (cur != kOutside) atomicAdd(image + cur, cnt);
+        else if (DROP) s.drop += cnt;
+    }
+}
+
+// One full unit of 64 pole-form heads over an affine suffix table, node by
+// node: each lane classifies its head's node (node_class); bins and
+// outside nodes extend the lane's run like single words, spanning nodes go
+// to the wave's queue, which lanes drain 64 entries at a time and at the
+// end of the unit.  The word counter advances 27 per node, so the runs
+// count exactly the words the per-word walk would.
+template <bool DROP>
+__device__ inline void bounded_unit(const Head<float>& h, int lane, const unsigned char* tail_lds,
+                                    const NodeDisk* nodes, uint16_t* queue, uint32_t per, uint32_t W, uint32_t H,
+                                    uint32_t* image, Runs<DROP>& s, uint32_t& t_words) {
+    const int ie = inv_letter(h.e);
+    const HeadBound hb = head_bound(h);
+    const float Wf = (float)W, Hf = (float)H;
+    uint32_t qn = 0;   // queued entries (wave-uniform)
+    auto drain = [&](uint32_t c) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        drain_span_queue<DROP>(h, lane, queue, c, tail_lds, per, W, H, image, s);
+        const uint32_t rest = qn - c;
+        const uint16_t v = (uint32_t)lane < rest ? queue[c + lane] : (uint16_t)0;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if ((uint32_t)lane < rest) queue[lane] = v;
+        qn = rest;
+    };
+    // one node's verdict: extend or close the lane's run, queue a spanning node
+    auto step = [&](uint32_t key, uint32_t n) {
+        const uint32_t tw = __builtin_amdgcn_readfirstlane(t_words);
+        if (key != s.cur) {
+            close_bounded(s, tw, image);
+            s.cur = key;
+            s.start = tw;
+        }
+        const uint64_t span = __ballot(key == kSpan);
+        if (span) {
+            if (key == kSpan) {
+                const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(span >> 32),
+                                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)span, 0u));
+                queue[qn + below] = (uint16_t)(((uint32_t)lane << 8) | n);
+            }
+            qn += (uint32_t)__popcll(span);
+            if (qn >= (uint32_t)kWave) drain((uint32_t)kWave);
+        }
+        t_words = tw + kNodeWords;
+    };
+    for (uint32_t j = 0; j < 3; ++j) {
+        const uint32_t y1 = j + (j >= (uint32_t)ie);
+        const NodeDisk* nd = nodes + y1 * per;
+        if (per % 9 == 0) {
+            // nine nodes at a time: their disks read together, their verdicts independent
+            for (uint32_t sub0 = 0; sub0 < per; sub0 += 9) {
+                NodeDisk dk[9];
+#pragma unroll
+                for (uint32_t u = 0; u < 9; ++u) dk[u] = nd[sub0 + u];
+                uint32_t key[9];
+#pragma unroll
+                for (uint32_t u = 0; u < 9; ++u) key[u] = node_class(h, hb, dk[u], Wf, Hf, W);
+#pragma unroll
+                for (uint32_t u = 0; u < 9; ++u) step(key[u], j * per + sub0 + u);
+            }
+        } else {
+            for (uint32_t sub = 0; sub < per; ++sub) step(node_class(h, hb, nd[sub], Wf, Hf, W), j * per + sub);
+        }
+    }
+    // the words of a queued node are counted by the drain, not by the run
+    if (s.cur == kSpan) {
+        s.cur = kOutside;
+        s.start = t_words;
+    }
+    while (qn > 0) drain(qn < (uint32_t)kWave ? qn : (uint32_t)kWave);
+}
+
+template <typename T, bool AFFINE, bool LDSHIST, bool DROP, bool BOUNDED>
 __device__ __forceinline__ void render_units(const RenderArgs& a, const unsigned char* tail_lds, const m64* G,
-                                             uint32_t* tile, Runs<DROP>& s) {
+                                             uint32_t* tile, const NodeDisk* nodes, uint16_t* queue,
+                                             Runs<DROP>& s) {
     const int lane = threadIdx.x & (kWave - 1);
     const uint32_t waves = gridDim.x * (kBlock / kWave);
     const uint32_t gwave = blockIdx.x * (kBlock / kWave) + (threadIdx.x / kWave);
@@ -738,6 +973,14 @@ __device__ __forceinline__ void render_units(const RenderArgs& a, const unsigned
         const uint64_t hidx = a.head_begin + (live ? local : a.n_heads - 1);
         const Head<T> h = compute_head<T>(hidx, a.sp, a.tab.prefix, a.tab.prefix_last, G, a.fold);
         const bool dual = wave_needs_dual(h);
+        if constexpr (BOUNDED && AFFINE && !LDSHIST) {
+            static_assert(std::is_same<T, float>::value, "block bounds are for the FP32 path");
+            if (full && !dual) {
+                bounded_unit<DROP>(h, lane, tail_lds, nodes, queue, a.sp.R1 / kNodeWords, a.W, a.H, a.image, s,
+                                   t_words);
+                continue;
+            }
+        }
         if constexpr (LDSHIST) {
             // move the tile to where this unit's words start
             const uint32_t k0 = first_key<T, AFFINE>(h, tail_lds, a.sp.R1, a.W, a.H);
@@ -784,8 +1027,11 @@ __device__ __forceinline__ void render_units(const RenderArgs& a, const unsigned
 // bin changes (consecutive tails of one head lie close together), and keeps
 // its dropped words in a register until the end.
 // LDS: suffix table (sized for the homogeneous form), generators, and with
-// LDSHIST one 32 x 32 tile of uint32 bins per wave.
-template <typename T, bool LDSHIST, bool DROP>
+// LDSHIST one 32 x 32 tile of uint32 bins per wave.  With BOUNDED (FP32,
+// affine suffix tables, r >= 4) full units of pole-form heads go node by
+// node (bounded_unit); LDS then also holds the nodes' bounding disks and
+// one span queue per wave.
+template <typename T, bool LDSHIST, bool DROP, bool BOUNDED = false>
 __global__ __launch_bounds__(kBlock) void render_kernel(const RenderArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     const uint32_t n_tail = 4 * a.sp.R1;
@@ -795,6 +1041,9 @@ __global__ __launch_bounds__(kBlock) void render_kernel(const RenderArgs a) {
     const size_t tmax = (n_tail * 2 * sizeof(cpx<T>) + 15) & ~size_t(15);
     m64* G = (m64*)(smem + tbytes);
     uint32_t* tile = (uint32_t*)(smem + tmax + 4 * sizeof(m64)) + (threadIdx.x / kWave) * (kTile * kTile);
+    NodeDisk* nodes = (NodeDisk*)(smem + tmax + 4 * sizeof(m64));
+    const uint32_t n_nodes = BOUNDED ? n_tail / kNodeWords : 0u;
+    uint16_t* queue = (uint16_t*)(nodes + n_nodes) + (threadIdx.x / kWave) * kQueue;
     {
         const uint4* src = (const uint4*)(affine ? a.tab.tail : a.tail_homog);
         uint4* dst = (uint4*)smem;
@@ -805,9 +1054,15 @@ __global__ __launch_bounds__(kBlock) void render_kernel(const RenderArgs a) {
             for (int i = threadIdx.x & (kWave - 1); i < kTile * kTile; i += kWave) tile[i] = 0;
     }
     __syncthreads();
+    if constexpr (BOUNDED) {
+        if (affine) {
+            for (uint32_t q = threadIdx.x; q < n_nodes; q += blockDim.x) node_disk((const cpx<float>*)smem, q, nodes);
+            __syncthreads();
+        }
+    }
     Runs<DROP> s = {kOutside, 0, 0};
-    if (affine) render_units<T, true, LDSHIST>(a, smem, G, tile, s);
-    else render_units<T, false, LDSHIST>(a, smem, G, tile, s);
+    if (affine) render_units<T, true, LDSHIST, DROP, BOUNDED>(a, smem, G, tile, nodes, queue, s);
+    else render_units<T, false, LDSHIST, DROP, false>(a, smem, G, tile, nodes, queue, s);
     if (DROP) {
         uint64_t drop = s.drop;
         for (int off = kWave / 2; off > 0; off >>= 1) drop += __shfl_down(drop, off, kWave);
@@ -975,11 +1230,16 @@ static hipError_t launch_render_t(const RenderJob& job, hipStream_t s) {
         a.n_units = job.n_units;
         const size_t n_tail = 4 * (size_t)job.sp.R1;
         const bool ldsh = job.hist_mode == KL_HIST_LDS;
+        const bool bounded = std::is_same<T, float>::value && job.bounded && !ldsh && job.sp.r >= 4;
         const size_t lds = ((n_tail * 2 * sizeof(cpx<T>) + 15) & ~size_t(15)) + 4 * sizeof(m64) +
-                           (ldsh ? (kBlock / kWave) * kTile * kTile * sizeof(uint32_t) : 0);
+                           (ldsh ? (kBlock / kWave) * kTile * kTile * sizeof(uint32_t) : 0) +
+                           (bounded ? n_tail / kNodeWords * sizeof(NodeDisk) + (kBlock / kWave) * kQueue * 2 : 0);
         const bool drop = job.dropped != nullptr;
         void (*kern)(RenderArgs) = ldsh ? (drop ? render_kernel<T, true, true> : render_kernel<T, true, false>)
                                         : (drop ? render_kernel<T, false, true> : render_kernel<T, false, false>);
+        if constexpr (std::is_same<T, float>::value) {
+            if (bounded) kern = drop ? render_kernel<float, false, true, true> : render_kernel<float, false, false, true>;
+        }
         const void* fn = reinterpret_cast<const void*>(kern);
         if (lds > 65536) {
             hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

@@ -132,6 +132,7 @@ struct RenderJob {
     uint64_t rag_first[2], rag_count[2];
     int hist_mode;
     int grid_blocks;
+    int bounded;               // FP32 persistent kernel with per-node bounds (kl_opts::block_bounds)
 };
 hipError_t launch_render(const RenderJob& job, hipStream_t s);
 

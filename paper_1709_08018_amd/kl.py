@@ -46,7 +46,7 @@ class Opts(ctypes.Structure):
                 ("stream", ctypes.c_void_p), ("dropped_out", ctypes.c_void_p), ("tail_len", ctypes.c_int),
                 ("lane_len", ctypes.c_int), ("hist_mode", ctypes.c_int), ("waves_per_cu", ctypes.c_int),
                 ("suffix_form", ctypes.c_int), ("seed_mode", ctypes.c_int), ("head_form", ctypes.c_int),
-                ("kernel_events", ctypes.c_void_p * 2)]
+                ("kernel_events", ctypes.c_void_p * 2), ("block_bounds", ctypes.c_int)]
 
 
 class CayleyT(ctypes.Structure):
@@ -169,7 +169,7 @@ def _stream(stream):
 
 def make_opts(*, min_depth=0, precision="fp32", first=None, count=None, accumulate=False, stream=None,
               dropped=None, tail_len=0, lane_len=0, hist_mode="auto", waves_per_cu=0, suffix_form=0,
-              head_form=0, seed="own", kernel_events=None, use_stream=True) -> Opts:
+              head_form=0, seed="own", kernel_events=None, block_bounds=False, use_stream=True) -> Opts:
     o = Opts()
     o.min_depth = int(min_depth)
     o.precision = PREC[precision] if isinstance(precision, str) else int(precision)
@@ -187,6 +187,7 @@ def make_opts(*, min_depth=0, precision="fp32", first=None, count=None, accumula
     o.suffix_form = int(suffix_form)
     o.head_form = int(head_form)
     o.seed_mode = SEED[seed] if isinstance(seed, str) else int(seed)
+    o.block_bounds = int(bool(block_bounds))
     if kernel_events is not None:
         o.kernel_events[0] = kernel_events[0]
         o.kernel_events[1] = kernel_events[1]

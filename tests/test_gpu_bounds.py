@@ -1,0 +1,121 @@
+"""Block bounds (kl_opts.block_bounds) through the C ABI.
+
+With block bounds the persistent renderer bounds, per head and per group of
+27 suffixes, the bins those words can reach, and evaluates word by word only
+the groups whose bound spans more than one bin.  Bar: images and dropped
+counts equal, bin for bin, to the per-word renderer on the same words, and to
+the histogram of the renderer's own per-word coordinates (kl_eval).
+"""
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+from paper_1709_08018_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+if torch.cuda.is_available():
+    from paper_1709_08018_amd import kl
+
+C2 = (wl.C2_TA, wl.C2_TB)
+C1 = (wl.C1_TA, wl.C1_TB)
+WIN_C2 = wl.QUASIFUCHSIAN_D18.window.as_tuple()
+WIN_64 = (-1.5, 1.5, -1.5, 1.5, 64, 64)
+WIN_ZOOM = (0.1, 0.6, -0.2, 0.3, 40, 40)
+WIN_ANISO = (-2.0, 2.0, -2.0, 2.0, 300, 100)
+
+
+def _both(render):
+    """(image, dropped) of render(block_bounds=b, image=..., dropped=...) for b = False, True."""
+    res = []
+    for b in (False, True):
+        d = torch.zeros(1, dtype=torch.int64, device="cuda")
+        img = render(block_bounds=b, dropped=d)
+        res.append((kl.as_u32(img).astype(np.int64), int(d.item())))
+    return res
+
+
+def _assert_same(render):
+    (a, da), (b, db) = _both(render)
+    np.testing.assert_array_equal(b, a)
+    assert db == da
+    return a, da
+
+
+def _bins_from_pixels(px, py, win):
+    W, H = win[4], win[5]
+    ok = ~np.isnan(px) & ~np.isnan(py) & ~np.signbit(px) & (px < W) & ~np.signbit(py) & (py < H)
+    img = np.zeros(W * H, np.int64)
+    np.add.at(img, np.floor(py[ok]).astype(np.int64) * W + np.floor(px[ok]).astype(np.int64), 1)
+    return img.reshape(H, W), int((~ok).sum())
+
+
+@pytest.mark.parametrize("depth,win", [(18, WIN_C2), (14, WIN_C2), (13, WIN_ZOOM), (12, WIN_64), (13, WIN_ANISO)],
+                         ids=["d18", "d14", "d13_zoom", "d12_64", "d13_aniso"])
+def test_bounded_equals_per_word(depth, win):
+    img, drop = _assert_same(lambda **kw: kl.render(*C2, depth, win, **kw))
+    assert int(img.sum()) + drop == kl.num_words(depth)
+
+
+@pytest.mark.parametrize("seed", ["b", "A", "all"])
+def test_bounded_seed_modes(seed):
+    _assert_same(lambda **kw: kl.render(*C2, 14, WIN_C2, seed=seed, **kw))
+
+
+@pytest.mark.parametrize("tail_len", [4, 5, 7, 8])
+def test_bounded_tail_lengths(tail_len):
+    _assert_same(lambda **kw: kl.render(*C2, 14, WIN_64, tail_len=tail_len, **kw))
+
+
+def test_bounded_equals_histogram_of_own_bins():
+    depth, win = 13, WIN_64
+    n = kl.num_words(depth)
+    dropped = torch.zeros(1, dtype=torch.int64, device="cuda")
+    img = kl.as_u32(kl.render(*C2, depth, win, block_bounds=True, dropped=dropped)).astype(np.int64)
+    p = kl.eval_values(*C2, depth, np.arange(n, dtype=np.uint64), window=win).cpu().numpy()
+    ref, drop = _bins_from_pixels(p[:, 0], p[:, 1], win)
+    np.testing.assert_array_equal(img, ref)
+    assert int(dropped.item()) == drop
+
+
+def test_bounded_ranges_and_accumulate():
+    depth, win = 15, WIN_C2
+    n = kl.num_words(depth)
+    cuts = sorted({0, 1, 12345, n // 3, n // 3 + 777, n - 5, n})
+
+    def render(block_bounds, dropped):
+        img = kl.new_image(win)
+        for a, b in zip(cuts[:-1], cuts[1:]):
+            kl.render(*C2, depth, win, image=img, first=a, count=b - a, accumulate=True, dropped=dropped,
+                      block_bounds=block_bounds)
+        return img
+    _assert_same(render)
+
+
+def test_bounded_group_with_heads_of_both_forms():
+    """Maskit's group: b is a translation, so heads without a pole form occur
+    and their units take the per-word walk."""
+    ab = kl.maskit_generators(wl.MASKIT_MU)
+    win = wl.MASKIT_D14.window.as_tuple()
+    _assert_same(lambda **kw: kl.render_group(ab, 13, win, **kw))
+    _assert_same(lambda **kw: kl.render(*C1, 14, wl.FUCHSIAN_TILING_D10.window.as_tuple(), **kw))
+
+
+def test_bounded_ignored_where_it_does_not_apply():
+    # FP64, the LDS tile histogram, a tiling render, and non-finite FP32 coordinates
+    _assert_same(lambda **kw: kl.render(*C2, 14, WIN_C2, precision="fp64", **kw))
+    _assert_same(lambda **kw: kl.render(*C2, 14, WIN_C2, hist_mode="lds", **kw))
+    _assert_same(lambda **kw: kl.render(*C1, 10, wl.FUCHSIAN_TILING_D10.window.as_tuple(), min_depth=1, **kw))
+    _assert_same(lambda **kw: kl.render(*C2, 12, (0.0, 1e-37, 0.0, 1e-37, 64, 64), **kw))
+
+
+def test_block_bounds_value_is_checked():
+    with pytest.raises(kl.KLError):
+        o = kl.make_opts()
+        o.block_bounds = 2
+        img = kl.new_image(WIN_64)
+        w = kl.make_window(WIN_64)
+        kl._check(kl.lib().kl_render_ex(kl._c(C2[0]), kl._c(C2[1]), 10, ctypes.byref(w), img.data_ptr(),
+                                        ctypes.byref(o)))
