@@ -731,6 +731,7 @@ __device__ __forceinline__ uint32_t first_key(const Head<T>& h, const unsigned c
 constexpr uint32_t kNodeWords = 27;
 constexpr uint32_t kSpan = 0xFFFFFFFEu;   // run key of a node whose words wait in the span queue
 constexpr uint32_t kQueue = 128;          // span queue entries per wave
+constexpr uint32_t kNodeGroup = 3;        // nodes classified together
 
 struct NodeDisk {
     float cr, ci, rho, pad;
@@ -933,17 +934,17 @@ __device__ inline void bounded_unit(const Head<float>& h, int lane, const unsign
     for (uint32_t j = 0; j < 3; ++j) {
         const uint32_t y1 = j + (j >= (uint32_t)ie);
         const NodeDisk* nd = nodes + y1 * per;
-        if (per % 9 == 0) {
-            // nine nodes at a time: their disks read together, their verdicts independent
-            for (uint32_t sub0 = 0; sub0 < per; sub0 += 9) {
-                NodeDisk dk[9];
+        if (per % kNodeGroup == 0) {
+            // kNodeGroup nodes at a time: their disks read together, their verdicts independent
+            for (uint32_t sub0 = 0; sub0 < per; sub0 += kNodeGroup) {
+                NodeDisk dk[kNodeGroup];
 #pragma unroll
-                for (uint32_t u = 0; u < 9; ++u) dk[u] = nd[sub0 + u];
-                uint32_t key[9];
+                for (uint32_t u = 0; u < kNodeGroup; ++u) dk[u] = nd[sub0 + u];
+                uint32_t key[kNodeGroup];
 #pragma unroll
-                for (uint32_t u = 0; u < 9; ++u) key[u] = node_class(h, hb, dk[u], Wf, Hf, W);
+                for (uint32_t u = 0; u < kNodeGroup; ++u) key[u] = node_class(h, hb, dk[u], Wf, Hf, W);
 #pragma unroll
-                for (uint32_t u = 0; u < 9; ++u) step(key[u], j * per + sub0 + u);
+                for (uint32_t u = 0; u < kNodeGroup; ++u) step(key[u], j * per + sub0 + u);
             }
         } else {
             for (uint32_t sub = 0; sub < per; ++sub) step(node_class(h, hb, nd[sub], Wf, Hf, W), j * per + sub);
@@ -1031,8 +1032,8 @@ __device__ __forceinline__ void render_units(const RenderArgs& a, const unsigned
 // affine suffix tables, r >= 4) full units of pole-form heads go node by
 // node (bounded_unit); LDS then also holds the nodes' bounding disks and
 // one span queue per wave.
-template <typename T, bool LDSHIST, bool DROP, bool BOUNDED = false>
-__global__ __launch_bounds__(kBlock) void render_kernel(const RenderArgs a) {
+template <typename T, bool LDSHIST, bool DROP, bool BOUNDED>
+__device__ __forceinline__ void render_body(const RenderArgs& a) {
     extern __shared__ __align__(16) unsigned char smem[];
     const uint32_t n_tail = 4 * a.sp.R1;
     const bool affine = tail_affine_block(a.tab);
@@ -1069,6 +1070,22 @@ __global__ __launch_bounds__(kBlock) void render_kernel(const RenderArgs a) {
         if ((threadIdx.x & (kWave - 1)) == 0 && drop)
             atomicAdd((unsigned long long*)a.dropped, (unsigned long long)drop);
     }
+}
+
+template <typename T, bool LDSHIST, bool DROP>
+__global__ __launch_bounds__(kBlock) void render_kernel(const RenderArgs a) {
+    render_body<T, LDSHIST, DROP, false>(a);
+}
+
+// The block-bounds variant (FP32, run-length histogram).  Its node
+// classification and span drains are chains of dependent operations, so it
+// is held to at least kBoundedWaves waves per SIMD to hide their latency.
+constexpr int kBoundedWaves = 5;
+
+template <bool DROP>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kBoundedWaves)))
+void render_bounded_kernel(const RenderArgs a) {
+    render_body<float, false, DROP, true>(a);
 }
 
 // ------------------------------------------------------------------ per-word kernel
@@ -1238,7 +1255,7 @@ static hipError_t launch_render_t(const RenderJob& job, hipStream_t s) {
         void (*kern)(RenderArgs) = ldsh ? (drop ? render_kernel<T, true, true> : render_kernel<T, true, false>)
                                         : (drop ? render_kernel<T, false, true> : render_kernel<T, false, false>);
         if constexpr (std::is_same<T, float>::value) {
-            if (bounded) kern = drop ? render_kernel<float, false, true, true> : render_kernel<float, false, false, true>;
+            if (bounded) kern = drop ? render_bounded_kernel<true> : render_bounded_kernel<false>;
         }
         const void* fn = reinterpret_cast<const void*>(kern);
         if (lds > 65536) {
