@@ -1064,11 +1064,12 @@ static int make_cayley(const kl_cayley* t, int min_depth, int max_depth, bool ne
     }
     j->depth_start[max_depth - min_depth + 1] = start;
     // tail length of the head/tail evaluation: the longest r <= 12 (and <= the
-    // largest depth) whose regular words fit the tail table
+    // largest depth) with at most kCayleyHeadTails regular words, which the
+    // render spreads one head per thread
     for (int r = std::min(kCayleyMaxTail, max_depth); r >= 1; --r) {
         uint64_t n = 0;
         for (int s = 1; s < S; ++s) n += C[r][s];
-        if (n <= (uint64_t)kCayleyMaxTails) {
+        if (n <= (uint64_t)kCayleyHeadTails) {
             j->r = r;
             j->n_tails = (int)n;
             break;

@@ -69,6 +69,8 @@ __device__ __forceinline__ int packed_symbol(uint64_t lo, uint64_t hi, int j) {
 // Choosing a symbol is then two table reads per candidate.  A word's
 // symbols are packed 3 bits each (x - 1) into two registers.
 //
+// Decode, eval, and renders of words shorter than r (launch_cayley sends a
+// render's words of depth >= r to cayley_head_kernel below).
 // Words of depth d >= r are evaluated as head . tail, the tail being the
 // last r symbols.  The tail read from state 0 ends in some state; the word
 // is regular when the head reads from that state, i.e. the state is in the
@@ -275,11 +277,273 @@ __global__ __launch_bounds__(256) void cayley_kernel(const CayleyJob a) {
     }
 }
 
+// ------------------------------------------------------------------ one head per thread
+// Render of the words of depths >= r: a thread takes a whole head (the
+// first d - r symbols) and every lane of a wave steps through the whole
+// tail table together, each evaluating the tails its head accepts, so no
+// lane re-ranks in the middle of a run.  Heads are ranked by their own
+// counts: NH[L][g] heads of L more symbols from good set g accept at least
+// one tail (NH[0][g] = [CM[r][g] > 0]), so head hh of a depth unranks as a
+// word does, with NH in place of CM, while the skipped CM counts give the
+// index of the head's first word.  The accepted tails of a head, in table
+// (lexicographic) order, are its words in index order; an index range cuts
+// the first and last of its heads.  The arithmetic of a word is that of
+// cayley_kernel: the head's FP64 product left to right, then cayley_pixel.
+//
+// LDS, sized from the table (HeadLayout): C, CM and NH rows for lengths
+// 0..D, the set automaton, the maps, the tail table, and per depth the
+// range's head offsets.
+struct HeadLayout {
+    // byte offsets: C, CM, NH rows ([(D + 1) * S], [(D + 1) * M] twice); per
+    // depth (index d - min_depth) the range's first head HA, the prefix of
+    // head counts HS and the word range WA, WB; the tail points TU, TV; the
+    // maps G; the sets SETS; the automaton NX; the tail end states TS
+    uint32_t C, CM, NH, HA, HS, WA, WB, TU, TV, G, SETS, NX, TS, total;
+};
+
+__host__ __device__ inline HeadLayout cayley_head_layout(int S, int M, int m, int D, int n_tails) {
+    HeadLayout L;
+    uint32_t off = 0;
+    auto take = [&](uint32_t bytes) {
+        const uint32_t at = off;
+        off = (off + bytes + 15u) & ~15u;
+        return at;
+    };
+    const uint32_t rows = (uint32_t)(D + 1);
+    L.C = take(rows * (uint32_t)S * 8u);
+    L.CM = take(rows * (uint32_t)M * 8u);
+    L.NH = take(rows * (uint32_t)M * 8u);
+    L.HA = take((KL_MAX_DEPTH + 1) * 8u);
+    L.HS = take((KL_MAX_DEPTH + 2) * 8u);
+    L.WA = take((KL_MAX_DEPTH + 1) * 8u);
+    L.WB = take((KL_MAX_DEPTH + 1) * 8u);
+    L.TU = take((uint32_t)n_tails * (uint32_t)sizeof(c64));
+    L.TV = take((uint32_t)n_tails * (uint32_t)sizeof(c64));
+    L.G = take((uint32_t)m * (uint32_t)sizeof(m64));
+    L.SETS = take((uint32_t)M * 2u);
+    L.NX = take((uint32_t)M * (uint32_t)m);
+    L.TS = take((uint32_t)n_tails);
+    L.total = off;
+    return L;
+}
+
+__global__ __launch_bounds__(256) void cayley_head_kernel(const CayleyJob a) {
+    extern __shared__ __align__(16) unsigned char lds[];
+    const int S = a.S, m = a.m, M = a.n_sets, D = a.max_depth, r = a.r;
+    const HeadLayout lay = cayley_head_layout(S, M, m, D, a.n_tails);
+    struct {
+        uint64_t *C, *CM, *NH, *HA, *HS, *WA, *WB;
+        c64 *TU, *TV;
+        m64* G;
+        uint16_t* SETS;
+        uint8_t *NX, *TS;
+    } q = {(uint64_t*)(lds + lay.C), (uint64_t*)(lds + lay.CM), (uint64_t*)(lds + lay.NH), (uint64_t*)(lds + lay.HA),
+           (uint64_t*)(lds + lay.HS), (uint64_t*)(lds + lay.WA), (uint64_t*)(lds + lay.WB), (c64*)(lds + lay.TU),
+           (c64*)(lds + lay.TV), (m64*)(lds + lay.G), (uint16_t*)(lds + lay.SETS), (uint8_t*)(lds + lay.NX),
+           (uint8_t*)(lds + lay.TS)};
+    for (int i = threadIdx.x; i < M * m; i += blockDim.x) q.NX[i] = a.next_set[i];
+    for (int i = threadIdx.x; i < M; i += blockDim.x) q.SETS[i] = a.sets[i];
+    for (int i = threadIdx.x; i < m; i += blockDim.x) q.G[i] = a.maps[i];
+    if (threadIdx.x < (unsigned)S) q.C[threadIdx.x] = threadIdx.x == 0 ? 1 : 0;
+    __syncthreads();
+    for (int L = 1; L <= D; ++L) {
+        const int t = threadIdx.x;
+        if (t < S) {
+            uint64_t n = 0;
+            if (t != 0)
+                for (int s = 0; s < S; ++s)
+                    for (int x = 1; x <= m; ++x)
+                        if (a.table[s * (m + 1) + x] == t) n += q.C[(L - 1) * S + s];
+            q.C[L * S + t] = n;
+        }
+        __syncthreads();
+    }
+    for (int i = threadIdx.x; i < (D + 1) * M; i += blockDim.x) {
+        const int L = i / M, g = i - L * M;
+        uint64_t n = 0;
+        for (int s = 0; s < S; ++s)
+            if ((a.sets[g] >> s) & 1u) n += q.C[L * S + s];
+        q.CM[i] = n;
+    }
+    __syncthreads();
+    // heads of L more symbols that accept at least one tail
+    for (int g = threadIdx.x; g < M; g += blockDim.x) q.NH[g] = q.CM[r * M + g] > 0 ? 1 : 0;
+    __syncthreads();
+    for (int L = 1; L + r <= D; ++L) {
+        for (int g = threadIdx.x; g < M; g += blockDim.x) {
+            uint64_t n = 0;
+            for (int x = 1; x <= m; ++x) n += q.NH[(L - 1) * M + q.NX[g * m + x - 1]];
+            q.NH[L * M + g] = n;
+        }
+        __syncthreads();
+    }
+    // the tail table: regular words of length r in lexicographic order, their
+    // end states and their points
+    for (int t = threadIdx.x; t < a.n_tails; t += blockDim.x) {
+        uint64_t local = (uint64_t)t, lo = 0, hi = 0;
+        int g = 0;
+        for (int j = 0; j < r; ++j) {
+            int x = 1, gx = 0;
+            for (; x <= m; ++x) {
+                gx = q.NX[g * m + x - 1];
+                const uint64_t n = q.CM[(r - j - 1) * M + gx];
+                if (local < n) break;
+                local -= n;
+            }
+            g = gx;
+            if (j < 21) lo |= (uint64_t)(x - 1) << (3 * j);
+            else hi |= (uint64_t)(x - 1) << (3 * (j - 21));
+        }
+        int s = 0;
+        for (int j = r - 1; j >= 0; --j) s = a.table[s * (m + 1) + packed_symbol(lo, hi, j) + 1];
+        q.TS[t] = (uint8_t)s;
+        const int last = packed_symbol(lo, hi, r - 1);
+        const int sd = a.seed < 0 ? last : a.seed;
+        c64 u = a.fix[sd], v = {1.0, 0.0};
+        if ((a.inf_mask >> sd) & 1u) {
+            u = {1.0, 0.0};
+            v = {0.0, 0.0};
+        }
+        for (int j = r - 1; j >= 0; --j) {
+            const m64& Gx = q.G[packed_symbol(lo, hi, j)];
+            const c64 nu = cfma(Gx.a, u, cmul(Gx.b, v));
+            const c64 nv = cfma(Gx.c, u, cmul(Gx.d, v));
+            u = nu;
+            v = nv;
+        }
+        q.TU[t] = u;
+        q.TV[t] = v;
+    }
+    // per depth: the range's local word interval and the heads it touches
+    const int d0 = r > a.min_depth ? r : a.min_depth;
+    for (int e = threadIdx.x; e < 2 * (D - d0 + 1); e += blockDim.x) {
+        const int d = d0 + e / 2, di = d - a.min_depth;
+        const uint64_t s0 = a.depth_start[di], s1 = a.depth_start[di + 1];
+        const uint64_t lo_w = a.first > s0 ? a.first - s0 : 0;
+        const uint64_t end = a.first + a.count;
+        const uint64_t hi_w = end < s1 ? (end > s0 ? end - s0 : 0) : s1 - s0;
+        if (e % 2 == 0) {
+            q.WA[di] = lo_w;
+            q.WB[di] = hi_w;
+        }
+        // rank of the head of word lo_w (e even) or hi_w - 1 (e odd)
+        uint64_t hr = 0;
+        if (hi_w > lo_w) {
+            uint64_t local = e % 2 == 0 ? lo_w : hi_w - 1;
+            const int hl = d - r;
+            int g = 0;
+            for (int j = 0; j < hl; ++j) {
+                int x = 1, gx = 0;
+                for (; x <= m; ++x) {
+                    gx = q.NX[g * m + x - 1];
+                    const uint64_t n = q.CM[(d - j - 1) * M + gx];
+                    if (local < n) break;
+                    local -= n;
+                    hr += q.NH[(hl - j - 1) * M + gx];
+                }
+                g = gx;
+            }
+        }
+        if (e % 2 == 0) q.HA[di] = hr;
+        else q.HS[di] = hr;   // the last head, turned into a count below
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t total = 0;
+        for (int d = d0; d <= D; ++d) {
+            const int di = d - a.min_depth;
+            const uint64_t n = q.WB[di] > q.WA[di] ? q.HS[di] - q.HA[di] + 1 : 0;
+            q.HS[di] = total;
+            total += n;
+        }
+        q.HS[D - a.min_depth + 1] = total;
+    }
+    __syncthreads();
+
+    const uint64_t total = q.HS[D - a.min_depth + 1];
+    uint64_t drop = 0;
+    uint32_t run_key = kCayleyOutside, run_len = 0;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t u = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; u < total; u += stride) {
+        int d = d0;
+        while (u >= q.HS[d + 1 - a.min_depth]) ++d;
+        const int di = d - a.min_depth, hl = d - r;
+        uint64_t hh = q.HA[di] + (u - q.HS[di]);
+        // unrank the head by NH; the skipped CM counts give its first word
+        int g = 0;
+        uint64_t wstart = 0;
+        m64 Mh = {{1.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}, {1.0, 0.0}};
+        for (int j = 0; j < hl; ++j) {
+            int x = 1, gx = 0;
+            for (; x <= m; ++x) {
+                gx = q.NX[g * m + x - 1];
+                const uint64_t n = q.NH[(hl - j - 1) * M + gx];
+                if (hh < n) break;
+                hh -= n;
+                wstart += q.CM[(d - j - 1) * M + gx];
+            }
+            g = gx;
+            Mh = mmul(Mh, q.G[x - 1]);
+        }
+        const uint32_t accept = q.SETS[g];
+        // this head's accepted tails with ordinals in [o0, o1) are words of the range
+        const uint64_t wa = q.WA[di], wb = q.WB[di];
+        const uint64_t o0 = wa > wstart ? wa - wstart : 0;
+        const uint64_t o1 = wb - wstart;
+        uint64_t ord = 0;
+        for (int t = 0; t < a.n_tails; ++t) {
+            const bool acc = (accept >> q.TS[t]) & 1u;
+            if (acc && ord >= o0 && ord < o1) {
+                const c64 tu = q.TU[t], tv = q.TV[t];
+                double px, py;
+                cayley_pixel(a, cfma(Mh.a, tu, cmul(Mh.b, tv)), cfma(Mh.c, tu, cmul(Mh.d, tv)), px, py);
+                const uint32_t key = cayley_bin(px, py, a.W, a.H);
+                if (key != run_key) {
+                    if (run_key == kCayleyOutside) drop += run_len;
+                    else if (run_len) atomicAdd(a.image + run_key, run_len);
+                    run_key = key;
+                    run_len = 0;
+                }
+                ++run_len;
+            }
+            ord += acc ? 1u : 0u;
+        }
+    }
+    if (run_key == kCayleyOutside) drop += run_len;
+    else if (run_len) atomicAdd(a.image + run_key, run_len);
+    if (a.dropped) {
+        for (int off = kWave / 2; off > 0; off >>= 1) drop += __shfl_down(drop, off, kWave);
+        if ((threadIdx.x & (kWave - 1)) == 0 && drop) atomicAdd((unsigned long long*)a.dropped, (unsigned long long)drop);
+    }
+}
+
 hipError_t launch_cayley(const CayleyJob& job, int mode, hipStream_t s) {
     if (job.count == 0) return hipSuccess;
     CayleyJob j = job;
     const uint64_t threads = 256ull * (uint64_t)std::max(1, j.grid_blocks);
     j.run = (int)std::min<uint64_t>(kCayleyRunMax, std::max<uint64_t>(kCayleyRunMin, j.count / threads));
+    if (mode == kCayleyRender && j.r > 0) {
+        // words of depths >= r go one head per thread; shorter words keep the per-word path
+        const uint64_t B = j.r > j.min_depth ? j.depth_start[j.r - j.min_depth] : 0;   // first word of depth r
+        const uint64_t end = j.first + j.count;
+        if (end > B) {
+            CayleyJob h = j;
+            h.first = j.first > B ? j.first : B;
+            h.count = end - h.first;
+            const size_t lds = cayley_head_layout(j.S, j.n_sets, j.m, j.max_depth, j.n_tails).total;
+            if (lds > 65536) {
+                hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(cayley_head_kernel),
+                                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+                if (e != hipSuccess) return e;
+            }
+            hipLaunchKernelGGL(cayley_head_kernel, dim3((unsigned)std::max(1, j.grid_blocks)), dim3(256), lds, s, h);
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
+        if (j.first >= B) return hipSuccess;
+        j.count = (end < B ? end : B) - j.first;
+        j.run = (int)std::min<uint64_t>(kCayleyRunMax, std::max<uint64_t>(kCayleyRunMin, j.count / threads));
+    }
     const uint64_t per = mode == kCayleyRender ? (uint64_t)j.run : 1;
     uint64_t blocks = (j.count + 256 * per - 1) / (256 * per);
     blocks = std::min<uint64_t>(blocks, (uint64_t)std::max(1, j.grid_blocks));

@@ -198,6 +198,12 @@ constexpr int kCayleyMaxStates = 16;
 constexpr int kCayleyMaxSymbols = 8;
 constexpr int kCayleyMaxSets = 64;      // good-state sets reachable from the set of all states
 constexpr int kCayleyMaxTails = 1024;   // entries of the tail table
+// The tail table's size in use: a render goes one head per thread, so
+// shorter tails give more heads to spread over the GPU (the once-punctured
+// torus table: 324 tails of 5 symbols, three times the heads of 972 tails of
+// 6, at 0.31 against 0.42 ms for depth 16), while longer tails spread each
+// head's ranking over more words.
+constexpr int kCayleyHeadTails = 400;
 constexpr int kCayleyMaxTail = 12;      // its longest tails
 enum { kCayleyDecode = 0, kCayleyEval = 1, kCayleyRender = 2 };
 struct CayleyJob {
