@@ -63,6 +63,43 @@ __device__ __forceinline__ int packed_symbol(uint64_t lo, uint64_t hi, int j) {
     return (int)((j < 21 ? lo >> (3 * j) : hi >> (3 * (j - 21))) & 7u);
 }
 
+// Wave-level barrier for LDS written and read by the lanes of one wave.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Counts of the regular words by length and end state, C[L * stride + s]
+// for L = 0..D, from the table copied to LDS (TB): A[t * S + s] counts the
+// symbols that take state s to state t != 0, and C[L][t] = sum over s of
+// A[t][s] C[L - 1][s].  The first wave forms the lengths one after another
+// (one lane per state); the block is synchronised on return.
+__device__ inline void cayley_counts(const uint8_t* TB, uint8_t* A, uint64_t* C, int stride, int S, int m, int D) {
+    for (int i = threadIdx.x; i < S * S; i += blockDim.x) {
+        const int t = i / S, s = i - t * S;
+        int n = 0;
+        if (t != 0)
+            for (int x = 1; x <= m; ++x) n += TB[s * (m + 1) + x] == t ? 1 : 0;
+        A[i] = (uint8_t)n;
+    }
+    __syncthreads();
+    if (threadIdx.x < (unsigned)kWave) {
+        const int t = threadIdx.x;
+        if (t < S) C[t] = t == 0 ? 1 : 0;
+        wave_sync();
+        for (int L = 1; L <= D; ++L) {
+            if (t < S) {
+                uint64_t n = 0;
+                for (int s = 0; s < S; ++s) n += (uint64_t)A[t * S + s] * C[(L - 1) * stride + s];
+                C[L * stride + t] = n;
+            }
+            wave_sync();
+        }
+    }
+    __syncthreads();
+}
+
 // The good sets reachable from the set of all states form a deterministic
 // automaton (next_set); CM[L][g] = sum over s in set g of C[L][s] counts the
 // words that begin with a prefix of good set g and have L symbols to go.
@@ -91,30 +128,23 @@ __global__ __launch_bounds__(256) void cayley_kernel(const CayleyJob a) {
     __shared__ m64 G[kCayleyMaxSymbols];
     __shared__ c64 TU[MODE == kCayleyDecode ? 1 : kCayleyMaxTails], TV[MODE == kCayleyDecode ? 1 : kCayleyMaxTails];
     __shared__ uint8_t TS[MODE == kCayleyDecode ? 1 : kCayleyMaxTails];
+    __shared__ uint8_t TB[kCayleyMaxStates * (kCayleyMaxSymbols + 1)];
+    __shared__ uint8_t A[kCayleyMaxStates * kCayleyMaxStates];
+    __shared__ uint64_t DS[KL_MAX_DEPTH + 2];
     const int S = a.S, m = a.m, M = a.n_sets, D = a.max_depth;
     const int r = MODE == kCayleyDecode ? 0 : a.r;
     for (int i = threadIdx.x; i < M * m; i += blockDim.x) NX[i] = a.next_set[i];
     for (int i = threadIdx.x; i < M; i += blockDim.x) SETS[i] = a.sets[i];
     for (int i = threadIdx.x; i < m; i += blockDim.x) G[i] = a.maps[i];
-    if (threadIdx.x < (unsigned)S) C[0][threadIdx.x] = threadIdx.x == 0 ? 1 : 0;
+    for (int i = threadIdx.x; i < S * (m + 1); i += blockDim.x) TB[i] = a.table[i];
+    for (int i = threadIdx.x; i < KL_MAX_DEPTH + 2; i += blockDim.x) DS[i] = a.depth_start[i];
     __syncthreads();
-    for (int L = 1; L <= D; ++L) {
-        const int t = threadIdx.x;
-        if (t < S) {
-            uint64_t n = 0;
-            if (t != 0)
-                for (int s = 0; s < S; ++s)
-                    for (int x = 1; x <= m; ++x)
-                        if (a.table[s * (m + 1) + x] == t) n += C[L - 1][s];
-            C[L][t] = n;
-        }
-        __syncthreads();
-    }
+    cayley_counts(TB, A, &C[0][0], kCayleyMaxStates, S, m, D);
     for (int i = threadIdx.x; i < (D + 1) * M; i += blockDim.x) {
         const int L = i / M, g = i - L * M;
         uint64_t n = 0;
         for (int s = 0; s < S; ++s)
-            if ((a.sets[g] >> s) & 1u) n += C[L][s];
+            if ((SETS[g] >> s) & 1u) n += C[L][s];
         CM[L][g] = n;
     }
     __syncthreads();
@@ -173,7 +203,7 @@ __global__ __launch_bounds__(256) void cayley_kernel(const CayleyJob a) {
             m64 unused;
             unrank((uint64_t)t, r, 0, -1, lo, hi, gh, unused, 0);
             int s = 0;
-            for (int j = r - 1; j >= 0; --j) s = a.table[s * (m + 1) + packed_symbol(lo, hi, j) + 1];
+            for (int j = r - 1; j >= 0; --j) s = TB[s * (m + 1) + packed_symbol(lo, hi, j) + 1];
             TS[t] = (uint8_t)s;
             c64 u, v;
             seed_point(packed_symbol(lo, hi, r - 1), u, v);
@@ -210,7 +240,7 @@ __global__ __launch_bounds__(256) void cayley_kernel(const CayleyJob a) {
             uint64_t local;
             if (MODE == kCayleyEval) {
                 local = a.idx[k];
-                if (local >= a.depth_start[1]) {
+                if (local >= DS[1]) {
                     a.z_out[k] = {__builtin_nan(""), __builtin_nan("")};
                     ++k;
                     continue;
@@ -218,8 +248,8 @@ __global__ __launch_bounds__(256) void cayley_kernel(const CayleyJob a) {
             } else {
                 const uint64_t i = a.first + k;
                 d = a.min_depth;
-                while (i >= a.depth_start[d - a.min_depth + 1]) ++d;
-                local = i - a.depth_start[d - a.min_depth];
+                while (i >= DS[d - a.min_depth + 1]) ++d;
+                local = i - DS[d - a.min_depth];
             }
             const int hl = (r > 0 && d >= r) ? d - r : -1;   // head length, -1: walk in full
             uint64_t lo, hi;
@@ -279,9 +309,9 @@ __global__ __launch_bounds__(256) void cayley_kernel(const CayleyJob a) {
 
 // ------------------------------------------------------------------ one head per thread
 // Render of the words of depths >= r: a thread takes a whole head (the
-// first d - r symbols) and every lane of a wave steps through the whole
-// tail table together, each evaluating the tails its head accepts, so no
-// lane re-ranks in the middle of a run.  Heads are ranked by their own
+// first d - r symbols) and walks the list of tails its head's good set
+// accepts (built per block in LDS), so no lane re-ranks in the middle of a
+// run or steps over a tail it rejects.  Heads are ranked by their own
 // counts: NH[L][g] heads of L more symbols from good set g accept at least
 // one tail (NH[0][g] = [CM[r][g] > 0]), so head hh of a depth unranks as a
 // word does, with NH in place of CM, while the skipped CM counts give the
@@ -297,8 +327,9 @@ struct HeadLayout {
     // byte offsets: C, CM, NH rows ([(D + 1) * S], [(D + 1) * M] twice); per
     // depth (index d - min_depth) the range's first head HA, the prefix of
     // head counts HS and the word range WA, WB; the tail points TU, TV; the
-    // maps G; the sets SETS; the automaton NX; the tail end states TS
-    uint32_t C, CM, NH, HA, HS, WA, WB, TU, TV, G, SETS, NX, TS, total;
+    // maps G; the sets SETS; the automaton NX; the tail end states TS; and
+    // per good set g the tails it accepts, in table order, at AL[g * n_tails]
+    uint32_t C, CM, NH, HA, HS, WA, WB, TU, TV, G, SETS, NX, TS, AL, TB, A, total;
 };
 
 __host__ __device__ inline HeadLayout cayley_head_layout(int S, int M, int m, int D, int n_tails) {
@@ -323,6 +354,9 @@ __host__ __device__ inline HeadLayout cayley_head_layout(int S, int M, int m, in
     L.SETS = take((uint32_t)M * 2u);
     L.NX = take((uint32_t)M * (uint32_t)m);
     L.TS = take((uint32_t)n_tails);
+    L.AL = take((uint32_t)M * (uint32_t)n_tails * 2u);
+    L.TB = take((uint32_t)S * (uint32_t)(m + 1));
+    L.A = take((uint32_t)S * (uint32_t)S);
     L.total = off;
     return L;
 }
@@ -337,46 +371,43 @@ __global__ __launch_bounds__(256) void cayley_head_kernel(const CayleyJob a) {
         m64* G;
         uint16_t* SETS;
         uint8_t *NX, *TS;
+        uint16_t* AL;
+        uint8_t *TB, *A;
     } q = {(uint64_t*)(lds + lay.C), (uint64_t*)(lds + lay.CM), (uint64_t*)(lds + lay.NH), (uint64_t*)(lds + lay.HA),
            (uint64_t*)(lds + lay.HS), (uint64_t*)(lds + lay.WA), (uint64_t*)(lds + lay.WB), (c64*)(lds + lay.TU),
            (c64*)(lds + lay.TV), (m64*)(lds + lay.G), (uint16_t*)(lds + lay.SETS), (uint8_t*)(lds + lay.NX),
-           (uint8_t*)(lds + lay.TS)};
+           (uint8_t*)(lds + lay.TS), (uint16_t*)(lds + lay.AL), (uint8_t*)(lds + lay.TB), (uint8_t*)(lds + lay.A)};
     for (int i = threadIdx.x; i < M * m; i += blockDim.x) q.NX[i] = a.next_set[i];
     for (int i = threadIdx.x; i < M; i += blockDim.x) q.SETS[i] = a.sets[i];
     for (int i = threadIdx.x; i < m; i += blockDim.x) q.G[i] = a.maps[i];
-    if (threadIdx.x < (unsigned)S) q.C[threadIdx.x] = threadIdx.x == 0 ? 1 : 0;
+    for (int i = threadIdx.x; i < S * (m + 1); i += blockDim.x) q.TB[i] = a.table[i];
     __syncthreads();
-    for (int L = 1; L <= D; ++L) {
-        const int t = threadIdx.x;
-        if (t < S) {
-            uint64_t n = 0;
-            if (t != 0)
-                for (int s = 0; s < S; ++s)
-                    for (int x = 1; x <= m; ++x)
-                        if (a.table[s * (m + 1) + x] == t) n += q.C[(L - 1) * S + s];
-            q.C[L * S + t] = n;
-        }
-        __syncthreads();
-    }
+    cayley_counts(q.TB, q.A, q.C, S, S, m, D);
     for (int i = threadIdx.x; i < (D + 1) * M; i += blockDim.x) {
         const int L = i / M, g = i - L * M;
         uint64_t n = 0;
         for (int s = 0; s < S; ++s)
-            if ((a.sets[g] >> s) & 1u) n += q.C[L * S + s];
+            if ((q.SETS[g] >> s) & 1u) n += q.C[L * S + s];
         q.CM[i] = n;
     }
     __syncthreads();
-    // heads of L more symbols that accept at least one tail
-    for (int g = threadIdx.x; g < M; g += blockDim.x) q.NH[g] = q.CM[r * M + g] > 0 ? 1 : 0;
-    __syncthreads();
-    for (int L = 1; L + r <= D; ++L) {
-        for (int g = threadIdx.x; g < M; g += blockDim.x) {
-            uint64_t n = 0;
-            for (int x = 1; x <= m; ++x) n += q.NH[(L - 1) * M + q.NX[g * m + x - 1]];
-            q.NH[L * M + g] = n;
+    // heads of L more symbols that accept at least one tail: the first wave,
+    // one lane per good set, one length after another
+    static_assert(kCayleyMaxSets <= kWave, "one lane per good set");
+    if (threadIdx.x < (unsigned)kWave) {
+        const int g = threadIdx.x;
+        if (g < M) q.NH[g] = q.CM[r * M + g] > 0 ? 1 : 0;
+        wave_sync();
+        for (int L = 1; L + r <= D; ++L) {
+            if (g < M) {
+                uint64_t n = 0;
+                for (int x = 1; x <= m; ++x) n += q.NH[(L - 1) * M + q.NX[g * m + x - 1]];
+                q.NH[L * M + g] = n;
+            }
+            wave_sync();
         }
-        __syncthreads();
     }
+    __syncthreads();
     // the tail table: regular words of length r in lexicographic order, their
     // end states and their points
     for (int t = threadIdx.x; t < a.n_tails; t += blockDim.x) {
@@ -395,7 +426,7 @@ __global__ __launch_bounds__(256) void cayley_head_kernel(const CayleyJob a) {
             else hi |= (uint64_t)(x - 1) << (3 * (j - 21));
         }
         int s = 0;
-        for (int j = r - 1; j >= 0; --j) s = a.table[s * (m + 1) + packed_symbol(lo, hi, j) + 1];
+        for (int j = r - 1; j >= 0; --j) s = q.TB[s * (m + 1) + packed_symbol(lo, hi, j) + 1];
         q.TS[t] = (uint8_t)s;
         const int last = packed_symbol(lo, hi, r - 1);
         const int sd = a.seed < 0 ? last : a.seed;
@@ -413,6 +444,13 @@ __global__ __launch_bounds__(256) void cayley_head_kernel(const CayleyJob a) {
         }
         q.TU[t] = u;
         q.TV[t] = v;
+    }
+    __syncthreads();
+    // per good set, the tails it accepts in table order
+    for (int g = threadIdx.x; g < M; g += blockDim.x) {
+        int k = 0;
+        for (int t = 0; t < a.n_tails; ++t)
+            if ((q.SETS[g] >> q.TS[t]) & 1u) q.AL[g * a.n_tails + k++] = (uint16_t)t;
     }
     // per depth: the range's local word interval and the heads it touches
     const int d0 = r > a.min_depth ? r : a.min_depth;
@@ -485,28 +523,24 @@ __global__ __launch_bounds__(256) void cayley_head_kernel(const CayleyJob a) {
             g = gx;
             Mh = mmul(Mh, q.G[x - 1]);
         }
-        const uint32_t accept = q.SETS[g];
         // this head's accepted tails with ordinals in [o0, o1) are words of the range
-        const uint64_t wa = q.WA[di], wb = q.WB[di];
-        const uint64_t o0 = wa > wstart ? wa - wstart : 0;
-        const uint64_t o1 = wb - wstart;
-        uint64_t ord = 0;
-        for (int t = 0; t < a.n_tails; ++t) {
-            const bool acc = (accept >> q.TS[t]) & 1u;
-            if (acc && ord >= o0 && ord < o1) {
-                const c64 tu = q.TU[t], tv = q.TV[t];
-                double px, py;
-                cayley_pixel(a, cfma(Mh.a, tu, cmul(Mh.b, tv)), cfma(Mh.c, tu, cmul(Mh.d, tv)), px, py);
-                const uint32_t key = cayley_bin(px, py, a.W, a.H);
-                if (key != run_key) {
-                    if (run_key == kCayleyOutside) drop += run_len;
-                    else if (run_len) atomicAdd(a.image + run_key, run_len);
-                    run_key = key;
-                    run_len = 0;
-                }
-                ++run_len;
+        const uint64_t wa = q.WA[di], wb = q.WB[di], n_acc = q.CM[r * M + g];
+        const uint32_t o0 = (uint32_t)(wa > wstart ? wa - wstart : 0);
+        const uint32_t o1 = (uint32_t)(wb - wstart < n_acc ? wb - wstart : n_acc);
+        const uint16_t* list = q.AL + (size_t)g * a.n_tails;
+        for (uint32_t i = o0; i < o1; ++i) {
+            const int t = list[i];
+            const c64 tu = q.TU[t], tv = q.TV[t];
+            double px, py;
+            cayley_pixel(a, cfma(Mh.a, tu, cmul(Mh.b, tv)), cfma(Mh.c, tu, cmul(Mh.d, tv)), px, py);
+            const uint32_t key = cayley_bin(px, py, a.W, a.H);
+            if (key != run_key) {
+                if (run_key == kCayleyOutside) drop += run_len;
+                else if (run_len) atomicAdd(a.image + run_key, run_len);
+                run_key = key;
+                run_len = 0;
             }
-            ord += acc ? 1u : 0u;
+            ++run_len;
         }
     }
     if (run_key == kCayleyOutside) drop += run_len;
@@ -541,8 +575,11 @@ hipError_t launch_cayley(const CayleyJob& job, int mode, hipStream_t s) {
             if (e != hipSuccess) return e;
         }
         if (j.first >= B) return hipSuccess;
+        // the words shorter than r, each walked in full by a thread of its own (no tail table)
         j.count = (end < B ? end : B) - j.first;
-        j.run = (int)std::min<uint64_t>(kCayleyRunMax, std::max<uint64_t>(kCayleyRunMin, j.count / threads));
+        j.r = 0;
+        j.n_tails = 0;
+        j.run = 1;
     }
     const uint64_t per = mode == kCayleyRender ? (uint64_t)j.run : 1;
     uint64_t blocks = (j.count + 256 * per - 1) / (256 * per);
