@@ -148,13 +148,14 @@ def test_range_additivity():
 
 
 def test_head_tail_boundary_depths():
-    """Table 2 takes tails of 6 symbols: depth 5 is walked in full, depth 6 is
-    a tail with an empty head, depth 7 a one-symbol head.  Values within
-    1e-10 of the reference at each, and a tiling render over all three equal
-    to the histogram of its own evaluated bins."""
+    """Table 2 takes tails of 5 symbols (the longest with at most 400 regular
+    words): depth 4 is walked in full, depth 5 is a tail with an empty head,
+    depths 6 and 7 have heads of one and two symbols.  Values within 1e-10 of
+    the reference at each, and a tiling render over all four equal to the
+    histogram of its own evaluated bins."""
     t, ref = _pair(T11, _recipe_maps())
     win = wl.QUASIFUCHSIAN_D18.window.as_tuple()
-    for d in (5, 6, 7):
+    for d in (4, 5, 6, 7):
         n = kl.cayley_num_words(t, d)
         idx = np.arange(n, dtype=np.uint64)
         for seed, s in (("own", -1), ("B", 3)):
@@ -165,10 +166,10 @@ def test_head_tail_boundary_depths():
             assert np.isfinite(z[fin]).all()
             assert (np.abs(z[fin] - zr[fin]) / np.maximum(1, np.abs(zr[fin]))).max() < 1e-10, (d, seed)
     dropped = torch.zeros(1, dtype=torch.int64, device="cuda")
-    img = kl.as_u32(kl.cayley_render(t, 7, win, min_depth=5, dropped=dropped)).astype(np.int64)
+    img = kl.as_u32(kl.cayley_render(t, 7, win, min_depth=4, dropped=dropped)).astype(np.int64)
     ref_img = np.zeros_like(img)
     drop = 0
-    for d in (5, 6, 7):
+    for d in (4, 5, 6, 7):
         p = kl.cayley_eval(t, d, np.arange(kl.cayley_num_words(t, d), dtype=np.uint64), window=win).cpu().numpy()
         r, dr = _bins(p[:, 0], p[:, 1], win)
         ref_img += r
