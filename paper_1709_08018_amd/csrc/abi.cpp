@@ -1225,10 +1225,11 @@ int kl_cayley_render_ex(const kl_cayley* t, int depth, const kl_window* window, 
     j.H = window->height;
     j.dropped = o.dropped_out;
     j.grid_blocks = device_cu_count() * 2;   // the tail table fits two workgroups per CU
-    for (int sd : seeds) {
-        j.seed = sd;
-        if ((e = launch_cayley(j, kCayleyRender, s)) != hipSuccess) return hip_fail(e, "Cayley render kernel");
-    }
+    // every seed in one render: one tail table per seed in the head kernel
+    j.n_seeds = (int)seeds.size();
+    for (int k = 0; k < j.n_seeds; ++k) j.seed_list[k] = (int8_t)seeds[k];
+    j.seed = seeds[0];
+    if ((e = launch_cayley(j, kCayleyRender, s)) != hipSuccess) return hip_fail(e, "Cayley render kernel");
     return KL_OK;
 }
 

@@ -332,7 +332,7 @@ struct HeadLayout {
     uint32_t C, CM, NH, HA, HS, WA, WB, TU, TV, G, SETS, NX, TS, AL, TB, A, total;
 };
 
-__host__ __device__ inline HeadLayout cayley_head_layout(int S, int M, int m, int D, int n_tails) {
+__host__ __device__ inline HeadLayout cayley_head_layout(int S, int M, int m, int D, int n_tails, int n_seeds) {
     HeadLayout L;
     uint32_t off = 0;
     auto take = [&](uint32_t bytes) {
@@ -348,8 +348,8 @@ __host__ __device__ inline HeadLayout cayley_head_layout(int S, int M, int m, in
     L.HS = take((KL_MAX_DEPTH + 2) * 8u);
     L.WA = take((KL_MAX_DEPTH + 1) * 8u);
     L.WB = take((KL_MAX_DEPTH + 1) * 8u);
-    L.TU = take((uint32_t)n_tails * (uint32_t)sizeof(c64));
-    L.TV = take((uint32_t)n_tails * (uint32_t)sizeof(c64));
+    L.TU = take((uint32_t)n_seeds * (uint32_t)n_tails * (uint32_t)sizeof(c64));
+    L.TV = take((uint32_t)n_seeds * (uint32_t)n_tails * (uint32_t)sizeof(c64));
     L.G = take((uint32_t)m * (uint32_t)sizeof(m64));
     L.SETS = take((uint32_t)M * 2u);
     L.NX = take((uint32_t)M * (uint32_t)m);
@@ -364,7 +364,8 @@ __host__ __device__ inline HeadLayout cayley_head_layout(int S, int M, int m, in
 __global__ __launch_bounds__(256) void cayley_head_kernel(const CayleyJob a) {
     extern __shared__ __align__(16) unsigned char lds[];
     const int S = a.S, m = a.m, M = a.n_sets, D = a.max_depth, r = a.r;
-    const HeadLayout lay = cayley_head_layout(S, M, m, D, a.n_tails);
+    const int NT = a.n_tails, NS = a.n_seeds;
+    const HeadLayout lay = cayley_head_layout(S, M, m, D, NT, NS);
     struct {
         uint64_t *C, *CM, *NH, *HA, *HS, *WA, *WB;
         c64 *TU, *TV;
@@ -409,8 +410,9 @@ __global__ __launch_bounds__(256) void cayley_head_kernel(const CayleyJob a) {
     }
     __syncthreads();
     // the tail table: regular words of length r in lexicographic order, their
-    // end states and their points
-    for (int t = threadIdx.x; t < a.n_tails; t += blockDim.x) {
+    // end states, and their points from each seed in turn (TU[slot * NT + t])
+    for (int e = threadIdx.x; e < NS * NT; e += blockDim.x) {
+        const int slot = e / NT, t = e - slot * NT;
         uint64_t local = (uint64_t)t, lo = 0, hi = 0;
         int g = 0;
         for (int j = 0; j < r; ++j) {
@@ -427,9 +429,9 @@ __global__ __launch_bounds__(256) void cayley_head_kernel(const CayleyJob a) {
         }
         int s = 0;
         for (int j = r - 1; j >= 0; --j) s = q.TB[s * (m + 1) + packed_symbol(lo, hi, j) + 1];
-        q.TS[t] = (uint8_t)s;
+        if (slot == 0) q.TS[t] = (uint8_t)s;
         const int last = packed_symbol(lo, hi, r - 1);
-        const int sd = a.seed < 0 ? last : a.seed;
+        const int sd = a.seed_list[slot] < 0 ? last : a.seed_list[slot];
         c64 u = a.fix[sd], v = {1.0, 0.0};
         if ((a.inf_mask >> sd) & 1u) {
             u = {1.0, 0.0};
@@ -442,8 +444,8 @@ __global__ __launch_bounds__(256) void cayley_head_kernel(const CayleyJob a) {
             u = nu;
             v = nv;
         }
-        q.TU[t] = u;
-        q.TV[t] = v;
+        q.TU[e] = u;
+        q.TV[e] = v;
     }
     __syncthreads();
     // per good set, the tails it accepts in table order
@@ -498,11 +500,16 @@ __global__ __launch_bounds__(256) void cayley_head_kernel(const CayleyJob a) {
     }
     __syncthreads();
 
+    // (seed, head) pairs, seed-major so that the lanes of a wave share a seed
     const uint64_t total = q.HS[D - a.min_depth + 1];
     uint64_t drop = 0;
     uint32_t run_key = kCayleyOutside, run_len = 0;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t u = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; u < total; u += stride) {
+    for (uint64_t uu = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; uu < total * (uint64_t)NS; uu += stride) {
+        const int slot = (int)(uu / total);
+        const uint64_t u = uu - (uint64_t)slot * total;
+        const c64* TU = q.TU + (size_t)slot * NT;
+        const c64* TV = q.TV + (size_t)slot * NT;
         int d = d0;
         while (u >= q.HS[d + 1 - a.min_depth]) ++d;
         const int di = d - a.min_depth, hl = d - r;
@@ -530,7 +537,7 @@ __global__ __launch_bounds__(256) void cayley_head_kernel(const CayleyJob a) {
         const uint16_t* list = q.AL + (size_t)g * a.n_tails;
         for (uint32_t i = o0; i < o1; ++i) {
             const int t = list[i];
-            const c64 tu = q.TU[t], tv = q.TV[t];
+            const c64 tu = TU[t], tv = TV[t];
             double px, py;
             cayley_pixel(a, cfma(Mh.a, tu, cmul(Mh.b, tv)), cfma(Mh.c, tu, cmul(Mh.d, tv)), px, py);
             const uint32_t key = cayley_bin(px, py, a.W, a.H);
@@ -564,22 +571,40 @@ hipError_t launch_cayley(const CayleyJob& job, int mode, hipStream_t s) {
             CayleyJob h = j;
             h.first = j.first > B ? j.first : B;
             h.count = end - h.first;
-            const size_t lds = cayley_head_layout(j.S, j.n_sets, j.m, j.max_depth, j.n_tails).total;
-            if (lds > 65536) {
-                hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(cayley_head_kernel),
-                                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            // as many seeds per launch as their tail tables fit the LDS of a CU
+            const size_t cap = 160 * 1024;
+            int per = j.n_seeds;
+            while (per > 1 && cayley_head_layout(j.S, j.n_sets, j.m, j.max_depth, j.n_tails, per).total > cap) --per;
+            for (int k0 = 0; k0 < j.n_seeds; k0 += per) {
+                h.n_seeds = std::min(per, j.n_seeds - k0);
+                for (int k = 0; k < h.n_seeds; ++k) h.seed_list[k] = j.seed_list[k0 + k];
+                const size_t lds = cayley_head_layout(j.S, j.n_sets, j.m, j.max_depth, j.n_tails, h.n_seeds).total;
+                if (lds > 65536) {
+                    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(cayley_head_kernel),
+                                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+                    if (e != hipSuccess) return e;
+                }
+                hipLaunchKernelGGL(cayley_head_kernel, dim3((unsigned)std::max(1, j.grid_blocks)), dim3(256), lds, s,
+                                   h);
+                hipError_t e = hipGetLastError();
                 if (e != hipSuccess) return e;
             }
-            hipLaunchKernelGGL(cayley_head_kernel, dim3((unsigned)std::max(1, j.grid_blocks)), dim3(256), lds, s, h);
-            hipError_t e = hipGetLastError();
-            if (e != hipSuccess) return e;
         }
         if (j.first >= B) return hipSuccess;
-        // the words shorter than r, each walked in full by a thread of its own (no tail table)
+        // the words shorter than r, each walked in full by a thread of its own
+        // (no tail table), one launch per seed
         j.count = (end < B ? end : B) - j.first;
         j.r = 0;
         j.n_tails = 0;
         j.run = 1;
+        const uint64_t blocks = std::min<uint64_t>((j.count + 255) / 256, (uint64_t)std::max(1, j.grid_blocks));
+        for (int k = 0; k < j.n_seeds; ++k) {
+            j.seed = j.seed_list[k];
+            hipLaunchKernelGGL(cayley_kernel<kCayleyRender>, dim3((unsigned)blocks), dim3(256), 0, s, j);
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
     }
     const uint64_t per = mode == kCayleyRender ? (uint64_t)j.run : 1;
     uint64_t blocks = (j.count + 256 * per - 1) / (256 * per);

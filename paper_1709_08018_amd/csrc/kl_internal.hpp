@@ -218,6 +218,8 @@ struct CayleyJob {
     uint32_t inf_mask;                  // bit x - 1: symbol x's fixed point is infinity
     int S, m, min_depth, max_depth;
     int seed;                           // -1: each word's last symbol's fixed point; else symbol seed + 1's
+    int n_seeds;                        // render: the seeds drawn in turn (each as `seed`), n_seeds >= 1
+    int8_t seed_list[kCayleyMaxSymbols];
     uint64_t first, count;              // decode / render: words [first, first + count) of the combined
     uint64_t depth_start[KL_MAX_DEPTH + 2];  // index space; depth_start[d - min_depth] = its first word
     Fold fold;
