@@ -349,6 +349,13 @@ static int grid_for(int waves_per_cu) {
 
 static bool persistent_ok(const Split& sp) { return sp.k + sp.m > 0 && sp.r >= 3 && sp.n_heads >= (uint64_t)kWave; }
 
+// Units of 64 heads below which a launch leaves the persistent kernel for the
+// per-word kernel.  With u units only u waves walk 3^r words each, one after
+// another (a unit of 729 words takes some 30 us at one wave per SIMD), while
+// the per-word kernel spreads the same words one per thread; the two break
+// even near a hundred units.  Both compute every word the same way.
+constexpr uint64_t kMinPersistentUnits = 128;
+
 // ------------------------------------------------------------------ tuned plans
 // Plans chosen by kl_autotune, keyed by (depth, precision): the split
 // decides the arithmetic of every word, so kl_eval and every render of one
@@ -463,9 +470,9 @@ static int render_depth(const Gens& G, const Fold& f, int depth, uint64_t lo, ui
     job.bounded = o.block_bounds && o.precision == KL_PREC_FP32 && sp.r >= 4 && o.hist_mode != KL_HIST_LDS;
     uint64_t rag_lo = lo, rag_hi = hi;  // default: every word by the per-word kernel
     if (persistent_ok(sp)) {
-        // whole heads inside [lo, hi) go to the persistent kernel
+        // whole heads inside [lo, hi) go to the persistent kernel, when they fill enough units
         const uint64_t hb = (lo + sp.R - 1) / sp.R, he = hi / sp.R;
-        if (he > hb) {
+        if (he > hb && he - hb >= kMinPersistentUnits * kWave) {
             if (o.kernel_events[0]) (void)hipEventRecord((hipEvent_t)o.kernel_events[0], s);
             const uint64_t max_heads = (uint64_t)kWave << 30;
             for (uint64_t h0 = hb; h0 < he;) {
@@ -689,8 +696,14 @@ static int render_sets(const std::vector<SetSpec>& specs, const kl_window* w, co
     std::vector<SetDesc> h_sets(nb), h_psets;
     std::vector<uint64_t> h_off(1, 0), h_woff(1, 0);
     std::vector<int> h_ids;
+    // the persistent kernel takes the deep sets when together they fill enough units
+    uint64_t units = 0;
+    for (int j = 0; j < nb; ++j)
+        if (persistent_ok(specs[j].sp)) units += (specs[j].sp.n_heads + kWave - 1) / kWave;
+    const bool persist = units >= kMinPersistentUnits;
+    auto persistent = [&](const Split& sp) { return persist && persistent_ok(sp); };
     for (int j = 0; j < nb; ++j) {
-        if (persistent_ok(specs[j].sp)) {
+        if (persistent(specs[j].sp)) {
             h_off.push_back(h_off.back() + (specs[j].sp.n_heads + kBlock - 1) / kBlock);  // block units: one head per thread
         } else {
             h_ids.push_back(j);
@@ -746,7 +759,7 @@ static int render_sets(const std::vector<SetSpec>& specs, const kl_window* w, co
         po += D.n_prefix;
         to_aff += ((D.n_tail * esz + 15) / 16) * 16;
         to_hom += ((2 * D.n_tail * esz + 15) / 16) * 16;
-        if (persistent_ok(q.sp)) {
+        if (persistent(q.sp)) {
             max_bytes = std::max<uint32_t>(max_bytes, (uint32_t)(((2 * D.n_tail * esz + 15) / 16) * 16));
             h_psets.push_back(D);
         }

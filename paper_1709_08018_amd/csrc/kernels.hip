@@ -1141,21 +1141,41 @@ __device__ inline void word_point(uint64_t i, const PerWordArgs& a, const m64* G
     word_point<T>(i, a.sp, a.tab, a.tail_homog, a.fold, G, affine, px, py);
 }
 
+// Runs of equal bins among consecutive lanes of a wave (consecutive words of
+// one head mostly share a bin): the first lane of a run gets the run's
+// length, the others 0.  `tag` separates runs that must not merge (the set
+// of a batched word); kDead marks a lane without a word.  All lanes of the
+// wave take part.
+constexpr uint32_t kDead = 0xFFFFFFFEu;
+
+__device__ __forceinline__ uint32_t lane_run_length(uint32_t key, uint32_t tag) {
+    const int lane = (int)(threadIdx.x & (kWave - 1));
+    const uint32_t pk = __shfl_up(key, 1, kWave), pt = __shfl_up(tag, 1, kWave);
+    const bool first = lane == 0 || key != pk || tag != pt;
+    const uint64_t starts = __ballot(first);
+    const uint64_t later = lane == kWave - 1 ? 0ull : starts & (~0ull << (lane + 1));
+    const int next = later ? __ffsll((unsigned long long)later) - 1 : kWave;
+    return first ? (uint32_t)(next - lane) : 0u;
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void perword_render_kernel(const PerWordArgs a) {
     __shared__ m64 G[4];
     if (threadIdx.x < 4) G[threadIdx.x] = a.gens.g[threadIdx.x];
     const bool affine = tail_affine_block(a.tab);  // also orders the G stores before their use
     const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    uint64_t drop = 0;
+    uint32_t key = kDead;
     if (tid < a.count0 + a.count1) {
         const uint64_t i = tid < a.count0 ? a.first0 + tid : a.first1 + (tid - a.count0);
         T px, py;
         word_point<T>(i, a, G, affine, px, py);
-        const uint32_t key = bin_key(px, py, a.W, a.H);
-        if (key == kOutside) drop = 1;
-        else atomicAdd(a.image + key, 1u);
+        key = bin_key(px, py, a.W, a.H);
     }
+    // one atomic per run of equal bins
+    const uint32_t len = lane_run_length(key, 0u);
+    uint64_t drop = 0;
+    if (len && key == kOutside) drop = len;
+    else if (len && key != kDead) atomicAdd(a.image + key, len);
     if (a.dropped) {
         for (int off = kWave / 2; off > 0; off >>= 1) drop += __shfl_down(drop, off, kWave);
         if ((threadIdx.x & (kWave - 1)) == 0 && drop)
@@ -1164,36 +1184,36 @@ __global__ __launch_bounds__(256) void perword_render_kernel(const PerWordArgs a
 }
 
 // Words of several sets (their tables built by the batch table kernels, one
-// form flag word per set), one per thread.  Dropped words are summed over
-// the wave when its lanes share one counter, else counted lane by lane.
+// form flag word per set), one per thread.  A run of equal bins of one set
+// among consecutive lanes is added with one atomic, to its image or to its
+// dropped counter.
 template <typename T>
 __global__ __launch_bounds__(256) void perword_batch_kernel(const PerWordBatchJob a) {
-    const int lane = (int)(threadIdx.x & (kWave - 1));
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < a.total; w += stride) {
-        int lo = 0, hi = a.n - 1;   // the last q with word_offsets[q] <= w
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (a.word_offsets[mid] <= w) lo = mid;
-            else hi = mid - 1;
+    // every lane of a block takes part in every round (lane_run_length)
+    for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x; base < a.total; base += stride) {
+        const uint64_t w = base + threadIdx.x;
+        uint32_t key = kDead, tag = 0xFFFFFFFFu;
+        const SetDesc* S = nullptr;
+        if (w < a.total) {
+            int lo = 0, hi = a.n - 1;   // the last q with word_offsets[q] <= w
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (a.word_offsets[mid] <= w) lo = mid;
+                else hi = mid - 1;
+            }
+            S = &a.sets[a.set_ids[lo]];
+            const bool affine = S->tab.tail_flags[0] == 0u;
+            T px, py;
+            word_point<T>(w - a.word_offsets[lo], S->sp, S->tab, S->tail_homog, a.fold, S->gens.g, affine, px, py);
+            key = bin_key(px, py, a.width, a.height);
+            tag = (uint32_t)lo;
         }
-        const SetDesc& S = a.sets[a.set_ids[lo]];
-        const bool affine = S.tab.tail_flags[0] == 0u;
-        T px, py;
-        word_point<T>(w - a.word_offsets[lo], S.sp, S.tab, S.tail_homog, a.fold, S.gens.g, affine, px, py);
-        const uint32_t key = bin_key(px, py, a.width, a.height);
-        if (key != kOutside) atomicAdd(S.image + key, 1u);
-        uint64_t* dst = S.dropped;
-        const uint64_t bits = (uint64_t)dst;
-        const uint32_t b0 = __builtin_amdgcn_readfirstlane((uint32_t)bits);
-        const uint32_t b1 = __builtin_amdgcn_readfirstlane((uint32_t)(bits >> 32));
-        const bool same = (uint32_t)bits == b0 && (uint32_t)(bits >> 32) == b1;
-        if (__ballot(!same) == 0) {
-            const uint64_t n = (uint64_t)__popcll(__ballot(key == kOutside));
-            const int first = __ffsll((long long)__ballot(1)) - 1;
-            if (lane == first && dst && n) atomicAdd((unsigned long long*)dst, (unsigned long long)n);
-        } else if (key == kOutside && dst) {
-            atomicAdd((unsigned long long*)dst, 1ull);
+        // one atomic per run of equal bins of one set
+        const uint32_t len = lane_run_length(key, tag);
+        if (len && key != kDead) {
+            if (key != kOutside) atomicAdd(S->image + key, len);
+            else if (S->dropped) atomicAdd((unsigned long long*)S->dropped, (unsigned long long)len);
         }
     }
 }

@@ -52,10 +52,13 @@ def _bins_from_pixels(px, py, win):
     return img.reshape(H, W), int((~ok).sum())
 
 
-@pytest.mark.parametrize("depth,win", [(18, WIN_C2), (14, WIN_C2), (13, WIN_ZOOM), (12, WIN_64), (13, WIN_ANISO)],
+# tail_len 4 gives depths 12 and 13 enough heads for the persistent kernel,
+# which alone takes block bounds
+@pytest.mark.parametrize("depth,win,tl", [(18, WIN_C2, 0), (14, WIN_C2, 0), (13, WIN_ZOOM, 4), (12, WIN_64, 4),
+                                          (13, WIN_ANISO, 4)],
                          ids=["d18", "d14", "d13_zoom", "d12_64", "d13_aniso"])
-def test_bounded_equals_per_word(depth, win):
-    img, drop = _assert_same(lambda **kw: kl.render(*C2, depth, win, **kw))
+def test_bounded_equals_per_word(depth, win, tl):
+    img, drop = _assert_same(lambda **kw: kl.render(*C2, depth, win, tail_len=tl, **kw))
     assert int(img.sum()) + drop == kl.num_words(depth)
 
 
@@ -66,15 +69,15 @@ def test_bounded_seed_modes(seed):
 
 @pytest.mark.parametrize("tail_len", [4, 5, 7, 8])
 def test_bounded_tail_lengths(tail_len):
-    _assert_same(lambda **kw: kl.render(*C2, 14, WIN_64, tail_len=tail_len, **kw))
+    _assert_same(lambda **kw: kl.render(*C2, 16, WIN_64, tail_len=tail_len, **kw))
 
 
 def test_bounded_equals_histogram_of_own_bins():
-    depth, win = 13, WIN_64
+    depth, win, tl = 13, WIN_64, 4
     n = kl.num_words(depth)
     dropped = torch.zeros(1, dtype=torch.int64, device="cuda")
-    img = kl.as_u32(kl.render(*C2, depth, win, block_bounds=True, dropped=dropped)).astype(np.int64)
-    p = kl.eval_values(*C2, depth, np.arange(n, dtype=np.uint64), window=win).cpu().numpy()
+    img = kl.as_u32(kl.render(*C2, depth, win, block_bounds=True, dropped=dropped, tail_len=tl)).astype(np.int64)
+    p = kl.eval_values(*C2, depth, np.arange(n, dtype=np.uint64), window=win, tail_len=tl).cpu().numpy()
     ref, drop = _bins_from_pixels(p[:, 0], p[:, 1], win)
     np.testing.assert_array_equal(img, ref)
     assert int(dropped.item()) == drop
@@ -99,7 +102,7 @@ def test_bounded_group_with_heads_of_both_forms():
     and their units take the per-word walk."""
     ab = kl.maskit_generators(wl.MASKIT_MU)
     win = wl.MASKIT_D14.window.as_tuple()
-    _assert_same(lambda **kw: kl.render_group(ab, 13, win, **kw))
+    _assert_same(lambda **kw: kl.render_group(ab, 13, win, tail_len=4, **kw))
     _assert_same(lambda **kw: kl.render(*C1, 14, wl.FUCHSIAN_TILING_D10.window.as_tuple(), **kw))
 
 

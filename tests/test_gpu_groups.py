@@ -78,11 +78,13 @@ def test_seeded_fp32_pixel_error(seed):
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
 def test_seeded_image_is_histogram_of_own_bins(precision):
     depth, win = 12, WIN_C2
+    tl = 4   # enough heads for the persistent kernel
     n = kl.num_words(depth)
     dropped = torch.zeros(1, dtype=torch.int64, device="cuda")
-    img = kl.as_u32(kl.render(*C2, depth, win, precision=precision, seed="b", dropped=dropped)).astype(np.int64)
+    img = kl.as_u32(kl.render(*C2, depth, win, precision=precision, seed="b", dropped=dropped,
+                              tail_len=tl)).astype(np.int64)
     p = kl.eval_values(*C2, depth, np.arange(n, dtype=np.uint64), precision=precision, window=win,
-                       seed="b").cpu().numpy()
+                       seed="b", tail_len=tl).cpu().numpy()
     ref, drop = _bins_from_pixels(p[:, 0], p[:, 1], win)
     np.testing.assert_array_equal(img, ref)
     assert int(dropped.item()) == drop

@@ -121,13 +121,18 @@ def test_eval_out_of_range_index_gives_nan():
 
 
 # ---------------------------------------------------------------- images
+# tail_len 4 gives these depths enough heads for the persistent kernel; the
+# planner's 6 leaves them to the per-word kernel
+@pytest.mark.parametrize("tail_len", [0, 4])
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
 @pytest.mark.parametrize("depth,win", [(12, WIN_C2), (13, (-2.0, 2.0, -2.0, 2.0, 300, 100))])
-def test_image_is_histogram_of_own_bins(precision, depth, win):
+def test_image_is_histogram_of_own_bins(precision, depth, win, tail_len):
     n = kl.num_words(depth)
     dropped = torch.zeros(1, dtype=torch.int64, device="cuda")
-    img = kl.as_u32(kl.render(*C2, depth, win, precision=precision, dropped=dropped)).astype(np.int64)
-    p = kl.eval_values(*C2, depth, np.arange(n, dtype=np.uint64), precision=precision, window=win).cpu().numpy()
+    img = kl.as_u32(kl.render(*C2, depth, win, precision=precision, dropped=dropped,
+                              tail_len=tail_len)).astype(np.int64)
+    p = kl.eval_values(*C2, depth, np.arange(n, dtype=np.uint64), precision=precision, window=win,
+                       tail_len=tail_len).cpu().numpy()
     ref, drop = _bins_from_pixels(p[:, 0], p[:, 1], win)
     np.testing.assert_array_equal(img, ref)
     assert int(dropped.item()) == drop
@@ -206,18 +211,19 @@ def test_ratio_form_heads_render_their_own_bins(head_form, precision):
     kl_eval gives their words under the same head form, with either
     histogram strategy and in the batched renderer."""
     depth, win = 13, (-1.7, 1.3, -1.4, 1.6, 640, 480)
+    tl = 4   # enough heads for the persistent kernel
     n = kl.num_words(depth)
     dropped = torch.zeros(1, dtype=torch.int64, device="cuda")
-    img = kl.render(*C2, depth, win, precision=precision, dropped=dropped, head_form=head_form)
+    img = kl.render(*C2, depth, win, precision=precision, dropped=dropped, head_form=head_form, tail_len=tl)
     p = kl.eval_values(*C2, depth, np.arange(n, dtype=np.uint64), precision=precision, window=win,
-                       head_form=head_form).cpu().numpy()
+                       head_form=head_form, tail_len=tl).cpu().numpy()
     ref, drop = _bins_from_pixels(p[:, 0], p[:, 1], win)
     np.testing.assert_array_equal(kl.as_u32(img).astype(np.int64), ref)
     assert int(dropped.item()) == drop
-    lds = kl.render(*C2, depth, win, precision=precision, head_form=head_form, hist_mode="lds")
+    lds = kl.render(*C2, depth, win, precision=precision, head_form=head_form, hist_mode="lds", tail_len=tl)
     assert torch.equal(lds, img)
     many = kl.render_many([C2[0]] * 2, [C2[1]] * 2, [depth, depth], win, precision=precision,
-                          head_form=head_form)
+                          head_form=head_form, tail_len=tl)
     assert torch.equal(many[0], img) and torch.equal(many[1], img)
 
 
@@ -290,10 +296,11 @@ def test_non_finite_and_far_coordinates_are_dropped(precision):
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
 def test_homogeneous_suffix_form(precision):
     depth, win = 12, WIN_C2
+    tl = 4   # enough heads for the persistent kernel
     n = kl.num_words(depth)
     idx = np.arange(n, dtype=np.uint64)
-    p = kl.eval_values(*C2, depth, idx, precision=precision, window=win, suffix_form=1).cpu().numpy()
-    img = kl.as_u32(kl.render(*C2, depth, win, precision=precision, suffix_form=1)).astype(np.int64)
+    p = kl.eval_values(*C2, depth, idx, precision=precision, window=win, suffix_form=1, tail_len=tl).cpu().numpy()
+    img = kl.as_u32(kl.render(*C2, depth, win, precision=precision, suffix_form=1, tail_len=tl)).astype(np.int64)
     ref, _ = _bins_from_pixels(p[:, 0], p[:, 1], win)
     np.testing.assert_array_equal(img, ref)
     if precision == "fp64":
