@@ -147,10 +147,11 @@ typedef struct {
                              counted as dropped, one inside a single bin is
                              added to it, and only the others are evaluated
                              word by word.  Images and dropped counts are
-                             bit for bit those of 0.  Applies to FP32
-                             renders of one depth (limit set, index ranges)
-                             with tail_len >= 4 and KL_HIST_RUNS or AUTO;
-                             ignored elsewhere. */
+                             bit for bit those of 0.  Applies where the
+                             persistent renderer runs (renders of one depth
+                             whose whole heads number at least 128 x 64)
+                             for FP32 with tail_len >= 4 and KL_HIST_RUNS or
+                             AUTO; ignored elsewhere. */
 } kl_opts;
 
 /* The split the renderer uses for one depth (see kl_plan). */
