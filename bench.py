@@ -246,12 +246,12 @@ def _kernel_ms(render, reps):
 
 
 def leg_bounded(args):
-    """Block bounds (kl_opts.block_bounds) on the depth-18 workload: each
-    head bounds where each group of 27 suffixes lands, and only groups whose
-    bound spans more than one bin are evaluated word by word.  Step time and
-    persistent-kernel time against the per-word renderer on the same words,
-    the two images and dropped counts compared bin for bin; and depth 22
-    streamed in 8 index ranges, both ways."""
+    """Block bounds (kl_opts.block_bounds) on the depth-18 workload, FP32 and
+    FP64: each head bounds where each group of 27 suffixes lands, and only
+    groups whose bound spans more than one bin are evaluated word by word.
+    Step time and persistent-kernel time against the per-word renderer on
+    the same words, the two images and dropped counts compared bin for bin;
+    and depth 22 streamed in 8 index ranges, both ways."""
     import numpy as np
     import torch
 
@@ -259,7 +259,8 @@ def leg_bounded(args):
     from paper_1709_08018_amd import workloads as wl
 
     out = {"workload": "block_bounds"}
-    for W, chunks in ((wl.QUASIFUCHSIAN_D18, 1), (wl.QUASIFUCHSIAN_D22, 8)):
+    for W, chunks, prec in ((wl.QUASIFUCHSIAN_D18, 1, "fp32"), (wl.QUASIFUCHSIAN_D18, 1, "fp64"),
+                            (wl.QUASIFUCHSIAN_D22, 8, "fp32")):
         n = kl.num_words(W.depth)
         cuts = [n * i // chunks for i in range(chunks + 1)]
         res = {"words": n, "chunks": chunks}
@@ -272,7 +273,7 @@ def leg_bounded(args):
                 for a, b in zip(cuts[:-1], cuts[1:]):
                     rng = {} if chunks == 1 else {"first": a, "count": b - a}
                     kl.render(W.ta, W.tb, W.depth, W.window, image=image, accumulate=a > 0, dropped=dropped,
-                              block_bounds=bounded, **rng, **kw)
+                              block_bounds=bounded, precision=prec, **rng, **kw)
             steps = max(2, args.steps // (4 * chunks))
             ms = _time(run, steps, max(2, steps // 4))
             key = "bounded" if bounded else "per_word"
@@ -285,7 +286,7 @@ def leg_bounded(args):
         res["dropped_equal"] = imgs[False][1] == imgs[True][1]
         res["speedup"] = round(res["per_word"]["ms"] / res["bounded"]["ms"], 2)
         assert res["images_equal"] and res["dropped_equal"], "block bounds changed the image"
-        out[W.name] = res
+        out[W.name if prec == "fp32" else W.name + "_fp64"] = res
     return out
 
 

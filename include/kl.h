@@ -149,9 +149,9 @@ typedef struct {
                              word by word.  Images and dropped counts are
                              bit for bit those of 0.  Applies where the
                              persistent renderer runs (renders of one depth
-                             whose whole heads number at least 128 x 64)
-                             for FP32 with tail_len >= 4 and KL_HIST_RUNS or
-                             AUTO; ignored elsewhere. */
+                             whose whole heads number at least 128 x 64),
+                             FP32 or FP64, with tail_len >= 4 and
+                             KL_HIST_RUNS or AUTO; ignored elsewhere. */
 } kl_opts;
 
 /* The split the renderer uses for one depth (see kl_plan). */

@@ -467,7 +467,7 @@ static int render_depth(const Gens& G, const Fold& f, int depth, uint64_t lo, ui
     job.dropped = dropped;
     job.hist_mode = o.hist_mode;
     job.grid_blocks = grid_for(o.waves_per_cu);
-    job.bounded = o.block_bounds && o.precision == KL_PREC_FP32 && sp.r >= 4 && o.hist_mode != KL_HIST_LDS;
+    job.bounded = o.block_bounds && sp.r >= 4 && o.hist_mode != KL_HIST_LDS;
     uint64_t rag_lo = lo, rag_hi = hi;  // default: every word by the per-word kernel
     if (persistent_ok(sp)) {
         // whole heads inside [lo, hi) go to the persistent kernel, when they fill enough units

@@ -733,61 +733,99 @@ constexpr uint32_t kSpan = 0xFFFFFFFEu;   // run key of a node whose words wait 
 constexpr uint32_t kQueue = 128;          // span queue entries per wave
 constexpr uint32_t kNodeGroup = 3;        // nodes classified together
 
+template <typename T>
 struct NodeDisk {
-    float cr, ci, rho, pad;
+    T cr, ci, rho, pad;
 };
 
+// Per-precision constants of the bounds below, with eps the unit roundoff
+// (2^-24 in FP32, 2^-53 in FP64): `sum` covers the rounding of c + S (4 and
+// 8 eps), `up` enlarges a radius, `p` and `g` are the margin's coefficients
+// (64 eps, and 1024 eps in FP32 and FP64 alike), and the guards keep every
+// product of a word's evaluation finite and normal.
+template <typename T> struct BoundK;
+template <> struct BoundK<float> {
+    static constexpr float sum = 0x1p-22f, up = 1.0f + 0x1p-20f, p = 0x1p-18f, g = 0x1p-14f, tiny = 0x1p-100f;
+    static constexpr float umin_abs = 0x1p-30f, umax = 0x1p40f, gmax = 0x1p60f, pmax = 0x1p100f;
+};
+template <> struct BoundK<double> {
+    static constexpr double sum = 0x1p-50, up = 1.0 + 0x1p-40, p = 0x1p-47, g = 0x1p-43, tiny = 0x1p-900;
+    static constexpr double umin_abs = 0x1p-100, umax = 0x1p100, gmax = 0x1p300, pmax = 0x1p100;
+};
+
+__device__ __forceinline__ float babs(float x) { return __builtin_fabsf(x); }
+__device__ __forceinline__ double babs(double x) { return __builtin_fabs(x); }
+__device__ __forceinline__ float bmin(float x, float y) { return __builtin_fminf(x, y); }
+__device__ __forceinline__ double bmin(double x, double y) { return __builtin_fmin(x, y); }
+__device__ __forceinline__ float bmax(float x, float y) { return __builtin_fmaxf(x, y); }
+__device__ __forceinline__ double bmax(double x, double y) { return __builtin_fmax(x, y); }
+__device__ __forceinline__ float bound_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double bound_sqrt(double x) { return sqrt(x); }
+
+// floor of a bound known to lie in (0, 2^31) where it is used; any value otherwise
+__device__ __forceinline__ int bound_floor(float x) { return floor_i32(x); }
+__device__ __forceinline__ int bound_floor(double x) {
+    return (int)__builtin_floor(__builtin_fmin(__builtin_fmax(x, -1.0), 2147483647.0));
+}
+
 // Bounding disk of node q's suffix points: the centre c is the midpoint of
-// their bounding box rounded to FP32; the radius is their largest distance
-// from c, computed in FP64 and enlarged by 2^-40, plus 2^-22 (|c.re| +
-// |c.im|), which covers the FP32 rounding of c + S in node_class; it is
-// rounded up to FP32.
-__device__ inline void node_disk(const cpx<float>* tail, uint32_t q, NodeDisk* out) {
-    const cpx<float>* p = tail + q * kNodeWords;
-    float x0 = p[0].re, x1 = p[0].re, y0 = p[0].im, y1 = p[0].im;
+// their bounding box rounded to T; the radius is their largest distance
+// from c, computed in FP64 and enlarged by 2^-40, plus BoundK<T>::sum
+// (|c.re| + |c.im|), which covers the rounding of c + S in node_class; in
+// FP32 it is rounded up.
+template <typename T>
+__device__ inline void node_disk(const cpx<T>* tail, uint32_t q, NodeDisk<T>* out) {
+    const cpx<T>* p = tail + q * kNodeWords;
+    T x0 = p[0].re, x1 = p[0].re, y0 = p[0].im, y1 = p[0].im;
     for (uint32_t t = 1; t < kNodeWords; ++t) {
-        x0 = fminf(x0, p[t].re);
-        x1 = fmaxf(x1, p[t].re);
-        y0 = fminf(y0, p[t].im);
-        y1 = fmaxf(y1, p[t].im);
+        x0 = bmin(x0, p[t].re);
+        x1 = bmax(x1, p[t].re);
+        y0 = bmin(y0, p[t].im);
+        y1 = bmax(y1, p[t].im);
     }
-    const float cr = (float)(0.5 * ((double)x0 + (double)x1));
-    const float ci = (float)(0.5 * ((double)y0 + (double)y1));
+    const T cr = (T)(0.5 * ((double)x0 + (double)x1));
+    const T ci = (T)(0.5 * ((double)y0 + (double)y1));
     double r2 = 0.0;
     for (uint32_t t = 0; t < kNodeWords; ++t) {
         const double dx = (double)p[t].re - (double)cr, dy = (double)p[t].im - (double)ci;
         r2 = fmax(r2, dx * dx + dy * dy);
     }
-    const double rho = sqrt(r2) * (1.0 + 0x1p-40) + 0x1p-22 * (fabs((double)cr) + fabs((double)ci)) + 0x1p-100;
-    out[q] = {cr, ci, __double2float_ru(rho), 0.0f};
+    const double rho = sqrt(r2) * (1.0 + 0x1p-40) + (double)BoundK<T>::sum * (fabs((double)cr) + fabs((double)ci)) +
+                       0x1p-900;
+    T rho_t;
+    if constexpr (std::is_same<T, float>::value) rho_t = __double2float_ru(rho);
+    else rho_t = rho;
+    out[q] = {cr, ci, rho_t, T(0)};
 }
 
 // Constants of node_class for one head, formed once per unit.
+template <typename T>
 struct HeadBound {
-    float gx, gy;       // |ax| + |bx|, |ay| + |by|
-    float gx14, gy14;   // 2^-14 times those
-    float mPx, mPy;     // 2^-18 |Px| + 2^-100, likewise Py
-    float sS;           // covers the FP32 rounding of c + S: 2^-22 (1 + 2^-20) (|S.re| + |S.im|)
-    bool ok;            // the products of one word stay finite (a NaN fails this too)
+    T gx, gy;       // |ax| + |bx|, |ay| + |by|
+    T gxg, gyg;     // BoundK<T>::g times those
+    T mPx, mPy;     // BoundK<T>::p |Px| + tiny, likewise Py
+    T sS;           // covers the rounding of c + S: sum (1 + up) (|S.re| + |S.im|)
+    bool ok;        // the products of one word stay finite (a NaN fails this too)
 };
 
-__device__ __forceinline__ HeadBound head_bound(const Head<float>& h) {
-    HeadBound b;
-    b.gx = fabsf(h.ax) + fabsf(h.bx);
-    b.gy = fabsf(h.ay) + fabsf(h.by);
-    b.gx14 = b.gx * 0x1p-14f;
-    b.gy14 = b.gy * 0x1p-14f;
-    b.mPx = fmaf(fabsf(h.Px), 0x1p-18f, 0x1p-100f);
-    b.mPy = fmaf(fabsf(h.Py), 0x1p-18f, 0x1p-100f);
-    b.sS = (fabsf(h.S.re) + fabsf(h.S.im)) * (0x1p-22f * (1.0f + 0x1p-20f));
-    b.ok = fmaxf(b.gx, b.gy) <= 0x1p60f && fabsf(h.Px) <= 0x1p100f && fabsf(h.Py) <= 0x1p100f;
+template <typename T>
+__device__ __forceinline__ HeadBound<T> head_bound(const Head<T>& h) {
+    using K = BoundK<T>;
+    HeadBound<T> b;
+    b.gx = babs(h.ax) + babs(h.bx);
+    b.gy = babs(h.ay) + babs(h.by);
+    b.gxg = b.gx * K::g;
+    b.gyg = b.gy * K::g;
+    b.mPx = fma_(babs(h.Px), K::p, K::tiny);
+    b.mPy = fma_(babs(h.Py), K::p, K::tiny);
+    b.sS = (babs(h.S.re) + babs(h.S.im)) * (K::sum * K::up);
+    b.ok = bmax(b.gx, b.gy) <= K::gmax && babs(h.Px) <= K::pmax && babs(h.Py) <= K::pmax;
     return b;
 }
 
-// Where a pole-form head sends the 27 words of a node, as the FP32
-// arithmetic of eval_pole computes them: kOutside when every word's bin is
-// outside the window, that bin when every word falls in one bin, kSpan
-// when neither can be shown.
+// Where a pole-form head sends the 27 words of a node, as eval_pole computes
+// them in T: kOutside when every word's bin is outside the window, that bin
+// when every word falls in one bin, kSpan when neither can be shown.
 //
 // For y in the disk D(c, rho) and w = c + S with |w| > rho, u = y + S lies
 // in D(w, rho), so 1/u lies in the disk of centre conj(w) / den and radius
@@ -795,34 +833,37 @@ __device__ __forceinline__ HeadBound head_bound(const Head<float>& h) {
 // + i bx) / u) lies within (|ax| + |bx|) rho / den of cx = Px + (ax w.re +
 // bx w.im) / den; likewise py with ay, by.
 //
-// Margins.  (1) The FP32 evaluation at the same inputs (two sums, |u|^2
-// from a product and an FMA, a reciprocal within one ulp, the numerator
-// from a product and an FMA, the closing FMA) differs from the exact value
-// by at most about eps (|Px| + 10 |ax + i bx| / |u|), eps = 2^-24, with
-// |u| >= |w| - rho.  (2) This function computes in FP32 too: w's rounding
-// is inside rho (node_disk, sS); with |w| - rho >= |w| / 64 (a guard) the
-// computed |w| - rho is within about 200 eps of its value, and cx - Px, the
-// radius and the reciprocal within about 420 eps of theirs, all relative
-// to (|ax| + |bx|) / (|w| - rho).  The margin 2^-18 |Px| + 2^-14 (|ax| +
-// |bx|) / (|w| - rho) holds both with room.  Guards keep every product of
-// the FP32 evaluation finite and normal, else kSpan; NaN fails them.
-__device__ __forceinline__ uint32_t node_class(const Head<float>& h, const HeadBound& b, const NodeDisk& d,
-                                               float Wf, float Hf, uint32_t W) {
-    const float wr = d.cr + h.S.re, wi = d.ci + h.S.im;
-    const float rp = fmaf(d.rho, 1.0f + 0x1p-20f, b.sS);
-    const float aw = __builtin_amdgcn_sqrtf(fmaf(wr, wr, wi * wi));
-    const float umin = aw - rp, umax = aw + rp;
-    const float inv = __builtin_amdgcn_rcpf(umin * umax);
-    const float kr = wr * inv, ki = wi * inv, kap = rp * inv, iu = umax * inv;
-    const float cx = fmaf(h.ax, kr, fmaf(h.bx, ki, h.Px));
-    const float cy = fmaf(h.ay, kr, fmaf(h.by, ki, h.Py));
-    const float hx = fmaf(b.gx, kap, fmaf(b.gx14, iu, b.mPx));
-    const float hy = fmaf(b.gy, kap, fmaf(b.gy14, iu, b.mPy));
-    const float lx = cx - hx, ux = cx + hx, ly = cy - hy, uy = cy + hy;
-    const bool ok = b.ok & (umin >= fmaxf(aw * 0x1p-6f, 0x1p-30f)) & (umax <= 0x1p40f);
-    const bool out = (ux < 0.0f) | (lx >= Wf) | (uy < 0.0f) | (ly >= Hf);
-    const int c0 = floor_i32(lx), c1 = floor_i32(ux), r0 = floor_i32(ly), r1 = floor_i32(uy);
-    const bool one = (lx > 0.0f) & (ux < Wf) & (ly > 0.0f) & (uy < Hf) & (c0 == c1) & (r0 == r1);
+// Margins, eps the unit roundoff of T.  (1) The evaluation at the same
+// inputs (two sums, |u|^2 from a product and an FMA, a reciprocal within
+// about one ulp, the numerator from a product and an FMA, the closing FMA)
+// differs from the exact value by at most about eps (|Px| + 12 |ax + i bx| /
+// |u|), with |u| >= |w| - rho.  (2) This function computes in T too: w's
+// rounding is inside rho (node_disk, sS); with |w| - rho >= |w| / 64 (a
+// guard) the computed |w| - rho is within about 200 eps of its value, and
+// cx - Px, the radius and the reciprocal within about 420 eps of theirs,
+// all relative to (|ax| + |bx|) / (|w| - rho).  The margin 64 eps |Px| +
+// 1024 eps (|ax| + |bx|) / (|w| - rho) holds both with room.  Guards keep
+// every product of the evaluation finite and normal, else kSpan; NaN fails
+// them.
+template <typename T>
+__device__ __forceinline__ uint32_t node_class(const Head<T>& h, const HeadBound<T>& b, const NodeDisk<T>& d, T Wf,
+                                               T Hf, uint32_t W) {
+    using K = BoundK<T>;
+    const T wr = d.cr + h.S.re, wi = d.ci + h.S.im;
+    const T rp = fma_(d.rho, K::up, b.sS);
+    const T aw = bound_sqrt(fma_(wr, wr, wi * wi));
+    const T umin = aw - rp, umax = aw + rp;
+    const T inv = recip(umin * umax);
+    const T kr = wr * inv, ki = wi * inv, kap = rp * inv, iu = umax * inv;
+    const T cx = fma_(h.ax, kr, fma_(h.bx, ki, h.Px));
+    const T cy = fma_(h.ay, kr, fma_(h.by, ki, h.Py));
+    const T hx = fma_(b.gx, kap, fma_(b.gxg, iu, b.mPx));
+    const T hy = fma_(b.gy, kap, fma_(b.gyg, iu, b.mPy));
+    const T lx = cx - hx, ux = cx + hx, ly = cy - hy, uy = cy + hy;
+    const bool ok = b.ok & (umin >= bmax(aw * T(0x1p-6), K::umin_abs)) & (umax <= K::umax);
+    const bool out = (ux < T(0)) | (lx >= Wf) | (uy < T(0)) | (ly >= Hf);
+    const int c0 = bound_floor(lx), c1 = bound_floor(ux), r0 = bound_floor(ly), r1 = bound_floor(uy);
+    const bool one = (lx > T(0)) & (ux < Wf) & (ly > T(0)) & (uy < Hf) & (c0 == c1) & (r0 == r1);
     const uint32_t key = one ? __umul24((uint32_t)r0, W) + (uint32_t)c0 : kSpan;
     return !ok ? kSpan : out ? kOutside : key;
 }
@@ -839,13 +880,13 @@ __device__ __forceinline__ void close_bounded(Runs<DROP>& s, uint32_t t_words, u
 // Lanes q < c evaluate the 27 words of span-queue entry q (the head of lane
 // entry >> 8, its node entry & 255) word by word, with eval_pole and
 // bin_key as every other kernel, and run-length counts of their own.
-template <bool DROP>
-__device__ inline void drain_span_queue(const Head<float>& h, int lane, const uint16_t* queue, uint32_t c,
+template <typename T, bool DROP>
+__device__ inline void drain_span_queue(const Head<T>& h, int lane, const uint16_t* queue, uint32_t c,
                                         const unsigned char* tail_lds, uint32_t per, uint32_t W, uint32_t H,
                                         uint32_t* image, Runs<DROP>& s) {
     const uint32_t entry = (uint32_t)lane < c ? queue[lane] : 0u;
     const int src = (int)(entry >> 8);
-    Head<float> g;
+    Head<T> g;
     g.S.re = __shfl(h.S.re, src, kWave);
     g.S.im = __shfl(h.S.im, src, kWave);
     g.ax = __shfl(h.ax, src, kWave);
@@ -862,12 +903,12 @@ __device__ inline void drain_span_queue(const Head<float>& h, int lane, const ui
         const uint32_t base = (y1 * per + sub) * kNodeWords;
         uint32_t cur = kOutside, cnt = 0;
         for (uint32_t t0 = 0; t0 < kNodeWords; t0 += 9) {
-            cpx<float> ya[9];
+            cpx<T> ya[9];
 #pragma unroll
-            for (uint32_t u = 0; u < 9; ++u) ya[u] = ((const cpx<float>*)tail_lds)[base + t0 + u];
+            for (uint32_t u = 0; u < 9; ++u) ya[u] = ((const cpx<T>*)tail_lds)[base + t0 + u];
 #pragma unroll
             for (uint32_t u = 0; u < 9; ++u) {
-                float px, py;
+                T px, py;
                 eval_pole(g, ya[u], px, py);
                 const uint32_t key = bin_key(px, py, W, H);
                 if (key != cur) {
@@ -890,19 +931,19 @@ __device__ inline void drain_span_queue(const Head<float>& h, int lane, const ui
 // to the wave's queue, which lanes drain 64 entries at a time and at the
 // end of the unit.  The word counter advances 27 per node, so the runs
 // count exactly the words the per-word walk would.
-template <bool DROP>
-__device__ inline void bounded_unit(const Head<float>& h, int lane, const unsigned char* tail_lds,
-                                    const NodeDisk* nodes, uint16_t* queue, uint32_t per, uint32_t W, uint32_t H,
+template <typename T, bool DROP>
+__device__ inline void bounded_unit(const Head<T>& h, int lane, const unsigned char* tail_lds,
+                                    const NodeDisk<T>* nodes, uint16_t* queue, uint32_t per, uint32_t W, uint32_t H,
                                     uint32_t* image, Runs<DROP>& s, uint32_t& t_words) {
     const int ie = inv_letter(h.e);
-    const HeadBound hb = head_bound(h);
-    const float Wf = (float)W, Hf = (float)H;
+    const HeadBound<T> hb = head_bound(h);
+    const T Wf = (T)W, Hf = (T)H;
     uint32_t qn = 0;   // queued entries (wave-uniform)
     auto drain = [&](uint32_t c) {
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        drain_span_queue<DROP>(h, lane, queue, c, tail_lds, per, W, H, image, s);
+        drain_span_queue<T, DROP>(h, lane, queue, c, tail_lds, per, W, H, image, s);
         const uint32_t rest = qn - c;
         const uint16_t v = (uint32_t)lane < rest ? queue[c + lane] : (uint16_t)0;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -933,11 +974,11 @@ __device__ inline void bounded_unit(const Head<float>& h, int lane, const unsign
     };
     for (uint32_t j = 0; j < 3; ++j) {
         const uint32_t y1 = j + (j >= (uint32_t)ie);
-        const NodeDisk* nd = nodes + y1 * per;
+        const NodeDisk<T>* nd = nodes + y1 * per;
         if (per % kNodeGroup == 0) {
             // kNodeGroup nodes at a time: their disks read together, their verdicts independent
             for (uint32_t sub0 = 0; sub0 < per; sub0 += kNodeGroup) {
-                NodeDisk dk[kNodeGroup];
+                NodeDisk<T> dk[kNodeGroup];
 #pragma unroll
                 for (uint32_t u = 0; u < kNodeGroup; ++u) dk[u] = nd[sub0 + u];
                 uint32_t key[kNodeGroup];
@@ -960,7 +1001,7 @@ __device__ inline void bounded_unit(const Head<float>& h, int lane, const unsign
 
 template <typename T, bool AFFINE, bool LDSHIST, bool DROP, bool BOUNDED>
 __device__ __forceinline__ void render_units(const RenderArgs& a, const unsigned char* tail_lds, const m64* G,
-                                             uint32_t* tile, const NodeDisk* nodes, uint16_t* queue,
+                                             uint32_t* tile, const NodeDisk<T>* nodes, uint16_t* queue,
                                              Runs<DROP>& s) {
     const int lane = threadIdx.x & (kWave - 1);
     const uint32_t waves = gridDim.x * (kBlock / kWave);
@@ -975,10 +1016,9 @@ __device__ __forceinline__ void render_units(const RenderArgs& a, const unsigned
         const Head<T> h = compute_head<T>(hidx, a.sp, a.tab.prefix, a.tab.prefix_last, G, a.fold);
         const bool dual = wave_needs_dual(h);
         if constexpr (BOUNDED && AFFINE && !LDSHIST) {
-            static_assert(std::is_same<T, float>::value, "block bounds are for the FP32 path");
             if (full && !dual) {
-                bounded_unit<DROP>(h, lane, tail_lds, nodes, queue, a.sp.R1 / kNodeWords, a.W, a.H, a.image, s,
-                                   t_words);
+                bounded_unit<T, DROP>(h, lane, tail_lds, nodes, queue, a.sp.R1 / kNodeWords, a.W, a.H, a.image, s,
+                                      t_words);
                 continue;
             }
         }
@@ -1042,7 +1082,7 @@ __device__ __forceinline__ void render_body(const RenderArgs& a) {
     const size_t tmax = (n_tail * 2 * sizeof(cpx<T>) + 15) & ~size_t(15);
     m64* G = (m64*)(smem + tbytes);
     uint32_t* tile = (uint32_t*)(smem + tmax + 4 * sizeof(m64)) + (threadIdx.x / kWave) * (kTile * kTile);
-    NodeDisk* nodes = (NodeDisk*)(smem + tmax + 4 * sizeof(m64));
+    NodeDisk<T>* nodes = (NodeDisk<T>*)(smem + tmax + 4 * sizeof(m64));
     const uint32_t n_nodes = BOUNDED ? n_tail / kNodeWords : 0u;
     uint16_t* queue = (uint16_t*)(nodes + n_nodes) + (threadIdx.x / kWave) * kQueue;
     {
@@ -1057,7 +1097,7 @@ __device__ __forceinline__ void render_body(const RenderArgs& a) {
     __syncthreads();
     if constexpr (BOUNDED) {
         if (affine) {
-            for (uint32_t q = threadIdx.x; q < n_nodes; q += blockDim.x) node_disk((const cpx<float>*)smem, q, nodes);
+            for (uint32_t q = threadIdx.x; q < n_nodes; q += blockDim.x) node_disk((const cpx<T>*)smem, q, nodes);
             __syncthreads();
         }
     }
@@ -1077,15 +1117,17 @@ __global__ __launch_bounds__(kBlock) void render_kernel(const RenderArgs a) {
     render_body<T, LDSHIST, DROP, false>(a);
 }
 
-// The block-bounds variant (FP32, run-length histogram).  Its node
+// The block-bounds variant (run-length histogram).  Its node
 // classification and span drains are chains of dependent operations, so it
-// is held to at least kBoundedWaves waves per SIMD to hide their latency.
-constexpr int kBoundedWaves = 5;
+// is held to at least kBoundedWaves waves per SIMD to hide their latency
+// (fewer in FP64, whose values take two registers each).
+template <typename T>
+constexpr int kBoundedWaves = std::is_same<T, float>::value ? 5 : 3;
 
-template <bool DROP>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kBoundedWaves)))
+template <typename T, bool DROP>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kBoundedWaves<T>)))
 void render_bounded_kernel(const RenderArgs a) {
-    render_body<float, false, DROP, true>(a);
+    render_body<T, false, DROP, true>(a);
 }
 
 // ------------------------------------------------------------------ per-word kernel
@@ -1267,16 +1309,14 @@ static hipError_t launch_render_t(const RenderJob& job, hipStream_t s) {
         a.n_units = job.n_units;
         const size_t n_tail = 4 * (size_t)job.sp.R1;
         const bool ldsh = job.hist_mode == KL_HIST_LDS;
-        const bool bounded = std::is_same<T, float>::value && job.bounded && !ldsh && job.sp.r >= 4;
+        const bool bounded = job.bounded && !ldsh && job.sp.r >= 4;
         const size_t lds = ((n_tail * 2 * sizeof(cpx<T>) + 15) & ~size_t(15)) + 4 * sizeof(m64) +
                            (ldsh ? (kBlock / kWave) * kTile * kTile * sizeof(uint32_t) : 0) +
-                           (bounded ? n_tail / kNodeWords * sizeof(NodeDisk) + (kBlock / kWave) * kQueue * 2 : 0);
+                           (bounded ? n_tail / kNodeWords * sizeof(NodeDisk<T>) + (kBlock / kWave) * kQueue * 2 : 0);
         const bool drop = job.dropped != nullptr;
         void (*kern)(RenderArgs) = ldsh ? (drop ? render_kernel<T, true, true> : render_kernel<T, true, false>)
                                         : (drop ? render_kernel<T, false, true> : render_kernel<T, false, false>);
-        if constexpr (std::is_same<T, float>::value) {
-            if (bounded) kern = drop ? render_bounded_kernel<true> : render_bounded_kernel<false>;
-        }
+        if (bounded) kern = drop ? render_bounded_kernel<T, true> : render_bounded_kernel<T, false>;
         const void* fn = reinterpret_cast<const void*>(kern);
         if (lds > 65536) {
             hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

@@ -54,17 +54,19 @@ def _bins_from_pixels(px, py, win):
 
 # tail_len 4 gives depths 12 and 13 enough heads for the persistent kernel,
 # which alone takes block bounds
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
 @pytest.mark.parametrize("depth,win,tl", [(18, WIN_C2, 0), (14, WIN_C2, 0), (13, WIN_ZOOM, 4), (12, WIN_64, 4),
                                           (13, WIN_ANISO, 4)],
                          ids=["d18", "d14", "d13_zoom", "d12_64", "d13_aniso"])
-def test_bounded_equals_per_word(depth, win, tl):
-    img, drop = _assert_same(lambda **kw: kl.render(*C2, depth, win, tail_len=tl, **kw))
+def test_bounded_equals_per_word(depth, win, tl, precision):
+    img, drop = _assert_same(lambda **kw: kl.render(*C2, depth, win, tail_len=tl, precision=precision, **kw))
     assert int(img.sum()) + drop == kl.num_words(depth)
 
 
 @pytest.mark.parametrize("seed", ["b", "A", "all"])
 def test_bounded_seed_modes(seed):
     _assert_same(lambda **kw: kl.render(*C2, 14, WIN_C2, seed=seed, **kw))
+    _assert_same(lambda **kw: kl.render(*C2, 14, WIN_C2, seed=seed, precision="fp64", **kw))
 
 
 @pytest.mark.parametrize("tail_len", [4, 5, 7, 8])
@@ -72,12 +74,15 @@ def test_bounded_tail_lengths(tail_len):
     _assert_same(lambda **kw: kl.render(*C2, 16, WIN_64, tail_len=tail_len, **kw))
 
 
-def test_bounded_equals_histogram_of_own_bins():
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_bounded_equals_histogram_of_own_bins(precision):
     depth, win, tl = 13, WIN_64, 4
     n = kl.num_words(depth)
     dropped = torch.zeros(1, dtype=torch.int64, device="cuda")
-    img = kl.as_u32(kl.render(*C2, depth, win, block_bounds=True, dropped=dropped, tail_len=tl)).astype(np.int64)
-    p = kl.eval_values(*C2, depth, np.arange(n, dtype=np.uint64), window=win, tail_len=tl).cpu().numpy()
+    img = kl.as_u32(kl.render(*C2, depth, win, block_bounds=True, dropped=dropped, tail_len=tl,
+                              precision=precision)).astype(np.int64)
+    p = kl.eval_values(*C2, depth, np.arange(n, dtype=np.uint64), window=win, tail_len=tl,
+                       precision=precision).cpu().numpy()
     ref, drop = _bins_from_pixels(p[:, 0], p[:, 1], win)
     np.testing.assert_array_equal(img, ref)
     assert int(dropped.item()) == drop
@@ -107,8 +112,7 @@ def test_bounded_group_with_heads_of_both_forms():
 
 
 def test_bounded_ignored_where_it_does_not_apply():
-    # FP64, the LDS tile histogram, a tiling render, and non-finite FP32 coordinates
-    _assert_same(lambda **kw: kl.render(*C2, 14, WIN_C2, precision="fp64", **kw))
+    # the LDS tile histogram, a tiling render, and non-finite FP32 coordinates
     _assert_same(lambda **kw: kl.render(*C2, 14, WIN_C2, hist_mode="lds", **kw))
     _assert_same(lambda **kw: kl.render(*C1, 10, wl.FUCHSIAN_TILING_D10.window.as_tuple(), min_depth=1, **kw))
     _assert_same(lambda **kw: kl.render(*C2, 12, (0.0, 1e-37, 0.0, 1e-37, 64, 64), **kw))
