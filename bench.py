@@ -287,6 +287,22 @@ def leg_bounded(args):
         res["speedup"] = round(res["per_word"]["ms"] / res["bounded"]["ms"], 2)
         assert res["images_equal"] and res["dropped_equal"], "block bounds changed the image"
         out[W.name if prec == "fp32" else W.name + "_fp64"] = res
+    # the batched renderer: the 256 parameter sets of depths 12..18 in one launch
+    ta, tb, depth = wl.batch256(seed=0)
+    win = wl.BATCH_WINDOW
+    words = sum(kl.num_words(int(d)) for d in depth)
+    res = {"words": words}
+    imgs = {}
+    for bounded in (False, True):
+        images = kl.new_image(win, len(ta))
+        ms = _time(lambda: kl.render_many(ta, tb, depth, win, images=images, block_bounds=bounded),
+                   max(2, args.steps // 8), 2)
+        res["bounded" if bounded else "per_word"] = {"ms": round(ms, 3), "gwords_per_s": round(words / ms / 1e6, 1)}
+        imgs[bounded] = images
+    res["images_equal"] = bool(torch.equal(imgs[False], imgs[True]))
+    res["speedup"] = round(res["per_word"]["ms"] / res["bounded"]["ms"], 2)
+    assert res["images_equal"], "block bounds changed a batched image"
+    out["batch256"] = res
     return out
 
 

@@ -147,10 +147,12 @@ typedef struct {
                              counted as dropped, one inside a single bin is
                              added to it, and only the others are evaluated
                              word by word.  Images and dropped counts are
-                             bit for bit those of 0.  Applies where the
-                             persistent renderer runs (renders of one depth
-                             whose whole heads number at least 128 x 64),
-                             FP32 or FP64, with tail_len >= 4 and
+                             bit for bit those of 0.  Applies where a
+                             persistent renderer runs: renders of one depth
+                             whose whole heads number at least 128 x 64,
+                             and the sets of kl_render_many and the depths
+                             and seeds of a tiling render that reach that
+                             size; FP32 or FP64, with tail_len >= 4 and
                              KL_HIST_RUNS or AUTO; ignored elsewhere. */
 } kl_opts;
 

@@ -788,6 +788,7 @@ static int render_sets(const std::vector<SetSpec>& specs, const kl_window* w, co
     job.max_tail = max_tail;
     job.force_homog = o.suffix_form;
     job.count_dropped = o.dropped_out != nullptr;
+    job.bounded = o.block_bounds;
     if (e == hipSuccess) e = launch_batch_tables(job, s);
     if (e == hipSuccess && np_sets) {
         BatchJob pj = job;

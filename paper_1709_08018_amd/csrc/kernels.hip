@@ -1430,6 +1430,7 @@ struct BatchArgs {
     Fold fold;
     uint32_t W, H;
     uint32_t table_bytes;          // LDS bytes of the largest suffix table (homogeneous form)
+    uint32_t max_nodes;            // block bounds: suffix nodes of the largest table
 };
 
 __device__ __forceinline__ void flush_drop(uint64_t& drop, uint64_t* dst) {
@@ -1446,12 +1447,15 @@ __device__ __forceinline__ void flush_drop(uint64_t& drop, uint64_t* dst) {
 // to another set.  The last unit of a set may be partial: waves past the
 // set's last head skip it, and the idle lanes of a partly filled wave walk a
 // valid head without binning.
-template <typename T, bool DROP>
+template <typename T, bool DROP, bool BOUNDED = false>
 __global__ __launch_bounds__(kBlock) void render_batch_kernel(const BatchArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     m64* G = (m64*)(smem + a.table_bytes);
     const uint64_t wid = threadIdx.x / kWave;
     const int lane = threadIdx.x & (kWave - 1);
+    // with BOUNDED: the set's node disks and one span queue per wave (bounded_unit)
+    NodeDisk<T>* nodes = (NodeDisk<T>*)(smem + a.table_bytes + 4 * sizeof(m64));
+    uint16_t* queue = (uint16_t*)(nodes + a.max_nodes) + wid * kQueue;
 
     int cur = -1;
     bool affine = true;
@@ -1493,6 +1497,13 @@ __global__ __launch_bounds__(kBlock) void render_batch_kernel(const BatchArgs a)
             const uint4* src = (const uint4*)(affine ? S.tab.tail : S.tail_homog);
             for (uint32_t i = threadIdx.x; i < (uint32_t)((bytes + 15) / 16); i += kBlock) ((uint4*)smem)[i] = src[i];
             if (threadIdx.x < 4) G[threadIdx.x] = S.gens.g[threadIdx.x];
+            if constexpr (BOUNDED) {
+                if (affine && sp.r >= 4) {
+                    __syncthreads();
+                    for (uint32_t q = threadIdx.x; q < S.n_tail / kNodeWords; q += kBlock)
+                        node_disk((const cpx<T>*)smem, q, nodes);
+                }
+            }
             __syncthreads();
         }
         const uint64_t wunit = (unit - base) * (kBlock / kWave) + wid;  // this wave's 64 heads of the set
@@ -1501,7 +1512,15 @@ __global__ __launch_bounds__(kBlock) void render_batch_kernel(const BatchArgs a)
         const bool partial = (wunit + 1) * kWave > sp.n_heads;
         if (!partial) {
             const Head<T> h = compute_head<T>(hidx, sp, prefix, plast, G, a.fold);
-            if (wave_needs_dual(h)) {
+            const bool dual = wave_needs_dual(h);
+            if constexpr (BOUNDED) {
+                if (affine && !dual && sp.r >= 4) {
+                    bounded_unit<T, DROP>(h, lane, smem, nodes, queue, sp.R1 / kNodeWords, a.W, a.H, image, s,
+                                          t_words);
+                    continue;
+                }
+            }
+            if (dual) {
                 if (affine) walk_tails<T, true, true>(h, smem, sp.R1, a.W, a.H, image, s, t_words);
                 else walk_tails<T, false, true>(h, smem, sp.R1, a.W, a.H, image, s, t_words);
             } else {
@@ -1539,13 +1558,22 @@ hipError_t launch_render_batch(const BatchJob& job, hipStream_t s) {
     a.W = job.width;
     a.H = job.height;
     a.table_bytes = job.table_bytes;
-    const size_t lds = (size_t)job.table_bytes + 4 * sizeof(m64);
+    const bool fp64 = job.precision == KL_PREC_FP64;
+    const size_t esz = fp64 ? sizeof(cpx<double>) : sizeof(cpx<float>);
+    // the largest table's suffix nodes (the table bytes hold its homogeneous form)
+    a.max_nodes = job.bounded ? (uint32_t)(job.table_bytes / (2 * esz) / kNodeWords) : 0u;
+    const size_t lds = (size_t)job.table_bytes + 4 * sizeof(m64) +
+                       (job.bounded ? (size_t)a.max_nodes * (fp64 ? sizeof(NodeDisk<double>) : sizeof(NodeDisk<float>)) +
+                                          (kBlock / kWave) * kQueue * 2
+                                    : 0);
     uint32_t grid = (uint32_t)std::min<uint64_t>(job.total_units, (uint64_t)job.grid_blocks);
     if (grid < 1) grid = 1;
     const bool drop = job.count_dropped != 0;
-    void (*kern)(BatchArgs) = job.precision == KL_PREC_FP64
-                                  ? (drop ? render_batch_kernel<double, true> : render_batch_kernel<double, false>)
-                                  : (drop ? render_batch_kernel<float, true> : render_batch_kernel<float, false>);
+    void (*kern)(BatchArgs) =
+        job.bounded ? (fp64 ? (drop ? render_batch_kernel<double, true, true> : render_batch_kernel<double, false, true>)
+                            : (drop ? render_batch_kernel<float, true, true> : render_batch_kernel<float, false, true>))
+                    : (fp64 ? (drop ? render_batch_kernel<double, true> : render_batch_kernel<double, false>)
+                            : (drop ? render_batch_kernel<float, true> : render_batch_kernel<float, false>));
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

@@ -174,6 +174,7 @@ struct BatchJob {
     uint32_t max_prefix, max_tail; // largest n_prefix / n_tail over the sets
     int force_homog;
     int count_dropped;             // the sets' dropped counters are set
+    int bounded;                   // block bounds in the persistent batch kernel (kl_opts::block_bounds)
 };
 hipError_t launch_batch_tables(const BatchJob& job, hipStream_t s);
 hipError_t launch_render_batch(const BatchJob& job, hipStream_t s);

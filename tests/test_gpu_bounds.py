@@ -111,8 +111,22 @@ def test_bounded_group_with_heads_of_both_forms():
     _assert_same(lambda **kw: kl.render(*C1, 14, wl.FUCHSIAN_TILING_D10.window.as_tuple(), **kw))
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_bounded_batched_and_tiling_renders(precision):
+    """The batched renderer takes block bounds for its persistent sets:
+    kl_render_many and whole tiling renders equal their per-word images."""
+    ta, tb, _ = wl.draw_param_sets(6, seed=11)
+    depths = [14, 15, 16, 14, 13, 17]
+    win = (-2.0, 2.0, -2.0, 2.0, 128, 128)
+    a = kl.render_many(ta, tb, depths, win, precision=precision)
+    b = kl.render_many(ta, tb, depths, win, precision=precision, block_bounds=True)
+    assert torch.equal(a, b)
+    _assert_same(lambda **kw: kl.render(*C2, 15, WIN_C2, min_depth=1, precision=precision, **kw))
+    _assert_same(lambda **kw: kl.render(*C2, 14, WIN_C2, min_depth=1, seed="all", precision=precision, **kw))
+
+
 def test_bounded_ignored_where_it_does_not_apply():
-    # the LDS tile histogram, a tiling render, and non-finite FP32 coordinates
+    # the LDS tile histogram, a small tiling render (per-word kernel), and non-finite FP32 coordinates
     _assert_same(lambda **kw: kl.render(*C2, 14, WIN_C2, hist_mode="lds", **kw))
     _assert_same(lambda **kw: kl.render(*C1, 10, wl.FUCHSIAN_TILING_D10.window.as_tuple(), min_depth=1, **kw))
     _assert_same(lambda **kw: kl.render(*C2, 12, (0.0, 1e-37, 0.0, 1e-37, 64, 64), **kw))
