@@ -38,6 +38,7 @@ FLOPS_PER_WORD = 16
 # FP32-equivalent flops (FP64 at half the FP32 rate)
 SURVEY_FP32_EQUIV_FLOPS_PER_WORD = 252 + 2 * 45
 FP32_PEAK_TFLOPS = 157.3  # MI355X FP32 vector peak (counts packed FMA)
+FP64_PEAK_TFLOPS = 78.6   # MI355X FP64 vector peak
 EVENT_EVERY = 10
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "render_kernel_quasifuchsian_d18_pmc.txt")
 VALU_SUMMARY = os.path.join(ROOT, "profiles", "render_kernel_quasifuchsian_d18_valu.txt")
@@ -214,11 +215,19 @@ def leg_d22(args):
         ms = _time(run, max(1, args.steps // 4), 1)
         h = kl.as_u32(image).astype(np.int64)
         assert int(h.sum()) + int(dropped.item()) == n
-        res[prec] = {"ms": round(ms, 3), "gwords_per_s": round(n / ms / 1e6, 2), "max_bin": int(h.max())}
+        res[prec] = {"ms": round(ms, 3), "gwords_per_s": round(n / ms / 1e6, 2), "max_bin": int(h.max()),
+                     "valu_frac": _valu_frac(n, ms, prec)}
     idx = wl.sample_indices(n, 1_000_000, seed=0)
     p = kl.eval_values(W.ta, W.tb, W.depth, idx, precision="fp32", window=W.window).cpu().numpy()
     return {"workload": W.name, "words": n, "chunks": chunks, **res,
             "cpu_baseline": cpu_baseline_d22(W, idx, p)}
+
+
+def _valu_frac(words, ms, precision):
+    """FLOPS_PER_WORD x words in ms, as a fraction of the vector peak of the
+    precision the suffix points are mapped in."""
+    peak = FP64_PEAK_TFLOPS if precision == "fp64" else FP32_PEAK_TFLOPS
+    return {"of_peak_tflops": peak, "frac": round(FLOPS_PER_WORD * words / (ms * 1e-3) / 1e12 / peak, 4)}
 
 
 def _kernel_ms(render, reps):
@@ -280,6 +289,8 @@ def leg_bounded(args):
             res[key] = {"ms": round(ms, 4), "gwords_per_s": round(n / ms / 1e6, 1)}
             if chunks == 1:
                 res[key]["kernel_ms"] = round(_kernel_ms(lambda **kw: run(**kw), steps), 4)
+                if not bounded:
+                    res[key]["kernel_valu_frac"] = _valu_frac(n, res[key]["kernel_ms"], prec)
             run(dropped=dropped)
             imgs[bounded] = (kl.as_u32(image).astype(np.int64), int(dropped.item()))
         res["images_equal"] = bool(np.array_equal(imgs[False][0], imgs[True][0]))
