@@ -100,9 +100,16 @@ __device__ inline uint64_t decode_packed(uint64_t index, int n) {
 // (previous letter, six digits) to the next six letters, 2 bits each.  A
 // shorter last group is padded with zero digits at its end, whose letters
 // are not kept.  Words are staged in LDS 256 at a time and written as one
-// contiguous byte range per tile: 16-byte stores where the destination is
-// aligned, byte stores otherwise.
+// contiguous byte range per tile.  For depths 16 .. 32 into a 16-byte
+// aligned destination a word is staged packed, 2 bits a letter in 64 bits,
+// and each thread forms 16-byte pieces of the tile's output, each from the
+// at most two words it covers; otherwise words are staged byte by byte.
 constexpr uint32_t kDigitGroup = 729;   // 3^6
+
+// Four letters, 2 bits each in b (< 256), as four bytes.
+__device__ __forceinline__ uint32_t spread_letters(uint32_t b) {
+    return (b | (b << 6) | (b << 12) | (b << 18)) & 0x03030303u;
+}
 
 __device__ __forceinline__ void put_letters(uint64_t& lo, uint64_t& hi, int pos, uint64_t bits) {
     const int sh = 2 * pos;   // pos <= 39, bits < 2^12
@@ -118,10 +125,17 @@ __device__ __forceinline__ uint8_t letter_at(uint64_t lo, uint64_t hi, int j) {
     return (uint8_t)((j < 32 ? lo >> (2 * j) : hi >> (2 * j - 64)) & 3u);
 }
 
+// K consecutive words per thread, a tile of 256 K words per workgroup.  With
+// PACK (depths 16 .. 32, 16-byte aligned destination) a thread unranks its
+// first word and steps to the next ones by adding one to the digit groups,
+// and words are staged packed; otherwise K = 1 and words are staged as bytes.
+template <int K, bool PACK>
 __global__ __launch_bounds__(256) void decode_kernel(uint64_t first, uint64_t count, int depth,
-                                                     uint8_t* __restrict__ out) {
+                                                     uint8_t* __restrict__ out, uint32_t div_magic) {
+    constexpr uint32_t kTileWords = 256u * K;
     __shared__ uint16_t next6[4 * kDigitGroup];
-    __shared__ __align__(16) uint8_t stage[256 * KL_MAX_DEPTH];
+    __shared__ __align__(16) uint8_t stage[PACK ? kTileWords * 8 : 256 * KL_MAX_DEPTH];
+    uint64_t* packed = (uint64_t*)stage;   // PACK: the tile's words, 2 bits a letter
     const int tid = threadIdx.x;
     for (uint32_t e = tid; e < 4 * kDigitGroup; e += 256) {
         int prev = (int)(e / kDigitGroup);
@@ -145,13 +159,15 @@ __global__ __launch_bounds__(256) void decode_kernel(uint64_t first, uint64_t co
     uint32_t pow_p = 1;
     for (int j = 0; j < p; ++j) pow_p *= 3;
     const uint32_t pad = kDigitGroup / pow_p;   // 3^(6 - p)
-    const uint64_t tiles = (count + 255) / 256;
+    const uint64_t tiles = (count + kTileWords - 1) / kTileWords;
     for (uint64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
-        const uint64_t tfirst = tile * 256;
+        const uint64_t tfirst = tile * kTileWords;
         const uint64_t rem = count - tfirst;
-        const int nw = rem < 256 ? (int)rem : 256;
-        if (tid < nw) {
-            uint64_t r = first + tfirst + tid;
+        const uint32_t nw = rem < kTileWords ? (uint32_t)rem : kTileWords;
+        uint8_t* dst = out + tfirst * (uint64_t)depth;
+        const uint32_t w0 = (uint32_t)tid * K;   // this thread's first word in the tile
+        if (w0 < nw) {
+            uint64_t r = first + tfirst + w0;
             uint32_t last = 0;
             if (p) {
                 uint64_t q = r;
@@ -169,29 +185,75 @@ __global__ __launch_bounds__(256) void decode_kernel(uint64_t first, uint64_t co
                     r = q;
                 }
             }
-            int prev = (int)(r & 3u);   // the first letter
-            uint64_t lo = (uint64_t)prev, hi = 0;
-            int pos = 1;
+            uint32_t f = (uint32_t)r;   // the first letter
 #pragma unroll
-            for (int k = 5; k >= 0; --k) {
-                if (k < groups) {
-                    const uint32_t bits = next6[prev * kDigitGroup + g[k]];
-                    put_letters(lo, hi, pos, bits);
-                    prev = (int)(bits >> 10);
-                    pos += 6;
+            for (int k = 0; k < K; ++k) {
+                if (w0 + (uint32_t)k < nw) {   // an index below first + count: f <= 3
+                    int prev = (int)f;
+                    uint64_t lo = (uint64_t)prev, hi = 0;
+                    int pos = 1;
+#pragma unroll
+                    for (int kk = 5; kk >= 0; --kk) {
+                        if (kk < groups) {
+                            const uint32_t bits = next6[prev * kDigitGroup + g[kk]];
+                            put_letters(lo, hi, pos, bits);
+                            prev = (int)(bits >> 10);
+                            pos += 6;
+                        }
+                    }
+                    if (p) {
+                        const uint32_t bits = next6[prev * kDigitGroup + last * pad] & ((1u << (2 * p)) - 1u);
+                        put_letters(lo, hi, pos, bits);
+                    }
+                    if constexpr (PACK) {
+                        packed[w0 + k] = lo;
+                    } else {
+                        uint8_t* w = stage + (w0 + k) * depth;
+                        for (int j = 0; j < depth; ++j) w[j] = letter_at(lo, hi, j);
+                    }
+                }
+                if (k + 1 < K) {
+                    // the next index: add one to the digit groups
+                    uint32_t c = 1;
+                    if (p) {
+                        last += 1;
+                        c = last == pow_p ? 1u : 0u;
+                        if (c) last = 0;
+                    }
+#pragma unroll
+                    for (int kk = 0; kk < 6; ++kk) {
+                        if (kk < groups) {
+                            const uint32_t v = g[kk] + c;
+                            c = v == kDigitGroup ? 1u : 0u;
+                            g[kk] = c ? 0u : v;
+                        }
+                    }
+                    f += c;
                 }
             }
-            if (p) {
-                const uint32_t bits = next6[prev * kDigitGroup + last * pad] & ((1u << (2 * p)) - 1u);
-                put_letters(lo, hi, pos, bits);
-            }
-            uint8_t* w = stage + tid * depth;
-            for (int j = 0; j < depth; ++j) w[j] = letter_at(lo, hi, j);
         }
         __syncthreads();
-        const uint32_t nbytes = (uint32_t)nw * (uint32_t)depth;
-        uint8_t* dst = out + tfirst * (uint64_t)depth;
-        if (((uintptr_t)dst & 15u) == 0) {
+        const uint32_t nbytes = nw * (uint32_t)depth;
+        if constexpr (PACK) {
+            // byte B of the tile is letter B - w d of word w = B / d (div_magic:
+            // exact for B < 2^16); a piece starting in word w ends in w or w + 1
+            const uint32_t n16 = nbytes / 16;
+            for (uint32_t i = tid; i < n16; i += 256) {
+                const uint32_t B = 16 * i;
+                const uint32_t w = __umulhi(B, div_magic);
+                const uint32_t o = B - w * (uint32_t)depth;
+                const uint32_t rest = (uint32_t)depth - o;   // letters of word w in the piece
+                uint64_t L = packed[w] >> (2 * o);
+                if (rest < 16) L |= packed[w + 1] << (2 * rest);
+                const uint32_t x = (uint32_t)L;
+                ((uint4*)dst)[i] = make_uint4(spread_letters(x & 0xFFu), spread_letters((x >> 8) & 0xFFu),
+                                              spread_letters((x >> 16) & 0xFFu), spread_letters(x >> 24));
+            }
+            for (uint32_t b = n16 * 16 + tid; b < nbytes; b += 256) {
+                const uint32_t w = __umulhi(b, div_magic);
+                dst[b] = (uint8_t)((packed[w] >> (2 * (b - w * (uint32_t)depth))) & 3u);
+            }
+        } else if (((uintptr_t)dst & 15u) == 0) {
             const uint32_t n16 = nbytes / 16;
             for (uint32_t i = tid; i < n16; i += 256) ((uint4*)dst)[i] = ((const uint4*)stage)[i];
             for (uint32_t i = n16 * 16 + tid; i < nbytes; i += 256) dst[i] = stage[i];
@@ -204,9 +266,26 @@ __global__ __launch_bounds__(256) void decode_kernel(uint64_t first, uint64_t co
 
 hipError_t launch_decode(uint64_t first, uint64_t count, int depth, uint8_t* out, hipStream_t s) {
     if (count == 0) return hipSuccess;
-    const uint64_t tiles = (count + 255) / 256;
-    const uint64_t blocks = std::min<uint64_t>(tiles, (uint64_t)device_cu_count() * 8);
-    hipLaunchKernelGGL(decode_kernel, dim3((unsigned)blocks), dim3(256), 0, s, first, count, depth, out);
+    const bool pack = depth >= 16 && depth <= 32 && ((uintptr_t)out & 15u) == 0;
+    const uint64_t tile_words = pack ? 2048 : 256;
+    const uint64_t tiles = (count + tile_words - 1) / tile_words;
+    // as many workgroups as fit on a CU at once, so that none waits for a
+    // second round (the same on every gfx950 device; asked once per variant)
+    auto fits = [](const void* fn) {
+        int n = 0;
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, 256, 0) == hipSuccess && n > 0 ? n : 1;
+    };
+    static const int fits_pack = fits(reinterpret_cast<const void*>(decode_kernel<8, true>));
+    static const int fits_bytes = fits(reinterpret_cast<const void*>(decode_kernel<1, false>));
+    const int resident = pack ? fits_pack : fits_bytes;
+    const uint64_t blocks = std::min<uint64_t>(tiles, (uint64_t)device_cu_count() * (uint64_t)resident);
+    const uint32_t div_magic = 0xFFFFFFFFu / (uint32_t)depth + 1u;   // B / depth = umulhi(B, div_magic), B < 2^16
+    if (pack)
+        hipLaunchKernelGGL((decode_kernel<8, true>), dim3((unsigned)blocks), dim3(256), 0, s, first, count, depth, out,
+                           div_magic);
+    else
+        hipLaunchKernelGGL((decode_kernel<1, false>), dim3((unsigned)blocks), dim3(256), 0, s, first, count, depth,
+                           out, div_magic);
     return hipGetLastError();
 }
 
