@@ -186,24 +186,41 @@ __global__ __launch_bounds__(256) void decode_kernel(uint64_t first, uint64_t co
                 }
             }
             uint32_t f = (uint32_t)r;   // the first letter
+            // The lowest group (the last p digits, or g[0] when p = 0) changes
+            // from one word to the next; the letters above it are kept until a
+            // carry leaves it.
+            const int low = p ? 0 : 1;   // groups kk >= low lie above the lowest group
+            uint64_t plo = 0, phi = 0;
+            int pprev = 0, ppos = 0;
+            bool stale = true;
 #pragma unroll
             for (int k = 0; k < K; ++k) {
                 if (w0 + (uint32_t)k < nw) {   // an index below first + count: f <= 3
-                    int prev = (int)f;
-                    uint64_t lo = (uint64_t)prev, hi = 0;
-                    int pos = 1;
+                    if (stale) {
+                        int prev = (int)f;
+                        uint64_t lo = (uint64_t)prev, hi = 0;
+                        int pos = 1;
 #pragma unroll
-                    for (int kk = 5; kk >= 0; --kk) {
-                        if (kk < groups) {
-                            const uint32_t bits = next6[prev * kDigitGroup + g[kk]];
-                            put_letters(lo, hi, pos, bits);
-                            prev = (int)(bits >> 10);
-                            pos += 6;
+                        for (int kk = 5; kk >= 0; --kk) {
+                            if (kk < groups && kk >= low) {
+                                const uint32_t bits = next6[prev * kDigitGroup + g[kk]];
+                                put_letters(lo, hi, pos, bits);
+                                prev = (int)(bits >> 10);
+                                pos += 6;
+                            }
                         }
+                        plo = lo;
+                        phi = hi;
+                        pprev = prev;
+                        ppos = pos;
+                        stale = false;
                     }
+                    uint64_t lo = plo, hi = phi;
                     if (p) {
-                        const uint32_t bits = next6[prev * kDigitGroup + last * pad] & ((1u << (2 * p)) - 1u);
-                        put_letters(lo, hi, pos, bits);
+                        const uint32_t bits = next6[pprev * kDigitGroup + last * pad] & ((1u << (2 * p)) - 1u);
+                        put_letters(lo, hi, ppos, bits);
+                    } else if (groups > 0) {
+                        put_letters(lo, hi, ppos, next6[pprev * kDigitGroup + g[0]]);
                     }
                     if constexpr (PACK) {
                         packed[w0 + k] = lo;
@@ -219,6 +236,7 @@ __global__ __launch_bounds__(256) void decode_kernel(uint64_t first, uint64_t co
                         last += 1;
                         c = last == pow_p ? 1u : 0u;
                         if (c) last = 0;
+                        stale = stale || c;
                     }
 #pragma unroll
                     for (int kk = 0; kk < 6; ++kk) {
@@ -226,8 +244,10 @@ __global__ __launch_bounds__(256) void decode_kernel(uint64_t first, uint64_t co
                             const uint32_t v = g[kk] + c;
                             c = v == kDigitGroup ? 1u : 0u;
                             g[kk] = c ? 0u : v;
+                            if (kk == 0 && !p) stale = stale || c;
                         }
                     }
+                    if (groups == 0 && !p) stale = true;
                     f += c;
                 }
             }
