@@ -62,6 +62,38 @@ def test_decode_sampled_ranges(depth):
             np.testing.assert_array_equal(got[j], O.unrank(first + j, depth))
 
 
+@pytest.mark.parametrize("depth", list(range(16, 33)))
+def test_decode_packed_path_every_word_of_ranges(depth):
+    """Depths 16..32 into an aligned destination take the packed staging, eight
+    consecutive words a thread stepped by carries through the digit groups:
+    ranges that start just before a carry out of the lowest group and out of
+    the next one, that cross tiles of 2048 words, and that end at the last
+    word, every word against the oracle's enumeration; the same range into an
+    unaligned destination (byte staging) gives the same bytes."""
+    n = kl.num_words(depth)
+    p = (depth - 1) % 6
+    low = 3 ** p if p else 729              # radix of the lowest digit group
+    starts = [0, low - 5, low * 729 - 11, 3 * low * 729 - 2, n // 3 + 7, n - 4101]
+    counts = [4101, 37, 2049, 300, 2048, 4101]
+    def oracle_words(first, count):
+        # the oracle's unranking word by word (its depth-first enumeration
+        # walks every word before `first`)
+        return np.stack([O.unrank(first + j, depth) for j in range(count)])
+
+    for first, count in zip(starts, counts):
+        first = max(0, min(first, n - 1))
+        count = min(count, n - first)
+        got = kl.decode(first, count, depth).cpu().numpy()
+        np.testing.assert_array_equal(got, oracle_words(first, count))
+    first, count = n // 5, 3001
+    buf = torch.full((count * depth + 16,), 255, dtype=torch.uint8, device="cuda")
+    view = buf[3:3 + count * depth]
+    kl._check(kl.lib().kl_decode_ex(first, count, depth, view.data_ptr(), kl._stream(None)))
+    host = buf.cpu().numpy()
+    np.testing.assert_array_equal(host[3:3 + count * depth].reshape(count, depth), oracle_words(first, count))
+    assert (host[:3] == 255).all() and (host[3 + count * depth:] == 255).all()
+
+
 def test_decode_misaligned_destination():
     depth = 7
     n = kl.num_words(depth)
