@@ -23,7 +23,10 @@
 // pole form of the head (compute_head, word_value below), which every
 // kernel shares.
 #include <algorithm>
+#include <array>
+#include <atomic>
 #include <type_traits>
+#include <utility>
 
 #include "kl_internal.hpp"
 
@@ -129,9 +132,13 @@ __device__ __forceinline__ uint8_t letter_at(uint64_t lo, uint64_t hi, int j) {
 // PACK (depths 16 .. 32, 16-byte aligned destination) a thread unranks its
 // first word and steps to the next ones by adding one to the digit groups,
 // and words are staged packed; otherwise K = 1 and words are staged as bytes.
-template <int K, bool PACK>
-__global__ __launch_bounds__(256) void decode_kernel(uint64_t first, uint64_t count, int depth,
+// D > 0 fixes the depth at compile time (the packed path has one kernel per
+// depth, so its digit groups, shifts and divisions are constants); D = 0
+// takes it from the argument.
+template <int K, bool PACK, int D = 0>
+__global__ __launch_bounds__(256) void decode_kernel(uint64_t first, uint64_t count, int depth_arg,
                                                      uint8_t* __restrict__ out, uint32_t div_magic) {
+    const int depth = D ? D : depth_arg;
     constexpr uint32_t kTileWords = 256u * K;
     __shared__ uint16_t next6[4 * kDigitGroup];
     __shared__ __align__(16) uint8_t stage[PACK ? kTileWords * 8 : 256 * KL_MAX_DEPTH];
@@ -260,7 +267,7 @@ __global__ __launch_bounds__(256) void decode_kernel(uint64_t first, uint64_t co
             const uint32_t n16 = nbytes / 16;
             for (uint32_t i = tid; i < n16; i += 256) {
                 const uint32_t B = 16 * i;
-                const uint32_t w = __umulhi(B, div_magic);
+                const uint32_t w = D ? B / (uint32_t)D : __umulhi(B, div_magic);
                 const uint32_t o = B - w * (uint32_t)depth;
                 const uint32_t rest = (uint32_t)depth - o;   // letters of word w in the piece
                 uint64_t L = packed[w] >> (2 * o);
@@ -270,7 +277,7 @@ __global__ __launch_bounds__(256) void decode_kernel(uint64_t first, uint64_t co
                                               spread_letters((x >> 16) & 0xFFu), spread_letters(x >> 24));
             }
             for (uint32_t b = n16 * 16 + tid; b < nbytes; b += 256) {
-                const uint32_t w = __umulhi(b, div_magic);
+                const uint32_t w = D ? b / (uint32_t)D : __umulhi(b, div_magic);
                 dst[b] = (uint8_t)((packed[w] >> (2 * (b - w * (uint32_t)depth))) & 3u);
             }
         } else if (((uintptr_t)dst & 15u) == 0) {
@@ -284,29 +291,36 @@ __global__ __launch_bounds__(256) void decode_kernel(uint64_t first, uint64_t co
     }
 }
 
+using DecodeKernel = void (*)(uint64_t, uint64_t, int, uint8_t*, uint32_t);
+
+template <int... I>
+static constexpr std::array<DecodeKernel, sizeof...(I)> packed_decode_kernels(std::integer_sequence<int, I...>) {
+    return {{decode_kernel<8, true, 16 + I>...}};
+}
+
 hipError_t launch_decode(uint64_t first, uint64_t count, int depth, uint8_t* out, hipStream_t s) {
     if (count == 0) return hipSuccess;
+    static constexpr std::array<DecodeKernel, 17> kPacked = packed_decode_kernels(std::make_integer_sequence<int, 17>{});
     const bool pack = depth >= 16 && depth <= 32 && ((uintptr_t)out & 15u) == 0;
+    const DecodeKernel fn = pack ? kPacked[depth - 16] : decode_kernel<1, false>;
     const uint64_t tile_words = pack ? 2048 : 256;
     const uint64_t tiles = (count + tile_words - 1) / tile_words;
     // as many workgroups as fit on a CU at once, so that none waits for a
-    // second round (the same on every gfx950 device; asked once per variant)
-    auto fits = [](const void* fn) {
+    // second round (the same on every gfx950 device; asked once per kernel)
+    static std::atomic<int> fits[18];
+    const int slot = pack ? depth - 16 : 17;
+    int resident = fits[slot].load(std::memory_order_relaxed);
+    if (resident == 0) {
         int n = 0;
-        return hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, 256, 0) == hipSuccess && n > 0 ? n : 1;
-    };
-    static const int fits_pack = fits(reinterpret_cast<const void*>(decode_kernel<8, true>));
-    static const int fits_bytes = fits(reinterpret_cast<const void*>(decode_kernel<1, false>));
-    const int resident = pack ? fits_pack : fits_bytes;
+        resident = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(fn), 256, 0) ==
+                                   hipSuccess && n > 0 ? n : 1;
+        fits[slot].store(resident, std::memory_order_relaxed);
+    }
     const uint64_t blocks = std::min<uint64_t>(tiles, (uint64_t)device_cu_count() * (uint64_t)resident);
-    const uint32_t div_magic = 0xFFFFFFFFu / (uint32_t)depth + 1u;   // B / depth = umulhi(B, div_magic), B < 2^16
-    if (pack)
-        hipLaunchKernelGGL((decode_kernel<8, true>), dim3((unsigned)blocks), dim3(256), 0, s, first, count, depth, out,
-                           div_magic);
-    else
-        hipLaunchKernelGGL((decode_kernel<1, false>), dim3((unsigned)blocks), dim3(256), 0, s, first, count, depth,
-                           out, div_magic);
-    return hipGetLastError();
+    uint32_t div_magic = 0xFFFFFFFFu / (uint32_t)depth + 1u;   // B / depth = umulhi(B, div_magic), B < 2^16
+    void* args[] = {&first, &count, &depth, &out, &div_magic};
+    hipError_t e = hipLaunchKernel(reinterpret_cast<const void*>(fn), dim3((unsigned)blocks), dim3(256), args, 0, s);
+    return e != hipSuccess ? e : hipGetLastError();
 }
 
 // ------------------------------------------------------------------ prefix table
