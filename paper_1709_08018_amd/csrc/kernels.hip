@@ -137,7 +137,8 @@ __device__ __forceinline__ uint8_t letter_at(uint64_t lo, uint64_t hi, int j) {
 // takes it from the argument.
 template <int K, bool PACK, int D = 0>
 __global__ __launch_bounds__(256) void decode_kernel(uint64_t first, uint64_t count, int depth_arg,
-                                                     uint8_t* __restrict__ out, uint32_t div_magic) {
+                                                     uint8_t* __restrict__ out) {
+    static_assert(!PACK || (D >= 16 && D <= 32), "the packed staging takes a fixed depth of 16 .. 32");
     const int depth = D ? D : depth_arg;
     constexpr uint32_t kTileWords = 256u * K;
     __shared__ uint16_t next6[4 * kDigitGroup];
@@ -262,12 +263,12 @@ __global__ __launch_bounds__(256) void decode_kernel(uint64_t first, uint64_t co
         __syncthreads();
         const uint32_t nbytes = nw * (uint32_t)depth;
         if constexpr (PACK) {
-            // byte B of the tile is letter B - w d of word w = B / d (div_magic:
-            // exact for B < 2^16); a piece starting in word w ends in w or w + 1
+            // byte B of the tile is letter B - w d of word w = B / d; a piece
+            // starting in word w ends in w or w + 1
             const uint32_t n16 = nbytes / 16;
             for (uint32_t i = tid; i < n16; i += 256) {
                 const uint32_t B = 16 * i;
-                const uint32_t w = D ? B / (uint32_t)D : __umulhi(B, div_magic);
+                const uint32_t w = B / (uint32_t)D;
                 const uint32_t o = B - w * (uint32_t)depth;
                 const uint32_t rest = (uint32_t)depth - o;   // letters of word w in the piece
                 uint64_t L = packed[w] >> (2 * o);
@@ -277,7 +278,7 @@ __global__ __launch_bounds__(256) void decode_kernel(uint64_t first, uint64_t co
                                               spread_letters((x >> 16) & 0xFFu), spread_letters(x >> 24));
             }
             for (uint32_t b = n16 * 16 + tid; b < nbytes; b += 256) {
-                const uint32_t w = D ? b / (uint32_t)D : __umulhi(b, div_magic);
+                const uint32_t w = b / (uint32_t)D;
                 dst[b] = (uint8_t)((packed[w] >> (2 * (b - w * (uint32_t)depth))) & 3u);
             }
         } else if (((uintptr_t)dst & 15u) == 0) {
@@ -291,7 +292,7 @@ __global__ __launch_bounds__(256) void decode_kernel(uint64_t first, uint64_t co
     }
 }
 
-using DecodeKernel = void (*)(uint64_t, uint64_t, int, uint8_t*, uint32_t);
+using DecodeKernel = void (*)(uint64_t, uint64_t, int, uint8_t*);
 
 template <int... I>
 static constexpr std::array<DecodeKernel, sizeof...(I)> packed_decode_kernels(std::integer_sequence<int, I...>) {
@@ -317,8 +318,7 @@ hipError_t launch_decode(uint64_t first, uint64_t count, int depth, uint8_t* out
         fits[slot].store(resident, std::memory_order_relaxed);
     }
     const uint64_t blocks = std::min<uint64_t>(tiles, (uint64_t)device_cu_count() * (uint64_t)resident);
-    uint32_t div_magic = 0xFFFFFFFFu / (uint32_t)depth + 1u;   // B / depth = umulhi(B, div_magic), B < 2^16
-    void* args[] = {&first, &count, &depth, &out, &div_magic};
+    void* args[] = {&first, &count, &depth, &out};
     hipError_t e = hipLaunchKernel(reinterpret_cast<const void*>(fn), dim3((unsigned)blocks), dim3(256), args, 0, s);
     return e != hipSuccess ? e : hipGetLastError();
 }
