@@ -377,6 +377,38 @@ def test_full_quasifuchsian_d18_invariants_and_samples():
     assert np.hypot(p[ok, 0] - fx[ok], p[ok, 1] - fy[ok]).max() <= 0.25
 
 
+def test_full_batch256_invariants_and_samples():
+    """The batched workload at its full size, in the launch the benchmark
+    times: 256 parameter sets of depths 12..18, 512 x 512 each, one
+    kl_render_many.  Every image holds its set's words exactly (bins plus
+    dropped words); a depth-18 set and a depth-12 set equal their single
+    renders bit for bit; and on four sets, sampled words the renderer bins
+    are counted where its own arithmetic puts them, within 0.25 px of the
+    oracle's FP64 value."""
+    ta, tb, depth = wl.batch256(seed=0)
+    win = wl.BATCH_WINDOW.as_tuple()
+    dropped = torch.zeros(len(ta), dtype=torch.int64, device="cuda")
+    imgs = kl.render_many(ta, tb, depth, win, dropped=dropped)
+    sums = kl.as_u32(imgs).astype(np.int64).reshape(len(ta), -1).sum(axis=1)
+    drops = dropped.cpu().numpy()
+    for i in range(len(ta)):
+        assert int(sums[i]) + int(drops[i]) == kl.num_words(int(depth[i])), i
+    picks = [int(np.argmax(depth)), int(np.argmin(depth)), 17, 200]
+    for i in picks[:2]:
+        single = kl.render(ta[i], tb[i], int(depth[i]), win)
+        assert torch.equal(imgs[i], single), i
+    for i in picks:
+        d = int(depth[i])
+        h = kl.as_u32(imgs[i]).astype(np.int64)
+        idx = wl.sample_indices(kl.num_words(d), 4000, seed=i)
+        pnt = kl.eval_values(ta[i], tb[i], d, idx, window=win).cpu().numpy()
+        fx, fy = _ref_pixels(O.eval_values(complex(ta[i]), complex(tb[i]), d, idx), win)
+        ok = ~np.signbit(pnt[:, 0]) & (pnt[:, 0] < win[4]) & ~np.signbit(pnt[:, 1]) & (pnt[:, 1] < win[5])
+        rows, cols = np.floor(pnt[ok, 1]).astype(int), np.floor(pnt[ok, 0]).astype(int)
+        assert (h[rows, cols] > 0).all(), i
+        assert np.hypot(pnt[ok, 0] - fx[ok], pnt[ok, 1] - fy[ok]).max() <= 0.25, i
+
+
 def test_autotune_keeps_eval_and_render_consistent():
     depth, win = 11, WIN_C2
     plan, ms = kl.autotune(*C2, depth, win)
