@@ -94,6 +94,26 @@ def test_decode_packed_path_every_word_of_ranges(depth):
     assert (host[:3] == 255).all() and (host[3 + count * depth:] == 255).all()
 
 
+@pytest.mark.parametrize("depth,count", [(18, 12_000_000), (17, 12_000_000), (32, 9_000_000), (40, 3_000_000)])
+def test_decode_many_tiles_per_workgroup(depth, count):
+    """Ranges long enough that every workgroup takes many tiles (a workgroup
+    steps its threads' first indices from tile to tile by adding digit
+    groups): rows at both ends of every 2048-word and 256-word tile boundary
+    in a stretch, and random rows, against the oracle's unranking."""
+    n = kl.num_words(depth)
+    first = n // 7
+    out = kl.decode(first, count, depth)
+    rng = np.random.default_rng(depth)
+    rows = set(rng.integers(0, count, size=3000).tolist()) | {0, 1, count - 2, count - 1}
+    for b in range(2048 * 1700, 2048 * 1800, 256):
+        if b + 1 < count:
+            rows |= {b - 1, b, b + 1}
+    rows = np.array(sorted(r for r in rows if 0 <= r < count))
+    got = out[torch.as_tensor(rows, device="cuda")].cpu().numpy()
+    want = np.stack([O.unrank(first + int(r), depth) for r in rows])
+    np.testing.assert_array_equal(got, want)
+
+
 def test_decode_misaligned_destination():
     depth = 7
     n = kl.num_words(depth)
