@@ -121,6 +121,14 @@ def test_bounded_batched_and_tiling_renders(precision):
     a = kl.render_many(ta, tb, depths, win, precision=precision)
     b = kl.render_many(ta, tb, depths, win, precision=precision, block_bounds=True)
     assert torch.equal(a, b)
+    # with dropped counters (the kernels that count them)
+    da = torch.zeros(len(ta), dtype=torch.int64, device="cuda")
+    db = torch.zeros(len(ta), dtype=torch.int64, device="cuda")
+    a = kl.render_many(ta, tb, depths, win, precision=precision, dropped=da)
+    b = kl.render_many(ta, tb, depths, win, precision=precision, dropped=db, block_bounds=True)
+    assert torch.equal(a, b) and torch.equal(da, db)
+    for i, d in enumerate(depths):
+        assert int(kl.as_u32(b[i]).astype(np.int64).sum()) + int(db[i].item()) == kl.num_words(d)
     _assert_same(lambda **kw: kl.render(*C2, 15, WIN_C2, min_depth=1, precision=precision, **kw))
     _assert_same(lambda **kw: kl.render(*C2, 14, WIN_C2, min_depth=1, seed="all", precision=precision, **kw))
 
