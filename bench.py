@@ -36,7 +36,7 @@ FLOPS_PER_WORD = 16
 # target was set: (d - k - 1) FP32 mat-vecs of 28 flops at depth 18 with an
 # 8-letter prefix (252 FP32) plus the FP64 prefix application (45 FP64), in
 # FP32-equivalent flops (FP64 at half the FP32 rate)
-SURVEY_FP32_EQUIV_FLOPS_PER_WORD = 252 + 2 * 45
+POINT_WALK_FP32_EQUIV_FLOPS_PER_WORD = 252 + 2 * 45
 FP32_PEAK_TFLOPS = 157.3  # MI355X FP32 vector peak (counts packed FMA)
 FP64_PEAK_TFLOPS = 78.6   # MI355X FP64 vector peak
 EVENT_EVERY = 10
@@ -569,7 +569,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the renderer shards by "
-              f"index range with one image reduction, which this build does not run.", file=sys.stderr)
+              f"index range with one image reduction, which this library does not implement.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -651,7 +651,7 @@ def main():
                 "kernel_ms": round(kernel_avg, 4),
                 "flops_per_word": FLOPS_PER_WORD, "words_per_launch": kernel_words,
                 "useful_frac_point_walk_formulation": round(
-                    SURVEY_FP32_EQUIV_FLOPS_PER_WORD * kernel_words / (kernel_avg * 1e-3) / 1e12 / FP32_PEAK_TFLOPS, 3)}
+                    POINT_WALK_FP32_EQUIV_FLOPS_PER_WORD * kernel_words / (kernel_avg * 1e-3) / 1e12 / FP32_PEAK_TFLOPS, 3)}
     # VALU issue: the kernel's VALU instructions (counters) against the issue slots
     # of its measured duration at the nominal 4 cycles per wave64 instruction
     vpw = _valu_per_wave_word(plan)

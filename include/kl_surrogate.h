@@ -5,7 +5,7 @@
  * to a 128 x 128 occupancy image of its depth-14 limit set over [-2, 2]^2
  * (the image the renderer of kl.h draws, thresholded at count > 0).  It is
  * trained on renders the renderer itself produces, and the plain renderer
- * remains both its fallback and the judge of its IoU.  None of this is in
+ * remains both its fallback and the reference for its IoU.  None of this is in
  * the paper (whose Section 7 only notes that the method needs
  * acceleration); the shapes are:
  *   u  = [(Re ta - 2.4)/0.6, Im ta/0.3, (Re tb - 2.4)/0.6, Im tb/0.3]

@@ -1,6 +1,6 @@
 """Occupancy surrogate: training data from the renderer, training on the
 GPU with the library's own kernels, an uncertainty gate, and the plain
-renderer as fallback and judge.
+renderer as fallback and as the reference for IoU.
 
 Every compute step (renders, occupancy, forward, backward, Adam, gate
 statistic, IoU) runs in libkl; this module orders the calls, slices device
@@ -243,7 +243,7 @@ def run(train_n=18000, calib_n=2000, test_n=2000, steps=3000, batch=128, lr=2e-3
     iou_cal = kl.iou(occ_cal, logits=logits_cal).cpu().numpy()
     unc_cal = kl.sur_uncertainty(logits_cal).cpu().numpy()
     tau = gate_threshold(unc_cal, iou_cal)
-    # held-out: plain scan (the judge) and gated surrogate scan
+    # held-out: plain scan (the IoU reference) and gated surrogate scan
     plain_scan(ta_te[:64], tb_te[:64], depth)  # warm-up
     (occ_true, _), plain_s = _median_of(lambda: plain_scan(ta_te, tb_te, depth), 5)
     scan(params, ta_te[:64], tb_te[:64], tau, depth)  # warm-up
