@@ -54,6 +54,68 @@ __device__ inline void cayley_pixel(const CayleyJob& a, c64 num, c64 den, double
     py = fma_(a.fold.s, im, a.fold.o.im);
 }
 
+// A tail point (u : v) as stored in a tail table: (y : 1) with y = u / v
+// where v != 0 and y is in range, else (u : v) unchanged (a point at or near
+// infinity).  Tails stored as (y : 1) take the pole form.
+__device__ inline void cayley_tail_normalize(c64& u, c64& v) {
+    const double n2 = fma_(v.re, v.re, v.im * v.im);
+    const c64 y = {fma_(u.re, v.re, u.im * v.im) / n2, fma_(u.im, v.re, -(u.re * v.im)) / n2};
+    if (n2 > 0.0 && y.re <= 0x1p32 && y.re >= -0x1p32 && y.im <= 0x1p32 && y.im >= -0x1p32) {
+        u = y;
+        v = {1.0, 0.0};
+    }
+}
+
+// A head's map [[a, b], [c, d]] in pole form, for c != 0:
+//   h(y) = P + Q / (y + S),  P = a / c,  S = d / c,  Q = -(a d - b c) / c^2,
+// with the pixel fold applied (P <- s P + o, Q <- s Q) and the x anisotropy
+// folded into the real part's coefficients, so that with u = y + S
+//   px = Px + (ax u.re + bx u.im) / |u|^2,  py = Py + (ay u.re + by u.im) / |u|^2;
+// the map itself is kept for the ratio form.
+struct CayleyHead {
+    m64 M;
+    c64 S;
+    double Px, Py, ax, bx, ay, by;
+    bool pole;
+};
+
+__device__ inline CayleyHead cayley_head(const CayleyJob& a, const m64& M) {
+    CayleyHead h;
+    h.M = M;
+    const double cn = fma_(M.c.re, M.c.re, M.c.im * M.c.im);
+    const c64 ic = {M.c.re / cn, -M.c.im / cn};
+    const c64 P = cmul(M.a, ic);
+    h.S = cmul(M.d, ic);
+    const c64 det = {fma_(M.a.re, M.d.re, -(M.a.im * M.d.im)) - fma_(M.b.re, M.c.re, -(M.b.im * M.c.im)),
+                     fma_(M.a.re, M.d.im, M.a.im * M.d.re) - fma_(M.b.re, M.c.im, M.b.im * M.c.re)};
+    const c64 q = cmul(det, cmul(ic, ic));
+    const double s = a.fold.s, an = a.fold.aniso;
+    h.Px = fma_(s, P.re, a.fold.o.re) * an;
+    h.Py = fma_(s, P.im, a.fold.o.im);
+    h.ax = -(s * q.re) * an;
+    h.bx = -(s * q.im) * an;
+    h.ay = -(s * q.im);
+    h.by = s * q.re;
+    auto in = [](double x, double lim) { return x <= lim && x >= -lim; };   // false for NaN
+    h.pole = cn > 0.0 && cn <= 0x1p1000 && in(h.S.re, 0x1p40) && in(h.S.im, 0x1p40) && in(h.ax, 0x1p80) &&
+             in(h.bx, 0x1p80) && in(h.ay, 0x1p80) && in(h.by, 0x1p80) && in(h.Px, 0x1p100) && in(h.Py, 0x1p100);
+    return h;
+}
+
+// Pixel coordinates of head . tail from the tail's stored point (u : v): the
+// pole form where the head has one and the point is (y : 1), else the ratio
+// form.  Render and eval both come here, so their values agree bit for bit.
+__device__ inline void cayley_word(const CayleyJob& a, const CayleyHead& h, c64 u, c64 v, double& px, double& py) {
+    if (h.pole && v.re == 1.0 && v.im == 0.0) {
+        const double ur = u.re + h.S.re, ui = u.im + h.S.im;
+        const double rc = cayley_recip(fma_(ur, ur, ui * ui));
+        px = fma_(fma_(h.ax, ur, h.bx * ui), rc, h.Px);
+        py = fma_(fma_(h.ay, ur, h.by * ui), rc, h.Py);
+    } else {
+        cayley_pixel(a, cfma(h.M.a, u, cmul(h.M.b, v)), cfma(h.M.c, u, cmul(h.M.d, v)), px, py);
+    }
+}
+
 // consecutive words per thread in a render: enough threads to fill the grid,
 // runs no shorter than 16 words and no longer than 256
 constexpr int kCayleyRunMin = 16, kCayleyRunMax = 256;
@@ -208,6 +270,7 @@ __global__ __launch_bounds__(256) void cayley_kernel(const CayleyJob a) {
             c64 u, v;
             seed_point(packed_symbol(lo, hi, r - 1), u, v);
             walk(lo, hi, 0, r, u, v);
+            cayley_tail_normalize(u, v);
             TU[t] = u;
             TV[t] = v;
         }
@@ -282,10 +345,10 @@ __global__ __launch_bounds__(256) void cayley_kernel(const CayleyJob a) {
                 }
             }
             const uint32_t accept = SETS[gh];   // end states after which the head reads
+            const CayleyHead ch = cayley_head(a, Mh);
             while (true) {
-                const c64 u = TU[t], v = TV[t];
                 double px, py;
-                cayley_pixel(a, cfma(Mh.a, u, cmul(Mh.b, v)), cfma(Mh.c, u, cmul(Mh.d, v)), px, py);
+                cayley_word(a, ch, TU[t], TV[t], px, py);
                 emit(k, px, py);
                 ++k;
                 if (MODE == kCayleyEval || k >= k1) break;
@@ -444,6 +507,7 @@ __global__ __launch_bounds__(256) void cayley_head_kernel(const CayleyJob a) {
             u = nu;
             v = nv;
         }
+        cayley_tail_normalize(u, v);
         q.TU[e] = u;
         q.TV[e] = v;
     }
@@ -535,11 +599,11 @@ __global__ __launch_bounds__(256) void cayley_head_kernel(const CayleyJob a) {
         const uint32_t o0 = (uint32_t)(wa > wstart ? wa - wstart : 0);
         const uint32_t o1 = (uint32_t)(wb - wstart < n_acc ? wb - wstart : n_acc);
         const uint16_t* list = q.AL + (size_t)g * a.n_tails;
+        const CayleyHead ch = cayley_head(a, Mh);
         for (uint32_t i = o0; i < o1; ++i) {
             const int t = list[i];
-            const c64 tu = TU[t], tv = TV[t];
             double px, py;
-            cayley_pixel(a, cfma(Mh.a, tu, cmul(Mh.b, tv)), cfma(Mh.c, tu, cmul(Mh.d, tv)), px, py);
+            cayley_word(a, ch, TU[t], TV[t], px, py);
             const uint32_t key = cayley_bin(px, py, a.W, a.H);
             if (key != run_key) {
                 if (run_key == kCayleyOutside) drop += run_len;
