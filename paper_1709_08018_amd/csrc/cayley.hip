@@ -83,7 +83,8 @@ __device__ inline CayleyHead cayley_head(const CayleyJob& a, const m64& M) {
     CayleyHead h;
     h.M = M;
     const double cn = fma_(M.c.re, M.c.re, M.c.im * M.c.im);
-    const c64 ic = {M.c.re / cn, -M.c.im / cn};
+    const double rn = cayley_recip(cn);
+    const c64 ic = {M.c.re * rn, -(M.c.im * rn)};
     const c64 P = cmul(M.a, ic);
     h.S = cmul(M.d, ic);
     const c64 det = {fma_(M.a.re, M.d.re, -(M.a.im * M.d.im)) - fma_(M.b.re, M.c.re, -(M.b.im * M.c.im)),
