@@ -32,12 +32,10 @@ METRIC = "Gwords/s and VALU roofline fraction at depth 18; surrogate vs plain sc
 # form P + Q / (y + S) applied to the suffix point y: u = y + S (2 flops),
 # |u|^2 (3), reciprocal (1), per pixel coordinate one product and two FMAs (10)
 FLOPS_PER_WORD = 16
-# the per-word work of the point-walk formulation in which the renderer's
-# target was set: (d - k - 1) FP32 mat-vecs of 28 flops at depth 18 with an
-# 8-letter prefix (252 FP32) plus the FP64 prefix application (45 FP64), in
-# FP32-equivalent flops (FP64 at half the FP32 rate)
-POINT_WALK_FP32_EQUIV_FLOPS_PER_WORD = 252 + 2 * 45
 FP32_PEAK_TFLOPS = 157.3  # MI355X FP32 vector peak (counts packed FMA)
+# the GPU clock ramps up over the first ~100 ms of work: before the counted
+# warm-up steps, steps run untimed until this much wall time has passed
+CLOCK_RAMP_MS = 300.0
 FP64_PEAK_TFLOPS = 78.6   # MI355X FP64 vector peak
 EVENT_EVERY = 10
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "render_kernel_quasifuchsian_d18_pmc.txt")
@@ -87,17 +85,45 @@ def _valu_per_wave_word(plan):
     return _profile_value(VALU_SUMMARY, "VALU instructions per wave-word (64 words)", plan)
 
 
+# A GPU machine grants one process a CPU share of 16 cores per GPU, whatever the
+# host reports; the oracle's threaded render uses at most that share.
+CPU_SHARE = 16
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(wl_obj, seconds_hint: float):
+    """The oracle timed on this host: the full workload on every core of the
+    process's CPU share (one thread per core, contiguous index ranges), and
+    one thread on a contiguous sixteenth of the index space."""
     from oracle import oracle as ref
 
-    threads = min(len(os.sched_getaffinity(0)), 16)
+    affinity = len(os.sched_getaffinity(0))
+    threads = min(affinity, CPU_SHARE)
     n = ref.num_words(wl_obj.depth)
+    win = wl_obj.window.as_tuple()
     t0 = time.perf_counter()
-    img, dropped, _ = ref.render(wl_obj.ta, wl_obj.tb, wl_obj.depth, wl_obj.window.as_tuple(), nthreads=threads)
+    img, dropped, _ = ref.render(wl_obj.ta, wl_obj.tb, wl_obj.depth, win, nthreads=threads)
     dt = time.perf_counter() - t0
+    n1 = n // 16
+    t0 = time.perf_counter()
+    ref.render(wl_obj.ta, wl_obj.tb, wl_obj.depth, win, first=n // 3, count=n1, nthreads=1)
+    dt1 = time.perf_counter() - t0
     return {"value": n / dt / 1e9, "unit": "Gwords/s", "cores": threads, "kind": "oracle",
             "sample": f"the full workload ({n} words, depth {wl_obj.depth}), FP64 depth-first walk, "
-                      f"{threads} threads over contiguous index ranges, {dt:.2f} s"}, img, dropped
+                      f"{threads} threads over contiguous index ranges, {dt:.2f} s",
+            "single_thread": {"value": n1 / dt1 / 1e9, "unit": "Gwords/s", "words": n1, "seconds": round(dt1, 3),
+                              "sample": f"words [{n // 3}, {n // 3 + n1}) of depth {wl_obj.depth}, one thread"},
+            "cpu_model": _cpu_model(), "host_cpus": os.cpu_count(), "affinity_cpus": affinity,
+            "cpu_share": CPU_SHARE}, img, dropped
 
 
 # The oracle, timed beside the GPU legs: each returns a leg's "cpu_baseline"
@@ -130,7 +156,7 @@ def cpu_baseline_maskit(W, words, img):
     GPU's FP64 image against it."""
     import numpy as np
     ref = _oracle()
-    threads = min(len(os.sched_getaffinity(0)), 16)
+    threads = min(len(os.sched_getaffinity(0)), CPU_SHARE)
     t0 = time.perf_counter()
     ref_img, _, near = ref.render_group(ref.group_maskit(W.ta), W.depth, W.window.as_tuple(), seed=4,
                                         min_depth=W.min_depth, edge_tol=1e-7, nthreads=threads)
@@ -146,7 +172,7 @@ def cpu_baseline_cayley_t11(ta, tb, depth, win, words, img):
     and the table path's image against it."""
     import numpy as np
     ref = _oracle()
-    threads = min(len(os.sched_getaffinity(0)), 16)
+    threads = min(len(os.sched_getaffinity(0)), CPU_SHARE)
     t0 = time.perf_counter()
     rimg, _, near = ref.render(ta, tb, depth, win, edge_tol=1e-7, nthreads=threads)
     dt = time.perf_counter() - t0
@@ -553,12 +579,52 @@ def leg_hist(args):
     return {"workload": W.name, "candidates": rows}
 
 
+def fp64_leg(W, image, n_words, hip, steps=20):
+    """The same step on the FP64 path (every step of the arithmetic in FP64):
+    its step time, and its render kernel's rate against the FP64 vector peak."""
+    import numpy as np
+    import torch
+
+    from paper_1709_08018_amd import kl
+
+    plan = kl.plan(W.depth, "fp64")
+    ev = []
+    for _ in range(2 * steps):
+        e = ctypes.c_void_p()
+        if hip.hipEventCreate(ctypes.byref(e)) != 0:
+            raise RuntimeError("hipEventCreate failed")
+        ev.append(e.value)
+    for _ in range(5):
+        kl.render(W.ta, W.tb, W.depth, W.window, image=image, precision="fp64")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        kl.render(W.ta, W.tb, W.depth, W.window, image=image, precision="fp64",
+                  kernel_events=(ev[2 * i], ev[2 * i + 1]))
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    kms = []
+    for i in range(steps):
+        f = ctypes.c_float()
+        hip.hipEventElapsedTime(ctypes.byref(f), ev[2 * i], ev[2 * i + 1])
+        kms.append(f.value)
+    for e in ev:
+        hip.hipEventDestroy(e)
+    kernel_ms = float(np.mean(kms))
+    R = 3 ** plan["tail_len"]
+    kw = (n_words // R) * R
+    return {"ms_per_step": round(ms, 4), "value": round(n_words / (ms * 1e-3) / 1e9, 3), "unit": "Gwords/s",
+            "kernel_ms": round(kernel_ms, 4),
+            "frac_of_fp64_peak": round(FLOPS_PER_WORD * kw / (kernel_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4),
+            "split": {k: plan[k] for k in ("prefix_len", "lane_len", "tail_len")}, "steps": steps}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=400,
-                    help="untimed steps first (the GPU clock ramps up over the first ~100 ms of work)")
+                    help="untimed steps after the clock ramp (CLOCK_RAMP_MS of untimed steps first)")
     ap.add_argument("--workload", default="quasifuchsian_d18",
                     choices=["quasifuchsian_d18", "quasifuchsian_d22", "decode", "bounded", "batch256", "fuchsian_tiling_d10",
                              "maskit_tiling_d14", "cayley", "surrogate", "hist", "calib"])
@@ -606,6 +672,13 @@ def main():
         ev = None if j is None else (events[2 * j], events[2 * j + 1])
         kl.render(W.ta, W.tb, W.depth, W.window, image=image, kernel_events=ev)
 
+    ramp_steps, t_ramp = 0, time.perf_counter()
+    while (time.perf_counter() - t_ramp) * 1e3 < CLOCK_RAMP_MS:
+        for _ in range(20):
+            step()
+        ramp_steps += 20
+        torch.cuda.synchronize()
+    ramp_ms = (time.perf_counter() - t_ramp) * 1e3
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -649,9 +722,7 @@ def main():
                 "frac": round(achieved / FP32_PEAK_TFLOPS, 4), "traffic": _traffic_from_profile(plan),
                 "kernel": "render_kernel<float, %s, false>" % ("true" if plan["hist_mode"] == 2 else "false"),
                 "kernel_ms": round(kernel_avg, 4),
-                "flops_per_word": FLOPS_PER_WORD, "words_per_launch": kernel_words,
-                "useful_frac_point_walk_formulation": round(
-                    POINT_WALK_FP32_EQUIV_FLOPS_PER_WORD * kernel_words / (kernel_avg * 1e-3) / 1e12 / FP32_PEAK_TFLOPS, 3)}
+                "flops_per_word": FLOPS_PER_WORD, "words_per_launch": kernel_words}
     # VALU issue: the kernel's VALU instructions (counters) against the issue slots
     # of its measured duration at the nominal 4 cycles per wave64 instruction
     vpw = _valu_per_wave_word(plan)
@@ -679,6 +750,9 @@ def main():
                    "split": {k: plan[k] for k in ("prefix_len", "lane_len", "tail_len", "waves_per_cu")},
                    "dropped": int(dropped.item())},
         "roofline": roofline,
+        "clock_ramp": {"ms": round(ramp_ms, 1), "steps": ramp_steps,
+                       "note": "untimed steps run before the counted warm-up until the GPU clock has ramped"},
+        "fp64": fp64_leg(W, image, n_words, hip),
     }
     if not args.no_cpu_baseline:
         cb, ref_img, ref_drop = cpu_baseline(W, 15.0)

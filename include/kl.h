@@ -117,7 +117,9 @@ typedef struct {
     uint64_t *dropped_out;/* device pointer to one uint64 or NULL: receives
                              (or, with accumulate, is increased by) the number
                              of words dropped as outside or not finite */
-    int tail_len;         /* r: letters per suffix table, 0 = planner (1..8) */
+    int tail_len;         /* r: letters per suffix table, 0 = planner (1..8 in
+                             FP32, 1..7 in FP64, whose r = 8 table would not
+                             fit a CU's LDS: KL_EINVAL) */
     int lane_len;         /* m: letters each lane adds to its prefix, 0 = planner (1..20) */
     int hist_mode;        /* KL_HIST_* */
     int waves_per_cu;     /* persistent grid size, 0 = planner */

@@ -30,8 +30,20 @@ FLAGS = [
 ]
 
 
-def _link(lib: str, sources: list[str], verbose: bool) -> None:
-    cmd = [HIPCC] + FLAGS + ["-o", lib + ".tmp", "-x", "hip"] + sources
+OBJ_DIR = os.path.join(PKG, "_build")
+
+
+def _compile(src: str, verbose: bool) -> str:
+    obj = os.path.join(OBJ_DIR, os.path.basename(src) + ".o")
+    cmd = [HIPCC] + [f for f in FLAGS if f != "-shared"] + ["-c", "-o", obj, "-x", "hip", src]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    return obj
+
+
+def _link(lib: str, objs: list[str], verbose: bool) -> None:
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", lib + ".tmp"] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
@@ -39,8 +51,16 @@ def _link(lib: str, sources: list[str], verbose: bool) -> None:
 
 
 def build(verbose: bool = False) -> str:
-    _link(LIB, SOURCES, verbose)
-    _link(CALIB_LIB, CALIB_SOURCES, verbose)
+    """Compile every source (in parallel, one hipcc per file), then link."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    os.makedirs(OBJ_DIR, exist_ok=True)
+    sources = SOURCES + CALIB_SOURCES
+    jobs = max(1, min(len(sources), os.cpu_count() or 1, 16))
+    with ThreadPoolExecutor(jobs) as ex:
+        objs = list(ex.map(lambda f: _compile(f, verbose), sources))
+    _link(LIB, objs[:len(SOURCES)], verbose)
+    _link(CALIB_LIB, objs[len(SOURCES):], verbose)
     return LIB
 
 

@@ -237,10 +237,14 @@ static const int kDefaultTail = 6;
 static const int kDefaultWavesPerCU = 32;
 
 int plan_split(int depth, int precision, int r_req, int m_req, Split* sp, int prefix_cap) {
-    (void)precision;
     int r;
     if (r_req > 0) {
         if (r_req > kMaxTail || r_req > depth) return fail(KL_EINVAL, "tail_len %d outside 1..min(8, depth)", r_req);
+        // the persistent kernels hold the homogeneous suffix table in LDS,
+        // 8 * 3^(r-1) points: in FP64 (16 B a point) r = 8 needs 280 KB,
+        // more than a CU's 160 KB
+        if (precision == KL_PREC_FP64 && r_req > kMaxTailFp64)
+            return fail(KL_EINVAL, "tail_len %d exceeds %d in FP64 (LDS suffix table)", r_req, kMaxTailFp64);
         r = r_req;
     } else {
         r = depth <= 4 ? depth : std::min(kDefaultTail, depth - 1);
@@ -380,10 +384,15 @@ static void load_tuned_locked() {
     char line[256];
     while (fgets(line, sizeof line, f)) {
         Tuned t;
+        Split sp;
+        // a line is kept only if the planner accepts its split: a stale or
+        // foreign line must not make every render of its depth fail
         if (sscanf(line, "%d %d %d %d %d %d %lf", &t.depth, &t.precision, &t.r, &t.m, &t.wpc, &t.hist, &t.ms) == 7 &&
             t.hist >= KL_HIST_AUTO && t.hist <= KL_HIST_LDS &&
+            (t.precision == KL_PREC_FP32 || t.precision == KL_PREC_FP64) &&
             t.depth >= 1 && t.depth <= KL_MAX_DEPTH && t.r >= 1 && t.r <= kMaxTail && t.r < t.depth && t.m >= 0 &&
-            t.m <= kMaxLane && t.wpc >= 0 && t.wpc <= 32) {
+            t.m <= kMaxLane && t.wpc >= 0 && t.wpc <= 32 &&
+            plan_split(t.depth, t.precision, t.r, t.m, &sp) == KL_OK) {
             auto it = std::find_if(g_tuned.begin(), g_tuned.end(),
                                    [&](const Tuned& x) { return x.depth == t.depth && x.precision == t.precision; });
             if (it != g_tuned.end()) *it = t;

@@ -13,6 +13,7 @@
 namespace kl {
 
 constexpr int kMaxTail = 8;         // LDS suffix tables hold 4*3^(r-1) <= 8748 entries
+constexpr int kMaxTailFp64 = 7;     // FP64: the homogeneous table of r = 8 exceeds a CU's LDS
 constexpr int kMaxLane = 20;        // letters a lane appends to its prefix (3^20 < 2^32)
 constexpr int kMaxPrefix = 14;      // prefix table depth (4*3^13 entries of 64 B at most)
 constexpr int kWave = 64;

@@ -145,6 +145,35 @@ def _check(rc):
         raise KLError(rc, f"{lib().kl_strerror(rc).decode()}: {msg}")
 
 
+_U32 = tuple(t for t in (torch.int32, getattr(torch, "uint32", None)) if t is not None)
+_U64 = tuple(t for t in (torch.int64, getattr(torch, "uint64", None)) if t is not None)
+
+
+def _dev_ptr(t, name, dtypes, min_numel, allow_none=False):
+    """Device address of tensor t after checking what the library will
+    assume of it: a torch tensor of one of `dtypes`, contiguous, with at
+    least `min_numel` elements, on the current HIP device.  The library
+    takes plain addresses and cannot check any of this itself."""
+    if t is None:
+        if allow_none:
+            return None
+        raise KLError(KL_EINVAL, f"{name} is None")
+    if not isinstance(t, torch.Tensor):
+        raise KLError(KL_EINVAL, f"{name} must be a torch.Tensor, not {type(t).__name__}")
+    if t.dtype not in dtypes:
+        raise KLError(KL_EINVAL, f"{name} has dtype {t.dtype}; expected {' or '.join(map(str, dtypes))}")
+    if not t.is_contiguous():
+        raise KLError(KL_EINVAL, f"{name} is not contiguous")
+    if t.numel() < min_numel:
+        raise KLError(KL_EINVAL, f"{name} holds {t.numel()} elements; the call writes or reads {min_numel}")
+    if t.device.type != "cuda":
+        raise KLError(KL_EINVAL, f"{name} is on {t.device}, not on a HIP device")
+    if t.device.index != torch.cuda.current_device():
+        raise KLError(KL_EINVAL, f"{name} is on {t.device}, not on the current device "
+                                 f"cuda:{torch.cuda.current_device()}")
+    return t.data_ptr()
+
+
 def _c(z) -> c64:
     z = complex(z)
     return c64(z.real, z.imag)
@@ -169,8 +198,10 @@ def _stream(stream):
 
 def make_opts(*, min_depth=0, precision="fp32", first=None, count=None, accumulate=False, stream=None,
               dropped=None, tail_len=0, lane_len=0, hist_mode="auto", waves_per_cu=0, suffix_form=0,
-              head_form=0, seed="own", kernel_events=None, block_bounds=False, use_stream=True) -> Opts:
+              head_form=0, seed="own", kernel_events=None, block_bounds=False, use_stream=True,
+              n_dropped=1) -> Opts:
     o = Opts()
+    o.dropped_out = _dev_ptr(dropped, "dropped", _U64, n_dropped, allow_none=True)
     o.min_depth = int(min_depth)
     o.precision = PREC[precision] if isinstance(precision, str) else int(precision)
     if first is not None or count is not None:
@@ -179,7 +210,6 @@ def make_opts(*, min_depth=0, precision="fp32", first=None, count=None, accumula
         o.count = int(count)
     o.accumulate = int(bool(accumulate))
     o.stream = _stream(stream).value if use_stream else None
-    o.dropped_out = None if dropped is None else dropped.data_ptr()
     o.tail_len = int(tail_len)
     o.lane_len = int(lane_len)
     o.hist_mode = HIST[hist_mode] if isinstance(hist_mode, str) else int(hist_mode)
@@ -227,8 +257,8 @@ def decode(first: int, count: int, depth: int, out: torch.Tensor | None = None, 
     """Letters of words first..first+count-1 of `depth`, shape (count, depth), uint8 on the GPU."""
     if out is None:
         out = torch.empty((count, depth), dtype=torch.uint8, device=_device())
-    _check(lib().kl_decode_ex(int(first), int(count), int(depth), out.data_ptr() if count else None,
-                              _stream(stream)))
+    ptr = _dev_ptr(out, "out", (torch.uint8,), int(count) * max(int(depth), 0)) if count else None
+    _check(lib().kl_decode_ex(int(first), int(count), int(depth), ptr, _stream(stream)))
     return out
 
 
@@ -243,8 +273,9 @@ def render(ta, tb, depth: int, window, image: torch.Tensor | None = None, **opts
     w = make_window(window)
     if image is None:
         image = new_image(w)
+    ptr = _dev_ptr(image, "image", _U32, w.width * w.height)
     o = make_opts(**opts)
-    _check(lib().kl_render_ex(_c(ta), _c(tb), int(depth), ctypes.byref(w), image.data_ptr(), ctypes.byref(o)))
+    _check(lib().kl_render_ex(_c(ta), _c(tb), int(depth), ctypes.byref(w), ptr, ctypes.byref(o)))
     return image
 
 
@@ -259,8 +290,9 @@ def render_many(ta, tb, depths, window, images: torch.Tensor | None = None, **op
     cta = (c64 * n)(*[c64(z.real, z.imag) for z in ta])
     ctb = (c64 * n)(*[c64(z.real, z.imag) for z in tb])
     cd = (ctypes.c_int * n)(*[int(d) for d in depths])
-    o = make_opts(**opts)
-    _check(lib().kl_render_many_ex(n, cta, ctb, cd, ctypes.byref(w), images.data_ptr(), ctypes.byref(o)))
+    ptr = _dev_ptr(images, "images", _U32, n * w.width * w.height)
+    o = make_opts(n_dropped=n, **opts)
+    _check(lib().kl_render_many_ex(n, cta, ctb, cd, ctypes.byref(w), ptr, ctypes.byref(o)))
     return images
 
 
@@ -284,7 +316,8 @@ def autotune(ta, tb, depth: int, window, precision="fp32", scratch: torch.Tensor
         scratch = new_image(w)
     p = Plan()
     ms = ctypes.c_double(0.0)
-    _check(lib().kl_autotune(_c(ta), _c(tb), int(depth), ctypes.byref(w), PREC[precision], scratch.data_ptr(),
+    _check(lib().kl_autotune(_c(ta), _c(tb), int(depth), ctypes.byref(w), PREC[precision],
+                             _dev_ptr(scratch, "scratch", _U32, w.width * w.height),
                              ctypes.byref(p), ctypes.byref(ms)))
     return {k: getattr(p, k) for k, _ in Plan._fields_}, ms.value
 
@@ -295,8 +328,8 @@ def as_u32(image: torch.Tensor) -> np.ndarray:
 
 
 # ---------------------------------------------------------------- surrogate
-def _p(t):
-    return None if t is None else t.data_ptr()
+F32, F64, U8 = (torch.float32,), (torch.float64,), (torch.uint8,)
+IMG = 128 * 128
 
 
 def sur_num_params() -> int:
@@ -314,55 +347,84 @@ def as_c64(z) -> torch.Tensor:
     return torch.as_tensor(np.stack([z.real, z.imag], 1)).to(_device())
 
 
-def sur_forward(params, ta, tb, workspace=None, out=None, stream=None):
-    ta_d, tb_d = (ta if isinstance(ta, torch.Tensor) else as_c64(ta)), (tb if isinstance(tb, torch.Tensor) else as_c64(tb))
-    B = ta_d.shape[0]
+def _traces(ta, tb):
+    ta_d = ta if isinstance(ta, torch.Tensor) else as_c64(ta)
+    tb_d = tb if isinstance(tb, torch.Tensor) else as_c64(tb)
+    B = ta_d.shape[0] if ta_d.dim() else 0
+    return ta_d, tb_d, B
+
+
+def _ws(workspace, B):
     ws = workspace if workspace is not None else sur_workspace(B)
+    return _dev_ptr(ws, "workspace", U8, 0), ws.numel()
+
+
+def sur_forward(params, ta, tb, workspace=None, out=None, stream=None):
+    ta_d, tb_d, B = _traces(ta, tb)
+    wp, wn = _ws(workspace, B)
     if out is None:
         out = torch.empty((B, 128, 128), dtype=torch.float32, device=_device())
-    _check(lib().kl_sur_forward(_p(params), _p(ta_d), _p(tb_d), B, _p(out), _p(ws), ws.numel(), _stream(stream)))
+    n = sur_num_params()
+    _check(lib().kl_sur_forward(_dev_ptr(params, "params", F32, n), _dev_ptr(ta_d, "ta", F64, 2 * B),
+                                _dev_ptr(tb_d, "tb", F64, 2 * B), B, _dev_ptr(out, "out", F32, B * IMG), wp, wn,
+                                _stream(stream)))
     return out
 
 
 def sur_loss_grad(params, ta, tb, targets, workspace=None, grad=None, stream=None):
-    ta_d, tb_d = (ta if isinstance(ta, torch.Tensor) else as_c64(ta)), (tb if isinstance(tb, torch.Tensor) else as_c64(tb))
-    B = ta_d.shape[0]
-    ws = workspace if workspace is not None else sur_workspace(B)
+    ta_d, tb_d, B = _traces(ta, tb)
+    wp, wn = _ws(workspace, B)
     if grad is None:
         grad = torch.empty_like(params)
     loss = torch.empty(1, dtype=torch.float32, device=_device())
-    _check(lib().kl_sur_loss_grad(_p(params), _p(ta_d), _p(tb_d), _p(targets), B, _p(grad), _p(loss), _p(ws),
-                                  ws.numel(), _stream(stream)))
+    n = sur_num_params()
+    _check(lib().kl_sur_loss_grad(_dev_ptr(params, "params", F32, n), _dev_ptr(ta_d, "ta", F64, 2 * B),
+                                  _dev_ptr(tb_d, "tb", F64, 2 * B), _dev_ptr(targets, "targets", U8, B * IMG), B,
+                                  _dev_ptr(grad, "grad", F32, n), _dev_ptr(loss, "loss", F32, 1), wp, wn,
+                                  _stream(stream)))
     return loss, grad
 
 
 def sur_adam(params, grad, m, v, step, lr, stream=None):
-    _check(lib().kl_sur_adam(_p(params), _p(grad), _p(m), _p(v), int(step), float(lr), _stream(stream)))
+    n = sur_num_params()
+    _check(lib().kl_sur_adam(_dev_ptr(params, "params", F32, n), _dev_ptr(grad, "grad", F32, n),
+                             _dev_ptr(m, "m", F32, n), _dev_ptr(v, "v", F32, n), int(step), float(lr),
+                             _stream(stream)))
 
 
 def sur_train_step(params, m, v, grad, step, lr, ta_d, tb_d, targets, workspace, loss, stream=None):
     B = ta_d.shape[0]
-    _check(lib().kl_sur_train_step(_p(params), _p(m), _p(v), _p(grad), int(step), float(lr), _p(ta_d), _p(tb_d),
-                                   _p(targets), B, _p(loss), _p(workspace), workspace.numel(), _stream(stream)))
+    n = sur_num_params()
+    _check(lib().kl_sur_train_step(_dev_ptr(params, "params", F32, n), _dev_ptr(m, "m", F32, n),
+                                   _dev_ptr(v, "v", F32, n), _dev_ptr(grad, "grad", F32, n), int(step), float(lr),
+                                   _dev_ptr(ta_d, "ta", F64, 2 * B), _dev_ptr(tb_d, "tb", F64, 2 * B),
+                                   _dev_ptr(targets, "targets", U8, B * IMG), B, _dev_ptr(loss, "loss", F32, 1),
+                                   _dev_ptr(workspace, "workspace", U8, 0), workspace.numel(), _stream(stream)))
 
 
 def occupancy(counts: torch.Tensor, out=None, stream=None) -> torch.Tensor:
     if out is None:
         out = torch.empty(counts.shape, dtype=torch.uint8, device=counts.device)
-    _check(lib().kl_occupancy(_p(counts), counts.numel(), _p(out), _stream(stream)))
+    n = counts.numel()
+    _check(lib().kl_occupancy(_dev_ptr(counts, "counts", _U32, n), n, _dev_ptr(out, "out", U8, n),
+                              _stream(stream)))
     return out
 
 
 def sur_predict_occupancy(logits: torch.Tensor, out=None, stream=None) -> torch.Tensor:
     if out is None:
         out = torch.empty(logits.shape, dtype=torch.uint8, device=logits.device)
-    _check(lib().kl_sur_predict_occupancy(_p(logits), logits.numel(), _p(out), _stream(stream)))
+    n = logits.numel()
+    _check(lib().kl_sur_predict_occupancy(_dev_ptr(logits, "logits", F32, n), n, _dev_ptr(out, "out", U8, n),
+                                          _stream(stream)))
     return out
 
 
 def sur_uncertainty(logits: torch.Tensor, stream=None) -> torch.Tensor:
-    out = torch.empty(logits.shape[0], dtype=torch.float32, device=logits.device)
-    _check(lib().kl_sur_uncertainty(_p(logits), logits.shape[0], _p(out), _stream(stream)))
+    B = logits.shape[0]
+    out = torch.empty(B, dtype=torch.float32, device=logits.device)
+    _check(lib().kl_sur_uncertainty(_dev_ptr(logits, "logits", F32, B * IMG), B, _dev_ptr(out, "out", F32, B),
+                                    _stream(stream)))
     return out
 
 
@@ -370,14 +432,27 @@ def iou(target_occ: torch.Tensor, logits: torch.Tensor | None = None, pred_occ: 
         stream=None) -> torch.Tensor:
     B = target_occ.shape[0]
     out = torch.empty(B, dtype=torch.float32, device=target_occ.device)
-    _check(lib().kl_iou(_p(logits), _p(pred_occ), _p(target_occ), B, _p(out), _stream(stream)))
+    _check(lib().kl_iou(_dev_ptr(logits, "logits", F32, B * IMG, allow_none=True),
+                        _dev_ptr(pred_occ, "pred_occ", U8, B * IMG, allow_none=True),
+                        _dev_ptr(target_occ, "target_occ", U8, B * IMG), B, _dev_ptr(out, "out", F32, B),
+                        _stream(stream)))
     return out
+
+
+def _span(rows, cols, s_row, s_col):
+    """Elements a strided rows x cols operand reaches (0 when empty)."""
+    if rows <= 0 or cols <= 0:
+        return 0
+    return (rows - 1) * int(s_row) + (cols - 1) * int(s_col) + 1
 
 
 def gemm_bf16(M, N, K, A, lda_m, lda_k, B, ldb_k, ldb_n, C, ldc, bias=None, relu=False, accumulate=False,
               stream=None):
-    _check(lib().kl_gemm_bf16(M, N, K, _p(A), lda_m, lda_k, _p(B), ldb_k, ldb_n, _p(C), ldc, _p(bias), int(relu),
-                              int(accumulate), _stream(stream)))
+    _check(lib().kl_gemm_bf16(M, N, K, _dev_ptr(A, "A", F32, _span(M, K, lda_m, lda_k)), lda_m, lda_k,
+                              _dev_ptr(B, "B", F32, _span(K, N, ldb_k, ldb_n)), ldb_k, ldb_n,
+                              _dev_ptr(C, "C", F32, _span(M, N, ldc, 1)), ldc,
+                              _dev_ptr(bias, "bias", F32, N, allow_none=True), int(relu), int(accumulate),
+                              _stream(stream)))
     return C
 
 
@@ -410,8 +485,9 @@ def render_group(ab, depth: int, window, image: torch.Tensor | None = None, **op
     w = make_window(window)
     if image is None:
         image = new_image(w)
+    ptr = _dev_ptr(image, "image", _U32, w.width * w.height)
     o = make_opts(**opts)
-    _check(lib().kl_render_group_ex(_ab(ab), int(depth), ctypes.byref(w), image.data_ptr(), ctypes.byref(o)))
+    _check(lib().kl_render_group_ex(_ab(ab), int(depth), ctypes.byref(w), ptr, ctypes.byref(o)))
     return image
 
 
@@ -477,6 +553,7 @@ def cayley_render(t: Cayley, depth: int, window, image: torch.Tensor | None = No
     w = make_window(window)
     if image is None:
         image = new_image(w)
+    ptr = _dev_ptr(image, "image", _U32, w.width * w.height)
     o = make_opts(**opts)
-    _check(lib().kl_cayley_render_ex(t.ref(), int(depth), ctypes.byref(w), image.data_ptr(), ctypes.byref(o)))
+    _check(lib().kl_cayley_render_ex(t.ref(), int(depth), ctypes.byref(w), ptr, ctypes.byref(o)))
     return image

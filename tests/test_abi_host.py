@@ -79,6 +79,68 @@ def test_plan_overrides_and_rejects():
         kl.plan(41, "fp32")
 
 
+def test_fp64_tail_length_limited_by_lds():
+    # the FP64 homogeneous suffix table of r = 8 (280 KB) does not fit a CU's LDS
+    assert kl.plan(18, "fp32", tail_len=8)["tail_len"] == 8
+    assert kl.plan(18, "fp64", tail_len=7)["tail_len"] == 7
+    with pytest.raises(kl.KLError) as e:
+        kl.plan(18, "fp64", tail_len=8)
+    assert e.value.code == kl.KL_EINVAL and "FP64" in str(e.value)
+    o = kl.make_opts(precision="fp64", tail_len=8, use_stream=False)
+    assert _render(window=_win(), opts=o) == kl.KL_EINVAL
+
+
+_CACHE_PROBE = """
+import sys
+sys.path.insert(0, {root!r})
+from paper_1709_08018_amd import kl
+print(kl.plan(30, "fp32")["tail_len"], kl.plan(18, "fp32")["tail_len"], kl.plan(18, "fp32")["lane_len"],
+      kl.plan(20, "fp64")["tail_len"])
+"""
+
+
+def test_autotune_cache_skips_lines_the_planner_rejects(tmp_path):
+    import os
+    import sys
+    # depth 30 with r = 3, m = 1 leaves a 26-letter prefix table (> 14);
+    # r = 8 is beyond FP64's limit; the depth-18 line is valid and applies
+    cache = tmp_path / "tune.txt"
+    cache.write_text("30 0 3 1 0 0 1.0\n20 1 8 2 0 1 1.0\n18 0 5 2 16 1 0.2\ngarbage\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    out = subprocess.run([sys.executable, "-c", _CACHE_PROBE.format(root=root)], capture_output=True, text=True,
+                         env={**os.environ, "KL_AUTOTUNE_CACHE": str(cache)}, check=True).stdout.split()
+    default30 = kl.plan(30, "fp32")["tail_len"]
+    default20 = kl.plan(20, "fp64")["tail_len"]
+    assert out == [str(default30), "5", "2", str(default20)]
+
+
+def test_binding_checks_tensors_before_the_call():
+    w = (-1.0, 1.0, -1.0, 1.0, 8, 8)
+    with pytest.raises(kl.KLError, match="dtype"):
+        kl.render(wl.C2_TA, wl.C2_TB, 3, w, image=torch.zeros((8, 8), dtype=torch.float32))
+    with pytest.raises(kl.KLError, match="elements"):
+        kl.render(wl.C2_TA, wl.C2_TB, 3, w, image=torch.zeros((4, 8), dtype=torch.int32))
+    with pytest.raises(kl.KLError, match="contiguous"):
+        kl.render(wl.C2_TA, wl.C2_TB, 3, w, image=torch.zeros((8, 16), dtype=torch.int32)[:, ::2])
+    with pytest.raises(kl.KLError, match="HIP device"):
+        kl.render(wl.C2_TA, wl.C2_TB, 3, w, image=torch.zeros((8, 8), dtype=torch.int32))
+    # render_many writes one dropped counter per set
+    with pytest.raises(kl.KLError, match="elements"):
+        kl.make_opts(dropped=torch.zeros(1, dtype=torch.int64), n_dropped=3)
+    with pytest.raises(kl.KLError, match="dtype"):
+        kl.make_opts(dropped=torch.zeros(3, dtype=torch.int32), n_dropped=3)
+    with pytest.raises(kl.KLError, match="elements"):
+        kl.render_many([2.0, 2.0], [2.0, 2.0], [3, 3], w, images=torch.zeros((1, 8, 8), dtype=torch.int32))
+    with pytest.raises(kl.KLError, match="elements"):
+        kl.decode(0, 10, 5, out=torch.zeros((10, 4), dtype=torch.uint8))
+    with pytest.raises(kl.KLError, match="dtype"):
+        kl.decode(0, 10, 5, out=torch.zeros((10, 5), dtype=torch.int8))
+    with pytest.raises(kl.KLError, match="elements"):
+        kl.gemm_bf16(4, 4, 4, torch.zeros(15), 4, 1, torch.zeros(16), 4, 1, torch.zeros(16), 4)
+    with pytest.raises(kl.KLError, match="dtype"):
+        kl.sur_adam(torch.zeros(kl.sur_num_params(), dtype=torch.float64), None, None, None, 1, 1e-3)
+
+
 def _win(x0=-1.5, x1=1.5, y0=-1.5, y1=1.5, w=64, h=64):
     return kl.Window(x0, x1, y0, y1, w, h)
 

@@ -21,6 +21,18 @@ if torch.cuda.is_available():
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
 
+def _assert_fp64_close(z, zr, what, floor=1e-6):
+    """FP64 values against the oracle: within 1e-10 of max(1, |z|), and for
+    |z| above `floor` within 1e-10 of |z| itself (truly relative)."""
+    fin = np.isfinite(zr)
+    assert np.isfinite(z[fin]).all(), what
+    dz, a = np.abs(z[fin] - zr[fin]), np.abs(zr[fin])
+    assert (dz / np.maximum(1, a)).max() < 1e-10, what
+    big = a > floor
+    if big.any():
+        rel = (dz[big] / a[big]).max()
+        assert rel < 1e-10, (what, f"relative {rel:.3e}; {int((~big).sum())} values below {floor}")
+
 def _golden_table(name):
     rows = [line.split() for line in open(os.path.join(GOLDEN, name)) if line.strip() and not line.startswith("#")]
     return np.array(rows, dtype=np.uint8)
@@ -92,9 +104,7 @@ def test_fp64_values(case):
         z = kl.cayley_eval(t, d, idx, seed=name).cpu().numpy()
         z = z[:, 0] + 1j * z[:, 1]
         zr = O.cayley_eval(ref, d, idx, seed=s)
-        fin = np.isfinite(zr)
-        assert np.isfinite(z[fin]).all()
-        assert (np.abs(z[fin] - zr[fin]) / np.maximum(1, np.abs(zr[fin]))).max() < 1e-10, name
+        _assert_fp64_close(z, zr, name)
     # an index beyond the words gives NaN
     z = kl.cayley_eval(t, d, np.array([n - 1, n], np.uint64)).cpu().numpy()
     assert np.isfinite(z[0]).all() and np.isnan(z[1]).all()
@@ -162,9 +172,7 @@ def test_head_tail_boundary_depths():
             z = kl.cayley_eval(t, d, idx, seed=seed).cpu().numpy()
             z = z[:, 0] + 1j * z[:, 1]
             zr = O.cayley_eval(ref, d, idx, seed=s)
-            fin = np.isfinite(zr)
-            assert np.isfinite(z[fin]).all()
-            assert (np.abs(z[fin] - zr[fin]) / np.maximum(1, np.abs(zr[fin]))).max() < 1e-10, (d, seed)
+            _assert_fp64_close(z, zr, (d, seed))
     dropped = torch.zeros(1, dtype=torch.int64, device="cuda")
     img = kl.as_u32(kl.cayley_render(t, 7, win, min_depth=4, dropped=dropped)).astype(np.int64)
     ref_img = np.zeros_like(img)

@@ -45,10 +45,17 @@ def _bins_from_pixels(px, py, win):
     return img.reshape(H, W), int((~ok).sum())
 
 
-def _rel_err(z, zr):
+def _rel_err(z, zr, floor=1e-6):
+    """Error against max(1, |z|); values with |z| above `floor` must also be
+    within 1e-10 of |z| itself (truly relative)."""
     fin = np.isfinite(zr)
     assert np.isfinite(z[fin]).all()
-    return (np.abs(z[fin] - zr[fin]) / np.maximum(1, np.abs(zr[fin]))).max()
+    dz, a = np.abs(z[fin] - zr[fin]), np.abs(zr[fin])
+    big = a > floor
+    if big.any():
+        rel = (dz[big] / a[big]).max()
+        assert rel < 1e-10, f"relative {rel:.3e}; {int((~big).sum())} values below {floor}"
+    return (dz / np.maximum(1, a)).max()
 
 
 # ---------------------------------------------------------------- seed modes

@@ -22,6 +22,9 @@ C1 = (wl.C1_TA, wl.C1_TB)
 WIN_C2 = wl.QUASIFUCHSIAN_D18.window.as_tuple()
 WIN_C3 = wl.QUASIFUCHSIAN_D22.window.as_tuple()
 WIN_C1 = wl.FUCHSIAN_TILING_D10.window.as_tuple()
+# edge band (px) of FP32 image comparisons with the oracle: above every
+# measured per-word error (pole form 1.7e-4 px at depth 18, ratio form 7.2e-4)
+FP32_EDGE_PX = 1e-3
 
 
 def _z(t):
@@ -129,10 +132,20 @@ def test_decode_misaligned_destination():
 
 
 # ---------------------------------------------------------------- values
+REL_FLOOR = 1e-6
+
+
 def _fp64_case(ta, tb, depth, idx):
+    """Largest error of the FP64 path's values against the oracle's: the bar
+    is 1e-10 relative to max(1, |z|); values with |z| above REL_FLOOR must
+    also be within 1e-10 of |z| itself (truly relative)."""
     z = _z(kl.eval_values(ta, tb, depth, idx, precision="fp64"))
     zr = O.eval_values(ta, tb, depth, idx)
-    return (np.abs(z - zr) / np.maximum(1, np.abs(zr))).max()
+    dz = np.abs(z - zr)
+    big = np.abs(zr) > REL_FLOOR
+    rel = (dz[big] / np.abs(zr[big])).max() if big.any() else 0.0
+    assert rel < 1e-10, f"relative error {rel:.3e} ({int((~big).sum())} values below {REL_FLOOR})"
+    return (dz / np.maximum(1, np.abs(zr))).max()
 
 
 def test_fp64_values_all_words_small():
@@ -208,9 +221,9 @@ def test_fp64_image_matches_reference(case):
 def test_fp32_image_close_to_reference():
     win = WIN_C2
     img = kl.as_u32(kl.render(*C2, 12, win, precision="fp32")).astype(np.int64)
-    ref, _, near = O.render(*C2, 12, win, edge_tol=0.25, nthreads=8)
+    ref, _, near = O.render(*C2, 12, win, edge_tol=FP32_EDGE_PX, nthreads=8)
     diff = int(np.abs(img - ref.astype(np.int64)).sum())
-    print(f"FP32 image L1 difference {diff} of {ref.sum()} counts; {near} words within 0.25 px of an edge")
+    print(f"FP32 image L1 difference {diff} of {ref.sum()} counts; {near} words within {FP32_EDGE_PX} px of an edge")
     assert diff <= 2 * near
 
 
@@ -292,7 +305,7 @@ def test_head_forms_meet_the_fp32_bar(head_form):
     print(f"head_form {head_form}: FP32 pixel error max {err[inside].max():.3e} mean {err[inside].mean():.3e}")
     assert err[inside].max() <= 0.25
     img = kl.as_u32(kl.render(*C2, 12, win, precision="fp32", head_form=head_form)).astype(np.int64)
-    ref, _, near = O.render(*C2, 12, win, edge_tol=0.25, nthreads=8)
+    ref, _, near = O.render(*C2, 12, win, edge_tol=FP32_EDGE_PX, nthreads=8)
     assert int(np.abs(img - ref.astype(np.int64)).sum()) <= 2 * near
 
 
@@ -392,9 +405,9 @@ def test_full_quasifuchsian_d18_invariants_and_samples():
     p = kl.eval_values(*C2, depth, idx, window=win).cpu().numpy()
     fx, fy = _ref_pixels(O.eval_values(*C2, depth, idx), win)
     ok = ~np.signbit(p[:, 0]) & (p[:, 0] < win[4]) & ~np.signbit(p[:, 1]) & (p[:, 1] < win[5])
-    rows, cols = np.floor(p[ok, 1]).astype(int), np.floor(p[ok, 0]).astype(int)
-    assert (h[rows, cols] > 0).all()
     assert np.hypot(p[ok, 0] - fx[ok], p[ok, 1] - fy[ok]).max() <= 0.25
+    # bin-for-bin equality with the histogram of every word's own coordinates:
+    # test_gpu_fullsize.py
 
 
 def test_full_batch256_invariants_and_samples():
@@ -402,9 +415,9 @@ def test_full_batch256_invariants_and_samples():
     times: 256 parameter sets of depths 12..18, 512 x 512 each, one
     kl_render_many.  Every image holds its set's words exactly (bins plus
     dropped words); a depth-18 set and a depth-12 set equal their single
-    renders bit for bit; and on four sets, sampled words the renderer bins
-    are counted where its own arithmetic puts them, within 0.25 px of the
-    oracle's FP64 value."""
+    renders bit for bit; and on four sets, sampled words lie within 0.25 px
+    of the oracle's FP64 value.  (Those four images against the histogram of
+    all their words' own coordinates: test_gpu_fullsize.py.)"""
     ta, tb, depth = wl.batch256(seed=0)
     win = wl.BATCH_WINDOW.as_tuple()
     dropped = torch.zeros(len(ta), dtype=torch.int64, device="cuda")
@@ -419,13 +432,10 @@ def test_full_batch256_invariants_and_samples():
         assert torch.equal(imgs[i], single), i
     for i in picks:
         d = int(depth[i])
-        h = kl.as_u32(imgs[i]).astype(np.int64)
         idx = wl.sample_indices(kl.num_words(d), 4000, seed=i)
         pnt = kl.eval_values(ta[i], tb[i], d, idx, window=win).cpu().numpy()
         fx, fy = _ref_pixels(O.eval_values(complex(ta[i]), complex(tb[i]), d, idx), win)
         ok = ~np.signbit(pnt[:, 0]) & (pnt[:, 0] < win[4]) & ~np.signbit(pnt[:, 1]) & (pnt[:, 1] < win[5])
-        rows, cols = np.floor(pnt[ok, 1]).astype(int), np.floor(pnt[ok, 0]).astype(int)
-        assert (h[rows, cols] > 0).all(), i
         assert np.hypot(pnt[ok, 0] - fx[ok], pnt[ok, 1] - fy[ok]).max() <= 0.25, i
 
 
