@@ -40,8 +40,6 @@ FP64_PEAK_TFLOPS = 78.6   # MI355X FP64 vector peak
 EVENT_EVERY = 10
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "render_kernel_quasifuchsian_d18_pmc.txt")
 VALU_SUMMARY = os.path.join(ROOT, "profiles", "render_kernel_quasifuchsian_d18_valu.txt")
-# VALU issue slots: 256 CUs x 4 SIMDs, one wave64 instruction per 4 cycles each, at 2.4 GHz
-SIMDS, CLOCK_HZ, CYCLES_PER_VALU = 1024, 2.4e9, 4
 KERNEL_SRC = os.path.join(ROOT, "paper_1709_08018_amd", "csrc", "kernels.hip")
 
 
@@ -63,14 +61,14 @@ def _profile_value(path, key, plan):
     for line in open(path):
         if ": " in line:
             k, v = line.split(": ", 1)
-            vals[k.strip()] = v.strip()
+            vals[k.split(" (")[0].strip() if k.startswith("VALU issue fraction") else k.strip()] = v.strip()
     if vals.get("kernels.hip sha256[:16]") != src_hash:
         return None
     split = f"prefix {plan['prefix_len']}, lane {plan['lane_len']}, tail {plan['tail_len']}"
     if split not in vals.get("split", ""):
         return None
     try:
-        return float(vals[key])
+        return float(vals[key].split()[0])
     except (KeyError, ValueError):
         return None
 
@@ -723,12 +721,12 @@ def main():
                 "kernel": "render_kernel<float, %s, false>" % ("true" if plan["hist_mode"] == 2 else "false"),
                 "kernel_ms": round(kernel_avg, 4),
                 "flops_per_word": FLOPS_PER_WORD, "words_per_launch": kernel_words}
-    # VALU issue: the kernel's VALU instructions (counters) against the issue slots
-    # of its measured duration at the nominal 4 cycles per wave64 instruction
-    vpw = _valu_per_wave_word(plan)
-    roofline["valu_instr_per_wave_word"] = vpw
-    roofline["valu_issue_frac_nominal"] = None if vpw is None else round(
-        vpw * (kernel_words / 64) * CYCLES_PER_VALU / (kernel_avg * 1e-3 * CLOCK_HZ * SIMDS), 3)
+    # VALU issue (committed counter summary of the current source and split):
+    # instructions per 64 words, and the fraction of the VALU issue slots the
+    # kernel fills -- its VALU instructions at 4 cycles each on the 1024 SIMDs,
+    # over the GPU-active cycles the same dispatches count (GRBM_GUI_ACTIVE)
+    roofline["valu_instr_per_wave_word"] = _valu_per_wave_word(plan)
+    roofline["valu_issue_frac"] = _profile_value(VALU_SUMMARY, "VALU issue fraction", plan)
 
     out = {
         "metric": METRIC,

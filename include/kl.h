@@ -37,8 +37,9 @@
  *           y in [y0, y0 + (y1 - y0)/height); bin index row * width + col.
  *           Values outside the window or not finite are dropped.  The
  *           bin is taken from the word's pixel coordinates (kl_eval_ex
- *           with the window): column floor(px) for px in [+0, width),
- *           row likewise; a coordinate of -0.0 counts as outside.
+ *           with the window): column floor(px) when 0 <= px < width,
+ *           row likewise, compared as IEEE numbers (-0.0 counts as 0, a
+ *           NaN is outside), as the oracle bins.
  * images    uint32 counts, row-major; additions wrap modulo 2^32.
  * memory    pointers named *_out, idx, letters_out, image_out and images_out
  *           are DEVICE pointers (memory of the current HIP device); all

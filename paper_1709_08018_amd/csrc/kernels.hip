@@ -590,11 +590,21 @@ __device__ __forceinline__ double recip(double x) {
     return fma_(r, e, r);
 }
 
+// The smallest normal number of T.  The pole forms add it to |u|^2 (inside
+// the FMA that forms it, so at no cost): |u|^2 is then a normal number, its
+// reciprocal finite, and with finite, bounded head and suffix data (the pole
+// form's guards) a coordinate is finite or an infinity, never NaN.  It
+// changes |u|^2 only where |u| < 2^-50 in FP32, far below the rounding error
+// of u = y + S itself.
+template <typename T> struct MinNormal;
+template <> struct MinNormal<float> { static constexpr float v = 0x1p-126f; };
+template <> struct MinNormal<double> { static constexpr double v = 0x1p-1022; };
+
 // Pole form at an affine suffix point y.
 template <typename T>
 __device__ __forceinline__ void eval_pole(const Head<T>& h, cpx<T> y, T& px, T& py) {
     const T ur = y.re + h.S.re, ui = y.im + h.S.im;
-    const T rc = recip(fma_(ur, ur, ui * ui));
+    const T rc = recip(fma_(ur, ur, fma_(ui, ui, MinNormal<T>::v)));
     px = fma_(fma_(h.ax, ur, h.bx * ui), rc, h.Px);
     py = fma_(fma_(h.ay, ur, h.by * ui), rc, h.Py);
 }
@@ -606,7 +616,7 @@ __device__ __forceinline__ void eval_pole_h(const Head<T>& h, cpx<T> p, cpx<T> q
     const cpx<T> u = cfma(h.S, q, p);
     const T vr = fma_(q.re, u.re, q.im * u.im);
     const T vi = fma_(q.im, u.re, -(q.re * u.im));
-    const T rc = recip(fma_(u.re, u.re, u.im * u.im));
+    const T rc = recip(fma_(u.re, u.re, fma_(u.im, u.im, MinNormal<T>::v)));
     px = fma_(fma_(h.ax, vr, -(h.bx * vi)), rc, h.Px);
     py = fma_(fma_(h.ay, vr, -(h.by * vi)), rc, h.Py);
 }
@@ -651,37 +661,86 @@ __device__ __forceinline__ void word_value(const Head<T>& h, cpx<T> y, cpx<T> q,
     }
 }
 
-// Bin of pixel coordinates: row floor(py), column floor(px) when px lies in
-// [+0, W) and py in [+0, H), else kOutside.  The range is taken in the
-// order of the floats' bit patterns: read as unsigned integers, the
-// patterns of +0 up to +infinity increase with the value, and a set sign
-// bit (-0 included) or a NaN's pattern lies above that of any finite W.  So
-// one unsigned compare per coordinate rejects a negative value, -0, a value
-// at or beyond the edge, an infinity and a NaN; -0 counts as outside.
+// Bin of pixel coordinates: row floor(py), column floor(px) when 0 <= px <
+// W and 0 <= py < H, else kOutside.  The comparisons are IEEE ones, as the
+// oracle's: -0 counts as 0, and a NaN is outside.  The range test is taken
+// on the floors as integers: floor(px) lies in [0, W) exactly when px does
+// (W an integer), and a saturated or negative floor is outside.
 constexpr uint32_t kOutside = 0xFFFFFFFFu;
 
-// floor(x) as int32, saturating (v_cvt_flr_i32_f32)
+// floor(x) as int32, saturating, NaN to 0 (v_cvt_flr_i32_f32)
 __device__ __forceinline__ int floor_i32(float x) {
     int r;
     asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(r) : "v"(x));
     return r;
 }
 
+// floor(x) as int32 for x in [-1, 2^31 - 1] after clamping; NaN to -1
+// (the clamp's maxNum keeps the number), so a NaN is outside
+__device__ __forceinline__ int floor_i32(double x) {
+    return (int)__builtin_floor(__builtin_fmin(__builtin_fmax(x, -1.0), 2147483647.0));
+}
+
 __device__ __forceinline__ uint32_t bin_key(float px, float py, uint32_t W, uint32_t H) {
     const uint32_t col = (uint32_t)floor_i32(px);
     const uint32_t row = (uint32_t)floor_i32(py);
-    const bool ok = (__float_as_uint(px) < __float_as_uint((float)W)) &
-                    (__float_as_uint(py) < __float_as_uint((float)H));
+    const bool ok = (col < W) & (row < H) & (px == px) & (py == py);
     return ok ? __umul24(row, W) + col : kOutside;
 }
 
 __device__ __forceinline__ uint32_t bin_key(double px, double py, uint32_t W, uint32_t H) {
-    const bool ok = ((uint64_t)__double_as_longlong(px) < (uint64_t)__double_as_longlong((double)W)) &
-                    ((uint64_t)__double_as_longlong(py) < (uint64_t)__double_as_longlong((double)H));
-    const uint32_t col = ok ? (uint32_t)px : 0u;
-    const uint32_t row = ok ? (uint32_t)py : 0u;
+    const uint32_t col = (uint32_t)floor_i32(px);
+    const uint32_t row = (uint32_t)floor_i32(py);
+    const bool ok = (col < W) & (row < H);
     return ok ? __umul24(row, W) + col : kOutside;
 }
+
+// Run keys of the persistent walks.  A lane counts runs of consecutive
+// words that share a bin.  The key of a word is the pair (floor(px),
+// floor(py)) of saturating int32 floors in one 64-bit value, so consecutive
+// words are compared with one 64-bit compare; whether a run lies in the
+// window (both floors in range, bin_key's rule) and its bin are worked out
+// only when the run closes.  v_cvt_flr_i32_f32 maps NaN to 0, so a word
+// whose coordinates may be NaN (the general form of DUAL waves) takes the
+// outside key explicitly; the pole form's coordinates are never NaN
+// (MinNormal).
+constexpr uint64_t kOutsideKey = ~0ull;        // floors (-1, -1): outside
+constexpr uint64_t kSpanKey = ~0ull - 1;       // bounded walk: a node waiting in the span queue; outside
+
+__device__ __forceinline__ uint64_t run_key(float px, float py) {
+    return (uint64_t)(uint32_t)floor_i32(px) | ((uint64_t)(uint32_t)floor_i32(py) << 32);
+}
+
+// floor(x) as int32, saturating, NaN to 0 (v_cvt_i32_f64 of the floor), as
+// v_cvt_flr_i32_f32 does in FP32
+__device__ __forceinline__ int floor_sat_i32(double x) {
+    int r;
+    asm("v_cvt_i32_f64 %0, %1" : "=v"(r) : "v"(__builtin_floor(x)));
+    return r;
+}
+
+__device__ __forceinline__ uint64_t run_key(double px, double py) {
+    return (uint64_t)(uint32_t)floor_sat_i32(px) | ((uint64_t)(uint32_t)floor_sat_i32(py) << 32);
+}
+
+// the key of bin (row, col) of the window
+__device__ __forceinline__ uint64_t bin_run_key(uint32_t row, uint32_t col) {
+    return (uint64_t)col | ((uint64_t)row << 32);
+}
+
+// The window of a run key.
+struct KeyRange {
+    uint32_t W, H;
+};
+
+__device__ __forceinline__ KeyRange key_range(uint32_t W, uint32_t H) { return {W, H}; }
+
+__device__ __forceinline__ bool key_inside(uint64_t k, const KeyRange& kr) {
+    return ((uint32_t)k < kr.W) & ((uint32_t)(k >> 32) < kr.H);
+}
+
+__device__ __forceinline__ uint32_t key_col(uint64_t k) { return (uint32_t)k; }
+__device__ __forceinline__ uint32_t key_row(uint64_t k) { return (uint32_t)(k >> 32); }
 
 // ------------------------------------------------------------------ persistent renderer
 struct RenderArgs {
@@ -698,12 +757,14 @@ struct RenderArgs {
     uint32_t n_units;
 };
 
-// Run-length binning state of one lane: the open run's bin and the word
-// count at which it began.  The word counter itself is wave-uniform.  With
-// DROP the lane also counts the words of its runs outside the image.
+// Run-length binning state of one lane: the open run's key (run_key) and
+// the word count at which it began.  The word counter itself is
+// wave-uniform.  With DROP the lane also counts the words of its runs
+// outside the image.
 template <bool DROP>
 struct Runs {
-    uint32_t cur, start;
+    uint64_t key;
+    uint32_t start;
     uint64_t drop;
 };
 
@@ -713,7 +774,11 @@ struct Runs {
 // one global add per non-zero bin whenever the wave moves its tile.
 struct GlobalSink {
     uint32_t* image;
-    __device__ __forceinline__ void add(uint32_t key, uint32_t cnt) const { atomicAdd(image + key, cnt); }
+    KeyRange kr;
+    __device__ __forceinline__ void add(uint32_t row, uint32_t col, uint32_t cnt) const {
+        const uint32_t bin = row * kr.W + col;
+        atomicAdd(image + bin, cnt);
+    }
 };
 
 constexpr int kTile = 32;
@@ -723,11 +788,11 @@ struct TileSink {
     uint32_t* tile;   // LDS, kTile * kTile bins of this wave
     uint32_t W, H;
     int col0, row0;   // image position of tile bin (0, 0)
-    __device__ __forceinline__ void add(uint32_t key, uint32_t cnt) const {
-        const uint32_t row = key / W, col = key - row * W;
+    KeyRange kr;
+    __device__ __forceinline__ void add(uint32_t row, uint32_t col, uint32_t cnt) const {
         const uint32_t tc = col - (uint32_t)col0, tr = row - (uint32_t)row0;
         if (tc < (uint32_t)kTile && tr < (uint32_t)kTile) atomicAdd(tile + tr * kTile + tc, cnt);
-        else atomicAdd(image + key, cnt);
+        else atomicAdd(image + row * W + col, cnt);
     }
     // merge the tile into the image and clear it (whole wave, uniform)
     __device__ __forceinline__ void merge(int lane) {
@@ -754,20 +819,22 @@ struct TileSink {
 template <bool DROP, typename Sink>
 __device__ __forceinline__ void close_run(Runs<DROP>& s, uint32_t t_words, const Sink& sink) {
     const uint32_t cnt = t_words - s.start;
-    if (s.cur != kOutside) sink.add(s.cur, cnt);
+    if (key_inside(s.key, sink.kr)) sink.add(key_row(s.key), key_col(s.key), cnt);
     else if (DROP) s.drop += cnt;
 }
 
+// open a new run at word count t_words (its key outside until a word sets it)
 template <bool DROP>
-__device__ __forceinline__ void close_run(Runs<DROP>& s, uint32_t t_words, uint32_t* image) {
-    close_run(s, t_words, GlobalSink{image});
+__device__ __forceinline__ void reset_run(Runs<DROP>& s, uint32_t t_words) {
+    s.key = kOutsideKey;
+    s.start = t_words;
 }
 
 // All tails of one head: the 3 blocks of suffixes whose first letter may
 // follow the head's last letter, each walked in index order, 9 suffix
 // points loaded from LDS ahead of their use.
 // With MASKED, lanes whose `live` is false walk along without binning
-// (their bin stays kOutside; the caller discards their count).
+// (their key stays kOutsideKey; the caller discards their count).
 template <typename T, bool AFFINE, bool DUAL, bool MASKED = false, typename Sink = GlobalSink, bool DROP = false>
 __device__ __forceinline__ void walk_tails_s(const Head<T>& h, const unsigned char* tail_lds, uint32_t R1,
                                              uint32_t W, uint32_t H, const Sink& sink, Runs<DROP>& s,
@@ -794,11 +861,13 @@ __device__ __forceinline__ void walk_tails_s(const Head<T>& h, const unsigned ch
             for (uint32_t u = 0; u < 9; ++u) {
                 T px, py;
                 word_value<T, AFFINE, DUAL>(h, ya[u], yb[u], px, py);
-                uint32_t key = bin_key(px, py, W, H);
-                if (MASKED && !live) key = kOutside;
-                if (key != s.cur) {
+                uint64_t key = run_key(px, py);
+                if constexpr (DUAL)   // the general form can give NaN
+                    if (!((px == px) & (py == py))) key = kOutsideKey;
+                if (MASKED && !live) key = kOutsideKey;
+                if (key != s.key) {
                     close_run(s, tw + u, sink);
-                    s.cur = key;
+                    s.key = key;
                     s.start = tw + u;
                 }
             }
@@ -811,7 +880,8 @@ template <typename T, bool AFFINE, bool DUAL, bool MASKED = false, bool DROP = f
 __device__ __forceinline__ void walk_tails(const Head<T>& h, const unsigned char* tail_lds, uint32_t R1,
                                            uint32_t W, uint32_t H, uint32_t* image, Runs<DROP>& s,
                                            uint32_t& t_words, bool live = true) {
-    walk_tails_s<T, AFFINE, DUAL, MASKED>(h, tail_lds, R1, W, H, GlobalSink{image}, s, t_words, live);
+    walk_tails_s<T, AFFINE, DUAL, MASKED>(h, tail_lds, R1, W, H, GlobalSink{image, key_range(W, H)}, s, t_words,
+                                          live);
 }
 
 // Whether some lane of the wave holds a head without a pole form (uniform).
@@ -842,7 +912,6 @@ __device__ __forceinline__ uint32_t first_key(const Head<T>& h, const unsigned c
 // 26).  A head with last letter e walks the 3^(r-3) nodes under its three
 // allowed first letters.
 constexpr uint32_t kNodeWords = 27;
-constexpr uint32_t kSpan = 0xFFFFFFFEu;   // run key of a node whose words wait in the span queue
 constexpr uint32_t kQueue = 128;          // span queue entries per wave
 constexpr uint32_t kNodeGroup = 3;        // nodes classified together
 
@@ -937,8 +1006,8 @@ __device__ __forceinline__ HeadBound<T> head_bound(const Head<T>& h) {
 }
 
 // Where a pole-form head sends the 27 words of a node, as eval_pole computes
-// them in T: kOutside when every word's bin is outside the window, that bin
-// when every word falls in one bin, kSpan when neither can be shown.
+// them in T: kOutsideKey when every word's bin is outside the window, that bin's key
+// when every word falls in one bin, kSpanKey when neither can be shown.
 //
 // For y in the disk D(c, rho) and w = c + S with |w| > rho, u = y + S lies
 // in D(w, rho), so 1/u lies in the disk of centre conj(w) / den and radius
@@ -956,11 +1025,11 @@ __device__ __forceinline__ HeadBound<T> head_bound(const Head<T>& h) {
 // cx - Px, the radius and the reciprocal within about 420 eps of theirs,
 // all relative to (|ax| + |bx|) / (|w| - rho).  The margin 64 eps |Px| +
 // 1024 eps (|ax| + |bx|) / (|w| - rho) holds both with room.  Guards keep
-// every product of the evaluation finite and normal, else kSpan; NaN fails
+// every product of the evaluation finite and normal, else kSpanKey; NaN fails
 // them.
 template <typename T>
-__device__ __forceinline__ uint32_t node_class(const Head<T>& h, const HeadBound<T>& b, const NodeDisk<T>& d, T Wf,
-                                               T Hf, uint32_t W) {
+__device__ __forceinline__ uint64_t node_class(const Head<T>& h, const HeadBound<T>& b, const NodeDisk<T>& d, T Wf,
+                                               T Hf) {
     using K = BoundK<T>;
     const T wr = d.cr + h.S.re, wi = d.ci + h.S.im;
     const T rp = fma_(d.rho, K::up, b.sS);
@@ -977,17 +1046,17 @@ __device__ __forceinline__ uint32_t node_class(const Head<T>& h, const HeadBound
     const bool out = (ux < T(0)) | (lx >= Wf) | (uy < T(0)) | (ly >= Hf);
     const int c0 = bound_floor(lx), c1 = bound_floor(ux), r0 = bound_floor(ly), r1 = bound_floor(uy);
     const bool one = (lx > T(0)) & (ux < Wf) & (ly > T(0)) & (uy < Hf) & (c0 == c1) & (r0 == r1);
-    const uint32_t key = one ? __umul24((uint32_t)r0, W) + (uint32_t)c0 : kSpan;
-    return !ok ? kSpan : out ? kOutside : key;
+    const uint64_t key = one ? bin_run_key((uint32_t)r0, (uint32_t)c0) : kSpanKey;
+    return !ok ? kSpanKey : out ? kOutsideKey : key;
 }
 
-// Close a run of the bounded walk: bins add their count, kOutside runs are
-// dropped words, kSpan runs were queued and add nothing here.
+// Close a run of the bounded walk: bins add their count, runs outside the
+// window are dropped words, kSpanKey runs were queued and add nothing here.
 template <bool DROP>
-__device__ __forceinline__ void close_bounded(Runs<DROP>& s, uint32_t t_words, uint32_t* image) {
+__device__ __forceinline__ void close_bounded(Runs<DROP>& s, uint32_t t_words, const GlobalSink& sink) {
     const uint32_t cnt = t_words - s.start;
-    if (s.cur < kSpan) atomicAdd(image + s.cur, cnt);
-    else if (DROP && s.cur == kOutside) s.drop += cnt;
+    if (key_inside(s.key, sink.kr)) sink.add(key_row(s.key), key_col(s.key), cnt);
+    else if (DROP && s.key != kSpanKey) s.drop += cnt;
 }
 
 // Lanes q < c evaluate the 27 words of span-queue entry q (the head of lane
@@ -1051,6 +1120,11 @@ __device__ inline void bounded_unit(const Head<T>& h, int lane, const unsigned c
     const int ie = inv_letter(h.e);
     const HeadBound<T> hb = head_bound(h);
     const T Wf = (T)W, Hf = (T)H;
+    const GlobalSink sink{image, key_range(W, H)};
+    // a word's key can equal kSpanKey: close the run the per-word walk left
+    // open, so that close_bounded sees only node_class's keys
+    close_run(s, t_words, sink);
+    reset_run(s, t_words);
     uint32_t qn = 0;   // queued entries (wave-uniform)
     auto drain = [&](uint32_t c) {
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -1066,16 +1140,16 @@ __device__ inline void bounded_unit(const Head<T>& h, int lane, const unsigned c
         qn = rest;
     };
     // one node's verdict: extend or close the lane's run, queue a spanning node
-    auto step = [&](uint32_t key, uint32_t n) {
+    auto step = [&](uint64_t key, uint32_t n) {
         const uint32_t tw = __builtin_amdgcn_readfirstlane(t_words);
-        if (key != s.cur) {
-            close_bounded(s, tw, image);
-            s.cur = key;
+        if (key != s.key) {
+            close_bounded(s, tw, sink);
+            s.key = key;
             s.start = tw;
         }
-        const uint64_t span = __ballot(key == kSpan);
+        const uint64_t span = __ballot(key == kSpanKey);
         if (span) {
-            if (key == kSpan) {
+            if (key == kSpanKey) {
                 const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(span >> 32),
                                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)span, 0u));
                 queue[qn + below] = (uint16_t)(((uint32_t)lane << 8) | n);
@@ -1094,21 +1168,18 @@ __device__ inline void bounded_unit(const Head<T>& h, int lane, const unsigned c
                 NodeDisk<T> dk[kNodeGroup];
 #pragma unroll
                 for (uint32_t u = 0; u < kNodeGroup; ++u) dk[u] = nd[sub0 + u];
-                uint32_t key[kNodeGroup];
+                uint64_t key[kNodeGroup];
 #pragma unroll
-                for (uint32_t u = 0; u < kNodeGroup; ++u) key[u] = node_class(h, hb, dk[u], Wf, Hf, W);
+                for (uint32_t u = 0; u < kNodeGroup; ++u) key[u] = node_class(h, hb, dk[u], Wf, Hf);
 #pragma unroll
                 for (uint32_t u = 0; u < kNodeGroup; ++u) step(key[u], j * per + sub0 + u);
             }
         } else {
-            for (uint32_t sub = 0; sub < per; ++sub) step(node_class(h, hb, nd[sub], Wf, Hf, W), j * per + sub);
+            for (uint32_t sub = 0; sub < per; ++sub) step(node_class(h, hb, nd[sub], Wf, Hf), j * per + sub);
         }
     }
     // the words of a queued node are counted by the drain, not by the run
-    if (s.cur == kSpan) {
-        s.cur = kOutside;
-        s.start = t_words;
-    }
+    if (s.key == kSpanKey) reset_run(s, t_words);
     while (qn > 0) drain(qn < (uint32_t)kWave ? qn : (uint32_t)kWave);
 }
 
@@ -1120,7 +1191,9 @@ __device__ __forceinline__ void render_units(const RenderArgs& a, const unsigned
     const uint32_t waves = gridDim.x * (kBlock / kWave);
     const uint32_t gwave = blockIdx.x * (kBlock / kWave) + (threadIdx.x / kWave);
     uint32_t t_words = 0;
-    TileSink ts{a.image, tile, a.W, a.H, -(1 << 30), -(1 << 30)};
+    const KeyRange kr = key_range(a.W, a.H);
+    const GlobalSink gs{a.image, kr};
+    TileSink ts{a.image, tile, a.W, a.H, -(1 << 30), -(1 << 30), kr};
     for (uint32_t unit = gwave; unit < a.n_units; unit += waves) {
         const uint64_t local = (uint64_t)unit * kWave + lane;
         const bool full = (uint64_t)(unit + 1) * kWave <= a.n_heads;
@@ -1158,20 +1231,18 @@ __device__ __forceinline__ void render_units(const RenderArgs& a, const unsigned
         } else {
             // last, partial unit: idle lanes walk a valid head without binning
             // and their count is discarded
-            close_run(s, t_words, a.image);
-            s.cur = kOutside;
-            s.start = t_words;
+            close_run(s, t_words, gs);
+            reset_run(s, t_words);
             walk_tails<T, AFFINE, true, true>(h, tail_lds, a.sp.R1, a.W, a.H, a.image, s, t_words, live);
-            if (live) close_run(s, t_words, a.image);
-            s.cur = kOutside;
-            s.start = t_words;
+            if (live) close_run(s, t_words, gs);
+            reset_run(s, t_words);
         }
     }
     if constexpr (LDSHIST) {
         close_run(s, t_words, ts);
         ts.merge(lane);
     } else {
-        close_run(s, t_words, a.image);
+        close_run(s, t_words, gs);
     }
 }
 
@@ -1214,7 +1285,7 @@ __device__ __forceinline__ void render_body(const RenderArgs& a) {
             __syncthreads();
         }
     }
-    Runs<DROP> s = {kOutside, 0, 0};
+    Runs<DROP> s = {kOutsideKey, 0, 0};
     if (affine) render_units<T, true, LDSHIST, DROP, BOUNDED>(a, smem, G, tile, nodes, queue, s);
     else render_units<T, false, LDSHIST, DROP, false>(a, smem, G, tile, nodes, queue, s);
     if (DROP) {
@@ -1578,8 +1649,9 @@ __global__ __launch_bounds__(kBlock) void render_batch_kernel(const BatchArgs a)
     uint32_t* image = nullptr;
     uint64_t* dropped = nullptr;
     uint64_t base = 0;
-    Runs<DROP> s = {kOutside, 0, 0};
+    Runs<DROP> s = {kOutsideKey, 0, 0};
     uint32_t t_words = 0;
+    const KeyRange kr = key_range(a.W, a.H);
 
     for (uint64_t unit = blockIdx.x; unit < a.total_units; unit += gridDim.x) {
         // set of this unit: the last set whose first unit is <= unit (uniform over the block)
@@ -1591,11 +1663,10 @@ __global__ __launch_bounds__(kBlock) void render_batch_kernel(const BatchArgs a)
         }
         if (lo != cur) {
             if (cur >= 0) {
-                close_run(s, t_words, image);
+                close_run(s, t_words, GlobalSink{image, kr});
                 if (DROP) flush_drop(s.drop, dropped);
             }
-            s.cur = kOutside;
-            s.start = t_words;
+            reset_run(s, t_words);
             cur = lo;
             const SetDesc& S = a.sets[cur];
             sp = S.sp;
@@ -1643,19 +1714,17 @@ __global__ __launch_bounds__(kBlock) void render_batch_kernel(const BatchArgs a)
         } else {
             const bool live = hidx < sp.n_heads;
             if (!live) hidx = sp.n_heads - 1;
-            close_run(s, t_words, image);
-            s.cur = kOutside;
-            s.start = t_words;
+            close_run(s, t_words, GlobalSink{image, kr});
+            reset_run(s, t_words);
             const Head<T> h = compute_head<T>(hidx, sp, prefix, plast, G, a.fold);
             if (affine) walk_tails<T, true, true, true>(h, smem, sp.R1, a.W, a.H, image, s, t_words, live);
             else walk_tails<T, false, true, true>(h, smem, sp.R1, a.W, a.H, image, s, t_words, live);
-            if (live) close_run(s, t_words, image);
-            s.cur = kOutside;
-            s.start = t_words;
+            if (live) close_run(s, t_words, GlobalSink{image, kr});
+            reset_run(s, t_words);
         }
     }
     if (cur >= 0) {
-        close_run(s, t_words, image);
+        close_run(s, t_words, GlobalSink{image, kr});
         if (DROP) flush_drop(s.drop, dropped);
     }
 }

@@ -61,3 +61,13 @@ def test_valu_figure_read_with_the_same_checks(tmp_path, monkeypatch):
     p.write_text("kernels.hip sha256[:16]: 0000000000000000\nsplit: prefix 9, lane 3, tail 6 letters\n"
                  "VALU instructions per wave-word (64 words): 20.49\n")
     assert bench._valu_per_wave_word(SPLIT) is None
+
+
+def test_issue_fraction_read_from_the_counter_summary(tmp_path, monkeypatch):
+    p = tmp_path / "valu.txt"
+    p.write_text(f"kernels.hip sha256[:16]: {_current_hash()}\n"
+                 "split: prefix 9, lane 3, tail 6 letters; 32 waves per CU\n"
+                 "VALU issue fraction (SQ_INSTS_VALU x 4 cycles / (GRBM_GUI_ACTIVE / 8 XCDs x 1024 SIMDs), "
+                 "per dispatch): 0.977 (median of 684; min 0.926, max 1.005)\n")
+    monkeypatch.setattr(bench, "VALU_SUMMARY", str(p))
+    assert bench._profile_value(bench.VALU_SUMMARY, "VALU issue fraction", SPLIT) == 0.977

@@ -46,7 +46,7 @@ def _assert_same(render):
 
 def _bins_from_pixels(px, py, win):
     W, H = win[4], win[5]
-    ok = ~np.isnan(px) & ~np.isnan(py) & ~np.signbit(px) & (px < W) & ~np.signbit(py) & (py < H)
+    ok = (px >= 0) & (px < W) & (py >= 0) & (py < H)   # IEEE: -0 counts as 0, NaN is outside
     img = np.zeros(W * H, np.int64)
     np.add.at(img, np.floor(py[ok]).astype(np.int64) * W + np.floor(px[ok]).astype(np.int64), 1)
     return img.reshape(H, W), int((~ok).sum())

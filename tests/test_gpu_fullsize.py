@@ -42,8 +42,9 @@ FP32_EDGE_PX = 1e-3
 def own_bins_histogram(ta, tb, depth, win, precision="fp32", chunk=1 << 25, **opts):
     """Histogram of the renderer's own pixel coordinates (kl_eval with the
     window) of every word of `depth`, binned on the GPU by the renderer's
-    rule: a coordinate is inside when it lies in [+0, W) (so -0, NaN and
-    infinities are outside), bin floor(py) * W + floor(px)."""
+    rule: inside when 0 <= px < W and 0 <= py < H as IEEE comparisons (-0
+    counts as 0; NaN and infinities are outside), bin floor(py) * W +
+    floor(px)."""
     n = kl.num_words(depth)
     W, H = win[4], win[5]
     hist = torch.zeros(W * H, dtype=torch.int64, device="cuda")
@@ -53,7 +54,7 @@ def own_bins_histogram(ta, tb, depth, win, precision="fp32", chunk=1 << 25, **op
         idx = torch.arange(a, b, dtype=torch.int64, device="cuda")
         p = kl.eval_values(ta, tb, depth, idx, precision=precision, window=win, **opts)
         px, py = p[:, 0], p[:, 1]
-        ok = (px >= 0) & ~torch.signbit(px) & (px < W) & (py >= 0) & ~torch.signbit(py) & (py < H)
+        ok = (px >= 0) & (px < W) & (py >= 0) & (py < H)
         key = torch.floor(py[ok]).to(torch.int64) * W + torch.floor(px[ok]).to(torch.int64)
         hist += torch.bincount(key, minlength=W * H)
         dropped += int((~ok).sum().item())

@@ -39,7 +39,9 @@ def _ref_pixels(z, win):
 
 def _bins_from_pixels(px, py, win):
     W, H = win[4], win[5]
-    ok = ~np.isnan(px) & ~np.isnan(py) & ~np.signbit(px) & (px < W) & ~np.signbit(py) & (py < H)
+    # the renderer's rule: 0 <= px < W and 0 <= py < H as IEEE comparisons
+    # (-0 counts as 0; NaN compares false)
+    ok = (px >= 0) & (px < W) & (py >= 0) & (py < H)
     img = np.zeros(W * H, np.int64)
     np.add.at(img, np.floor(py[ok]).astype(np.int64) * W + np.floor(px[ok]).astype(np.int64), 1)
     return img.reshape(H, W), int((~ok).sum())
@@ -404,7 +406,7 @@ def test_full_quasifuchsian_d18_invariants_and_samples():
     idx = wl.sample_indices(n, 50000, seed=2)
     p = kl.eval_values(*C2, depth, idx, window=win).cpu().numpy()
     fx, fy = _ref_pixels(O.eval_values(*C2, depth, idx), win)
-    ok = ~np.signbit(p[:, 0]) & (p[:, 0] < win[4]) & ~np.signbit(p[:, 1]) & (p[:, 1] < win[5])
+    ok = (p[:, 0] >= 0) & (p[:, 0] < win[4]) & (p[:, 1] >= 0) & (p[:, 1] < win[5])
     assert np.hypot(p[ok, 0] - fx[ok], p[ok, 1] - fy[ok]).max() <= 0.25
     # bin-for-bin equality with the histogram of every word's own coordinates:
     # test_gpu_fullsize.py
@@ -435,7 +437,7 @@ def test_full_batch256_invariants_and_samples():
         idx = wl.sample_indices(kl.num_words(d), 4000, seed=i)
         pnt = kl.eval_values(ta[i], tb[i], d, idx, window=win).cpu().numpy()
         fx, fy = _ref_pixels(O.eval_values(complex(ta[i]), complex(tb[i]), d, idx), win)
-        ok = ~np.signbit(pnt[:, 0]) & (pnt[:, 0] < win[4]) & ~np.signbit(pnt[:, 1]) & (pnt[:, 1] < win[5])
+        ok = (pnt[:, 0] >= 0) & (pnt[:, 0] < win[4]) & (pnt[:, 1] >= 0) & (pnt[:, 1] < win[5])
         assert np.hypot(pnt[ok, 0] - fx[ok], pnt[ok, 1] - fy[ok]).max() <= 0.25, i
 
 
