@@ -200,6 +200,29 @@ int kl_render(kl_c64 ta, kl_c64 tb, int depth, const kl_window *window, uint32_t
 int kl_render_ex(kl_c64 ta, kl_c64 tb, int depth, const kl_window *window,
                  uint32_t *image_out, const kl_opts *opts);
 
+/* Bytes of the library's per-device scratch array (kl_render_noalloc). */
+#define KL_NOALLOC_SCRATCH_BYTES (4u << 20)
+
+/* kl_render_noalloc: for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, options and result as kl_render_ex for a
+ * render of one depth: image_out (and opts->dropped_out) as there, bit for
+ * bit the same image.  It allocates nothing: the prefix and suffix tables
+ * that kl_render_ex puts in a hipMallocAsync temporary go to a
+ * library-owned device array of KL_NOALLOC_SCRATCH_BYTES, one per device,
+ * held until the process ends, whose address is taken once per device on
+ * its first call.  Every call on a device shares that device's array and
+ * rewrites the tables it uses before reading them, so nothing carries over
+ * between calls; calls that overlap on one device (two streams, or two host
+ * threads) race on it and must be serialised by the caller, while calls on
+ * one stream are ordered by it.
+ * Errors: as kl_render_ex; KL_EINVAL for a tiling render (min_depth other
+ * than 0 or depth); KL_ENOMEM when the split's tables exceed the array
+ * (prefix tables of 10 or more letters: depths above 35 under the planner's
+ * splits), before anything is enqueued. */
+int kl_render_noalloc(kl_c64 ta, kl_c64 tb, int depth, const kl_window *window,
+                      uint32_t *image_out, const kl_opts *opts);
+
 /* kl_render_many: n independent limit-set renders in one persistent launch
  * (parameter sets of uneven depth share one work queue).
  *   ta, tb, depth  host arrays of n entries

@@ -214,15 +214,16 @@ static Fold make_fold(const kl_window* w, int head_form) {
 // ------------------------------------------------------------------ devices
 struct DeviceInfo {
     int cus = 0;
+    void* scratch = nullptr;   // device address of this device's copy of `scratch` (kl_render_noalloc)
 };
+constexpr int kMaxDevices = 64;
 static std::mutex g_dev_mutex;
-static std::vector<DeviceInfo> g_devs;
+static DeviceInfo g_devs[kMaxDevices];
 
 int device_cu_count() {
     int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return 256;
     std::lock_guard<std::mutex> lk(g_dev_mutex);
-    if ((int)g_devs.size() <= dev) g_devs.resize(dev + 1);
     if (g_devs[dev].cus == 0) {
         int cus = 0;
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
@@ -230,6 +231,29 @@ int device_cu_count() {
         g_devs[dev].cus = cus;
     }
     return g_devs[dev].cus;
+}
+
+// ------------------------------------------------------------------ allocation-free scratch
+// The tables of kl_render_noalloc: one array per device, held until the
+// process ends.  Host code never uses the array's name as an address: the
+// device address of the current device's copy comes from
+// hipGetSymbolAddress, taken once per device on its first call.
+static __device__ __align__(256) unsigned char scratch[KL_NOALLOC_SCRATCH_BYTES];
+
+static int scratch_address(void** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(KL_EDEVICE, "device %d beyond the %d the library tracks", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lk(g_dev_mutex);
+    if (!g_devs[dev].scratch) {
+        void* p = nullptr;
+        if ((e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch))) != hipSuccess) return hip_fail(e, "scratch address");
+        if (!p) return fail(KL_EDEVICE, "scratch array has no device address");
+        g_devs[dev].scratch = p;
+    }
+    *out = g_devs[dev].scratch;
+    return KL_OK;
 }
 
 // ------------------------------------------------------------------ planning
@@ -306,21 +330,49 @@ struct SetTables {
 
 static size_t round16(size_t x) { return (x + 15) & ~size_t(15); }
 
+// Layout of one set's tables in one buffer.
+struct TableLayout {
+    uint64_t np, nt;
+    size_t off_last, off_aff, off_hom, off_flags, total;
+    uint32_t n_flags;
+};
+
+static TableLayout table_layout(const Split& sp, int precision) {
+    TableLayout L;
+    L.np = sp.k ? num_words(sp.k) : 0;
+    L.nt = num_words(sp.r);
+    const size_t esz = precision == KL_PREC_FP64 ? sizeof(c64) : sizeof(c32);
+    L.off_last = round16(L.np * sizeof(m64));
+    L.off_aff = L.off_last + round16(L.np);
+    L.off_hom = L.off_aff + round16(L.nt * esz + 16);
+    L.off_flags = L.off_hom + round16(2 * L.nt * esz + 16);
+    L.n_flags = (uint32_t)((L.nt + 255) / 256);  // one per set-up block of suffix points
+    L.total = L.off_flags + round16(L.n_flags * sizeof(uint32_t));
+    return L;
+}
+
+// A caller-provided table buffer (kl_render_noalloc): base and capacity.
+struct TableBuf {
+    unsigned char* base = nullptr;
+    size_t bytes = 0;
+};
+
 static int build_tables(const Gens& G, const Split& sp, int precision, int force_homog, int seed, Temp& tmp,
                         SetTables* out, uint32_t* clear_image = nullptr, uint64_t bins = 0,
-                        uint64_t* clear_dropped = nullptr) {
-    const uint64_t np = sp.k ? num_words(sp.k) : 0;
-    const uint64_t nt = num_words(sp.r);
-    const size_t esz = precision == KL_PREC_FP64 ? sizeof(c64) : sizeof(c32);
-    const size_t off_last = round16(np * sizeof(m64));
-    const size_t off_aff = off_last + round16(np);
-    const size_t off_hom = off_aff + round16(nt * esz + 16);
-    const size_t off_flags = off_hom + round16(2 * nt * esz + 16);
-    const uint32_t n_flags = (uint32_t)((nt + 255) / 256);  // one per set-up block of suffix points
-    const size_t total = off_flags + round16(n_flags * sizeof(uint32_t));
+                        uint64_t* clear_dropped = nullptr, const TableBuf* buf = nullptr) {
+    const TableLayout L = table_layout(sp, precision);
+    const uint64_t np = L.np, nt = L.nt;
+    const size_t off_last = L.off_last, off_aff = L.off_aff, off_hom = L.off_hom, off_flags = L.off_flags;
+    const uint32_t n_flags = L.n_flags;
     unsigned char* base = nullptr;
-    hipError_t e = tmp.alloc((void**)&base, total);
-    if (e != hipSuccess) return hip_fail(e, "tables");
+    hipError_t e = hipSuccess;
+    if (buf) {
+        if (L.total > buf->bytes)
+            return fail(KL_ENOMEM, "tables of %zu bytes exceed the %zu-byte scratch array", L.total, buf->bytes);
+        base = buf->base;
+    } else if ((e = tmp.alloc((void**)&base, L.total)) != hipSuccess) {
+        return hip_fail(e, "tables");
+    }
     SetupJob j{};
     j.gens = G;
     j.precision = precision;
@@ -450,7 +502,8 @@ static kl_opts apply_tuned(const kl_opts& o, int depth, const kl_window* w) {
 // Render the words [lo, hi) of one depth; with `clear`, the set-up kernel
 // also clears the image and the dropped counter first.
 static int render_depth(const Gens& G, const Fold& f, int depth, uint64_t lo, uint64_t hi, const kl_opts& o_in,
-                        const kl_window* w, uint32_t* image, uint64_t* dropped, hipStream_t s, bool clear) {
+                        const kl_window* w, uint32_t* image, uint64_t* dropped, hipStream_t s, bool clear,
+                        const TableBuf* buf = nullptr) {
     if (lo >= hi && !clear) return KL_OK;
     const kl_opts o = apply_tuned(o_in, depth, w);
     Split sp;
@@ -460,7 +513,7 @@ static int render_depth(const Gens& G, const Fold& f, int depth, uint64_t lo, ui
     SetTables st;
     const uint64_t bins = (uint64_t)w->width * w->height;
     if ((rc = build_tables(G, sp, o.precision, o.suffix_form, seed_index(o), tmp, &st, clear ? image : nullptr, bins,
-                           clear ? dropped : nullptr)))
+                           clear ? dropped : nullptr, buf)))
         return rc;
     if (lo >= hi) return KL_OK;
     RenderJob job{};
@@ -863,9 +916,9 @@ static int render_tiling(const Gens& G, int depth, const kl_window* w, uint32_t*
 // four renders of the same words, one per generator's fixed point (the
 // paper's index-search loop), accumulated.
 static int render_run(const Gens& G, int depth, const kl_window* window, uint32_t* image_out, const kl_opts& o,
-                      const RenderSpan& span) {
+                      const RenderSpan& span, const TableBuf* buf = nullptr) {
     int rc;
-    if (span.min_depth < depth && !o.kernel_events[0] && !o.kernel_events[1]) {
+    if (!buf && span.min_depth < depth && !o.kernel_events[0] && !o.kernel_events[1]) {
         uint64_t total = 0;
         for (int d = span.min_depth; d <= depth; ++d) total += num_words(d);
         if (span.first == 0 && span.count == total) return render_tiling(G, depth, window, image_out, o, span.min_depth);
@@ -875,7 +928,7 @@ static int render_run(const Gens& G, int depth, const kl_window* window, uint32_
             kl_opts oq = o;
             oq.seed_mode = KL_SEED_A + q;
             oq.accumulate = o.accumulate || q > 0;
-            if ((rc = render_run(G, depth, window, image_out, oq, span))) return rc;
+            if ((rc = render_run(G, depth, window, image_out, oq, span, buf))) return rc;
         }
         return KL_OK;
     }
@@ -892,7 +945,7 @@ static int render_run(const Gens& G, int depth, const kl_window* window, uint32_
             const kl_opts od = d == depth ? o : opts_for_depth(o, d);
             const bool any = end > offset && first < offset + n && lo < hi;
             if ((rc = render_depth(G, f, d, any ? lo : 0, any ? hi : 0, od, window, image_out, o.dropped_out, s,
-                                   clear)))
+                                   clear, buf)))
                 return rc;
             clear = false;
         }
@@ -949,6 +1002,30 @@ int kl_render_ex(kl_c64 ta, kl_c64 tb, int depth, const kl_window* window, uint3
     Gens G;
     if ((rc = make_gens(ta, tb, &G))) return rc;
     return render_run(G, depth, window, image_out, o, span);
+}
+
+int kl_render_noalloc(kl_c64 ta, kl_c64 tb, int depth, const kl_window* window, uint32_t* image_out,
+                      const kl_opts* opts) {
+    const kl_opts o = opts ? *opts : default_opts();
+    RenderSpan span;
+    int rc = check_render(depth, window, image_out, o, &span);
+    if (rc) return rc;
+    if (span.min_depth != depth)
+        return fail(KL_EINVAL, "kl_render_noalloc renders one depth: min_depth must be 0 or %d", depth);
+    // the split's tables must fit the scratch array, checked before anything is enqueued
+    const kl_opts ot = apply_tuned(o, depth, window);
+    Split sp;
+    if ((rc = plan_split(depth, ot.precision, ot.tail_len, ot.lane_len, &sp))) return rc;
+    const size_t need = table_layout(sp, ot.precision).total;
+    if (need > (size_t)KL_NOALLOC_SCRATCH_BYTES)
+        return fail(KL_ENOMEM, "depth %d (prefix %d, tail %d letters) needs %zu bytes of tables; the scratch array "
+                    "holds %zu", depth, sp.k, sp.r, need, (size_t)KL_NOALLOC_SCRATCH_BYTES);
+    Gens G;
+    if ((rc = make_gens(ta, tb, &G))) return rc;
+    void* p = nullptr;
+    if ((rc = scratch_address(&p))) return rc;
+    const TableBuf buf{(unsigned char*)p, (size_t)KL_NOALLOC_SCRATCH_BYTES};
+    return render_run(G, depth, window, image_out, o, span, &buf);
 }
 
 int kl_render_group_ex(const kl_c64* ab, int depth, const kl_window* window, uint32_t* image_out,

@@ -82,6 +82,7 @@ def lib():
         L.kl_decode_ex.argtypes = [u64, u64, i, vp, vp]
         L.kl_render.argtypes = [c64, c64, i, W, vp]
         L.kl_render_ex.argtypes = [c64, c64, i, W, vp, O]
+        L.kl_render_noalloc.argtypes = [c64, c64, i, W, vp, O]
         L.kl_render_many.argtypes = [i, C, C, ctypes.POINTER(i), W, vp]
         L.kl_render_many_ex.argtypes = [i, C, C, ctypes.POINTER(i), W, vp, O]
         L.kl_eval.argtypes = [c64, c64, i, vp, u64, i, vp]
@@ -105,7 +106,7 @@ def lib():
         L.kl_strerror.restype = ctypes.c_char_p
         L.kl_last_error.argtypes = []
         L.kl_last_error.restype = ctypes.c_char_p
-        for f in ("kl_decode", "kl_decode_ex", "kl_render", "kl_render_ex", "kl_render_many",
+        for f in ("kl_decode", "kl_decode_ex", "kl_render", "kl_render_ex", "kl_render_noalloc", "kl_render_many",
                   "kl_render_many_ex", "kl_eval", "kl_eval_ex", "kl_generators", "kl_plan", "kl_autotune",
                   "kl_group_seeds", "kl_maskit_generators", "kl_render_group_ex", "kl_eval_group_ex"):
             getattr(L, f).restype = i
@@ -276,6 +277,16 @@ def render(ta, tb, depth: int, window, image: torch.Tensor | None = None, **opts
     ptr = _dev_ptr(image, "image", _U32, w.width * w.height)
     o = make_opts(**opts)
     _check(lib().kl_render_ex(_c(ta), _c(tb), int(depth), ctypes.byref(w), ptr, ctypes.byref(o)))
+    return image
+
+
+def render_noalloc(ta, tb, depth: int, window, image: torch.Tensor, **opts) -> torch.Tensor:
+    """kl_render_noalloc: kl_render_ex of one depth with the tables in the
+    library's scratch array; the caller supplies the image."""
+    w = make_window(window)
+    ptr = _dev_ptr(image, "image", _U32, w.width * w.height)
+    o = make_opts(**opts)
+    _check(lib().kl_render_noalloc(_c(ta), _c(tb), int(depth), ctypes.byref(w), ptr, ctypes.byref(o)))
     return image
 
 

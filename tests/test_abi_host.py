@@ -214,6 +214,18 @@ def test_render_many_argument_errors():
     assert L.kl_render_many_ex(n, ta, tb, good, ctypes.byref(w), FAKE, ctypes.byref(o)) == kl.KL_EINVAL
 
 
+def test_noalloc_rejects_before_touching_the_device():
+    good = _win()
+    # depth 37: an 11-letter prefix table (15 MB) exceeds the scratch array
+    assert L.kl_render_noalloc(kl._c(wl.C2_TA), kl._c(wl.C2_TB), 37, ctypes.byref(good), FAKE, None) == kl.KL_ENOMEM
+    assert "scratch" in L.kl_last_error().decode()
+    o = kl.make_opts(min_depth=3, use_stream=False)
+    assert L.kl_render_noalloc(kl._c(wl.C2_TA), kl._c(wl.C2_TB), 10, ctypes.byref(good), FAKE,
+                               ctypes.byref(o)) == kl.KL_EINVAL
+    assert L.kl_render_noalloc(kl._c(wl.C2_TA), kl._c(wl.C2_TB), 10, ctypes.byref(good), None, None) == kl.KL_EINVAL
+    assert L.kl_render_noalloc(kl._c(0), kl._c(0), 10, ctypes.byref(good), FAKE, None) == kl.KL_ESINGULAR
+
+
 def test_strerror_names_every_code():
     for code in (0, -1, -2, -3, -4, -5):
         assert L.kl_strerror(code)

@@ -1,0 +1,73 @@
+"""kl_render_noalloc (the entry point for callers that cannot allocate device
+memory) against kl_render_ex, through the C ABI: two calls in a row, the
+second with a smaller input, each image and dropped count bit for bit those
+of kl_render_ex on the same arguments.  Calls in between with other splits,
+seed modes and index ranges rewrite the shared scratch array first."""
+import numpy as np
+import pytest
+import torch
+
+from paper_1709_08018_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+if torch.cuda.is_available():
+    from paper_1709_08018_amd import kl
+
+
+def _pair(ta, tb, depth, win, **opts):
+    img = kl.new_image(win)
+    img.fill_(7)   # garbage: the call clears it (or accumulates into it when asked)
+    d = torch.full((1,), 5, dtype=torch.int64, device="cuda")
+    kl.render_noalloc(ta, tb, depth, win, image=img, dropped=d, **opts)
+    ref = kl.new_image(win)
+    ref.fill_(7)
+    dr = torch.full((1,), 5, dtype=torch.int64, device="cuda")
+    kl.render(ta, tb, depth, win, image=ref, dropped=dr, **opts)
+    return img, d, ref, dr
+
+
+def test_noalloc_equals_render_ex_on_two_calls_the_second_smaller():
+    W = wl.QUASIFUCHSIAN_D18
+    win = W.window.as_tuple()
+    img, d, ref, dr = _pair(W.ta, W.tb, 18, win)
+    assert torch.equal(img, ref)
+    assert int(d.item()) == int(dr.item())
+    assert int(kl.as_u32(img).astype(np.int64).sum()) + int(d.item()) == kl.num_words(18)
+    # second call: a smaller render with another split and precision
+    win2 = (-2.0, 2.0, -2.0, 2.0, 256, 192)
+    img2, d2, ref2, dr2 = _pair(wl.C1_TA, wl.C1_TB, 12, win2, precision="fp64", tail_len=4)
+    assert torch.equal(img2, ref2)
+    assert int(d2.item()) == int(dr2.item())
+    assert int(kl.as_u32(img2).astype(np.int64).sum()) + int(d2.item()) == kl.num_words(12)
+
+
+@pytest.mark.parametrize("opts", [dict(seed="all"), dict(first=12345, count=5_000_001),
+                                  dict(block_bounds=True), dict(hist_mode="lds"), dict(precision="fp64")])
+def test_noalloc_options_equal_render_ex(opts):
+    W = wl.QUASIFUCHSIAN_D18
+    ta, tb, depth, win = W.ta, W.tb, 16, (-1.5, 1.5, -1.5, 1.5, 512, 512)
+    img, d, ref, dr = _pair(ta, tb, depth, win, **opts)
+    assert torch.equal(img, ref)
+    assert int(d.item()) == int(dr.item())
+
+
+def test_noalloc_accumulates_like_render_ex():
+    W = wl.QUASIFUCHSIAN_D18
+    win = (-1.5, 1.5, -1.5, 1.5, 300, 200)
+    n = kl.num_words(14)
+    a = kl.new_image(win)
+    kl.render_noalloc(W.ta, W.tb, 14, win, image=a, first=0, count=n // 3)
+    kl.render_noalloc(W.ta, W.tb, 14, win, image=a, first=n // 3, count=n - n // 3, accumulate=True)
+    assert torch.equal(a, kl.render(W.ta, W.tb, 14, win))
+
+
+def test_noalloc_rejects_what_does_not_fit():
+    win = (-1.5, 1.5, -1.5, 1.5, 64, 64)
+    img = kl.new_image(win)
+    with pytest.raises(kl.KLError) as e:
+        kl.render_noalloc(wl.C2_TA, wl.C2_TB, 37, win, image=img)
+    assert e.value.code == kl.KL_ENOMEM
+    with pytest.raises(kl.KLError) as e:
+        kl.render_noalloc(wl.C2_TA, wl.C2_TB, 10, win, image=img, min_depth=1)
+    assert e.value.code == kl.KL_EINVAL
