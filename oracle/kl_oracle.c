@@ -980,3 +980,182 @@ int oracle_cayley_render(const uint8_t *table, int n_states, int n_symbols, cons
     if (near_edge) *near_edge = near;
     return 0;
 }
+
+/* ------------------------------------------------------------------ */
+/* probabilistic rendering: one orbit per walker (Section 4)           */
+/* ------------------------------------------------------------------ */
+
+/* Section 4 describes the probabilistic approach only in words: a single
+ * word grows as generators are appended through random picks under some
+ * probability law, and its orbit is drawn.  The reading taken here:
+ *   - a walker's first letter c_0 is uniform over a, b, A, B, and its
+ *     orbit starts at the attracting fixed point of c_0;
+ *   - step n >= 1 picks c_n uniformly among the three letters that do not
+ *     undo c_{n-1} (the word stays reduced) and maps the point:
+ *     z_n = G_{c_n}(z_{n-1});
+ *   - after burn_in steps, the next n_steps points are drawn.
+ * So z_n is the value of the reduced word c_n ... c_1 c_0 (rightmost letter
+ * applied first, from the fixed point of its last letter), the word value of
+ * Section 1.  The commutator "boost" of the Fig. 3 caption is not applied.
+ *
+ * Random numbers: Philox4x64-10 (J. Salmon, M. Moraes, R. Dror, D. Shaw,
+ * "Parallel random numbers: as easy as 1, 2, 3", SC'11).  A counter of four
+ * 64-bit words is encrypted under a key of two by ten rounds; a round takes
+ * the 128-bit products of words 0 and 2 with two multipliers and mixes their
+ * halves with words 1 and 3 and the key, and the key is advanced by two
+ * Weyl constants between rounds. */
+static const uint64_t PHILOX_M0 = 0xD2E7470EE14C6C93ull, PHILOX_M1 = 0xCA5A826395121157ull;
+static const uint64_t PHILOX_W0 = 0x9E3779B97F4A7C15ull, PHILOX_W1 = 0xBB67AE8584CAA73Bull;
+
+static void mul_full64(uint64_t a, uint64_t b, uint64_t *hi, uint64_t *lo)
+{
+    __extension__ unsigned __int128 p = (unsigned __int128)a * b;
+    *hi = (uint64_t)(p >> 64);
+    *lo = (uint64_t)p;
+}
+
+int oracle_philox4x64_10(const uint64_t *ctr, const uint64_t *key, uint64_t *out)
+{
+    if (!ctr || !key || !out) return -1;
+    uint64_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+    uint64_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; round++) {
+        if (round > 0) {
+            k0 += PHILOX_W0;
+            k1 += PHILOX_W1;
+        }
+        uint64_t hi0, lo0, hi1, lo1;
+        mul_full64(PHILOX_M0, x0, &hi0, &lo0);
+        mul_full64(PHILOX_M1, x2, &hi1, &lo1);
+        uint64_t y0 = hi1 ^ x1 ^ k0, y1 = lo1, y2 = hi0 ^ x3 ^ k1, y3 = lo0;
+        x0 = y0;
+        x1 = y1;
+        x2 = y2;
+        x3 = y3;
+    }
+    out[0] = x0;
+    out[1] = x1;
+    out[2] = x2;
+    out[3] = x3;
+    return 0;
+}
+
+/* The n-th 32-bit random value of walker `walker`: block n / 8 is Philox4x64-10
+ * of the counter (n / 8, walker, 0, 0) under the key (seed, 0); its 64-bit
+ * outputs r0..r3 give the values r0 low, r0 high, r1 low, ..., r3 high. */
+static uint32_t walk_value(uint64_t seed, uint64_t walker, uint64_t n)
+{
+    uint64_t ctr[4] = {n / 8, walker, 0, 0}, key[2] = {seed, 0}, r[4];
+    oracle_philox4x64_10(ctr, key, r);
+    uint64_t w = r[(n % 8) / 2];
+    return (uint32_t)((n % 2) ? (w >> 32) : w);
+}
+
+/* Letters c_0 .. c_{n-1} of a walker: c_0 = the value's top two bits (a
+ * uniform letter); for k >= 1 the value x picks t = floor(3 x / 2^32) in
+ * {0, 1, 2} and c_k is the t-th letter, in code order, other than the
+ * inverse of c_{k-1}. */
+int oracle_walk_letters(uint64_t seed, uint64_t walker, uint32_t n, uint8_t *letters)
+{
+    if (!letters && n) return -1;
+    for (uint32_t k = 0; k < n; k++) {
+        uint32_t x = walk_value(seed, walker, k);
+        if (k == 0) {
+            letters[0] = (uint8_t)(x >> 30);
+            continue;
+        }
+        uint32_t t = (uint32_t)(((uint64_t)x * 3u) >> 32);
+        int skip = INVERSE[letters[k - 1]];
+        int c = -1;
+        for (int cand = 0, seen = 0; cand < 4; cand++) {
+            if (cand == skip) continue;
+            if (seen == (int)t) {
+                c = cand;
+                break;
+            }
+            seen++;
+        }
+        letters[k] = (uint8_t)c;
+    }
+    return 0;
+}
+
+/* Points of walkers first_walker .. first_walker + n_walkers - 1: for each,
+ * z_{burn_in + 1} .. z_{burn_in + n_steps}, walker-major, each step applied
+ * to the previous point literally, z <- (a z + b) / (c z + d) on the
+ * Riemann sphere (infinity as (1 : 0)). */
+static int walk_run(const group *g, uint64_t seed, uint64_t walker, uint32_t burn_in, uint32_t n_steps,
+                    cplx *z_out)
+{
+    const uint32_t n = 1 + burn_in + n_steps;
+    uint8_t *c = (uint8_t *)malloc(n);
+    if (!c) return -1;
+    oracle_walk_letters(seed, walker, n, c);
+    cplx u = g->fu[c[0]], v = g->fv[c[0]];
+    for (uint32_t k = 1; k < n; k++) {
+        cplx z = mobius_h(g->g[c[k]], u, v);
+        if (finite_c(z)) {
+            u = z;
+            v = 1;
+        } else {
+            u = 1;
+            v = 0;
+        }
+        if (k > burn_in) z_out[k - burn_in - 1] = point_of(u, v);
+    }
+    free(c);
+    return 0;
+}
+
+int oracle_walk_points(const double *gens, const double *seeds, uint64_t seed, uint64_t first_walker,
+                       uint64_t n_walkers, uint32_t burn_in, uint32_t n_steps, double *z_out)
+{
+    if (!gens || !seeds || (!z_out && n_walkers && n_steps)) return -1;
+    if (first_walker + n_walkers < first_walker) return -1;
+    group g;
+    group_from_group_arrays(gens, seeds, &g);
+    cplx *z = (cplx *)malloc((size_t)(n_steps ? n_steps : 1) * sizeof(cplx));
+    if (!z) return -1;
+    for (uint64_t w = 0; w < n_walkers; w++) {
+        if (walk_run(&g, seed, first_walker + w, burn_in, n_steps, z)) {
+            free(z);
+            return -1;
+        }
+        for (uint32_t s = 0; s < n_steps; s++) put_c(z_out + 2 * (w * n_steps + s), z[s]);
+    }
+    free(z);
+    return 0;
+}
+
+/* The walkers' points binned as every render bins (bin_point). */
+int oracle_walk_render(const double *gens, const double *seeds, uint64_t seed, uint64_t first_walker,
+                       uint64_t n_walkers, uint32_t burn_in, uint32_t n_steps,
+                       double x0, double x1, double y0, double y1, uint32_t width, uint32_t height,
+                       double edge_tol, uint32_t *image, uint64_t *dropped, uint64_t *near_edge)
+{
+    if (!gens || !seeds || !image || width == 0 || height == 0) return -1;
+    if (first_walker + n_walkers < first_walker) return -1;
+    group g;
+    group_from_group_arrays(gens, seeds, &g);
+    window win = {x0, x1, y0, y1, width, height, edge_tol};
+    cplx *z = (cplx *)malloc((size_t)(n_steps ? n_steps : 1) * sizeof(cplx));
+    if (!z) return -1;
+    uint64_t drop = 0, near = 0;
+    for (uint64_t w = 0; w < n_walkers; w++) {
+        if (walk_run(&g, seed, first_walker + w, burn_in, n_steps, z)) {
+            free(z);
+            return -1;
+        }
+        for (uint32_t s = 0; s < n_steps; s++) {
+            uint32_t bin;
+            int ne;
+            if (bin_point(&win, z[s], &bin, &ne)) image[bin] += 1;
+            else drop++;
+            near += (uint64_t)ne;
+        }
+    }
+    free(z);
+    if (dropped) *dropped = drop;
+    if (near_edge) *near_edge = near;
+    return 0;
+}

@@ -102,6 +102,22 @@ int oracle_cayley_render(const uint8_t *table, int n_states, int n_symbols, cons
                          uint32_t width, uint32_t height, double edge_tol, uint32_t *image,
                          uint64_t *dropped, uint64_t *near_edge);
 
+/* Probabilistic rendering (Section 4): random walks.  Walker w's letters
+ * come from Philox4x64-10 under the key (seed, 0), block j at the counter
+ * (j, w, 0, 0), eight 32-bit values a block (low, high half of each output);
+ * c_0 = value >> 30, and c_k (k >= 1) is the floor(3 value / 2^32)-th letter
+ * other than the inverse of c_{k-1}.  The walk starts at the attracting
+ * fixed point of c_0 and applies G_{c_k} at step k; points z_{burn_in+1} ..
+ * z_{burn_in+n_steps} are drawn (walker-major in z_out). */
+int oracle_philox4x64_10(const uint64_t *ctr, const uint64_t *key, uint64_t *out);
+int oracle_walk_letters(uint64_t seed, uint64_t walker, uint32_t n, uint8_t *letters);
+int oracle_walk_points(const double *gens, const double *seeds, uint64_t seed, uint64_t first_walker,
+                       uint64_t n_walkers, uint32_t burn_in, uint32_t n_steps, double *z_out);
+int oracle_walk_render(const double *gens, const double *seeds, uint64_t seed, uint64_t first_walker,
+                       uint64_t n_walkers, uint32_t burn_in, uint32_t n_steps,
+                       double x0, double x1, double y0, double y1, uint32_t width, uint32_t height,
+                       double edge_tol, uint32_t *image, uint64_t *dropped, uint64_t *near_edge);
+
 #ifdef __cplusplus
 }
 #endif

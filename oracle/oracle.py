@@ -85,6 +85,14 @@ def lib():
                                            u32p, u64p, u64p]
         for f in (L.oracle_cayley_unrank, L.oracle_cayley_scan, L.oracle_cayley_eval, L.oracle_cayley_render):
             f.restype = ctypes.c_int
+        u64 = ctypes.c_uint64
+        L.oracle_philox4x64_10.argtypes = [u64p, u64p, u64p]
+        L.oracle_walk_letters.argtypes = [u64, u64, ctypes.c_uint32, u8p]
+        L.oracle_walk_points.argtypes = [dp, dp, u64, u64, u64, ctypes.c_uint32, ctypes.c_uint32, dp]
+        L.oracle_walk_render.argtypes = [dp, dp, u64, u64, u64, ctypes.c_uint32, ctypes.c_uint32,
+                                         d, d, d, d, ctypes.c_uint32, ctypes.c_uint32, d, u32p, u64p, u64p]
+        for f in (L.oracle_philox4x64_10, L.oracle_walk_letters, L.oracle_walk_points, L.oracle_walk_render):
+            f.restype = ctypes.c_int
         for f in (L.oracle_unrank, L.oracle_enumerate, L.oracle_generators,
                   L.oracle_word_value, L.oracle_eval, L.oracle_render, L.oracle_group_recipe,
                   L.oracle_group_explicit, L.oracle_group_maskit, L.oracle_eval_group,
@@ -318,4 +326,48 @@ def cayley_render(c: Cayley, depth: int, window, *, seed: int = -1, min_depth: i
                                       depth if min_depth is None else min_depth, x0, x1, y0, y1, W, H, edge_tol,
                                       _ptr(image, ctypes.c_uint32), ctypes.byref(dropped),
                                       ctypes.byref(near)), "cayley_render")
+    return image, int(dropped.value), int(near.value)
+
+
+# ---------------------------------------------------------------- random walks (Section 4)
+def philox4x64_10(counter, key) -> np.ndarray:
+    """Philox4x64-10 of a counter (4 uint64) under a key (2 uint64): 4 uint64."""
+    c = np.ascontiguousarray(counter, np.uint64)
+    k = np.ascontiguousarray(key, np.uint64)
+    out = np.zeros(4, np.uint64)
+    _check(lib().oracle_philox4x64_10(_ptr(c, ctypes.c_uint64), _ptr(k, ctypes.c_uint64),
+                                      _ptr(out, ctypes.c_uint64)), "philox")
+    return out
+
+
+def walk_letters(seed: int, walker: int, n: int) -> np.ndarray:
+    """Letters c_0 .. c_{n-1} of one walker (c_0 first, i.e. rightmost)."""
+    out = np.zeros(max(n, 1), np.uint8)
+    _check(lib().oracle_walk_letters(seed, walker, n, _ptr(out, ctypes.c_uint8)), "walk_letters")
+    return out[:n]
+
+
+def walk_points(group: Group, seed: int, first_walker: int, n_walkers: int, burn_in: int,
+                n_steps: int) -> np.ndarray:
+    """Drawn points of the walkers, (n_walkers, n_steps) complex (inf at infinity)."""
+    g, s = group._arrays()
+    z = np.zeros(2 * max(n_walkers * n_steps, 1))
+    _check(lib().oracle_walk_points(_ptr(g, ctypes.c_double), _ptr(s, ctypes.c_double), seed, first_walker,
+                                    n_walkers, burn_in, n_steps, _ptr(z, ctypes.c_double)), "walk_points")
+    return z.view(np.complex128)[:n_walkers * n_steps].reshape(n_walkers, n_steps)
+
+
+def walk_render(group: Group, seed: int, first_walker: int, n_walkers: int, burn_in: int, n_steps: int,
+                window, *, edge_tol: float = 0.0, image: np.ndarray | None = None):
+    """The walkers' points binned; returns (image, dropped, near_edge)."""
+    g, s = group._arrays()
+    x0, x1, y0, y1, W, H = window
+    if image is None:
+        image = np.zeros((H, W), np.uint32)
+    dropped = ctypes.c_uint64(0)
+    near = ctypes.c_uint64(0)
+    _check(lib().oracle_walk_render(_ptr(g, ctypes.c_double), _ptr(s, ctypes.c_double), seed, first_walker,
+                                    n_walkers, burn_in, n_steps, x0, x1, y0, y1, W, H, edge_tol,
+                                    _ptr(image, ctypes.c_uint32), ctypes.byref(dropped), ctypes.byref(near)),
+           "walk_render")
     return image, int(dropped.value), int(near.value)

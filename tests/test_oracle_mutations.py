@@ -8,7 +8,10 @@ term, the other root of the trace quadratic, a sign in Maskit's
 generators, the repelling point of an affine map as its seed, the wrong
 generator's seed fed to every word, a seed at infinity treated as finite,
 a transposed good-set update, the wrong start state of the empty walk and
-a scan that reads words left to right in the Cayley-table path),
+a scan that reads words left to right in the Cayley-table path; in the
+random walks a Philox multiplier, the key schedule, swapped product
+halves, the stream's half order, a skip of the letter itself instead of
+its inverse, inverse maps, and the seed of the wrong letter),
 builds it with gcc, and runs the pin tests against the planted build in a
 child process.  The pins pass
 on the real reference and must fail on every planted copy.
@@ -46,9 +49,17 @@ MUTATIONS = {
     "cayley_empty_walk_state": ("c->C[0][0] = 1;", "c->C[0][1] = 1;"),
     "cayley_scan_left_to_right": ("for (int j = depth - 1; j >= 0 && ok; j--) {",
                                   "for (int j = 0; j < depth && ok; j++) {"),
+    "philox_multiplier": ("PHILOX_M0 = 0xD2E7470EE14C6C93ull", "PHILOX_M0 = 0xD2E7470EE14C6C95ull"),
+    "philox_key_bump_late": ("if (round > 0) {", "if (round > 1) {"),
+    "philox_halves_swapped": ("uint64_t y0 = hi1 ^ x1 ^ k0, y1 = lo1, y2 = hi0 ^ x3 ^ k1, y3 = lo0;",
+                              "uint64_t y0 = lo1 ^ x1 ^ k0, y1 = hi1, y2 = lo0 ^ x3 ^ k1, y3 = hi0;"),
+    "walk_value_halves": ("return (uint32_t)((n % 2) ? (w >> 32) : w);", "return (uint32_t)((n % 2) ? w : (w >> 32));"),
+    "walk_skips_the_letter_itself": ("int skip = INVERSE[letters[k - 1]];", "int skip = letters[k - 1];"),
+    "walk_applies_inverses": ("cplx z = mobius_h(g->g[c[k]], u, v);", "cplx z = mobius_h(g->g[INVERSE[c[k]]], u, v);"),
+    "walk_seed_of_second_letter": ("cplx u = g->fu[c[0]], v = g->fv[c[0]];", "cplx u = g->fu[c[1]], v = g->fv[c[1]];"),
 }
 PINS = [os.path.join(ROOT, "tests", f) for f in ("test_oracle_pins.py", "test_oracle_groups.py",
-                                                  "test_oracle_cayley.py")]
+                                                  "test_oracle_cayley.py", "test_oracle_walk.py")]
 
 
 @pytest.mark.parametrize("name", sorted(MUTATIONS))
