@@ -538,6 +538,80 @@ def leg_surrogate(args):
     return res
 
 
+def cpu_baseline_walk(W, img):
+    """The oracle's walk render of the Fig. 3 points, timed on one thread,
+    and the GPU's FP64 image against it."""
+    import numpy as np
+    ref = _oracle()
+    g = ref.group_maskit(W.mu)
+    t0 = time.perf_counter()
+    rimg, _, near = ref.walk_render(g, W.seed, 0, W.n_walkers, W.burn_in, W.n_steps, W.window.as_tuple(),
+                                    edge_tol=1e-7)
+    dt = time.perf_counter() - t0
+    return {"kind": "oracle", "value": round(W.points / dt / 1e9, 5), "unit": "Gpoints/s", "cores": 1,
+            "sample": f"the full workload ({W.points} points)", "seconds": round(dt, 3),
+            "fp64_l1_vs_oracle": int(np.abs(img - rimg.astype(np.int64)).sum()), "oracle_near_edge_words": int(near)}
+
+
+def leg_walk(args):
+    """The probabilistic approach (Section 4, Fig. 3): random walks in
+    Maskit's group at mu = -0.097 + 1.838i, 2^20 drawn points, FP32 and FP64,
+    against the indexed renderer on the same group, window and image: the
+    depth-13 limit set (2,125,764 words) beside a walk of as many points, and
+    2^30 points beside the depth-19 limit set.  Coverage: the occupied
+    pixels (count > 0) of each image, and the IoU of the two occupancies."""
+    import numpy as np
+    import torch
+
+    from paper_1709_08018_amd import kl
+    from paper_1709_08018_amd import workloads as wl
+
+    def occ(t):
+        return kl.as_u32(t) > 0
+
+    def iou(a, b):
+        u = int((a | b).sum())
+        return 1.0 if u == 0 else int((a & b).sum()) / u
+
+    W = wl.WALK_FIG3
+    ab = kl.maskit_generators(W.mu)
+    win = W.window.as_tuple()
+    image = kl.new_image(win)
+    out = {"workload": W.name, "mu": [W.mu.real, W.mu.imag], "points": W.points, "walkers": W.n_walkers,
+           "steps": W.n_steps, "burn_in": W.burn_in, "seed": W.seed,
+           "reading": "first letter uniform, each step uniform over the three letters that keep the word "
+                      "reduced, from the first letter's attracting fixed point; no commutator boost"}
+    steps = max(5, args.steps // 4)
+    for prec in ("fp32", "fp64"):
+        ms = _time(lambda: kl.walk_render(ab, W.seed, 0, W.n_walkers, W.burn_in, W.n_steps, win, image=image,
+                                          precision=prec), steps, 3)
+        out[prec] = {"ms": round(ms, 4), "gpoints_per_s": round(W.points / ms / 1e6, 3)}
+    dropped = torch.zeros(1, dtype=torch.int64, device="cuda")
+    kl.walk_render(ab, W.seed, 0, W.n_walkers, W.burn_in, W.n_steps, win, image=image, precision="fp64",
+                   dropped=dropped)
+    img = kl.as_u32(image).astype(np.int64)
+    out["points_in_window"] = int(img.sum())
+    out["dropped"] = int(dropped.item())
+    out["cpu_baseline"] = cpu_baseline_walk(W, img)
+    # equal point counts: the indexed limit set against a walk of as many points
+    cmp = []
+    for Wc, depth in ((wl.WALK_D13_POINTS, 13), (wl.WALK_LARGE, 19)):
+        idx_img = kl.new_image(win)
+        walk_img = kl.new_image(win)
+        ms_i = _time(lambda: kl.render_group(ab, depth, win, image=idx_img), steps, 3)
+        ms_w = _time(lambda: kl.walk_render(ab, Wc.seed, 0, Wc.n_walkers, Wc.burn_in, Wc.n_steps, win,
+                                            image=walk_img), steps, 3)
+        oi, ow = occ(idx_img), occ(walk_img)
+        cmp.append({"indexed_depth": depth, "indexed_words": kl.num_words(depth), "walk": Wc.name,
+                    "walk_points": Wc.points, "indexed_ms": round(ms_i, 4), "walk_ms": round(ms_w, 4),
+                    "indexed_gwords_per_s": round(kl.num_words(depth) / ms_i / 1e6, 2),
+                    "walk_gpoints_per_s": round(Wc.points / ms_w / 1e6, 2),
+                    "occupied_pixels": {"indexed": int(oi.sum()), "walk": int(ow.sum())},
+                    "occupancy_iou": round(iou(oi, ow), 4)})
+    out["indexed_vs_walk"] = cmp
+    return out
+
+
 def leg_calib(args):
     """Instruction-throughput calibration of the VALU roofline (libkl_calib.so):
     SIMD cycles per wave64 instruction of each class the renderer's word loop
@@ -625,7 +699,7 @@ def main():
                     help="untimed steps after the clock ramp (CLOCK_RAMP_MS of untimed steps first)")
     ap.add_argument("--workload", default="quasifuchsian_d18",
                     choices=["quasifuchsian_d18", "quasifuchsian_d22", "decode", "bounded", "batch256", "fuchsian_tiling_d10",
-                             "maskit_tiling_d14", "cayley", "surrogate", "hist", "calib"])
+                             "maskit_tiling_d14", "cayley", "surrogate", "hist", "calib", "walk"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="after the steps, copy 256 MiB device to device twice (a kernel of known HBM "
@@ -645,7 +719,7 @@ def main():
     torch.cuda.set_device(0)
     legs = {"quasifuchsian_d22": leg_d22, "decode": leg_decode, "bounded": leg_bounded, "batch256": leg_batch, "fuchsian_tiling_d10": leg_tiling,
             "maskit_tiling_d14": leg_maskit, "cayley": leg_cayley, "surrogate": leg_surrogate, "hist": leg_hist,
-            "calib": leg_calib}
+            "calib": leg_calib, "walk": leg_walk}
     if args.workload in legs:
         print(json.dumps(legs[args.workload](args)), flush=True)
         return

@@ -298,6 +298,55 @@ int kl_render_group_ex(const kl_c64 *ab, int depth, const kl_window *window, uin
 int kl_eval_group_ex(const kl_c64 *ab, int depth, const uint64_t *idx, uint64_t n,
                      const kl_window *window, kl_c64 *z_out, const kl_opts *opts);
 
+/* Random walks: the probabilistic approach of Section 4 (the rendering of
+ * Fig. 3), the paper's alternative to its indexed method.  One word grows by
+ * random picks of generators and the orbit of a point under it is drawn.
+ * Walker w (first_walker <= w < first_walker + n_walkers) takes letters c_0,
+ * c_1, ... (codes as everywhere: 0=a 1=b 2=A 3=B):
+ *   c_0       uniform over the four letters: the top two bits of value 0;
+ *   c_k       (k >= 1) uniform over the three letters other than the
+ *             inverse of c_{k-1} (the word stays reduced): the
+ *             floor(3 x / 2^32)-th of them in code order, x = value k;
+ * where value k is the 32-bit half k % 2 (low half first) of 64-bit output
+ * (k % 8) / 2 of Philox4x64-10 (Salmon et al., SC'11) at the counter
+ * (k / 8, w, 0, 0) under the key (seed, 0).  The walker starts at the
+ * attracting fixed point of c_0 and applies G_{c_k} at step k, so its point
+ * after step k is the value of the reduced word c_k ... c_1 c_0 (Section 1).
+ * It draws its points after steps burn_in + 1 .. burn_in + n_steps.  The
+ * commutator "boost" of Fig. 3's caption is not applied.
+ * A group is given by its generators a, b as for kl_render_group_ex. */
+typedef struct {
+    uint64_t seed;          /* Philox key (seed, 0) */
+    uint64_t first_walker;  /* walkers first_walker .. first_walker + n_walkers - 1 */
+    uint64_t n_walkers;
+    uint32_t burn_in;       /* steps taken before the first drawn point */
+    uint32_t n_steps;       /* points drawn per walker */
+} kl_walk;
+
+/* kl_walk_letters: letters c_0 .. c_{burn_in + n_steps} of each walker into
+ * letters_out (device, n_walkers * (1 + burn_in + n_steps) bytes,
+ * walker-major), asynchronously on `stream` (a hipStream_t).
+ * Errors: KL_EINVAL (NULL walk or letters_out, 1 + burn_in + n_steps above
+ * 2^32 - 1), KL_ERANGE (walker indices past 2^64), KL_EDEVICE. */
+int kl_walk_letters(const kl_walk *walk, uint8_t *letters_out, void *stream);
+
+/* kl_walk_eval_ex: the drawn points (z_out: device, n_walkers * n_steps,
+ * walker-major), or with a window their pixel coordinates, computed as
+ * kl_walk_render_ex computes them.  opts: precision, stream.
+ * Errors: as kl_walk_letters, KL_EINVAL (bad window or option), and as
+ * kl_group_seeds. */
+int kl_walk_eval_ex(const kl_c64 *ab, const kl_walk *walk, const kl_window *window, kl_c64 *z_out,
+                    const kl_opts *opts);
+
+/* kl_walk_render_ex: the drawn points binned into image_out (device,
+ * width * height uint32, cleared first unless accumulate) as every render
+ * bins; dropped_out (if set) receives the points outside the window or not
+ * finite.  image + dropped = n_walkers * n_steps.  opts: precision,
+ * accumulate, stream, dropped_out.
+ * Errors: as kl_walk_eval_ex. */
+int kl_walk_render_ex(const kl_c64 *ab, const kl_walk *walk, const kl_window *window, uint32_t *image_out,
+                      const kl_opts *opts);
+
 /* Indexed Cayley tables (Section 5, Tables 2 and 3): words over any finite
  * presentation the table encodes, drawn with one Moebius map per symbol.
  *   n_states   2..16; state 0 is where a walk starts and, reached again,

@@ -1111,7 +1111,7 @@ int oracle_walk_points(const double *gens, const double *seeds, uint64_t seed, u
                        uint64_t n_walkers, uint32_t burn_in, uint32_t n_steps, double *z_out)
 {
     if (!gens || !seeds || (!z_out && n_walkers && n_steps)) return -1;
-    if (first_walker + n_walkers < first_walker) return -1;
+    if (n_walkers && n_walkers - 1 > UINT64_MAX - first_walker) return -1;
     group g;
     group_from_group_arrays(gens, seeds, &g);
     cplx *z = (cplx *)malloc((size_t)(n_steps ? n_steps : 1) * sizeof(cplx));
@@ -1134,7 +1134,7 @@ int oracle_walk_render(const double *gens, const double *seeds, uint64_t seed, u
                        double edge_tol, uint32_t *image, uint64_t *dropped, uint64_t *near_edge)
 {
     if (!gens || !seeds || !image || width == 0 || height == 0) return -1;
-    if (first_walker + n_walkers < first_walker) return -1;
+    if (n_walkers && n_walkers - 1 > UINT64_MAX - first_walker) return -1;
     group g;
     group_from_group_arrays(gens, seeds, &g);
     window win = {x0, x1, y0, y1, width, height, edge_tol};

@@ -361,7 +361,7 @@ static int build_tables(const Gens& G, const Split& sp, int precision, int force
                         SetTables* out, uint32_t* clear_image = nullptr, uint64_t bins = 0,
                         uint64_t* clear_dropped = nullptr, const TableBuf* buf = nullptr) {
     const TableLayout L = table_layout(sp, precision);
-    const uint64_t np = L.np, nt = L.nt;
+    const uint64_t np = L.np;
     const size_t off_last = L.off_last, off_aff = L.off_aff, off_hom = L.off_hom, off_flags = L.off_flags;
     const uint32_t n_flags = L.n_flags;
     unsigned char* base = nullptr;
@@ -1068,6 +1068,104 @@ int kl_eval_group_ex(const kl_c64* ab, int depth, const uint64_t* idx, uint64_t 
     Gens G;
     if ((rc = make_gens_ab(ab, &G))) return rc;
     return eval_run(G, sp, idx, n, window, z_out, o);
+}
+
+// ------------------------------------------------------------------ random walks (Section 4)
+}  // extern "C"
+
+namespace kl {
+
+// The walk's shape, checked before anything is enqueued; n_total letters per
+// walker and n_points drawn points in all.
+static int check_walk(const kl_walk* walk, uint64_t* n_total, uint64_t* n_points) {
+    if (!walk) return fail(KL_EINVAL, "walk is NULL");
+    // the last walker, first_walker + n_walkers - 1, must be below 2^64
+    if (walk->n_walkers && walk->n_walkers - 1 > UINT64_MAX - walk->first_walker)
+        return fail(KL_ERANGE, "walkers [%llu, +%llu) pass 2^64", (unsigned long long)walk->first_walker,
+                    (unsigned long long)walk->n_walkers);
+    const uint64_t nt = 1ull + walk->burn_in + walk->n_steps;
+    if (nt > 0xFFFFFFFFull) return fail(KL_EINVAL, "1 + burn_in + n_steps exceeds 2^32 - 1");
+    if (walk->n_walkers && (walk->n_walkers > UINT64_MAX / nt))
+        return fail(KL_ERANGE, "walkers times letters exceeds 2^64");
+    *n_total = nt;
+    *n_points = walk->n_walkers * walk->n_steps;
+    return KL_OK;
+}
+
+static WalkJob walk_job(const Gens& G, const kl_walk* walk, const kl_window* window, int precision, int mode) {
+    WalkJob j{};
+    j.gens = G;
+    j.fold = make_fold(window, 0);
+    j.precision = precision;
+    j.mode = mode;
+    j.seed = walk->seed;
+    j.first_walker = walk->first_walker;
+    j.n_walkers = walk->n_walkers;
+    j.burn_in = walk->burn_in;
+    j.n_steps = walk->n_steps;
+    return j;
+}
+
+}  // namespace kl
+
+extern "C" {
+
+int kl_walk_letters(const kl_walk* walk, uint8_t* letters_out, void* stream) {
+    uint64_t nt, np;
+    int rc = check_walk(walk, &nt, &np);
+    if (rc) return rc;
+    if (walk->n_walkers && !letters_out) return fail(KL_EINVAL, "letters_out is NULL");
+    Gens G{};
+    for (int k = 0; k < 4; ++k) G.g[k] = {{1.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}, {1.0, 0.0}};
+    WalkJob j = walk_job(G, walk, nullptr, KL_PREC_FP32, kWalkLetters);
+    j.letters = letters_out;
+    hipError_t e = launch_walk(j, (hipStream_t)stream);
+    return e == hipSuccess ? KL_OK : hip_fail(e, "walk kernel");
+}
+
+int kl_walk_eval_ex(const kl_c64* ab, const kl_walk* walk, const kl_window* window, kl_c64* z_out,
+                    const kl_opts* opts) {
+    const kl_opts o = opts ? *opts : default_opts();
+    uint64_t nt, np;
+    int rc = check_walk(walk, &nt, &np);
+    if (rc) return rc;
+    if ((rc = check_opts_common(o))) return rc;
+    if (window && (rc = check_window(window))) return rc;
+    if (np && !z_out) return fail(KL_EINVAL, "z_out is NULL");
+    Gens G;
+    if ((rc = make_gens_ab(ab, &G))) return rc;
+    WalkJob j = walk_job(G, walk, window, o.precision, kWalkEval);
+    j.z_out = (c64*)z_out;
+    hipError_t e = launch_walk(j, (hipStream_t)o.stream);
+    return e == hipSuccess ? KL_OK : hip_fail(e, "walk kernel");
+}
+
+int kl_walk_render_ex(const kl_c64* ab, const kl_walk* walk, const kl_window* window, uint32_t* image_out,
+                      const kl_opts* opts) {
+    const kl_opts o = opts ? *opts : default_opts();
+    uint64_t nt, np;
+    int rc = check_walk(walk, &nt, &np);
+    if (rc) return rc;
+    if ((rc = check_opts_common(o))) return rc;
+    if ((rc = check_window(window))) return rc;
+    if (!image_out) return fail(KL_EINVAL, "image_out is NULL");
+    Gens G;
+    if ((rc = make_gens_ab(ab, &G))) return rc;
+    hipStream_t s = (hipStream_t)o.stream;
+    hipError_t e;
+    if (!o.accumulate) {
+        if ((e = launch_fill_u32(image_out, (uint64_t)window->width * window->height, 0, s)) != hipSuccess)
+            return hip_fail(e, "clear image");
+        if (o.dropped_out && (e = launch_fill_u64(o.dropped_out, 1, 0, s)) != hipSuccess)
+            return hip_fail(e, "clear dropped");
+    }
+    WalkJob j = walk_job(G, walk, window, o.precision, kWalkRender);
+    j.image = image_out;
+    j.W = window->width;
+    j.H = window->height;
+    j.dropped = o.dropped_out;
+    e = launch_walk(j, s);
+    return e == hipSuccess ? KL_OK : hip_fail(e, "walk kernel");
 }
 
 int kl_group_seeds(const kl_c64* ab, kl_c64* gens_out, kl_c64* seeds_out) {

@@ -239,6 +239,24 @@ struct CayleyJob {
 };
 hipError_t launch_cayley(const CayleyJob& j, int mode, hipStream_t s);
 
+// Random walks (Section 4, the probabilistic approach), one thread per
+// walker: the letters of each walker, or its drawn points (values, or pixel
+// coordinates with a window), or its points binned into an image.
+enum { kWalkLetters = 0, kWalkEval = 1, kWalkRender = 2 };
+struct WalkJob {
+    Gens gens;
+    Fold fold;                 // identity without a window
+    int precision, mode;
+    uint64_t seed, first_walker, n_walkers;
+    uint32_t burn_in, n_steps;
+    uint8_t* letters;          // letters: n_walkers * (1 + burn_in + n_steps), walker-major
+    c64* z_out;                // eval: n_walkers * n_steps, walker-major
+    uint32_t* image;           // render
+    uint32_t W, H;
+    uint64_t* dropped;         // render: device u64 or null
+};
+hipError_t launch_walk(const WalkJob& j, hipStream_t s);
+
 int device_cu_count();
 
 }  // namespace kl

@@ -54,6 +54,11 @@ class CayleyT(ctypes.Structure):
                 ("table", ctypes.POINTER(ctypes.c_uint8)), ("maps", ctypes.POINTER(c64))]
 
 
+class Walk(ctypes.Structure):
+    _fields_ = [("seed", ctypes.c_uint64), ("first_walker", ctypes.c_uint64), ("n_walkers", ctypes.c_uint64),
+                ("burn_in", ctypes.c_uint32), ("n_steps", ctypes.c_uint32)]
+
+
 class Plan(ctypes.Structure):
     _fields_ = [("depth", ctypes.c_int), ("tail_len", ctypes.c_int), ("lane_len", ctypes.c_int),
                 ("prefix_len", ctypes.c_int), ("hist_mode", ctypes.c_int), ("waves_per_cu", ctypes.c_int)]
@@ -101,6 +106,12 @@ def lib():
         L.kl_render_group_ex.argtypes = [C, i, W, vp, O]
         L.kl_eval_group_ex.argtypes = [C, i, vp, u64, W, vp, O]
         L.kl_plan.argtypes = [i, i, W, O, ctypes.POINTER(Plan)]
+        WK = ctypes.POINTER(Walk)
+        L.kl_walk_letters.argtypes = [WK, vp, vp]
+        L.kl_walk_eval_ex.argtypes = [C, WK, W, vp, O]
+        L.kl_walk_render_ex.argtypes = [C, WK, W, vp, O]
+        for f in ("kl_walk_letters", "kl_walk_eval_ex", "kl_walk_render_ex"):
+            getattr(L, f).restype = i
         L.kl_autotune.argtypes = [c64, c64, i, W, i, vp, ctypes.POINTER(Plan), ctypes.POINTER(ctypes.c_double)]
         L.kl_strerror.argtypes = [i]
         L.kl_strerror.restype = ctypes.c_char_p
@@ -567,4 +578,44 @@ def cayley_render(t: Cayley, depth: int, window, image: torch.Tensor | None = No
     ptr = _dev_ptr(image, "image", _U32, w.width * w.height)
     o = make_opts(**opts)
     _check(lib().kl_cayley_render_ex(t.ref(), int(depth), ctypes.byref(w), ptr, ctypes.byref(o)))
+    return image
+
+
+# ---------------------------------------------------------------- random walks (Section 4)
+def make_walk(seed: int, first_walker: int, n_walkers: int, burn_in: int, n_steps: int) -> Walk:
+    return Walk(int(seed), int(first_walker), int(n_walkers), int(burn_in), int(n_steps))
+
+
+def walk_letters(seed: int, first_walker: int, n_walkers: int, burn_in: int, n_steps: int,
+                 stream=None) -> torch.Tensor:
+    """Letters c_0 .. c_{burn_in + n_steps} of each walker: (n_walkers, 1 + burn_in + n_steps) uint8."""
+    wk = make_walk(seed, first_walker, n_walkers, burn_in, n_steps)
+    out = torch.empty((n_walkers, 1 + burn_in + n_steps), dtype=torch.uint8, device=_device())
+    ptr = _dev_ptr(out, "letters_out", (torch.uint8,), out.numel()) if n_walkers else None
+    _check(lib().kl_walk_letters(ctypes.byref(wk), ptr, _stream(stream)))
+    return out
+
+
+def walk_eval(ab, seed: int, first_walker: int, n_walkers: int, burn_in: int, n_steps: int, window=None,
+              **opts) -> torch.Tensor:
+    """Drawn points (or pixel coordinates with a window): (n_walkers, n_steps, 2) float64."""
+    wk = make_walk(seed, first_walker, n_walkers, burn_in, n_steps)
+    out = torch.empty((n_walkers, n_steps, 2), dtype=torch.float64, device=_device())
+    ptr = _dev_ptr(out, "z_out", (torch.float64,), out.numel()) if out.numel() else None
+    o = make_opts(**opts)
+    w = None if window is None else ctypes.byref(make_window(window))
+    _check(lib().kl_walk_eval_ex(_ab(ab), ctypes.byref(wk), w, ptr, ctypes.byref(o)))
+    return out
+
+
+def walk_render(ab, seed: int, first_walker: int, n_walkers: int, burn_in: int, n_steps: int, window,
+                image: torch.Tensor | None = None, **opts) -> torch.Tensor:
+    """The walkers' drawn points binned: (height, width) int32 storage of uint32 counts."""
+    wk = make_walk(seed, first_walker, n_walkers, burn_in, n_steps)
+    w = make_window(window)
+    if image is None:
+        image = new_image(w)
+    ptr = _dev_ptr(image, "image", _U32, w.width * w.height)
+    o = make_opts(**opts)
+    _check(lib().kl_walk_render_ex(_ab(ab), ctypes.byref(wk), ctypes.byref(w), ptr, ctypes.byref(o)))
     return image

@@ -24,6 +24,9 @@ Workloads (traces are those of the trace recipe; windows are
                         every word (the paper's index-search loop);
                         1024 x 1024 over one period of the translation b,
                         [-1.05, 1.05] x [-0.1, 2.0]
+  walk_maskit_fig3      random walks (the probabilistic approach) in
+                        Maskit's group at the same mu: 2^14 walkers of 64
+                        drawn points (2^20 points, Fig. 3), the same window
 """
 from __future__ import annotations
 
@@ -77,6 +80,32 @@ MASKIT_MU = complex(-0.097, 1.838)
 # ta holds Maskit's parameter mu for this workload; tb is unused
 MASKIT_D14 = Workload("maskit_tiling_d14", MASKIT_MU, complex(0.0, 0.0), 14, 1,
                       Window(-1.05, 1.05, -0.1, 2.0, 1024, 1024))
+
+
+@dataclass(frozen=True)
+class WalkWorkload:
+    """Random walks (the probabilistic approach): walkers x drawn points each."""
+    name: str
+    mu: complex          # Maskit's parameter
+    seed: int
+    n_walkers: int
+    burn_in: int
+    n_steps: int
+    window: Window
+
+    @property
+    def points(self) -> int:
+        return self.n_walkers * self.n_steps
+
+
+# The configuration of the paper's probabilistic rendering (Fig. 3): Maskit's
+# group at mu = -0.097 + 1.838i, 1,048,576 points (2^14 walkers of 64 drawn
+# points each), the window of maskit_tiling_d14
+WALK_FIG3 = WalkWorkload("walk_maskit_fig3", MASKIT_MU, 0, 1 << 14, 0, 64, MASKIT_D14.window)
+# as many points as the depth-13 limit set has words (4 * 3^12 = 3^11 walkers x 12)
+WALK_D13_POINTS = WalkWorkload("walk_maskit_d13_points", MASKIT_MU, 1, 3 ** 11, 0, 12, MASKIT_D14.window)
+# 2^30 points
+WALK_LARGE = WalkWorkload("walk_maskit_2p30", MASKIT_MU, 2, 1 << 24, 0, 64, MASKIT_D14.window)
 
 
 def draw_param_sets(n: int, seed: int, depth_range=(12, 18)):

@@ -226,6 +226,25 @@ def test_noalloc_rejects_before_touching_the_device():
     assert L.kl_render_noalloc(kl._c(0), kl._c(0), 10, ctypes.byref(good), FAKE, None) == kl.KL_ESINGULAR
 
 
+def test_walk_argument_errors():
+    ab = (kl.c64 * 8)(*[kl.c64(1, 0), kl.c64(1, 0), kl.c64(0, 0), kl.c64(1, 0)] * 2)
+    w = kl.make_walk(0, 0, 10, 0, 5)
+    assert L.kl_walk_letters(None, FAKE, None) == kl.KL_EINVAL
+    assert L.kl_walk_letters(ctypes.byref(w), None, None) == kl.KL_EINVAL
+    assert L.kl_walk_letters(ctypes.byref(kl.make_walk(0, 2 ** 64 - 5, 10, 0, 5)), FAKE, None) == kl.KL_ERANGE
+    assert L.kl_walk_letters(ctypes.byref(kl.make_walk(0, 0, 1, 2 ** 32 - 1, 2 ** 32 - 1)), FAKE, None) == kl.KL_EINVAL
+    assert L.kl_walk_letters(ctypes.byref(kl.make_walk(0, 0, 0, 0, 5)), None, None) == kl.KL_OK   # nothing to do
+    good = _win()
+    assert L.kl_walk_render_ex(ab, ctypes.byref(w), ctypes.byref(_win(w=0)), FAKE, None) == kl.KL_EINVAL
+    assert L.kl_walk_render_ex(ab, ctypes.byref(w), ctypes.byref(good), None, None) == kl.KL_EINVAL
+    assert L.kl_walk_render_ex(None, ctypes.byref(w), ctypes.byref(good), FAKE, None) == kl.KL_EINVAL
+    o = kl.make_opts(precision=3, use_stream=False)
+    assert L.kl_walk_render_ex(ab, ctypes.byref(w), ctypes.byref(good), FAKE, ctypes.byref(o)) == kl.KL_EINVAL
+    assert L.kl_walk_eval_ex(ab, ctypes.byref(w), None, None, None) == kl.KL_EINVAL
+    zero = (kl.c64 * 8)(*[kl.c64(0, 0)] * 8)
+    assert L.kl_walk_eval_ex(zero, ctypes.byref(w), None, FAKE, None) == kl.KL_ESINGULAR
+
+
 def test_strerror_names_every_code():
     for code in (0, -1, -2, -3, -4, -5):
         assert L.kl_strerror(code)

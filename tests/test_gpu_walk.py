@@ -1,0 +1,138 @@
+"""Random walks (the probabilistic approach of Section 4) on the GPU against
+the oracle, through the C ABI.
+
+Bars: letters bit-exact; FP64 points within 1e-10 of max(1, |z|) (and
+truly relative above 1e-6); FP32 points within 0.25 px; every image equal
+to the histogram of its own points' pixel coordinates, and the FP64 image
+equal to the oracle's up to points within 1e-7 px of a bin edge.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_1709_08018_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+if torch.cuda.is_available():
+    from paper_1709_08018_amd import kl
+
+MU = wl.MASKIT_MU
+WIN_M = wl.MASKIT_D14.window.as_tuple()
+WIN_C2 = (-2.0, 2.0, -2.0, 2.0, 512, 512)
+
+
+def _maskit():
+    ab = kl.maskit_generators(MU)
+    return ab, O.group_maskit(MU)
+
+
+def _recipe():
+    _, g, _ = kl.generators(wl.C2_TA, wl.C2_TB)
+    return np.stack([g[0], g[1]]), O.group_recipe(wl.C2_TA, wl.C2_TB)
+
+
+def _z(t):
+    a = t.cpu().numpy()
+    return a[..., 0] + 1j * a[..., 1]
+
+
+@pytest.mark.parametrize("seed,first,n,burn,steps", [
+    (0, 0, 1000, 0, 99), (12345, 7, 333, 5, 17), (2 ** 64 - 1, 2 ** 64 - 300, 300, 0, 40), (3, 2 ** 40, 64, 0, 1),
+])
+def test_letters_bit_exact(seed, first, n, burn, steps):
+    got = kl.walk_letters(seed, first, n, burn, steps).cpu().numpy()
+    for i in list(range(min(n, 50))) + [n - 1]:
+        np.testing.assert_array_equal(got[i], O.walk_letters(seed, first + i, 1 + burn + steps), err_msg=str(i))
+
+
+def _assert_fp64(z, zr, what):
+    fin = np.isfinite(zr)
+    assert np.all(~np.isfinite(z[~fin])), what
+    assert np.isfinite(z[fin]).all(), what
+    dz, a = np.abs(z[fin] - zr[fin]), np.abs(zr[fin])
+    assert (dz / np.maximum(1, a)).max() < 1e-10, what
+    big = a > 1e-6
+    assert (dz[big] / a[big]).max() < 1e-10, what
+
+
+@pytest.mark.parametrize("group", ["recipe", "maskit"])
+@pytest.mark.parametrize("burn,steps", [(0, 40), (7, 600)])
+def test_fp64_points_match_the_oracle(group, burn, steps):
+    ab, g = _recipe() if group == "recipe" else _maskit()
+    seed, first, n = 99, 1000, 300
+    z = _z(kl.walk_eval(ab, seed, first, n, burn, steps, precision="fp64"))
+    zr = O.walk_points(g, seed, first, n, burn, steps)
+    _assert_fp64(z, zr, (group, burn, steps))
+
+
+def test_fp32_pixel_error():
+    ab, g = _maskit()
+    seed, n, steps = 5, 4096, 64
+    p = kl.walk_eval(ab, seed, 0, n, 0, steps, window=WIN_M, precision="fp32").cpu().numpy().reshape(-1, 2)
+    z = O.walk_points(g, seed, 0, n, 0, steps).ravel()
+    x0, x1, y0, y1, W, H = WIN_M
+    with np.errstate(invalid="ignore"):
+        fx, fy = (z.real - x0) * W / (x1 - x0), (z.imag - y0) * H / (y1 - y0)
+        near = np.isfinite(z) & (fx > -1) & (fx < W + 1) & (fy > -1) & (fy < H + 1)
+    err = np.hypot(p[near, 0] - fx[near], p[near, 1] - fy[near])
+    print(f"walk FP32 pixel error over {near.sum()} points near the window: max {err.max():.3e} "
+          f"p99 {np.quantile(err, 0.99):.3e} mean {err.mean():.3e}")
+    assert near.sum() > 100_000
+    assert err.max() <= 0.25
+
+
+def _own_bins(p, win):
+    W, H = win[4], win[5]
+    px, py = p[..., 0].ravel(), p[..., 1].ravel()
+    with np.errstate(invalid="ignore"):
+        ok = (px >= 0) & (px < W) & (py >= 0) & (py < H)
+    img = np.zeros(W * H, np.int64)
+    np.add.at(img, np.floor(py[ok]).astype(np.int64) * W + np.floor(px[ok]).astype(np.int64), 1)
+    return img.reshape(H, W), int((~ok).sum())
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("group", ["recipe", "maskit"])
+def test_image_is_histogram_of_own_points(precision, group):
+    ab, _ = _recipe() if group == "recipe" else _maskit()
+    win = WIN_C2 if group == "recipe" else WIN_M
+    seed, n, burn, steps = 8, 3001, 2, 77
+    dropped = torch.zeros(1, dtype=torch.int64, device="cuda")
+    img = kl.as_u32(kl.walk_render(ab, seed, 0, n, burn, steps, win, precision=precision,
+                                   dropped=dropped)).astype(np.int64)
+    p = kl.walk_eval(ab, seed, 0, n, burn, steps, window=win, precision=precision).cpu().numpy()
+    ref, drop = _own_bins(p, win)
+    np.testing.assert_array_equal(img, ref)
+    assert int(dropped.item()) == drop
+    assert int(img.sum()) + drop == n * steps
+
+
+@pytest.mark.parametrize("group", ["recipe", "maskit"])
+def test_fp64_image_matches_the_oracle(group):
+    ab, g = _recipe() if group == "recipe" else _maskit()
+    win = WIN_C2 if group == "recipe" else WIN_M
+    seed, n, burn, steps = 21, 2000, 3, 128
+    img = kl.as_u32(kl.walk_render(ab, seed, 0, n, burn, steps, win, precision="fp64")).astype(np.int64)
+    ref, _, near = O.walk_render(g, seed, 0, n, burn, steps, win, edge_tol=1e-7)
+    diff = int(np.abs(img - ref.astype(np.int64)).sum())
+    assert diff <= 2 * near, (diff, near)
+
+
+def test_walker_ranges_accumulate_and_edge_cases():
+    ab, _ = _maskit()
+    n, steps = 1000, 50
+    full = kl.walk_render(ab, 4, 0, n, 0, steps, WIN_M)
+    acc = kl.new_image(WIN_M)
+    for a, b in [(0, 1), (1, 257), (257, 999), (999, 1000)]:
+        kl.walk_render(ab, 4, a, b - a, 0, steps, WIN_M, image=acc, accumulate=True)
+    assert torch.equal(acc, full)
+    # no walkers, no drawn points: an empty image
+    empty = kl.walk_render(ab, 4, 0, 0, 0, steps, WIN_M)
+    assert int(empty.abs().sum()) == 0
+    assert int(kl.walk_render(ab, 4, 0, 10, 5, 0, WIN_M).abs().sum()) == 0
+    assert kl.walk_eval(ab, 4, 0, 10, 5, 0).numel() == 0
+    with pytest.raises(kl.KLError) as e:
+        kl.walk_render(ab, 4, 2 ** 64 - 5, 10, 0, steps, WIN_M)
+    assert e.value.code == kl.KL_ERANGE
