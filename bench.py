@@ -389,7 +389,10 @@ def leg_decode(args):
 
 def leg_batch(args):
     """256 parameter sets of depths 12..18: one batched persistent launch vs
-    256 single renders enqueued back to back on one stream."""
+    256 single renders enqueued back to back on one stream; with the
+    planner's plans, with the plans kl_autotune_many keeps for the batch as a
+    whole (the same plans given to the single renders, images compared), and
+    the single renders with kl_autotune's plans for single renders."""
     import numpy as np
     import torch
 
@@ -404,40 +407,49 @@ def leg_batch(args):
     def batched():
         kl.render_many(ta, tb, depth, win, images=imgs)
 
-    def separate():
+    def separate(plans=None):
         for i in range(len(ta)):
-            kl.render(ta[i], tb[i], int(depth[i]), win, image=imgs[i])
+            o = {} if plans is None else {"tail_len": plans[i]["tail_len"], "lane_len": plans[i]["lane_len"],
+                                          "waves_per_cu": plans[i]["waves_per_cu"]}
+            kl.render(ta[i], tb[i], int(depth[i]), win, image=imgs[i], **o)
 
     reps = max(2, args.steps // 4)
-    # default plans: one batched launch, then 256 plain kl_render calls
+    # the planner's plans: one batched launch, then 256 plain kl_render calls
     ms_b_default = _time(batched, reps, 1)
     ref = imgs.clone()
     ms_s_default = _time(separate, reps, 1)
     same_default = bool(torch.equal(ref, imgs))
-    # one plan per depth, tuned by kl_autotune on the first set of that depth;
-    # every later render of that depth, batched or single, takes it
-    plans = {}
-    scratch = kl.new_image(win)
+    # plans tuned for the batch as a whole (timing whole batched launches)
     t0 = time.perf_counter()
-    for d in sorted({int(x) for x in depth}):
-        i = int(np.nonzero(depth == d)[0][0])
-        plan, ms = kl.autotune(ta[i], tb[i], d, win, scratch=scratch)
-        plans[d] = {"tail_len": plan["tail_len"], "lane_len": plan["lane_len"],
-                    "waves_per_cu": plan["waves_per_cu"], "hist_mode": plan["hist_mode"], "ms": round(ms, 4)}
+    plans, tuned_ms, default_ms = kl.autotune_many(ta, tb, depth, win)
     tune_s = time.perf_counter() - t0
     ms_b_tuned = _time(batched, reps, 1)
     ref = imgs.clone()
-    ms_s_tuned = _time(separate, reps, 1)
+    ms_s_same = _time(lambda: separate(plans), reps, 1)
     same_tuned = bool(torch.equal(ref, imgs))
+    by_depth = {}
+    for i, d in enumerate(depth):
+        by_depth[int(d)] = {k: plans[i][k] for k in ("tail_len", "lane_len", "prefix_len", "waves_per_cu")}
+    # the single renders with plans tuned for single renders, one per depth
+    t0 = time.perf_counter()
+    scratch = kl.new_image(win)
+    for d in sorted({int(x) for x in depth}):
+        i = int(np.nonzero(depth == d)[0][0])
+        kl.autotune(ta[i], tb[i], d, win, scratch=scratch)
+    tune1_s = time.perf_counter() - t0
+    ms_s_single = _time(separate, reps, 1)
     ms_b = min(ms_b_default, ms_b_tuned)
     return {"workload": "batch256", "sets": len(ta), "words": words,
             "batched_ms": round(ms_b, 3), "separate_ms": round(ms_s_default, 3),
             "speedup": round(ms_s_default / ms_b, 3), "batched_gwords_per_s": round(words / ms_b / 1e6, 2),
             "default_plans": {"batched_ms": round(ms_b_default, 3), "separate_ms": round(ms_s_default, 3),
                               "images_identical": same_default},
-            "autotuned_plans": {"batched_ms": round(ms_b_tuned, 3), "separate_ms": round(ms_s_tuned, 3),
-                                "images_identical": same_tuned, "tune_seconds": round(tune_s, 2), "plans": plans},
-            "note": "speedup: the faster batched launch against 256 plain renders with default plans"}
+            "batch_tuned_plans": {"batched_ms": round(ms_b_tuned, 3), "tuner_batched_ms": round(tuned_ms, 3),
+                                  "tuner_default_ms": round(default_ms, 3), "separate_same_plans_ms": round(ms_s_same, 3),
+                                  "images_identical": same_tuned, "tune_seconds": round(tune_s, 2),
+                                  "plans": by_depth},
+            "single_tuned_plans": {"separate_ms": round(ms_s_single, 3), "tune_seconds": round(tune1_s, 2)},
+            "note": "speedup: the faster batched launch against 256 plain renders with the planner's plans"}
 
 
 def leg_tiling(args):
@@ -551,6 +563,18 @@ def cpu_baseline_walk(W, img):
     return {"kind": "oracle", "value": round(W.points / dt / 1e9, 5), "unit": "Gpoints/s", "cores": 1,
             "sample": f"the full workload ({W.points} points)", "seconds": round(dt, 3),
             "fp64_l1_vs_oracle": int(np.abs(img - rimg.astype(np.int64)).sum()), "oracle_near_edge_words": int(near)}
+
+
+def leg_surrogate_kernels(args):
+    """The surrogate's kernels alone, with untrained parameters: the fused
+    forward pass on 512 sets and a training step on 128 (the timings of the
+    surrogate leg's kernel_rates, without its data and training)."""
+    from paper_1709_08018_amd import surrogate as S
+    from paper_1709_08018_amd import workloads as wl
+
+    ta, tb = wl.surrogate_sets(512, seed=2)
+    params = S.init_params(0)
+    return {"workload": "surrogate_kernels", "kernel_rates": S.kernel_rates(params, ta, tb, reps=max(5, args.steps // 10))}
 
 
 def leg_walk(args):
@@ -699,7 +723,8 @@ def main():
                     help="untimed steps after the clock ramp (CLOCK_RAMP_MS of untimed steps first)")
     ap.add_argument("--workload", default="quasifuchsian_d18",
                     choices=["quasifuchsian_d18", "quasifuchsian_d22", "decode", "bounded", "batch256", "fuchsian_tiling_d10",
-                             "maskit_tiling_d14", "cayley", "surrogate", "hist", "calib", "walk"])
+                             "maskit_tiling_d14", "cayley", "surrogate", "surrogate_kernels", "hist", "calib",
+                             "walk"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="after the steps, copy 256 MiB device to device twice (a kernel of known HBM "
@@ -719,7 +744,7 @@ def main():
     torch.cuda.set_device(0)
     legs = {"quasifuchsian_d22": leg_d22, "decode": leg_decode, "bounded": leg_bounded, "batch256": leg_batch, "fuchsian_tiling_d10": leg_tiling,
             "maskit_tiling_d14": leg_maskit, "cayley": leg_cayley, "surrogate": leg_surrogate, "hist": leg_hist,
-            "calib": leg_calib, "walk": leg_walk}
+            "calib": leg_calib, "walk": leg_walk, "surrogate_kernels": leg_surrogate_kernels}
     if args.workload in legs:
         print(json.dumps(legs[args.workload](args)), flush=True)
         return

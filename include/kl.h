@@ -408,15 +408,46 @@ int kl_plan(int depth, int precision, const kl_window *window, const kl_opts *op
 /* kl_autotune: times the candidate splits, histogram strategies and grid
  * sizes for (ta, tb, depth, window, precision) on the current device,
  * keeps the fastest as the plan for every later render and evaluation
- * with the same (depth, precision) in this process that leaves tail_len
- * and lane_len to the planner, and appends it to the file named by the
- * environment variable KL_AUTOTUNE_CACHE, if set (that file is read at
- * the first plan lookup of the process).  scratch_image: device,
- * width * height uint32, overwritten.  best_out may be NULL; best_ms_out
- * (host, may be NULL) receives the winner's median time.
+ * of one depth with the same (device architecture, depth, precision) in
+ * this process that leaves tail_len and lane_len to the planner, and
+ * appends it to the file named by the environment variable
+ * KL_AUTOTUNE_CACHE, if set (that file is read at the first plan lookup of
+ * the process; lines "arch context depth precision width height tail_len
+ * lane_len waves_per_cu hist_mode ms", context 0 for these plans with width
+ * and height 0, arch "*" for any device; a line the planner rejects is
+ * skipped).  scratch_image: device, width * height uint32, overwritten.
+ * best_out may be NULL; best_ms_out (host, may be NULL) receives the
+ * winner's median time.
  * Errors: as kl_render_ex. */
 int kl_autotune(kl_c64 ta, kl_c64 tb, int depth, const kl_window *window, int precision,
                 uint32_t *scratch_image, kl_plan_t *best_out, double *best_ms_out);
+
+/* kl_autotune_many: tunes the plans of a batched render as a whole, timing
+ * whole kl_render_many_ex launches of the given sets (n, ta, tb, depth,
+ * window, precision; scratch_images: device, n * width * height uint32,
+ * overwritten).  From the planner's plans it tries, for each depth of the
+ * batch, deepest first, the splits with tails of 4..7 letters and prefix
+ * tables of 1..9 letters, the other depths fixed, then persistent grids of
+ * 16 and 24 waves per CU; a change is kept only when the batch gets at least
+ * 1% faster, and the result only when, timed alternately with the planner's
+ * plans three times more, it is still 1% faster (else the planner's plans
+ * are kept).  The kept plans apply to every later kl_render_many_ex on a
+ * device of the same architecture with the same image size and precision
+ * that leaves tail_len and lane_len to the planner (kl_render_ex and kl_eval
+ * keep their own plans), and are appended to KL_AUTOTUNE_CACHE as context 1
+ * lines keyed by (arch, depth, width, height, precision).
+ * plans_out (host, n entries, may be NULL): each set's plan;
+ * best_ms_out / default_ms_out (host, may be NULL): the median batch time
+ * with the kept plans / with the planner's.
+ * Errors: as kl_render_many_ex. */
+int kl_autotune_many(int n, const kl_c64 *ta, const kl_c64 *tb, const int *depth, const kl_window *window,
+                     int precision, uint32_t *scratch_images, kl_plan_t *plans_out, double *best_ms_out,
+                     double *default_ms_out);
+
+/* kl_plan_many: the plan a set of this depth takes in kl_render_many_ex on
+ * the current device with this window and precision (tuned by
+ * kl_autotune_many, else the planner's).  Errors: KL_EINVAL. */
+int kl_plan_many(int depth, int precision, const kl_window *window, kl_plan_t *plan_out);
 
 const char *kl_strerror(int code);
 const char *kl_last_error(void);

@@ -215,6 +215,7 @@ static Fold make_fold(const kl_window* w, int head_form) {
 struct DeviceInfo {
     int cus = 0;
     void* scratch = nullptr;   // device address of this device's copy of `scratch` (kl_render_noalloc)
+    char arch[32] = {0};       // architecture name up to its first ':' (tuned-plan keys)
 };
 constexpr int kMaxDevices = 64;
 static std::mutex g_dev_mutex;
@@ -413,18 +414,58 @@ static bool persistent_ok(const Split& sp) { return sp.k + sp.m > 0 && sp.r >= 3
 constexpr uint64_t kMinPersistentUnits = 128;
 
 // ------------------------------------------------------------------ tuned plans
-// Plans chosen by kl_autotune, keyed by (depth, precision): the split
-// decides the arithmetic of every word, so kl_eval and every render of one
-// depth and precision share it.  KL_AUTOTUNE_CACHE names a text file of
-// "depth precision tail_len lane_len waves_per_cu hist_mode ms" lines that
-// is read at the first lookup and appended to by kl_autotune.
+// Plans chosen by the autotuners, in two contexts:
+//   single (kl_autotune): renders and evaluations of one depth, keyed by
+//     (device architecture, depth, precision) -- the split decides the
+//     arithmetic of every word, so kl_eval (which may have no window) and
+//     every render of that depth and precision share it;
+//   batch (kl_autotune_many): the sets of batched renders, keyed by
+//     (architecture, depth, image width and height, precision).
+// KL_AUTOTUNE_CACHE names a text file of lines
+//   "arch context depth precision width height tail_len lane_len
+//    waves_per_cu hist_mode ms"
+// (context 0 single with width = height = 0, 1 batch; arch "*" matches any
+// device) read at the first lookup and appended to by the tuners.
+enum { kTuneSingle = 0, kTuneBatch = 1 };
 struct Tuned {
-    int depth, precision, r, m, wpc, hist;
+    char arch[32];
+    int ctx, depth, precision;
+    uint32_t W, H;
+    int r, m, wpc, hist;
     double ms;
 };
 static std::mutex g_tune_mutex;
 static std::vector<Tuned> g_tuned;
 static bool g_tune_loaded = false;
+
+// "gfx950" for the current device (up to the first ':' of its architecture
+// name), "none" without one
+static void device_arch(char* out, size_t n) {
+    snprintf(out, n, "none");
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return;
+    std::lock_guard<std::mutex> lk(g_dev_mutex);
+    if (!g_devs[dev].arch[0]) {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return;
+        size_t i = 0;
+        for (; i + 1 < sizeof g_devs[dev].arch && prop.gcnArchName[i] && prop.gcnArchName[i] != ':'; ++i)
+            g_devs[dev].arch[i] = prop.gcnArchName[i];
+        g_devs[dev].arch[i] = 0;
+    }
+    snprintf(out, n, "%s", g_devs[dev].arch);
+}
+
+static bool same_key(const Tuned& a, const Tuned& b) {
+    return strcmp(a.arch, b.arch) == 0 && a.ctx == b.ctx && a.depth == b.depth && a.precision == b.precision &&
+           a.W == b.W && a.H == b.H;
+}
+
+static void put_tuned_locked(const Tuned& t) {
+    auto it = std::find_if(g_tuned.begin(), g_tuned.end(), [&](const Tuned& x) { return same_key(x, t); });
+    if (it != g_tuned.end()) *it = t;
+    else g_tuned.push_back(t);
+}
 
 static void load_tuned_locked() {
     if (g_tune_loaded) return;
@@ -439,28 +480,41 @@ static void load_tuned_locked() {
         Split sp;
         // a line is kept only if the planner accepts its split: a stale or
         // foreign line must not make every render of its depth fail
-        if (sscanf(line, "%d %d %d %d %d %d %lf", &t.depth, &t.precision, &t.r, &t.m, &t.wpc, &t.hist, &t.ms) == 7 &&
-            t.hist >= KL_HIST_AUTO && t.hist <= KL_HIST_LDS &&
+        if (sscanf(line, "%31s %d %d %d %u %u %d %d %d %d %lf", t.arch, &t.ctx, &t.depth, &t.precision, &t.W,
+                   &t.H, &t.r, &t.m, &t.wpc, &t.hist, &t.ms) == 11 &&
+            (t.ctx == kTuneSingle || t.ctx == kTuneBatch) && t.hist >= KL_HIST_AUTO && t.hist <= KL_HIST_LDS &&
             (t.precision == KL_PREC_FP32 || t.precision == KL_PREC_FP64) &&
             t.depth >= 1 && t.depth <= KL_MAX_DEPTH && t.r >= 1 && t.r <= kMaxTail && t.r < t.depth && t.m >= 0 &&
-            t.m <= kMaxLane && t.wpc >= 0 && t.wpc <= 32 &&
-            plan_split(t.depth, t.precision, t.r, t.m, &sp) == KL_OK) {
-            auto it = std::find_if(g_tuned.begin(), g_tuned.end(),
-                                   [&](const Tuned& x) { return x.depth == t.depth && x.precision == t.precision; });
-            if (it != g_tuned.end()) *it = t;
-            else g_tuned.push_back(t);
-        }
+            t.m <= kMaxLane && t.wpc >= 0 && t.wpc <= 32 && t.W <= 32768 && t.H <= 32768 &&
+            plan_split(t.depth, t.precision, t.r, t.m, &sp, t.ctx == kTuneBatch ? 8 : 9) == KL_OK)
+            put_tuned_locked(t);
     }
     fclose(f);
 }
 
-static bool find_tuned(int depth, int precision, Tuned* out) {
+// The tuned plan of a context, depth, image size (batch only) and precision
+// on the current device.
+static bool find_tuned(int ctx, int depth, int precision, const kl_window* w, Tuned* out) {
+    Tuned key{};
+    device_arch(key.arch, sizeof key.arch);
+    key.ctx = ctx;
+    key.depth = depth;
+    key.precision = precision;
+    if (ctx == kTuneBatch) {
+        if (!w) return false;
+        key.W = w->width;
+        key.H = w->height;
+    }
     std::lock_guard<std::mutex> lk(g_tune_mutex);
     load_tuned_locked();
-    for (const Tuned& t : g_tuned)
-        if (t.depth == depth && t.precision == precision) {
-            *out = t;
-            return true;
+    for (int pass = 0; pass < 2; ++pass)   // this device's architecture, then "*"
+        for (const Tuned& t : g_tuned) {
+            Tuned k2 = key;
+            if (pass) snprintf(k2.arch, sizeof k2.arch, "*");
+            if (same_key(t, k2)) {
+                *out = t;
+                return true;
+            }
         }
     return false;
 }
@@ -468,15 +522,13 @@ static bool find_tuned(int depth, int precision, Tuned* out) {
 static void store_tuned(const Tuned& t) {
     std::lock_guard<std::mutex> lk(g_tune_mutex);
     load_tuned_locked();
-    auto it = std::find_if(g_tuned.begin(), g_tuned.end(),
-                           [&](const Tuned& x) { return x.depth == t.depth && x.precision == t.precision; });
-    if (it != g_tuned.end()) *it = t;
-    else g_tuned.push_back(t);
+    put_tuned_locked(t);
     const char* path = getenv("KL_AUTOTUNE_CACHE");
     if (path && *path) {
         FILE* f = fopen(path, "a");
         if (f) {
-            fprintf(f, "%d %d %d %d %d %d %.6f\n", t.depth, t.precision, t.r, t.m, t.wpc, t.hist, t.ms);
+            fprintf(f, "%s %d %d %d %u %u %d %d %d %d %.6f\n", t.arch, t.ctx, t.depth, t.precision, t.W, t.H, t.r,
+                    t.m, t.wpc, t.hist, t.ms);
             fclose(f);
         }
     }
@@ -485,12 +537,12 @@ static void store_tuned(const Tuned& t) {
 // Seed of every word for the suffix tables: -1 (each word's own) or a generator.
 static int seed_index(const kl_opts& o) { return o.seed_mode >= KL_SEED_A ? o.seed_mode - KL_SEED_A : -1; }
 
-// Options with the tuned plan filled in where the caller left the planner's choice.
-static kl_opts apply_tuned(const kl_opts& o, int depth, const kl_window* w) {
-    (void)w;
+// Options with the tuned plan filled in where the caller left the planner's
+// choice: the single-render plan, or with `batch` the batched one.
+static kl_opts apply_tuned(const kl_opts& o, int depth, const kl_window* w, bool batch = false) {
     kl_opts r = o;
     Tuned t;
-    if (o.tail_len == 0 && o.lane_len == 0 && find_tuned(depth, o.precision, &t)) {
+    if (o.tail_len == 0 && o.lane_len == 0 && find_tuned(batch ? kTuneBatch : kTuneSingle, depth, o.precision, w, &t)) {
         r.tail_len = t.r;
         r.lane_len = t.m;
         if (r.waves_per_cu == 0) r.waves_per_cu = t.wpc;
@@ -1431,9 +1483,38 @@ int kl_cayley_render_ex(const kl_cayley* t, int depth, const kl_window* window, 
     return KL_OK;
 }
 
+}  // extern "C"
+
+namespace kl {
+
+// Explicit per-depth splits of a batched render (the batch tuner's
+// candidates): tail and lane lengths by depth, 0 for the planner's or the
+// tuned plan; wpc 0 for the planner's grid.
+struct BatchPlans {
+    int r[KL_MAX_DEPTH + 1] = {};
+    int m[KL_MAX_DEPTH + 1] = {};
+    int wpc = 0;
+};
+
+static int render_many_run(int n, const kl_c64* ta, const kl_c64* tb, const int* depth, const kl_window* window,
+                           uint32_t* images_out, const kl_opts& o_in, const BatchPlans* bp);
+
+}  // namespace kl
+
+extern "C" {
+
 int kl_render_many_ex(int n, const kl_c64* ta, const kl_c64* tb, const int* depth, const kl_window* window,
                       uint32_t* images_out, const kl_opts* opts) {
-    kl_opts o = opts ? *opts : default_opts();
+    return render_many_run(n, ta, tb, depth, window, images_out, opts ? *opts : default_opts(), nullptr);
+}
+
+}  // extern "C"
+
+namespace kl {
+
+static int render_many_run(int n, const kl_c64* ta, const kl_c64* tb, const int* depth, const kl_window* window,
+                           uint32_t* images_out, const kl_opts& o_in, const BatchPlans* bp) {
+    kl_opts o = o_in;
     if (n <= 0) return fail(KL_EINVAL, "n = %d must be positive", n);
     if (!ta || !tb || !depth) return fail(KL_EINVAL, "ta, tb and depth must not be NULL");
     int rc = check_window(window);
@@ -1447,7 +1528,7 @@ int kl_render_many_ex(int n, const kl_c64* ta, const kl_c64* tb, const int* dept
             kl_opts oq = o;
             oq.seed_mode = KL_SEED_A + q;
             oq.accumulate = o.accumulate || q > 0;
-            if ((rc = kl_render_many_ex(n, ta, tb, depth, window, images_out, &oq))) return rc;
+            if ((rc = render_many_run(n, ta, tb, depth, window, images_out, oq, bp))) return rc;
         }
         return KL_OK;
     }
@@ -1457,7 +1538,11 @@ int kl_render_many_ex(int n, const kl_c64* ta, const kl_c64* tb, const int* dept
     std::vector<kl_opts> per(n);
     for (int i = 0; i < n; ++i) {
         if (depth[i] < 1 || depth[i] > KL_MAX_DEPTH) return fail(KL_EINVAL, "set %d: depth %d outside 1..40", i, depth[i]);
-        per[i] = apply_tuned(opts_for_depth(o, depth[i]), depth[i], window);
+        per[i] = apply_tuned(opts_for_depth(o, depth[i]), depth[i], window, true);
+        if (bp && bp->r[depth[i]]) {
+            per[i].tail_len = bp->r[depth[i]];
+            per[i].lane_len = bp->m[depth[i]];
+        }
         if ((rc = plan_split(depth[i], o.precision, per[i].tail_len, per[i].lane_len, &splits[i], 8))) {
             std::string m = g_last_error;
             return fail(rc, "set %d: %s", i, m.c_str());
@@ -1475,12 +1560,181 @@ int kl_render_many_ex(int n, const kl_c64* ta, const kl_c64* tb, const int* dept
             return hip_fail(e, "clear dropped");
     }
     std::vector<SetSpec> specs(n);
-    int wpc = o.waves_per_cu;
+    int wpc = o.waves_per_cu ? o.waves_per_cu : (bp ? bp->wpc : 0);
     for (int i = 0; i < n; ++i) {
         specs[i] = {gens[i], splits[i], seed_index(o), images_out + bins * i, o.dropped_out ? o.dropped_out + i : nullptr};
         if (!wpc && persistent_ok(splits[i])) wpc = per[i].waves_per_cu;
     }
     return render_sets(specs, window, o, wpc, s);
+}
+
+// Median time of a batched render with plans bp (one untimed run first).
+static int time_batch(int n, const kl_c64* ta, const kl_c64* tb, const int* depth, const kl_window* window,
+                      uint32_t* images, const kl_opts& o, const BatchPlans& bp, hipEvent_t e0, hipEvent_t e1,
+                      double* ms_out) {
+    std::vector<float> times;
+    for (int rep = 0; rep < 4; ++rep) {
+        (void)hipEventRecord(e0, nullptr);
+        int rc = render_many_run(n, ta, tb, depth, window, images, o, &bp);
+        (void)hipEventRecord(e1, nullptr);
+        if (rc) return rc;
+        if (hipEventSynchronize(e1) != hipSuccess) return fail(KL_EDEVICE, "batch autotune timing failed");
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (rep) times.push_back(ms);
+    }
+    std::sort(times.begin(), times.end());
+    *ms_out = times[times.size() / 2];
+    return KL_OK;
+}
+
+}  // namespace kl
+
+extern "C" {
+
+int kl_autotune_many(int n, const kl_c64* ta, const kl_c64* tb, const int* depth, const kl_window* window,
+                     int precision, uint32_t* scratch_images, kl_plan_t* plans_out, double* best_ms_out,
+                     double* default_ms_out) {
+    if (n <= 0) return fail(KL_EINVAL, "n = %d must be positive", n);
+    if (!ta || !tb || !depth) return fail(KL_EINVAL, "ta, tb and depth must not be NULL");
+    int rc = check_window(window);
+    if (rc) return rc;
+    if (!scratch_images) return fail(KL_EINVAL, "scratch_images is NULL");
+    if (precision != KL_PREC_FP32 && precision != KL_PREC_FP64) return fail(KL_EINVAL, "precision %d", precision);
+    bool present[KL_MAX_DEPTH + 1] = {};
+    for (int i = 0; i < n; ++i) {
+        if (depth[i] < 1 || depth[i] > KL_MAX_DEPTH) return fail(KL_EINVAL, "set %d: depth %d outside 1..40", i, depth[i]);
+        present[depth[i]] = true;
+    }
+    kl_opts o = default_opts();
+    o.precision = precision;
+    // the planner's plans, whatever was tuned before
+    BatchPlans cur;
+    for (int d = 1; d <= KL_MAX_DEPTH; ++d) {
+        if (!present[d]) continue;
+        Split sp;
+        if ((rc = plan_split(d, precision, 0, 0, &sp, 8))) return rc;
+        cur.r[d] = sp.r;
+        cur.m[d] = sp.m;
+    }
+    cur.wpc = kDefaultWavesPerCU;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return fail(KL_EDEVICE, "hipEventCreate failed");
+    double def_ms = 0, best = 0;
+    rc = time_batch(n, ta, tb, depth, window, scratch_images, o, cur, e0, e1, &def_ms);
+    best = def_ms;
+    // coordinate descent: each depth's split, deepest first, then the grid;
+    // a change is kept only when the whole batch gets at least 1% faster
+    for (int d = KL_MAX_DEPTH; d >= 1 && rc == KL_OK; --d) {
+        if (!present[d]) continue;
+        for (int r = 4; r <= std::min(7, d - 1) && rc == KL_OK; ++r)
+            for (int m = 1; m <= 6 && rc == KL_OK; ++m) {
+                const int k = d - r - m;
+                if (k < 1 || k > 9 || (r == cur.r[d] && m == cur.m[d])) continue;
+                BatchPlans trial = cur;
+                trial.r[d] = r;
+                trial.m[d] = m;
+                double t = 0;
+                if ((rc = time_batch(n, ta, tb, depth, window, scratch_images, o, trial, e0, e1, &t))) break;
+                if (t < 0.99 * best) {
+                    best = t;
+                    cur = trial;
+                }
+            }
+    }
+    for (int wpc : {16, 24}) {
+        if (rc) break;
+        BatchPlans trial = cur;
+        trial.wpc = wpc;
+        double t = 0;
+        if ((rc = time_batch(n, ta, tb, depth, window, scratch_images, o, trial, e0, e1, &t))) break;
+        if (t < 0.99 * best) {
+            best = t;
+            cur = trial;
+        }
+    }
+    // confirmation: the kept plans and the planner's, timed alternately;
+    // the planner's stay unless the kept ones still win by 1%
+    BatchPlans def;
+    for (int d = 1; d <= KL_MAX_DEPTH; ++d) {
+        def.r[d] = 0;
+        def.m[d] = 0;
+        if (!present[d]) continue;
+        Split sp;
+        if (rc == KL_OK && (rc = plan_split(d, precision, 0, 0, &sp, 8)) == KL_OK) {
+            def.r[d] = sp.r;
+            def.m[d] = sp.m;
+        }
+    }
+    def.wpc = kDefaultWavesPerCU;
+    if (rc == KL_OK && best < def_ms) {
+        double td[3] = {}, tt[3] = {};
+        for (int q = 0; q < 3 && rc == KL_OK; ++q) {
+            if ((rc = time_batch(n, ta, tb, depth, window, scratch_images, o, def, e0, e1, &td[q]))) break;
+            rc = time_batch(n, ta, tb, depth, window, scratch_images, o, cur, e0, e1, &tt[q]);
+        }
+        std::sort(td, td + 3);
+        std::sort(tt, tt + 3);
+        def_ms = td[1];
+        best = tt[1];
+        if (best >= 0.99 * def_ms) {
+            cur = def;
+            best = def_ms;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    for (int d = 1; d <= KL_MAX_DEPTH; ++d) {
+        if (!present[d]) continue;
+        Tuned t{};
+        device_arch(t.arch, sizeof t.arch);
+        t.ctx = kTuneBatch;
+        t.depth = d;
+        t.precision = precision;
+        t.W = window->width;
+        t.H = window->height;
+        t.r = cur.r[d];
+        t.m = cur.m[d];
+        t.wpc = cur.wpc;
+        t.hist = KL_HIST_RUNS;
+        t.ms = best;
+        store_tuned(t);
+    }
+    if (plans_out)
+        for (int i = 0; i < n; ++i) {
+            const int d = depth[i];
+            plans_out[i].depth = d;
+            plans_out[i].tail_len = cur.r[d];
+            plans_out[i].lane_len = cur.m[d];
+            plans_out[i].prefix_len = d - cur.r[d] - cur.m[d];
+            plans_out[i].hist_mode = KL_HIST_RUNS;
+            plans_out[i].waves_per_cu = cur.wpc;
+        }
+    if (best_ms_out) *best_ms_out = best;
+    if (default_ms_out) *default_ms_out = def_ms;
+    return KL_OK;
+}
+
+int kl_plan_many(int depth, int precision, const kl_window* window, kl_plan_t* plan_out) {
+    if (depth < 1 || depth > KL_MAX_DEPTH) return fail(KL_EINVAL, "depth %d outside 1..40", depth);
+    if (!plan_out) return fail(KL_EINVAL, "plan_out is NULL");
+    if (precision != KL_PREC_FP32 && precision != KL_PREC_FP64) return fail(KL_EINVAL, "precision %d", precision);
+    int rc = check_window(window);
+    if (rc) return rc;
+    kl_opts o = default_opts();
+    o.precision = precision;
+    o = apply_tuned(o, depth, window, true);
+    Split sp;
+    if ((rc = plan_split(depth, precision, o.tail_len, o.lane_len, &sp, 8))) return rc;
+    plan_out->depth = depth;
+    plan_out->tail_len = sp.r;
+    plan_out->lane_len = sp.m;
+    plan_out->prefix_len = sp.k;
+    plan_out->hist_mode = KL_HIST_RUNS;
+    plan_out->waves_per_cu = o.waves_per_cu ? o.waves_per_cu : kDefaultWavesPerCU;
+    return KL_OK;
 }
 
 int kl_render_many(int n, const kl_c64* ta, const kl_c64* tb, const int* depth, const kl_window* window,
@@ -1503,7 +1757,13 @@ int kl_autotune(kl_c64 ta, kl_c64 tb, int depth, const kl_window* window, int pr
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return fail(KL_EDEVICE, "hipEventCreate failed");
-    Tuned best{depth, precision, 0, 0, 0, KL_HIST_RUNS, 1e300};
+    Tuned best{};
+    device_arch(best.arch, sizeof best.arch);
+    best.ctx = kTuneSingle;
+    best.depth = depth;
+    best.precision = precision;
+    best.hist = KL_HIST_RUNS;
+    best.ms = 1e300;
     const int wpcs[] = {8, 16, 24, 32};
     for (int r = 3; r <= std::min(kMaxTail - 1, depth - 1); ++r) {
         for (int m = 1; m <= std::min(6, depth - r - 1); ++m) {
@@ -1536,7 +1796,13 @@ int kl_autotune(kl_c64 ta, kl_c64 tb, int depth, const kl_window* window, int pr
                 }
                 std::sort(times.begin(), times.end());
                 const double med = times[times.size() / 2];
-                if (med < best.ms) best = Tuned{depth, precision, r, m, wpc, hist, med};
+                if (med < best.ms) {
+                    best.r = r;
+                    best.m = m;
+                    best.wpc = wpc;
+                    best.hist = hist;
+                    best.ms = med;
+                }
             }
         }
     }

@@ -113,6 +113,11 @@ def lib():
         for f in ("kl_walk_letters", "kl_walk_eval_ex", "kl_walk_render_ex"):
             getattr(L, f).restype = i
         L.kl_autotune.argtypes = [c64, c64, i, W, i, vp, ctypes.POINTER(Plan), ctypes.POINTER(ctypes.c_double)]
+        L.kl_autotune_many.argtypes = [i, C, C, ctypes.POINTER(i), W, i, vp, ctypes.POINTER(Plan),
+                                       ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+        L.kl_plan_many.argtypes = [i, i, W, ctypes.POINTER(Plan)]
+        L.kl_autotune_many.restype = i
+        L.kl_plan_many.restype = i
         L.kl_strerror.argtypes = [i]
         L.kl_strerror.restype = ctypes.c_char_p
         L.kl_last_error.argtypes = []
@@ -342,6 +347,33 @@ def autotune(ta, tb, depth: int, window, precision="fp32", scratch: torch.Tensor
                              _dev_ptr(scratch, "scratch", _U32, w.width * w.height),
                              ctypes.byref(p), ctypes.byref(ms)))
     return {k: getattr(p, k) for k, _ in Plan._fields_}, ms.value
+
+
+def autotune_many(ta, tb, depths, window, precision="fp32", scratch: torch.Tensor | None = None):
+    """kl_autotune_many: (each set's plan, tuned batch ms, planner's batch ms)."""
+    ta = np.asarray(ta, np.complex128).ravel()
+    tb = np.asarray(tb, np.complex128).ravel()
+    depths = np.asarray(depths, np.int32).ravel()
+    n = len(ta)
+    w = make_window(window)
+    if scratch is None:
+        scratch = new_image(w, n)
+    cta = (c64 * n)(*[c64(z.real, z.imag) for z in ta])
+    ctb = (c64 * n)(*[c64(z.real, z.imag) for z in tb])
+    cd = (ctypes.c_int * n)(*[int(d) for d in depths])
+    plans = (Plan * n)()
+    best, default = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    _check(lib().kl_autotune_many(n, cta, ctb, cd, ctypes.byref(w), PREC[precision],
+                                  _dev_ptr(scratch, "scratch", _U32, n * w.width * w.height), plans,
+                                  ctypes.byref(best), ctypes.byref(default)))
+    return [{k: getattr(p, k) for k, _ in Plan._fields_} for p in plans], best.value, default.value
+
+
+def plan_many(depth: int, precision="fp32", window=None) -> dict:
+    """kl_plan_many: the plan a set of this depth takes in a batched render."""
+    p = Plan()
+    _check(lib().kl_plan_many(int(depth), PREC[precision], ctypes.byref(make_window(window)), ctypes.byref(p)))
+    return {k: getattr(p, k) for k, _ in Plan._fields_}
 
 
 def as_u32(image: torch.Tensor) -> np.ndarray:

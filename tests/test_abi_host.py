@@ -103,15 +103,43 @@ def test_autotune_cache_skips_lines_the_planner_rejects(tmp_path):
     import os
     import sys
     # depth 30 with r = 3, m = 1 leaves a 26-letter prefix table (> 14);
-    # r = 8 is beyond FP64's limit; the depth-18 line is valid and applies
+    # r = 8 is beyond FP64's limit; the depth-18 line for any device is valid
+    # and applies; a line of the old format and one for another architecture
+    # do not
     cache = tmp_path / "tune.txt"
-    cache.write_text("30 0 3 1 0 0 1.0\n20 1 8 2 0 1 1.0\n18 0 5 2 16 1 0.2\ngarbage\n")
+    cache.write_text("* 0 30 0 0 0 3 1 0 0 1.0\n* 0 20 1 0 0 8 2 0 1 1.0\n* 0 18 0 0 0 5 2 16 1 0.2\n"
+                     "garbage\n18 0 5 2 16 1 0.2\ngfx000 0 18 0 0 0 4 2 16 1 0.1\n")
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
     out = subprocess.run([sys.executable, "-c", _CACHE_PROBE.format(root=root)], capture_output=True, text=True,
                          env={**os.environ, "KL_AUTOTUNE_CACHE": str(cache)}, check=True).stdout.split()
     default30 = kl.plan(30, "fp32")["tail_len"]
     default20 = kl.plan(20, "fp64")["tail_len"]
     assert out == [str(default30), "5", "2", str(default20)]
+
+
+_BATCH_PROBE = """
+import sys
+sys.path.insert(0, {root!r})
+from paper_1709_08018_amd import kl
+w = (-2.0, 2.0, -2.0, 2.0, 320, 200)
+a, b = kl.plan_many(16, "fp32", w), kl.plan(16, "fp32")
+c = kl.plan_many(16, "fp32", (-2.0, 2.0, -2.0, 2.0, 512, 512))
+print(a["tail_len"], a["lane_len"], a["waves_per_cu"], b["tail_len"], b["lane_len"], c["tail_len"], c["lane_len"])
+"""
+
+
+def test_batch_plans_are_keyed_by_image_size_and_separate_from_single_plans(tmp_path):
+    import os
+    import sys
+    cache = tmp_path / "tune.txt"
+    cache.write_text("* 1 16 0 320 200 5 3 24 1 3.0\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    out = subprocess.run([sys.executable, "-c", _BATCH_PROBE.format(root=root)], capture_output=True, text=True,
+                         env={**os.environ, "KL_AUTOTUNE_CACHE": str(cache)}, check=True).stdout.split()
+    single = kl.plan(16, "fp32")
+    default_batch = kl.plan_many(16, "fp32", (-2.0, 2.0, -2.0, 2.0, 512, 512))
+    assert out == ["5", "3", "24", str(single["tail_len"]), str(single["lane_len"]),
+                   str(default_batch["tail_len"]), str(default_batch["lane_len"])]
 
 
 def test_binding_checks_tensors_before_the_call():
