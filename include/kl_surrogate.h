@@ -54,6 +54,24 @@ size_t kl_sur_num_params(void);
  * (1 <= batch <= 512 for the calls below). */
 size_t kl_sur_workspace_bytes(int batch);
 
+/* The training path's FP32 buffers in a workspace of `batch` sets, as
+ * kl_sur_loss_grad (and kl_sur_train_step) leave them, for checking each
+ * layer on its own inputs: offset in bytes from the workspace's start and
+ * number of floats.  Layouts (b the set; NHWC = set, row, column, channel):
+ *   U       b x 4 features       H1, H2   b x 256 (after bias and ReLU)
+ *   X0      H2 as NHWC 4 x 4 x 16 (H2 feature c * 16 + q is pixel q, channel c)
+ *   Y1      NHWC 16 x 16 x 64    Y2  NHWC 32 x 32 x 32    Y3  NHWC 64 x 64 x 16
+ *   LOGITS  b x 128 x 128        DLOGITS  d loss / d logits, b x 128 x 128
+ *   DY3, DY2, DY1  d loss / d Y3, Y2, Y1 (ReLU mask applied), as Y3, Y2, Y1
+ *   DX0     d loss / d X0 (NHWC 4 x 4 x 16)
+ *   DH2, DH1  d loss / d H2, H1 (ReLU mask applied), b x 256
+ * Errors: KL_EINVAL (batch <= 0, NULL outputs, unknown tensor). */
+enum {
+    KL_SUR_T_U = 0, KL_SUR_T_H1, KL_SUR_T_H2, KL_SUR_T_X0, KL_SUR_T_Y1, KL_SUR_T_Y2, KL_SUR_T_Y3, KL_SUR_T_LOGITS,
+    KL_SUR_T_DLOGITS, KL_SUR_T_DY3, KL_SUR_T_DY2, KL_SUR_T_DY1, KL_SUR_T_DX0, KL_SUR_T_DH2, KL_SUR_T_DH1
+};
+int kl_sur_workspace_tensor(int batch, int which, size_t *offset_bytes, size_t *n_floats);
+
 /* logits_out: batch x 128 x 128 FP32 (row-major image per set). */
 int kl_sur_forward(const float *params, const kl_c64 *ta, const kl_c64 *tb, int batch,
                    float *logits_out, void *workspace, size_t workspace_bytes, void *stream);

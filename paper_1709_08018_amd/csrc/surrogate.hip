@@ -852,6 +852,37 @@ size_t kl_sur_num_params(void) { return layout().total; }
 
 size_t kl_sur_workspace_bytes(int batch) { return batch > 0 ? carve(nullptr, batch).bytes : 0; }
 
+int kl_sur_workspace_tensor(int batch, int which, size_t* offset_bytes, size_t* n_floats) {
+    if (batch <= 0 || !offset_bytes || !n_floats) return sur_fail(KL_EINVAL, "bad workspace query");
+    const WS w = carve(nullptr, batch);
+    const WS z = carve((void*)(uintptr_t)256, batch);   // offsets relative to a nonzero base
+    const size_t b = (size_t)batch;
+    const float* p = nullptr;
+    size_t n = 0;
+    switch (which) {
+        case KL_SUR_T_U: p = z.u; n = b * 4; break;
+        case KL_SUR_T_H1: p = z.h1; n = b * 256; break;
+        case KL_SUR_T_H2: p = z.h2; n = b * 256; break;
+        case KL_SUR_T_X0: p = z.x0; n = b * 256; break;
+        case KL_SUR_T_Y1: p = z.y1; n = b * 256 * 64; break;
+        case KL_SUR_T_Y2: p = z.y2; n = b * 1024 * 32; break;
+        case KL_SUR_T_Y3: p = z.y3; n = b * 4096 * 16; break;
+        case KL_SUR_T_LOGITS: p = z.logits; n = b * kImg * kImg; break;
+        case KL_SUR_T_DLOGITS: p = z.dlogits; n = b * kImg * kImg; break;
+        case KL_SUR_T_DY3: p = z.dy3; n = b * 4096 * 16; break;
+        case KL_SUR_T_DY2: p = z.dy2; n = b * 1024 * 32; break;
+        case KL_SUR_T_DY1: p = z.dy1; n = b * 256 * 64; break;
+        case KL_SUR_T_DX0: p = z.dx0; n = b * 256; break;
+        case KL_SUR_T_DH2: p = z.dh2; n = b * 256; break;
+        case KL_SUR_T_DH1: p = z.dh1; n = b * 256; break;
+        default: return sur_fail(KL_EINVAL, "unknown workspace tensor");
+    }
+    (void)w;
+    *offset_bytes = (size_t)((const char*)p - (const char*)(uintptr_t)256);
+    *n_floats = n;
+    return KL_OK;
+}
+
 int kl_gemm_bf16(int M, int N, int K, const float* A, int64_t lda_m, int64_t lda_k, const float* B, int64_t ldb_k,
                  int64_t ldb_n, float* C, int64_t ldc, const float* bias, int relu, int accumulate, void* stream) {
     if (M < 0 || N < 0 || K < 0) return sur_fail(KL_EINVAL, "negative GEMM size");

@@ -131,6 +131,8 @@ def lib():
         L.kl_sur_num_params.restype = sz
         L.kl_sur_workspace_bytes.argtypes = [i]
         L.kl_sur_workspace_bytes.restype = sz
+        L.kl_sur_workspace_tensor.argtypes = [i, i, ctypes.POINTER(sz), ctypes.POINTER(sz)]
+        L.kl_sur_workspace_tensor.restype = i
         L.kl_sur_forward.argtypes = [vp, vp, vp, i, vp, vp, sz, vp]
         L.kl_sur_loss_grad.argtypes = [vp, vp, vp, vp, i, vp, vp, vp, sz, vp]
         L.kl_sur_adam.argtypes = [vp, vp, vp, vp, i, f32, vp]
@@ -393,6 +395,20 @@ def sur_num_params() -> int:
 def sur_workspace(batch: int) -> torch.Tensor:
     n = int(lib().kl_sur_workspace_bytes(batch))
     return torch.empty(n, dtype=torch.uint8, device=_device())
+
+
+SUR_TENSORS = ["u", "h1", "h2", "x0", "y1", "y2", "y3", "logits", "dlogits", "dy3", "dy2", "dy1", "dx0", "dh2",
+               "dh1"]
+
+
+def sur_workspace_tensor(workspace: torch.Tensor, batch: int, name: str) -> torch.Tensor:
+    """A view of one FP32 buffer of the training path in `workspace`
+    (kl_sur_workspace_tensor), flat."""
+    off, n = ctypes.c_size_t(), ctypes.c_size_t()
+    _check(lib().kl_sur_workspace_tensor(int(batch), SUR_TENSORS.index(name), ctypes.byref(off), ctypes.byref(n)))
+    if off.value + 4 * n.value > workspace.numel():
+        raise KLError(KL_EINVAL, "workspace too small for this batch")
+    return workspace[off.value:off.value + 4 * n.value].view(torch.float32)
 
 
 def as_c64(z) -> torch.Tensor:

@@ -107,13 +107,13 @@ def train(ta, tb, occ: torch.Tensor, steps: int, batch: int = 128, lr: float = 2
 def gate_threshold(uncertainty: np.ndarray, iou: np.ndarray, target: float = IOU_TARGET) -> float:
     """Largest uncertainty u such that every calibration set with uncertainty
     <= u reaches IoU >= target (-inf when even the most certain one fails)."""
-    order = np.argsort(uncertainty, kind="stable")
-    tau = -np.inf
-    for i in order:
-        if iou[i] < target:
-            break
-        tau = float(uncertainty[i])
-    return tau
+    unc = np.asarray(uncertainty, np.float64)
+    fail = unc[np.asarray(iou) < target]
+    limit = fail.min() if len(fail) else np.inf
+    # strictly below the most certain failing set: a passing set that ties
+    # with it cannot be told apart at scan time
+    ok = unc[unc < limit]
+    return float(ok.max()) if len(ok) else -np.inf
 
 
 def scan(params: torch.Tensor, ta, tb, tau: float, depth: int = DEPTH, batch: int = 512):

@@ -66,14 +66,163 @@ def _sets(n, seed):
     return ta, tb
 
 
-def test_forward_matches_reference():
-    # 36 sets: every layer's buffers exceed 2^21 elements, beyond one thread per element of a capped grid
+U32 = 2.0 ** -24
+
+
+def _gamma(n):
+    """Bound of an FP32 sum of n terms in any order, relative to the sum of
+    their magnitudes: (n - 1) u / (1 - (n - 1) u)."""
+    return (n - 1) * U32 / (1 - (n - 1) * U32)
+
+
+def _close(name, got, ref, S, n):
+    """Element by element: |got - ref| <= gamma(n) S + the rounding of an
+    FP32 store."""
+    got, ref, S = (np.asarray(a, np.float64) for a in (got, ref, S))
+    bound = _gamma(n) * S + U32 * np.abs(ref)
+    err = np.abs(got - ref)
+    bad = err > bound
+    if bad.any():
+        i = np.unravel_index(np.argmax(err - bound), err.shape)
+        raise AssertionError(f"{name}: {int(bad.sum())} of {err.size} elements beyond their bound; worst at {i}: "
+                             f"got {got[i]!r} ref {ref[i]!r} bound {bound[i]!r}")
+    return float((err / np.maximum(bound, 1e-300)).max())
+
+
+def _nchw(x_nhwc, B, H, C):
+    return x_nhwc.reshape(B, H, H, C).transpose(0, 3, 1, 2)
+
+
+def _nhwc(x_nchw):
+    return x_nchw.transpose(0, 2, 3, 1)
+
+
+def test_training_layers_match_reference_element_by_element():
+    """Every layer of the training forward and backward on the GPU, checked
+    on its own FP32 inputs (read from the workspace, kl_sur_workspace_tensor):
+    the reference rounds those same inputs to bfloat16 as the GPU does and
+    sums the exact bfloat16 products in FP64, so the GPU's result may differ
+    only by its FP32 sums, element by element within gamma(n) times the sum
+    of the terms' magnitudes (n terms, in any order); permutations and ReLU
+    masks match exactly.  Layer shapes: nn_ref's header."""
+    B = 4
+    flat = _params(1).astype(np.float32).astype(np.float64)
+    P = N.unflatten(flat)
+    ta, tb = _sets(B, 12)
+    rng = np.random.default_rng(3)
+    targets = (rng.random((B, 128, 128)) < 0.05).astype(np.uint8)
+    ws = kl.sur_workspace(B)
+    loss, grad = kl.sur_loss_grad(_dev(flat), ta, tb, _dev(targets, torch.uint8), workspace=ws)
+    torch.cuda.synchronize()
+    T = {n: kl.sur_workspace_tensor(ws, B, n).cpu().numpy().astype(np.float64) for n in kl.SUR_TENSORS}
+    G = N.unflatten(grad.cpu().numpy().astype(np.float64))
+    bf, A = N.bf16, np.abs
+    worst = {}
+
+    # features: the FP64 formula rounded once to FP32
+    np.testing.assert_array_equal(T["u"].reshape(B, 4), N.features(ta, tb).astype(np.float32))
+    u = T["u"].reshape(B, 4)
+    # linear layers (bias and ReLU; ReLU cannot increase an error)
+    for name, x, W, b, n_in in (("h1", u, P["W1"], P["b1"], 4), ("h2", T["h1"].reshape(B, 256), P["W2"], P["b2"], 256)):
+        ref = np.maximum(bf(x) @ bf(W) + b, 0)
+        worst[name] = _close(name, T[name].reshape(B, 256), ref, A(bf(x)) @ A(bf(W)) + A(b), n_in + 1)
+    # X0 is H2 rearranged
+    h2 = T["h2"].reshape(B, 16, 4, 4)
+    np.testing.assert_array_equal(_nchw(T["x0"], B, 4, 16), h2)
+    # transposed convolutions, NHWC buffers
+    ins = [("x0", 4, 16), ("y1", 16, 64), ("y2", 32, 32), ("y3", 64, 16)]
+    outs = ["y1", "y2", "y3", "logits"]
+    for n, ((K, c, st, pd), (xin, Hi, Ci), yout) in enumerate(zip(N.CONVS, ins, outs)):
+        x = _nchw(T[xin], B, Hi, Ci)
+        z = N.convT(bf(x), bf(P[K]), P[c], st, pd)
+        S = N.convT(A(bf(x)), A(bf(P[K])), A(P[c]), st, pd)
+        taps = (-(-4 // st)) ** 2
+        if n < 3:
+            worst[yout] = _close(yout, T[yout], _nhwc(np.maximum(z, 0)).ravel(), _nhwc(S).ravel(), Ci * taps + 1)
+        else:
+            worst[yout] = _close(yout, T[yout].reshape(B, 128, 128), z[:, 0], S[:, 0], Ci * taps + 1)
+    # loss gradient: (sigmoid(z) - t) / n from the GPU's logits (expf and a few FP32 roundings)
+    zl = T["logits"].reshape(B, 128, 128)
+    sg = 1 / (1 + np.exp(-zl))
+    npx = zl.size
+    dref = (sg - targets) / npx
+    dl = T["dlogits"].reshape(B, 128, 128)
+    assert (np.abs(dl - dref) <= 8 * U32 * (1 + np.abs(sg - targets)) / npx).all()
+    # transposed convolutions backward: the input gradient (then the ReLU mask of
+    # the forward activation), the weight gradient and the bias gradient
+    douts = [("dlogits", 128, 1), ("dy3", 64, 16), ("dy2", 32, 32), ("dy1", 16, 64)]
+    dins = ["dy3", "dy2", "dy1", "dx0"]
+    for n in range(3, -1, -1):
+        K, c, st, pd = N.CONVS[n]
+        dname, Ho, Co = douts[3 - n]
+        xin, Hi, Ci = ins[n]
+        d = _nchw(T[dname], B, Ho, Co)
+        x = _nchw(T[xin], B, Hi, Ci)
+        dx, dK, db = N.convT_backward(x, P[K], d, st, pd, rnd=bf)
+        Sx, SK, _ = N.convT_backward(A(bf(x)), A(bf(P[K])), A(bf(d)), st, pd)
+        if n > 0:
+            mask = T[xin] > 0
+            worst[dins[3 - n]] = _close(dins[3 - n], T[dins[3 - n]], _nhwc(dx).ravel() * mask,
+                                        _nhwc(Sx).ravel() * mask, Co * 16)
+        else:
+            worst["dx0"] = _close("dx0", T["dx0"], _nhwc(dx).ravel(), _nhwc(Sx).ravel(), Co * 16)
+        worst["g" + K] = _close("grad " + K, G[K], dK, SK, B * Hi * Hi)
+        worst["g" + c] = _close("grad " + c, G[c], d.sum(axis=(0, 2, 3)), A(d).sum(axis=(0, 2, 3)), B * Ho * Ho)
+    # DH2 is DX0 rearranged and masked by H2 > 0
+    dh2 = _nchw(T["dx0"], B, 4, 16).reshape(B, 256) * (T["h2"].reshape(B, 256) > 0)
+    np.testing.assert_array_equal(T["dh2"].reshape(B, 256), dh2)
+    h1 = T["h1"].reshape(B, 256)
+    worst["gW2"] = _close("grad W2", G["W2"], bf(h1).T @ bf(dh2), A(bf(h1)).T @ A(bf(dh2)), B)
+    worst["gb2"] = _close("grad b2", G["b2"], dh2.sum(0), A(dh2).sum(0), B)
+    dh1 = T["dh1"].reshape(B, 256)
+    ref = (bf(dh2) @ bf(P["W2"]).T) * (h1 > 0)
+    worst["dh1"] = _close("dh1", dh1, ref, (A(bf(dh2)) @ A(bf(P["W2"])).T) * (h1 > 0), 256)
+    worst["gW1"] = _close("grad W1", G["W1"], bf(u).T @ bf(dh1), A(bf(u)).T @ A(bf(dh1)), B)
+    worst["gb1"] = _close("grad b1", G["b1"], dh1.sum(0), A(dh1).sum(0), B)
+    print("largest error / bound per layer:", {k: round(v, 4) for k, v in worst.items()})
+    # the loss: the mean BCE of the GPU's logits
+    assert abs(loss.item() - N.bce_loss(zl, targets)[0]) <= 1e-5 * N.bce_loss(zl, targets)[0]
+
+
+def test_fused_forward_matches_the_training_forward():
+    """Inference (one fused kernel per set, activations in LDS as bfloat16)
+    rounds the same operands to bfloat16 as the training forward; the two
+    differ by the order of their FP32 sums, and where that moves an
+    activation across a bfloat16 rounding boundary, by one bfloat16 step of
+    it.  So nearly every logit agrees within gamma(n) of the last layer's
+    magnitudes, computed from the training path's own last input, and every
+    logit within one bfloat16 step of every term of the last layer."""
+    B = 36
+    flat = _params(0).astype(np.float32).astype(np.float64)
+    P = N.unflatten(flat)
+    ta, tb = _sets(B, 11)
+    rng = np.random.default_rng(8)
+    targets = (rng.random((B, 128, 128)) < 0.05).astype(np.uint8)
+    ws = kl.sur_workspace(B)
+    kl.sur_loss_grad(_dev(flat), ta, tb, _dev(targets, torch.uint8), workspace=ws)
+    z_train = kl.sur_workspace_tensor(ws, B, "logits").cpu().numpy().astype(np.float64).reshape(B, 128, 128)
+    y3 = _nchw(kl.sur_workspace_tensor(ws, B, "y3").cpu().numpy().astype(np.float64), B, 64, 16)
+    z = kl.sur_forward(_dev(flat), ta, tb).cpu().numpy().astype(np.float64)
+    K, c, st, pd = N.CONVS[3]
+    S = N.convT(np.abs(N.bf16(y3)), np.abs(N.bf16(P[K])), np.abs(P[c]), st, pd)[:, 0]
+    err = np.abs(z - z_train)
+    tight = 2 * _gamma(65) * S + 2 * U32 * np.abs(z_train)
+    frac = float((err > tight).mean())
+    print(f"fused vs training logits: {frac:.2e} of {err.size} beyond 2 gamma(65) S; max err / S {(err / S).max():.2e}")
+    assert frac < 1e-3
+    assert (err <= 2.0 ** -8 * S + tight).all()
+
+
+def test_fused_forward_logits_match_reference_statistically():
+    """The fused forward against the FP64 reference from the features on:
+    rounding differences compound over six layers, so this is checked on the
+    whole image: the logits' RMS error stays within 1e-3 of their RMS."""
     flat = _params(0)
     ta, tb = _sets(36, 11)
     z = kl.sur_forward(_dev(flat), ta, tb).cpu().numpy()
-    ref, _ = N.forward(flat, ta, tb, rnd=N.bf16)
+    ref, _ = N.forward(flat.astype(np.float32).astype(np.float64), ta, tb, rnd=N.bf16)
     rms = np.sqrt((ref ** 2).mean())
-    assert np.abs(z - ref).max() <= 2e-2 * rms + 1e-4, (np.abs(z - ref).max(), rms)
+    assert np.sqrt(((z - ref) ** 2).mean()) <= 1e-3 * rms
 
 
 def test_fused_forward_is_batch_independent():
@@ -100,24 +249,6 @@ def test_fused_forward_agrees_with_the_training_forward():
     loss, _ = kl.sur_loss_grad(_dev(flat), ta, tb, _dev(targets, torch.uint8))
     z = kl.sur_forward(_dev(flat), ta, tb).cpu().numpy().astype(np.float64)
     assert abs(N.bce_loss(z, targets)[0] - loss.item()) <= 1e-4 * abs(loss.item())
-
-
-def test_loss_and_gradients_match_reference():
-    flat = _params(1)
-    ta, tb = _sets(12, 12)
-    rng = np.random.default_rng(3)
-    targets = (rng.random((12, 128, 128)) < 0.05).astype(np.uint8)
-    loss, grad = kl.sur_loss_grad(_dev(flat), ta, tb, _dev(targets, torch.uint8))
-    ref_loss, ref_grad = N.loss_and_grad(flat, ta, tb, targets, rnd=N.bf16)
-    assert abs(loss.item() - ref_loss) <= 1e-3 * abs(ref_loss)
-    g = grad.cpu().numpy().astype(np.float64)
-    off = 0
-    for name, shape in N.LAYOUT:
-        n = int(np.prod(shape))
-        a, b = g[off:off + n], ref_grad[off:off + n]
-        rel = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
-        assert rel <= 3e-2, (name, rel)
-        off += n
 
 
 def test_adam_matches_reference():
@@ -202,3 +333,28 @@ def test_training_reduces_loss():
         losses.append(loss.item())
     const = -(p0 * np.log(p0) + (1 - p0) * np.log(1 - p0))
     assert np.mean(losses[-16:]) < 0.8 * const, (const, losses[:8], losses[-8:])
+
+
+def test_gated_scan_keeps_accepted_predictions_and_renders_the_rest():
+    """scan(): the sets the gate accepts keep the surrogate's predicted
+    occupancy (logits > 0), the others are the plain renderer's occupancy bit
+    for bit; after a short training, every calibration set at or below the
+    calibrated threshold reaches the IoU target."""
+    from paper_1709_08018_amd import surrogate as S
+    ta, tb = _sets(96, 21)
+    occ = _targets(ta, tb, 10)
+    params, _ = S.train(ta[:64], tb[:64], occ[:64], steps=150, batch=16, lr=2e-3, seed=0)
+    logits = S.predict(params, ta[64:], tb[64:])
+    iou = kl.iou(occ[64:], logits=logits).cpu().numpy()
+    unc = kl.sur_uncertainty(logits).cpu().numpy()
+    target = float(np.median(iou))
+    tau = S.gate_threshold(unc, iou, target)
+    assert (iou[unc <= tau] >= target).all()
+    tau_s = float(np.median(unc))
+    scan_occ, accepted, _ = S.scan(params, ta[64:], tb[64:], tau_s, depth=10)
+    np.testing.assert_array_equal(accepted, unc <= tau_s)
+    assert accepted.any() and (~accepted).any()
+    pred = (logits > 0).to(torch.uint8)
+    for i in range(len(accepted)):
+        want = pred[i] if accepted[i] else occ[64 + i]
+        assert torch.equal(scan_occ[i], want), i
