@@ -636,6 +636,62 @@ def leg_walk(args):
     return out
 
 
+def surrogate_summary():
+    """The metric's second half, measured in the headline run: the learned
+    surrogate trained on 18,000 renders of depth 14 (the surrogate leg's
+    configuration), its gate calibrated on 2,000 more at the IoU target 0.95,
+    and the scan of 2,000 held-out sets -- surrogate, gate and fallback
+    renders -- timed against the plain renderer's scan (median of 5 each)."""
+    from paper_1709_08018_amd import surrogate as S
+
+    res, _ = S.run(train_n=18000, calib_n=2000, test_n=2000, steps=12000, batch=128, lr=2e-3, log_every=0)
+    sc = res["scan"]
+    return {"metric": "surrogate vs plain scan time @IoU>=0.95", "iou_target": S.IOU_TARGET,
+            "held_out_sets": res["held_out_sets"], "accepted": sc["accepted"],
+            "gated_scan_s": sc["surrogate_seconds"], "plain_scan_s": sc["plain_seconds"],
+            "speedup": sc["speedup"], "held_out_mean_iou": round(res["held_out"]["mean_iou_surrogate"], 4),
+            "held_out_max_iou": round(res["held_out_iou_quantiles"]["max"], 4),
+            "scan_min_iou_vs_plain": round(sc["min_iou_vs_plain"], 4), "train_sets": res["train_sets"],
+            "train_seconds": res["train_seconds"], "data_seconds": res["data_seconds"]}
+
+
+def leg_surrogate_curve(args):
+    """Held-out IoU of the surrogate against the number of training renders
+    (18k, 100k, 500k sets at depth 14), each trained for 12,000 steps of 128
+    sets, and 500k for 48,000 steps: whether more data closes the gap to the
+    gate's IoU target of 0.95."""
+    import numpy as np
+    import torch
+
+    from paper_1709_08018_amd import kl
+    from paper_1709_08018_amd import surrogate as S
+    from paper_1709_08018_amd import workloads as wl
+
+    ta_te, tb_te = wl.surrogate_sets(2000, seed=2)
+    occ_te = S.render_occupancy(ta_te, tb_te)
+    ta_all, tb_all = wl.surrogate_sets(500_000, seed=1)
+    t0 = time.perf_counter()
+    occ_all = S.render_occupancy(ta_all, tb_all)
+    torch.cuda.synchronize()
+    data_s = time.perf_counter() - t0
+    rows = []
+    for n, steps in ((18_000, 12_000), (100_000, 12_000), (500_000, 12_000), (500_000, 48_000)):
+        t0 = time.perf_counter()
+        params, hist = S.train(ta_all[:n], tb_all[:n], occ_all[:n], steps, 128, 2e-3, 0, log_every=steps)
+        torch.cuda.synchronize()
+        tr_s = time.perf_counter() - t0
+        logits = S.predict(params, ta_te, tb_te)
+        iou = kl.iou(occ_te, logits=logits).cpu().numpy()
+        rows.append({"train_sets": n, "steps": steps, "epochs": round(steps * 128 / n, 2), "train_seconds": round(tr_s, 1),
+                     "final_loss": round(hist[-1][1], 5) if hist else None,
+                     "held_out_mean_iou": round(float(iou.mean()), 4),
+                     "held_out_p90_iou": round(float(np.quantile(iou, 0.9)), 4),
+                     "held_out_max_iou": round(float(iou.max()), 4),
+                     "held_out_at_0.95": int((iou >= 0.95).sum())})
+        print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+    return {"workload": "surrogate_curve", "held_out_sets": 2000, "data_seconds_500k": round(data_s, 1), "curve": rows}
+
+
 def leg_calib(args):
     """Instruction-throughput calibration of the VALU roofline (libkl_calib.so):
     SIMD cycles per wave64 instruction of each class the renderer's word loop
@@ -723,8 +779,10 @@ def main():
                     help="untimed steps after the clock ramp (CLOCK_RAMP_MS of untimed steps first)")
     ap.add_argument("--workload", default="quasifuchsian_d18",
                     choices=["quasifuchsian_d18", "quasifuchsian_d22", "decode", "bounded", "batch256", "fuchsian_tiling_d10",
-                             "maskit_tiling_d14", "cayley", "surrogate", "surrogate_kernels", "hist", "calib",
-                             "walk"])
+                             "maskit_tiling_d14", "cayley", "surrogate", "surrogate_kernels", "surrogate_curve", "hist",
+                             "calib", "walk"])
+    ap.add_argument("--no-surrogate", action="store_true",
+                    help="leave the surrogate's training and gated scan out of the headline line")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="after the steps, copy 256 MiB device to device twice (a kernel of known HBM "
@@ -744,7 +802,8 @@ def main():
     torch.cuda.set_device(0)
     legs = {"quasifuchsian_d22": leg_d22, "decode": leg_decode, "bounded": leg_bounded, "batch256": leg_batch, "fuchsian_tiling_d10": leg_tiling,
             "maskit_tiling_d14": leg_maskit, "cayley": leg_cayley, "surrogate": leg_surrogate, "hist": leg_hist,
-            "calib": leg_calib, "walk": leg_walk, "surrogate_kernels": leg_surrogate_kernels}
+            "calib": leg_calib, "walk": leg_walk, "surrogate_kernels": leg_surrogate_kernels,
+            "surrogate_curve": leg_surrogate_curve}
     if args.workload in legs:
         print(json.dumps(legs[args.workload](args)), flush=True)
         return
@@ -851,6 +910,8 @@ def main():
                        "note": "untimed steps run before the counted warm-up until the GPU clock has ramped"},
         "fp64": fp64_leg(W, image, n_words, hip),
     }
+    if not args.no_surrogate:
+        out["surrogate"] = surrogate_summary()
     if not args.no_cpu_baseline:
         cb, ref_img, ref_drop = cpu_baseline(W, 15.0)
         out["cpu_baseline"] = cb
