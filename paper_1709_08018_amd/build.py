@@ -14,7 +14,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libkl.so")
-SOURCES = [os.path.join(CSRC, f) for f in ("kernels.hip", "cayley.hip", "surrogate.hip", "walk.hip", "abi.cpp")]
+SOURCES = [os.path.join(CSRC, f) for f in ("kernels.hip", "decode.hip", "cayley.hip", "surrogate.hip", "walk.hip", "abi.cpp")]
 CALIB_LIB = os.path.join(PKG, "libkl_calib.so")
 CALIB_SOURCES = [os.path.join(CSRC, "calib.hip")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

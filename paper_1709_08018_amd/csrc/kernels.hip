@@ -23,10 +23,7 @@
 // pole form of the head (compute_head, word_value below), which every
 // kernel shares.
 #include <algorithm>
-#include <array>
-#include <atomic>
 #include <type_traits>
-#include <utility>
 
 #include "kl_internal.hpp"
 
@@ -93,234 +90,6 @@ __device__ inline uint64_t decode_packed(uint64_t index, int n) {
         prev = c;
     }
     return letters;
-}
-
-// ------------------------------------------------------------------ decode
-// A word of depth d is its first letter index / 3^(d-1) followed by the
-// d - 1 base-3 digits of the rest, most significant first; letter j is the
-// t_j-th letter that is not the inverse of letter j - 1.  The digits go six
-// at a time through a table, built once per workgroup in LDS, that maps
-// (previous letter, six digits) to the next six letters, 2 bits each.  A
-// shorter last group is padded with zero digits at its end, whose letters
-// are not kept.  Words are staged in LDS 256 at a time and written as one
-// contiguous byte range per tile.  For depths 16 .. 32 into a 16-byte
-// aligned destination a word is staged packed, 2 bits a letter in 64 bits,
-// and each thread forms 16-byte pieces of the tile's output, each from the
-// at most two words it covers; otherwise words are staged byte by byte.
-constexpr uint32_t kDigitGroup = 729;   // 3^6
-
-// Four letters, 2 bits each in b (< 256), as four bytes.
-__device__ __forceinline__ uint32_t spread_letters(uint32_t b) {
-    return (b | (b << 6) | (b << 12) | (b << 18)) & 0x03030303u;
-}
-
-__device__ __forceinline__ void put_letters(uint64_t& lo, uint64_t& hi, int pos, uint64_t bits) {
-    const int sh = 2 * pos;   // pos <= 39, bits < 2^12
-    if (sh < 64) {
-        lo |= bits << sh;
-        if (sh > 52) hi |= bits >> (64 - sh);
-    } else {
-        hi |= bits << (sh - 64);
-    }
-}
-
-__device__ __forceinline__ uint8_t letter_at(uint64_t lo, uint64_t hi, int j) {
-    return (uint8_t)((j < 32 ? lo >> (2 * j) : hi >> (2 * j - 64)) & 3u);
-}
-
-// K consecutive words per thread, a tile of 256 K words per workgroup.  With
-// PACK (depths 16 .. 32, 16-byte aligned destination) a thread unranks its
-// first word and steps to the next ones by adding one to the digit groups,
-// and words are staged packed; otherwise K = 1 and words are staged as bytes.
-// D > 0 fixes the depth at compile time (the packed path has one kernel per
-// depth, so its digit groups, shifts and divisions are constants); D = 0
-// takes it from the argument.
-template <int K, bool PACK, int D = 0>
-__global__ __launch_bounds__(256) void decode_kernel(uint64_t first, uint64_t count, int depth_arg,
-                                                     uint8_t* __restrict__ out) {
-    static_assert(!PACK || (D >= 16 && D <= 32), "the packed staging takes a fixed depth of 16 .. 32");
-    const int depth = D ? D : depth_arg;
-    constexpr uint32_t kTileWords = 256u * K;
-    __shared__ uint16_t next6[4 * kDigitGroup];
-    __shared__ __align__(16) uint8_t stage[PACK ? kTileWords * 8 : 256 * KL_MAX_DEPTH];
-    uint64_t* packed = (uint64_t*)stage;   // PACK: the tile's words, 2 bits a letter
-    const int tid = threadIdx.x;
-    for (uint32_t e = tid; e < 4 * kDigitGroup; e += 256) {
-        int prev = (int)(e / kDigitGroup);
-        uint32_t v = e - (uint32_t)prev * kDigitGroup;
-        int dg[6];
-        for (int j = 5; j >= 0; --j) {
-            const uint32_t q = v / 3;
-            dg[j] = (int)(v - 3 * q);
-            v = q;
-        }
-        uint32_t bits = 0;
-        for (int j = 0; j < 6; ++j) {
-            const int c = dg[j] + (dg[j] >= inv_letter(prev));
-            bits |= (uint32_t)c << (2 * j);
-            prev = c;
-        }
-        next6[e] = (uint16_t)bits;
-    }
-    __syncthreads();
-    const int n = depth - 1, groups = n / 6, p = n - 6 * groups;   // p digits in a last, shorter group
-    uint32_t pow_p = 1;
-    for (int j = 0; j < p; ++j) pow_p *= 3;
-    const uint32_t pad = kDigitGroup / pow_p;   // 3^(6 - p)
-    const uint64_t tiles = (count + kTileWords - 1) / kTileWords;
-    for (uint64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
-        const uint64_t tfirst = tile * kTileWords;
-        const uint64_t rem = count - tfirst;
-        const uint32_t nw = rem < kTileWords ? (uint32_t)rem : kTileWords;
-        uint8_t* dst = out + tfirst * (uint64_t)depth;
-        const uint32_t w0 = (uint32_t)tid * K;   // this thread's first word in the tile
-        if (w0 < nw) {
-            uint64_t r = first + tfirst + w0;
-            uint32_t last = 0;
-            if (p) {
-                uint64_t q = r;
-                for (int j = 0; j < p; ++j) q = div3_u64(q);
-                last = (uint32_t)(r - q * pow_p);
-                r = q;
-            }
-            uint32_t g[6];   // groups of six digits, least significant first
-#pragma unroll
-            for (int k = 0; k < 6; ++k) {
-                g[k] = 0;
-                if (k < groups) {
-                    const uint64_t q = r / kDigitGroup;
-                    g[k] = (uint32_t)(r - q * kDigitGroup);
-                    r = q;
-                }
-            }
-            uint32_t f = (uint32_t)r;   // the first letter
-            // The lowest group (the last p digits, or g[0] when p = 0) changes
-            // from one word to the next; the letters above it are kept until a
-            // carry leaves it.
-            const int low = p ? 0 : 1;   // groups kk >= low lie above the lowest group
-            uint64_t plo = 0, phi = 0;
-            int pprev = 0, ppos = 0;
-            bool stale = true;
-#pragma unroll
-            for (int k = 0; k < K; ++k) {
-                if (w0 + (uint32_t)k < nw) {   // an index below first + count: f <= 3
-                    if (stale) {
-                        int prev = (int)f;
-                        uint64_t lo = (uint64_t)prev, hi = 0;
-                        int pos = 1;
-#pragma unroll
-                        for (int kk = 5; kk >= 0; --kk) {
-                            if (kk < groups && kk >= low) {
-                                const uint32_t bits = next6[prev * kDigitGroup + g[kk]];
-                                put_letters(lo, hi, pos, bits);
-                                prev = (int)(bits >> 10);
-                                pos += 6;
-                            }
-                        }
-                        plo = lo;
-                        phi = hi;
-                        pprev = prev;
-                        ppos = pos;
-                        stale = false;
-                    }
-                    uint64_t lo = plo, hi = phi;
-                    if (p) {
-                        const uint32_t bits = next6[pprev * kDigitGroup + last * pad] & ((1u << (2 * p)) - 1u);
-                        put_letters(lo, hi, ppos, bits);
-                    } else if (groups > 0) {
-                        put_letters(lo, hi, ppos, next6[pprev * kDigitGroup + g[0]]);
-                    }
-                    if constexpr (PACK) {
-                        packed[w0 + k] = lo;
-                    } else {
-                        uint8_t* w = stage + (w0 + k) * depth;
-                        for (int j = 0; j < depth; ++j) w[j] = letter_at(lo, hi, j);
-                    }
-                }
-                if (k + 1 < K) {
-                    // the next index: add one to the digit groups
-                    uint32_t c = 1;
-                    if (p) {
-                        last += 1;
-                        c = last == pow_p ? 1u : 0u;
-                        if (c) last = 0;
-                        stale = stale || c;
-                    }
-#pragma unroll
-                    for (int kk = 0; kk < 6; ++kk) {
-                        if (kk < groups) {
-                            const uint32_t v = g[kk] + c;
-                            c = v == kDigitGroup ? 1u : 0u;
-                            g[kk] = c ? 0u : v;
-                            if (kk == 0 && !p) stale = stale || c;
-                        }
-                    }
-                    if (groups == 0 && !p) stale = true;
-                    f += c;
-                }
-            }
-        }
-        __syncthreads();
-        const uint32_t nbytes = nw * (uint32_t)depth;
-        if constexpr (PACK) {
-            // byte B of the tile is letter B - w d of word w = B / d; a piece
-            // starting in word w ends in w or w + 1
-            const uint32_t n16 = nbytes / 16;
-            for (uint32_t i = tid; i < n16; i += 256) {
-                const uint32_t B = 16 * i;
-                const uint32_t w = B / (uint32_t)D;
-                const uint32_t o = B - w * (uint32_t)depth;
-                const uint32_t rest = (uint32_t)depth - o;   // letters of word w in the piece
-                uint64_t L = packed[w] >> (2 * o);
-                if (rest < 16) L |= packed[w + 1] << (2 * rest);
-                const uint32_t x = (uint32_t)L;
-                ((uint4*)dst)[i] = make_uint4(spread_letters(x & 0xFFu), spread_letters((x >> 8) & 0xFFu),
-                                              spread_letters((x >> 16) & 0xFFu), spread_letters(x >> 24));
-            }
-            for (uint32_t b = n16 * 16 + tid; b < nbytes; b += 256) {
-                const uint32_t w = b / (uint32_t)D;
-                dst[b] = (uint8_t)((packed[w] >> (2 * (b - w * (uint32_t)depth))) & 3u);
-            }
-        } else if (((uintptr_t)dst & 15u) == 0) {
-            const uint32_t n16 = nbytes / 16;
-            for (uint32_t i = tid; i < n16; i += 256) ((uint4*)dst)[i] = ((const uint4*)stage)[i];
-            for (uint32_t i = n16 * 16 + tid; i < nbytes; i += 256) dst[i] = stage[i];
-        } else {
-            for (uint32_t i = tid; i < nbytes; i += 256) dst[i] = stage[i];
-        }
-        __syncthreads();
-    }
-}
-
-using DecodeKernel = void (*)(uint64_t, uint64_t, int, uint8_t*);
-
-template <int... I>
-static constexpr std::array<DecodeKernel, sizeof...(I)> packed_decode_kernels(std::integer_sequence<int, I...>) {
-    return {{decode_kernel<8, true, 16 + I>...}};
-}
-
-hipError_t launch_decode(uint64_t first, uint64_t count, int depth, uint8_t* out, hipStream_t s) {
-    if (count == 0) return hipSuccess;
-    static constexpr std::array<DecodeKernel, 17> kPacked = packed_decode_kernels(std::make_integer_sequence<int, 17>{});
-    const bool pack = depth >= 16 && depth <= 32 && ((uintptr_t)out & 15u) == 0;
-    const DecodeKernel fn = pack ? kPacked[depth - 16] : decode_kernel<1, false>;
-    const uint64_t tile_words = pack ? 2048 : 256;
-    const uint64_t tiles = (count + tile_words - 1) / tile_words;
-    // as many workgroups as fit on a CU at once, so that none waits for a
-    // second round (the same on every gfx950 device; asked once per kernel)
-    static std::atomic<int> fits[18];
-    const int slot = pack ? depth - 16 : 17;
-    int resident = fits[slot].load(std::memory_order_relaxed);
-    if (resident == 0) {
-        int n = 0;
-        resident = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(fn), 256, 0) ==
-                                   hipSuccess && n > 0 ? n : 1;
-        fits[slot].store(resident, std::memory_order_relaxed);
-    }
-    const uint64_t blocks = std::min<uint64_t>(tiles, (uint64_t)device_cu_count() * (uint64_t)resident);
-    void* args[] = {&first, &count, &depth, &out};
-    hipError_t e = hipLaunchKernel(reinterpret_cast<const void*>(fn), dim3((unsigned)blocks), dim3(256), args, 0, s);
-    return e != hipSuccess ? e : hipGetLastError();
 }
 
 // ------------------------------------------------------------------ prefix table

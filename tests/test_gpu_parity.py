@@ -69,17 +69,23 @@ def test_decode_sampled_ranges(depth):
 
 @pytest.mark.parametrize("depth", list(range(16, 33)))
 def test_decode_packed_path_every_word_of_ranges(depth):
-    """Depths 16..32 into an aligned destination take the packed staging, eight
-    consecutive words a thread stepped by carries through the digit groups:
-    ranges that start just before a carry out of the lowest group and out of
-    the next one, that cross tiles of 2048 words, and that end at the last
-    word, every word against the oracle's enumeration; the same range into an
-    unaligned destination (byte staging) gives the same bytes."""
+    """Depths 16..32 into an aligned destination take the packed stream
+    staging: 8 (even depths) or 16 (odd) consecutive words a thread, whose
+    low part (the last 3..8 digits: the short digit group, widened by six
+    when it has fewer than three) wraps at most once among them, picking the
+    letters above it for the high digits or for those plus one.  Ranges
+    that start just before a wrap of the low part, of the shortest group and
+    of the group above, that cross tiles of 2048 and 4096 words, and that end
+    at the last word, every word against the oracle's enumeration; the same
+    range into an unaligned destination (byte staging) gives the same
+    bytes."""
     n = kl.num_words(depth)
     p = (depth - 1) % 6
-    low = 3 ** p if p else 729              # radix of the lowest digit group
-    starts = [0, low - 5, low * 729 - 11, 3 * low * 729 - 2, n // 3 + 7, n - 4101]
-    counts = [4101, 37, 2049, 300, 2048, 4101]
+    low = 3 ** p if p else 729              # radix of the shortest digit group
+    radix = 3 ** (p if p >= 3 else p + 6)   # radix of the packed kernel's low part
+    starts = [0, low - 5, low * 729 - 11, 3 * low * 729 - 2, n // 3 + 7, n - 4101,
+              radix - 13, radix * 729 - 7, 5 * radix - 1]
+    counts = [4101, 37, 2049, 300, 2048, 4101, 4097, 300, 33]
     def oracle_words(first, count):
         # the oracle's unranking word by word (its depth-first enumeration
         # walks every word before `first`)
@@ -101,10 +107,10 @@ def test_decode_packed_path_every_word_of_ranges(depth):
 
 @pytest.mark.parametrize("depth,count", [(18, 12_000_000), (17, 12_000_000), (32, 9_000_000), (40, 3_000_000)])
 def test_decode_many_tiles_per_workgroup(depth, count):
-    """Ranges long enough that every workgroup takes many tiles (a workgroup
-    steps its threads' first indices from tile to tile by adding digit
-    groups): rows at both ends of every 2048-word and 256-word tile boundary
-    in a stretch, and random rows, against the oracle's unranking."""
+    """Ranges long enough that every workgroup takes many tiles: rows at both
+    ends of every 2048-word and 256-word tile boundary in a stretch (4096-word
+    tiles at odd depths fall on them too), and random rows, against the
+    oracle's unranking."""
     n = kl.num_words(depth)
     first = n // 7
     out = kl.decode(first, count, depth)
