@@ -592,6 +592,15 @@ __device__ __forceinline__ void close_run(Runs<DROP>& s, uint32_t t_words, const
     else if (DROP) s.drop += cnt;
 }
 
+// close_run for a run whose key is `key` (the lane's state already holds the
+// next run's key)
+template <bool DROP, typename Sink>
+__device__ __forceinline__ void close_run_key(Runs<DROP>& s, uint64_t key, uint32_t t_words, const Sink& sink) {
+    const uint32_t cnt = t_words - s.start;
+    if (key_inside(key, sink.kr)) sink.add(key_row(key), key_col(key), cnt);
+    else if (DROP) s.drop += cnt;
+}
+
 // open a new run at word count t_words (its key outside until a word sets it)
 template <bool DROP>
 __device__ __forceinline__ void reset_run(Runs<DROP>& s, uint32_t t_words) {
@@ -634,9 +643,12 @@ __device__ __forceinline__ void walk_tails_s(const Head<T>& h, const unsigned ch
                 if constexpr (DUAL)   // the general form can give NaN
                     if (!((px == px) & (py == py))) key = kOutsideKey;
                 if (MASKED && !live) key = kOutsideKey;
-                if (key != s.key) {
-                    close_run(s, tw + u, sink);
-                    s.key = key;
+                // the new key replaces the open run's unconditionally (a
+                // rename, no copy); the run closes with the key it had
+                const uint64_t open = s.key;
+                s.key = key;
+                if (key != open) {
+                    close_run_key(s, open, tw + u, sink);
                     s.start = tw + u;
                 }
             }

@@ -148,3 +148,23 @@ def test_block_bounds_value_is_checked():
         w = kl.make_window(WIN_64)
         kl._check(kl.lib().kl_render_ex(kl._c(C2[0]), kl._c(C2[1]), 10, ctypes.byref(w), img.data_ptr(),
                                         ctypes.byref(o)))
+
+
+# The per-word renderer (block bounds off) on windows where nearly every head
+# lies wholly outside, and one where most are inside: lanes whose words stay
+# outside keep changing their run keys without adding to the image.  Images
+# and dropped counts against the words' own coordinates, in both precisions.
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("win", [(0.1, 0.6, -0.2, 0.3, 40, 40), (0.9, 0.95, 0.3, 0.35, 64, 48),
+                                 (-4.0, 4.0, -4.0, 4.0, 128, 128)], ids=["zoom", "tiny", "wide"])
+def test_outside_heads_keep_images_and_dropped_counts(precision, win):
+    depth = 13
+    n = kl.num_words(depth)
+    d = torch.zeros(1, dtype=torch.int64, device="cuda")
+    img = kl.as_u32(kl.render(*C2, depth, win, precision=precision, dropped=d, tail_len=4)).astype(np.int64)
+    p = kl.eval_values(*C2, depth, torch.arange(n, dtype=torch.int64, device="cuda"), precision=precision,
+                       window=win, tail_len=4).cpu().numpy()
+    ref, drop = _bins_from_pixels(p[:, 0], p[:, 1], win)
+    np.testing.assert_array_equal(img, ref)
+    assert int(d.item()) == drop
+    assert int(img.sum()) + drop == n
