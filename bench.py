@@ -633,6 +633,22 @@ def leg_walk(args):
                     "occupied_pixels": {"indexed": int(oi.sum()), "walk": int(ow.sum())},
                     "occupancy_iou": round(iou(oi, ow), 4)})
     out["indexed_vs_walk"] = cmp
+    # the two histogram paths on every walk workload (the renders above take
+    # the planner's choice): one global atomic per point, and the binned path
+    # (points sorted by image tile in LDS, counted tile by tile); images equal
+    paths = []
+    for Wc in (W, wl.WALK_D13_POINTS, wl.WALK_LARGE):
+        row = {"walk": Wc.name, "points": Wc.points}
+        imgs = {}
+        for mode in ("runs", "lds"):
+            img = kl.new_image(win)
+            row[mode + "_ms"] = round(_time(lambda: kl.walk_render(ab, Wc.seed, 0, Wc.n_walkers, Wc.burn_in,
+                                                                   Wc.n_steps, win, image=img, hist_mode=mode),
+                                            steps, 3), 4)
+            imgs[mode] = img
+        row["images_equal"] = bool(torch.equal(imgs["runs"], imgs["lds"]))
+        paths.append(row)
+    out["histogram_paths"] = paths
     return out
 
 

@@ -342,8 +342,17 @@ int kl_walk_eval_ex(const kl_c64 *ab, const kl_walk *walk, const kl_window *wind
  * width * height uint32, cleared first unless accumulate) as every render
  * bins; dropped_out (if set) receives the points outside the window or not
  * finite.  image + dropped = n_walkers * n_steps.  opts: precision,
- * accumulate, stream, dropped_out.
- * Errors: as kl_walk_eval_ex. */
+ * accumulate, stream, dropped_out, hist_mode:
+ *   KL_HIST_RUNS  one global atomic add per point in the window;
+ *   KL_HIST_LDS   each workgroup's points of 16 steps sorted by image tile
+ *                 (2^15 bins) in LDS and staged in device temporaries
+ *                 (2 bytes a point, allocated on the stream), then counted
+ *                 tile by tile in LDS; images of at most 256 tiles
+ *                 (8,388,608 bins), at most 524,288 drawn points a walker;
+ *   KL_HIST_AUTO  KL_HIST_LDS from 2^18 points up where it applies, else
+ *                 KL_HIST_RUNS.
+ * Both give the same image and dropped count.
+ * Errors: as kl_walk_eval_ex; KL_EINVAL for KL_HIST_LDS beyond its limits. */
 int kl_walk_render_ex(const kl_c64 *ab, const kl_walk *walk, const kl_window *window, uint32_t *image_out,
                       const kl_opts *opts);
 

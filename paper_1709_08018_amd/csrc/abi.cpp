@@ -1201,6 +1201,11 @@ int kl_walk_render_ex(const kl_c64* ab, const kl_walk* walk, const kl_window* wi
     if ((rc = check_opts_common(o))) return rc;
     if ((rc = check_window(window))) return rc;
     if (!image_out) return fail(KL_EINVAL, "image_out is NULL");
+    if (o.hist_mode == KL_HIST_LDS && walk_tiles(window->width, window->height) > kMaxWalkTiles)
+        return fail(KL_EINVAL, "hist_mode KL_HIST_LDS takes images of at most %u x 32768 bins", kMaxWalkTiles);
+    if (o.hist_mode == KL_HIST_LDS && walk_region_points(walk->n_steps) > kWalkBinnedPoints)
+        return fail(KL_EINVAL, "hist_mode KL_HIST_LDS takes at most %llu drawn points per walker",
+                    (unsigned long long)(kWalkBinnedPoints / 256));
     Gens G;
     if ((rc = make_gens_ab(ab, &G))) return rc;
     hipStream_t s = (hipStream_t)o.stream;
@@ -1216,7 +1221,11 @@ int kl_walk_render_ex(const kl_c64* ab, const kl_walk* walk, const kl_window* wi
     j.W = window->width;
     j.H = window->height;
     j.dropped = o.dropped_out;
-    e = launch_walk(j, s);
+    e = o.hist_mode == KL_HIST_LDS || (o.hist_mode == KL_HIST_AUTO && np >= (1ull << 18) &&
+                                       walk_tiles(j.W, j.H) <= kMaxWalkTiles &&
+                                       walk_region_points(walk->n_steps) <= kWalkBinnedPoints)
+            ? launch_walk_binned(j, s)
+            : launch_walk(j, s);
     return e == hipSuccess ? KL_OK : hip_fail(e, "walk kernel");
 }
 

@@ -256,6 +256,14 @@ struct WalkJob {
     uint64_t* dropped;         // render: device u64 or null
 };
 hipError_t launch_walk(const WalkJob& j, hipStream_t s);
+// Binned walk render: points sorted by image tile of 2^15 bins, counted in
+// LDS; images of at most kMaxWalkTiles tiles, at most kWalkBinnedPoints
+// points staged per launch (walk_region_points(n_steps) per 256 walkers).
+constexpr uint32_t kMaxWalkTiles = 256;
+constexpr uint64_t kWalkBinnedPoints = 1ull << 27;
+uint32_t walk_tiles(uint32_t W, uint32_t H);
+uint64_t walk_region_points(uint32_t n_steps);
+hipError_t launch_walk_binned(const WalkJob& j, hipStream_t s);
 
 int device_cu_count();
 

@@ -25,8 +25,13 @@
 // maps read from LDS, rescaled by a power of two (exact) every eight steps;
 // each drawn point is u / v, folded into pixel coordinates and binned with
 // the renderer's rule (0 <= px < W, 0 <= py < H as IEEE comparisons, NaN and
-// infinity outside), one global atomic per point in the window: the points
-// of a walk jump across the limit set, so there are no runs to merge.
+// infinity outside).  The points of a walk jump across the limit set, so
+// there are no runs to merge, and a global atomic per point (walk_kernel)
+// costs a cache line per lane.  The binned path (walk_bin_kernel,
+// walk_tile_hist_kernel) instead sorts each workgroup's points of 16 steps
+// by image tile of 2^15 bins in LDS and writes them out as 16-bit offsets
+// within their tiles; a second kernel counts each tile's offsets in an LDS
+// histogram and adds its non-zero bins to the image.
 #include <hip/hip_runtime.h>
 
 #include "kl_internal.hpp"
@@ -100,76 +105,246 @@ __device__ __forceinline__ void walk_rescale(cpx<T>& u, cpx<T>& v) {
 template <typename T>
 __device__ __forceinline__ T walk_recip(T x) { return T(1) / x; }
 
+// The four maps and the seeds (u : v) in LDS, one entry per letter.
 template <typename T>
-__global__ __launch_bounds__(256) void walk_kernel(const WalkJob j) {
-    __shared__ mat<T> G[4];
-    __shared__ cpx<T> SU[4], SV[4];
+struct WalkMaps {
+    mat<T> G[4];
+    cpx<T> SU[4], SV[4];
+};
+
+template <typename T>
+__device__ __forceinline__ void load_walk_maps(const WalkJob& j, WalkMaps<T>& m) {
     if (threadIdx.x < 4) {
         const m64& g = j.gens.g[threadIdx.x];
-        G[threadIdx.x] = {{(T)g.a.re, (T)g.a.im}, {(T)g.b.re, (T)g.b.im}, {(T)g.c.re, (T)g.c.im},
-                          {(T)g.d.re, (T)g.d.im}};
+        m.G[threadIdx.x] = {{(T)g.a.re, (T)g.a.im}, {(T)g.b.re, (T)g.b.im}, {(T)g.c.re, (T)g.c.im},
+                            {(T)g.d.re, (T)g.d.im}};
         const bool inf = (j.gens.inf_mask >> threadIdx.x) & 1u;
-        SU[threadIdx.x] = inf ? cpx<T>{T(1), T(0)} : cpx<T>{(T)j.gens.fix[threadIdx.x].re, (T)j.gens.fix[threadIdx.x].im};
-        SV[threadIdx.x] = inf ? cpx<T>{T(0), T(0)} : cpx<T>{T(1), T(0)};
+        m.SU[threadIdx.x] = inf ? cpx<T>{T(1), T(0)} : cpx<T>{(T)j.gens.fix[threadIdx.x].re, (T)j.gens.fix[threadIdx.x].im};
+        m.SV[threadIdx.x] = inf ? cpx<T>{T(0), T(0)} : cpx<T>{T(1), T(0)};
     }
+}
+
+// The walk of one walker: letters c_0 .. c_{n_total - 1} (letter(k, c)),
+// and after each step k > burn_in its drawn point in the window's pixel
+// coordinates (point(d, px, py), d = k - burn_in - 1).  All walkers of a
+// launch take the same steps, so calls happen at the same k in every lane
+// (`active` lanes without a walker step along on walker 0's stream and
+// report nothing).
+template <typename T, typename Letter, typename Point>
+__device__ __forceinline__ void walk_walker(const WalkJob& j, const WalkMaps<T>& m, uint64_t walker, bool active,
+                                            Letter letter, Point point) {
+    const uint32_t n_total = 1 + j.burn_in + j.n_steps;
+    const T s = (T)j.fold.s, ox = (T)j.fold.o.re, oy = (T)j.fold.o.im, an = (T)j.fold.aniso;
+    cpx<T> u = {T(0), T(0)}, v = {T(1), T(0)};
+    int prev = 0;
+    uint32_t k = 0;
+    for (uint64_t blk = 0; k < n_total; ++blk) {
+        uint64_t r[4];
+        philox4x64_10(blk, walker, 0, 0, j.seed, 0, r);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            if (k < n_total) {
+                const uint32_t x = (uint32_t)(r[i >> 1] >> (32 * (i & 1)));
+                int c;
+                if (k == 0) {
+                    c = (int)(x >> 30);
+                    u = m.SU[c];
+                    v = m.SV[c];
+                } else {
+                    const int t = (int)__umulhi(x, 3u);
+                    c = t + (t >= (prev ^ 2));
+                    const mat<T> g = m.G[c];
+                    const cpx<T> nu = cfma(g.a, u, cmul(g.b, v));
+                    const cpx<T> nv = cfma(g.c, u, cmul(g.d, v));
+                    u = nu;
+                    v = nv;
+                }
+                if (active) letter(k, c);
+                if (k > j.burn_in) {
+                    // z = u / v, then the window's affine map s z + o (x anisotropy on the real part)
+                    const T n2 = fma_(v.re, v.re, v.im * v.im);
+                    const T rc = walk_recip(n2);
+                    const T zr = fma_(u.re, v.re, u.im * v.im) * rc;
+                    const T zi = fma_(u.im, v.re, -(u.re * v.im)) * rc;
+                    const T px = fma_(s, zr, ox) * an, py = fma_(s, zi, oy);
+                    point(k - j.burn_in - 1, px, py, active);
+                }
+                prev = c;
+                ++k;
+            }
+        }
+        walk_rescale(u, v);
+    }
+}
+
+// Letters, points or a render with one global atomic per point.
+template <typename T>
+__global__ __launch_bounds__(256) void walk_kernel(const WalkJob j) {
+    __shared__ WalkMaps<T> m;
+    load_walk_maps(j, m);
     __syncthreads();
     const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     uint64_t drop = 0;
     if (tid < j.n_walkers) {
-        const uint64_t walker = j.first_walker + tid;
         const uint32_t n_total = 1 + j.burn_in + j.n_steps;
-        const T s = (T)j.fold.s, ox = (T)j.fold.o.re, oy = (T)j.fold.o.im, an = (T)j.fold.aniso;
-        cpx<T> u = {T(0), T(0)}, v = {T(1), T(0)};
-        int prev = 0;
-        uint32_t k = 0;
-        for (uint64_t blk = 0; k < n_total; ++blk) {
-            uint64_t r[4];
-            philox4x64_10(blk, walker, 0, 0, j.seed, 0, r);
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                if (k < n_total) {
-                    const uint32_t x = (uint32_t)(r[i >> 1] >> (32 * (i & 1)));
-                    int c;
-                    if (k == 0) {
-                        c = (int)(x >> 30);
-                        u = SU[c];
-                        v = SV[c];
-                    } else {
-                        const int t = (int)__umulhi(x, 3u);
-                        c = t + (t >= (prev ^ 2));
-                        const mat<T> g = G[c];
-                        const cpx<T> nu = cfma(g.a, u, cmul(g.b, v));
-                        const cpx<T> nv = cfma(g.c, u, cmul(g.d, v));
-                        u = nu;
-                        v = nv;
-                    }
-                    if (j.mode == kWalkLetters) j.letters[tid * n_total + k] = (uint8_t)c;
-                    if (k > j.burn_in && j.mode != kWalkLetters) {
-                        // z = u / v, then the window's affine map s z + o (x anisotropy on the real part)
-                        const T n2 = fma_(v.re, v.re, v.im * v.im);
-                        const T rc = walk_recip(n2);
-                        const T zr = fma_(u.re, v.re, u.im * v.im) * rc;
-                        const T zi = fma_(u.im, v.re, -(u.re * v.im)) * rc;
-                        const T px = fma_(s, zr, ox) * an, py = fma_(s, zi, oy);
-                        const uint64_t p = tid * j.n_steps + (k - j.burn_in - 1);
-                        if (j.mode == kWalkEval) {
-                            j.z_out[p] = {(double)px, (double)py};
-                        } else {
-                            const uint32_t b = walk_bin(px, py, j.W, j.H);
-                            if (b != kWalkOutside) atomicAdd(j.image + b, 1u);
-                            else ++drop;
-                        }
-                    }
-                    prev = c;
-                    ++k;
-                }
-            }
-            walk_rescale(u, v);
-        }
+        walk_walker<T>(j, m, j.first_walker + tid, true,
+                       [&](uint32_t k, int c) {
+                           if (j.mode == kWalkLetters) j.letters[tid * n_total + k] = (uint8_t)c;
+                       },
+                       [&](uint32_t d, T px, T py, bool) {
+                           const uint64_t p = tid * j.n_steps + d;
+                           if (j.mode == kWalkEval) {
+                               j.z_out[p] = {(double)px, (double)py};
+                           } else if (j.mode == kWalkRender) {
+                               const uint32_t b = walk_bin(px, py, j.W, j.H);
+                               if (b != kWalkOutside) atomicAdd(j.image + b, 1u);
+                               else ++drop;
+                           }
+                       });
     }
     if (j.mode == kWalkRender && j.dropped) {
         for (int off = 32; off > 0; off >>= 1) drop += __shfl_down(drop, off, 64);
         if ((threadIdx.x & 63) == 0 && drop) atomicAdd((unsigned long long*)j.dropped, (unsigned long long)drop);
+    }
+}
+
+// ---- binned render
+constexpr uint32_t kWalkTileBits = 15;                    // a tile: 2^15 bins
+constexpr uint32_t kWalkTileBins = 1u << kWalkTileBits;
+constexpr uint32_t kWalkChunk = 16;                       // drawn steps per region
+constexpr uint32_t kWalkRegion = 256 * kWalkChunk;        // points of a region at most
+constexpr uint32_t kNoKey = 0xFFFFFFFFu;
+
+// One region per (workgroup, chunk of kWalkChunk drawn steps): its points
+// in the window as offsets within their tiles, tile by tile (ids, kWalkRegion
+// slots a region), and where each tile's offsets start (starts, T + 1
+// entries a region: starts[T] is the region's count).
+template <typename T>
+__global__ __launch_bounds__(256) void walk_bin_kernel(const WalkJob j, uint16_t* __restrict__ ids,
+                                                       uint32_t* __restrict__ starts, uint32_t T_tiles,
+                                                       uint32_t n_chunks) {
+    __shared__ WalkMaps<T> m;
+    __shared__ uint32_t keys[kWalkRegion];
+    __shared__ uint16_t sorted[kWalkRegion];
+    __shared__ uint32_t cnt[kMaxWalkTiles + 1], cur[kMaxWalkTiles];
+    load_walk_maps(j, m);
+    for (uint32_t t = threadIdx.x; t <= kMaxWalkTiles; t += blockDim.x) cnt[t] = 0;
+    __syncthreads();
+    const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool active = tid < j.n_walkers;
+    const uint32_t lane_slot = threadIdx.x * kWalkChunk;
+    uint64_t drop = 0;
+    walk_walker<T>(j, m, j.first_walker + (active ? tid : 0), active, [](uint32_t, int) {},
+                   [&](uint32_t d, T px, T py, bool act) {
+                       const uint32_t slot = d % kWalkChunk;
+                       const uint32_t b = walk_bin(px, py, j.W, j.H);
+                       uint32_t key = kNoKey;
+                       if (act) {
+                           if (b != kWalkOutside) key = b;
+                           else ++drop;
+                       }
+                       keys[lane_slot + slot] = key;
+                       if (key != kNoKey) atomicAdd(&cnt[key >> kWalkTileBits], 1u);
+                       // the chunk is full, or the walk ends: sort it into its region
+                       if (slot == kWalkChunk - 1 || d == j.n_steps - 1) {
+                           const uint32_t nk = slot + 1;
+                           __syncthreads();
+                           if (threadIdx.x < 64) {
+                               // exclusive scan of cnt[0 .. T) by one wave, into cnt, with cnt[T] the total
+                               uint32_t carry = 0;
+                               for (uint32_t base = 0; base < T_tiles; base += 64) {
+                                   const uint32_t t = base + threadIdx.x;
+                                   const uint32_t c = t < T_tiles ? cnt[t] : 0u;
+                                   uint32_t x = c;
+                                   for (int off = 1; off < 64; off <<= 1) {
+                                       const uint32_t y = __shfl_up(x, off, 64);
+                                       if ((int)threadIdx.x >= off) x += y;
+                                   }
+                                   if (t < T_tiles) {
+                                       cnt[t] = carry + x - c;
+                                       cur[t] = carry + x - c;
+                                   }
+                                   carry += __shfl(x, 63, 64);
+                               }
+                               if (threadIdx.x == 0) cnt[T_tiles] = carry;
+                           }
+                           __syncthreads();
+                           for (uint32_t q = 0; q < nk; ++q) {
+                               const uint32_t kq = keys[lane_slot + q];
+                               if (kq != kNoKey)
+                                   sorted[atomicAdd(&cur[kq >> kWalkTileBits], 1u)] = (uint16_t)(kq & (kWalkTileBins - 1));
+                           }
+                           __syncthreads();
+                           const uint64_t region = (uint64_t)blockIdx.x * n_chunks + d / kWalkChunk;
+                           const uint32_t n_in = cnt[T_tiles];
+                           uint16_t* out = ids + region * kWalkRegion;
+                           for (uint32_t i = threadIdx.x; i < n_in; i += blockDim.x) out[i] = sorted[i];
+                           uint32_t* st = starts + region * (T_tiles + 1);
+                           for (uint32_t t = threadIdx.x; t <= T_tiles; t += blockDim.x) st[t] = cnt[t];
+                           __syncthreads();
+                           for (uint32_t t = threadIdx.x; t <= T_tiles; t += blockDim.x) cnt[t] = 0;
+                           __syncthreads();
+                       }
+                   });
+    if (j.dropped) {
+        for (int off = 32; off > 0; off >>= 1) drop += __shfl_down(drop, off, 64);
+        if ((threadIdx.x & 63) == 0 && drop) atomicAdd((unsigned long long*)j.dropped, (unsigned long long)drop);
+    }
+}
+
+// Tile blockIdx.x / split over its share of the regions: every offset
+// counted in an LDS histogram, then each non-zero bin added to the image.
+__global__ __launch_bounds__(1024) void walk_tile_hist_kernel(const uint16_t* __restrict__ ids,
+                                                              const uint32_t* __restrict__ starts,
+                                                              uint64_t n_regions, uint32_t T_tiles, uint32_t split,
+                                                              uint32_t* __restrict__ image) {
+    __shared__ uint32_t hist[kWalkTileBins];
+    const uint32_t tile = blockIdx.x / split, part = blockIdx.x % split;
+    for (uint32_t i = threadIdx.x; i < kWalkTileBins; i += blockDim.x) hist[i] = 0;
+    __syncthreads();
+    const uint64_t r0 = n_regions * part / split, r1 = n_regions * (part + 1) / split;
+    const uint32_t wave = threadIdx.x / 64, lane = threadIdx.x % 64, waves = blockDim.x / 64;
+    // a wave takes its slice of the regions 64 at a time: each lane fetches
+    // one region's segment bounds, then the wave loads four regions' first 64
+    // offsets before counting them, so those loads overlap; longer segments
+    // go on
+    const uint64_t per = (r1 - r0 + waves - 1) / waves;
+    const uint64_t w0 = r0 + wave * per, w1 = w0 + per < r1 ? w0 + per : r1;
+    for (uint64_t base = w0; base < w1; base += 64) {
+        const uint64_t rl = base + lane;
+        uint32_t a = 0, b = 0;
+        if (rl < w1) {
+            const uint32_t* st = starts + rl * (T_tiles + 1);
+            a = st[tile];
+            b = st[tile + 1];
+        }
+        const uint32_t nb = w1 - base < 64 ? (uint32_t)(w1 - base) : 64u;
+        for (uint32_t j = 0; j < nb; j += 4) {
+            uint32_t v[4], aj[4], bj[4];
+            bool ok[4];
+#pragma unroll
+            for (uint32_t q = 0; q < 4; ++q) {
+                aj[q] = __shfl(a, (int)(j + q), 64);
+                bj[q] = __shfl(b, (int)(j + q), 64);   // 0, 0 past the regions
+                const uint32_t i = aj[q] + lane;
+                ok[q] = i < bj[q];
+                v[q] = ok[q] ? ids[(base + j + q) * kWalkRegion + i] : 0u;
+            }
+#pragma unroll
+            for (uint32_t q = 0; q < 4; ++q)
+                if (ok[q]) atomicAdd(&hist[v[q]], 1u);
+#pragma unroll
+            for (uint32_t q = 0; q < 4; ++q) {
+                const uint16_t* in = ids + (base + j + q) * kWalkRegion;
+                for (uint32_t i = aj[q] + 64 + lane; i < bj[q]; i += 64) atomicAdd(&hist[in[i]], 1u);
+            }
+        }
+    }
+    __syncthreads();
+    uint32_t* img = image + (uint64_t)tile * kWalkTileBins;
+    for (uint32_t i = threadIdx.x; i < kWalkTileBins; i += blockDim.x) {
+        const uint32_t v = hist[i];
+        if (v) atomicAdd(img + i, v);
     }
 }
 
@@ -195,6 +370,64 @@ hipError_t launch_walk(const WalkJob& j, hipStream_t s) {
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+uint32_t walk_tiles(uint32_t W, uint32_t H) {
+    const uint64_t bins = (uint64_t)W * H;
+    return (uint32_t)((bins + kWalkTileBins - 1) / kWalkTileBins);
+}
+
+uint64_t walk_region_points(uint32_t n_steps) {
+    return 256ull * kWalkChunk * ((n_steps + kWalkChunk - 1) / kWalkChunk);
+}
+
+// The binned render: walkers in launches whose regions hold at most
+// kWalkBinnedPoints points, each launch binning its walkers' points
+// (walk_bin_kernel) and then counting them tile by tile
+// (walk_tile_hist_kernel), in temporaries allocated on the stream.
+hipError_t launch_walk_binned(const WalkJob& j, hipStream_t s) {
+    if (j.n_walkers == 0 || j.n_steps == 0) return hipSuccess;
+    const uint32_t T_tiles = walk_tiles(j.W, j.H);
+    const uint32_t n_chunks = (j.n_steps + kWalkChunk - 1) / kWalkChunk;
+    const uint64_t block_points = walk_region_points(j.n_steps);   // one block of 256 walkers
+    uint64_t blocks_per = kWalkBinnedPoints / block_points;
+    if (blocks_per == 0) return hipErrorInvalidValue;
+    const uint64_t total_blocks = (j.n_walkers + 255) / 256;
+    if (blocks_per > total_blocks) blocks_per = total_blocks;
+    uint16_t* ids = nullptr;
+    uint32_t* starts = nullptr;
+    const uint64_t regions_per = blocks_per * n_chunks;
+    hipError_t e = hipMallocAsync((void**)&ids, regions_per * kWalkRegion * sizeof(uint16_t), s);
+    if (e != hipSuccess) return e;
+    e = hipMallocAsync((void**)&starts, regions_per * (T_tiles + 1) * sizeof(uint32_t), s);
+    if (e != hipSuccess) {
+        (void)hipFreeAsync(ids, s);
+        return e;
+    }
+    int cus = device_cu_count();
+    for (uint64_t b0 = 0; b0 < total_blocks && e == hipSuccess; b0 += blocks_per) {
+        const uint64_t nb = total_blocks - b0 < blocks_per ? total_blocks - b0 : blocks_per;
+        WalkJob c = j;
+        c.first_walker = j.first_walker + b0 * 256;
+        c.n_walkers = j.n_walkers - b0 * 256 < nb * 256 ? j.n_walkers - b0 * 256 : nb * 256;
+        if (j.precision == KL_PREC_FP64)
+            hipLaunchKernelGGL(walk_bin_kernel<double>, dim3((unsigned)nb), dim3(256), 0, s, c, ids, starts, T_tiles,
+                               n_chunks);
+        else
+            hipLaunchKernelGGL(walk_bin_kernel<float>, dim3((unsigned)nb), dim3(256), 0, s, c, ids, starts, T_tiles,
+                               n_chunks);
+        if ((e = hipGetLastError()) != hipSuccess) break;
+        const uint64_t n_regions = nb * n_chunks;
+        // enough workgroups to fill the GPU twice over, each tile split evenly
+        uint64_t split = (2ull * (uint64_t)cus + T_tiles - 1) / T_tiles;
+        if (split > n_regions) split = n_regions;
+        if (split < 1) split = 1;
+        hipLaunchKernelGGL(walk_tile_hist_kernel, dim3((unsigned)(T_tiles * split)), dim3(1024), 0, s, ids, starts,
+                           n_regions, T_tiles, (uint32_t)split, j.image);
+        e = hipGetLastError();
+    }
+    const hipError_t f1 = hipFreeAsync(ids, s), f2 = hipFreeAsync(starts, s);
+    return e != hipSuccess ? e : f1 != hipSuccess ? f1 : f2;
 }
 
 }  // namespace kl

@@ -271,6 +271,13 @@ def test_walk_argument_errors():
     assert L.kl_walk_eval_ex(ab, ctypes.byref(w), None, None, None) == kl.KL_EINVAL
     zero = (kl.c64 * 8)(*[kl.c64(0, 0)] * 8)
     assert L.kl_walk_eval_ex(zero, ctypes.byref(w), None, FAKE, None) == kl.KL_ESINGULAR
+    # the binned render (KL_HIST_LDS): images of at most 256 tiles of 2^15
+    # bins, at most 2^19 drawn points a walker; refused before anything runs
+    lds = kl.make_opts(hist_mode="lds", use_stream=False)
+    big = _win(w=4096, h=2056)      # 257 tiles
+    assert L.kl_walk_render_ex(ab, ctypes.byref(w), ctypes.byref(big), FAKE, ctypes.byref(lds)) == kl.KL_EINVAL
+    long_walk = kl.make_walk(0, 0, 1, 0, 2 ** 19 + 1)
+    assert L.kl_walk_render_ex(ab, ctypes.byref(long_walk), ctypes.byref(good), FAKE, ctypes.byref(lds)) == kl.KL_EINVAL
 
 
 def test_strerror_names_every_code():

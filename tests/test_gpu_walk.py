@@ -136,3 +136,62 @@ def test_walker_ranges_accumulate_and_edge_cases():
     with pytest.raises(kl.KLError) as e:
         kl.walk_render(ab, 4, 2 ** 64 - 5, 10, 0, steps, WIN_M)
     assert e.value.code == kl.KL_ERANGE
+
+
+def _render_both(ab, seed, first, n, burn, steps, win, precision, accumulate_into=None):
+    """(image, dropped) of the binned path and of the one-atomic-per-point path."""
+    out = []
+    for mode in ("lds", "runs"):
+        dropped = torch.zeros(1, dtype=torch.int64, device="cuda")
+        img = kl.walk_render(ab, seed, first, n, burn, steps, win, precision=precision, dropped=dropped,
+                             hist_mode=mode)
+        out.append((kl.as_u32(img).astype(np.int64), int(dropped.item())))
+    return out
+
+
+# Binned render (points sorted by image tile of 2^15 bins in LDS, counted
+# tile by tile) against the direct one: ragged walker blocks, walks whose
+# drawn steps are not a multiple of the 16-step chunk, burn-in, one tile and
+# many, both precisions.
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("n,burn,steps,win", [
+    (1, 0, 1, WIN_M), (255, 3, 17, WIN_M), (256, 0, 16, WIN_M), (4097, 5, 64, WIN_M),
+    (3000, 0, 33, (-1.05, 1.05, -0.1, 2.0, 100, 100)), (513, 2, 40, (-1.05, 1.05, -0.1, 2.0, 182, 181)),
+    (20000, 0, 100, WIN_M),
+], ids=["one", "ragged", "block", "tiles", "one_tile", "edge_tile", "long"])
+def test_binned_render_equals_direct(precision, n, burn, steps, win):
+    ab, _ = _maskit()
+    (a, da), (b, db) = _render_both(ab, 7, 11, n, burn, steps, win, precision)
+    np.testing.assert_array_equal(a, b)
+    assert da == db
+    assert int(a.sum()) + da == n * steps
+
+
+def test_binned_render_matches_own_points_and_accumulates():
+    ab, _ = _recipe()
+    seed, n, burn, steps = 8, 5001, 2, 77
+    dropped = torch.zeros(1, dtype=torch.int64, device="cuda")
+    img = kl.as_u32(kl.walk_render(ab, seed, 0, n, burn, steps, WIN_C2, dropped=dropped,
+                                   hist_mode="lds")).astype(np.int64)
+    p = kl.walk_eval(ab, seed, 0, n, burn, steps, window=WIN_C2).cpu().numpy()
+    ref, drop = _own_bins(p, WIN_C2)
+    np.testing.assert_array_equal(img, ref)
+    assert int(dropped.item()) == drop
+    acc = kl.new_image(WIN_C2)
+    for a, b in [(0, 300), (300, 4000), (4000, 5001)]:
+        kl.walk_render(ab, seed, a, b - a, burn, steps, WIN_C2, image=acc, accumulate=True, hist_mode="lds")
+    np.testing.assert_array_equal(kl.as_u32(acc).astype(np.int64), img)
+
+
+def test_binned_render_limits():
+    ab, _ = _maskit()
+    # 257 tiles of 2^15 bins: the binned path is refused, the direct one renders
+    big = (-1.05, 1.05, -0.1, 2.0, 4096, 2056)
+    with pytest.raises(kl.KLError) as e:
+        kl.walk_render(ab, 1, 0, 10, 0, 4, big, hist_mode="lds")
+    assert e.value.code == kl.KL_EINVAL
+    img = kl.walk_render(ab, 1, 0, 10, 0, 4, big, hist_mode="auto")
+    assert int(kl.as_u32(img).astype(np.int64).sum()) <= 40
+    # no points: an empty image either way
+    assert int(kl.walk_render(ab, 1, 0, 0, 0, 4, WIN_M, hist_mode="lds").abs().sum()) == 0
+    assert int(kl.walk_render(ab, 1, 0, 10, 3, 0, WIN_M, hist_mode="lds").abs().sum()) == 0
