@@ -102,8 +102,18 @@ __device__ __forceinline__ void walk_rescale(cpx<T>& u, cpx<T>& v) {
     }
 }
 
-template <typename T>
-__device__ __forceinline__ T walk_recip(T x) { return T(1) / x; }
+// 1 / x as the renderer takes it: v_rcp_f32 in FP32 (within an ulp), and in
+// FP64 v_rcp_f64 refined by two Newton steps r <- r + r (1 - x r), a
+// full-precision reciprocal.  x = 0 (a point at infinity) gives infinity or
+// NaN, and the point is dropped.
+__device__ __forceinline__ float walk_recip(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double walk_recip(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma_(-x, r, 1.0);
+    r = fma_(r, e, r);
+    e = fma_(-x, r, 1.0);
+    return fma_(r, e, r);
+}
 
 // The four maps and the seeds (u : v) in LDS, one entry per letter.
 template <typename T>
@@ -292,6 +302,8 @@ __global__ __launch_bounds__(256) void walk_bin_kernel(const WalkJob j, uint16_t
     }
 }
 
+constexpr uint32_t kHistBatch = 16;   // regions whose offsets a wave loads before counting them
+
 // Tile blockIdx.x / split over its share of the regions: every offset
 // counted in an LDS histogram, then each non-zero bin added to the image.
 __global__ __launch_bounds__(1024) void walk_tile_hist_kernel(const uint16_t* __restrict__ ids,
@@ -305,9 +317,9 @@ __global__ __launch_bounds__(1024) void walk_tile_hist_kernel(const uint16_t* __
     const uint64_t r0 = n_regions * part / split, r1 = n_regions * (part + 1) / split;
     const uint32_t wave = threadIdx.x / 64, lane = threadIdx.x % 64, waves = blockDim.x / 64;
     // a wave takes its slice of the regions 64 at a time: each lane fetches
-    // one region's segment bounds, then the wave loads four regions' first 64
-    // offsets before counting them, so those loads overlap; longer segments
-    // go on
+    // one region's segment bounds, then the wave loads kHistBatch regions'
+    // first 64 offsets before counting them, so those loads overlap; longer
+    // segments go on
     const uint64_t per = (r1 - r0 + waves - 1) / waves;
     const uint64_t w0 = r0 + wave * per, w1 = w0 + per < r1 ? w0 + per : r1;
     for (uint64_t base = w0; base < w1; base += 64) {
@@ -319,11 +331,11 @@ __global__ __launch_bounds__(1024) void walk_tile_hist_kernel(const uint16_t* __
             b = st[tile + 1];
         }
         const uint32_t nb = w1 - base < 64 ? (uint32_t)(w1 - base) : 64u;
-        for (uint32_t j = 0; j < nb; j += 4) {
-            uint32_t v[4], aj[4], bj[4];
-            bool ok[4];
+        for (uint32_t j = 0; j < nb; j += kHistBatch) {
+            uint32_t v[kHistBatch], aj[kHistBatch], bj[kHistBatch];
+            bool ok[kHistBatch];
 #pragma unroll
-            for (uint32_t q = 0; q < 4; ++q) {
+            for (uint32_t q = 0; q < kHistBatch; ++q) {
                 aj[q] = __shfl(a, (int)(j + q), 64);
                 bj[q] = __shfl(b, (int)(j + q), 64);   // 0, 0 past the regions
                 const uint32_t i = aj[q] + lane;
@@ -331,10 +343,10 @@ __global__ __launch_bounds__(1024) void walk_tile_hist_kernel(const uint16_t* __
                 v[q] = ok[q] ? ids[(base + j + q) * kWalkRegion + i] : 0u;
             }
 #pragma unroll
-            for (uint32_t q = 0; q < 4; ++q)
+            for (uint32_t q = 0; q < kHistBatch; ++q)
                 if (ok[q]) atomicAdd(&hist[v[q]], 1u);
 #pragma unroll
-            for (uint32_t q = 0; q < 4; ++q) {
+            for (uint32_t q = 0; q < kHistBatch; ++q) {
                 const uint16_t* in = ids + (base + j + q) * kWalkRegion;
                 for (uint32_t i = aj[q] + 64 + lane; i < bj[q]; i += 64) atomicAdd(&hist[in[i]], 1u);
             }
