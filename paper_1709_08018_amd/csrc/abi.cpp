@@ -212,9 +212,17 @@ static Fold make_fold(const kl_window* w, int head_form) {
 }
 
 // ------------------------------------------------------------------ devices
+// Table buffer that single-set calls on a device's null stream reuse (Temp::tables).
+struct TableCache {
+    void* base = nullptr;
+    size_t bytes = 0;
+    bool busy = false;   // leased to a call that is still enqueuing its kernels
+};
+
 struct DeviceInfo {
     int cus = 0;
     void* scratch = nullptr;   // device address of this device's copy of `scratch` (kl_render_noalloc)
+    TableCache tables;
     char arch[32] = {0};       // architecture name up to its first ':' (tuned-plan keys)
 };
 constexpr int kMaxDevices = 64;
@@ -305,9 +313,24 @@ int plan_split(int depth, int precision, int r_req, int m_req, Split* sp, int pr
 }
 
 // ------------------------------------------------------------------ temporaries
+// Largest table set that the per-device table cache holds.
+constexpr size_t kTableCacheMax = size_t(64) << 20;
+
+// Stream-ordered temporaries of one call, freed on its stream when the call
+// returns.  tables() lends the call its device's cached table buffer instead
+// when the call runs on the null stream: every user of that buffer enqueues
+// on the null stream, which lives as long as the process, so the set-up
+// kernel that rewrites the tables runs after every kernel that read them
+// before, and the steady state of repeated renders enqueues no allocation
+// (a hipMallocAsync / hipFreeAsync pair costs the GPU some 3 us of idle
+// time per call).  The lease ends with the call, once its kernels are
+// enqueued; a call that finds the buffer leased to another thread, or that
+// runs on another stream, or that needs more than kTableCacheMax bytes,
+// takes a temporary.
 struct Temp {
     hipStream_t s;
     std::vector<void*> ptrs;
+    int lease = -1;   // device whose table cache this call holds
     explicit Temp(hipStream_t st) : s(st) {}
     hipError_t alloc(void** p, size_t bytes) {
         *p = nullptr;
@@ -316,8 +339,37 @@ struct Temp {
         if (e == hipSuccess) ptrs.push_back(*p);
         return e;
     }
+    hipError_t tables(void** p, size_t bytes) {
+        int dev = -1;
+        if (s == nullptr && lease < 0 && bytes <= kTableCacheMax && hipGetDevice(&dev) == hipSuccess && dev >= 0 &&
+            dev < kMaxDevices) {
+            std::lock_guard<std::mutex> lk(g_dev_mutex);
+            TableCache& c = g_devs[dev].tables;
+            if (!c.busy) {
+                if (c.bytes < bytes) {
+                    if (c.base) (void)hipFreeAsync(c.base, s);
+                    c.base = nullptr;
+                    c.bytes = 0;
+                    const size_t want = std::max(bytes, size_t(1) << 20);
+                    if (hipMallocAsync(&c.base, want, s) == hipSuccess) c.bytes = want;
+                    else c.base = nullptr;
+                }
+                if (c.base) {
+                    c.busy = true;
+                    lease = dev;
+                    *p = c.base;
+                    return hipSuccess;
+                }
+            }
+        }
+        return alloc(p, bytes);
+    }
     ~Temp() {
         for (void* p : ptrs) (void)hipFreeAsync(p, s);
+        if (lease >= 0) {
+            std::lock_guard<std::mutex> lk(g_dev_mutex);
+            g_devs[lease].tables.busy = false;
+        }
     }
 };
 
@@ -371,7 +423,7 @@ static int build_tables(const Gens& G, const Split& sp, int precision, int force
         if (L.total > buf->bytes)
             return fail(KL_ENOMEM, "tables of %zu bytes exceed the %zu-byte scratch array", L.total, buf->bytes);
         base = buf->base;
-    } else if ((e = tmp.alloc((void**)&base, L.total)) != hipSuccess) {
+    } else if ((e = tmp.tables((void**)&base, L.total)) != hipSuccess) {
         return hip_fail(e, "tables");
     }
     SetupJob j{};

@@ -323,6 +323,33 @@ def test_run_to_run_bit_equality():
     assert torch.equal(a, b)
 
 
+def test_table_buffer_reuse_across_calls_and_streams():
+    """Renders on the null stream reuse one table buffer per device, which
+    grows when a call needs more; renders on other streams take temporaries.
+    Calls enqueued back to back, without synchronising, in an order that
+    grows the buffer and shrinks the tables again and mixes in a side stream,
+    give the images that each call gives alone."""
+    cases = [(C2, 12, WIN_C2, "fp32"), (C2, 18, WIN_C2, "fp32"), (C1, 10, WIN_C1, "fp64"),
+             (C2, 19, WIN_C2, "fp64"), (C2, 14, WIN_C2, "fp32")]
+    alone = []
+    for g, d, w, p in cases:
+        alone.append(kl.render(*g, d, w, precision=p))
+        torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    out = []
+    for i, (g, d, w, p) in enumerate(cases):
+        if i == 2:
+            side.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(side):
+                out.append(kl.render(*g, d, w, precision=p))
+            torch.cuda.current_stream().wait_stream(side)
+        else:
+            out.append(kl.render(*g, d, w, precision=p))
+    torch.cuda.synchronize()
+    for (g, d, w, p), a, b in zip(cases, alone, out):
+        assert torch.equal(a, b), (d, p)
+
+
 @pytest.mark.parametrize("depth", [1, 2, 3, 4, 5])
 def test_shallow_depths(depth):
     win = (-2.0, 2.0, -2.0, 2.0, 64, 64)
