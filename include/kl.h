@@ -45,7 +45,11 @@
  *           are DEVICE pointers (memory of the current HIP device); all
  *           others are host pointers.  The caller owns every buffer; the
  *           library never frees caller memory.  The library allocates its
- *           own temporaries with hipMallocAsync on the call's stream.
+ *           own temporaries with hipMallocAsync on the call's stream; calls
+ *           on the null stream keep their prefix and suffix tables in one
+ *           buffer per device instead (1 MiB growing to at most 64 MiB,
+ *           held until the process ends), which calls on other streams,
+ *           or on another host thread while one holds it, do not touch.
  * streams   the plain entry points run on the null stream and return after
  *           the device has finished; the *_ex entry points enqueue on
  *           opts->stream (a hipStream_t, NULL = null stream) and return at
@@ -208,7 +212,7 @@ int kl_render_ex(kl_c64 ta, kl_c64 tb, int depth, const kl_window *window,
  * hipMalloc).  Same arguments, options and result as kl_render_ex for a
  * render of one depth: image_out (and opts->dropped_out) as there, bit for
  * bit the same image.  It allocates nothing: the prefix and suffix tables
- * that kl_render_ex puts in a hipMallocAsync temporary go to a
+ * that kl_render_ex puts in a library buffer or temporary go to a
  * library-owned device array of KL_NOALLOC_SCRATCH_BYTES, one per device,
  * held until the process ends, whose address is taken once per device on
  * its first call.  Every call on a device shares that device's array and
