@@ -351,8 +351,14 @@ struct Temp {
                     c.base = nullptr;
                     c.bytes = 0;
                     const size_t want = std::max(bytes, size_t(1) << 20);
-                    if (hipMallocAsync(&c.base, want, s) == hipSuccess) c.bytes = want;
-                    else c.base = nullptr;
+                    if (hipMallocAsync(&c.base, want, s) == hipSuccess) {
+                        c.bytes = want;
+                    } else {
+                        // a temporary of the exact size may still fit; clear the
+                        // error so that the next launch check does not report it
+                        c.base = nullptr;
+                        (void)hipGetLastError();
+                    }
                 }
                 if (c.base) {
                     c.busy = true;
