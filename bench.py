@@ -192,6 +192,44 @@ def cpu_baseline_cayley_modular(table, maps, win, words, img):
             "l1_vs_oracle": int(np.abs(img - rimg.astype(np.int64)).sum()), "oracle_near_edge_words": int(near)}
 
 
+def cpu_baseline_batch(ta, tb, depth, win, imgs, every=16):
+    """The oracle's renders of every `every`-th set of the batch, timed on
+    the process's CPU share, and the batched FP32 images of those sets
+    against them (L1 within twice the words the oracle places within
+    1e-3 px of a bin edge)."""
+    import numpy as np
+    ref = _oracle()
+    threads = min(len(os.sched_getaffinity(0)), CPU_SHARE)
+    sets = list(range(0, len(ta), every))
+    win = win.as_tuple()
+    words, l1, near, dt = 0, 0, 0, 0.0
+    for i in sets:
+        t0 = time.perf_counter()
+        rimg, _, nr = ref.render(complex(ta[i]), complex(tb[i]), int(depth[i]), win, edge_tol=1e-3, nthreads=threads)
+        dt += time.perf_counter() - t0
+        words += ref.num_words(int(depth[i]))
+        l1 += int(np.abs(imgs[i].astype(np.int64) - rimg.astype(np.int64)).sum())
+        near += int(nr)
+    return {"kind": "oracle", "value": round(words / dt / 1e9, 4), "unit": "Gwords/s", "cores": threads,
+            "sample": f"sets {sets[0]}, {sets[1]}, ... every {every}th of the batch ({len(sets)} sets, {words} words), "
+                      f"FP64 depth-first walk, {dt:.2f} s",
+            "l1_vs_oracle": l1, "oracle_near_edge_words": near, "within_bar": l1 <= 2 * near}
+
+
+def cpu_baseline_tiling(W, words, img):
+    """The oracle's render of the whole tiling, timed, and the GPU's FP64
+    image against it."""
+    import numpy as np
+    ref = _oracle()
+    threads = min(len(os.sched_getaffinity(0)), CPU_SHARE)
+    t0 = time.perf_counter()
+    rimg, _, near = ref.render(W.ta, W.tb, W.depth, W.window.as_tuple(), min_depth=1, edge_tol=1e-7, nthreads=threads)
+    dt = time.perf_counter() - t0
+    return {"kind": "oracle", "value": round(words / dt / 1e9, 4), "unit": "Gwords/s", "cores": threads,
+            "sample": "the full workload", "seconds": round(dt, 3),
+            "fp64_l1_vs_oracle": int(np.abs(img - rimg.astype(np.int64)).sum()), "oracle_near_edge_words": int(near)}
+
+
 def cpu_baseline_decode(first, depth, rows, got):
     """The oracle's unranking of the sampled rows, timed, against the kernel's."""
     import numpy as np
@@ -439,6 +477,9 @@ def leg_batch(args):
     tune1_s = time.perf_counter() - t0
     ms_s_single = _time(separate, reps, 1)
     ms_b = min(ms_b_default, ms_b_tuned)
+    batched()
+    torch.cuda.synchronize()
+    cpu = cpu_baseline_batch(ta, tb, depth, win, kl.as_u32(imgs)) if not args.no_cpu_baseline else None
     return {"workload": "batch256", "sets": len(ta), "words": words,
             "batched_ms": round(ms_b, 3), "separate_ms": round(ms_s_default, 3),
             "speedup": round(ms_s_default / ms_b, 3), "batched_gwords_per_s": round(words / ms_b / 1e6, 2),
@@ -449,7 +490,8 @@ def leg_batch(args):
                                   "images_identical": same_tuned, "tune_seconds": round(tune_s, 2),
                                   "plans": by_depth},
             "single_tuned_plans": {"separate_ms": round(ms_s_single, 3), "tune_seconds": round(tune1_s, 2)},
-            "note": "speedup: the faster batched launch against 256 plain renders with the planner's plans"}
+            "note": "speedup: the faster batched launch against 256 plain renders with the planner's plans",
+            "cpu_baseline": cpu}
 
 
 def leg_tiling(args):
@@ -465,6 +507,9 @@ def leg_tiling(args):
         ms = _time(lambda: kl.render(W.ta, W.tb, W.depth, W.window, image=image, min_depth=1, precision=prec),
                    args.steps, args.warmup)
         out[prec] = {"ms": round(ms, 4), "gwords_per_s": round(words / ms / 1e6, 3)}
+    if not args.no_cpu_baseline:
+        kl.render(W.ta, W.tb, W.depth, W.window, image=image, min_depth=1, precision="fp64")
+        out["cpu_baseline"] = cpu_baseline_tiling(W, words, kl.as_u32(image).astype("int64"))
     return out
 
 

@@ -1,6 +1,7 @@
 """Host logic of bench.py: the HBM traffic figure is read from the committed
 counter summary only when that summary was taken on the current kernel
-source and split."""
+source and split; the oracle baselines of the tiling and batch legs compare
+what they are given with the oracle's own images."""
 import hashlib
 
 import bench
@@ -71,3 +72,43 @@ def test_issue_fraction_read_from_the_counter_summary(tmp_path, monkeypatch):
                  "per dispatch): 0.977 (median of 684; min 0.926, max 1.005)\n")
     monkeypatch.setattr(bench, "VALU_SUMMARY", str(p))
     assert bench._profile_value(bench.VALU_SUMMARY, "VALU issue fraction", SPLIT) == 0.977
+
+
+def test_tiling_baseline_compares_the_image_with_the_oracle():
+    """The tiling leg's oracle baseline: L1 0 for the oracle's own FP64
+    image, and every count for an empty image."""
+    import numpy as np
+
+    from oracle import oracle as O
+    from paper_1709_08018_amd import workloads as wl
+
+    W = wl.FUCHSIAN_TILING_D10
+    own, _, _ = O.render(W.ta, W.tb, W.depth, W.window.as_tuple(), min_depth=1)
+    words = sum(O.num_words(d) for d in range(1, W.depth + 1))
+    r = bench.cpu_baseline_tiling(W, words, own.astype(np.int64))
+    assert r["fp64_l1_vs_oracle"] == 0 and r["kind"] == "oracle"
+    r = bench.cpu_baseline_tiling(W, words, np.zeros_like(own, dtype=np.int64))
+    assert r["fp64_l1_vs_oracle"] == int(own.sum())
+
+
+def test_batch_baseline_samples_every_nth_set():
+    """The batch leg's oracle baseline renders sets 0, 16, ..., compares each
+    with the batched image of the same set, and reports the bar."""
+    import numpy as np
+
+    from oracle import oracle as O
+    from paper_1709_08018_amd import workloads as wl
+
+    ta, tb, depth = wl.batch256(seed=0)
+    win = wl.BATCH_WINDOW
+    # shallow stand-ins keep the oracle's work small; the sampling is what is checked
+    depth = np.full_like(depth, 6)
+    imgs = np.zeros((len(ta), win.height, win.width), np.uint32)
+    for i in range(0, len(ta), 64):
+        imgs[i] = O.render(complex(ta[i]), complex(tb[i]), 6, win.as_tuple())[0]
+    r = bench.cpu_baseline_batch(ta, tb, depth, win, imgs, every=64)
+    assert r["sample"].startswith("sets 0, 64, ... every 64th of the batch (4 sets")
+    assert r["l1_vs_oracle"] == 0 and r["within_bar"]
+    imgs[64] = 0
+    r = bench.cpu_baseline_batch(ta, tb, depth, win, imgs, every=64)
+    assert r["l1_vs_oracle"] == int(O.render(complex(ta[64]), complex(tb[64]), 6, win.as_tuple())[0].sum())
