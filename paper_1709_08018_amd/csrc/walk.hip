@@ -43,6 +43,20 @@ namespace {
 constexpr uint64_t kPhiloxM0 = 0xD2E7470EE14C6C93ull, kPhiloxM1 = 0xCA5A826395121157ull;
 constexpr uint64_t kPhiloxW0 = 0x9E3779B97F4A7C15ull, kPhiloxW1 = 0xBB67AE8584CAA73Bull;
 
+// The 128-bit product a m of 64-bit words, from the four 32 x 32-bit
+// partial products (each a multiply-add into 64 bits that cannot overflow):
+// both halves come from the same four multiply-adds.
+template <uint64_t M>
+__device__ __forceinline__ void mul128(uint64_t a, uint64_t& hi, uint64_t& lo) {
+    constexpr uint32_t m0 = (uint32_t)M, m1 = (uint32_t)(M >> 32);
+    const uint32_t a0 = (uint32_t)a, a1 = (uint32_t)(a >> 32);
+    const uint64_t p0 = (uint64_t)a0 * m0;
+    const uint64_t p1 = (uint64_t)a0 * m1 + (p0 >> 32);
+    const uint64_t p2 = (uint64_t)a1 * m0 + (uint32_t)p1;
+    hi = (uint64_t)a1 * m1 + (p1 >> 32) + (p2 >> 32);
+    lo = (p2 << 32) | (uint32_t)p0;
+}
+
 // Ten Philox4x64 rounds: each takes the 128-bit products of words 0 and 2
 // with the two multipliers and mixes their halves with words 1 and 3 and
 // the key; the key advances by the two Weyl constants between rounds.
@@ -54,8 +68,9 @@ __device__ __forceinline__ void philox4x64_10(uint64_t c0, uint64_t c1, uint64_t
             k0 += kPhiloxW0;
             k1 += kPhiloxW1;
         }
-        const uint64_t hi0 = __umul64hi(kPhiloxM0, c0), lo0 = kPhiloxM0 * c0;
-        const uint64_t hi1 = __umul64hi(kPhiloxM1, c2), lo1 = kPhiloxM1 * c2;
+        uint64_t hi0, lo0, hi1, lo1;
+        mul128<kPhiloxM0>(c0, hi0, lo0);
+        mul128<kPhiloxM1>(c2, hi1, lo1);
         const uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
         c0 = n0;
         c1 = lo1;
@@ -302,7 +317,25 @@ __global__ __launch_bounds__(256) void walk_bin_kernel(const WalkJob j, uint16_t
     }
 }
 
-constexpr uint32_t kHistBatch = 16;   // regions whose offsets a wave loads before counting them
+// The tile histogram reads a region's offsets of one tile (its segment) in
+// 16-byte chunks of 8 offsets, 8 lanes to a region, so that one load
+// instruction of a wave covers the first 64 offsets of 8 regions; a wave
+// loads the first chunks of kHistPasses such groups of 8 regions before
+// counting them, and loads the segment bounds of its next 64 regions while
+// it counts the current ones.
+constexpr uint32_t kHistLanes = 8;    // lanes per region
+constexpr uint32_t kHistPasses = 4;   // groups of 8 regions loaded before counting
+
+// count the offsets of chunk c (offsets 8c .. 8c + 7 of the region) that
+// lie in the segment [a, b)
+__device__ __forceinline__ void hist_chunk(uint32_t* hist, uint4 v, uint32_t c, uint32_t a, uint32_t b) {
+    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (uint32_t e = 0; e < 8; ++e) {
+        const uint32_t i = 8 * c + e;
+        if (i >= a && i < b) atomicAdd(&hist[(w[e / 2] >> (16 * (e % 2))) & 0xFFFFu], 1u);
+    }
+}
 
 // Tile blockIdx.x / split over its share of the regions: every offset
 // counted in an LDS histogram, then each non-zero bin added to the image.
@@ -316,40 +349,48 @@ __global__ __launch_bounds__(1024) void walk_tile_hist_kernel(const uint16_t* __
     __syncthreads();
     const uint64_t r0 = n_regions * part / split, r1 = n_regions * (part + 1) / split;
     const uint32_t wave = threadIdx.x / 64, lane = threadIdx.x % 64, waves = blockDim.x / 64;
-    // a wave takes its slice of the regions 64 at a time: each lane fetches
-    // one region's segment bounds, then the wave loads kHistBatch regions'
-    // first 64 offsets before counting them, so those loads overlap; longer
-    // segments go on
+    const uint32_t grp = lane / kHistLanes, sub = lane % kHistLanes;
+    // a wave takes a contiguous slice of the regions, 64 at a time; lane l
+    // holds the segment bounds [a, b) of region base + l (0, 0 past the slice)
     const uint64_t per = (r1 - r0 + waves - 1) / waves;
     const uint64_t w0 = r0 + wave * per, w1 = w0 + per < r1 ? w0 + per : r1;
+    uint32_t na = 0, nb_ = 0;
+    if (w0 + lane < w1) {
+        const uint32_t* st = starts + (w0 + lane) * (T_tiles + 1);
+        na = st[tile];
+        nb_ = st[tile + 1];
+    }
     for (uint64_t base = w0; base < w1; base += 64) {
-        const uint64_t rl = base + lane;
-        uint32_t a = 0, b = 0;
-        if (rl < w1) {
-            const uint32_t* st = starts + rl * (T_tiles + 1);
-            a = st[tile];
-            b = st[tile + 1];
+        const uint32_t a = na, b = nb_;
+        na = 0;
+        nb_ = 0;
+        if (base + 64 + lane < w1) {
+            const uint32_t* st = starts + (base + 64 + lane) * (T_tiles + 1);
+            na = st[tile];
+            nb_ = st[tile + 1];
         }
-        const uint32_t nb = w1 - base < 64 ? (uint32_t)(w1 - base) : 64u;
-        for (uint32_t j = 0; j < nb; j += kHistBatch) {
-            uint32_t v[kHistBatch], aj[kHistBatch], bj[kHistBatch];
-            bool ok[kHistBatch];
+        const uint32_t n = w1 - base < 64 ? (uint32_t)(w1 - base) : 64u;
+        for (uint32_t j = 0; j < n; j += kHistLanes * kHistPasses) {
+            uint4 v[kHistPasses];
+            uint32_t aq[kHistPasses], bq[kHistPasses], cq[kHistPasses];
+            const uint16_t* seg[kHistPasses];
 #pragma unroll
-            for (uint32_t q = 0; q < kHistBatch; ++q) {
-                aj[q] = __shfl(a, (int)(j + q), 64);
-                bj[q] = __shfl(b, (int)(j + q), 64);   // 0, 0 past the regions
-                const uint32_t i = aj[q] + lane;
-                ok[q] = i < bj[q];
-                v[q] = ok[q] ? ids[(base + j + q) * kWalkRegion + i] : 0u;
+            for (uint32_t q = 0; q < kHistPasses; ++q) {
+                const uint32_t r = j + kHistLanes * q + grp;   // < 64
+                aq[q] = __shfl(a, (int)r, 64);
+                bq[q] = __shfl(b, (int)r, 64);
+                cq[q] = aq[q] / 8 + sub;
+                seg[q] = ids + (base + r) * kWalkRegion;
+                v[q] = 8 * cq[q] < bq[q] ? *(const uint4*)(seg[q] + 8 * cq[q]) : make_uint4(0, 0, 0, 0);
             }
 #pragma unroll
-            for (uint32_t q = 0; q < kHistBatch; ++q)
-                if (ok[q]) atomicAdd(&hist[v[q]], 1u);
+            for (uint32_t q = 0; q < kHistPasses; ++q)
+                if (8 * cq[q] < bq[q]) hist_chunk(hist, v[q], cq[q], aq[q], bq[q]);
+            // segments longer than the group's first 8 chunks
 #pragma unroll
-            for (uint32_t q = 0; q < kHistBatch; ++q) {
-                const uint16_t* in = ids + (base + j + q) * kWalkRegion;
-                for (uint32_t i = aj[q] + 64 + lane; i < bj[q]; i += 64) atomicAdd(&hist[in[i]], 1u);
-            }
+            for (uint32_t q = 0; q < kHistPasses; ++q)
+                for (uint32_t c = cq[q] + kHistLanes; 8 * c < bq[q]; c += kHistLanes)
+                    hist_chunk(hist, *(const uint4*)(seg[q] + 8 * c), c, aq[q], bq[q]);
         }
     }
     __syncthreads();
