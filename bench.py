@@ -878,7 +878,7 @@ def main():
     # (an event pair costs a few microseconds of queue time per step)
     sampled = list(range(0, args.steps, EVENT_EVERY))
     events = []
-    for _ in range(2 * len(sampled)):
+    for _ in range(max(2, 2 * len(sampled))):
         e = ctypes.c_void_p()
         if hip.hipEventCreate(ctypes.byref(e)) != 0:
             raise RuntimeError("hipEventCreate failed")
@@ -910,6 +910,16 @@ def main():
         ms = ctypes.c_float()
         hip.hipEventElapsedTime(ctypes.byref(ms), events[2 * j], events[2 * j + 1])
         kernel_ms.append(ms.value)
+    # the kernel alone, after the timed steps: 3 warm-up and 20 timed renders,
+    # each waited for, with events around the persistent kernel's launch
+    reps = []
+    for r in range(23):
+        kl.render(W.ta, W.tb, W.depth, W.window, image=image, kernel_events=(events[0], events[1]))
+        hip.hipEventSynchronize(ctypes.c_void_p(events[1]))
+        ms = ctypes.c_float()
+        hip.hipEventElapsedTime(ctypes.byref(ms), events[0], events[1])
+        if r >= 3:
+            reps.append(ms.value)
     for e in events:
         hip.hipEventDestroy(e)
     kernel_avg = float(np.mean(kernel_ms))
@@ -939,6 +949,9 @@ def main():
                 "frac": round(achieved / FP32_PEAK_TFLOPS, 4), "traffic": _traffic_from_profile(plan),
                 "kernel": "render_kernel<float, %s, false>" % ("true" if plan["hist_mode"] == 2 else "false"),
                 "kernel_ms": round(kernel_avg, 4),
+                "kernel_ms_alone": {"reps": len(reps), "warmup": 3, "median": round(float(np.median(reps)), 4),
+                                    "min": round(float(np.min(reps)), 4), "mean": round(float(np.mean(reps)), 4),
+                                    "note": "renders waited for one at a time after the timed steps"},
                 "flops_per_word": FLOPS_PER_WORD, "words_per_launch": kernel_words}
     # VALU issue (committed counter summary of the current source and split):
     # instructions per 64 words, and the fraction of the VALU issue slots the
