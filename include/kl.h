@@ -348,7 +348,7 @@ int kl_walk_eval_ex(const kl_c64 *ab, const kl_walk *walk, const kl_window *wind
  * finite.  image + dropped = n_walkers * n_steps.  opts: precision,
  * accumulate, stream, dropped_out, hist_mode:
  *   KL_HIST_RUNS  one global atomic add per point in the window;
- *   KL_HIST_LDS   each workgroup's points of 16 steps sorted by image tile
+ *   KL_HIST_LDS   each workgroup's points of 8 steps sorted by image tile
  *                 (2^15 bins) in LDS and staged in device temporaries
  *                 (2 bytes a point, allocated on the stream), then counted
  *                 tile by tile in LDS; images of at most 256 tiles

@@ -28,7 +28,7 @@
 // infinity outside).  The points of a walk jump across the limit set, so
 // there are no runs to merge, and a global atomic per point (walk_kernel)
 // costs a cache line per lane.  The binned path (walk_bin_kernel,
-// walk_tile_hist_kernel) instead sorts each workgroup's points of 16 steps
+// walk_tile_hist_kernel) instead sorts each workgroup's points of 8 steps
 // by image tile of 2^15 bins in LDS and writes them out as 16-bit offsets
 // within their tiles; a second kernel counts each tile's offsets in an LDS
 // histogram and adds its non-zero bins to the image.
@@ -236,7 +236,12 @@ __global__ __launch_bounds__(256) void walk_kernel(const WalkJob j) {
 // ---- binned render
 constexpr uint32_t kWalkTileBits = 15;                    // a tile: 2^15 bins
 constexpr uint32_t kWalkTileBins = 1u << kWalkTileBits;
-constexpr uint32_t kWalkChunk = 16;                       // drawn steps per region
+// Drawn steps per region.  Eight keep a workgroup's LDS near 14 KB, so that
+// eight workgroups (32 waves) fit a CU and hide the sort's barriers and
+// LDS atomics behind each other's arithmetic; sixteen steps (26 KB, six
+// workgroups) took 15% longer on 2^30 points, thirty-two 72% longer, and
+// four no shorter.
+constexpr uint32_t kWalkChunk = 8;
 constexpr uint32_t kWalkRegion = 256 * kWalkChunk;        // points of a region at most
 constexpr uint32_t kNoKey = 0xFFFFFFFFu;
 

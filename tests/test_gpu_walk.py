@@ -151,7 +151,7 @@ def _render_both(ab, seed, first, n, burn, steps, win, precision, accumulate_int
 
 # Binned render (points sorted by image tile of 2^15 bins in LDS, counted
 # tile by tile) against the direct one: ragged walker blocks, walks whose
-# drawn steps are not a multiple of the 16-step chunk, burn-in, one tile and
+# drawn steps are not a multiple of the 8-step chunk, burn-in, one tile and
 # many, both precisions.
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
 @pytest.mark.parametrize("n,burn,steps,win", [
