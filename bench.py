@@ -453,9 +453,12 @@ def leg_batch(args):
 
     reps = max(2, args.steps // 4)
     # the planner's plans: one batched launch, then 256 plain kl_render calls
+    # (a single render plans shorter tails at depths 13-16 than a set of a
+    # batch does, so the images are compared under the batch's plans)
     ms_b_default = _time(batched, reps, 1)
     ref = imgs.clone()
     ms_s_default = _time(separate, reps, 1)
+    separate([kl.plan_many(int(d), "fp32", win) for d in depth])
     same_default = bool(torch.equal(ref, imgs))
     # plans tuned for the batch as a whole (timing whole batched launches)
     t0 = time.perf_counter()

@@ -124,7 +124,13 @@ typedef struct {
                              of words dropped as outside or not finite */
     int tail_len;         /* r: letters per suffix table, 0 = planner (1..8 in
                              FP32, 1..7 in FP64, whose r = 8 table would not
-                             fit a CU's LDS: KL_EINVAL) */
+                             fit a CU's LDS: KL_EINVAL).  The planner takes 6
+                             letters, fewer below depth 7, and for a render
+                             of one depth of 13..16 letters (and kl_eval and
+                             kl_plan of such a depth) 4 letters at depths
+                             13-14 and 5 at 15-16; a word's value depends on
+                             r, so renders compared bit for bit across these
+                             contexts pass the same r */
     int lane_len;         /* m: letters each lane adds to its prefix, 0 = planner (1..20) */
     int hist_mode;        /* KL_HIST_* */
     int waves_per_cu;     /* persistent grid size, 0 = planner */

@@ -269,7 +269,8 @@ static int scratch_address(void** out) {
 static const int kDefaultTail = 6;
 static const int kDefaultWavesPerCU = 32;
 
-int plan_split(int depth, int precision, int r_req, int m_req, Split* sp, int prefix_cap) {
+int plan_split(int depth, int precision, int r_req, int m_req, Split* sp, PlanContext ctx) {
+    const int prefix_cap = ctx == kPlanBatch ? 8 : 9;
     int r;
     if (r_req > 0) {
         if (r_req > kMaxTail || r_req > depth) return fail(KL_EINVAL, "tail_len %d outside 1..min(8, depth)", r_req);
@@ -281,6 +282,22 @@ int plan_split(int depth, int precision, int r_req, int m_req, Split* sp, int pr
         r = r_req;
     } else {
         r = depth <= 4 ? depth : std::min(kDefaultTail, depth - 1);
+        // A render of one depth from 13 to 16 letters has few heads for
+        // the persistent kernel's 8,192 waves with 6-letter tails (137
+        // units of 64 heads at depth 14), so it takes shorter ones: 4
+        // letters at depths 13-14, 5 at 15-16.  Measured, FP32, 6-letter
+        // tails against these: 2048^2 image over [-1.5, 1.5]^2, 33 / 21,
+        // 104 / 26, 101 / 47, 109 / 59 us at depths 13..16; 512^2 over
+        // [-2, 2]^2, 34 / 19, 86 / 32, 88 / 42, 93 / 87 us.  Still shorter
+        // tails lose there (depth 16 with 4 letters: 231 us), many more
+        // heads flushing their runs into the same coarse bins; depths 17 and
+        // up keep 6.  A batch of many sets fills the GPU with its sets and
+        // keeps 6 letters, which its many small images favour; so do the
+        // depths of a tiling, which go in one batched launch whose units
+        // of 256 heads are dealt round robin: mixing 4- and 6-letter tails
+        // there leaves units of unequal work (the tiling of Maskit's group
+        // to depth 14 took 0.25 ms against 0.215 ms with 6 letters throughout).
+        if (ctx == kPlanSingle && depth >= 13 && depth <= 16) r = depth <= 14 ? 4 : 5;
         // the deepest words need a longer tail: k <= 14 and m <= 20
         r = std::max(r, std::min(kMaxTail, depth - kMaxLane - kMaxPrefix));
     }
@@ -544,7 +561,7 @@ static void load_tuned_locked() {
             (t.precision == KL_PREC_FP32 || t.precision == KL_PREC_FP64) &&
             t.depth >= 1 && t.depth <= KL_MAX_DEPTH && t.r >= 1 && t.r <= kMaxTail && t.r < t.depth && t.m >= 0 &&
             t.m <= kMaxLane && t.wpc >= 0 && t.wpc <= 32 && t.W <= 32768 && t.H <= 32768 &&
-            plan_split(t.depth, t.precision, t.r, t.m, &sp, t.ctx == kTuneBatch ? 8 : 9) == KL_OK)
+            plan_split(t.depth, t.precision, t.r, t.m, &sp, t.ctx == kTuneBatch ? kPlanBatch : kPlanSingle) == KL_OK)
             put_tuned_locked(t);
     }
     fclose(f);
@@ -613,11 +630,11 @@ static kl_opts apply_tuned(const kl_opts& o, int depth, const kl_window* w, bool
 // also clears the image and the dropped counter first.
 static int render_depth(const Gens& G, const Fold& f, int depth, uint64_t lo, uint64_t hi, const kl_opts& o_in,
                         const kl_window* w, uint32_t* image, uint64_t* dropped, hipStream_t s, bool clear,
-                        const TableBuf* buf = nullptr) {
+                        const TableBuf* buf = nullptr, PlanContext ctx = kPlanSingle) {
     if (lo >= hi && !clear) return KL_OK;
     const kl_opts o = apply_tuned(o_in, depth, w);
     Split sp;
-    int rc = plan_split(depth, o.precision, o.tail_len, o.lane_len, &sp);
+    int rc = plan_split(depth, o.precision, o.tail_len, o.lane_len, &sp, ctx);
     if (rc) return rc;
     Temp tmp(s);
     SetTables st;
@@ -826,7 +843,9 @@ static int check_render(int depth, const kl_window* window, const uint32_t* imag
     for (int d = min_depth; d <= depth; ++d) {
         Split sp;
         const kl_opts od = d == depth ? o : opts_for_depth(o, d);
-        if ((rc = plan_split(d, od.precision, od.tail_len, od.lane_len, &sp))) return rc;
+        if ((rc = plan_split(d, od.precision, od.tail_len, od.lane_len, &sp,
+                             min_depth < depth ? kPlanTiling : kPlanSingle)))
+            return rc;
     }
     *span = {min_depth, first, count};
     return KL_OK;
@@ -1007,7 +1026,7 @@ static int render_tiling(const Gens& G, int depth, const kl_window* w, uint32_t*
         for (int d = min_depth; d <= depth; ++d) {
             const kl_opts od = apply_tuned(d == depth ? o : opts_for_depth(o, d), d, w);
             Split sp;
-            int rc = plan_split(d, od.precision, od.tail_len, od.lane_len, &sp);
+            int rc = plan_split(d, od.precision, od.tail_len, od.lane_len, &sp, kPlanTiling);
             if (rc) return rc;
             if (!wpc && d == depth) wpc = od.waves_per_cu;
             specs.push_back({G, sp, sd, image, o.dropped_out});
@@ -1055,7 +1074,7 @@ static int render_run(const Gens& G, int depth, const kl_window* window, uint32_
             const kl_opts od = d == depth ? o : opts_for_depth(o, d);
             const bool any = end > offset && first < offset + n && lo < hi;
             if ((rc = render_depth(G, f, d, any ? lo : 0, any ? hi : 0, od, window, image_out, o.dropped_out, s,
-                                   clear, buf)))
+                                   clear, buf, span.min_depth < depth ? kPlanTiling : kPlanSingle)))
                 return rc;
             clear = false;
         }
@@ -1610,7 +1629,7 @@ static int render_many_run(int n, const kl_c64* ta, const kl_c64* tb, const int*
             per[i].tail_len = bp->r[depth[i]];
             per[i].lane_len = bp->m[depth[i]];
         }
-        if ((rc = plan_split(depth[i], o.precision, per[i].tail_len, per[i].lane_len, &splits[i], 8))) {
+        if ((rc = plan_split(depth[i], o.precision, per[i].tail_len, per[i].lane_len, &splits[i], kPlanBatch))) {
             std::string m = g_last_error;
             return fail(rc, "set %d: %s", i, m.c_str());
         }
@@ -1680,7 +1699,7 @@ int kl_autotune_many(int n, const kl_c64* ta, const kl_c64* tb, const int* depth
     for (int d = 1; d <= KL_MAX_DEPTH; ++d) {
         if (!present[d]) continue;
         Split sp;
-        if ((rc = plan_split(d, precision, 0, 0, &sp, 8))) return rc;
+        if ((rc = plan_split(d, precision, 0, 0, &sp, kPlanBatch))) return rc;
         cur.r[d] = sp.r;
         cur.m[d] = sp.m;
     }
@@ -1729,7 +1748,7 @@ int kl_autotune_many(int n, const kl_c64* ta, const kl_c64* tb, const int* depth
         def.m[d] = 0;
         if (!present[d]) continue;
         Split sp;
-        if (rc == KL_OK && (rc = plan_split(d, precision, 0, 0, &sp, 8)) == KL_OK) {
+        if (rc == KL_OK && (rc = plan_split(d, precision, 0, 0, &sp, kPlanBatch)) == KL_OK) {
             def.r[d] = sp.r;
             def.m[d] = sp.m;
         }
@@ -1794,7 +1813,7 @@ int kl_plan_many(int depth, int precision, const kl_window* window, kl_plan_t* p
     o.precision = precision;
     o = apply_tuned(o, depth, window, true);
     Split sp;
-    if ((rc = plan_split(depth, precision, o.tail_len, o.lane_len, &sp, 8))) return rc;
+    if ((rc = plan_split(depth, precision, o.tail_len, o.lane_len, &sp, kPlanBatch))) return rc;
     plan_out->depth = depth;
     plan_out->tail_len = sp.r;
     plan_out->lane_len = sp.m;

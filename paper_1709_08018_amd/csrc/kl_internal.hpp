@@ -89,7 +89,12 @@ struct Tables {                // device pointers of one parameter set
 
 // Host-side planning and validation helpers (abi.cpp)
 int set_error(int code, const char* fmt, ...);  // records kl_last_error(), returns code
-int plan_split(int depth, int precision, int r_req, int m_req, Split* out, int prefix_cap = 9);
+// Where a split is used: a render of one depth (and kl_eval and kl_plan,
+// which must agree with it word for word); a depth of a tiling render
+// (min_depth < depth, whole or by index ranges); or one set of a batched
+// render of many parameter sets.
+enum PlanContext { kPlanSingle, kPlanTiling, kPlanBatch };
+int plan_split(int depth, int precision, int r_req, int m_req, Split* out, PlanContext ctx = kPlanSingle);
 uint64_t num_words(int depth);
 uint64_t pow3_u64(int n);
 

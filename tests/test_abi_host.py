@@ -65,6 +65,19 @@ def test_plans_cover_every_depth(precision):
             assert p["prefix_len"] >= 1
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_default_tail_by_depth_and_context(precision):
+    """A render of one depth takes 4-letter tails at depths 13-14 and 5-letter
+    ones at 15-16 (enough heads for the persistent kernel), 6 letters from
+    depth 17 on; a set of a batched render keeps 6 letters from depth 7 on."""
+    w = (-2.0, 2.0, -2.0, 2.0, 512, 512)
+    single = {d: kl.plan(d, precision)["tail_len"] for d in range(7, 23)}
+    batch = {d: kl.plan_many(d, precision, w)["tail_len"] for d in range(7, 23)}
+    assert [single[d] for d in range(12, 19)] == [6, 4, 4, 5, 5, 6, 6]
+    assert all(single[d] == 6 for d in range(17, 23)) and all(single[d] == 6 for d in range(7, 13))
+    assert all(batch[d] == 6 for d in range(7, 23))
+
+
 def test_plan_overrides_and_rejects():
     p = kl.plan(18, "fp32", tail_len=6, lane_len=4)
     assert (p["tail_len"], p["lane_len"], p["prefix_len"]) == (6, 4, 8)

@@ -117,7 +117,9 @@ def test_batch256_depth18_set_is_histogram_of_all_its_words():
     imgs = kl.render_many(ta, tb, depth, win, dropped=dropped)
     for i in (int(np.argmax(depth)), int(np.argmin(depth)), 17, 200):
         d = int(depth[i])
-        ref, drop = own_bins_histogram(complex(ta[i]), complex(tb[i]), d, win)
+        p = kl.plan_many(d, "fp32", win)   # the words' values under the batch's split for the set
+        ref, drop = own_bins_histogram(complex(ta[i]), complex(tb[i]), d, win, tail_len=p["tail_len"],
+                                       lane_len=p["lane_len"])
         got = _image(imgs[i])
         assert int((got - ref.cpu()).abs().sum()) == 0, (i, d)
         assert int(dropped[i].item()) == drop, (i, d)

@@ -122,7 +122,9 @@ def test_render_many_with_seeds_equals_single_renders(seed):
     win = (-2.0, 2.0, -2.0, 2.0, 256, 256)
     many = kl.render_many(ta, tb, depths, win, seed=seed)
     for i in range(5):
-        one = kl.render(complex(ta[i]), complex(tb[i]), int(depths[i]), win, seed=seed)
+        p = kl.plan_many(int(depths[i]), "fp32", win)   # the batch's split for the set
+        one = kl.render(complex(ta[i]), complex(tb[i]), int(depths[i]), win, seed=seed,
+                        tail_len=p["tail_len"], lane_len=p["lane_len"])
         assert torch.equal(many[i], one), i
 
 
