@@ -514,3 +514,26 @@ def test_tiling_render_equals_sum_of_single_depths(precision, seed):
     copies = 4 if seed == "all" else 1
     assert int(kl.as_u32(img).astype(np.int64).sum()) + int(dropped.item()) == copies * sum(
         kl.num_words(d) for d in range(mind, depth + 1))
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_tiling_takes_its_deepest_depth_tail(precision):
+    """A tiling whose deepest depth plans a shorter tail when rendered alone
+    (depth 14: 4 letters) takes that tail at every depth long enough for it:
+    it equals the single-depth renders added up under that tail, and its
+    index ranges add up to it."""
+    depth, mind, win = 14, 1, (-2.0, 2.0, -2.0, 2.0, 512, 512)
+    r = kl.plan(depth, precision)["tail_len"]
+    assert r == 4
+    full = kl.render(*C2, depth, win, precision=precision, min_depth=mind)
+    acc = kl.new_image(win)
+    for d in range(mind, depth + 1):
+        kl.render(*C2, d, win, image=acc, precision=precision, accumulate=d > mind, tail_len=r if d > r else 0)
+    assert torch.equal(full, acc)
+    total = sum(kl.num_words(d) for d in range(mind, depth + 1))
+    acc2 = kl.new_image(win)
+    cuts = [0, 1000, total // 3, total - 5, total]
+    for a, b in zip(cuts[:-1], cuts[1:]):
+        kl.render(*C2, depth, win, image=acc2, precision=precision, min_depth=mind, first=a, count=b - a,
+                  accumulate=a > 0)
+    assert torch.equal(full, acc2)
