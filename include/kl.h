@@ -418,9 +418,14 @@ int kl_cayley_eval_ex(const kl_cayley *t, int depth, const uint64_t *idx, uint64
 int kl_cayley_render_ex(const kl_cayley *t, int depth, const kl_window *window, uint32_t *image_out,
                         const kl_opts *opts);
 
-/* kl_plan: the split and histogram strategy the renderer would use for one
- * depth and precision on the current device, after the options' overrides.
- * Errors: KL_EINVAL. */
+/* kl_plan: the split and histogram strategy the renderer would use for a
+ * render of this one depth and precision on the current device, after the
+ * options' overrides (kl_eval takes the same split).  A tiling render
+ * (min_depth < depth) that leaves the split to the planner takes its
+ * deepest depth's tail_len from this plan at every depth longer than it
+ * when that tail is not 6 letters and no tuned plan covers the deepest
+ * depth; otherwise each depth takes 6 letters (fewer below depth 7) or its
+ * tuned plan.  Errors: KL_EINVAL. */
 int kl_plan(int depth, int precision, const kl_window *window, const kl_opts *opts,
             kl_plan_t *plan_out);
 
