@@ -535,12 +535,42 @@ def leg_maskit(args):
     for prec in ("fp32", "fp64"):
         ms = _time(lambda: kl.render_group(ab, W.depth, W.window, image=image, min_depth=W.min_depth, seed="all",
                                            precision=prec), max(2, args.steps // 4), 3)
-        out[prec] = {"ms": round(ms, 4), "gpoints_per_s": round(4 * words / ms / 1e6, 3)}
+        # the same tiling with 6-letter tails throughout (the planner gives a
+        # tiling its deepest depth's single-render tail, 4 letters here)
+        ms6 = _time(lambda: kl.render_group(ab, W.depth, W.window, image=image, min_depth=W.min_depth, seed="all",
+                                            precision=prec, tail_len=6), max(2, args.steps // 4), 3)
+        out[prec] = {"ms": round(ms, 4), "gpoints_per_s": round(4 * words / ms / 1e6, 3),
+                     "tail_len": kl.plan(W.depth, prec)["tail_len"], "ms_tail_6": round(ms6, 4)}
     kl.render_group(ab, W.depth, W.window, image=image, min_depth=W.min_depth, seed="all", precision="fp64")
     img = kl.as_u32(image).astype(np.int64)
     out["points_in_window"] = int(img.sum())
     out["cpu_baseline"] = cpu_baseline_maskit(W, words, img)
     return out
+
+
+def leg_splits(args):
+    """Single renders of one depth against the tail length: depths 13..18,
+    FP32, images of 512^2 to 4096^2 over [-1.5, 1.5]^2, averaged over four
+    parameter sets (the quasi-Fuchsian pair and sets 3, 50 and 120 of the
+    256-set batch); microseconds per render with the planner's split and
+    with 6-, 5- and 4-letter tails."""
+    from paper_1709_08018_amd import kl
+    from paper_1709_08018_amd import workloads as wl
+
+    ta, tb, _ = wl.batch256(seed=0)
+    sets = [(wl.C2_TA, wl.C2_TB)] + [(complex(ta[i]), complex(tb[i])) for i in (3, 50, 120)]
+    reps = max(3, args.steps // 20)
+    rows = []
+    for W in (512, 1024, 2048, 4096):
+        win = (-1.5, 1.5, -1.5, 1.5, W, W)
+        image = kl.new_image(win)
+        for d in range(13, 19):
+            row = {"image": f"{W}x{W}", "depth": d, "planner_tail_len": kl.plan(d, "fp32", win)["tail_len"]}
+            for r in (0, 6, 5, 4):
+                ms = _time(lambda: [kl.render(a, b, d, win, image=image, tail_len=r) for a, b in sets], reps, 2)
+                row["planner_us" if r == 0 else f"tail_{r}_us"] = round(ms * 1e3 / len(sets), 1)
+            rows.append(row)
+    return {"workload": "splits", "rows": rows}
 
 
 def leg_cayley(args):
@@ -844,7 +874,7 @@ def main():
     ap.add_argument("--workload", default="quasifuchsian_d18",
                     choices=["quasifuchsian_d18", "quasifuchsian_d22", "decode", "bounded", "batch256", "fuchsian_tiling_d10",
                              "maskit_tiling_d14", "cayley", "surrogate", "surrogate_kernels", "surrogate_curve", "hist",
-                             "calib", "walk"])
+                             "calib", "walk", "splits"])
     ap.add_argument("--no-surrogate", action="store_true",
                     help="leave the surrogate's training and gated scan out of the headline line")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -865,7 +895,7 @@ def main():
 
     torch.cuda.set_device(0)
     legs = {"quasifuchsian_d22": leg_d22, "decode": leg_decode, "bounded": leg_bounded, "batch256": leg_batch, "fuchsian_tiling_d10": leg_tiling,
-            "maskit_tiling_d14": leg_maskit, "cayley": leg_cayley, "surrogate": leg_surrogate, "hist": leg_hist,
+            "maskit_tiling_d14": leg_maskit, "splits": leg_splits, "cayley": leg_cayley, "surrogate": leg_surrogate, "hist": leg_hist,
             "calib": leg_calib, "walk": leg_walk, "surrogate_kernels": leg_surrogate_kernels,
             "surrogate_curve": leg_surrogate_curve}
     if args.workload in legs:
