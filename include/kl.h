@@ -225,7 +225,9 @@ int kl_render_ex(kl_c64 ta, kl_c64 tb, int depth, const kl_window *window,
  * rewrites the tables it uses before reading them, so nothing carries over
  * between calls; calls that overlap on one device (two streams, or two host
  * threads) race on it and must be serialised by the caller, while calls on
- * one stream are ordered by it.
+ * one stream are ordered by it.  It enqueues only kernels on opts->stream,
+ * so a HIP graph can capture it once a first call outside capture has taken
+ * the array's address on the device.
  * Errors: as kl_render_ex; KL_EINVAL for a tiling render (min_depth other
  * than 0 or depth); KL_ENOMEM when the split's tables exceed the array
  * (prefix tables of 10 or more letters: depths above 35 under the planner's

@@ -71,3 +71,32 @@ def test_noalloc_rejects_what_does_not_fit():
     with pytest.raises(kl.KLError) as e:
         kl.render_noalloc(wl.C2_TA, wl.C2_TB, 10, win, image=img, min_depth=1)
     assert e.value.code == kl.KL_EINVAL
+
+
+def test_noalloc_render_replays_from_a_captured_graph():
+    """kl_render_noalloc enqueues only kernels on the caller's stream and
+    allocates nothing, so a HIP graph can capture it (after a first call
+    outside capture, which takes the scratch array's address): every replay,
+    with eager work and synchronisations between replays, draws the image
+    kl_render_ex draws."""
+    win = (-1.5, 1.5, -1.5, 1.5, 1024, 1024)
+    ref = kl.render(wl.C2_TA, wl.C2_TB, 14, win)
+    img = kl.new_image(win)
+    kl.render_noalloc(wl.C2_TA, wl.C2_TB, 14, win, image=img)
+    torch.cuda.synchronize()
+    assert torch.equal(img, ref)
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            kl.render_noalloc(wl.C2_TA, wl.C2_TB, 14, win, image=img)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    for rep in range(4):
+        img.fill_(7)
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(img, ref), rep
+        kl.render(wl.C1_TA, wl.C1_TB, 10, (-2.0, 2.0, -2.0, 2.0, 256, 256))   # the library between replays
+        torch.cuda.synchronize()
