@@ -413,6 +413,17 @@ def leg_decode(args):
         e1.record()
         torch.cuda.synchronize()
         plain[name] = round(count * d / (e0.elapsed_time(e1) / reps) / 1e6, 1)
+    # the same bytes in the store orders of libkl_calib.so: one chunk a
+    # workgroup in launch order, or a persistent grid writing tiles in turn
+    # as the decode kernel does (36,864 B: its tile at depth 18)
+    clib = ctypes.CDLL(os.path.join(ROOT, "paper_1709_08018_amd", "libkl_calib.so"))
+    clib.kl_calib_store.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double)]
+    gbs_pat = (ctypes.c_double * clib.kl_calib_store_patterns())()
+    if clib.kl_calib_store(ctypes.c_void_p(out.data_ptr()), ctypes.c_uint64(count * d), gbs_pat) != 0:
+        raise RuntimeError("kl_calib_store failed")
+    names = ("chunk_4k", "chunk_16k", "chunk_64k", "persistent_tiles_4k", "persistent_tiles_36k",
+             "persistent_tiles_144k")
+    patterns = {n: round(g, 1) for n, g in zip(names, gbs_pat)}
     for _ in range(2):
         kl.decode(first, count, d, out=out)
     rows = [0, 1, count // 2, count - 1]
@@ -421,7 +432,8 @@ def leg_decode(args):
             "gwords_per_s": round(count / ms / 1e6, 2),
             "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": 8000.0, "unit": "GB/s",
                          "frac": round(gbs / 8000.0, 3), "bytes_per_word": d,
-                         "plain_write_gbs": plain},
+                         "plain_write_gbs": plain, "store_pattern_gbs": patterns,
+                         "frac_of_own_store_pattern": round(gbs / patterns["persistent_tiles_36k"], 3)},
             "cpu_baseline": cpu_baseline_decode(first, d, rows, got)}
 
 

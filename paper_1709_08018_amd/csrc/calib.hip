@@ -1,6 +1,7 @@
 // calib.hip -- libkl_calib.so: instruction-throughput microbenchmarks that
-// calibrate the renderer's VALU roofline on gfx950.  Not part of the
-// renderer's ABI; bench.py --workload calib calls it.
+// calibrate the renderer's VALU roofline on gfx950, and store-pattern
+// microbenchmarks beside the decode kernel's HBM roofline.  Not part of the
+// renderer's ABI; bench.py --workload calib and --workload decode call it.
 //
 // Each kernel runs 8 independent dependency chains of one instruction class
 // per lane for a fixed trip count on 32 waves per CU, and stores one value
@@ -65,9 +66,83 @@ hipError_t time_class(float* out, int blocks, hipEvent_t e0, hipEvent_t e1, floa
     return e == hipSuccess ? hipGetLastError() : e;
 }
 
+// ---- store patterns
+// The same bytes written in different orders, 16 bytes a thread and store.
+// Chunks: workgroup c writes chunk c (per_thread stores a thread, 4 KB
+// apart), one chunk a workgroup, in launch order.
+__global__ __launch_bounds__(256) void store_chunks(uint4* __restrict__ p, uint64_t n16, uint32_t per_thread) {
+    const uint64_t base = (uint64_t)blockIdx.x * 256u * per_thread;
+    for (uint32_t k = 0; k < per_thread; ++k) {
+        const uint64_t i = base + (uint64_t)k * 256u + threadIdx.x;
+        if (i < n16) p[i] = make_uint4((uint32_t)i, 1u, 2u, 3u);
+    }
+}
+
+// Tiles: a persistent grid, workgroup b writing tiles b, b + grid, ... of
+// tile16 16-byte pieces each, as the decode kernel writes its letters.
+__global__ __launch_bounds__(256) void store_tiles(uint4* __restrict__ p, uint64_t n16, uint32_t tile16) {
+    const uint64_t tiles = (n16 + tile16 - 1) / tile16;
+    for (uint64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
+        const uint64_t base = t * tile16;
+        for (uint32_t k = threadIdx.x; k < tile16; k += 256) {
+            const uint64_t i = base + k;
+            if (i < n16) p[i] = make_uint4((uint32_t)i, 1u, 2u, 3u);
+        }
+    }
+}
+
 }  // namespace
 
 extern "C" {
+
+// Store patterns: `bytes` (a multiple of 16) written to the device buffer
+// `buf` (16-byte aligned) in each of kl_calib_store_patterns orders, 2
+// warm-up and 5 timed launches each; gbs_out[i] (host) receives GB/s:
+//   0..2  one chunk of 4, 16, 64 KB a workgroup, non-persistent;
+//   3..5  persistent, 8 workgroups a CU, tiles of 4 KB, 36,864 B (the
+//         decode's tile at depth 18: 2048 words of 18 letters) and 144 KB.
+// Returns 0, -1 for a misaligned or unsized buffer, or -4 on a HIP error.
+int kl_calib_store_patterns(void) { return 6; }
+
+int kl_calib_store(void* buf, uint64_t bytes, double* gbs_out) {
+    if (!buf || !gbs_out || bytes == 0 || (bytes & 15) || ((uintptr_t)buf & 15)) return -1;
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return -4;
+    uint4* p = (uint4*)buf;
+    const uint64_t n16 = bytes / 16;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return -4;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return -4;
+    }
+    hipError_t e = hipSuccess;
+    for (int pat = 0; pat < 6 && e == hipSuccess; ++pat) {
+        auto launch = [&]() {
+            if (pat < 3) {
+                const uint32_t per = pat == 0 ? 1u : pat == 1 ? 4u : 16u;
+                const uint64_t blocks = (n16 + 256ull * per - 1) / (256ull * per);
+                hipLaunchKernelGGL(store_chunks, dim3((unsigned)blocks), dim3(256), 0, 0, p, n16, per);
+            } else {
+                const uint32_t tile16 = pat == 3 ? 256u : pat == 4 ? 2304u : 9216u;
+                hipLaunchKernelGGL(store_tiles, dim3((unsigned)(cus * 8)), dim3(256), 0, 0, p, n16, tile16);
+            }
+        };
+        for (int w = 0; w < 2; ++w) launch();
+        e = hipEventRecord(e0, nullptr);
+        for (int w = 0; w < 5 && e == hipSuccess; ++w) launch();
+        if (e == hipSuccess) e = hipEventRecord(e1, nullptr);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e == hipSuccess) e = hipGetLastError();
+        gbs_out[pat] = e == hipSuccess && ms > 0.0f ? (double)bytes * 5 / (ms * 1e-3) / 1e9 : 0.0;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return e == hipSuccess ? 0 : -4;
+}
 
 // Instruction classes, in the order of the outputs:
 //   0 v_fma_f32, 1 v_mul_f32, 2 v_add_f32, 3 v_add_u32, 4 v_rcp_f32,
