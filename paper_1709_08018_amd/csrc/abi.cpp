@@ -270,7 +270,7 @@ static const int kDefaultTail = 6;
 static const int kDefaultWavesPerCU = 32;
 
 int plan_split(int depth, int precision, int r_req, int m_req, Split* sp, PlanContext ctx) {
-    const int prefix_cap = ctx == kPlanBatch ? 8 : 9;
+    const int prefix_cap = ctx == kPlanBatch ? 8 : ctx == kPlanTiling ? 6 : 9;
     int r;
     if (r_req > 0) {
         if (r_req > kMaxTail || r_req > depth) return fail(KL_EINVAL, "tail_len %d outside 1..min(8, depth)", r_req);
