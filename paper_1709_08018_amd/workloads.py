@@ -108,6 +108,17 @@ WALK_D13_POINTS = WalkWorkload("walk_maskit_d13_points", MASKIT_MU, 1, 3 ** 11, 
 WALK_LARGE = WalkWorkload("walk_maskit_2p30", MASKIT_MU, 2, 1 << 24, 0, 64, MASKIT_D14.window)
 
 
+def draw_maskit_mu(n: int, seed: int, depth_range=(8, 16)):
+    """n Maskit parameters mu with depths, from numpy's PCG64 with the given
+    seed: Re mu ~ U[-1, 1], Im mu ~ U[2.0, 2.6] (inside the Maskit slice);
+    depth ~ uniform integer in depth_range (inclusive)."""
+    rng = np.random.default_rng(seed)
+    mu = rng.uniform(-1.0, 1.0, size=n) + 1j * rng.uniform(2.0, 2.6, size=n)
+    lo, hi = depth_range
+    depth = rng.integers(lo, hi + 1, size=n)
+    return mu.astype(np.complex128), depth.astype(np.int32)
+
+
 def draw_param_sets(n: int, seed: int, depth_range=(12, 18)):
     """n parameter sets (ta, tb, depth) from numpy's PCG64 with the given seed.
 

@@ -152,6 +152,31 @@ def test_maskit_fp64_values(seed):
     assert _rel_err(_z(kl.eval_group(ab, 14, idx, precision="fp64", seed=seed)), O.eval_group(G, 14, idx, seed=s)) < 1e-10
 
 
+def test_maskit_values_on_drawn_mu():
+    """12 Maskit parameters drawn inside the slice (Re mu in [-1, 1], Im mu in
+    [2.0, 2.6]) at depths 8..16, 2,000 sampled words each, the words' own
+    seeds: FP64 values within the 1e-10 bar of the oracle's, FP32 pixel
+    coordinates within 0.25 px of the oracle's near the window."""
+    mus, depths = wl.draw_maskit_mu(12, seed=5)
+    worst = 0.0
+    for i, (mu, d) in enumerate(zip(mus, depths)):
+        ab = kl.maskit_generators(complex(mu))
+        G = O.group_maskit(complex(mu))
+        d = int(d)
+        idx = wl.sample_indices(kl.num_words(d), 2000, seed=200 + i)
+        zr = O.eval_group(G, d, idx, seed=-1)
+        assert _rel_err(_z(kl.eval_group(ab, d, idx, precision="fp64")), zr) < 1e-10, (i, mu, d)
+        p = kl.eval_group(ab, d, idx, precision="fp32", window=WIN_MASKIT).cpu().numpy()
+        fx, fy = _ref_pixels(zr, WIN_MASKIT)
+        near = np.isfinite(fx) & np.isfinite(fy) & (fx > -1) & (fx < WIN_MASKIT[4] + 1) & (fy > -1) & \
+            (fy < WIN_MASKIT[5] + 1)
+        if near.any():
+            err = np.hypot(p[near, 0] - fx[near], p[near, 1] - fy[near]).max()
+            worst = max(worst, err)
+            assert err <= 0.25, (i, mu, d, err)
+    print(f"largest FP32 pixel error over the drawn parameters: {worst:.3e} px")
+
+
 @pytest.mark.parametrize("seed", ["own", "b"])
 def test_maskit_fp32_pixel_error(seed):
     ab = kl.maskit_generators(MU)

@@ -175,6 +175,29 @@ def test_fp64_values_batch_law():
         assert _fp64_case(complex(a), complex(b), 14, idx) < 1e-10
 
 
+def test_values_on_drawn_parameter_sets_and_depths():
+    """32 parameter sets of the batch's law (Re ta, Re tb in [1.8, 3.0], Im
+    in [-0.3, 0.3]) at depths drawn from 5..30, 2,000 sampled words each:
+    FP64 values within the 1e-10 bar of the oracle's, and FP32 pixel
+    coordinates on a 1024^2 window over [-2, 2]^2 within 0.25 px of the
+    oracle's for every word near the window."""
+    ta, tb, depth = wl.draw_param_sets(32, seed=41, depth_range=(5, 30))
+    win = (-2.0, 2.0, -2.0, 2.0, 1024, 1024)
+    worst = 0.0
+    for i in range(len(ta)):
+        a, b, d = complex(ta[i]), complex(tb[i]), int(depth[i])
+        idx = wl.sample_indices(kl.num_words(d), 2000, seed=100 + i)
+        assert _fp64_case(a, b, d, idx) < 1e-10, (i, d)
+        p = kl.eval_values(a, b, d, idx, precision="fp32", window=win).cpu().numpy()
+        fx, fy = _ref_pixels(O.eval_values(a, b, d, idx), win)
+        near = (fx > -1) & (fx < win[4] + 1) & (fy > -1) & (fy < win[5] + 1)
+        if near.any():
+            err = np.hypot(p[near, 0] - fx[near], p[near, 1] - fy[near]).max()
+            worst = max(worst, err)
+            assert err <= 0.25, (i, d, err)
+    print(f"largest FP32 pixel error over the drawn sets: {worst:.3e} px")
+
+
 @pytest.mark.parametrize("depth,win", [(18, WIN_C2), (22, WIN_C3)])
 def test_fp32_pixel_error(depth, win):
     idx = wl.sample_indices(kl.num_words(depth), 100000, seed=0)
