@@ -235,6 +235,25 @@ def test_image_is_histogram_of_own_bins(precision, depth, win, tail_len):
     assert int(img.sum()) + drop == n
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_drawn_sets_images_are_histograms_of_own_bins(precision):
+    """Six parameter sets of the batch's law at depths 9..15 (the planner's
+    splits, which at depths 13-15 take shorter tails and the persistent
+    kernel): each image and dropped count equal the histogram of kl_eval's
+    pixel coordinates of every word, bit for bit."""
+    ta, tb, depth = wl.draw_param_sets(6, seed=53, depth_range=(9, 15))
+    win = (-2.0, 2.0, -1.5, 1.5, 640, 480)
+    for i in range(len(ta)):
+        a, b, d = complex(ta[i]), complex(tb[i]), int(depth[i])
+        n = kl.num_words(d)
+        dropped = torch.zeros(1, dtype=torch.int64, device="cuda")
+        img = kl.as_u32(kl.render(a, b, d, win, precision=precision, dropped=dropped)).astype(np.int64)
+        p = kl.eval_values(a, b, d, np.arange(n, dtype=np.uint64), precision=precision, window=win).cpu().numpy()
+        ref, drop = _bins_from_pixels(p[:, 0], p[:, 1], win)
+        np.testing.assert_array_equal(img, ref, err_msg=f"set {i}, depth {d}")
+        assert int(dropped.item()) == drop, (i, d)
+
+
 @pytest.mark.parametrize("case", ["c1_tiling", "c2_d11", "c2_d12_aniso"])
 def test_fp64_image_matches_reference(case):
     if case == "c1_tiling":
