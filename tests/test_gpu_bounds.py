@@ -63,6 +63,19 @@ def test_bounded_equals_per_word(depth, win, tl, precision):
     assert int(img.sum()) + drop == kl.num_words(depth)
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_bounded_equals_per_word_on_drawn_sets(precision):
+    """Eight parameter sets of the batch's law at depths 13..17 (the planner's
+    4-, 5- and 6-letter tails) on a zoomed and a whole window: block bounds
+    leave every image and dropped count bit for bit as the per-word render."""
+    ta, tb, depth = wl.draw_param_sets(8, seed=61, depth_range=(13, 17))
+    for i in range(len(ta)):
+        win = WIN_ZOOM if i % 2 else (-2.0, 2.0, -2.0, 2.0, 512, 512)
+        a, b, d = complex(ta[i]), complex(tb[i]), int(depth[i])
+        img, drop = _assert_same(lambda **kw: kl.render(a, b, d, win, precision=precision, **kw))
+        assert int(img.sum()) + drop == kl.num_words(d), (i, d)
+
+
 @pytest.mark.parametrize("seed", ["b", "A", "all"])
 def test_bounded_seed_modes(seed):
     _assert_same(lambda **kw: kl.render(*C2, 14, WIN_C2, seed=seed, **kw))
