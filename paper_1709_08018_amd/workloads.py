@@ -119,6 +119,22 @@ def draw_maskit_mu(n: int, seed: int, depth_range=(8, 16)):
     return mu.astype(np.complex128), depth.astype(np.int32)
 
 
+def draw_decode_ranges(n: int, seed: int, max_count: int = 5000):
+    """n index ranges (depth, first, count) from numpy's PCG64 with the given
+    seed: depth ~ uniform integer in 1..40, count ~ uniform in 1..max_count
+    (at most the depth's words), first ~ uniform over the indices that leave
+    room for count words."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n):
+        d = int(rng.integers(1, 41))
+        total = 4 * 3 ** (d - 1)
+        count = int(rng.integers(1, min(max_count, total) + 1))
+        first = int(rng.integers(0, total - count + 1, dtype=np.uint64))
+        out.append((d, first, count))
+    return out
+
+
 def draw_param_sets(n: int, seed: int, depth_range=(12, 18)):
     """n parameter sets (ta, tb, depth) from numpy's PCG64 with the given seed.
 

@@ -125,6 +125,28 @@ def test_decode_many_tiles_per_workgroup(depth, count):
     np.testing.assert_array_equal(got, want)
 
 
+def test_decode_drawn_ranges():
+    """24 ranges drawn at depths 1..40, up to 5,000 words from anywhere in
+    the index space, decoded into 16-byte aligned and misaligned
+    destinations (the packed path at depths 16-32 when aligned, the byte
+    path otherwise): bit for bit the oracle's words, and nothing written
+    outside the range's bytes."""
+    for i, (depth, first, count) in enumerate(wl.draw_decode_ranges(24, seed=71)):
+        off = 16 if i % 2 == 0 else 16 + 1 + i % 7
+        nbytes = count * depth
+        buf = torch.full((nbytes + 48,), 255, dtype=torch.uint8, device="cuda")
+        view = buf[off:off + nbytes]
+        kl._check(kl.lib().kl_decode_ex(first, count, depth, view.data_ptr(), kl._stream(None)))
+        host = buf.cpu().numpy()
+        # the oracle's enumeration walks the word tree (depths up to 20);
+        # deeper words are unranked one by one
+        want = (O.enumerate_words(depth, first, count) if depth <= 20 else
+                np.stack([O.unrank(first + k, depth) for k in range(count)]))
+        np.testing.assert_array_equal(host[off:off + nbytes].reshape(count, depth), want,
+                                      err_msg=f"{depth} {first} {count}")
+        assert (host[:off] == 255).all() and (host[off + nbytes:] == 255).all()
+
+
 def test_decode_misaligned_destination():
     depth = 7
     n = kl.num_words(depth)
