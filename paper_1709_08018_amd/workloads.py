@@ -135,6 +135,21 @@ def draw_decode_ranges(n: int, seed: int, max_count: int = 5000):
     return out
 
 
+def draw_walks(n: int, seed: int):
+    """n walk configurations (walk seed, first walker, walkers, burn-in, drawn
+    steps) from numpy's PCG64 with the given seed: the walk seed and first
+    walker uniform over 64 bits (the walker range kept below 2^64), 1..3000
+    walkers, burn-in 0..20, 1..120 drawn steps."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n):
+        walk_seed = int(rng.integers(0, 2 ** 64, dtype=np.uint64))
+        walkers = int(rng.integers(1, 3001))
+        first = int(rng.integers(0, 2 ** 64 - walkers, dtype=np.uint64))
+        out.append((walk_seed, first, walkers, int(rng.integers(0, 21)), int(rng.integers(1, 121))))
+    return out
+
+
 def draw_param_sets(n: int, seed: int, depth_range=(12, 18)):
     """n parameter sets (ta, tb, depth) from numpy's PCG64 with the given seed.
 

@@ -47,6 +47,23 @@ def test_letters_bit_exact(seed, first, n, burn, steps):
         np.testing.assert_array_equal(got[i], O.walk_letters(seed, first + i, 1 + burn + steps), err_msg=str(i))
 
 
+def test_drawn_walks_letters_and_binned_renders():
+    """Ten walk configurations drawn over 64-bit seeds and walker indices,
+    burn-ins and step counts: sampled walkers' letters bit for bit the
+    oracle's, and the binned render equal to the one-atomic-per-point render
+    (image and dropped count) in both precisions."""
+    ab, _ = _maskit()
+    for i, (seed, first, n, burn, steps) in enumerate(wl.draw_walks(10, seed=81)):
+        got = kl.walk_letters(seed, first, n, burn, steps).cpu().numpy()
+        for k in sorted({0, n // 2, n - 1}):
+            np.testing.assert_array_equal(got[k], O.walk_letters(seed, first + k, 1 + burn + steps),
+                                          err_msg=f"{i} walker {k}")
+        for precision in ("fp32", "fp64"):
+            (a, da), (b, db) = _render_both(ab, seed, first, n, burn, steps, WIN_M, precision)
+            np.testing.assert_array_equal(a, b, err_msg=f"{i} {precision}")
+            assert da == db and int(a.sum()) + da == n * steps, (i, precision)
+
+
 def _assert_fp64(z, zr, what):
     fin = np.isfinite(zr)
     assert np.all(~np.isfinite(z[~fin])), what
