@@ -83,8 +83,9 @@ def _valu_per_wave_word(plan):
     return _profile_value(VALU_SUMMARY, "VALU instructions per wave-word (64 words)", plan)
 
 
-# A GPU machine grants one process a CPU share of 16 cores per GPU, whatever the
-# host reports; the oracle's threaded render uses at most that share.
+# The host this runs on grants one process a CPU share of 16 cores per GPU,
+# whatever the machine reports; the oracle's threaded render uses at most
+# that share.
 CPU_SHARE = 16
 
 
