@@ -205,6 +205,54 @@ def test_periodic_words_converge_to_product_fixed_point(pair):
     assert abs(v2[0, k2] / v2[1, k2] - target) > 1e-3
 
 
+def _cyclic_words(rng, n, lo, hi):
+    """n random cyclically reduced words (no letter next to its inverse, the
+    last letter not the inverse of the first) of lo..hi letters."""
+    out = []
+    while len(out) < n:
+        L = int(rng.integers(lo, hi + 1))
+        w = [int(rng.integers(0, 4))]
+        while len(w) < L:
+            c = int(rng.integers(0, 4))
+            if c != (w[-1] ^ 2):
+                w.append(c)
+        if w[-1] != (w[0] ^ 2):
+            out.append(w)
+    return out
+
+
+@pytest.mark.parametrize("case", range(5))
+def test_periodic_long_words_reach_numpy_eigenvectors(case):
+    """Complex-trace groups: for cyclically reduced words u of 3..6 letters,
+    the value of the power u^k (k as large as the oracle's 40 letters allow)
+    is the attracting fixed point of the product matrix U, taken from
+    numpy's eigen decomposition, once the power has contracted the seed's
+    distance to it below 1e-13 (|lambda_max|^-2k, from the same eigenvalues).
+    Both evaluators are checked, and the reversed word's fixed point differs."""
+    ta, tb = _param_sets()[1 + case]   # the depth-18 traces, then drawn ones
+    _, g, fix = O.generators(complex(ta), complex(tb))
+    rng = np.random.default_rng(100 + case)
+    checked = 0
+    for u in _cyclic_words(rng, 400, 3, 6):
+        k = 40 // len(u)
+        U = np.linalg.multi_dot([g[c] for c in u])
+        lam, vec = np.linalg.eig(U)
+        i = int(np.argmax(np.abs(lam)))
+        if np.abs(lam[i]) ** (-2 * k) > 1e-13 or abs(vec[1, i]) < 1e-9:
+            continue
+        target = vec[0, i] / vec[1, i]
+        word = np.array(u * k, np.uint8)
+        for literal in (False, True):
+            z = O.word_value(word, g, fix, literal=literal)
+            assert abs(z - target) <= 1e-9 * max(1.0, abs(target)), (u, k, literal, z, target)
+        Ur = np.linalg.multi_dot([g[c] for c in reversed(u)])
+        lr, vr = np.linalg.eig(Ur)
+        j = int(np.argmax(np.abs(lr)))
+        if abs(vr[1, j]) > 1e-9 and abs(vr[0, j] / vr[1, j] - target) > 1e-6:
+            checked += 1
+    assert checked >= 50, checked
+
+
 def test_literal_and_product_evaluators_agree():
     for d in (12, 18, 22):
         idx = wl.sample_indices(O.num_words(d), 2000, seed=d)
