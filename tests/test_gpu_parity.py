@@ -318,6 +318,56 @@ def test_range_additivity_and_ragged_ranges(precision):
             assert img.sum() <= count
 
 
+@pytest.mark.parametrize("depth", [33, 40])
+def test_deep_index_ranges(depth):
+    """Renders of index ranges at depths 33 and 40.  Head indices there need
+    64 bits, and at depth 40 (4 * 3^39, about 1.6e19 words) word indices pass
+    2^63.  The ranges are:
+      * one that crosses 2^63 (at depth 33, the middle);
+      * one that ends at the last word;
+      * 1,000 words at the start.
+    Each range is rendered into a 512^2 window fitted to the oracle's values
+    of 4,000 of its words.  At depth 40 the first range spans about 1e-9, a
+    deep zoom.  The long ranges hold over 8,192 whole heads: the persistent
+    kernel renders those and the per-word kernel renders the ragged ends.
+    In both precisions:
+      * each image and dropped count equal the histogram of kl_eval's pixel
+        coordinates of the same words, bit for bit;
+      * on the 4,000 words, FP64 values are within 1e-10 of the oracle's, and
+        FP32 pixel coordinates within 0.25 px for words near the window."""
+    n = kl.num_words(depth)
+    mid = 1 << 63 if depth == 40 else n // 2
+    for first, count in [(mid - 3_000_017, 6_100_003), (n - 6_200_011, 6_200_011), (0, 1000)]:
+        print(f"depth {depth}: words [{first}, {first + count})", flush=True)
+        rng = np.random.default_rng(first % 1000)
+        sample = np.unique(np.uint64(first) + rng.integers(0, count, 4000).astype(np.uint64))
+        z = O.eval_values(*C2, depth, sample)
+        mx, my = 0.1 * np.ptp(z.real) + 1e-12, 0.1 * np.ptp(z.imag) + 1e-12
+        win = (z.real.min() - mx, z.real.max() + mx, z.imag.min() - my, z.imag.max() + my, 512, 512)
+        W, H = win[4], win[5]
+        idx = np.uint64(first) + np.arange(count, dtype=np.uint64)
+        for precision in ("fp32", "fp64"):
+            dropped = torch.zeros(1, dtype=torch.int64, device="cuda")
+            img = kl.as_u32(kl.render(*C2, depth, win, precision=precision, first=first, count=count,
+                                      dropped=dropped)).astype(np.int64)
+            p = kl.eval_values(*C2, depth, idx, precision=precision, window=win).cpu().numpy()
+            px, py = p[:, 0], p[:, 1]
+            ok = (px >= 0) & (px < W) & (py >= 0) & (py < H)
+            key = np.floor(py[ok]).astype(np.int64) * W + np.floor(px[ok]).astype(np.int64)
+            ref = np.bincount(key, minlength=W * H).reshape(H, W)
+            np.testing.assert_array_equal(img, ref, err_msg=f"{precision} [{first}, +{count})")
+            assert int(dropped.item()) == int((~ok).sum()), (precision, first)
+            assert int(img.sum()) + int(dropped.item()) == count
+            del p, px, py, ok, key
+        assert _fp64_case(*C2, depth, sample) < 1e-10, first
+        q = kl.eval_values(*C2, depth, sample, precision="fp32", window=win).cpu().numpy()
+        fx, fy = _ref_pixels(z, win)
+        near = (fx > -1) & (fx < W + 1) & (fy > -1) & (fy < H + 1)
+        err = np.maximum(np.abs(q[:, 0] - fx), np.abs(q[:, 1] - fy))[near]
+        print(f"  {int(near.sum())} sampled words near the window; largest FP32 error {err.max():.2e} px")
+        assert near.sum() > 0.9 * len(sample) and err.max() < 0.25, (first, err.max())
+
+
 def test_tiling_ranges_cross_depths():
     depth, mind, win = 9, 2, WIN_C1
     total = sum(kl.num_words(d) for d in range(mind, depth + 1))
