@@ -293,8 +293,9 @@ static int build_group(cplx ta, cplx tb, group *g)
         mat2 m = g->g[k];
         if (!finite_c(m.a) || !finite_c(m.b) || !finite_c(m.c) || !finite_c(m.d))
             return -2;
+        /* a seed may be infinity: a has c = 0 on a curve of traces, among
+         * them ta = tb = 2 (the double cusp), where it is a translation */
         if (attracting_fixed_point(m, &g->fu[k], &g->fv[k]) != 0) return -2;
-        if (g->fv[k] == 0) return -2;  /* no recipe map fixes infinity */
     }
     return 0;
 }
@@ -336,7 +337,7 @@ int oracle_generators(double ta_re, double ta_im, double tb_re, double tb_im,
         }
     }
     if (fix_out)
-        for (int k = 0; k < 4; k++) put_c(fix_out + 2 * k, g.fu[k] / g.fv[k]);
+        for (int k = 0; k < 4; k++) put_c(fix_out + 2 * k, g.fv[k] == 0 ? INFINITY : g.fu[k] / g.fv[k]);
     return 0;
 }
 
@@ -425,6 +426,10 @@ static int group_from_arrays(const double *gens, const double *fix, group *g)
         g->g[k].d = get_c(gens + ((k * 2 + 1) * 2 + 1) * 2);
         g->fu[k] = get_c(fix + 2 * k);
         g->fv[k] = 1;
+        if (isinf(creal(g->fu[k])) || isinf(cimag(g->fu[k]))) {  /* infinity, as oracle_generators writes it */
+            g->fu[k] = 1;
+            g->fv[k] = 0;
+        }
     }
     return 0;
 }

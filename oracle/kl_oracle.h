@@ -33,6 +33,11 @@
  *            a homogeneous pair (u, v) of complex numbers, the point u / v
  *            (v = 0: infinity).  Matrices have determinant 1.
  *
+ *   fix      oracle_generators writes each seed as a point, infinity as
+ *            (inf, 0): the recipe's a fixes infinity on a curve of traces,
+ *            among them ta = tb = 2, where it is the translation z + 2i;
+ *            oracle_word_value reads such a value back as infinity.
+ *
  * Return codes: 0 ok, -1 bad argument, -2 singular parameters.
  */
 #ifndef KL_ORACLE_H

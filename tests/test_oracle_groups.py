@@ -170,3 +170,43 @@ def test_render_of_all_seeds_is_the_sum_of_single_seeds():
     img4, dr4, _ = O.render_group(G, d, win, seed=4)
     assert np.array_equal(img4.astype(np.uint64), total) and dr4 == drops
     assert int(img4.sum()) + dr4 == 4 * O.num_words(d)
+
+
+def test_double_cusp_closed_forms():
+    """ta = tb = 2, the double cusp.  The recipe is worked by hand:
+      * the trace quadratic x^2 - 4x + 8 = 0 has the root 2 + 2i in the upper
+        half plane;
+      * a becomes the translation z -> z + 2i, so its seed (and A's) is
+        infinity;
+      * b = [[1 - i, 1], [1, 1 + i]] is parabolic, fixing only -i.
+    The limit set is the Apollonian gasket between the lines Re z = -1 and
+    Re z = 1, the circles through infinity that a's translation slides along
+    themselves.  So:
+      * every finite word value lies in that strip and comes close to both
+        lines;
+      * the words a^d and A^d keep a's seed at infinity; every other word has
+        a finite value, since only the powers of a fix infinity in this free
+        group, whose other cusps are finite;
+      * a render counts every word (image + dropped)."""
+    tab, g, fix = O.generators(2 + 0j, 2 + 0j)
+    assert tab == pytest.approx(2 + 2j, abs=1e-14)
+    np.testing.assert_allclose(g[0], [[1, 2j], [0, 1]], atol=1e-14)
+    np.testing.assert_allclose(g[1], [[1 - 1j, 1], [1, 1 + 1j]], atol=1e-14)
+    assert np.isinf(fix[0]) and np.isinf(fix[2])
+    np.testing.assert_allclose(fix[[1, 3]], [-1j, -1j], atol=1e-14)
+    for d in range(1, 11):
+        n = O.num_words(d)
+        z = O.eval_values(2 + 0j, 2 + 0j, d, np.arange(n, dtype=np.uint64))
+        inf = ~np.isfinite(z)
+        words = np.array([O.unrank(int(i), d) for i in np.flatnonzero(inf)])
+        assert len(words) == 2 and (words[0] == 0).all() and (words[1] == 2).all(), d   # a^d and A^d
+        assert np.abs(z.real[~inf]).max() <= 1 + 1e-12, d
+        if d == 10:
+            assert z.real[~inf].max() > 0.99 and z.real[~inf].min() < -0.99
+    # a word with the letter a (A) applied to a value: the value moves by 2i (-2i)
+    zb = O.word_value(np.array([0, 1, 0, 1], np.uint8), g, fix)
+    zc = O.word_value(np.array([1, 0, 1], np.uint8), g, fix)
+    assert abs(zb - (zc + 2j)) < 1e-12
+    win = (-1.5, 1.5, -3.0, 3.0, 60, 120)
+    img, dropped, _ = O.render(2 + 0j, 2 + 0j, 9, win)
+    assert int(img.sum()) + dropped == O.num_words(9)
