@@ -274,7 +274,13 @@ int kl_eval_ex(kl_c64 ta, kl_c64 tb, int depth, const uint64_t *idx, uint64_t n,
  *   tab_out     tr ab
  *   gens_out    16 entries: generator g (0=a 1=b 2=A 3=B) entry (row, col)
  *               at gens_out[g * 4 + row * 2 + col]
- *   fix_out     4 entries: attracting fixed point of each generator
+ *   fix_out     4 entries: attracting fixed point of each generator; a
+ *               seed at infinity is written as (HUGE_VAL, 0).  On a curve of
+ *               traces, among them ta = tb = 2 (the double cusp, whose
+ *               limit set is the Apollonian gasket), a has c = 0: it is a
+ *               translation, and a and A take infinity as their seed.
+ *               Words whose value is infinity are dropped like any
+ *               non-finite value.
  * Any output pointer may be NULL.  Errors: KL_ESINGULAR. */
 int kl_generators(kl_c64 ta, kl_c64 tb, kl_c64 *tab_out, kl_c64 *gens_out, kl_c64 *fix_out);
 

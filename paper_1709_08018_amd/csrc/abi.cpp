@@ -108,8 +108,10 @@ static void store_gens(const cd g[4][4], const cd fix[4], const bool inf[4], Gen
 }
 
 // Trace recipe: tab solves tab^2 - ta tb tab + ta^2 + tb^2 = 0, root
-// (ta tb + s)/2 with s in the closed upper half plane.
-static int recipe(cd ta, cd tb, cd* tab_out, cd g[4][4], cd fix[4]) {
+// (ta tb + s)/2 with s in the closed upper half plane.  On a curve of
+// traces, among them ta = tb = 2 (the double cusp), a comes out with c = 0,
+// a translation whose seed (and A's) is infinity (inf[k]).
+static int recipe(cd ta, cd tb, cd* tab_out, cd g[4][4], cd fix[4], bool inf[4]) {
     const cd i1(0.0, 1.0);
     const cd p = ta * tb;
     cd s = std::sqrt(p * p - 4.0 * (ta * ta + tb * tb));
@@ -134,9 +136,8 @@ static int recipe(cd ta, cd tb, cd* tab_out, cd g[4][4], cd fix[4]) {
     for (int k = 0; k < 4; ++k) {
         for (int j = 0; j < 4; ++j)
             if (!finite(g[k][j])) return fail(KL_ESINGULAR, "generator %d not finite", k);
-        bool at_inf;
-        if (attracting_point(g[k], &fix[k], &at_inf) != KL_OK || at_inf)
-            return fail(KL_ESINGULAR, "generator %d has no finite attracting fixed point", k);
+        if (attracting_point(g[k], &fix[k], &inf[k]) != KL_OK)
+            return fail(KL_ESINGULAR, "generator %d has no attracting fixed point", k);
     }
     *tab_out = tab;
     return KL_OK;
@@ -144,11 +145,11 @@ static int recipe(cd ta, cd tb, cd* tab_out, cd g[4][4], cd fix[4]) {
 
 static int make_gens(kl_c64 ta, kl_c64 tb, Gens* G, cd* tab_out = nullptr) {
     cd g[4][4], fix[4], tab;
+    bool inf[4];
     if (!std::isfinite(ta.re) || !std::isfinite(ta.im) || !std::isfinite(tb.re) || !std::isfinite(tb.im))
         return fail(KL_EINVAL, "traces must be finite");
-    int rc = recipe(cd(ta.re, ta.im), cd(tb.re, tb.im), &tab, g, fix);
+    int rc = recipe(cd(ta.re, ta.im), cd(tb.re, tb.im), &tab, g, fix, inf);
     if (rc) return rc;
-    const bool inf[4] = {false, false, false, false};
     store_gens(g, fix, inf, G);
     if (tab_out) *tab_out = tab;
     return KL_OK;
@@ -759,7 +760,8 @@ int kl_generators(kl_c64 ta, kl_c64 tb, kl_c64* tab_out, kl_c64* gens_out, kl_c6
             gens_out[4 * k + 3] = {G.g[k].d.re, G.g[k].d.im};
         }
     if (fix_out)
-        for (int k = 0; k < 4; ++k) fix_out[k] = {G.fix[k].re, G.fix[k].im};
+        for (int k = 0; k < 4; ++k)
+            fix_out[k] = (G.inf_mask >> k) & 1u ? kl_c64{HUGE_VAL, 0.0} : kl_c64{G.fix[k].re, G.fix[k].im};
     return KL_OK;
 }
 

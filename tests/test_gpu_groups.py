@@ -221,3 +221,79 @@ def test_maskit_all_seeds_fp64_image_matches_reference():
     assert int(np.abs(img - ref.astype(np.int64)).sum()) <= 2 * near
     assert int(img.sum()) + int(dropped.item()) == 4 * sum(kl.num_words(d) for d in range(1, depth + 1))
     assert int(dropped.item()) == drop or abs(int(dropped.item()) - drop) <= near
+
+
+DC = (2 + 0j, 2 + 0j)
+WIN_DC = (-1.25, 1.25, -4.0, 4.0, 320, 1024)   # the gasket's strip |Re z| <= 1, four translates
+
+
+def test_double_cusp_values_and_images():
+    """ta = tb = 2, the double cusp (the Apollonian gasket).  The recipe's a
+    is the translation z -> z + 2i, so a and A take their seeds at infinity.
+    Heads that are powers of a fix infinity, and the suffix tables hold
+    points at infinity: the recipe path runs the homogeneous and ratio forms.
+    The checks:
+      * FP64 values within 1e-10 of the oracle's, and infinite on the same
+        words (a^d and A^d);
+      * FP32 pixel coordinates within 0.25 px;
+      * limit-set and tiling images in both precisions equal the histograms
+        of their own bins;
+      * the FP64 images are within the edge bar of the oracle's."""
+    W, H = WIN_DC[4], WIN_DC[5]
+    _, _, fix = kl.generators(*DC)
+    assert np.isinf(fix[0]) and np.isinf(fix[2]) and abs(fix[1] + 1j) < 1e-14 and abs(fix[3] + 1j) < 1e-14
+    worst = 0.0
+    for d in (1, 5, 9, 14, 22):
+        n = kl.num_words(d)
+        idx = np.arange(n, dtype=np.uint64) if n <= 50000 else wl.sample_indices(n, 20000, seed=d)
+        z = _z(kl.eval_values(*DC, d, idx, precision="fp64"))
+        zr = O.eval_values(*DC, d, idx)
+        np.testing.assert_array_equal(np.isfinite(z), np.isfinite(zr), err_msg=f"depth {d}")
+        assert _rel_err(z, zr) < 1e-10, d
+        p = kl.eval_values(*DC, d, idx, precision="fp32", window=WIN_DC).cpu().numpy()
+        fin = np.isfinite(zr)
+        fx, fy = _ref_pixels(zr[fin], WIN_DC)
+        near = (fx > -1) & (fx < W + 1) & (fy > -1) & (fy < H + 1)
+        err = np.maximum(np.abs(p[fin, 0] - fx), np.abs(p[fin, 1] - fy))[near]
+        worst = max(worst, float(err.max()))
+    print(f"double cusp: largest FP32 error {worst:.2e} px")
+    assert worst < 0.25
+    for depth, mind in ((12, 12), (10, 1)):
+        for precision in ("fp32", "fp64"):
+            dropped = torch.zeros(1, dtype=torch.int64, device="cuda")
+            img = kl.as_u32(kl.render(*DC, depth, WIN_DC, precision=precision, min_depth=mind,
+                                      dropped=dropped)).astype(np.int64)
+            ref, drop = np.zeros((H, W), np.int64), 0
+            for d in range(mind, depth + 1):
+                q = kl.eval_values(*DC, d, np.arange(kl.num_words(d), dtype=np.uint64), precision=precision,
+                                   window=WIN_DC).cpu().numpy()
+                r, dd = _bins_from_pixels(q[:, 0], q[:, 1], WIN_DC)
+                ref += r
+                drop += dd
+            np.testing.assert_array_equal(img, ref, err_msg=f"{precision} depth {depth} from {mind}")
+            assert int(dropped.item()) == drop
+        oref, _, near = O.render(*DC, depth, WIN_DC, min_depth=mind, edge_tol=1e-7, nthreads=8)
+        diff = int(np.abs(img - oref.astype(np.int64)).sum())
+        assert diff <= 2 * near, (depth, mind, diff, near)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_double_cusp_in_a_batch_equals_single_renders(precision):
+    """A batch that mixes the double cusp (seeds at infinity, homogeneous
+    suffix tables) with ordinary sets at depths 9 to 17 draws each image bit
+    for bit as a single render of that set under the batch's split.  The
+    depth-17 sets go to the persistent batched kernel."""
+    ta = np.array([2, wl.C2_TA, 2, wl.C1_TA, 2], complex)
+    tb = np.array([2, wl.C2_TB, 2, wl.C1_TB, 2], complex)
+    depth = np.array([17, 12, 9, 17, 14], np.int32)
+    win = WIN_DC
+    dropped = torch.zeros(len(ta), dtype=torch.int64, device="cuda")
+    imgs = kl.render_many(ta, tb, depth, win, precision=precision, dropped=dropped)
+    for i in range(len(ta)):
+        d1 = torch.zeros(1, dtype=torch.int64, device="cuda")
+        p = kl.plan_many(int(depth[i]), precision, win)
+        single = kl.render(complex(ta[i]), complex(tb[i]), int(depth[i]), win, precision=precision, dropped=d1,
+                           tail_len=p["tail_len"], lane_len=p["lane_len"])
+        assert torch.equal(imgs[i], single), i
+        assert int(dropped[i].item()) == int(d1.item())
+        assert int(kl.as_u32(imgs[i]).sum()) + int(d1.item()) == kl.num_words(int(depth[i]))

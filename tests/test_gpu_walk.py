@@ -33,6 +33,16 @@ def _recipe():
     return np.stack([g[0], g[1]]), O.group_recipe(wl.C2_TA, wl.C2_TB)
 
 
+def _dcusp():
+    """ta = tb = 2: a is the translation z + 2i, its seed (and A's) infinity."""
+    _, g, _ = kl.generators(2 + 0j, 2 + 0j)
+    return np.stack([g[0], g[1]]), O.group_recipe(2 + 0j, 2 + 0j)
+
+
+def _group(name):
+    return {"recipe": _recipe, "maskit": _maskit, "dcusp": _dcusp}[name]()
+
+
 def _z(t):
     a = t.cpu().numpy()
     return a[..., 0] + 1j * a[..., 1]
@@ -74,10 +84,10 @@ def _assert_fp64(z, zr, what):
     assert (dz[big] / a[big]).max() < 1e-10, what
 
 
-@pytest.mark.parametrize("group", ["recipe", "maskit"])
+@pytest.mark.parametrize("group", ["recipe", "maskit", "dcusp"])
 @pytest.mark.parametrize("burn,steps", [(0, 40), (7, 600)])
 def test_fp64_points_match_the_oracle(group, burn, steps):
-    ab, g = _recipe() if group == "recipe" else _maskit()
+    ab, g = _group(group)
     seed, first, n = 99, 1000, 300
     z = _z(kl.walk_eval(ab, seed, first, n, burn, steps, precision="fp64"))
     zr = O.walk_points(g, seed, first, n, burn, steps)
@@ -126,10 +136,10 @@ def test_image_is_histogram_of_own_points(precision, group):
     assert int(img.sum()) + drop == n * steps
 
 
-@pytest.mark.parametrize("group", ["recipe", "maskit"])
+@pytest.mark.parametrize("group", ["recipe", "maskit", "dcusp"])
 def test_fp64_image_matches_the_oracle(group):
-    ab, g = _recipe() if group == "recipe" else _maskit()
-    win = WIN_C2 if group == "recipe" else WIN_M
+    ab, g = _group(group)
+    win = {"recipe": WIN_C2, "maskit": WIN_M, "dcusp": (-1.25, 1.25, -4.0, 4.0, 320, 1024)}[group]
     seed, n, burn, steps = 21, 2000, 3, 128
     img = kl.as_u32(kl.walk_render(ab, seed, 0, n, burn, steps, win, precision="fp64")).astype(np.int64)
     ref, _, near = O.walk_render(g, seed, 0, n, burn, steps, win, edge_tol=1e-7)
