@@ -223,6 +223,19 @@ def test_render_singular_and_nonfinite_traces():
     assert _render(ta=complex(float("nan"), 0), window=good) == kl.KL_EINVAL
 
 
+def test_double_cusp_generators_keep_seeds_at_infinity():
+    """ta = tb = 2: the recipe's a is the translation z + 2i (c = 0), whose
+    seed, like A's, is infinity, reported as (HUGE_VAL, 0); b is parabolic at
+    -i.  The same traces with a tiny offset give finite seeds again."""
+    tab, g, fix = kl.generators(2 + 0j, 2 + 0j)
+    assert tab == 2 + 2j
+    np.testing.assert_array_equal(g[0], [[1, 2j], [0, 1]])
+    assert np.isinf(fix[0].real) and fix[0].imag == 0 and np.isinf(fix[2].real)
+    assert fix[1] == -1j and fix[3] == -1j
+    _, _, fix2 = kl.generators(2 + 0j, 2.001 + 0j)
+    assert np.isfinite(fix2).all()
+
+
 def test_decode_and_eval_argument_errors():
     assert L.kl_decode(0, 1, 0, FAKE) == kl.KL_EINVAL
     assert L.kl_decode(0, 1, 41, FAKE) == kl.KL_EINVAL
