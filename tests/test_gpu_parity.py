@@ -368,6 +368,37 @@ def test_deep_index_ranges(depth):
         assert near.sum() > 0.9 * len(sample) and err.max() < 0.25, (first, err.max())
 
 
+@pytest.mark.parametrize("W,H", [(32768, 32768), (1, 1), (32768, 1), (1, 32768)])
+def test_extreme_windows(W, H):
+    """Windows at the library's limits: 32768 x 32768 bins (2^30, a 4 GiB
+    image, the largest accepted), a single bin, a single row and a single
+    column, over [-1.5, 1.5]^2 at depth 12.  In both precisions, and with
+    register runs and the LDS tile histogram, the image and dropped count
+    equal the histogram of kl_eval's pixel coordinates of every word, bit for
+    bit (compared sparsely on the GPU)."""
+    depth = 12
+    win = (-1.5, 1.5, -1.5, 1.5, W, H)
+    n = kl.num_words(depth)
+    idx = torch.arange(n, dtype=torch.int64, device="cuda")
+    img = kl.new_image(win)
+    for precision in ("fp32", "fp64"):
+        p = kl.eval_values(*C2, depth, idx, precision=precision, window=win)
+        px, py = p[:, 0], p[:, 1]
+        ok = (px >= 0) & (px < W) & (py >= 0) & (py < H)
+        key = torch.floor(py[ok]).to(torch.int64) * W + torch.floor(px[ok]).to(torch.int64)
+        want_bins, want_counts = torch.unique(key, return_counts=True)
+        for hist_mode in ("runs", "lds"):
+            print(f"{W}x{H} {precision} {hist_mode}", flush=True)
+            dropped = torch.zeros(1, dtype=torch.int64, device="cuda")
+            kl.render(*C2, depth, win, image=img, precision=precision, hist_mode=hist_mode, dropped=dropped)
+            flat = img.view(-1)
+            bins = torch.nonzero(flat).view(-1)
+            assert torch.equal(bins, want_bins), (precision, hist_mode)
+            assert torch.equal(flat[bins].to(torch.int64), want_counts), (precision, hist_mode)
+            assert int(dropped.item()) == int((~ok).sum().item()) == n - int(want_counts.sum().item())
+    del img
+
+
 def test_tiling_ranges_cross_depths():
     depth, mind, win = 9, 2, WIN_C1
     total = sum(kl.num_words(d) for d in range(mind, depth + 1))
