@@ -575,6 +575,29 @@ def test_render_many_equals_single_renders(precision):
         assert int(kl.as_u32(imgs[i]).sum()) + int(d1.item()) == kl.num_words(int(depth[i]))
 
 
+def test_render_many_with_twenty_thousand_sets():
+    """20,000 parameter sets of the batch's law at depths 3 to 13 in one
+    batched render (64 x 64 images over [-2, 2]^2).  The shallow sets take
+    the per-word batch kernel and the deeper ones the persistent batched
+    kernel, so both search thousands of sets.  Every set's image sum plus
+    its dropped count equals its words, and 40 sets spread over the batch
+    equal their single renders under the batch's split, bit for bit."""
+    ta, tb, depth = wl.draw_param_sets(20_000, seed=97, depth_range=(3, 13))
+    win = (-2.0, 2.0, -2.0, 2.0, 64, 64)
+    dropped = torch.zeros(len(ta), dtype=torch.int64, device="cuda")
+    imgs = kl.render_many(ta, tb, depth, win, dropped=dropped)
+    words = torch.as_tensor([kl.num_words(int(d)) for d in depth], dtype=torch.int64, device="cuda")
+    sums = imgs.view(len(ta), -1).to(torch.int64).sum(1)
+    assert torch.equal(sums + dropped, words)
+    for i in np.linspace(0, len(ta) - 1, 40).astype(int):
+        d1 = torch.zeros(1, dtype=torch.int64, device="cuda")
+        p = kl.plan_many(int(depth[i]), "fp32", win)
+        single = kl.render(ta[i], tb[i], int(depth[i]), win, dropped=d1, tail_len=p["tail_len"],
+                           lane_len=p["lane_len"])
+        assert torch.equal(imgs[i], single), i
+        assert int(dropped[i].item()) == int(d1.item()), i
+
+
 # ---------------------------------------------------------------- full size
 def test_full_quasifuchsian_d18_invariants_and_samples():
     depth, win = 18, WIN_C2
