@@ -763,6 +763,13 @@ static int cayley_init(const uint8_t *table, int S, int m, int depth, cayley *c)
                 c->C[L][t] += c->C[L - 1][s];
             }
         }
+        /* every word of a length gets a 64-bit index: their total, which
+         * bounds every count by a good set, must fit */
+        uint64_t total = 0;
+        for (int s = 0; s < S; s++) {
+            if (total > UINT64_MAX - c->C[L][s]) return -1;
+            total += c->C[L][s];
+        }
     }
     return 0;
 }

@@ -80,6 +80,26 @@ def test_closed_form_counts():
         assert O.cayley_num_words(mod, d) == 2 ** ((d) // 2) + 2 * 2 ** ((d - 1) // 2)
 
 
+def test_counts_past_64_bits_are_refused():
+    """16 states, 7 symbols and no crash: symbol x in state s leads to state
+    1 + (x - 1 + 7 (s mod 2)) mod 15, so every string is regular and there
+    are exactly 7^L words of length L, and a state's count is at most the
+    previous length's total.  7^22 fits 64 bits.  7^23 does not, though each
+    state's count (at most 7^22) stays below 2^63; it is refused (0) rather
+    than wrapped."""
+    S, m = 16, 7
+    t = np.zeros((S, m + 1), np.uint8)
+    t[:, 0] = np.arange(S)
+    for st in range(S):
+        for x in range(1, m + 1):
+            t[st, x] = 1 + ((x - 1) + 7 * (st & 1)) % 15
+    c = O.Cayley(t, np.array([[[2, 0], [0, 0.5]]] * m, complex))
+    for d in (1, 2, 10, 22):
+        assert O.cayley_num_words(c, d) == 7 ** d
+    assert 7 ** 23 >= 2 ** 64 and 7 ** 22 < 2 ** 63
+    assert O.cayley_num_words(c, 23) == 0
+
+
 def test_free_group_table_values_and_render_equal_the_recipe_path():
     R = O.group_recipe(wl.C2_TA, wl.C2_TB)
     c = O.Cayley(T11, R.gens)
