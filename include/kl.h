@@ -393,7 +393,10 @@ int kl_walk_render_ex(const kl_c64 *ab, const kl_walk *walk, const kl_window *wi
  * A word's value applies its maps right to left to its seed: the
  * attracting fixed point of its last symbol (KL_SEED_OWN), of symbol q + 1
  * for every word (KL_SEED_A + q, q < n_symbols), or each symbol's in turn
- * (KL_SEED_ALL, renders).  This path computes in FP64 throughout. */
+ * (KL_SEED_ALL, renders).  This path computes in FP64 throughout.
+ * A table is refused (KL_EINVAL) when ranking its words needs more than 64
+ * good-state sets: the sets of states a word's prefix can be read from,
+ * which the kernels keep in LDS. */
 typedef struct {
     int n_states;
     int n_symbols;

@@ -691,7 +691,9 @@ static int render_depth(const Gens& G, const Fold& f, int depth, uint64_t lo, ui
     return KL_OK;
 }
 
-static int check_opts_common(const kl_opts& o) {
+// max_seed_mode: KL_SEED_INV_B for the four letters; a Cayley table names
+// up to eight symbols, KL_SEED_A + 7.
+static int check_opts_common(const kl_opts& o, int max_seed_mode = KL_SEED_INV_B) {
     if (o.precision != KL_PREC_FP32 && o.precision != KL_PREC_FP64)
         return fail(KL_EINVAL, "precision %d is neither KL_PREC_FP32 nor KL_PREC_FP64", o.precision);
     if (o.tail_len < 0 || o.tail_len > kMaxTail) return fail(KL_EINVAL, "tail_len %d outside 0..8", o.tail_len);
@@ -699,8 +701,8 @@ static int check_opts_common(const kl_opts& o) {
     if (o.hist_mode < KL_HIST_AUTO || o.hist_mode > KL_HIST_LDS) return fail(KL_EINVAL, "hist_mode %d", o.hist_mode);
     if (o.waves_per_cu < 0 || o.waves_per_cu > 32) return fail(KL_EINVAL, "waves_per_cu %d outside 0..32", o.waves_per_cu);
     if (o.head_form < 0 || o.head_form > 2) return fail(KL_EINVAL, "head_form %d outside 0..2", o.head_form);
-    if (o.seed_mode < KL_SEED_OWN || o.seed_mode > KL_SEED_INV_B)
-        return fail(KL_EINVAL, "seed_mode %d outside 0..5", o.seed_mode);
+    if (o.seed_mode < KL_SEED_OWN || o.seed_mode > max_seed_mode)
+        return fail(KL_EINVAL, "seed_mode %d outside 0..%d", o.seed_mode, max_seed_mode);
     if (o.block_bounds != 0 && o.block_bounds != 1)
         return fail(KL_EINVAL, "block_bounds %d is neither 0 nor 1", o.block_bounds);
     return KL_OK;
@@ -1486,7 +1488,7 @@ static int make_cayley(const kl_cayley* t, int min_depth, int max_depth, bool ne
 
 static int cayley_seed(const kl_opts& o, int m, int* seed) {
     if (o.seed_mode == KL_SEED_OWN) *seed = -1;
-    else if (o.seed_mode >= KL_SEED_A && o.seed_mode <= KL_SEED_INV_B && o.seed_mode - KL_SEED_A < m)
+    else if (o.seed_mode >= KL_SEED_A && o.seed_mode - KL_SEED_A < m)
         *seed = o.seed_mode - KL_SEED_A;
     else return fail(KL_EINVAL, "seed_mode %d does not name one of the %d symbols", o.seed_mode, m);
     return KL_OK;
@@ -1527,7 +1529,8 @@ int kl_cayley_eval_ex(const kl_cayley* t, int depth, const uint64_t* idx, uint64
     CayleyJob j;
     int rc = make_cayley(t, depth, depth, true, &j);
     if (rc) return rc;
-    if ((rc = check_opts_common(o)) || (rc = cayley_seed(o, j.m, &j.seed))) return rc;
+    if ((rc = check_opts_common(o, KL_SEED_A + kCayleyMaxSymbols - 1)) || (rc = cayley_seed(o, j.m, &j.seed)))
+        return rc;
     if (window && (rc = check_window(window))) return rc;
     if (n == 0) return KL_OK;
     if (!idx || !z_out) return fail(KL_EINVAL, "idx and z_out must not be NULL");
@@ -1546,7 +1549,7 @@ int kl_cayley_render_ex(const kl_cayley* t, int depth, const kl_window* window, 
     int rc = check_window(window);
     if (rc) return rc;
     if (!image_out) return fail(KL_EINVAL, "image_out is NULL");
-    if ((rc = check_opts_common(o))) return rc;
+    if ((rc = check_opts_common(o, KL_SEED_A + kCayleyMaxSymbols - 1))) return rc;
     if (depth < 1 || depth > KL_MAX_DEPTH) return fail(KL_EINVAL, "depth %d outside 1..40", depth);
     const int min_depth = o.min_depth == 0 ? depth : o.min_depth;
     CayleyJob j;

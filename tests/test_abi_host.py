@@ -431,6 +431,14 @@ def test_cayley_argument_errors():
     assert L.kl_cayley_render_ex(singular.ref(), 5, ctypes.byref(w), FAKE, ctypes.byref(o)) == kl.KL_ESINGULAR
     o4 = kl.make_opts(seed="B", use_stream=False)   # symbol 4: the table has 3
     assert L.kl_cayley_render_ex(good.ref(), 5, ctypes.byref(w), FAKE, ctypes.byref(o4)) == kl.KL_EINVAL
+    # a table of up to eight symbols names each one's seed as KL_SEED_A + q; past its
+    # symbols, and past the eighth, it is refused
+    eight = kl.Cayley(np.hstack([np.arange(2)[:, None], np.ones((2, 8))]).astype(np.uint8),
+                      np.array([[[2, 0], [0, 0.5]]] * 8, complex))
+    for mode in (2 + 8, 2 + 9, -1):
+        om = kl.make_opts(seed=mode, use_stream=False)
+        assert L.kl_cayley_render_ex(eight.ref(), 3, ctypes.byref(w), FAKE, ctypes.byref(om)) == kl.KL_EINVAL
+        assert L.kl_cayley_eval_ex(eight.ref(), 3, FAKE, 1, None, FAKE, ctypes.byref(om)) == kl.KL_EINVAL
     n = kl.cayley_num_words(good, 6)
     assert L.kl_cayley_decode_ex(good.ref(), n - 1, 2, 6, FAKE, None) == kl.KL_ERANGE
     assert L.kl_cayley_decode_ex(good.ref(), 0, 0, 6, None, None) == kl.KL_OK
@@ -439,5 +447,14 @@ def test_cayley_argument_errors():
     free8[:, 0] = 0
     assert kl.cayley_num_words(kl.Cayley(free8), 20) == 8 ** 20
     assert kl.cayley_num_words(kl.Cayley(free8), 21) == 0
+    # 16 states, 7 symbols, no crash: 7^L words; 7^23 passes 2^64 while every
+    # state's count (at most 7^22) stays below 2^63
+    seven = np.zeros((16, 8), np.uint8)
+    seven[:, 0] = np.arange(16)
+    for st in range(16):
+        for x in range(1, 8):
+            seven[st, x] = 1 + ((x - 1) + 7 * (st & 1)) % 15
+    assert kl.cayley_num_words(kl.Cayley(seven), 22) == 7 ** 22
+    assert kl.cayley_num_words(kl.Cayley(seven), 23) == 0
     huge = kl.Cayley(free8, np.array([[[2, 0], [0, 0.5]]] * 8, complex))
     assert L.kl_cayley_render_ex(huge.ref(), 21, ctypes.byref(w), FAKE, ctypes.byref(o)) == kl.KL_EINVAL

@@ -184,3 +184,70 @@ def test_head_tail_boundary_depths():
         drop += dr
     np.testing.assert_array_equal(img, ref_img)
     assert int(dropped.item()) == drop
+
+
+def _largest_table():
+    """16 states and 8 symbols, the most the library takes.  Symbol x read in
+    state s leads to state 1 + (x - 1 + 8 (s mod 2)) mod 15, except for a
+    seeded quarter of the (state, symbol) pairs, which crash.  The next
+    state depends only on the symbol and the parity of the state, so the
+    good-state sets stay within the library's 64."""
+    S, m = 16, 8
+    t = np.zeros((S, m + 1), np.uint8)
+    t[:, 0] = np.arange(S)
+    for s in range(S):
+        for x in range(1, m + 1):
+            t[s, x] = 1 + ((x - 1) + 8 * (s & 1)) % 15
+    crash = np.random.default_rng(5).random((S, m + 1)) < 0.25
+    crash[:, 0] = False
+    t[crash] = 0
+    rng = np.random.default_rng(8)
+    maps = rng.normal(size=(m, 2, 2)) + 1j * rng.normal(size=(m, 2, 2))
+    maps /= np.sqrt(np.linalg.det(maps))[:, None, None]
+    return t, maps
+
+
+def test_largest_table():
+    """The largest table (16 states, 8 symbols), whose word counts grow about
+    sixfold a letter: 4.2e18 words at length 24, and past 2^64 at 25.  Checks:
+      * counts agree with the oracle's at depths 1-26, where both refuse
+        depths 25 and 26;
+      * decoding of every word at depth 5 (the paper's scan of all 8^5
+        digit strings), and of sampled ranges at depths 12 and 24, matches
+        the oracle bit for bit;
+      * FP64 values at depths 12 and 24 lie within 1e-10 of the oracle's,
+        own seed and symbol 8's;
+      * the depth-8 limit set and the tiling of depths 1-7 from all eight
+        symbols' fixed points (several launches of seeds) equal their own
+        bins and are within the edge bar of the oracle's images."""
+    table, maps = _largest_table()
+    t, ref = _pair(table, maps)
+    for d in range(1, 27):
+        assert kl.cayley_num_words(t, d) == O.cayley_num_words(ref, d), d
+    assert kl.cayley_num_words(t, 24) > 2 ** 61 and kl.cayley_num_words(t, 25) == 0
+    np.testing.assert_array_equal(kl.cayley_decode(t, 0, kl.cayley_num_words(t, 5), 5).cpu().numpy(),
+                                  O.cayley_scan(ref, 5))
+    for d in (12, 24):
+        n = kl.cayley_num_words(t, d)
+        for first in (0, n // 3, n - 500):
+            got = kl.cayley_decode(t, first, 500, d).cpu().numpy()
+            want = np.stack([O.cayley_unrank(ref, first + k, d) for k in range(500)])
+            np.testing.assert_array_equal(got, want, err_msg=f"depth {d} first {first}")
+        idx = wl.sample_indices(n, 2000, seed=d)
+        for name, s in (("own", -1), (2 + 7, 7)):   # KL_SEED_A + 7: symbol 8's fixed point
+            z = kl.cayley_eval(t, d, idx, seed=name).cpu().numpy()
+            _assert_fp64_close(z[:, 0] + 1j * z[:, 1], O.cayley_eval(ref, d, idx, seed=s), (d, name))
+    win = (-2.5, 2.5, -2.5, 2.5, 400, 400)
+    for depth, mind, seed, s, copies in ((8, 8, "own", -1, 1), (7, 1, "all", 8, 8)):
+        dropped = torch.zeros(1, dtype=torch.int64, device="cuda")
+        img = kl.as_u32(kl.cayley_render(t, depth, win, min_depth=mind, seed=seed, dropped=dropped)).astype(np.int64)
+        words = sum(kl.cayley_num_words(t, d) for d in range(mind, depth + 1))
+        assert int(img.sum()) + int(dropped.item()) == copies * words
+        if seed == "own":
+            n = kl.cayley_num_words(t, depth)
+            p = kl.cayley_eval(t, depth, np.arange(n, dtype=np.uint64), window=win).cpu().numpy()
+            own, drop = _bins(p[:, 0], p[:, 1], win)
+            np.testing.assert_array_equal(img, own)
+            assert int(dropped.item()) == drop
+        rimg, _, near = O.cayley_render(ref, depth, win, seed=s, min_depth=mind, edge_tol=1e-7)
+        assert int(np.abs(img - rimg.astype(np.int64)).sum()) <= 2 * near, (depth, seed)
