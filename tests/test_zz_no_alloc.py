@@ -52,6 +52,18 @@ def test_noalloc_options_equal_render_ex(opts):
     assert int(d.item()) == int(dr.item())
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_noalloc_double_cusp_equals_render_ex(precision):
+    """ta = tb = 2: a and A seed at infinity, so the suffix tables in the
+    scratch array take their homogeneous form."""
+    win = (-1.25, 1.25, -4.0, 4.0, 320, 1024)
+    for depth in (15, 11):
+        img, d, ref, dr = _pair(2 + 0j, 2 + 0j, depth, win, precision=precision)
+        assert torch.equal(img, ref), depth
+        assert int(d.item()) == int(dr.item())
+        assert int(kl.as_u32(img).astype(np.int64).sum()) + int(d.item()) == kl.num_words(depth)
+
+
 def test_noalloc_accumulates_like_render_ex():
     W = wl.QUASIFUCHSIAN_D18
     win = (-1.5, 1.5, -1.5, 1.5, 300, 200)
