@@ -146,6 +146,22 @@ def test_bounded_batched_and_tiling_renders(precision):
     _assert_same(lambda **kw: kl.render(*C2, 14, WIN_C2, min_depth=1, seed="all", precision=precision, **kw))
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_bounded_double_cusp(precision):
+    """ta = tb = 2: the recipe's a is a translation seeded at infinity, so
+    the suffix tables are homogeneous and heads that are powers of a have no
+    pole form; block bounds leave those to the per-word walk, single and
+    batched, and the images stay those of the per-word renderer."""
+    win = (-1.25, 1.25, -4.0, 4.0, 320, 1024)
+    _assert_same(lambda **kw: kl.render(2 + 0j, 2 + 0j, 16, win, precision=precision, **kw))
+    _assert_same(lambda **kw: kl.render(2 + 0j, 2 + 0j, 13, win, precision=precision, seed="b", **kw))
+    ta = np.array([2, wl.C2_TA, 2], complex)
+    tb = np.array([2, wl.C2_TB, 2], complex)
+    a = kl.render_many(ta, tb, [16, 15, 14], win, precision=precision)
+    b = kl.render_many(ta, tb, [16, 15, 14], win, precision=precision, block_bounds=True)
+    assert torch.equal(a, b)
+
+
 def test_bounded_ignored_where_it_does_not_apply():
     # the LDS tile histogram, a small tiling render (per-word kernel), and non-finite FP32 coordinates
     _assert_same(lambda **kw: kl.render(*C2, 14, WIN_C2, hist_mode="lds", **kw))
