@@ -399,6 +399,44 @@ def test_extreme_windows(W, H):
     del img
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_deep_tiling_ranges_cross_depths(precision):
+    """Tiling renders (every depth from 1 to 30, about 1.4e14 words) of index
+    ranges that cross from depth 29 into depth 30, and that end at the
+    tiling's last word.  Each image equals the histogram of kl_eval's pixel
+    coordinates of the same words, taken depth by depth.  The FP64 image is
+    also within the edge bar of the oracle's render of the range."""
+    depth, mind, win = 30, 1, WIN_C2
+    W, H = win[4], win[5]
+    starts = [0]
+    for d in range(mind, depth + 1):
+        starts.append(starts[-1] + kl.num_words(d))
+    b29 = starts[depth - mind]           # first word of depth 30 in the tiling's index space
+    total = starts[-1]
+    for first, count in [(b29 - 1_200_007, 2_500_011), (total - 900_001, 900_001)]:
+        dropped = torch.zeros(1, dtype=torch.int64, device="cuda")
+        img = kl.as_u32(kl.render(*C2, depth, win, min_depth=mind, precision=precision, first=first, count=count,
+                                  dropped=dropped)).astype(np.int64)
+        ref = np.zeros((H, W), np.int64)
+        drop = 0
+        for d in range(mind, depth + 1):
+            lo, hi = max(first, starts[d - mind]), min(first + count, starts[d - mind + 1])
+            if lo >= hi:
+                continue
+            local = np.uint64(lo - starts[d - mind]) + np.arange(hi - lo, dtype=np.uint64)
+            p = kl.eval_values(*C2, d, local, precision=precision, window=win).cpu().numpy()
+            ok = (p[:, 0] >= 0) & (p[:, 0] < W) & (p[:, 1] >= 0) & (p[:, 1] < H)
+            key = np.floor(p[ok, 1]).astype(np.int64) * W + np.floor(p[ok, 0]).astype(np.int64)
+            ref += np.bincount(key, minlength=W * H).reshape(H, W)
+            drop += int((~ok).sum())
+        np.testing.assert_array_equal(img, ref, err_msg=f"{precision} [{first}, +{count})")
+        assert int(dropped.item()) == drop
+        if precision == "fp64":
+            oimg, _, near = O.render(*C2, depth, win, min_depth=mind, first=first, count=count, edge_tol=1e-7,
+                                     nthreads=8)
+            assert int(np.abs(img - oimg.astype(np.int64)).sum()) <= 2 * near
+
+
 def test_tiling_ranges_cross_depths():
     depth, mind, win = 9, 2, WIN_C1
     total = sum(kl.num_words(d) for d in range(mind, depth + 1))
