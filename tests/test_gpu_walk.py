@@ -147,6 +147,31 @@ def test_fp64_image_matches_the_oracle(group):
     assert diff <= 2 * near, (diff, near)
 
 
+@pytest.mark.parametrize("hist_mode", ["runs", "lds"])
+def test_walker_counts_past_one_launch(hist_mode):
+    """2^30 + 3,000 walkers of one drawn step each: more than one launch
+    takes (2^30 walkers; the binned path stages 2^27 points a pass).  Three
+    checks:
+      * rendered at once, they equal the same walkers rendered in three
+        uneven pieces;
+      * every point is counted (image + dropped);
+      * the two histogram modes agree."""
+    ab, _ = _maskit()
+    n = (1 << 30) + 3000
+    d_all = torch.zeros(1, dtype=torch.int64, device="cuda")
+    full = kl.walk_render(ab, 17, 5, n, 0, 1, WIN_M, hist_mode=hist_mode, dropped=d_all)
+    assert int(kl.as_u32(full).astype(np.int64).sum()) + int(d_all.item()) == n
+    acc = kl.new_image(WIN_M)
+    d_acc = torch.zeros(1, dtype=torch.int64, device="cuda")
+    for a, b in [(0, (1 << 29) + 7), ((1 << 29) + 7, (1 << 30) + 11), ((1 << 30) + 11, n)]:
+        kl.walk_render(ab, 17, 5 + a, b - a, 0, 1, WIN_M, image=acc, accumulate=True, hist_mode=hist_mode,
+                       dropped=d_acc)
+    assert torch.equal(acc, full)
+    assert int(d_acc.item()) == int(d_all.item())
+    other = kl.walk_render(ab, 17, 5, n, 0, 1, WIN_M, hist_mode="lds" if hist_mode == "runs" else "runs")
+    assert torch.equal(other, full)
+
+
 def test_walker_ranges_accumulate_and_edge_cases():
     ab, _ = _maskit()
     n, steps = 1000, 50
