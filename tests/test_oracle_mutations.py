@@ -11,7 +11,8 @@ a transposed good-set update, the wrong start state of the empty walk and
 a scan that reads words left to right in the Cayley-table path; in the
 random walks a Philox multiplier, the key schedule, swapped product
 halves, the stream's half order, a skip of the letter itself instead of
-its inverse, inverse maps, and the seed of the wrong letter),
+its inverse, inverse maps, and the seed of the wrong letter; Cayley counts
+that wrap past 2^64, and a recipe that refuses a seed at infinity),
 builds it with gcc, and runs the pin tests against the planted build in a
 child process.  The pins pass
 on the real reference and must fail on every planted copy.
@@ -57,6 +58,10 @@ MUTATIONS = {
     "walk_skips_the_letter_itself": ("int skip = INVERSE[letters[k - 1]];", "int skip = letters[k - 1];"),
     "walk_applies_inverses": ("cplx z = mobius_h(g->g[c[k]], u, v);", "cplx z = mobius_h(g->g[INVERSE[c[k]]], u, v);"),
     "walk_seed_of_second_letter": ("cplx u = g->fu[c[0]], v = g->fv[c[0]];", "cplx u = g->fu[c[1]], v = g->fv[c[1]];"),
+    "cayley_total_wraps": ("if (total > UINT64_MAX - c->C[L][s]) return -1;", "(void)0;"),
+    "recipe_rejects_seed_at_infinity": ("translation */\n        if (attracting_fixed_point(m, &g->fu[k], &g->fv[k]) != 0) return -2;",
+                                        "translation */\n        if (attracting_fixed_point(m, &g->fu[k], &g->fv[k]) != 0) return -2;"
+                                        "\n        if (g->fv[k] == 0) return -2;"),
 }
 PINS = [os.path.join(ROOT, "tests", f) for f in ("test_oracle_pins.py", "test_oracle_groups.py",
                                                   "test_oracle_cayley.py", "test_oracle_walk.py")]
