@@ -248,7 +248,8 @@ def num_words(depth: int) -> int:
 
 
 def generators(ta, tb):
-    """Host-side trace recipe: (tab, gens[4, 2, 2] complex, fix[4] complex)."""
+    """Host-side trace recipe: (tab, gens[4, 2, 2] complex, fix[4] complex);
+    a seed at infinity (a and A at ta = tb = 2, the double cusp) is inf+0j."""
     tab = c64()
     gens = (c64 * 16)()
     fix = (c64 * 4)()
