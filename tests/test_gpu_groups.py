@@ -129,14 +129,23 @@ def test_render_many_with_seeds_equals_single_renders(seed):
 
 
 # ---------------------------------------------------------------- explicit groups
-def test_explicit_recipe_generators_give_the_recipe_values():
-    _, g, _ = kl.generators(*C2)
+@pytest.mark.parametrize("traces", ["c2", "double_cusp"])
+def test_explicit_recipe_generators_give_the_recipe_values(traces):
+    """The recipe's matrices given as an explicit group give the recipe's
+    values (the double cusp: with seeds at infinity, infinite on the same
+    words) and, at the double cusp, the same image."""
+    ta, tb = C2 if traces == "c2" else (2 + 0j, 2 + 0j)
+    _, g, _ = kl.generators(ta, tb)
     ab = np.stack([g[0], g[1]])
     idx = wl.sample_indices(kl.num_words(16), 20000, seed=2)
     for seed in ("own", "a", "B"):
         za = _z(kl.eval_group(ab, 16, idx, precision="fp64", seed=seed))
-        zb = _z(kl.eval_values(*C2, 16, idx, precision="fp64", seed=seed))
-        assert (np.abs(za - zb) / np.maximum(1, np.abs(zb))).max() < 1e-10
+        zb = _z(kl.eval_values(ta, tb, 16, idx, precision="fp64", seed=seed))
+        fin = np.isfinite(zb)
+        np.testing.assert_array_equal(np.isfinite(za), fin)
+        assert (np.abs(za[fin] - zb[fin]) / np.maximum(1, np.abs(zb[fin]))).max() < 1e-10
+    if traces == "double_cusp":
+        assert torch.equal(kl.render_group(ab, 14, WIN_DC), kl.render(ta, tb, 14, WIN_DC))
 
 
 @pytest.mark.parametrize("seed", ["own", "b", "A"])
